@@ -1,0 +1,145 @@
+"""Seeded synthetic inputs for the Stokes-sphere resistance workloads.
+
+This module only draws random numbers and places spheres: it holds none of
+the solver's arithmetic (no kernels, no node sets, no factors).  Both the
+FP64 CPU oracle and the HIP library are fed from here, so every test and
+benchmark sees the same centres, radii and rigid-body velocities.
+
+Workloads (all unit spheres, viscosity 1):
+
+* ``two_sphere``     -- two spheres on the x axis with a given gap; the
+                        squeeze/separation problem of the paper's two-sphere
+                        studies (Section 3, eq. Brenner).
+* ``cluster``        -- cluster-growth random sequential addition in a cube
+                        sized for a target volume fraction: every new sphere
+                        is placed at a log-uniform gap from a random existing
+                        sphere in a random direction and rejected when it
+                        leaves the cube or comes closer than ``gap_min`` to
+                        any other sphere.  Stands in for the paper's random
+                        clusters (Sections 4 and 5.2), whose geometries are
+                        not published.
+* ``random_rbm``     -- rigid-body velocities (v, omega) drawn from N(0, 1).
+* ``random_factors`` -- arbitrary dense factors (U, sigma, V) of given
+                        shapes, used only to exercise the matrix-vector
+                        product at full size with inputs that need no SVD.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Packing:
+    centers: np.ndarray          # (P, 3) float64
+    radius: float                # common sphere radius
+    box: float                   # cube side (0 when unbounded)
+    anchor_gaps: np.ndarray = field(default_factory=lambda: np.zeros(0))
+
+    @property
+    def P(self) -> int:
+        return int(self.centers.shape[0])
+
+    def min_gaps(self) -> np.ndarray:
+        """Nearest-neighbour surface gap of every sphere (in radii)."""
+        c = self.centers
+        if c.shape[0] < 2:
+            return np.full(c.shape[0], np.inf)
+        d = np.sqrt(((c[:, None, :] - c[None, :, :]) ** 2).sum(-1))
+        np.fill_diagonal(d, np.inf)
+        return d.min(1) / self.radius - 2.0
+
+
+def two_sphere(gap: float, radius: float = 1.0) -> Packing:
+    """Two spheres centred at -/+ (radius + gap*radius/2) on the x axis."""
+    h = radius * (1.0 + 0.5 * gap)
+    c = np.array([[-h, 0.0, 0.0], [h, 0.0, 0.0]], dtype=np.float64)
+    return Packing(centers=c, radius=radius, box=0.0,
+                   anchor_gaps=np.array([gap]))
+
+
+def separating_pair_rbm(speed: float = 1.0) -> np.ndarray:
+    """Rigid-body data (1, 2, 6) for the two_sphere pair moving apart along
+    the line of centres at relative speed ``speed`` (each at speed/2)."""
+    rbm = np.zeros((1, 2, 6))
+    rbm[0, 0, 0] = -0.5 * speed
+    rbm[0, 1, 0] = +0.5 * speed
+    return rbm
+
+
+def _unit_vectors(rng: np.random.Generator, n: int) -> np.ndarray:
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def cluster(P: int, phi: float, gap_lo: float, gap_hi: float, seed: int,
+            gap_min: float = 1e-3, radius: float = 1.0,
+            max_tries: int = 2_000_000) -> Packing:
+    """Cluster-growth packing of ``P`` spheres (see module docstring)."""
+    rng = np.random.default_rng(seed)
+    a = radius
+    L = (P * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0) * a
+    centers = np.empty((P, 3))
+    centers[0] = 0.5 * L
+    gaps = [0.0]
+    n = 1
+    tries = 0
+    lg_lo, lg_hi = math.log10(gap_lo), math.log10(gap_hi)
+    while n < P:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("cluster packing did not converge")
+        anchor = int(rng.integers(n))
+        g = 10.0 ** rng.uniform(lg_lo, lg_hi)
+        d = _unit_vectors(rng, 1)[0]
+        c = centers[anchor] + (2.0 + g) * a * d
+        if np.any(c < a) or np.any(c > L - a):
+            continue
+        dist = np.sqrt(((centers[:n] - c) ** 2).sum(1))
+        if np.min(dist) / a - 2.0 < min(gap_min, g) * (1.0 - 1e-12):
+            continue
+        centers[n] = c
+        gaps.append(g)
+        n += 1
+    return Packing(centers=centers, radius=a, box=L,
+                   anchor_gaps=np.asarray(gaps))
+
+
+def random_rbm(P: int, nrhs: int, seed: int) -> np.ndarray:
+    """Rigid-body velocities, shape (nrhs, P, 6) = (v_x, v_y, v_z, w_x, w_y,
+    w_z), every component N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nrhs, P, 6))
+
+
+def random_factors(rows: int, cols: int, rank: int, seed: int,
+                   sigma_lo: float = 0.1):
+    """Dense factors U (rows x rank), sigma (rank), V (cols x rank), all
+    column-major-agnostic numpy arrays in float64.  Entries of U and V are
+    N(0, 1) scaled by 1/sqrt(rows) and 1/sqrt(cols); sigma is log-uniform
+    in [sigma_lo, 1] and sorted descending."""
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((rows, rank)) / math.sqrt(rows)
+    V = rng.standard_normal((cols, rank)) / math.sqrt(cols)
+    s = np.sort(10.0 ** rng.uniform(math.log10(sigma_lo), 0.0, rank))[::-1]
+    return U, s.copy(), V
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+# Named workloads -----------------------------------------------------------
+
+def workload_two_sphere_gap001():
+    """Two unit spheres, gap 0.01 radius, separating at unit relative speed."""
+    return two_sphere(0.01), separating_pair_rbm(1.0)
+
+
+def workload_cluster100(seed: int = 0):
+    """100 unit spheres, cube at volume fraction 0.2, gaps log-uniform in
+    [1e-3, 1e-1]; N(0,1) rigid-body velocities."""
+    pk = cluster(100, 0.2, 1e-3, 1e-1, seed=seed)
+    return pk, random_rbm(pk.P, 1, seed + 1000)

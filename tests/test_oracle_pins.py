@@ -1,0 +1,306 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by the
+mathematics (closed forms, exact identities, asymptotic limits, brute force).
+CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import geometry as geo, kernels, mfs, brenner
+from oracle.pairsum import pairsum
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+def _sphere_points(n, rng):
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+# -- kernels: exact single-sphere identities ------------------------------
+
+@pytest.mark.parametrize("a,mu", [(1.0, 1.0), (1.3, 0.7)])
+def test_translating_sphere_identity(a, mu):
+    """Stokeslet 6 pi mu a U plus potential dipole -pi a^3 U at the centre
+    give exactly u = U on |x - c| = a (rigid translation)."""
+    rng = np.random.default_rng(0)
+    c = np.array([0.3, -0.2, 0.5])
+    U = np.array([0.4, -1.1, 0.7])
+    x = c + a * _sphere_points(200, rng)
+    r = x - c
+    u = kernels.stokeslet(r, mu) @ (6 * math.pi * mu * a * U) + kernels.dipole(r) @ (-math.pi * a ** 3 * U)
+    assert np.abs(u - U).max() < 1e-13
+
+
+@pytest.mark.parametrize("a,mu", [(1.0, 1.0), (0.8, 2.5)])
+def test_rotating_sphere_identity(a, mu):
+    """Rotlet 8 pi mu a^3 omega at the centre gives omega x (x - c) on the sphere."""
+    rng = np.random.default_rng(1)
+    c = np.array([1.0, 2.0, -1.0])
+    w = np.array([0.2, 0.9, -0.5])
+    x = c + a * _sphere_points(200, rng)
+    u = kernels.rotlet(x - c, mu) @ (8 * math.pi * mu * a ** 3 * w)
+    assert np.abs(u - np.cross(w, x - c)).max() < 1e-13
+
+
+def test_kernel_symmetries():
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal((50, 3))
+    S, R, D = kernels.stokeslet(r, 1.0), kernels.rotlet(r, 1.0), kernels.dipole(r)
+    assert np.abs(S - np.swapaxes(S, 1, 2)).max() < 1e-15
+    assert np.abs(D - np.swapaxes(D, 1, 2)).max() < 1e-15
+    assert np.abs(R + np.swapaxes(R, 1, 2)).max() < 1e-15
+    # rotlet is the cross product t x r / (8 pi |r|^3)
+    t = rng.standard_normal(3)
+    rn = np.linalg.norm(r, axis=1)[:, None]
+    assert np.allclose(R @ t, np.cross(t, r) / (8 * math.pi * rn ** 3), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", [geo.KIND_S, geo.KIND_R, geo.KIND_D])
+def test_kernel_divergence_free(kind):
+    rng = np.random.default_rng(3)
+    h = 1e-4
+    for _ in range(10):
+        x = rng.standard_normal(3) * 2
+        lam = rng.standard_normal(3)
+        div = 0.0
+        for c in range(3):
+            e = np.zeros(3)
+            e[c] = h
+            up = kernels.tensor(kind, (x + e)[None], 1.0)[0] @ lam
+            um = kernels.tensor(kind, (x - e)[None], 1.0)[0] @ lam
+            div += (up[c] - um[c]) / (2 * h)
+        scale = np.abs(kernels.tensor(kind, x[None], 1.0)[0] @ lam).max() / np.linalg.norm(x)
+        assert abs(div) < 1e-6 * scale
+
+
+def test_kernel_far_field_decay():
+    """Stokeslet decays like 1/r, rotlet and dipole like 1/r^2."""
+    e = np.array([0.3, 0.4, 0.866])
+    for kind, p in ((geo.KIND_S, 1), (geo.KIND_R, 2), (geo.KIND_D, 3)):
+        a = np.abs(kernels.tensor(kind, (10 * e)[None], 1.0)).max()
+        b = np.abs(kernels.tensor(kind, (20 * e)[None], 1.0)).max()
+        assert abs(a / b - 2 ** p) < 1e-12 * 2 ** p
+
+
+def test_c_pairsum_matches_dense_blocks(oracle_pairsum_built):
+    rng = np.random.default_rng(4)
+    nt, ns = 37, 53
+    x = rng.standard_normal((nt, 3)) * 3
+    y = rng.standard_normal((ns, 3)) * 0.5
+    kinds = rng.integers(0, 3, ns).astype(np.int32)
+    lam = rng.standard_normal((ns, 3))
+    G = kernels.dense_block(x, y, kinds, 0.9)
+    u = pairsum(x, y, kinds, lam, 0.9)
+    ref = (G @ lam.reshape(-1)).reshape(-1, 3)
+    assert np.abs(u - ref).max() < 1e-13 * np.abs(ref).max()
+    # skip pairs in the same "sphere"
+    tsph = rng.integers(0, 4, nt).astype(np.int32)
+    ssph = rng.integers(0, 4, ns).astype(np.int32)
+    u2 = pairsum(x, y, kinds, lam, 0.9, tsph, ssph, skip_same=True)
+    mask = (tsph[:, None] != ssph[None, :]).astype(float)
+    Gm = G.reshape(nt, 3, ns, 3) * mask[:, None, :, None]
+    ref2 = (Gm.reshape(3 * nt, 3 * ns) @ lam.reshape(-1)).reshape(-1, 3)
+    assert np.abs(u2 - ref2).max() < 1e-13 * np.abs(ref2).max()
+
+
+# -- geometry ------------------------------------------------------------
+
+@pytest.mark.parametrize("delta", [0.1, 0.5, 1.0])
+def test_accumulation_point_is_limit_of_reflections(delta):
+    """Reflecting each centre in the other sphere over and over converges
+    to eq. (acc_points); its distance to the centre is eq. (Racc)."""
+    c1 = np.array([0.0, 0.0, 0.0])
+    c2 = np.array([2.0 + delta, 0.0, 0.0])
+    x = c2.copy()                  # image of c2 in sphere 1, then alternate
+    img1 = None
+    for _ in range(20000):
+        img1 = geo.kelvin_reflect(x, c1)
+        x = geo.kelvin_reflect(img1, c2)
+    a1, a2 = geo.accumulation_points(c1, c2)
+    assert np.abs(img1 - a1).max() < 1e-12
+    assert np.abs(x - a2).max() < 1e-12
+    assert abs(np.linalg.norm(a1 - c1) - geo.r_acc(delta)) < 1e-14
+
+
+@pytest.mark.parametrize("Rp", [0.5, 0.63, 0.7, 0.9])
+def test_delta_star_solves_racc(Rp):
+    assert abs(geo.r_acc(geo.delta_star(Rp)) - Rp) < 1e-14
+
+
+def test_paper_printed_values():
+    """Values printed in the paper (tests/golden/paper_values.json)."""
+    gv = json.load(open(GOLDEN))
+    # delta* ~ 0.129 for R_p = 0.7 (Section 3, after Figure Rg_sweep)
+    assert abs(geo.delta_star(0.7) - gv["delta_star_Rp_0p7"]["value"]) < 5e-4
+    # 3 M = 3 (801 + 12 n_c 3 20) with n_c = 3 printed as 3*2960 (Section 5.3)
+    m = geo.m_estimate(801, [20, 20, 20])
+    assert abs(m - gv["m_tetrahedron"]["value"]) <= 1
+    # 4.81e6 degrees of freedom for 2000 spheres of 801 nodes (Section 4, Ex. 2)
+    assert abs(3 * 801 * 2000 - gv["dof_2000"]["value"]) / gv["dof_2000"]["value"] < 2e-3
+    # image count rule, eq. (image_est): 20 images suffice for delta > 1e-3
+    assert geo.n_image_rule(1.01e-3) <= 20
+    assert geo.n_image_rule(0.2) == 0
+
+
+def test_image_nodes():
+    delta, Rp, n, D = 0.01, 0.7, 20, 0.05
+    t = geo.image_t(delta, Rp, n, D)
+    assert abs(t[0] - geo.r_acc(delta)) < 1e-15          # first node at x_acc
+    assert np.all(np.diff(t) < 0)                          # clustered toward x_acc
+    assert abs(t[-1] - (Rp * (1 + D) + (geo.r_acc(delta) - Rp * (1 + D)) * math.sin(math.pi / (2 * n)))) < 1e-15
+    assert abs(geo.r_acc(0.01) - 0.904875) < 1e-6
+
+
+def test_geometry_counts_and_caps():
+    c = np.array([[0.0, 0, 0], [2.01, 0, 0], [20.0, 0, 0]])
+    g = geo.build(c, 1.0)
+    assert g.M(0) == 1500 and g.Nk(0) == 660          # one-contact sphere
+    assert g.M(2) == 780 and g.Nk(2) == 600           # contact-free sphere
+    assert g.M(0) == geo.m_estimate(780, [20])
+    # caps: points on the unit sphere, within their half-angle of the axis
+    k = 0
+    t0 = g.target_offsets[k]
+    X = g.targets[t0:t0 + g.M(k)] - c[k]
+    assert np.abs(np.linalg.norm(X, axis=1) - 1).max() < 1e-14
+    e = np.array([1.0, 0, 0])
+    cap1 = X[780:780 + 360]
+    cap2 = X[780 + 360:]
+    ang1 = np.arccos(np.clip(cap1 @ e, -1, 1))
+    ang2 = np.arccos(np.clip(cap2 @ e, -1, 1))
+    assert ang1.max() <= math.pi / 5 + 1e-12 and ang1.max() > 0.98 * math.pi / 5
+    assert ang2.max() <= math.pi / 60 + 1e-12 and ang2.max() > 0.98 * math.pi / 60
+    # weights sum to the sphere area for the base set and to the cap areas
+    w = g.target_weight[t0:t0 + g.M(k)]
+    assert abs(w[:780].sum() - 4 * math.pi) < 1e-12
+    assert abs(w[780:1140].sum() - 2 * math.pi * (1 - math.cos(math.pi / 5))) < 1e-12
+    # proxy and image sources inside the sphere, images on the line of centres
+    src = g.src_pos[g.local_sources[0]] - c[0]
+    assert np.linalg.norm(src, axis=1).max() < 1.0
+    img = src[600:620]
+    assert np.abs(img[:, 1:]).max() < 1e-15 and np.all(img[:, 0] > 0.7)
+    # kinds: 620 S, 20 R, 20 D in local order
+    kinds = g.src_kind[g.local_sources[0]]
+    assert (kinds[:620] == 0).all() and (kinds[620:640] == 1).all() and (kinds[640:] == 2).all()
+
+
+# -- Brenner series ---------------------------------------------------------
+
+def test_brenner_far_field_limit():
+    """Approaching spheres far apart: F / (6 pi v) = 1 + 3/(2d) + O(d^-2)."""
+    res = []
+    for delta in (50.0, 100.0, 200.0):
+        d = 2 + delta
+        res.append(brenner.brenner_force(delta) / (6 * math.pi) - 1 - 1.5 / d)
+    # the remainder is second order: halving 1/d quarters it
+    assert 3.0 < res[0] / res[1] < 5.0 and 3.0 < res[1] / res[2] < 5.0
+
+
+def test_brenner_lubrication_limit():
+    """F / (6 pi v) = 1/(2 delta) + (9/20) log(1/delta) + O(1)."""
+    c = [brenner.brenner_force(d) / (6 * math.pi) - 0.5 / d - 0.45 * math.log(1 / d)
+         for d in (1e-3, 1e-4, 1e-5)]
+    assert abs(c[1] - c[2]) < 0.02 and abs(c[0] - c[1]) < 0.1
+    assert abs(c[2]) < 5.0
+
+
+# -- solve-level pins ---------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def single_sphere(oracle_pairsum_built):
+    g = geo.build(np.array([[0.5, -0.25, 2.0]]), 1.0)
+    pb = mfs.Problem(g).setup()
+    return g, pb
+
+
+def test_single_sphere_translation_and_rotation(single_sphere):
+    g, pb = single_sphere
+    rbm = np.array([[0.3, -0.8, 0.5, 0.0, 0.0, 0.0]])
+    out = mfs.solve_resistance(pb, rbm, tol=1e-12)
+    assert out["iterations"] <= 1                     # G_hat = I for one sphere
+    assert np.allclose(out["mu"], out["b"], rtol=0, atol=1e-14)
+    F = out["ft"][0, :3]
+    assert np.abs(F - mfs.stokes_drag(1.0, 1.0, rbm[0, :3])).max() < 1e-6 * np.linalg.norm(F)
+    assert np.abs(out["ft"][0, 3:]).max() < 1e-6 * np.linalg.norm(F)
+    rbm = np.array([[0.0, 0.0, 0.0, 0.2, 0.9, -0.4]])
+    out = mfs.solve_resistance(pb, rbm, tol=1e-12)
+    T = out["ft"][0, 3:]
+    assert np.abs(T - mfs.stokes_torque(1.0, 1.0, rbm[0, 3:])).max() < 1e-6 * np.linalg.norm(T)
+    assert np.abs(out["ft"][0, :3]).max() < 1e-6 * np.linalg.norm(T)
+
+
+def test_pseudo_inverse_properties(single_sphere):
+    g, pb = single_sphere
+    f = pb.factors[0]
+    B = mfs.self_block(g, 0)
+    assert np.abs(f.U.T @ f.U - np.eye(f.s.size)).max() < 1e-12
+    assert np.abs(f.V.T @ f.V - np.eye(f.s.size)).max() < 1e-12
+    Bp_B = f.V @ ((f.U.T @ B) / f.s[:, None])
+    assert np.abs(B @ Bp_B - B).max() < 1e-9 * f.sigma_max
+
+
+def test_two_spheres_against_brenner(pair001):
+    """Gap 0.01, separating at unit relative speed: each force equals
+    Brenner's |F| with |v| = 1/2 (target accuracy 1e-3 of the paper)."""
+    out = pair001["out"]
+    Fb = brenner.brenner_force(0.01, 0.5)
+    F1, F2 = out["ft"][0, :3], out["ft"][1, :3]
+    assert abs(np.linalg.norm(F1) - Fb) < 1e-3 * Fb
+    assert abs(np.linalg.norm(F2) - Fb) < 1e-3 * Fb
+    # force on the fluid points along each sphere's own velocity
+    assert F1[0] < 0 < F2[0]
+    assert np.abs(F1 + F2).max() < 1e-4 * Fb
+    eps, _ = pair001["pb"].residuals(out["lam"], pair001["rbm"][0], pair001["g"].check,
+                                     pair001["g"].check_sphere)
+    assert eps < 1e-3
+
+
+def test_resistance_matrix_symmetric_positive(pair001):
+    """Lorentz reciprocity: the 12 x 12 resistance matrix of the pair is
+    symmetric and positive definite (to discretisation accuracy)."""
+    pb = pair001["pb"]
+    R = np.zeros((12, 12))
+    for j in range(12):
+        rbm = np.zeros((2, 6))
+        rbm[j // 6, j % 6] = 1.0
+        out = mfs.solve_resistance(pb, rbm, tol=1e-9)
+        R[:, j] = out["ft"].reshape(-1)
+    asym = np.abs(R - R.T).max() / np.abs(R).max()
+    assert asym < 1e-4
+    assert np.linalg.eigvalsh(0.5 * (R + R.T)).min() > 0
+
+
+def test_gmres_matches_dense_lu(oracle_pairsum_built):
+    """Brute force: G_hat formed column by column and solved by LU."""
+    prm = geo.Params(n_proxy=60, n_colloc_base=80, n_image=4)
+    c = np.array([[0.0, 0, 0], [2.05, 0.3, 0.0], [0.4, 2.3, 0.1]])
+    g = geo.build(c, 1.0, prm)
+    pb = mfs.Problem(g).setup()
+    rbm = np.random.default_rng(5).standard_normal((3, 6))
+    b = pb.rhs(rbm)
+    A = pb.dense_Ghat()
+    x_lu = np.linalg.solve(A, b)
+    res = mfs.gmres(pb.apply, b, tol=1e-13, max_it=3 * g.T)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(res.x - x_lu) / np.linalg.norm(x_lu) < max(1e-8, kappa * 1e-12)
+    # diagonal blocks of G_hat are the identity
+    for k in range(g.P):
+        s = pb.tslice(k)
+        assert np.abs(A[s, s] - np.eye(s.stop - s.start)).max() < 1e-14
+
+
+def test_translation_and_permutation_invariance(pair001):
+    """Shifting and reordering the spheres changes only rounding.  The
+    truncated pseudo-inverses (eps_trunc = 5e-12) make the discrete solution
+    sensitive to rounding-level changes of the node coordinates: about 1e-6
+    relative in F at gap 0.01, so the bound is 1e-5."""
+    pk, rbm = pair001["pk"], pair001["rbm"]
+    ft0 = pair001["out"]["ft"]
+    shift = np.array([3.25, -1.5, 0.75])
+    c = pk.centers[::-1] + shift
+    g = geo.build(c, 1.0)
+    pb = mfs.Problem(g).setup()
+    out = mfs.solve_resistance(pb, rbm[0][::-1], tol=1e-10)
+    assert np.abs(out["ft"][::-1] - ft0).max() < 1e-5 * np.abs(ft0).max()
