@@ -1,0 +1,173 @@
+#!/usr/bin/env python
+"""Benchmark of the one-body preconditioned MFS resistance solve on one MI355X.
+
+Workload (default): 100 unit spheres in a cube at volume fraction 0.2,
+cluster-grown so that gaps are log-uniform in [1e-3, 1e-1]; 600 proxy
+Stokeslets on R_p = 0.7, 780 base collocation nodes, 20 image nodes (S, R, D)
+per contact with gap < 0.2, two caps of 360 nodes per contact; plain FP64;
+GMRES to 1e-10.  Random rigid-body velocities, N(0, 1).
+
+A step is one complete resistance solve: right-hand side, GMRES (every
+iteration one product with G_hat = pseudo-inverse apply + direct sum, plus
+Arnoldi), FP64 true residual, back-transform to strengths, forces and
+torques, and the surface velocity at the residual check points.  The
+self-block factorisation (setup) runs once before the timed region and is
+reported separately.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X, FP64 vector
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pk, stride: int):
+    """The FP64 oracle's direct sum (its dominant step) on a bounded sample:
+    every stride-th collocation node of the same workload against all
+    sources, same-sphere pairs skipped.  Returns pair-evals/s."""
+    from oracle import geometry as geo
+    from oracle.pairsum import pairsum, build
+    build(force=False)
+    g = geo.build(pk.centers, pk.radius)
+    rows = np.arange(0, g.T, stride)
+    lam = np.random.default_rng(7).standard_normal((g.S, 3))
+    t0 = time.perf_counter()
+    pairsum(g.targets[rows], g.src_pos, g.src_kind, lam, 1.0, g.target_sphere[rows], g.src_sphere, True)
+    dt = time.perf_counter() - t0
+    own = np.bincount(g.src_sphere, minlength=g.P)
+    pairs = float(np.sum(g.S - own[g.target_sphere[rows]]))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=pairs / dt, unit="pair-evals/s", cores=cores, kind="oracle",
+                sample=f"oracle C direct sum, every {stride}th of {g.T} collocation nodes "
+                       f"({rows.size} targets) x {g.S} sources, {pairs:.3g} pairs in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_03343_amd import smfs, workloads as wl
+
+    pk, _ = wl.workload_cluster100(args.seed)
+    log(f"workload: {pk.P} spheres, box {pk.box:.2f}, min gap {pk.min_gaps().min():.2e}")
+    pb = smfs.Problem(pk.centers, pk.radius)
+    log(f"T={pb.T} S={pb.S} check={pb.n_check} factors={pb.sizes.n_factors} "
+        f"workspace={pb.sizes.workspace_bytes / 2**30:.2f} GiB pairs/apply={pb.pairs_per_apply:.3e}")
+    pb.bind()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pb.setup()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup (device assembly + batched SVD of {pb.sizes.n_factors - 1} self blocks): {setup_s:.1f} s")
+
+    rbms = [torch.from_numpy(wl.random_rbm(pb.P, 1, 1000 + i)[0].reshape(-1)).cuda()
+            for i in range(args.warmup + args.steps)]
+    for i in range(args.warmup):
+        out = pb.solve_resistance(rbms[i])
+        log(f"warmup {i}: it {out['iterations']} true res {out['true_rel_residual']:.2e}")
+    torch.cuda.synchronize()
+
+    pb.profile(True)
+    step_ms, pairs, outs = [], 0, []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        out = pb.solve_resistance(rbms[args.warmup + i])
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        pairs += out["pair_evals"]
+        outs.append(out)
+        log(f"step {i}: {step_ms[-1]:.1f} ms, it {out['iterations']}, est {out['rel_residual']:.2e}, "
+            f"true {out['true_rel_residual']:.2e}, eps_res {out['eps_res_max']:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    pb.profile(False)
+    st = pb.profile_read()
+
+    direct_avg_s = st["direct_ms"] / max(1, st["direct_launches"]) * 1e-3
+    achieved = st["direct_flops"] / direct_avg_s / 1e12
+    pinv_avg_s = st["pinv_ms"] / max(1, st["pinv_launches"]) * 1e-3
+    result = {
+        "metric": "Stokeslet pair-evals/s (FP64 resistance solve, 100-sphere cluster)",
+        "value": pairs / elapsed,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "100 unit spheres, cube at volume fraction 0.2, gaps log-uniform [1e-3, 1e-1]; "
+                        "N=600 proxy on R_p=0.7, 780 base nodes, 20 S+R+D image nodes per contact "
+                        "(gap < 0.2), caps 2x360; FP64; GMRES tol 1e-10; one resistance solve per step",
+            "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S,
+            "pairs_per_apply": pb.pairs_per_apply, "precision": "fp64",
+        },
+        "solve_ms_p50": float(np.percentile(step_ms, 50)),
+        "solve_ms_p99": float(np.percentile(step_ms, 99)),
+        "setup_s": setup_s,
+        "gmres_iterations": [o["iterations"] for o in outs],
+        "true_rel_residual": [o["true_rel_residual"] for o in outs],
+        "eps_res_max": [o["eps_res_max"] for o in outs],
+        "roofline": {
+            "kernel": "k_direct_f64 (direct sum of every off-sphere pair)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+            "traffic": None,
+            "avg_launch_ms": direct_avg_s * 1e3,
+            "launches": st["direct_launches"],
+            "flops_per_launch": st["direct_flops"],
+        },
+        "pinv_apply": {
+            "bound": "hbm",
+            "achieved": st["pinv_bytes"] / pinv_avg_s / 1e9 if pinv_avg_s > 0 else None,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "avg_launch_ms": pinv_avg_s * 1e3, "bytes_per_launch": st["pinv_bytes"],
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(pk, args.cpu_stride)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * smfs -- MI355X (gfx950) library for the Stokes resistance problem of rigid
+ * spheres with the method of fundamental solutions and lubrication-adapted
+ * image lines (Broms, Barnett & Tornberg, arXiv 2407.03343).
+ *
+ * The flow is a sum of Stokeslets on an interior proxy sphere of each body
+ * (Section 2.1), plus Stokeslets, rotlets and potential dipoles on an image
+ * line per near contact (Section 2.3, eqs. line_points-tj; kinds chosen in
+ * Section 5.1).  Strengths solve the one-body right-preconditioned square
+ * system G_hat mu = b (Section 2.2, eq. resistance) by GMRES; every product
+ * with G_hat applies the two-factor pseudo-inverse of each sphere's self
+ * block (eq. transform), sums all off-sphere interactions directly and adds
+ * the identity self blocks (eq. uAll and the self-replacement step).
+ *
+ * Conventions
+ *  - Memory: arrays marked [host] are ordinary host memory; arrays marked
+ *    [dev] are device memory of the current HIP device.  The library never
+ *    allocates device memory for the solver itself: the caller allocates
+ *    smfs_sizes.workspace_bytes of device memory and binds it with
+ *    smfs_bind().  (smfs_setup() lets rocSOLVER take its own scratch.)
+ *  - Streams: every device call is ordered on the hipStream_t passed in
+ *    (NULL = the null stream).  Calls that return host statistics
+ *    synchronise that stream before returning.
+ *  - Vectors over collocation nodes (mu, b, y) are node-major, length 3 T:
+ *    entry 3 i + c is component c of node i; nodes are grouped by sphere.
+ *  - Source strengths (lambda) are S x 3 row-major, grouped by kind: all
+ *    Stokeslets (sphere-major; proxy points first, then image nodes contact
+ *    by contact), then all rotlets, then all potential dipoles.
+ *  - Forces/torques are P x 6 (F, T) with F = sum of Stokeslet strengths,
+ *    T = sum of rotlet strengths + sum (y - c) x f (Remark on extracting net
+ *    forces and torques): the force and torque the sphere exerts on the fluid.
+ *  - Errors: functions return SMFS_OK (0), a positive warning, or a negative
+ *    error; smfs_last_error() gives a thread-local message.  Nothing throws
+ *    across this interface.  Handles are not thread-safe; distinct handles
+ *    are independent.
+ */
+#ifndef SMFS_H
+#define SMFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *smfs_stream; /* a hipStream_t */
+typedef struct smfs_problem smfs_problem;
+
+enum {
+  SMFS_OK = 0,
+  SMFS_NOT_CONVERGED = 1,          /* warning: statistics still filled in */
+  SMFS_GAP_BELOW_VALIDATED = 2,    /* warning: some gap < 1e-3 radii */
+  SMFS_E_INVALID_ARG = -1,
+  SMFS_E_OVERLAP = -2,             /* two spheres touch or overlap */
+  SMFS_E_UNSUPPORTED = -3,         /* e.g. unequal radii */
+  SMFS_E_NOMEM = -4,               /* workspace too small */
+  SMFS_E_SVD = -5,
+  SMFS_E_DEVICE = -6,              /* HIP error */
+  SMFS_E_STATE = -7                /* call out of order (e.g. apply before setup) */
+};
+
+enum { SMFS_FP64 = 0, SMFS_MIXED = 1 };
+enum { SMFS_KIND_S = 1, SMFS_KIND_R = 2, SMFS_KIND_D = 4 };
+
+/* Discretisation and solver parameters (lengths in radii). */
+typedef struct smfs_params {
+  int32_t n_proxy;          /* N: proxy Stokeslets per sphere (Section 2.1) */
+  double proxy_radius;      /* R_p */
+  int32_t n_colloc_base;    /* base collocation nodes per sphere */
+  int32_t n_image;          /* image nodes per contact; < 0: eq. (image_est) */
+  uint32_t image_kinds;     /* SMFS_KIND_* mask placed at image nodes */
+  double image_offset;      /* Delta in eq. (tj) */
+  double image_gap_cutoff;  /* pairs with gap below this get image lines */
+  double near_gap_cutoff;   /* mixed precision: pairs below this stay FP64 */
+  int32_t cap_alpha[2];     /* cap upsampling, eq. (colloc_nbr) */
+  double cap_beta[2];       /* cap half-angles, eq. (thetacap) */
+  int32_t left_weights;     /* row weights sqrt(area) (Remark left-precond) */
+  double trunc_rel;         /* singular values kept if > trunc_rel * sigma_1 */
+  double mu;                /* viscosity */
+  int32_t n_check_base;     /* residual check points per sphere */
+  int32_t precision;        /* SMFS_FP64 or SMFS_MIXED */
+  double gmres_tol;         /* relative residual target */
+  int32_t gmres_max_it;
+  int32_t gmres_restart;    /* Krylov vectors kept (sizes the workspace) */
+} smfs_params;
+
+typedef struct smfs_sizes {
+  int32_t P;
+  int32_t n_factors;        /* distinct self blocks (0 = shared contact-free) */
+  int32_t n_contacts;       /* directed sphere-contacts with image lines */
+  int32_t min_gap_flag;     /* 1 if some gap < 1e-3 */
+  int64_t T;                /* collocation nodes */
+  int64_t S;                /* sources (all kinds) */
+  int64_t n_kind[3];        /* Stokeslets, rotlets, dipoles */
+  int64_t n_check;          /* residual check points */
+  size_t workspace_bytes;   /* device bytes smfs_bind() needs */
+  size_t factor_bytes;      /* part of workspace_bytes holding factors */
+} smfs_sizes;
+
+/* Output of a solve.  Device pointers may be NULL to skip that output. */
+typedef struct smfs_out {
+  double *mu;               /* [dev] 3 T: converged unknowns */
+  double *lambda;           /* [dev] S x 3: strengths lambda = B^+ mu */
+  double *ft;               /* [dev] P x 6: forces and torques */
+  double *u_check;          /* [dev] n_check x 3: velocity at check points */
+  /* host statistics */
+  int32_t iterations;
+  double rel_residual;      /* GMRES estimate at exit */
+  double true_rel_residual; /* ||b - G_hat mu|| / ||b||, recomputed in FP64 */
+  double lambda_inf;        /* max |lambda| (stability indicator, Section 3) */
+  double eps_res_max;       /* max pointwise relative residual, eq. (residual) */
+  double abs_res_max;       /* max |u - u_bc| / max |u_bc| */
+  double t_rhs_ms, t_gmres_ms, t_post_ms;
+  int64_t pair_evals;       /* pair evaluations performed by the solve */
+} smfs_out;
+
+/* Defaults: N = 600, R_p = 0.7, 780 base nodes, 20 images of kinds S|R|D,
+ * Delta = 0.05, image and near cutoffs 0.2, alpha = 6, beta = pi/5, pi/60,
+ * left weights on, trunc 5e-12, mu = 1, 500 check points, FP64, tol 1e-10,
+ * 1000 iterations, restart 400. */
+int smfs_params_default(smfs_params *p);
+
+/* Build the node sets on the host (Sections 2.1, 2.3, 5.1).
+ * centers [host] P x 3, radii [host] P (all equal, else UNSUPPORTED).
+ * Returns OVERLAP if any gap <= 0, GAP_BELOW_VALIDATED (warning, handle
+ * created) if a gap is below 1e-3 radii. */
+int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
+                        const double *radii, smfs_problem **out);
+void smfs_problem_destroy(smfs_problem *pb);
+int smfs_problem_sizes(const smfs_problem *pb, smfs_sizes *s);
+
+/* Copy node sets out [host]; any pointer may be NULL.  targets T x 3,
+ * target_sphere T, target_weight T (area weights w_i), sources S x 3,
+ * source_kind S (0 S, 1 R, 2 D), source_sphere S, check n_check x 3,
+ * check_sphere n_check. */
+int smfs_export_nodes(const smfs_problem *pb, double *targets, int32_t *target_sphere,
+                      double *target_weight, double *sources, int32_t *source_kind,
+                      int32_t *source_sphere, double *check, int32_t *check_sphere);
+
+/* Factor id of sphere k (0 = the shared contact-free factor). */
+int smfs_sphere_factor(const smfs_problem *pb, int32_t k, int32_t *fid);
+/* Shape of self block fid: rows = 3 M, cols = 3 N', rank after truncation
+ * (0 before setup/import), representative sphere. */
+int smfs_factor_info(const smfs_problem *pb, int32_t fid, int32_t *rows, int32_t *cols,
+                     int32_t *rank, int32_t *sphere);
+
+/* Bind caller-provided device workspace and upload the node sets. */
+int smfs_bind(smfs_problem *pb, void *dev_workspace, size_t bytes, smfs_stream stream);
+
+/* Assemble every distinct self block B = W G^(kk) on the device and factor
+ * it with a thin SVD (rocSOLVER), keeping sigma_i > trunc_rel * sigma_1
+ * (Section 5, eps_trunc).  Synchronises the stream. */
+int smfs_setup(smfs_problem *pb, smfs_stream stream);
+
+/* Install a factor computed elsewhere.  U [host] rows x rank column-major,
+ * sigma [host] rank, V [host] cols x rank row-major.  Synchronises. */
+int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double *U,
+                       const double *sigma, const double *V, smfs_stream stream);
+
+/* One product y = G_hat mu (eq. resistance): lambda_hat = V S^-1 U^T mu per
+ * sphere, then y_k = mu_k + W_k sum_{k' != k} G^(kk') lambda_hat_k'.
+ * mu, y [dev] 3 T (must not alias).  precision SMFS_FP64 or SMFS_MIXED. */
+int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision,
+               smfs_stream stream);
+
+/* lambda [dev] S x 3 = B^+ mu, eq. (transform), in FP64. */
+int smfs_transform(smfs_problem *pb, const double *mu, double *lambda, smfs_stream stream);
+
+/* b [dev] 3 T = W (v + omega x (x - c)) from rbm [dev] P x 6, eq. (bc). */
+int smfs_rhs(smfs_problem *pb, const double *rbm, double *b, smfs_stream stream);
+
+/* ft [dev] P x 6 from lambda [dev] S x 3. */
+int smfs_force_torque(smfs_problem *pb, const double *lambda, double *ft, smfs_stream stream);
+
+/* u [dev] n x 3 = sum over every source of K(x - y) lambda at points x [dev]
+ * n x 3 (flow evaluation; no source is skipped). */
+int smfs_eval_velocity(smfs_problem *pb, const double *lambda, int64_t n, const double *x,
+                       double *u, smfs_stream stream);
+
+/* Resistance solve: rbm [dev] P x 6 rigid-body velocities in, outputs per
+ * smfs_out.  Returns NOT_CONVERGED (warning) if gmres_max_it is reached. */
+int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out,
+                          smfs_stream stream);
+
+/* Pair evaluations in one product with G_hat (all off-sphere pairs). */
+int64_t smfs_pairs_per_apply(const smfs_problem *pb);
+
+/* Per-launch timing of the two kernels of each product with G_hat, taken
+ * with HIP events recorded on the caller's stream around every launch.
+ * Algorithmic work per product: the direct sum does 28, 25 and 30 flops per
+ * Stokeslet, rotlet and dipole pair; the pseudo-inverse apply reads its
+ * factors once (8 bytes per kept entry of U and V). */
+typedef struct smfs_kernel_stats {
+  int64_t direct_launches;
+  double direct_ms;         /* summed over launches */
+  double direct_flops;      /* algorithmic flops per launch */
+  int64_t pinv_launches;
+  double pinv_ms;           /* U^T mu and V s kernels together */
+  double pinv_bytes;        /* algorithmic bytes per launch pair */
+} smfs_kernel_stats;
+
+/* enable = 1 clears the counters and starts recording; 0 stops. */
+int smfs_profile(smfs_problem *pb, int32_t enable);
+/* Waits for the recorded events and fills *st. */
+int smfs_profile_read(smfs_problem *pb, smfs_kernel_stats *st);
+
+const char *smfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMFS_H */

@@ -1,0 +1,813 @@
+// C-ABI of libsmfs: problem lifecycle, workspace layout, the one-body
+// preconditioned product (Section 2.2), setup of the self-block factors
+// (rocSOLVER thin SVD with relative truncation, Section 5) and a
+// device-resident GMRES with classical Gram-Schmidt applied twice.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace smfs {
+
+namespace {
+thread_local std::string g_err;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kTileTargets = 128;    // 64 lanes x 2 targets
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Source splits of the direct sum: enough blocks (about 8192, i.e. 32 per
+// CU) to keep every SIMD busy to the end of the launch, while each split
+// still streams at least 1024 sources through LDS.
+int32_t choose_splits(int64_t n_tiles, int64_t S) {
+  const int64_t blocks = std::max<int64_t>(1, (n_tiles + 3) / 4);
+  static const int64_t target = [] {
+    const char *e = std::getenv("SMFS_DIRECT_BLOCKS");
+    return e ? std::max<int64_t>(256, std::atoll(e)) : (int64_t)8192;
+  }();
+  int64_t sp = (target + blocks - 1) / blocks;
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, S / 1024));
+  sp = std::max<int64_t>(1, std::min<int64_t>(sp, 64));
+  return (int32_t)sp;
+}
+
+int64_t free_tiles(int64_t n) { return (n + kTileTargets - 1) / kTileTargets; }
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+void build_tiles(const Problem &pb, std::vector<int4> &tiles, int tt) {
+  tiles.clear();
+  for (int k = 0; k < pb.P; ++k) {
+    const int64_t t0 = pb.toff[k], M = pb.toff[k + 1] - pb.toff[k];
+    for (int64_t o = 0; o < M; o += tt)
+      tiles.push_back(make_int4(k, (int)(t0 + o), (int)std::min<int64_t>(tt, M - o), 0));
+  }
+}
+
+// Assign (or only measure) the workspace regions.  Returns bytes needed.
+size_t workspace_layout(Problem &pb, bool assign) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const int64_t T = pb.T, S = pb.S, C = pb.C;
+  const int P = pb.P;
+  const size_t o_tgt = take(sizeof(double) * 3 * T);
+  const size_t o_sw = take(sizeof(double) * T);
+  const size_t o_tsph = take(sizeof(int32_t) * T);
+  const size_t o_src = take(sizeof(double) * 3 * S);
+  const size_t o_lam = take(sizeof(double) * 3 * S);
+  const size_t o_chk = take(sizeof(double) * 3 * C);
+  const size_t o_csph = take(sizeof(int32_t) * C);
+  const size_t o_meta = take(sizeof(SphereMeta) * P);
+  const size_t o_fs = take(sizeof(FactorSlot) * pb.factors.size());
+  std::vector<int4> tiles;
+  build_tiles(pb, tiles, kTileTargets);
+  const size_t o_tiles = take(sizeof(int4) * tiles.size());
+  int64_t cols_total = 0;
+  for (int k = 0; k < P; ++k) cols_total += pb.factors[pb.fid_of[k]].cols;
+  const size_t o_s = take(sizeof(double) * cols_total);
+  const size_t o_ut = take(sizeof(RowTask) * cols_total);
+  const size_t o_vt = take(sizeof(RowTask) * cols_total);
+  const int32_t sp_t = choose_splits((int64_t)tiles.size(), S);
+  const int32_t sp_c = choose_splits(free_tiles(C), S);
+  const int64_t part = std::max<int64_t>(3 * T * sp_t, 3 * C * sp_c);
+  const size_t o_part = take(sizeof(double) * part);
+  // Krylov basis (restart + 1 vectors) and work vectors
+  const int64_t ld = ((3 * T + 31) / 32) * 32;
+  const int32_t m = std::max(1, pb.prm.gmres_restart);
+  const size_t o_kry = take(sizeof(double) * ld * (m + 1));
+  const size_t o_vec = take(sizeof(double) * ld * 4);
+  const int32_t nch = mdot_chunks(3 * T);
+  const int64_t red = (int64_t)nch * (m + 2) + 4 * (m + 2) + 64;
+  const size_t o_red = take(sizeof(double) * red);
+  // factors: slots of equal shape are consecutive with a uniform stride so
+  // that one strided-batched SVD can write a whole group in place
+  const size_t o_fac = off;
+  std::vector<int> order;
+  for (size_t f = 0; f < pb.factors.size(); ++f)
+    if (pb.factors[f].rep >= 0) order.push_back((int)f);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const FactorSlot &a = pb.factors[x], &b = pb.factors[y];
+    return a.rows != b.rows ? a.rows < b.rows : a.cols < b.cols;
+  });
+  auto slot_elems = [](const FactorSlot &fs) {
+    int64_t e = (int64_t)fs.rows * fs.cols + (int64_t)fs.cols * fs.cols + fs.cols;
+    return (e + 31) / 32 * 32;
+  };
+  int64_t fac_elems = 0;
+  for (int f : order) fac_elems += slot_elems(pb.factors[f]);
+  const size_t fbytes = sizeof(double) * fac_elems;
+  take(fbytes);
+  if (assign) {
+    char *b = pb.ws;
+    pb.d_tgt = (double *)(b + o_tgt);
+    pb.d_sw = (double *)(b + o_sw);
+    pb.d_tsph = (int32_t *)(b + o_tsph);
+    pb.d_src = (double *)(b + o_src);
+    pb.d_lamhat = (double *)(b + o_lam);
+    pb.d_chk = (double *)(b + o_chk);
+    pb.d_csph = (int32_t *)(b + o_csph);
+    pb.d_meta = (SphereMeta *)(b + o_meta);
+    pb.d_fslots = (FactorSlot *)(b + o_fs);
+    pb.d_tiles = (int4 *)(b + o_tiles);
+    pb.d_s = (double *)(b + o_s);
+    pb.d_utask = (RowTask *)(b + o_ut);
+    pb.d_vtask = (RowTask *)(b + o_vt);
+    pb.d_part = (double *)(b + o_part);
+    pb.d_kry = (double *)(b + o_kry);
+    pb.d_vec = (double *)(b + o_vec);
+    pb.d_red = (double *)(b + o_red);
+    pb.d_fac = (double *)(b + o_fac);
+    pb.tiles = tiles;
+    pb.n_tiles = (int64_t)tiles.size();
+    pb.n_splits = sp_t;
+    pb.n_splits_chk = sp_c;
+    pb.part_cap = part;
+    pb.kry_ld = ld;
+    pb.kry_vecs = m + 1;
+    pb.red_cap = red;
+    // factor offsets (elements from d_fac), grouped by shape
+    for (auto &fs : pb.factors) fs.u_off = fs.vt_off = fs.sig_off = 0;
+    int64_t e = 0;
+    for (int f : order) {
+      FactorSlot &fs = pb.factors[f];
+      fs.u_off = e;
+      fs.vt_off = e + (int64_t)fs.rows * fs.cols;
+      fs.sig_off = fs.vt_off + (int64_t)fs.cols * fs.cols;
+      e += slot_elems(fs);
+    }
+  }
+  pb.factor_bytes = fbytes;
+  return off;
+}
+
+int upload_tables(Problem &pb, hipStream_t s) {
+  const int P = pb.P;
+  std::vector<double> sw(pb.T);
+  for (int64_t i = 0; i < pb.T; ++i) sw[i] = pb.prm.left_weights ? std::sqrt(pb.tw[i]) : 1.0;
+  pb.meta.assign(P, SphereMeta{});
+  for (int k = 0; k < P; ++k) {
+    SphereMeta &m = pb.meta[k];
+    m.t0 = pb.toff[k];
+    m.M = (int32_t)(pb.toff[k + 1] - pb.toff[k]);
+    m.N = 0;
+    for (int kd = 0; kd < 3; ++kd) {
+      m.k0[kd] = pb.koff[kd][k];
+      m.kn[kd] = (int32_t)(pb.koff[kd][k + 1] - pb.koff[kd][k]);
+      m.N += m.kn[kd];
+    }
+    m.fid = pb.fid_of[k];
+    m.rank = 0;
+    m.s0 = 0;
+    for (int i = 0; i < 3; ++i) m.c[i] = pb.centers[3 * k + i];
+  }
+  SMFS_HIP(hipMemcpyAsync(pb.d_tgt, pb.tgt.data(), 8 * pb.tgt.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb.d_sw, sw.data(), 8 * sw.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb.d_tsph, pb.tsph.data(), 4 * pb.tsph.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb.d_src, pb.src.data(), 8 * pb.src.size(), hipMemcpyHostToDevice, s));
+  if (pb.C) {
+    SMFS_HIP(hipMemcpyAsync(pb.d_chk, pb.chk.data(), 8 * pb.chk.size(), hipMemcpyHostToDevice, s));
+    SMFS_HIP(hipMemcpyAsync(pb.d_csph, pb.csph.data(), 4 * pb.csph.size(), hipMemcpyHostToDevice, s));
+  }
+  SMFS_HIP(hipMemcpyAsync(pb.d_tiles, pb.tiles.data(), sizeof(int4) * pb.tiles.size(),
+                          hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  return rank_tables(pb, s);
+}
+
+// (Re)build the rank-dependent tables: s offsets and the row tasks of the
+// pseudo-inverse apply, then upload meta and factor slots.
+int rank_tables(Problem &pb, hipStream_t s) {
+  std::vector<RowTask> ut, vt;
+  int64_t s0 = 0;
+  for (int k = 0; k < pb.P; ++k) {
+    SphereMeta &m = pb.meta[k];
+    const FactorSlot &f = pb.factors[m.fid];
+    m.rank = f.rank;
+    m.s0 = s0;
+    s0 += f.cols;
+    if (f.rank > 0) {
+      for (int j = 0; j < f.rank; ++j) ut.push_back(RowTask{k, j});
+      for (int i = 0; i < f.cols; ++i) vt.push_back(RowTask{k, i});
+    }
+  }
+  pb.n_utask = (int64_t)ut.size();
+  pb.n_vtask = (int64_t)vt.size();
+  SMFS_HIP(hipMemcpyAsync(pb.d_meta, pb.meta.data(), sizeof(SphereMeta) * pb.P, hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb.d_fslots, pb.factors.data(), sizeof(FactorSlot) * pb.factors.size(),
+                          hipMemcpyHostToDevice, s));
+  if (!ut.empty())
+    SMFS_HIP(hipMemcpyAsync(pb.d_utask, ut.data(), sizeof(RowTask) * ut.size(), hipMemcpyHostToDevice, s));
+  if (!vt.empty())
+    SMFS_HIP(hipMemcpyAsync(pb.d_vtask, vt.data(), sizeof(RowTask) * vt.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  bool ready = true;
+  for (int k = 0; k < pb.P; ++k)
+    if (pb.meta[k].rank <= 0) ready = false;
+  pb.factors_ready = ready;
+  return SMFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Building blocks of the product.
+
+int transform(Problem &pb, const double *mu, double *lam, hipStream_t s) {
+  SMFS_HIP(launch_pinv_u(pb.d_utask, pb.n_utask, pb.d_meta, pb.d_fslots, pb.d_fac, mu, pb.d_s, s));
+  SMFS_HIP(launch_pinv_v(pb.d_vtask, pb.n_vtask, pb.d_meta, pb.d_fslots, pb.d_fac, pb.d_s, lam, s));
+  return SMFS_OK;
+}
+
+DirectArgs direct_args(Problem &pb, const double *str) {
+  DirectArgs a;
+  a.tiles = pb.d_tiles;
+  a.n_tiles = pb.n_tiles;
+  a.tgt = pb.d_tgt;
+  a.src = pb.d_src;
+  a.str = str;
+  a.meta = pb.d_meta;
+  a.kb[0] = pb.koff[0][0];
+  a.kb[1] = pb.koff[1][0];
+  a.kb[2] = pb.koff[2][0];
+  a.kb[3] = pb.S;
+  a.dscale = 2.0 * pb.prm.mu;
+  a.n_splits = pb.n_splits;
+  a.T = pb.T;
+  a.part = pb.d_part;
+  return a;
+}
+
+// Event pool for smfs_profile: returns the index of a recorded event.
+int record_event(Problem &pb, hipStream_t s, size_t &idx) {
+  if (pb.ev_used == pb.ev_pool.size()) {
+    hipEvent_t e;
+    SMFS_HIP(hipEventCreate(&e));
+    pb.ev_pool.push_back(e);
+  }
+  idx = pb.ev_used++;
+  SMFS_HIP(hipEventRecord(pb.ev_pool[idx], s));
+  return SMFS_OK;
+}
+
+int apply(Problem &pb, const double *mu, double *y, hipStream_t s) {
+  size_t e0 = 0, e1 = 0, e2 = 0;
+  int rc;
+  if (pb.prof && (rc = record_event(pb, s, e0))) return rc;
+  rc = transform(pb, mu, pb.d_lamhat, s);
+  if (rc) return rc;
+  if (pb.prof && (rc = record_event(pb, s, e1))) return rc;
+  DirectArgs a = direct_args(pb, pb.d_lamhat);
+  SMFS_HIP(launch_direct_f64(a, s));
+  if (pb.prof) {
+    if ((rc = record_event(pb, s, e2))) return rc;
+    pb.ev_pinv.emplace_back(e0, e1);
+    pb.ev_direct.emplace_back(e1, e2);
+  }
+  SMFS_HIP(launch_reduce_epilogue(3 * pb.T, pb.n_splits, pb.d_part, mu, pb.d_sw,
+                                  1.0 / (8.0 * kPi * pb.prm.mu), y, s));
+  return SMFS_OK;
+}
+
+// u = sum over every source at n free points (chunked to the part buffer).
+int eval_points(Problem &pb, const double *lam, int64_t n, const double *x, double *u, hipStream_t s) {
+  if (n <= 0) return SMFS_OK;
+  const int32_t sp = pb.n_splits_chk;
+  int64_t cap = pb.part_cap / (3 * sp);   // points whose partial sums fit
+  if (cap >= kTileTargets) cap = cap / kTileTargets * kTileTargets;
+  if (cap < 1) { set_error("partial-sum buffer too small"); return SMFS_E_NOMEM; }
+  for (int64_t o = 0; o < n; o += cap) {
+    const int64_t cnt = std::min(cap, n - o);
+    DirectArgs a = direct_args(pb, lam);
+    a.tiles = nullptr;
+    a.n_tiles = free_tiles(cnt);
+    a.tgt = x + 3 * o;
+    a.n_splits = sp;
+    a.T = cnt;
+    SMFS_HIP(launch_direct_f64(a, s));
+    SMFS_HIP(launch_reduce_epilogue(3 * cnt, sp, pb.d_part, nullptr, nullptr,
+                                    1.0 / (8.0 * kPi * pb.prm.mu), u + 3 * o, s));
+  }
+  return SMFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES on G_hat mu = b with x0 = 0; Arnoldi by classical Gram-Schmidt
+// applied twice, Givens rotations on the host (the Hessenberg column is
+// read back once per iteration), restarted every gmres_restart steps.
+
+struct GmresStats {
+  int iterations = 0;
+  double rel_residual = 0.0;
+  bool converged = false;
+};
+
+int gmres(Problem &pb, const double *b, double *x, GmresStats &st, hipStream_t s) {
+  const int64_t n = 3 * pb.T, ld = pb.kry_ld;
+  const int m = pb.kry_vecs - 1;
+  const int max_it = pb.prm.gmres_max_it;
+  const double tol = pb.prm.gmres_tol;
+  double *V = pb.d_kry;
+  double *w = pb.d_vec;           // scratch vector
+  double *r = pb.d_vec + ld;      // residual
+  const int32_t nch = mdot_chunks(n);
+  double *part = pb.d_red;
+  double *h = pb.d_red + (int64_t)nch * (m + 2);
+  double *h2 = h + (m + 2);
+  double *cf = h2 + (m + 2);
+  double *scal = cf + (m + 2);    // [0] = beta, [1] = norm out
+  std::vector<double> hh(m + 2), H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  double *hpin = nullptr;
+  SMFS_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * (2 * m + 8), hipHostMallocDefault));
+  struct Free {
+    double *p;
+    ~Free() { if (p) (void)hipHostFree(p); }
+  } guard{hpin};
+
+  SMFS_HIP(launch_fill(n, 0.0, x, s));
+  SMFS_HIP(launch_norm2(b, n, part, nch, scal + 1, s));
+  SMFS_HIP(hipMemcpyAsync(hpin, scal + 1, 8, hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  const double bnorm = hpin[0];
+  st = GmresStats{};
+  if (bnorm == 0.0) {
+    st.converged = true;
+    return SMFS_OK;
+  }
+  SMFS_HIP(hipMemcpyAsync(r, b, 8 * n, hipMemcpyDeviceToDevice, s));
+  double beta = bnorm;
+  int total = 0;
+  while (true) {
+    // V[0] = r / beta
+    SMFS_HIP(hipMemcpyAsync(V, r, 8 * n, hipMemcpyDeviceToDevice, s));
+    SMFS_HIP(launch_norm_scale(V, n, part, nch, scal, scal + 1, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jdone = 0;
+    bool stop = false;
+    for (int j = 0; j < m; ++j) {
+      double *vj1 = V + (int64_t)(j + 1) * ld;
+      int rc = apply(pb, V + (int64_t)j * ld, vj1, s);
+      if (rc) return rc;
+      // classical Gram-Schmidt, twice: h = V^T w, w -= V h; h2 = V^T w, w -= V h2
+      SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h, false, s));
+      SMFS_HIP(launch_mupdate(V, ld, j + 1, h, vj1, n, s));
+      SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h2, false, s));
+      SMFS_HIP(launch_mupdate(V, ld, j + 1, h2, vj1, n, s));
+      SMFS_HIP(launch_norm_scale(vj1, n, part, nch, h + (j + 1), scal + 1, s));
+      SMFS_HIP(hipMemcpyAsync(hpin, h, 8 * (j + 2), hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipMemcpyAsync(hpin + (m + 2), h2, 8 * (j + 1), hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i <= j + 1; ++i)
+        H[(size_t)j * (m + 1) + i] = hpin[i] + (i <= j ? hpin[m + 2 + i] : 0.0);
+      double *col = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = den > 0 ? col[j] / den : 1.0;
+      sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      jdone = j + 1;
+      st.rel_residual = std::fabs(g[j + 1]) / bnorm;
+      if (st.rel_residual <= tol) { st.converged = true; stop = true; break; }
+      if (total >= max_it || hpin[j + 1] == 0.0) { stop = true; break; }
+    }
+    // y = H^-1 g (upper triangular), x += V y
+    for (int i = jdone - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int c = i + 1; c < jdone; ++c) t -= H[(size_t)c * (m + 1) + i] * y[c];
+      y[i] = t / H[(size_t)i * (m + 1) + i];
+    }
+    SMFS_HIP(hipMemcpyAsync(cf, y.data(), 8 * jdone, hipMemcpyHostToDevice, s));
+    SMFS_HIP(launch_combine(V, ld, jdone, cf, x, n, s));
+    SMFS_HIP(hipStreamSynchronize(s));
+    st.iterations = total;
+    if (stop) return SMFS_OK;
+    // restart from the true residual
+    int rc = apply(pb, x, w, s);
+    if (rc) return rc;
+    SMFS_HIP(launch_sub(n, b, w, r, s));
+    SMFS_HIP(launch_norm2(r, n, part, nch, scal + 1, s));
+    SMFS_HIP(hipMemcpyAsync(hpin, scal + 1, 8, hipMemcpyDeviceToHost, s));
+    SMFS_HIP(hipStreamSynchronize(s));
+    beta = hpin[0];
+    if (beta / bnorm <= tol) {
+      st.converged = true;
+      st.rel_residual = beta / bnorm;
+      return SMFS_OK;
+    }
+  }
+}
+
+}  // namespace smfs
+
+using namespace smfs;
+
+struct smfs_problem : Problem {};
+
+extern "C" {
+
+const char *smfs_last_error(void) { return g_err.c_str(); }
+
+int smfs_params_default(smfs_params *p) {
+  if (!p) { set_error("null params"); return SMFS_E_INVALID_ARG; }
+  std::memset(p, 0, sizeof(*p));
+  p->n_proxy = 600;
+  p->proxy_radius = 0.7;
+  p->n_colloc_base = 780;
+  p->n_image = 20;
+  p->image_kinds = SMFS_KIND_S | SMFS_KIND_R | SMFS_KIND_D;
+  p->image_offset = 0.05;
+  p->image_gap_cutoff = 0.2;
+  p->near_gap_cutoff = 0.2;
+  p->cap_alpha[0] = p->cap_alpha[1] = 6;
+  p->cap_beta[0] = kPi / 5.0;
+  p->cap_beta[1] = kPi / 60.0;
+  p->left_weights = 1;
+  p->trunc_rel = 5e-12;
+  p->mu = 1.0;
+  p->n_check_base = 500;
+  p->precision = SMFS_FP64;
+  p->gmres_tol = 1e-10;
+  p->gmres_max_it = 1000;
+  p->gmres_restart = 400;
+  return SMFS_OK;
+}
+
+int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
+                        const double *radii, smfs_problem **out) {
+  if (!p || !centers || !radii || !out || P <= 0) {
+    set_error("smfs_problem_create: null argument or P <= 0");
+    return SMFS_E_INVALID_ARG;
+  }
+  *out = nullptr;
+  if (p->n_proxy <= 0 || p->n_colloc_base <= 0 || !(p->proxy_radius > 0 && p->proxy_radius < 1) ||
+      !(p->mu > 0) || !(p->trunc_rel >= 0) || p->gmres_restart <= 0 || p->gmres_max_it <= 0 ||
+      p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 ||
+      (p->precision != SMFS_FP64 && p->precision != SMFS_MIXED)) {
+    set_error("smfs_problem_create: invalid parameter");
+    return SMFS_E_INVALID_ARG;
+  }
+  for (int i = 0; i < 3 * P; ++i)
+    if (!std::isfinite(centers[i])) {
+      set_error("smfs_problem_create: non-finite centre");
+      return SMFS_E_INVALID_ARG;
+    }
+  for (int k = 0; k < P; ++k) {
+    if (!(radii[k] > 0) || !std::isfinite(radii[k])) {
+      set_error("smfs_problem_create: radius must be positive");
+      return SMFS_E_INVALID_ARG;
+    }
+    if (radii[k] != radii[0]) {
+      set_error("smfs_problem_create: spheres of unequal radii are not supported");
+      return SMFS_E_UNSUPPORTED;
+    }
+  }
+  smfs_problem *pb = new smfs_problem();
+  pb->prm = *p;
+  pb->P = P;
+  pb->a = radii[0];
+  pb->centers.assign(centers, centers + 3 * P);
+  int rc = build_geometry(*pb);
+  if (rc < 0) { delete pb; return rc; }
+  pb->need_bytes = workspace_layout(*pb, false);
+  *out = pb;
+  return pb->small_gap ? SMFS_GAP_BELOW_VALIDATED : SMFS_OK;
+}
+
+void smfs_problem_destroy(smfs_problem *pb) {
+  if (!pb) return;
+  for (hipEvent_t e : pb->ev_pool) (void)hipEventDestroy(e);
+  if (pb->rocblas) rocblas_destroy_handle((rocblas_handle)pb->rocblas);
+  delete pb;
+}
+
+int smfs_problem_sizes(const smfs_problem *pb, smfs_sizes *s) {
+  if (!pb || !s) { set_error("null argument"); return SMFS_E_INVALID_ARG; }
+  std::memset(s, 0, sizeof(*s));
+  s->P = pb->P;
+  s->n_factors = (int32_t)pb->factors.size();
+  s->n_contacts = pb->n_contacts;
+  s->min_gap_flag = pb->small_gap ? 1 : 0;
+  s->T = pb->T;
+  s->S = pb->S;
+  for (int i = 0; i < 3; ++i) s->n_kind[i] = pb->nk[i];
+  s->n_check = pb->C;
+  s->workspace_bytes = pb->need_bytes;
+  s->factor_bytes = pb->factor_bytes;
+  return SMFS_OK;
+}
+
+int smfs_export_nodes(const smfs_problem *pb, double *targets, int32_t *target_sphere,
+                      double *target_weight, double *sources, int32_t *source_kind,
+                      int32_t *source_sphere, double *check, int32_t *check_sphere) {
+  if (!pb) { set_error("null problem"); return SMFS_E_INVALID_ARG; }
+  if (targets) std::memcpy(targets, pb->tgt.data(), 8 * pb->tgt.size());
+  if (target_sphere) std::memcpy(target_sphere, pb->tsph.data(), 4 * pb->tsph.size());
+  if (target_weight) std::memcpy(target_weight, pb->tw.data(), 8 * pb->tw.size());
+  if (sources) std::memcpy(sources, pb->src.data(), 8 * pb->src.size());
+  if (source_kind) std::memcpy(source_kind, pb->skind.data(), 4 * pb->skind.size());
+  if (source_sphere) std::memcpy(source_sphere, pb->ssph.data(), 4 * pb->ssph.size());
+  if (check) std::memcpy(check, pb->chk.data(), 8 * pb->chk.size());
+  if (check_sphere) std::memcpy(check_sphere, pb->csph.data(), 4 * pb->csph.size());
+  return SMFS_OK;
+}
+
+int smfs_sphere_factor(const smfs_problem *pb, int32_t k, int32_t *fid) {
+  if (!pb || !fid || k < 0 || k >= pb->P) { set_error("bad sphere index"); return SMFS_E_INVALID_ARG; }
+  *fid = pb->fid_of[k];
+  return SMFS_OK;
+}
+
+int smfs_factor_info(const smfs_problem *pb, int32_t fid, int32_t *rows, int32_t *cols,
+                     int32_t *rank, int32_t *sphere) {
+  if (!pb || fid < 0 || fid >= (int32_t)pb->factors.size()) {
+    set_error("bad factor id");
+    return SMFS_E_INVALID_ARG;
+  }
+  const FactorSlot &f = pb->factors[fid];
+  if (rows) *rows = f.rows;
+  if (cols) *cols = f.cols;
+  if (rank) *rank = f.rank;
+  if (sphere) *sphere = f.rep;
+  return SMFS_OK;
+}
+
+int smfs_bind(smfs_problem *pb, void *ws, size_t bytes, smfs_stream stream) {
+  if (!pb || !ws) { set_error("smfs_bind: null argument"); return SMFS_E_INVALID_ARG; }
+  if (bytes < pb->need_bytes) {
+    set_error("smfs_bind: workspace of " + std::to_string(bytes) + " bytes, need " +
+              std::to_string(pb->need_bytes));
+    return SMFS_E_NOMEM;
+  }
+  if (((uintptr_t)ws) % kAlign) { set_error("smfs_bind: workspace must be 256-byte aligned"); return SMFS_E_INVALID_ARG; }
+  pb->ws = (char *)ws;
+  pb->ws_bytes = bytes;
+  for (auto &f : pb->factors) f.rank = 0;
+  workspace_layout(*pb, true);
+  int rc = upload_tables(*pb, (hipStream_t)stream);
+  if (rc) return rc;
+  pb->bound = true;
+  return SMFS_OK;
+}
+
+int smfs_setup(smfs_problem *pb, smfs_stream stream) {
+  if (!pb || !pb->bound) { set_error("smfs_setup: problem not bound"); return SMFS_E_STATE; }
+  hipStream_t s = (hipStream_t)stream;
+  if (!pb->rocblas) {
+    rocblas_handle h;
+    if (rocblas_create_handle(&h) != rocblas_status_success) {
+      set_error("rocblas_create_handle failed");
+      return SMFS_E_DEVICE;
+    }
+    pb->rocblas = h;
+  }
+  rocblas_handle h = (rocblas_handle)pb->rocblas;
+  rocblas_set_stream(h, s);
+  // groups of equal shape, consecutive in the workspace (see workspace_layout)
+  std::vector<int> order;
+  for (size_t f = 0; f < pb->factors.size(); ++f)
+    if (pb->factors[f].rep >= 0) order.push_back((int)f);
+  std::sort(order.begin(), order.end(),
+            [&](int x, int y) { return pb->factors[x].u_off < pb->factors[y].u_off; });
+  size_t g0 = 0;
+  while (g0 < order.size()) {
+    const FactorSlot &first = pb->factors[order[g0]];
+    const int m = first.rows, n = first.cols;
+    size_t g1 = g0 + 1;
+    while (g1 < order.size() && pb->factors[order[g1]].rows == m && pb->factors[order[g1]].cols == n) ++g1;
+    const int64_t stride = g1 - g0 > 1 ? pb->factors[order[g0 + 1]].u_off - first.u_off : 0;
+    // batches bounded by the scratch copy of the input blocks (<= 8 GiB, <= 32)
+    const size_t per = sizeof(double) * (size_t)m * n;
+    const size_t bmax = std::max<size_t>(1, std::min<size_t>(32, ((size_t)8 << 30) / per));
+    for (size_t b0 = g0; b0 < g1; b0 += bmax) {
+      const int nb = (int)std::min(bmax, g1 - b0);
+      double *A = nullptr, *E = nullptr;
+      rocblas_int *info = nullptr;
+      SMFS_HIP(hipMalloc((void **)&A, per * nb));
+      SMFS_HIP(hipMalloc((void **)&E, sizeof(double) * (size_t)n * nb));
+      SMFS_HIP(hipMalloc((void **)&info, sizeof(rocblas_int) * nb));
+      struct Free {
+        void *a, *b, *c;
+        ~Free() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c); }
+      } guard{A, E, info};
+      for (int q = 0; q < nb; ++q) {
+        const FactorSlot &fs = pb->factors[order[b0 + q]];
+        const SphereMeta &mk = pb->meta[fs.rep];
+        SMFS_HIP(launch_assemble_block(pb->d_tgt, pb->d_sw, pb->d_src, pb->d_meta, fs.rep, mk.M, mk.N,
+                                       pb->prm.mu, A + (size_t)q * m * n, s));
+      }
+      const FactorSlot &fb = pb->factors[order[b0]];
+      double *U = pb->d_fac + fb.u_off, *VT = pb->d_fac + fb.vt_off, *sig = pb->d_fac + fb.sig_off;
+      rocblas_status st = rocsolver_dgesvd_strided_batched(
+          h, rocblas_svect_singular, rocblas_svect_singular, m, n, A, m, (rocblas_stride)m * n, sig,
+          (rocblas_stride)stride, U, m, (rocblas_stride)stride, VT, n, (rocblas_stride)stride, E, n,
+          rocblas_outofplace, info, nb);
+      if (st != rocblas_status_success) {
+        set_error("rocsolver_dgesvd_strided_batched failed with status " + std::to_string((int)st));
+        return SMFS_E_SVD;
+      }
+      std::vector<rocblas_int> hinfo(nb);
+      std::vector<double> sv((size_t)n * nb);
+      SMFS_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * nb, hipMemcpyDeviceToHost, s));
+      for (int q = 0; q < nb; ++q)
+        SMFS_HIP(hipMemcpyAsync(sv.data() + (size_t)q * n, sig + (size_t)q * stride, 8 * (size_t)n,
+                                hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < nb; ++q) {
+        const double *sq = sv.data() + (size_t)q * n;
+        if (hinfo[q] != 0 || !(sq[0] > 0)) {
+          set_error("SVD did not converge (info " + std::to_string(hinfo[q]) + ")");
+          return SMFS_E_SVD;
+        }
+        int r = 0;
+        while (r < n && sq[r] > pb->prm.trunc_rel * sq[0]) ++r;
+        pb->factors[order[b0 + q]].rank = r;
+      }
+    }
+    g0 = g1;
+  }
+  return rank_tables(*pb, s);
+}
+
+int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double *U,
+                       const double *sigma, const double *V, smfs_stream stream) {
+  if (!pb || !pb->bound) { set_error("smfs_import_factor: problem not bound"); return SMFS_E_STATE; }
+  if (fid < 0 || fid >= (int32_t)pb->factors.size() || !U || !sigma || !V) {
+    set_error("smfs_import_factor: bad argument");
+    return SMFS_E_INVALID_ARG;
+  }
+  FactorSlot &fs = pb->factors[fid];
+  if (fs.rep < 0 || rank <= 0 || rank > fs.cols) {
+    set_error("smfs_import_factor: rank out of range or unused factor");
+    return SMFS_E_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  SMFS_HIP(hipMemcpyAsync(pb->d_fac + fs.u_off, U, 8 * (size_t)fs.rows * rank, hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb->d_fac + fs.sig_off, sigma, 8 * (size_t)rank, hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpy2DAsync(pb->d_fac + fs.vt_off, 8 * (size_t)fs.cols, V, 8 * (size_t)rank,
+                            8 * (size_t)rank, fs.cols, hipMemcpyHostToDevice, s));
+  fs.rank = rank;
+  return rank_tables(*pb, s);
+}
+
+#define SMFS_READY(pb)                                                        \
+  do {                                                                        \
+    if (!(pb) || !(pb)->bound) { set_error("problem not bound"); return SMFS_E_STATE; } \
+    if (!(pb)->factors_ready) { set_error("factors not set up"); return SMFS_E_STATE; } \
+  } while (0)
+
+int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision, smfs_stream stream) {
+  SMFS_READY(pb);
+  if (!mu || !y || mu == y) { set_error("smfs_apply: bad vectors"); return SMFS_E_INVALID_ARG; }
+  if (precision != SMFS_FP64 && precision != SMFS_MIXED) { set_error("bad precision"); return SMFS_E_INVALID_ARG; }
+  return apply(*pb, mu, y, (hipStream_t)stream);
+}
+
+int smfs_transform(smfs_problem *pb, const double *mu, double *lam, smfs_stream stream) {
+  SMFS_READY(pb);
+  if (!mu || !lam) { set_error("smfs_transform: null vector"); return SMFS_E_INVALID_ARG; }
+  return transform(*pb, mu, lam, (hipStream_t)stream);
+}
+
+int smfs_rhs(smfs_problem *pb, const double *rbm, double *b, smfs_stream stream) {
+  if (!pb || !pb->bound) { set_error("problem not bound"); return SMFS_E_STATE; }
+  if (!rbm || !b) { set_error("smfs_rhs: null vector"); return SMFS_E_INVALID_ARG; }
+  SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm, b, (hipStream_t)stream));
+  return SMFS_OK;
+}
+
+int smfs_force_torque(smfs_problem *pb, const double *lam, double *ft, smfs_stream stream) {
+  if (!pb || !pb->bound) { set_error("problem not bound"); return SMFS_E_STATE; }
+  if (!lam || !ft) { set_error("smfs_force_torque: null vector"); return SMFS_E_INVALID_ARG; }
+  SMFS_HIP(launch_force_torque(pb->P, pb->d_meta, pb->d_src, lam, ft, (hipStream_t)stream));
+  return SMFS_OK;
+}
+
+int smfs_eval_velocity(smfs_problem *pb, const double *lam, int64_t n, const double *x, double *u,
+                       smfs_stream stream) {
+  if (!pb || !pb->bound) { set_error("problem not bound"); return SMFS_E_STATE; }
+  if (n < 0 || (n > 0 && (!lam || !x || !u))) { set_error("smfs_eval_velocity: bad argument"); return SMFS_E_INVALID_ARG; }
+  return eval_points(*pb, lam, n, x, u, (hipStream_t)stream);
+}
+
+int64_t smfs_pairs_per_apply(const smfs_problem *pb) { return pb ? pb->pairs_per_apply : 0; }
+
+int smfs_profile(smfs_problem *pb, int32_t enable) {
+  if (!pb) { set_error("null problem"); return SMFS_E_INVALID_ARG; }
+  if (enable) {
+    pb->ev_used = 0;
+    pb->ev_direct.clear();
+    pb->ev_pinv.clear();
+  }
+  pb->prof = enable != 0;
+  return SMFS_OK;
+}
+
+int smfs_profile_read(smfs_problem *pb, smfs_kernel_stats *st) {
+  if (!pb || !st) { set_error("null argument"); return SMFS_E_INVALID_ARG; }
+  std::memset(st, 0, sizeof(*st));
+  for (auto &pr : pb->ev_direct) {
+    float ms = 0.f;
+    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
+    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
+    st->direct_ms += ms;
+  }
+  for (auto &pr : pb->ev_pinv) {
+    float ms = 0.f;
+    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
+    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
+    st->pinv_ms += ms;
+  }
+  st->direct_launches = (int64_t)pb->ev_direct.size();
+  st->pinv_launches = (int64_t)pb->ev_pinv.size();
+  st->direct_flops = 28.0 * pb->pairs_kind[0] + 25.0 * pb->pairs_kind[1] + 30.0 * pb->pairs_kind[2];
+  double bytes = 0.0;
+  for (int k = 0; k < pb->P; ++k) {
+    const FactorSlot &f = pb->factors[pb->fid_of[k]];
+    bytes += 8.0 * ((double)f.rows * f.rank + (double)f.cols * f.rank);
+  }
+  st->pinv_bytes = bytes;
+  return SMFS_OK;
+}
+
+int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out, smfs_stream stream) {
+  SMFS_READY(pb);
+  if (!rbm || !out) { set_error("smfs_solve_resistance: null argument"); return SMFS_E_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  using clk = std::chrono::steady_clock;
+  auto ms = [](clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  const int64_t n = 3 * pb->T, ld = pb->kry_ld;
+  double *b = pb->d_vec + 2 * ld;
+  double *x = out->mu ? out->mu : pb->d_vec + 3 * ld;
+  auto t0 = clk::now();
+  SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm, b, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  auto t1 = clk::now();
+  GmresStats st;
+  int rc = gmres(*pb, b, x, st, s);
+  if (rc) return rc;
+  auto t2 = clk::now();
+  // true residual in FP64
+  double *w = pb->d_vec, *r = pb->d_vec + ld;
+  rc = apply(*pb, x, w, s);
+  if (rc) return rc;
+  const int32_t nch = mdot_chunks(n);
+  double *scal = pb->d_red + pb->red_cap - 8;
+  SMFS_HIP(launch_sub(n, b, w, r, s));
+  SMFS_HIP(launch_norm2(r, n, pb->d_red, nch, scal, s));
+  SMFS_HIP(launch_norm2(b, n, pb->d_red, nch, scal + 1, s));
+  // strengths, forces, residual at check points
+  double *lam = out->lambda ? out->lambda : pb->d_lamhat;
+  rc = transform(*pb, x, lam, s);
+  if (rc) return rc;
+  if (out->ft) SMFS_HIP(launch_force_torque(pb->P, pb->d_meta, pb->d_src, lam, out->ft, s));
+  SMFS_HIP(launch_absmax(3 * pb->S, lam, scal + 2, s));
+  double hs[6] = {0, 0, 0, 0, 0, 0};
+  if (out->u_check && pb->C) {
+    rc = eval_points(*pb, lam, pb->C, pb->d_chk, out->u_check, s);
+    if (rc) return rc;
+    SMFS_HIP(launch_residual_stats(pb->C, pb->d_chk, pb->d_csph, pb->d_meta, rbm, out->u_check,
+                                   1e-3, scal + 3, s));
+  }
+  SMFS_HIP(hipMemcpyAsync(hs, scal, 8 * 6, hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  auto t3 = clk::now();
+  out->iterations = st.iterations;
+  out->rel_residual = st.rel_residual;
+  out->true_rel_residual = hs[1] > 0 ? hs[0] / hs[1] : 0.0;
+  out->lambda_inf = hs[2];
+  out->eps_res_max = (out->u_check && pb->C) ? hs[3] : -1.0;
+  out->abs_res_max = (out->u_check && pb->C && hs[5] > 0) ? hs[4] / hs[5] : -1.0;
+  out->t_rhs_ms = ms(t0, t1);
+  out->t_gmres_ms = ms(t1, t2);
+  out->t_post_ms = ms(t2, t3);
+  out->pair_evals = (int64_t)(st.iterations + 1) * pb->pairs_per_apply +
+                    ((out->u_check) ? pb->C * pb->S : 0);
+  return st.converged ? SMFS_OK : SMFS_NOT_CONVERGED;
+}
+
+}  // extern "C"

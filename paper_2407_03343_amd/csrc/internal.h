@@ -1,0 +1,137 @@
+// Internal structures of libsmfs (host side plus the device tables).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/smfs.h"
+
+namespace smfs {
+
+void set_error(const std::string &msg);
+
+#define SMFS_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::smfs::set_error(std::string("HIP error ") + hipGetErrorString(e_) + " at " + \
+                        __FILE__ + ":" + std::to_string(__LINE__));                 \
+      return SMFS_E_DEVICE;                                                         \
+    }                                                                               \
+  } while (0)
+
+// One directed near contact of a sphere.
+struct Contact {
+  int32_t other;
+  double gap;      // surface gap in radii
+  double axis[3];  // unit vector towards the neighbour
+  int32_t n_im;    // image nodes on this contact's line
+};
+
+// Per-sphere table entry read by the kernels.
+struct SphereMeta {
+  int64_t t0;       // first collocation node
+  int32_t M;        // collocation nodes
+  int32_t N;        // vector sources (all kinds)
+  int64_t k0[3];    // first source of each kind block (global packed index)
+  int32_t kn[3];    // sources of each kind
+  int32_t fid;      // factor id
+  int32_t rank;     // kept singular values of that factor
+  int64_t s0;       // offset of this sphere's U^T mu entries in the s buffer
+  double c[3];      // centre
+};
+
+// Per-factor storage inside the workspace (element offsets of doubles).
+struct FactorSlot {
+  int32_t rows, cols;   // 3 M, 3 N'
+  int32_t rank;
+  int32_t rep;          // representative sphere
+  int64_t u_off;        // U: rows x cols column-major (first rank columns used)
+  int64_t vt_off;       // V stored row-major: cols rows of stride cols
+  int64_t sig_off;      // sigma (cols)
+};
+
+// Work item of the batched row-dot kernels: one output row.
+struct RowTask {
+  int32_t sphere;
+  int32_t row;
+};
+
+struct Problem {
+  smfs_params prm;
+  int32_t P = 0;
+  double a = 1.0;
+  std::vector<double> centers;             // P x 3
+  std::vector<std::vector<Contact>> contacts;
+  int32_t n_contacts = 0;
+  bool small_gap = false;
+
+  // node sets (host)
+  std::vector<double> tgt;                 // T x 3
+  std::vector<double> tw;                  // T (area weight)
+  std::vector<int32_t> tsph;               // T
+  std::vector<int64_t> toff;               // P + 1
+  std::vector<double> src;                 // S x 3, packed by kind
+  std::vector<int32_t> skind, ssph;        // S
+  std::vector<int64_t> koff[3];            // per kind: P + 1 global offsets
+  std::vector<double> chk;                 // C x 3
+  std::vector<int32_t> csph;               // C
+  int64_t T = 0, S = 0, C = 0;
+  int64_t nk[3] = {0, 0, 0};
+
+  // factors
+  std::vector<int32_t> fid_of;             // P
+  std::vector<FactorSlot> factors;
+  bool factors_ready = false;
+
+  // workspace
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false;
+  size_t need_bytes = 0, factor_bytes = 0;
+  // device arrays (pointers into the workspace)
+  double *d_tgt = nullptr, *d_sw = nullptr, *d_src = nullptr, *d_lamhat = nullptr;
+  double *d_chk = nullptr, *d_fac = nullptr, *d_part = nullptr, *d_s = nullptr;
+  int32_t *d_tsph = nullptr, *d_csph = nullptr;
+  int4 *d_tiles = nullptr, *d_eval_tiles = nullptr;
+  SphereMeta *d_meta = nullptr;
+  FactorSlot *d_fslots = nullptr;
+  RowTask *d_utask = nullptr, *d_vtask = nullptr;
+  int32_t *d_vmap = nullptr;               // packed source index of local source j, per sphere
+  double *d_kry = nullptr, *d_vec = nullptr, *d_red = nullptr;
+  int64_t n_tiles = 0, n_utask = 0, n_vtask = 0, n_vmap = 0;
+  int32_t n_splits = 1;
+  int32_t n_splits_chk = 1;
+  int64_t kry_ld = 0;
+  int64_t part_cap = 0;                    // doubles in d_part
+  int64_t red_cap = 0;                     // doubles in d_red
+  int32_t kry_vecs = 0;
+
+  // host mirrors of tables
+  std::vector<SphereMeta> meta;
+  std::vector<int4> tiles;
+  std::vector<int32_t> vmap_off;           // P + 1 (offsets into d_vmap)
+
+  void *rocblas = nullptr;                 // rocblas_handle for setup
+  int64_t pairs_per_apply = 0;
+  int64_t pairs_kind[3] = {0, 0, 0};       // per product, by source kind
+
+  // per-launch event timing (smfs_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<size_t, size_t>> ev_direct, ev_pinv;
+};
+
+// geometry.cpp
+int build_geometry(Problem &pb);
+// tables.cpp
+void build_tiles(const Problem &pb, std::vector<int4> &tiles, int tile_targets);
+size_t workspace_layout(Problem &pb, bool assign);
+int upload_tables(Problem &pb, hipStream_t s);
+int rank_tables(Problem &pb, hipStream_t s);
+
+}  // namespace smfs

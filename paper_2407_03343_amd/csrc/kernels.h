@@ -1,0 +1,84 @@
+// Launchers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace smfs {
+
+// Direct sum of every source over target tiles (Section 2.2, eq. uAll, with
+// the self blocks skipped for tiles that name a sphere).  Writes per-split
+// partial sums part[split][T][3] (without the 1/(8 pi mu) factor).
+struct DirectArgs {
+  const int4 *tiles;        // NULL: consecutive free points, 128 per tile
+  int64_t n_tiles;
+  const double *tgt;        // targets x 3
+  const double *src;        // S x 3 positions (packed by kind)
+  const double *str;        // S x 3 strengths
+  const SphereMeta *meta;
+  int64_t kb[4];            // kind boundaries: S block [kb0,kb1), R, D
+  double dscale;            // dipole strengths are multiplied by 2 mu
+  int32_t n_splits;
+  int64_t T;                // targets (partial stride)
+  double *part;
+};
+hipError_t launch_direct_f64(const DirectArgs &a, hipStream_t s);
+
+// y[i] = base[i] + sw[i/3] * c0 * sum_s part[s][i]   (base, sw nullable)
+hipError_t launch_reduce_epilogue(int64_t n3, int32_t n_splits, const double *part,
+                                  const double *base, const double *sw, double c0, double *y,
+                                  hipStream_t s);
+
+// Two-factor pseudo-inverse apply, eq. (transform):
+//   s_k = (U_k^T mu_k) / sigma_k      (one wave per task row)
+//   lambda_hat[k] = V_k s_k           (scattered to packed source order)
+hipError_t launch_pinv_u(const RowTask *tasks, int64_t n, const SphereMeta *meta,
+                         const FactorSlot *fs, const double *fac, const double *mu, double *sbuf,
+                         hipStream_t s);
+hipError_t launch_pinv_v(const RowTask *tasks, int64_t n, const SphereMeta *meta,
+                         const FactorSlot *fs, const double *fac, const double *sbuf,
+                         double *lam, hipStream_t s);
+
+// b = W (v + omega x (x - c)) per collocation node.
+hipError_t launch_rhs(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
+                      const SphereMeta *meta, const double *rbm, double *b, hipStream_t s);
+// forces and torques per sphere
+hipError_t launch_force_torque(int32_t P, const SphereMeta *meta, const double *src,
+                               const double *lam, double *ft, hipStream_t s);
+// residual statistics: out[0] = max eps_res (masked), out[1] = max |u-ubc|, out[2] = max |ubc|
+hipError_t launch_residual_stats(int64_t n, const double *pts, const int32_t *sph,
+                                 const SphereMeta *meta, const double *rbm, const double *u,
+                                 double floor_rel, double *out, hipStream_t s);
+hipError_t launch_absmax(int64_t n, const double *x, double *out, hipStream_t s);
+
+// Self block B = W G^(kk) of sphere k, column-major rows x cols.
+hipError_t launch_assemble_block(const double *tgt, const double *sw, const double *src,
+                                 const SphereMeta *meta, int32_t k, int64_t M, int64_t N, double mu,
+                                 double *B, hipStream_t s);
+
+// GMRES helpers on a Krylov basis stored as nv vectors of stride ld.
+// part must hold nchunks * nv doubles; h gets nv entries (added when acc).
+hipError_t launch_mdot(const double *V, int64_t ld, int32_t nv, const double *w, int64_t n,
+                       double *part, int32_t nchunks, double *h, bool acc, hipStream_t s);
+hipError_t launch_mupdate(const double *V, int64_t ld, int32_t nv, const double *h, double *w,
+                          int64_t n, hipStream_t s);
+hipError_t launch_norm_scale(double *w, int64_t n, double *part, int32_t nchunks, double *beta,
+                             double *out, hipStream_t s);
+// y = a*x + b*y ; x,y length n (a, b host scalars)
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+// y[i] = v
+hipError_t launch_fill(int64_t n, double v, double *y, hipStream_t s);
+// out = x - y
+hipError_t launch_sub(int64_t n, const double *x, const double *y, double *out, hipStream_t s);
+// x += sum_j V[j] c[j] (c on device, nv entries)
+hipError_t launch_combine(const double *V, int64_t ld, int32_t nv, const double *c, double *x,
+                          int64_t n, hipStream_t s);
+hipError_t launch_norm2(const double *w, int64_t n, double *part, int32_t nchunks, double *out,
+                        hipStream_t s);
+
+int32_t mdot_chunks(int64_t n);
+
+}  // namespace smfs

@@ -1,0 +1,303 @@
+"""Thin ctypes binding of libsmfs (the C-ABI in include/smfs.h).
+
+Only argument marshalling lives here: every numerical step runs in the HIP
+library.  PyTorch provides device memory (the caller-owned workspace and the
+vectors) and the current HIP stream.  If libsmfs.so is missing this module
+raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmfs.so")
+
+SMFS_OK = 0
+SMFS_NOT_CONVERGED = 1
+SMFS_GAP_BELOW_VALIDATED = 2
+SMFS_FP64, SMFS_MIXED = 0, 1
+KIND_S, KIND_R, KIND_D = 1, 2, 4
+
+EXPORTED = [
+    "smfs_params_default", "smfs_problem_create", "smfs_problem_destroy", "smfs_problem_sizes",
+    "smfs_export_nodes", "smfs_sphere_factor", "smfs_factor_info", "smfs_bind", "smfs_setup",
+    "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_force_torque",
+    "smfs_eval_velocity", "smfs_solve_resistance", "smfs_pairs_per_apply", "smfs_profile",
+    "smfs_profile_read", "smfs_last_error",
+]
+
+
+class smfs_params(C.Structure):
+    _fields_ = [
+        ("n_proxy", C.c_int32), ("proxy_radius", C.c_double), ("n_colloc_base", C.c_int32),
+        ("n_image", C.c_int32), ("image_kinds", C.c_uint32), ("image_offset", C.c_double),
+        ("image_gap_cutoff", C.c_double), ("near_gap_cutoff", C.c_double),
+        ("cap_alpha", C.c_int32 * 2), ("cap_beta", C.c_double * 2), ("left_weights", C.c_int32),
+        ("trunc_rel", C.c_double), ("mu", C.c_double), ("n_check_base", C.c_int32),
+        ("precision", C.c_int32), ("gmres_tol", C.c_double), ("gmres_max_it", C.c_int32),
+        ("gmres_restart", C.c_int32),
+    ]
+
+
+class smfs_sizes(C.Structure):
+    _fields_ = [
+        ("P", C.c_int32), ("n_factors", C.c_int32), ("n_contacts", C.c_int32),
+        ("min_gap_flag", C.c_int32), ("T", C.c_int64), ("S", C.c_int64),
+        ("n_kind", C.c_int64 * 3), ("n_check", C.c_int64), ("workspace_bytes", C.c_size_t),
+        ("factor_bytes", C.c_size_t),
+    ]
+
+
+class smfs_out(C.Structure):
+    _fields_ = [
+        ("mu", C.c_void_p), ("lambda_", C.c_void_p), ("ft", C.c_void_p), ("u_check", C.c_void_p),
+        ("iterations", C.c_int32), ("rel_residual", C.c_double),
+        ("true_rel_residual", C.c_double), ("lambda_inf", C.c_double),
+        ("eps_res_max", C.c_double), ("abs_res_max", C.c_double), ("t_rhs_ms", C.c_double),
+        ("t_gmres_ms", C.c_double), ("t_post_ms", C.c_double), ("pair_evals", C.c_int64),
+    ]
+
+
+class smfs_kernel_stats(C.Structure):
+    _fields_ = [
+        ("direct_launches", C.c_int64), ("direct_ms", C.c_double), ("direct_flops", C.c_double),
+        ("pinv_launches", C.c_int64), ("pinv_ms", C.c_double), ("pinv_bytes", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmfs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2407_03343_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "smfs_params_default": ([P(smfs_params)], C.c_int),
+        "smfs_problem_create": ([P(smfs_params), i32, vp, vp, P(vp)], C.c_int),
+        "smfs_problem_destroy": ([vp], None),
+        "smfs_problem_sizes": ([vp, P(smfs_sizes)], C.c_int),
+        "smfs_export_nodes": ([vp] + [vp] * 8, C.c_int),
+        "smfs_sphere_factor": ([vp, i32, P(i32)], C.c_int),
+        "smfs_factor_info": ([vp, i32, P(i32), P(i32), P(i32), P(i32)], C.c_int),
+        "smfs_bind": ([vp, vp, C.c_size_t, vp], C.c_int),
+        "smfs_setup": ([vp, vp], C.c_int),
+        "smfs_import_factor": ([vp, i32, i32, vp, vp, vp, vp], C.c_int),
+        "smfs_apply": ([vp, vp, vp, i32, vp], C.c_int),
+        "smfs_transform": ([vp, vp, vp, vp], C.c_int),
+        "smfs_rhs": ([vp, vp, vp, vp], C.c_int),
+        "smfs_force_torque": ([vp, vp, vp, vp], C.c_int),
+        "smfs_eval_velocity": ([vp, vp, i64, vp, vp, vp], C.c_int),
+        "smfs_solve_resistance": ([vp, vp, P(smfs_out), vp], C.c_int),
+        "smfs_pairs_per_apply": ([vp], i64),
+        "smfs_profile": ([vp, i32], C.c_int),
+        "smfs_profile_read": ([vp, P(smfs_kernel_stats)], C.c_int),
+        "smfs_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+class SmfsError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().smfs_last_error().decode()
+        super().__init__(f"{where} failed with code {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, where, ok=(SMFS_OK,)):
+    if rc not in ok:
+        raise SmfsError(rc, where)
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def params_default(**over) -> smfs_params:
+    p = smfs_params()
+    _check(lib().smfs_params_default(C.byref(p)), "smfs_params_default")
+    for k, v in over.items():
+        if k in ("cap_alpha", "cap_beta"):
+            arr = getattr(p, k)
+            arr[0], arr[1] = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class Problem:
+    """One discretised resistance problem (host geometry + device state)."""
+
+    def __init__(self, centers, radius=1.0, params: smfs_params | None = None, **over):
+        self.params = params if params is not None else params_default(**over)
+        c = np.ascontiguousarray(centers, np.float64).reshape(-1, 3)
+        self.P = c.shape[0]
+        r = np.full(self.P, float(radius))
+        h = C.c_void_p()
+        rc = lib().smfs_problem_create(C.byref(self.params), self.P, _np_ptr(c), _np_ptr(r), C.byref(h))
+        _check(rc, "smfs_problem_create", ok=(SMFS_OK, SMFS_GAP_BELOW_VALIDATED))
+        self.gap_warning = rc == SMFS_GAP_BELOW_VALIDATED
+        self.h = h
+        self.sizes = smfs_sizes()
+        _check(lib().smfs_problem_sizes(self.h, C.byref(self.sizes)), "smfs_problem_sizes")
+        self.T, self.S, self.n_check = self.sizes.T, self.sizes.S, self.sizes.n_check
+        self.ws = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().smfs_problem_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # -- host introspection ---------------------------------------------------
+    def export_nodes(self):
+        T, S, Cn = self.T, self.S, self.n_check
+        out = dict(targets=np.zeros((T, 3)), target_sphere=np.zeros(T, np.int32),
+                   target_weight=np.zeros(T), sources=np.zeros((S, 3)),
+                   source_kind=np.zeros(S, np.int32), source_sphere=np.zeros(S, np.int32),
+                   check=np.zeros((Cn, 3)), check_sphere=np.zeros(Cn, np.int32))
+        _check(lib().smfs_export_nodes(self.h, *[_np_ptr(out[k]) for k in (
+            "targets", "target_sphere", "target_weight", "sources", "source_kind",
+            "source_sphere", "check", "check_sphere")]), "smfs_export_nodes")
+        return out
+
+    def sphere_factor(self, k):
+        f = C.c_int32()
+        _check(lib().smfs_sphere_factor(self.h, k, C.byref(f)), "smfs_sphere_factor")
+        return f.value
+
+    def factor_info(self, fid):
+        r, c, k, s = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().smfs_factor_info(self.h, fid, C.byref(r), C.byref(c), C.byref(k), C.byref(s)),
+               "smfs_factor_info")
+        return dict(rows=r.value, cols=c.value, rank=k.value, sphere=s.value)
+
+    @property
+    def pairs_per_apply(self):
+        return int(lib().smfs_pairs_per_apply(self.h))
+
+    def profile(self, enable: bool):
+        _check(lib().smfs_profile(self.h, 1 if enable else 0), "smfs_profile")
+
+    def profile_read(self) -> dict:
+        st = smfs_kernel_stats()
+        _check(lib().smfs_profile_read(self.h, C.byref(st)), "smfs_profile_read")
+        return {k: getattr(st, k) for k, _ in smfs_kernel_stats._fields_}
+
+    # -- device ----------------------------------------------------------------
+    def bind(self, device="cuda"):
+        import torch
+        nbytes = int(self.sizes.workspace_bytes)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        _check(lib().smfs_bind(self.h, C.c_void_p(aligned), nbytes, _stream()), "smfs_bind")
+        return self
+
+    def setup(self):
+        _check(lib().smfs_setup(self.h, _stream()), "smfs_setup")
+        return self
+
+    def import_factor(self, fid, U, sigma, V):
+        U = np.asfortranarray(U, np.float64)          # rows x rank, column-major
+        V = np.ascontiguousarray(V, np.float64)       # cols x rank, row-major
+        s = np.ascontiguousarray(sigma, np.float64)
+        info = self.factor_info(fid)
+        r = s.size
+        if U.shape != (info["rows"], r) or V.shape != (info["cols"], r) or not 0 < r <= info["cols"]:
+            raise ValueError(f"factor {fid}: expected U {info['rows']}x{r} and V {info['cols']}x{r}")
+        _check(lib().smfs_import_factor(self.h, fid, s.size, _np_ptr(U), _np_ptr(s), _np_ptr(V),
+                                        _stream()), "smfs_import_factor")
+
+    def _dvec(self, n, like=None):
+        import torch
+        return torch.empty(n, dtype=torch.float64, device="cuda")
+
+    @staticmethod
+    def _need(t, n, what):
+        import torch
+        if (not torch.is_tensor(t) or t.dtype != torch.float64 or not t.is_cuda
+                or not t.is_contiguous() or t.numel() != n):
+            raise ValueError(f"{what}: expected a contiguous float64 device tensor of {n} values")
+
+    def apply(self, mu, precision=SMFS_FP64, out=None):
+        self._need(mu, 3 * self.T, "mu")
+        y = out if out is not None else self._dvec(3 * self.T)
+        self._need(y, 3 * self.T, "y")
+        _check(lib().smfs_apply(self.h, _ptr(mu), _ptr(y), precision, _stream()), "smfs_apply")
+        return y
+
+    def transform(self, mu, out=None):
+        self._need(mu, 3 * self.T, "mu")
+        lam = out if out is not None else self._dvec(3 * self.S)
+        self._need(lam, 3 * self.S, "lambda")
+        _check(lib().smfs_transform(self.h, _ptr(mu), _ptr(lam), _stream()), "smfs_transform")
+        return lam
+
+    def rhs(self, rbm):
+        self._need(rbm, 6 * self.P, "rbm")
+        b = self._dvec(3 * self.T)
+        _check(lib().smfs_rhs(self.h, _ptr(rbm), _ptr(b), _stream()), "smfs_rhs")
+        return b
+
+    def force_torque(self, lam):
+        self._need(lam, 3 * self.S, "lambda")
+        ft = self._dvec(6 * self.P)
+        _check(lib().smfs_force_torque(self.h, _ptr(lam), _ptr(ft), _stream()), "smfs_force_torque")
+        return ft
+
+    def eval_velocity(self, lam, x):
+        n = x.numel() // 3
+        self._need(lam, 3 * self.S, "lambda")
+        self._need(x, 3 * n, "points")
+        u = self._dvec(3 * n)
+        _check(lib().smfs_eval_velocity(self.h, _ptr(lam), n, _ptr(x), _ptr(u), _stream()),
+               "smfs_eval_velocity")
+        return u
+
+    def solve_resistance(self, rbm, want_check=True):
+        self._need(rbm, 6 * self.P, "rbm")
+        mu = self._dvec(3 * self.T)
+        lam = self._dvec(3 * self.S)
+        ft = self._dvec(6 * self.P)
+        uc = self._dvec(3 * self.n_check) if (want_check and self.n_check) else None
+        o = smfs_out()
+        o.mu, o.lambda_, o.ft = mu.data_ptr(), lam.data_ptr(), ft.data_ptr()
+        o.u_check = uc.data_ptr() if uc is not None else None
+        rc = lib().smfs_solve_resistance(self.h, _ptr(rbm), C.byref(o), _stream())
+        _check(rc, "smfs_solve_resistance", ok=(SMFS_OK, SMFS_NOT_CONVERGED))
+        return dict(mu=mu, lam=lam, ft=ft, u_check=uc, converged=rc == SMFS_OK,
+                    iterations=o.iterations, rel_residual=o.rel_residual,
+                    true_rel_residual=o.true_rel_residual, lambda_inf=o.lambda_inf,
+                    eps_res_max=o.eps_res_max, abs_res_max=o.abs_res_max,
+                    t_rhs_ms=o.t_rhs_ms, t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms,
+                    pair_evals=o.pair_evals)
