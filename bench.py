@@ -60,6 +60,32 @@ def cpu_baseline(pk, stride: int):
                        f"({rows.size} targets) x {g.S} sources, {pairs:.3g} pairs in {dt:.1f} s")
 
 
+def apply_only(pb, n, wl, torch):
+    for fid in range(pb.sizes.n_factors):
+        info = pb.factor_info(fid)
+        if info["sphere"] < 0:
+            continue
+        U, s, V = wl.random_factors(info["rows"], info["cols"], info["cols"], seed=100 + fid)
+        pb.import_factor(fid, U, s, V)
+    mu = torch.from_numpy(wl.random_vector(3 * pb.T, 3)).cuda()
+    y = torch.empty_like(mu)
+    pb.profile(True)
+    for _ in range(n):
+        pb.apply(mu, out=y)
+    torch.cuda.synchronize()
+    pb.profile(False)
+    st = pb.profile_read()
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    z = torch.empty_like(x)
+    x.fill_(1.0)
+    z.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"apply_only": n, "direct_avg_ms": st["direct_ms"] / max(1, st["direct_launches"]),
+                      "pinv_avg_ms": st["pinv_ms"] / max(1, st["pinv_launches"]),
+                      "direct_flops": st["direct_flops"], "pinv_bytes": st["pinv_bytes"],
+                      "copy_bytes": 1 << 30}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +94,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--apply-only", type=int, default=0, metavar="N",
+                    help="profiling aid: N products with G_hat on the same workload with "
+                         "seeded full-rank factors instead of the SVD setup, then one plain "
+                         "1 GiB device copy (the counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -84,6 +114,9 @@ def main():
         f"workspace={pb.sizes.workspace_bytes / 2**30:.2f} GiB pairs/apply={pb.pairs_per_apply:.3e}")
     pb.bind()
     torch.cuda.synchronize()
+    if args.apply_only:
+        apply_only(pb, args.apply_only, wl, torch)
+        return
     t0 = time.perf_counter()
     pb.setup()
     torch.cuda.synchronize()

@@ -148,14 +148,14 @@ __device__ __forceinline__ void body_d(const double2 (*sh)[kTileSrc], int a, int
   }
 }
 
-template <int kTpl>
+template <int kTpl, bool kFree>
 __global__ __launch_bounds__(kBlock) void k_direct_f64(DirectArgs A) {
   __shared__ double2 sh[3][kTileSrc];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
   int k = -1, t0 = 0, tc = 0;
   if (tile < A.n_tiles) {
-    if (A.tiles) {
+    if (!kFree) {
       const int4 tl = A.tiles[tile];
       k = tl.x;
       t0 = tl.y;
@@ -608,7 +608,12 @@ int32_t mdot_chunks(int64_t n) {
 hipError_t launch_direct_f64(const DirectArgs &a, hipStream_t s) {
   if (a.n_tiles == 0) return hipSuccess;
   dim3 grid((unsigned)((a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)a.n_splits);
-  hipLaunchKernelGGL(k_direct_f64<2>, grid, dim3(kBlock), 0, s, a);
+  // free points (no tile table) get their own instantiation so that kernel
+  // statistics of the product with G_hat are not mixed with flow evaluation
+  if (a.tiles)
+    hipLaunchKernelGGL((k_direct_f64<2, false>), grid, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_direct_f64<2, true>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
