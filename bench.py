@@ -60,6 +60,62 @@ def cpu_baseline(pk, stride: int):
                        f"({rows.size} targets) x {g.S} sources, {pairs:.3g} pairs in {dt:.1f} s")
 
 
+def mixed_vs_fp64(args, torch, smfs, wl):
+    """Solve time to 1e-3 relative surface velocity, plain FP64 against the
+    mixed form, on a cut of the volume-fraction-0.3 packing with 5% of the
+    spheres in near-contact pairs.  The reference is the FP64 solve at
+    tolerance 1e-10; for each form the loosest GMRES tolerance whose
+    check-point velocities and forces meet 1e-3 / 1e-5 is reported."""
+    pk = wl.workload_packing2000(args.mixed_spheres, seed=args.seed)
+    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=1000, gmres_max_it=1000)
+    pb.bind()
+    t0 = time.perf_counter()
+    pb.setup()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    rbm = torch.from_numpy(wl.random_rbm(pb.P, 1, 77)[0].reshape(-1)).cuda()
+    pb.set_solver(smfs.SMFS_FP64, 1e-10)
+    ref = pb.solve_resistance(rbm)
+    u_ref = ref["u_check"].cpu().numpy()
+    ft_ref = ref["ft"].cpu().numpy()
+    log(f"mixed section: {pb.P} spheres, T={pb.T}, S={pb.S}, setup {setup_s:.1f} s, "
+        f"reference it {ref['iterations']}")
+    out = {"spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S,
+           "pairs_per_apply": pb.pairs_per_apply, "reference_iterations": ref["iterations"],
+           "setup_s": setup_s, "forms": {}}
+    for name, prec in (("fp64", smfs.SMFS_FP64), ("mixed", smfs.SMFS_MIXED)):
+        rows = []
+        for tol in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
+            pb.set_solver(prec, tol)
+            pb.solve_resistance(rbm)                       # warm
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t1 = time.perf_counter()
+                o = pb.solve_resistance(rbm)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t1) * 1e3)
+            u = o["u_check"].cpu().numpy()
+            du = float(np.abs(u - u_ref).max() / np.abs(u_ref).max())
+            dft = float(np.abs(o["ft"].cpu().numpy() - ft_ref).max() / np.abs(ft_ref).max())
+            rows.append(dict(tol=tol, iterations=o["iterations"], refinements=o["refinements"],
+                             solve_ms_p50=float(np.percentile(ts, 50)),
+                             solve_ms_p99=float(np.percentile(ts, 99)),
+                             u_rel_err=du, ft_rel_err=dft,
+                             pair_evals=o["pair_evals"], pair_evals_f32=o["pair_evals_f32"],
+                             pair_evals_per_s=o["pair_evals"] / (np.percentile(ts, 50) * 1e-3)))
+            log(f"  {name} tol {tol:.0e}: it {o['iterations']} (+{o['refinements']}), "
+                f"{rows[-1]['solve_ms_p50']:.1f} ms, u err {du:.2e}, F/T err {dft:.2e}")
+        ok = [r for r in rows if r["u_rel_err"] <= 1e-3 and r["ft_rel_err"] <= 1e-5]
+        best = min(ok, key=lambda r: r["solve_ms_p50"]) if ok else None
+        out["forms"][name] = {"scan": rows, "at_1e-3_surface_velocity": best}
+    f64 = out["forms"]["fp64"]["at_1e-3_surface_velocity"]
+    mx = out["forms"]["mixed"]["at_1e-3_surface_velocity"]
+    if f64 and mx:
+        out["speedup_mixed_over_fp64"] = f64["solve_ms_p50"] / mx["solve_ms_p50"]
+    return out
+
+
 def apply_only(pb, n, wl, torch):
     for fid in range(pb.sizes.n_factors):
         info = pb.factor_info(fid)
@@ -94,6 +150,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-vs-FP64 comparison on the volume-fraction-0.3 packing")
+    ap.add_argument("--mixed-spheres", type=int, default=200)
     ap.add_argument("--apply-only", type=int, default=0, metavar="N",
                     help="profiling aid: N products with G_hat on the same workload with "
                          "seeded full-rank factors instead of the SVD setup, then one plain "
@@ -109,7 +168,7 @@ def main():
 
     pk, _ = wl.workload_cluster100(args.seed)
     log(f"workload: {pk.P} spheres, box {pk.box:.2f}, min gap {pk.min_gaps().min():.2e}")
-    pb = smfs.Problem(pk.centers, pk.radius)
+    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=2000, gmres_max_it=2000)
     log(f"T={pb.T} S={pb.S} check={pb.n_check} factors={pb.sizes.n_factors} "
         f"workspace={pb.sizes.workspace_bytes / 2**30:.2f} GiB pairs/apply={pb.pairs_per_apply:.3e}")
     pb.bind()
@@ -152,7 +211,8 @@ def main():
     achieved = st["direct_flops"] / direct_avg_s / 1e12
     pinv_avg_s = st["pinv_ms"] / max(1, st["pinv_launches"]) * 1e-3
     result = {
-        "metric": "Stokeslet pair-evals/s (FP64 resistance solve, 100-sphere cluster)",
+        "metric": "Stokeslet pair-evals/s (FP64 resistance solve, 100-sphere cluster); "
+                  "solve time at 1e-3 relative surface velocity, mixed vs FP64, p50/p99",
         "value": pairs / elapsed,
         "unit": "pair-evals/s",
         "n_gpus": 1,
@@ -167,7 +227,8 @@ def main():
         "config": {
             "workload": "100 unit spheres, cube at volume fraction 0.2, gaps log-uniform [1e-3, 1e-1]; "
                         "N=600 proxy on R_p=0.7, 780 base nodes, 20 S+R+D image nodes per contact "
-                        "(gap < 0.2), caps 2x360; FP64; GMRES tol 1e-10; one resistance solve per step",
+                        "(gap < 0.2), caps 2x360; FP64; GMRES tol 1e-10 (unrestarted, <= 2000 iterations); "
+                        "one resistance solve per step",
             "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S,
             "pairs_per_apply": pb.pairs_per_apply, "precision": "fp64",
         },
@@ -196,6 +257,8 @@ def main():
             "avg_launch_ms": pinv_avg_s * 1e3, "bytes_per_launch": st["pinv_bytes"],
         },
     }
+    if not args.no_mixed:
+        result["mixed_vs_fp64"] = mixed_vs_fp64(args, torch, smfs, wl)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(pk, args.cpu_stride)

@@ -113,6 +113,8 @@ typedef struct smfs_out {
   double abs_res_max;       /* max |u - u_bc| / max |u_bc| */
   double t_rhs_ms, t_gmres_ms, t_post_ms;
   int64_t pair_evals;       /* pair evaluations performed by the solve */
+  int64_t pair_evals_f32;   /* of which evaluated in FP32 (mixed precision) */
+  int32_t refinements;      /* FP64 residual refinement sweeps (mixed precision) */
 } smfs_out;
 
 /* Defaults: N = 600, R_p = 0.7, 780 base nodes, 20 images of kinds S|R|D,
@@ -179,9 +181,19 @@ int smfs_eval_velocity(smfs_problem *pb, const double *lambda, int64_t n, const 
                        double *u, smfs_stream stream);
 
 /* Resistance solve: rbm [dev] P x 6 rigid-body velocities in, outputs per
- * smfs_out.  Returns NOT_CONVERGED (warning) if gmres_max_it is reached. */
+ * smfs_out.  Returns NOT_CONVERGED (warning) if gmres_max_it is reached.
+ * With params.precision = SMFS_MIXED the products inside GMRES take the
+ * sources of contact-free spheres (pseudo-inverse and pair sums) in FP32
+ * and everything else in FP64; Arnoldi, the true residual, up to two
+ * refinement sweeps on the FP64 residual, the back-transform and the
+ * forces stay in FP64. */
 int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out,
                           smfs_stream stream);
+
+/* Change the solver settings of a problem after creation (the Krylov
+ * restart length sizes the workspace and cannot change).  precision is
+ * SMFS_FP64 or SMFS_MIXED; gmres_max_it > 0; gmres_tol > 0. */
+int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32_t gmres_max_it);
 
 /* Pair evaluations in one product with G_hat (all off-sphere pairs). */
 int64_t smfs_pairs_per_apply(const smfs_problem *pb);
@@ -194,10 +206,16 @@ int64_t smfs_pairs_per_apply(const smfs_problem *pb);
 typedef struct smfs_kernel_stats {
   int64_t direct_launches;
   double direct_ms;         /* summed over launches */
-  double direct_flops;      /* algorithmic flops per launch */
+  double direct_flops;      /* algorithmic flops per launch (FP64 product) */
   int64_t pinv_launches;
   double pinv_ms;           /* U^T mu and V s kernels together */
-  double pinv_bytes;        /* algorithmic bytes per launch pair */
+  double pinv_bytes;        /* algorithmic bytes per launch pair (FP64 product) */
+  int64_t far32_launches;   /* mixed precision: FP32 direct sum */
+  double far32_ms;
+  double far32_flops;       /* algorithmic flops per launch (28 per pair) */
+  int64_t mixed64_launches; /* mixed precision: FP64 part of the direct sum */
+  double mixed64_ms;
+  double mixed64_flops;     /* FP64 direct-sum flops per mixed product */
 } smfs_kernel_stats;
 
 /* enable = 1 clears the counters and starts recording; 0 stops. */

@@ -22,11 +22,11 @@ Conventions shared with any implementation that exchanges arrays with this
 oracle (they are a data contract, not code):
   * targets of sphere k: base nodes, then for each contact (neighbours in
     increasing index) the beta_1 cap then the beta_2 cap;
-  * sources are packed globally by kind: every Stokeslet (sphere-major; in a
-    sphere the proxy points first, then image nodes contact by contact),
-    then every rotlet, then every potential dipole, each sphere-major;
+  * sources are packed globally in four blocks, each sphere-major: every
+    proxy Stokeslet, then every image Stokeslet (contact by contact), then
+    every rotlet, then every potential dipole;
   * the local source order of sphere k (the columns of its self block) is
-    its Stokeslets, then its rotlets, then its dipoles;
+    its proxy Stokeslets, image Stokeslets, rotlets, dipoles;
   * vectors are node-major: entry 3 i + c is component c of node i.
 """
 from __future__ import annotations
@@ -38,6 +38,8 @@ import numpy as np
 
 GOLDEN = (1.0 + math.sqrt(5.0)) / 2.0
 KIND_S, KIND_R, KIND_D = 0, 1, 2
+# packing blocks: proxy Stokeslets, image Stokeslets, rotlets, dipoles
+BLOCK_KIND = (KIND_S, KIND_S, KIND_R, KIND_D)
 
 
 @dataclass
@@ -165,12 +167,13 @@ class Geometry:
     src_pos: np.ndarray                # (S, 3), packed by kind
     src_kind: np.ndarray               # (S,)
     src_sphere: np.ndarray             # (S,)
-    kind_offsets: np.ndarray           # (3, P+1): sphere ranges in each kind block
+    kind_offsets: np.ndarray           # (4, P+1): sphere ranges in each packing block
     local_sources: list                # per sphere: packed indices, local order
     check: np.ndarray                  # (C, 3) residual check points
     check_sphere: np.ndarray
     check_offsets: np.ndarray
     n_kind: np.ndarray = field(default_factory=lambda: np.zeros(3, np.int64))
+    n_block: np.ndarray = field(default_factory=lambda: np.zeros(4, np.int64))
 
     @property
     def P(self):
@@ -227,19 +230,18 @@ def build(centers, radius: float, prm: Params | None = None) -> Geometry:
 
     tg, tg_s, tg_w, toff = [], [], [], [0]
     ck, ck_s, coff = [], [], [0]
-    per_kind = {KIND_S: [], KIND_R: [], KIND_D: []}
+    per_block = [[], [], [], []]
     for k in range(P):
         c = centers[k]
         blocks = [c + base]
         wts = [np.full(prm.n_colloc_base, w_base)]
         cblocks = [c + chk]
-        s_pos = [c + proxy]
-        r_pos, d_pos = [], []
+        s_img, r_pos, d_pos = [], [], []
         for ct in contacts[k]:
             t = image_t(ct.gap, prm.proxy_radius, ct.n_im, prm.image_offset)
             line = c + a * t[:, None] * ct.axis[None, :]
             if "S" in prm.kinds:
-                s_pos.append(line)
+                s_img.append(line)
             if "R" in prm.kinds:
                 r_pos.append(line)
             if "D" in prm.kinds:
@@ -258,28 +260,30 @@ def build(centers, radius: float, prm: Params | None = None) -> Geometry:
         ck.append(C)
         ck_s.append(np.full(len(C), k))
         coff.append(coff[-1] + len(C))
-        per_kind[KIND_S].append(np.concatenate(s_pos))
-        per_kind[KIND_R].append(np.concatenate(r_pos) if r_pos else np.zeros((0, 3)))
-        per_kind[KIND_D].append(np.concatenate(d_pos) if d_pos else np.zeros((0, 3)))
+        empty = np.zeros((0, 3))
+        per_block[0].append(c + proxy)
+        per_block[1].append(np.concatenate(s_img) if s_img else empty)
+        per_block[2].append(np.concatenate(r_pos) if r_pos else empty)
+        per_block[3].append(np.concatenate(d_pos) if d_pos else empty)
 
-    kind_off = np.zeros((3, P + 1), np.int64)
+    kind_off = np.zeros((4, P + 1), np.int64)
     pos_all, kind_all, sph_all = [], [], []
     base_idx = 0
-    n_kind = np.zeros(3, np.int64)
-    for kind in (KIND_S, KIND_R, KIND_D):
-        kind_off[kind, 0] = base_idx
+    n_block = np.zeros(4, np.int64)
+    for blk in range(4):
+        kind_off[blk, 0] = base_idx
         for k in range(P):
-            arr = per_kind[kind][k]
+            arr = per_block[blk][k]
             pos_all.append(arr)
-            kind_all.append(np.full(len(arr), kind))
+            kind_all.append(np.full(len(arr), BLOCK_KIND[blk]))
             sph_all.append(np.full(len(arr), k))
             base_idx += len(arr)
-            kind_off[kind, k + 1] = base_idx
-        n_kind[kind] = kind_off[kind, P] - kind_off[kind, 0]
+            kind_off[blk, k + 1] = base_idx
+        n_block[blk] = kind_off[blk, P] - kind_off[blk, 0]
+    n_kind = np.array([n_block[0] + n_block[1], n_block[2], n_block[3]], np.int64)
     local = []
     for k in range(P):
-        idx = np.concatenate([np.arange(kind_off[kd, k], kind_off[kd, k + 1])
-                              for kd in (KIND_S, KIND_R, KIND_D)])
+        idx = np.concatenate([np.arange(kind_off[b, k], kind_off[b, k + 1]) for b in range(4)])
         local.append(idx.astype(np.int64))
     return Geometry(
         params=prm, centers=centers, radius=a, contacts=contacts,
@@ -289,7 +293,7 @@ def build(centers, radius: float, prm: Params | None = None) -> Geometry:
         src_sphere=np.concatenate(sph_all).astype(np.int32), kind_offsets=kind_off,
         local_sources=local, check=np.concatenate(ck),
         check_sphere=np.concatenate(ck_s), check_offsets=np.asarray(coff, np.int64),
-        n_kind=n_kind)
+        n_kind=n_kind, n_block=n_block)
 
 
 def m_estimate(n_base: int, n_ims) -> int:

@@ -157,14 +157,13 @@ class Problem:
         g = self.g
         out = np.zeros((g.P, 6))
         for k in range(g.P):
-            for kind in (KIND_S, KIND_R):
-                a, b = g.kind_offsets[kind, k], g.kind_offsets[kind, k + 1]
-                if kind == KIND_S:
-                    f = lam[a:b]
-                    out[k, :3] = f.sum(0)
-                    out[k, 3:] += np.cross(g.src_pos[a:b] - g.centers[k], f).sum(0)
-                else:
-                    out[k, 3:] += lam[a:b].sum(0)
+            idx = g.local_sources[k]
+            kinds = g.src_kind[idx]
+            s = idx[kinds == KIND_S]
+            r = idx[kinds == KIND_R]
+            f = lam[s]
+            out[k, :3] = f.sum(0)
+            out[k, 3:] = np.cross(g.src_pos[s] - g.centers[k], f).sum(0) + lam[r].sum(0)
         return out
 
     def velocity(self, lam: np.ndarray, pts: np.ndarray) -> np.ndarray:

@@ -22,19 +22,20 @@ namespace smfs {
 namespace {
 thread_local std::string g_err;
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kTileTargets = 128;    // 64 lanes x 2 targets
+constexpr int kTileTargets = 64 * kDirectTpl;   // targets per wave tile
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Source splits of the direct sum: enough blocks (about 8192, i.e. 32 per
-// CU) to keep every SIMD busy to the end of the launch, while each split
-// still streams at least 1024 sources through LDS.
+// Source splits of the direct sum: enough blocks (about 32768, i.e. 128 per
+// CU; measured best among 8192/16384/32768) to keep every SIMD busy to the
+// end of the launch and balance the tail, while each split still streams at
+// least 1024 sources.
 int32_t choose_splits(int64_t n_tiles, int64_t S) {
   const int64_t blocks = std::max<int64_t>(1, (n_tiles + 3) / 4);
   static const int64_t target = [] {
     const char *e = std::getenv("SMFS_DIRECT_BLOCKS");
-    return e ? std::max<int64_t>(256, std::atoll(e)) : (int64_t)8192;
+    return e ? std::max<int64_t>(256, std::atoll(e)) : (int64_t)32768;
   }();
   int64_t sp = (target + blocks - 1) / blocks;
   sp = std::min<int64_t>(sp, std::max<int64_t>(1, S / 1024));
@@ -88,11 +89,29 @@ size_t workspace_layout(Problem &pb, bool assign) {
   const int32_t sp_c = choose_splits(free_tiles(C), S);
   const int64_t part = std::max<int64_t>(3 * T * sp_t, 3 * C * sp_c);
   const size_t o_part = take(sizeof(double) * part);
+  // mixed precision: FP32 coordinates/strengths of proxies, FP32 partials
+  int32_t n_free = 0;
+  for (int k = 0; k < P; ++k) n_free += pb.contacts[k].empty() ? 1 : 0;
+  const int64_t nprox = pb.nb[0];
+  const int32_t sp32 = n_free > 0 ? std::min<int32_t>(choose_splits((int64_t)tiles.size(),
+                                                                   (int64_t)n_free * pb.prm.n_proxy),
+                                                      std::max(1, n_free)) : 0;
+  const size_t o_tgt32 = take(sizeof(float) * 3 * T);
+  const size_t o_src32 = take(sizeof(float) * 3 * nprox);
+  const size_t o_str32 = take(sizeof(float) * 3 * nprox);
+  const size_t o_part32 = take(sizeof(float) * 3 * T * std::max(sp32, 1));
+  const size_t o_s32 = take(sizeof(float) * cols_total);
+  const size_t o_free = take(sizeof(int32_t) * std::max(1, P));
+  const size_t o_cen = take(sizeof(double) * 3 * P);
+  const size_t o_rng = take(sizeof(SrcRange) * (2 * (P + 8)));
+  const FactorSlot &f0 = pb.factors[0];
+  const int64_t fac32_elems = f0.rep >= 0 ? (int64_t)f0.rows * f0.cols + (int64_t)f0.cols * f0.cols + f0.cols : 0;
+  const size_t o_fac32 = take(sizeof(float) * std::max<int64_t>(1, fac32_elems));
   // Krylov basis (restart + 1 vectors) and work vectors
   const int64_t ld = ((3 * T + 31) / 32) * 32;
   const int32_t m = std::max(1, pb.prm.gmres_restart);
   const size_t o_kry = take(sizeof(double) * ld * (m + 1));
-  const size_t o_vec = take(sizeof(double) * ld * 4);
+  const size_t o_vec = take(sizeof(double) * ld * 6);
   const int32_t nch = mdot_chunks(3 * T);
   const int64_t red = (int64_t)nch * (m + 2) + 4 * (m + 2) + 64;
   const size_t o_red = take(sizeof(double) * red);
@@ -134,6 +153,17 @@ size_t workspace_layout(Problem &pb, bool assign) {
     pb.d_vec = (double *)(b + o_vec);
     pb.d_red = (double *)(b + o_red);
     pb.d_fac = (double *)(b + o_fac);
+    pb.d_tgt32 = (float *)(b + o_tgt32);
+    pb.d_src32 = (float *)(b + o_src32);
+    pb.d_str32 = (float *)(b + o_str32);
+    pb.d_part32 = (float *)(b + o_part32);
+    pb.d_s32 = (float *)(b + o_s32);
+    pb.d_free = (int32_t *)(b + o_free);
+    pb.d_centers = (double *)(b + o_cen);
+    pb.d_ranges = (SrcRange *)(b + o_rng);
+    pb.d_fac32 = (float *)(b + o_fac32);
+    pb.n_free = n_free;
+    pb.n_splits32 = sp32;
     pb.tiles = tiles;
     pb.n_tiles = (int64_t)tiles.size();
     pb.n_splits = sp_t;
@@ -167,10 +197,10 @@ int upload_tables(Problem &pb, hipStream_t s) {
     m.t0 = pb.toff[k];
     m.M = (int32_t)(pb.toff[k + 1] - pb.toff[k]);
     m.N = 0;
-    for (int kd = 0; kd < 3; ++kd) {
-      m.k0[kd] = pb.koff[kd][k];
-      m.kn[kd] = (int32_t)(pb.koff[kd][k + 1] - pb.koff[kd][k]);
-      m.N += m.kn[kd];
+    for (int b = 0; b < kBlocks; ++b) {
+      m.k0[b] = pb.koff[b][k];
+      m.kn[b] = (int32_t)(pb.koff[b][k + 1] - pb.koff[b][k]);
+      m.N += m.kn[b];
     }
     m.fid = pb.fid_of[k];
     m.rank = 0;
@@ -187,6 +217,47 @@ int upload_tables(Problem &pb, hipStream_t s) {
   }
   SMFS_HIP(hipMemcpyAsync(pb.d_tiles, pb.tiles.data(), sizeof(int4) * pb.tiles.size(),
                           hipMemcpyHostToDevice, s));
+  // mixed precision: coordinates relative to each sphere's centre in FP32
+  std::vector<float> t32(3 * pb.T), s32(3 * pb.nb[0]);
+  for (int64_t i = 0; i < pb.T; ++i)
+    for (int c = 0; c < 3; ++c) t32[3 * i + c] = (float)(pb.tgt[3 * i + c] - pb.centers[3 * pb.tsph[i] + c]);
+  for (int64_t j = 0; j < pb.nb[0]; ++j)
+    for (int c = 0; c < 3; ++c) s32[3 * j + c] = (float)(pb.src[3 * j + c] - pb.centers[3 * pb.ssph[j] + c]);
+  std::vector<int32_t> free_ids;
+  for (int k = 0; k < P; ++k)
+    if (pb.contacts[k].empty()) free_ids.push_back(k);
+  // source ranges: plain = every block; mixed FP64 = proxies of contact
+  // spheres (runs of consecutive spheres) and every image block
+  std::vector<SrcRange> rng;
+  pb.rng_total_plain = 0;
+  for (int b = 0; b < kBlocks; ++b)
+    if (pb.nb[b] > 0) {
+      rng.push_back(SrcRange{(int32_t)pb.koff[b][0], (int32_t)pb.koff[b][P], b, 0});
+      pb.rng_total_plain += pb.nb[b];
+    }
+  pb.n_rng_plain = (int32_t)rng.size();
+  pb.rng_total_mixed = 0;
+  for (int k = 0; k < P;) {
+    if (pb.contacts[k].empty()) { ++k; continue; }
+    int e = k;
+    while (e < P && !pb.contacts[e].empty()) ++e;
+    rng.push_back(SrcRange{(int32_t)pb.koff[0][k], (int32_t)pb.koff[0][e], 0, 0});
+    pb.rng_total_mixed += pb.koff[0][e] - pb.koff[0][k];
+    k = e;
+  }
+  for (int b = 1; b < kBlocks; ++b)
+    if (pb.nb[b] > 0) {
+      rng.push_back(SrcRange{(int32_t)pb.koff[b][0], (int32_t)pb.koff[b][P], b, 0});
+      pb.rng_total_mixed += pb.nb[b];
+    }
+  pb.n_rng_mixed = (int32_t)rng.size() - pb.n_rng_plain;
+  SMFS_HIP(hipMemcpyAsync(pb.d_centers, pb.centers.data(), 8 * pb.centers.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb.d_tgt32, t32.data(), 4 * t32.size(), hipMemcpyHostToDevice, s));
+  if (!s32.empty())
+    SMFS_HIP(hipMemcpyAsync(pb.d_src32, s32.data(), 4 * s32.size(), hipMemcpyHostToDevice, s));
+  if (!free_ids.empty())
+    SMFS_HIP(hipMemcpyAsync(pb.d_free, free_ids.data(), 4 * free_ids.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb.d_ranges, rng.data(), sizeof(SrcRange) * rng.size(), hipMemcpyHostToDevice, s));
   SMFS_HIP(hipStreamSynchronize(s));
   return rank_tables(pb, s);
 }
@@ -194,6 +265,8 @@ int upload_tables(Problem &pb, hipStream_t s) {
 // (Re)build the rank-dependent tables: s offsets and the row tasks of the
 // pseudo-inverse apply, then upload meta and factor slots.
 int rank_tables(Problem &pb, hipStream_t s) {
+  // row tasks of contact spheres first, then of contact-free spheres, so
+  // that the FP64 tasks of a mixed-precision product are a prefix
   std::vector<RowTask> ut, vt;
   int64_t s0 = 0;
   for (int k = 0; k < pb.P; ++k) {
@@ -202,13 +275,30 @@ int rank_tables(Problem &pb, hipStream_t s) {
     m.rank = f.rank;
     m.s0 = s0;
     s0 += f.cols;
-    if (f.rank > 0) {
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int k = 0; k < pb.P; ++k) {
+      if ((pass == 0) == pb.contacts[k].empty()) continue;
+      const FactorSlot &f = pb.factors[pb.meta[k].fid];
+      if (f.rank <= 0) continue;
       for (int j = 0; j < f.rank; ++j) ut.push_back(RowTask{k, j});
       for (int i = 0; i < f.cols; ++i) vt.push_back(RowTask{k, i});
+    }
+    if (pass == 0) {
+      pb.n_utask_c = (int64_t)ut.size();
+      pb.n_vtask_c = (int64_t)vt.size();
     }
   }
   pb.n_utask = (int64_t)ut.size();
   pb.n_vtask = (int64_t)vt.size();
+  // FP32 copy of the shared contact-free factor (mixed precision)
+  pb.fac32_ready = false;
+  const FactorSlot &f0 = pb.factors[0];
+  if (f0.rep >= 0 && f0.rank > 0) {
+    const int64_t e = (int64_t)f0.rows * f0.cols + (int64_t)f0.cols * f0.cols + f0.cols;
+    SMFS_HIP(launch_to_f32(e, pb.d_fac + f0.u_off, pb.d_fac32, s));
+    pb.fac32_ready = true;
+  }
   SMFS_HIP(hipMemcpyAsync(pb.d_meta, pb.meta.data(), sizeof(SphereMeta) * pb.P, hipMemcpyHostToDevice, s));
   SMFS_HIP(hipMemcpyAsync(pb.d_fslots, pb.factors.data(), sizeof(FactorSlot) * pb.factors.size(),
                           hipMemcpyHostToDevice, s));
@@ -227,27 +317,34 @@ int rank_tables(Problem &pb, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Building blocks of the product.
 
-int transform(Problem &pb, const double *mu, double *lam, hipStream_t s) {
-  SMFS_HIP(launch_pinv_u(pb.d_utask, pb.n_utask, pb.d_meta, pb.d_fslots, pb.d_fac, mu, pb.d_s, s));
-  SMFS_HIP(launch_pinv_v(pb.d_vtask, pb.n_vtask, pb.d_meta, pb.d_fslots, pb.d_fac, pb.d_s, lam, s));
+// lambda = B^+ mu for every sphere, FP64 (n_u, n_v limit the task lists:
+// the contact-sphere prefix in a mixed-precision product).
+int transform_tasks(Problem &pb, const double *mu, double *lam, int64_t n_u, int64_t n_v,
+                    double dscale, hipStream_t s) {
+  SMFS_HIP(launch_pinv_u(pb.d_utask, n_u, pb.d_meta, pb.d_fslots, pb.d_fac, mu, pb.d_s, s));
+  SMFS_HIP(launch_pinv_v(pb.d_vtask, n_v, pb.d_meta, pb.d_fslots, pb.d_fac, pb.d_s, lam, dscale, s));
   return SMFS_OK;
 }
 
-DirectArgs direct_args(Problem &pb, const double *str) {
+// physical strengths lambda = B^+ mu
+int transform(Problem &pb, const double *mu, double *lam, hipStream_t s) {
+  return transform_tasks(pb, mu, lam, pb.n_utask, pb.n_vtask, 1.0, s);
+}
+
+DirectArgs direct_args(Problem &pb, const double *str, bool mixed) {
   DirectArgs a;
   a.tiles = pb.d_tiles;
   a.n_tiles = pb.n_tiles;
   a.tgt = pb.d_tgt;
+  a.T = pb.T;
   a.src = pb.d_src;
   a.str = str;
   a.meta = pb.d_meta;
-  a.kb[0] = pb.koff[0][0];
-  a.kb[1] = pb.koff[1][0];
-  a.kb[2] = pb.koff[2][0];
-  a.kb[3] = pb.S;
+  a.ranges = mixed ? pb.d_ranges + pb.n_rng_plain : pb.d_ranges;
+  a.n_ranges = mixed ? pb.n_rng_mixed : pb.n_rng_plain;
+  a.range_total = mixed ? pb.rng_total_mixed : pb.rng_total_plain;
   a.dscale = 2.0 * pb.prm.mu;
   a.n_splits = pb.n_splits;
-  a.T = pb.T;
   a.part = pb.d_part;
   return a;
 }
@@ -264,22 +361,58 @@ int record_event(Problem &pb, hipStream_t s, size_t &idx) {
   return SMFS_OK;
 }
 
-int apply(Problem &pb, const double *mu, double *y, hipStream_t s) {
-  size_t e0 = 0, e1 = 0, e2 = 0;
+// y = G_hat mu.  FP64: every sphere's pseudo-inverse and every off-sphere
+// pair in FP64.  Mixed: contact-free spheres (shared factor) go through the
+// FP32 pseudo-inverse and the FP32 far-field kernel; contact spheres, with
+// their image lines, stay FP64 throughout.
+int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s) {
+  const bool mixed = precision == SMFS_MIXED && pb.n_free > 0 && pb.fac32_ready;
+  size_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
   int rc;
   if (pb.prof && (rc = record_event(pb, s, e0))) return rc;
-  rc = transform(pb, mu, pb.d_lamhat, s);
+  // dipole strengths pre-multiplied by 2 mu for the direct-sum kernel
+  const double ds = 2.0 * pb.prm.mu;
+  if (!mixed) {
+    rc = transform_tasks(pb, mu, pb.d_lamhat, pb.n_utask, pb.n_vtask, ds, s);
+  } else {
+    rc = transform_tasks(pb, mu, pb.d_lamhat, pb.n_utask_c, pb.n_vtask_c, ds, s);
+    const int64_t off0 = pb.factors[0].u_off;   // FP32 copy holds factor 0 only
+    SMFS_HIP(launch_pinv_u32(pb.d_utask + pb.n_utask_c, pb.n_utask - pb.n_utask_c, pb.d_meta,
+                             pb.d_fslots, pb.d_fac32, off0, mu, pb.d_s32, s));
+    SMFS_HIP(launch_pinv_v32(pb.d_vtask + pb.n_vtask_c, pb.n_vtask - pb.n_vtask_c, pb.d_meta,
+                             pb.d_fslots, pb.d_fac32, off0, pb.d_s32, pb.d_str32, s));
+  }
   if (rc) return rc;
   if (pb.prof && (rc = record_event(pb, s, e1))) return rc;
-  DirectArgs a = direct_args(pb, pb.d_lamhat);
+  DirectArgs a = direct_args(pb, pb.d_lamhat, mixed);
   SMFS_HIP(launch_direct_f64(a, s));
-  if (pb.prof) {
-    if ((rc = record_event(pb, s, e2))) return rc;
-    pb.ev_pinv.emplace_back(e0, e1);
-    pb.ev_direct.emplace_back(e1, e2);
+  if (pb.prof && (rc = record_event(pb, s, e2))) return rc;
+  int32_t ns32 = 0;
+  if (mixed) {
+    Far32Args f;
+    f.tiles = pb.d_tiles;
+    f.n_tiles = pb.n_tiles;
+    f.tgt32 = pb.d_tgt32;
+    f.src32 = pb.d_src32;
+    f.str32 = pb.d_str32;
+    f.free_ids = pb.d_free;
+    f.n_free = pb.n_free;
+    f.n_proxy = pb.prm.n_proxy;
+    f.n_splits = pb.n_splits32;
+    f.T = pb.T;
+    f.part32 = pb.d_part32;
+    f.centers = pb.d_centers;
+    SMFS_HIP(launch_far_f32(f, s));
+    ns32 = pb.n_splits32;
+    if (pb.prof && (rc = record_event(pb, s, e3))) return rc;
   }
-  SMFS_HIP(launch_reduce_epilogue(3 * pb.T, pb.n_splits, pb.d_part, mu, pb.d_sw,
-                                  1.0 / (8.0 * kPi * pb.prm.mu), y, s));
+  if (pb.prof) {
+    pb.ev_pinv.emplace_back(e0, e1);
+    if (mixed) pb.ev_mixed64.emplace_back(e1, e2), pb.ev_far32.emplace_back(e2, e3);
+    else pb.ev_direct.emplace_back(e1, e2);
+  }
+  SMFS_HIP(launch_reduce_epilogue(3 * pb.T, pb.n_splits, pb.d_part, ns32, mixed ? pb.d_part32 : nullptr,
+                                  mu, pb.d_sw, 1.0 / (8.0 * kPi * pb.prm.mu), y, s));
   return SMFS_OK;
 }
 
@@ -292,14 +425,14 @@ int eval_points(Problem &pb, const double *lam, int64_t n, const double *x, doub
   if (cap < 1) { set_error("partial-sum buffer too small"); return SMFS_E_NOMEM; }
   for (int64_t o = 0; o < n; o += cap) {
     const int64_t cnt = std::min(cap, n - o);
-    DirectArgs a = direct_args(pb, lam);
+    DirectArgs a = direct_args(pb, lam, false);
     a.tiles = nullptr;
     a.n_tiles = free_tiles(cnt);
     a.tgt = x + 3 * o;
     a.n_splits = sp;
     a.T = cnt;
     SMFS_HIP(launch_direct_f64(a, s));
-    SMFS_HIP(launch_reduce_epilogue(3 * cnt, sp, pb.d_part, nullptr, nullptr,
+    SMFS_HIP(launch_reduce_epilogue(3 * cnt, sp, pb.d_part, 0, nullptr, nullptr, nullptr,
                                     1.0 / (8.0 * kPi * pb.prm.mu), u + 3 * o, s));
   }
   return SMFS_OK;
@@ -316,11 +449,10 @@ struct GmresStats {
   bool converged = false;
 };
 
-int gmres(Problem &pb, const double *b, double *x, GmresStats &st, hipStream_t s) {
+int gmres(Problem &pb, const double *b, double *x, GmresStats &st, int precision, double tol,
+          int max_it, hipStream_t s) {
   const int64_t n = 3 * pb.T, ld = pb.kry_ld;
   const int m = pb.kry_vecs - 1;
-  const int max_it = pb.prm.gmres_max_it;
-  const double tol = pb.prm.gmres_tol;
   double *V = pb.d_kry;
   double *w = pb.d_vec;           // scratch vector
   double *r = pb.d_vec + ld;      // residual
@@ -361,7 +493,7 @@ int gmres(Problem &pb, const double *b, double *x, GmresStats &st, hipStream_t s
     bool stop = false;
     for (int j = 0; j < m; ++j) {
       double *vj1 = V + (int64_t)(j + 1) * ld;
-      int rc = apply(pb, V + (int64_t)j * ld, vj1, s);
+      int rc = apply(pb, V + (int64_t)j * ld, vj1, precision, s);
       if (rc) return rc;
       // classical Gram-Schmidt, twice: h = V^T w, w -= V h; h2 = V^T w, w -= V h2
       SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h, false, s));
@@ -405,7 +537,7 @@ int gmres(Problem &pb, const double *b, double *x, GmresStats &st, hipStream_t s
     st.iterations = total;
     if (stop) return SMFS_OK;
     // restart from the true residual
-    int rc = apply(pb, x, w, s);
+    int rc = apply(pb, x, w, precision, s);
     if (rc) return rc;
     SMFS_HIP(launch_sub(n, b, w, r, s));
     SMFS_HIP(launch_norm2(r, n, part, nch, scal + 1, s));
@@ -462,7 +594,7 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
     return SMFS_E_INVALID_ARG;
   }
   *out = nullptr;
-  if (p->n_proxy <= 0 || p->n_colloc_base <= 0 || !(p->proxy_radius > 0 && p->proxy_radius < 1) ||
+  if (p->n_proxy <= 0 || p->n_colloc_base <= 0 || p->gmres_restart > 20000 || !(p->proxy_radius > 0 && p->proxy_radius < 1) ||
       !(p->mu > 0) || !(p->trunc_rel >= 0) || p->gmres_restart <= 0 || p->gmres_max_it <= 0 ||
       p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 ||
       (p->precision != SMFS_FP64 && p->precision != SMFS_MIXED)) {
@@ -682,7 +814,7 @@ int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision,
   SMFS_READY(pb);
   if (!mu || !y || mu == y) { set_error("smfs_apply: bad vectors"); return SMFS_E_INVALID_ARG; }
   if (precision != SMFS_FP64 && precision != SMFS_MIXED) { set_error("bad precision"); return SMFS_E_INVALID_ARG; }
-  return apply(*pb, mu, y, (hipStream_t)stream);
+  return apply(*pb, mu, y, precision, (hipStream_t)stream);
 }
 
 int smfs_transform(smfs_problem *pb, const double *mu, double *lam, smfs_stream stream) {
@@ -714,12 +846,26 @@ int smfs_eval_velocity(smfs_problem *pb, const double *lam, int64_t n, const dou
 
 int64_t smfs_pairs_per_apply(const smfs_problem *pb) { return pb ? pb->pairs_per_apply : 0; }
 
+int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32_t gmres_max_it) {
+  if (!pb || (precision != SMFS_FP64 && precision != SMFS_MIXED) || !(gmres_tol > 0) ||
+      gmres_max_it <= 0) {
+    set_error("smfs_set_solver: bad argument");
+    return SMFS_E_INVALID_ARG;
+  }
+  pb->prm.precision = precision;
+  pb->prm.gmres_tol = gmres_tol;
+  pb->prm.gmres_max_it = gmres_max_it;
+  return SMFS_OK;
+}
+
 int smfs_profile(smfs_problem *pb, int32_t enable) {
   if (!pb) { set_error("null problem"); return SMFS_E_INVALID_ARG; }
   if (enable) {
     pb->ev_used = 0;
     pb->ev_direct.clear();
     pb->ev_pinv.clear();
+    pb->ev_mixed64.clear();
+    pb->ev_far32.clear();
   }
   pb->prof = enable != 0;
   return SMFS_OK;
@@ -740,8 +886,25 @@ int smfs_profile_read(smfs_problem *pb, smfs_kernel_stats *st) {
     SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
     st->pinv_ms += ms;
   }
+  for (auto &pr : pb->ev_mixed64) {
+    float ms = 0.f;
+    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
+    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
+    st->mixed64_ms += ms;
+  }
+  st->mixed64_launches = (int64_t)pb->ev_mixed64.size();
+  for (auto &pr : pb->ev_far32) {
+    float ms = 0.f;
+    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
+    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
+    st->far32_ms += ms;
+  }
   st->direct_launches = (int64_t)pb->ev_direct.size();
   st->pinv_launches = (int64_t)pb->ev_pinv.size();
+  st->far32_launches = (int64_t)pb->ev_far32.size();
+  st->far32_flops = 28.0 * pb->pairs_f32;
+  st->mixed64_flops = 28.0 * (pb->pairs_kind[0] - pb->pairs_f32) + 25.0 * pb->pairs_kind[1] +
+                      30.0 * pb->pairs_kind[2];
   st->direct_flops = 28.0 * pb->pairs_kind[0] + 25.0 * pb->pairs_kind[1] + 30.0 * pb->pairs_kind[2];
   double bytes = 0.0;
   for (int k = 0; k < pb->P; ++k) {
@@ -767,47 +930,76 @@ int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out, sm
   SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm, b, s));
   SMFS_HIP(hipStreamSynchronize(s));
   auto t1 = clk::now();
+  const int precision = pb->prm.precision;
+  const double tol = pb->prm.gmres_tol;
   GmresStats st;
-  int rc = gmres(*pb, b, x, st, s);
+  int rc = gmres(*pb, b, x, st, precision, tol, pb->prm.gmres_max_it, s);
   if (rc) return rc;
+  int iterations = st.iterations;
+  bool converged = st.converged;
   auto t2 = clk::now();
-  // true residual in FP64
-  double *w = pb->d_vec, *r = pb->d_vec + ld;
-  rc = apply(*pb, x, w, s);
-  if (rc) return rc;
+  // true residual in FP64; in mixed precision, refine on it (at most twice)
+  double *w = pb->d_vec, *r = pb->d_vec + ld, *rr = pb->d_vec + 4 * ld, *d = pb->d_vec + 5 * ld;
   const int32_t nch = mdot_chunks(n);
   double *scal = pb->d_red + pb->red_cap - 8;
-  SMFS_HIP(launch_sub(n, b, w, r, s));
-  SMFS_HIP(launch_norm2(r, n, pb->d_red, nch, scal, s));
-  SMFS_HIP(launch_norm2(b, n, pb->d_red, nch, scal + 1, s));
+  double hres[2] = {0, 0};
+  int refinements = 0;
+  while (true) {
+    rc = apply(*pb, x, w, SMFS_FP64, s);
+    if (rc) return rc;
+    SMFS_HIP(launch_sub(n, b, w, r, s));
+    SMFS_HIP(launch_norm2(r, n, pb->d_red, nch, scal, s));
+    SMFS_HIP(launch_norm2(b, n, pb->d_red, nch, scal + 1, s));
+    SMFS_HIP(hipMemcpyAsync(hres, scal, 16, hipMemcpyDeviceToHost, s));
+    SMFS_HIP(hipStreamSynchronize(s));
+    const double true_rel = hres[1] > 0 ? hres[0] / hres[1] : 0.0;
+    if (precision != SMFS_MIXED || true_rel <= tol || refinements >= 2 ||
+        iterations >= pb->prm.gmres_max_it)
+      break;
+    // solve G_hat d = r with the mixed product, then x += d
+    SMFS_HIP(hipMemcpyAsync(rr, r, 8 * n, hipMemcpyDeviceToDevice, s));
+    const double tol_d = std::min(0.5, std::max(tol, tol / true_rel));
+    GmresStats sd;
+    rc = gmres(*pb, rr, d, sd, SMFS_MIXED, tol_d, pb->prm.gmres_max_it - iterations, s);
+    if (rc) return rc;
+    iterations += sd.iterations;
+    converged = sd.converged;
+    SMFS_HIP(launch_axpby(n, 1.0, d, 1.0, x, s));
+    ++refinements;
+  }
+  auto t2b = clk::now();
   // strengths, forces, residual at check points
   double *lam = out->lambda ? out->lambda : pb->d_lamhat;
   rc = transform(*pb, x, lam, s);
   if (rc) return rc;
   if (out->ft) SMFS_HIP(launch_force_torque(pb->P, pb->d_meta, pb->d_src, lam, out->ft, s));
   SMFS_HIP(launch_absmax(3 * pb->S, lam, scal + 2, s));
-  double hs[6] = {0, 0, 0, 0, 0, 0};
+  double hs[6] = {hres[0], hres[1], 0, 0, 0, 0};
   if (out->u_check && pb->C) {
     rc = eval_points(*pb, lam, pb->C, pb->d_chk, out->u_check, s);
     if (rc) return rc;
     SMFS_HIP(launch_residual_stats(pb->C, pb->d_chk, pb->d_csph, pb->d_meta, rbm, out->u_check,
                                    1e-3, scal + 3, s));
   }
-  SMFS_HIP(hipMemcpyAsync(hs, scal, 8 * 6, hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipMemcpyAsync(hs + 2, scal + 2, 8 * 4, hipMemcpyDeviceToHost, s));
   SMFS_HIP(hipStreamSynchronize(s));
   auto t3 = clk::now();
-  out->iterations = st.iterations;
+  out->iterations = iterations;
+  out->refinements = refinements;
   out->rel_residual = st.rel_residual;
   out->true_rel_residual = hs[1] > 0 ? hs[0] / hs[1] : 0.0;
   out->lambda_inf = hs[2];
   out->eps_res_max = (out->u_check && pb->C) ? hs[3] : -1.0;
   out->abs_res_max = (out->u_check && pb->C && hs[5] > 0) ? hs[4] / hs[5] : -1.0;
   out->t_rhs_ms = ms(t0, t1);
-  out->t_gmres_ms = ms(t1, t2);
-  out->t_post_ms = ms(t2, t3);
-  out->pair_evals = (int64_t)(st.iterations + 1) * pb->pairs_per_apply +
+  out->t_gmres_ms = ms(t1, t2b);
+  out->t_post_ms = ms(t2b, t3);
+  (void)t2;
+  const bool mixed = precision == SMFS_MIXED && pb->n_free > 0 && pb->fac32_ready;
+  out->pair_evals = (int64_t)(iterations + refinements + 1) * pb->pairs_per_apply +
                     ((out->u_check) ? pb->C * pb->S : 0);
-  return st.converged ? SMFS_OK : SMFS_NOT_CONVERGED;
+  out->pair_evals_f32 = mixed ? (int64_t)iterations * pb->pairs_f32 : 0;
+  return converged ? SMFS_OK : SMFS_NOT_CONVERGED;
 }
 
 }  // extern "C"

@@ -118,9 +118,10 @@ int build_geometry(Problem &pb) {
              kD = p.image_kinds & SMFS_KIND_D;
   pb.tgt.clear(); pb.tw.clear(); pb.tsph.clear(); pb.toff.assign(1, 0);
   pb.chk.clear(); pb.csph.clear();
-  std::vector<double> spos[3];
-  std::vector<int32_t> scount[3];
-  for (int kd = 0; kd < 3; ++kd) scount[kd].assign(P, 0);
+  // blocks: 0 proxy Stokeslets, 1 image Stokeslets, 2 rotlets, 3 dipoles
+  std::vector<double> spos[kBlocks];
+  std::vector<int32_t> scount[kBlocks];
+  for (int b = 0; b < kBlocks; ++b) scount[b].assign(P, 0);
 
   const double w_base = 4.0 * kPi * a * a / p.n_colloc_base;
   for (int k = 0; k < P; ++k) {
@@ -150,9 +151,9 @@ int build_geometry(Problem &pb) {
         double t = t0 + (ra - t0) * std::cos((j - 1.0) * kPi / (2.0 * ct.n_im));
         double x = c[0] + a * t * ct.axis[0], y = c[1] + a * t * ct.axis[1],
                z = c[2] + a * t * ct.axis[2];
-        if (kS) { push3(spos[0], x, y, z); scount[0][k]++; }
-        if (kR) { push3(spos[1], x, y, z); scount[1][k]++; }
-        if (kD) { push3(spos[2], x, y, z); scount[2][k]++; }
+        if (kS) { push3(spos[1], x, y, z); scount[1][k]++; }
+        if (kR) { push3(spos[2], x, y, z); scount[2][k]++; }
+        if (kD) { push3(spos[3], x, y, z); scount[3][k]++; }
       }
       double e1[3], e2[3];
       frame(ct.axis, e1, e2);
@@ -183,24 +184,28 @@ int build_geometry(Problem &pb) {
   pb.T = (int64_t)pb.tsph.size();
   pb.C = (int64_t)pb.csph.size();
 
-  // pack sources by kind, sphere-major inside each kind
+  // pack sources block by block, sphere-major inside each block
+  static const int kBlockKind[kBlocks] = {0, 0, 1, 2};
   pb.src.clear(); pb.skind.clear(); pb.ssph.clear();
   int64_t base = 0;
-  for (int kd = 0; kd < 3; ++kd) {
-    pb.koff[kd].assign(P + 1, 0);
-    pb.koff[kd][0] = base;
+  for (int b = 0; b < kBlocks; ++b) {
+    pb.koff[b].assign(P + 1, 0);
+    pb.koff[b][0] = base;
     int64_t pos = 0;
     for (int k = 0; k < P; ++k) {
-      for (int j = 0; j < scount[kd][k]; ++j, ++pos) {
-        push3(pb.src, spos[kd][3 * pos], spos[kd][3 * pos + 1], spos[kd][3 * pos + 2]);
-        pb.skind.push_back(kd);
+      for (int j = 0; j < scount[b][k]; ++j, ++pos) {
+        push3(pb.src, spos[b][3 * pos], spos[b][3 * pos + 1], spos[b][3 * pos + 2]);
+        pb.skind.push_back(kBlockKind[b]);
         pb.ssph.push_back(k);
       }
-      base += scount[kd][k];
-      pb.koff[kd][k + 1] = base;
+      base += scount[b][k];
+      pb.koff[b][k + 1] = base;
     }
-    pb.nk[kd] = pb.koff[kd][P] - pb.koff[kd][0];
+    pb.nb[b] = pb.koff[b][P] - pb.koff[b][0];
   }
+  pb.nk[0] = pb.nb[0] + pb.nb[1];
+  pb.nk[1] = pb.nb[2];
+  pb.nk[2] = pb.nb[3];
   pb.S = base;
 
   // factor ids: 0 for every contact-free sphere, then one per contact sphere
@@ -224,16 +229,22 @@ int build_geometry(Problem &pb) {
     int k = fs.rep;
     fs.rows = (int32_t)(3 * (pb.toff[k + 1] - pb.toff[k]));
     int64_t n = 0;
-    for (int kd = 0; kd < 3; ++kd) n += pb.koff[kd][k + 1] - pb.koff[kd][k];
+    for (int b = 0; b < kBlocks; ++b) n += pb.koff[b][k + 1] - pb.koff[b][k];
     fs.cols = (int32_t)(3 * n);
   }
   // pairs per apply: every collocation node against every source of other spheres
   pb.pairs_per_apply = 0;
+  pb.pairs_f32 = 0;
   for (int kd = 0; kd < 3; ++kd) pb.pairs_kind[kd] = 0;
+  int64_t free_proxies = 0;
+  for (int k = 0; k < P; ++k)
+    if (pb.contacts[k].empty()) free_proxies += pb.koff[0][k + 1] - pb.koff[0][k];
   for (int k = 0; k < P; ++k) {
     const int64_t Mk = pb.toff[k + 1] - pb.toff[k];
-    for (int kd = 0; kd < 3; ++kd)
-      pb.pairs_kind[kd] += Mk * (pb.nk[kd] - (pb.koff[kd][k + 1] - pb.koff[kd][k]));
+    for (int b = 0; b < kBlocks; ++b)
+      pb.pairs_kind[kBlockKind[b]] += Mk * (pb.nb[b] - (pb.koff[b][k + 1] - pb.koff[b][k]));
+    const int64_t own = pb.contacts[k].empty() ? pb.koff[0][k + 1] - pb.koff[0][k] : 0;
+    pb.pairs_f32 += Mk * (free_proxies - own);
   }
   pb.pairs_per_apply = pb.pairs_kind[0] + pb.pairs_kind[1] + pb.pairs_kind[2];
   return SMFS_OK;

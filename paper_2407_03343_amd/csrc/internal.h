@@ -31,17 +31,26 @@ struct Contact {
   int32_t n_im;    // image nodes on this contact's line
 };
 
+// Packing blocks of the source array: proxy Stokeslets, image Stokeslets,
+// rotlets, potential dipoles (each sphere-major).
+constexpr int kBlocks = 4;
+
 // Per-sphere table entry read by the kernels.
 struct SphereMeta {
-  int64_t t0;       // first collocation node
-  int32_t M;        // collocation nodes
-  int32_t N;        // vector sources (all kinds)
-  int64_t k0[3];    // first source of each kind block (global packed index)
-  int32_t kn[3];    // sources of each kind
-  int32_t fid;      // factor id
-  int32_t rank;     // kept singular values of that factor
-  int64_t s0;       // offset of this sphere's U^T mu entries in the s buffer
-  double c[3];      // centre
+  int64_t t0;             // first collocation node
+  int32_t M;              // collocation nodes
+  int32_t N;              // vector sources (all kinds)
+  int64_t k0[kBlocks];    // first source of the sphere in each block (packed index)
+  int32_t kn[kBlocks];    // sources of the sphere in each block
+  int32_t fid;            // factor id
+  int32_t rank;           // kept singular values of that factor
+  int64_t s0;             // offset of this sphere's U^T mu entries in the s buffer
+  double c[3];            // centre
+};
+
+// A contiguous run of packed sources inside one block.
+struct SrcRange {
+  int32_t begin, end, block, pad;
 };
 
 // Per-factor storage inside the workspace (element offsets of doubles).
@@ -76,11 +85,12 @@ struct Problem {
   std::vector<int64_t> toff;               // P + 1
   std::vector<double> src;                 // S x 3, packed by kind
   std::vector<int32_t> skind, ssph;        // S
-  std::vector<int64_t> koff[3];            // per kind: P + 1 global offsets
+  std::vector<int64_t> koff[kBlocks];      // per block: P + 1 global offsets
   std::vector<double> chk;                 // C x 3
   std::vector<int32_t> csph;               // C
   int64_t T = 0, S = 0, C = 0;
-  int64_t nk[3] = {0, 0, 0};
+  int64_t nk[3] = {0, 0, 0};               // per kind (S = proxy + image blocks)
+  int64_t nb[kBlocks] = {0, 0, 0, 0};      // per block
 
   // factors
   std::vector<int32_t> fid_of;             // P
@@ -97,6 +107,17 @@ struct Problem {
   double *d_chk = nullptr, *d_fac = nullptr, *d_part = nullptr, *d_s = nullptr;
   int32_t *d_tsph = nullptr, *d_csph = nullptr;
   int4 *d_tiles = nullptr, *d_eval_tiles = nullptr;
+  // mixed precision arrays
+  float *d_tgt32 = nullptr, *d_src32 = nullptr, *d_str32 = nullptr, *d_part32 = nullptr;
+  float *d_s32 = nullptr, *d_fac32 = nullptr;
+  int32_t *d_free = nullptr;
+  double *d_centers = nullptr;             // P x 3
+  SrcRange *d_ranges = nullptr;            // [plain ranges | mixed FP64 ranges]
+  int32_t n_free = 0, n_splits32 = 1;
+  int32_t n_rng_plain = 0, n_rng_mixed = 0;
+  int64_t rng_total_plain = 0, rng_total_mixed = 0;
+  int64_t n_utask_c = 0, n_vtask_c = 0;    // tasks of contact spheres (a prefix)
+  bool fac32_ready = false;
   SphereMeta *d_meta = nullptr;
   FactorSlot *d_fslots = nullptr;
   RowTask *d_utask = nullptr, *d_vtask = nullptr;
@@ -118,12 +139,13 @@ struct Problem {
   void *rocblas = nullptr;                 // rocblas_handle for setup
   int64_t pairs_per_apply = 0;
   int64_t pairs_kind[3] = {0, 0, 0};       // per product, by source kind
+  int64_t pairs_f32 = 0;                   // mixed precision: pairs with contact-free sources
 
   // per-launch event timing (smfs_profile)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<size_t, size_t>> ev_direct, ev_pinv;
+  std::vector<std::pair<size_t, size_t>> ev_direct, ev_pinv, ev_mixed64, ev_far32;
 };
 
 // geometry.cpp

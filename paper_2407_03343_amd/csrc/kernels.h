@@ -9,28 +9,53 @@
 
 namespace smfs {
 
-// Direct sum of every source over target tiles (Section 2.2, eq. uAll, with
-// the self blocks skipped for tiles that name a sphere).  Writes per-split
-// partial sums part[split][T][3] (without the 1/(8 pi mu) factor).
+// Targets per lane of the direct-sum kernels (tiles hold 64 * kDirectTpl).
+constexpr int kDirectTpl = 2;
+
+// Direct sum over target tiles (Section 2.2, eq. uAll) in FP64: every source
+// in the given ranges of the packed source array, minus the tile's own
+// sphere (the identity self blocks).  Writes per-split partial sums
+// part[split][T][3] without the common factor 1/(8 pi mu).
 struct DirectArgs {
-  const int4 *tiles;        // NULL: consecutive free points, 128 per tile
+  const int4 *tiles;        // (sphere, first target, count); NULL: free points
   int64_t n_tiles;
   const double *tgt;        // targets x 3
-  const double *src;        // S x 3 positions (packed by kind)
+  int64_t T;                // targets (partial stride)
+  const double *src;        // S x 3 positions (packed)
   const double *str;        // S x 3 strengths
   const SphereMeta *meta;
-  int64_t kb[4];            // kind boundaries: S block [kb0,kb1), R, D
+  const SrcRange *ranges;   // source ranges visited
+  int32_t n_ranges;
+  int64_t range_total;      // sum of range lengths (split base)
   double dscale;            // dipole strengths are multiplied by 2 mu
   int32_t n_splits;
-  int64_t T;                // targets (partial stride)
   double *part;
 };
 hipError_t launch_direct_f64(const DirectArgs &a, hipStream_t s);
 
-// y[i] = base[i] + sw[i/3] * c0 * sum_s part[s][i]   (base, sw nullable)
-hipError_t launch_reduce_epilogue(int64_t n3, int32_t n_splits, const double *part,
-                                  const double *base, const double *sw, double c0, double *y,
-                                  hipStream_t s);
+// Mixed precision: FP32 sum of the proxy Stokeslets of contact-free
+// spheres over the tiles, coordinates relative to sphere centres.
+struct Far32Args {
+  const int4 *tiles;
+  int64_t n_tiles;
+  const float *tgt32;       // targets minus own centre, T x 3
+  const float *src32;       // proxies minus own centre, P*n_proxy x 3 (block 0 order)
+  const float *str32;       // proxy strengths (FP32)
+  const double *centers;    // P x 3
+  const int32_t *free_ids;  // contact-free spheres
+  int32_t n_free;
+  int32_t n_proxy;
+  int32_t n_splits;
+  int64_t T;
+  float *part32;            // [split][T][3]
+};
+hipError_t launch_far_f32(const Far32Args &a, hipStream_t s);
+
+// y[i] = base[i] + sw[i/3] * c0 * (sum_s part[s][i] + sum_s part32[s][i])
+// (base, sw, part32 nullable)
+hipError_t launch_reduce_epilogue(int64_t n3, int32_t n_splits, const double *part, int32_t ns32,
+                                  const float *part32, const double *base, const double *sw,
+                                  double c0, double *y, hipStream_t s);
 
 // Two-factor pseudo-inverse apply, eq. (transform):
 //   s_k = (U_k^T mu_k) / sigma_k      (one wave per task row)
@@ -38,9 +63,21 @@ hipError_t launch_reduce_epilogue(int64_t n3, int32_t n_splits, const double *pa
 hipError_t launch_pinv_u(const RowTask *tasks, int64_t n, const SphereMeta *meta,
                          const FactorSlot *fs, const double *fac, const double *mu, double *sbuf,
                          hipStream_t s);
+// dscale multiplies the dipole strengths (2 mu inside a product with G_hat,
+// 1 for physical strengths)
 hipError_t launch_pinv_v(const RowTask *tasks, int64_t n, const SphereMeta *meta,
                          const FactorSlot *fs, const double *fac, const double *sbuf,
-                         double *lam, hipStream_t s);
+                         double *lam, double dscale, hipStream_t s);
+
+// FP32 copy of the shared factor: fac32 holds factor slot 0, whose FP64
+// offsets start at off0.
+hipError_t launch_pinv_u32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
+                           const FactorSlot *fs, const float *fac32, int64_t off0,
+                           const double *mu, float *sbuf, hipStream_t s);
+hipError_t launch_pinv_v32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
+                           const FactorSlot *fs, const float *fac32, int64_t off0,
+                           const float *sbuf, float *str32, hipStream_t s);
+hipError_t launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 
 // b = W (v + omega x (x - c)) per collocation node.
 hipError_t launch_rhs(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,

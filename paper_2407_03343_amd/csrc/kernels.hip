@@ -15,7 +15,10 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kTileSrc = 256;  // sources staged in LDS per pass
+// occupancy target of the FP64 direct sum (waves per SIMD; sets its VGPR budget)
+#ifndef SMFS_DIRECT_WAVES
+#define SMFS_DIRECT_WAVES 4
+#endif
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -61,98 +64,124 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
-// Direct sum, FP64.  One wave owns a tile of up to kTpl*64 targets of one
-// sphere (or of free points when the tile's sphere is -1); the four waves
-// of a block share each LDS-staged pass of 256 sources.  blockIdx.y picks a
-// contiguous slice of the packed source range (split over sources).
+// Direct sum, FP64.  One wave owns a tile of up to 64*kTpl targets of one
+// sphere (or of free points).  Sources are streamed with wave-uniform
+// addresses, so they arrive through scalar loads into SGPRs and every VALU
+// instruction of a pair reads at most one of them: no LDS staging and no
+// barriers.  The sources visited are a list of ranges of the packed source
+// array (per precision mode); blockIdx.y takes a contiguous slice of the
+// concatenated ranges (split over sources), and the tile's own sphere is
+// cut out of each range (the identity self blocks of G_hat).
 
 // Stokeslet: u += (f + r (r.f)/|r|^2) / |r|, written as ri (f + r t) with
-// t = (r.f) ri^2 so that a pair costs 21 VALU operations plus one rsq.
-template <int kTpl>
-__device__ __forceinline__ void pair_s(const double2 &q0, const double2 &q1, const double2 &q2,
-                                       double tx, double ty, double tz, double &ax, double &ay,
-                                       double &az) {
-  const double rx = tx - q0.x, ry = ty - q0.y, rz = tz - q1.x;
+// t = (r.f) ri^2: 21 VALU operations plus one rsq per pair.
+__device__ __forceinline__ void pair_s(double sx, double sy, double sz, double fx, double fy,
+                                       double fz, double tx, double ty, double tz, double &ax,
+                                       double &ay, double &az) {
+  const double rx = tx - sx, ry = ty - sy, rz = tz - sz;
   const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
   const double ri = rsqrt_f64(r2);
-  const double rf = fma(rx, q1.y, fma(ry, q2.x, rz * q2.y));
+  const double rf = fma(rx, fx, fma(ry, fy, rz * fz));
   const double t = rf * (ri * ri);
-  ax = fma(fma(rx, t, q1.y), ri, ax);
-  ay = fma(fma(ry, t, q2.x), ri, ay);
-  az = fma(fma(rz, t, q2.y), ri, az);
+  ax = fma(fma(rx, t, fx), ri, ax);
+  ay = fma(fma(ry, t, fy), ri, ay);
+  az = fma(fma(rz, t, fz), ri, az);
+}
+
+// Rotlet: u += (t x r) / |r|^3.
+__device__ __forceinline__ void pair_r(double sx, double sy, double sz, double t0, double t1,
+                                       double t2, double tx, double ty, double tz, double &ax,
+                                       double &ay, double &az) {
+  const double rx = tx - sx, ry = ty - sy, rz = tz - sz;
+  const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+  const double ri = rsqrt_f64(r2);
+  const double c = ri * ri * ri;
+  ax = fma(c, fma(t1, rz, -t2 * ry), ax);
+  ay = fma(c, fma(t2, rx, -t0 * rz), ay);
+  az = fma(c, fma(t0, ry, -t1 * rx), az);
+}
+
+// Potential dipole (strength pre-multiplied by 2 mu so that the common
+// factor 1/(8 pi mu) applies): u += -d/|r|^3 + 3 r (r.d)/|r|^5.
+__device__ __forceinline__ void pair_d(double sx, double sy, double sz, double d0, double d1,
+                                       double d2, double tx, double ty, double tz, double &ax,
+                                       double &ay, double &az) {
+  const double rx = tx - sx, ry = ty - sy, rz = tz - sz;
+  const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+  const double ri = rsqrt_f64(r2);
+  const double ri2 = ri * ri;
+  const double ri3 = ri2 * ri;
+  const double rd = fma(rx, d0, fma(ry, d1, rz * d2));
+  const double bb = 3.0 * rd * ri3 * ri2;
+  ax = fma(-d0, ri3, fma(rx, bb, ax));
+  ay = fma(-d1, ri3, fma(ry, bb, ay));
+  az = fma(-d2, ri3, fma(rz, bb, az));
 }
 
 template <int kTpl>
-__device__ __forceinline__ void body_s(const double2 (*sh)[kTileSrc], int a, int b,
-                                       const double (&tx)[kTpl], const double (&ty)[kTpl],
-                                       const double (&tz)[kTpl], double (&ax)[kTpl],
-                                       double (&ay)[kTpl], double (&az)[kTpl]) {
-  int j = a;
-  for (; j + 1 < b; j += 2) {  // two sources per step: both LDS reads issued first
-    const double2 a0 = sh[0][j], a1 = sh[1][j], a2 = sh[2][j];
-    const double2 b0 = sh[0][j + 1], b1 = sh[1][j + 1], b2 = sh[2][j + 1];
+struct Acc {
+  double tx[kTpl], ty[kTpl], tz[kTpl], ax[kTpl], ay[kTpl], az[kTpl];
+};
+
+// Sources [j0, j1) of one kind; j0, j1 wave-uniform.
+template <int kTpl, int kKind, bool kScaleD>
+__device__ __forceinline__ void run_sources(const double *__restrict__ src,
+                                            const double *__restrict__ str, double dscale,
+                                            int64_t j0, int64_t j1, Acc<kTpl> &A) {
+  int64_t j = j0;
+  // two Stokeslets per step (rotlet and dipole ranges are short: one per step)
+  for (; kKind == 0 && j + 1 < j1; j += 2) {
+    const double *p0 = src + 3 * j, *q0 = str + 3 * j;
+    const double s0x = p0[0], s0y = p0[1], s0z = p0[2], s1x = p0[3], s1y = p0[4], s1z = p0[5];
+    double f0x = q0[0], f0y = q0[1], f0z = q0[2], f1x = q0[3], f1y = q0[4], f1z = q0[5];
+    if (kKind == 2 && kScaleD) {
+      f0x *= dscale; f0y *= dscale; f0z *= dscale;
+      f1x *= dscale; f1y *= dscale; f1z *= dscale;
+    }
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
-      pair_s<kTpl>(a0, a1, a2, tx[p], ty[p], tz[p], ax[p], ay[p], az[p]);
-      pair_s<kTpl>(b0, b1, b2, tx[p], ty[p], tz[p], ax[p], ay[p], az[p]);
+      if (kKind == 0) {
+        pair_s(s0x, s0y, s0z, f0x, f0y, f0z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+        pair_s(s1x, s1y, s1z, f1x, f1y, f1z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+      } else if (kKind == 1) {
+        pair_r(s0x, s0y, s0z, f0x, f0y, f0z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+        pair_r(s1x, s1y, s1z, f1x, f1y, f1z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+      } else {
+        pair_d(s0x, s0y, s0z, f0x, f0y, f0z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+        pair_d(s1x, s1y, s1z, f1x, f1y, f1z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+      }
     }
   }
-  if (j < b) {
-    const double2 a0 = sh[0][j], a1 = sh[1][j], a2 = sh[2][j];
+  for (; j < j1; ++j) {
+    const double *p0 = src + 3 * j, *q0 = str + 3 * j;
+    const double sx = p0[0], sy = p0[1], sz = p0[2];
+    double fx = q0[0], fy = q0[1], fz = q0[2];
+    if (kKind == 2 && kScaleD) { fx *= dscale; fy *= dscale; fz *= dscale; }
 #pragma unroll
-    for (int p = 0; p < kTpl; ++p) pair_s<kTpl>(a0, a1, a2, tx[p], ty[p], tz[p], ax[p], ay[p], az[p]);
+    for (int p = 0; p < kTpl; ++p) {
+      if (kKind == 0) pair_s(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+      else if (kKind == 1) pair_r(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+      else pair_d(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+    }
   }
 }
 
-template <int kTpl>
-__device__ __forceinline__ void body_r(const double2 (*sh)[kTileSrc], int a, int b,
-                                       const double (&tx)[kTpl], const double (&ty)[kTpl],
-                                       const double (&tz)[kTpl], double (&ax)[kTpl],
-                                       double (&ay)[kTpl], double (&az)[kTpl]) {
-  for (int j = a; j < b; ++j) {
-    const double2 q0 = sh[0][j], q1 = sh[1][j], q2 = sh[2][j];
-    const double t0 = q1.y, t1 = q2.x, t2 = q2.y;
-#pragma unroll
-    for (int p = 0; p < kTpl; ++p) {
-      const double rx = tx[p] - q0.x, ry = ty[p] - q0.y, rz = tz[p] - q1.x;
-      const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const double ri = rsqrt_f64(r2);
-      const double c = ri * ri * ri;
-      ax[p] = fma(c, fma(t1, rz, -t2 * ry), ax[p]);
-      ay[p] = fma(c, fma(t2, rx, -t0 * rz), ay[p]);
-      az[p] = fma(c, fma(t0, ry, -t1 * rx), az[p]);
-    }
-  }
-}
-
-template <int kTpl>
-__device__ __forceinline__ void body_d(const double2 (*sh)[kTileSrc], int a, int b,
-                                       const double (&tx)[kTpl], const double (&ty)[kTpl],
-                                       const double (&tz)[kTpl], double (&ax)[kTpl],
-                                       double (&ay)[kTpl], double (&az)[kTpl]) {
-  for (int j = a; j < b; ++j) {
-    const double2 q0 = sh[0][j], q1 = sh[1][j], q2 = sh[2][j];
-#pragma unroll
-    for (int p = 0; p < kTpl; ++p) {
-      const double rx = tx[p] - q0.x, ry = ty[p] - q0.y, rz = tz[p] - q1.x;
-      const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const double ri = rsqrt_f64(r2);
-      const double ri2 = ri * ri;
-      const double ri3 = ri2 * ri;
-      const double rd = fma(rx, q1.y, fma(ry, q2.x, rz * q2.y));
-      const double bb = 3.0 * rd * ri3 * ri2;
-      ax[p] = fma(-q1.y, ri3, fma(rx, bb, ax[p]));
-      ay[p] = fma(-q2.x, ri3, fma(ry, bb, ay[p]));
-      az[p] = fma(-q2.y, ri3, fma(rz, bb, az[p]));
-    }
-  }
+// Dipole strengths of a product with G_hat arrive pre-multiplied by 2 mu
+// (written so by the pseudo-inverse apply); free-point evaluation takes
+// physical strengths and scales them here.
+template <int kTpl, bool kScaleD>
+__device__ __forceinline__ void run_block(int block, const DirectArgs &A, int64_t j0, int64_t j1,
+                                          Acc<kTpl> &acc) {
+  if (j0 >= j1) return;
+  if (block <= 1) run_sources<kTpl, 0, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc);
+  else if (block == 2) run_sources<kTpl, 1, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc);
+  else run_sources<kTpl, 2, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc);
 }
 
 template <int kTpl, bool kFree>
-__global__ __launch_bounds__(kBlock) void k_direct_f64(DirectArgs A) {
-  __shared__ double2 sh[3][kTileSrc];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIRECT_WAVES, 8))) void k_direct_f64(DirectArgs A) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
   int k = -1, t0 = 0, tc = 0;
   if (tile < A.n_tiles) {
     if (!kFree) {
@@ -168,65 +197,111 @@ __global__ __launch_bounds__(kBlock) void k_direct_f64(DirectArgs A) {
   k = uniform(k);
   t0 = uniform(t0);
   tc = uniform(tc);
+  if (tc <= 0) return;  // whole wave idle (no barriers in this kernel)
 
-  double tx[kTpl], ty[kTpl], tz[kTpl], ax[kTpl], ay[kTpl], az[kTpl];
+  Acc<kTpl> acc;
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
     const int i = lane + kWave * p;
     const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
-    tx[p] = A.tgt[3 * ti];
-    ty[p] = A.tgt[3 * ti + 1];
-    tz[p] = A.tgt[3 * ti + 2];
-    ax[p] = ay[p] = az[p] = 0.0;
+    acc.tx[p] = A.tgt[3 * ti];
+    acc.ty[p] = A.tgt[3 * ti + 1];
+    acc.tz[p] = A.tgt[3 * ti + 2];
+    acc.ax[p] = acc.ay[p] = acc.az[p] = 0.0;
   }
 
-  const int64_t S = A.kb[3];
-  const int64_t lo = S * blockIdx.y / A.n_splits;
-  const int64_t hi = S * (blockIdx.y + 1) / A.n_splits;
-
-  for (int kd = 0; kd < 3; ++kd) {
-    const int64_t a0 = max(lo, A.kb[kd]), a1 = min(hi, A.kb[kd + 1]);
-    int64_t slo = 0, shi = 0;
-    if (k >= 0) {
-      slo = A.meta[k].k0[kd];
-      shi = slo + A.meta[k].kn[kd];
-    }
-    for (int64_t j0 = a0; j0 < a1; j0 += kTileSrc) {
-      const int cnt = (int)min((int64_t)kTileSrc, a1 - j0);
-      __syncthreads();
-      if ((int)threadIdx.x < cnt) {
-        const int64_t j = j0 + threadIdx.x;
-        double f0 = A.str[3 * j], f1 = A.str[3 * j + 1], f2 = A.str[3 * j + 2];
-        if (kd == 2) {
-          f0 *= A.dscale;
-          f1 *= A.dscale;
-          f2 *= A.dscale;
-        }
-        sh[0][threadIdx.x] = make_double2(A.src[3 * j], A.src[3 * j + 1]);
-        sh[1][threadIdx.x] = make_double2(A.src[3 * j + 2], f0);
-        sh[2][threadIdx.x] = make_double2(f1, f2);
-      }
-      __syncthreads();
-      if (tc == 0) continue;
-      int b1 = cnt, a2 = cnt;
-      if (shi > slo) {
-        b1 = (int)min<int64_t>(max<int64_t>(slo - j0, 0), cnt);
-        a2 = (int)min<int64_t>(max<int64_t>(shi - j0, 0), cnt);
-      }
-      if (kd == 0) {
-        body_s<kTpl>(sh, 0, b1, tx, ty, tz, ax, ay, az);
-        body_s<kTpl>(sh, a2, cnt, tx, ty, tz, ax, ay, az);
-      } else if (kd == 1) {
-        body_r<kTpl>(sh, 0, b1, tx, ty, tz, ax, ay, az);
-        body_r<kTpl>(sh, a2, cnt, tx, ty, tz, ax, ay, az);
-      } else {
-        body_d<kTpl>(sh, 0, b1, tx, ty, tz, ax, ay, az);
-        body_d<kTpl>(sh, a2, cnt, tx, ty, tz, ax, ay, az);
-      }
+  const int64_t L = A.range_total;
+  const int64_t lo = L * blockIdx.y / A.n_splits;
+  const int64_t hi = L * (blockIdx.y + 1) / A.n_splits;
+  int64_t pos = 0;
+  for (int r = 0; r < A.n_ranges && pos < hi; ++r) {
+    const SrcRange R = A.ranges[r];
+    const int64_t len = R.end - R.begin;
+    const int64_t a = max<int64_t>(lo - pos, 0), b = min<int64_t>(hi - pos, len);
+    pos += len;
+    if (a >= b) continue;
+    const int64_t j0 = R.begin + a, j1 = R.begin + b;
+    if (k >= 0) {  // cut the tile's own sphere out of this block
+      const int64_t s0 = A.meta[k].k0[R.block], s1 = s0 + A.meta[k].kn[R.block];
+      run_block<kTpl, kFree>(R.block, A, j0, min(j1, s0), acc);
+      run_block<kTpl, kFree>(R.block, A, max(j0, s1), j1, acc);
+    } else {
+      run_block<kTpl, kFree>(R.block, A, j0, j1, acc);
     }
   }
 
   double *out = A.part + (int64_t)blockIdx.y * A.T * 3;
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    if (i < tc) {
+      const int64_t o = 3 * ((int64_t)t0 + i);
+      out[o] = acc.ax[p];
+      out[o + 1] = acc.ay[p];
+      out[o + 2] = acc.az[p];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Direct sum, FP32 (mixed precision): Stokeslets of contact-free spheres
+// only (every pair with such a source is well separated: its sphere has no
+// neighbour closer than the image cutoff).  Coordinates are relative to
+// each sphere's centre; the centre offset of every source sphere is formed
+// in FP64 and rounded once, so the FP32 separation keeps its relative
+// accuracy at every distance.  Accumulation in FP32.
+
+template <int kTpl>
+__global__ __launch_bounds__(kBlock) void k_far_f32(Far32Args A) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (tile >= A.n_tiles) return;
+  const int4 tl = A.tiles[tile];
+  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  if (tc <= 0) return;
+  float tx[kTpl], ty[kTpl], tz[kTpl], ax[kTpl], ay[kTpl], az[kTpl];
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
+    tx[p] = A.tgt32[3 * ti];
+    ty[p] = A.tgt32[3 * ti + 1];
+    tz[p] = A.tgt32[3 * ti + 2];
+    ax[p] = ay[p] = az[p] = 0.f;
+  }
+  const double ckx = A.centers[3 * k], cky = A.centers[3 * k + 1], ckz = A.centers[3 * k + 2];
+  const int q0 = (int)((int64_t)A.n_free * blockIdx.y / A.n_splits);
+  const int q1 = (int)((int64_t)A.n_free * (blockIdx.y + 1) / A.n_splits);
+  for (int q = q0; q < q1; ++q) {
+    const int ks = A.free_ids[q];
+    if (ks == k) continue;
+    const float dx = (float)(A.centers[3 * ks] - ckx), dy = (float)(A.centers[3 * ks + 1] - cky),
+                dz = (float)(A.centers[3 * ks + 2] - ckz);
+    float ux[kTpl], uy[kTpl], uz[kTpl];
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      ux[p] = tx[p] - dx;
+      uy[p] = ty[p] - dy;
+      uz[p] = tz[p] - dz;
+    }
+    const int64_t j0 = (int64_t)ks * A.n_proxy, j1 = j0 + A.n_proxy;
+    for (int64_t j = j0; j < j1; ++j) {
+      const float *ps = A.src32 + 3 * j, *pf = A.str32 + 3 * j;
+      const float sx = ps[0], sy = ps[1], sz = ps[2], fx = pf[0], fy = pf[1], fz = pf[2];
+#pragma unroll
+      for (int p = 0; p < kTpl; ++p) {
+        const float rx = ux[p] - sx, ry = uy[p] - sy, rz = uz[p] - sz;
+        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float rf = fmaf(rx, fx, fmaf(ry, fy, rz * fz));
+        const float t = rf * (ri * ri);
+        ax[p] = fmaf(fmaf(rx, t, fx), ri, ax[p]);
+        ay[p] = fmaf(fmaf(ry, t, fy), ri, ay[p]);
+        az[p] = fmaf(fmaf(rz, t, fz), ri, az[p]);
+      }
+    }
+  }
+  float *out = A.part32 + (int64_t)blockIdx.y * A.T * 3;
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
     const int i = lane + kWave * p;
@@ -240,16 +315,35 @@ __global__ __launch_bounds__(kBlock) void k_direct_f64(DirectArgs A) {
 }
 
 __global__ void k_reduce_epilogue(int64_t n3, int32_t ns, const double *__restrict__ part,
+                                  int32_t ns32, const float *__restrict__ part32,
                                   const double *__restrict__ base, const double *__restrict__ sw,
                                   double c0, double *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
   double acc = 0.0;
   for (int s = 0; s < ns; ++s) acc += part[(int64_t)s * n3 + i];
+  for (int s = 0; s < ns32; ++s) acc += (double)part32[(int64_t)s * n3 + i];
   double v = c0 * acc;
   if (sw) v *= sw[i / 3];
   if (base) v += base[i];
   y[i] = v;
+}
+
+// Packed index of local source jl of sphere m (local order: proxy
+// Stokeslets, image Stokeslets, rotlets, dipoles).
+__device__ __forceinline__ int64_t packed_index(const SphereMeta &m, int jl) {
+  if (jl < m.kn[0]) return m.k0[0] + jl;
+  jl -= m.kn[0];
+  if (jl < m.kn[1]) return m.k0[1] + jl;
+  jl -= m.kn[1];
+  if (jl < m.kn[2]) return m.k0[2] + jl;
+  return m.k0[3] + (jl - m.kn[2]);
+}
+
+__device__ __forceinline__ int block_kind(const SphereMeta &m, int jl) {
+  if (jl < m.kn[0] + m.kn[1]) return 0;
+  if (jl < m.kn[0] + m.kn[1] + m.kn[2]) return 1;
+  return 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -289,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_pinv_v(const RowTask *__restrict__ t
                                                    const FactorSlot *__restrict__ fs,
                                                    const double *__restrict__ fac,
                                                    const double *__restrict__ sbuf,
-                                                   double *__restrict__ lam) {
+                                                   double *__restrict__ lam, double dscale) {
   const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (t >= n) return;
   const int lane = threadIdx.x & (kWave - 1);
@@ -311,12 +405,80 @@ __global__ __launch_bounds__(kBlock) void k_pinv_v(const RowTask *__restrict__ t
   const double s = wave_sum((a0 + a1) + (a2 + a3));
   if (lane == 0) {
     const int jl = r / 3, c = r - 3 * (r / 3);
-    int64_t p;
-    if (jl < m.kn[0]) p = m.k0[0] + jl;
-    else if (jl < m.kn[0] + m.kn[1]) p = m.k0[1] + (jl - m.kn[0]);
-    else p = m.k0[2] + (jl - m.kn[0] - m.kn[1]);
-    lam[3 * p + c] = s;
+    const bool dip = jl >= m.kn[0] + m.kn[1] + m.kn[2];
+    lam[3 * packed_index(m, jl) + c] = dip ? s * dscale : s;
   }
+}
+
+// FP32 pseudo-inverse apply for contact-free spheres (mixed precision):
+// FP32 copies of the shared factor, FP32 accumulation; the strengths are
+// written to the FP32 proxy array read by k_far_f32.
+__global__ __launch_bounds__(kBlock) void k_pinv_u32(const RowTask *__restrict__ tasks, int64_t n,
+                                                     const SphereMeta *__restrict__ meta,
+                                                     const FactorSlot *__restrict__ fs,
+                                                     const float *__restrict__ fac32, int64_t off0,
+                                                     const double *__restrict__ mu,
+                                                     float *__restrict__ sbuf) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (t >= n) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int k = uniform(tasks[t].sphere), j = uniform(tasks[t].row);
+  const SphereMeta &m = meta[k];
+  const FactorSlot &f = fs[m.fid];
+  const int rows = f.rows;
+  const float *col = fac32 + (f.u_off - off0) + (int64_t)j * rows;
+  const double *x = mu + 3 * m.t0;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int i = lane;
+  for (; i + 3 * kWave < rows; i += 4 * kWave) {
+    a0 = fmaf(col[i], (float)x[i], a0);
+    a1 = fmaf(col[i + kWave], (float)x[i + kWave], a1);
+    a2 = fmaf(col[i + 2 * kWave], (float)x[i + 2 * kWave], a2);
+    a3 = fmaf(col[i + 3 * kWave], (float)x[i + 3 * kWave], a3);
+  }
+  for (; i < rows; i += kWave) a0 = fmaf(col[i], (float)x[i], a0);
+  float v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) sbuf[m.s0 + j] = v / fac32[(f.sig_off - off0) + j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pinv_v32(const RowTask *__restrict__ tasks, int64_t n,
+                                                     const SphereMeta *__restrict__ meta,
+                                                     const FactorSlot *__restrict__ fs,
+                                                     const float *__restrict__ fac32, int64_t off0,
+                                                     const float *__restrict__ sbuf,
+                                                     float *__restrict__ str32) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (t >= n) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int k = uniform(tasks[t].sphere), r = uniform(tasks[t].row);
+  const SphereMeta &m = meta[k];
+  const FactorSlot &f = fs[m.fid];
+  const int rank = m.rank;
+  const float *row = fac32 + (f.vt_off - off0) + (int64_t)r * f.cols;
+  const float *x = sbuf + m.s0;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int i = lane;
+  for (; i + 3 * kWave < rank; i += 4 * kWave) {
+    a0 = fmaf(row[i], x[i], a0);
+    a1 = fmaf(row[i + kWave], x[i + kWave], a1);
+    a2 = fmaf(row[i + 2 * kWave], x[i + 2 * kWave], a2);
+    a3 = fmaf(row[i + 3 * kWave], x[i + 3 * kWave], a3);
+  }
+  for (; i < rank; i += kWave) a0 = fmaf(row[i], x[i], a0);
+  float v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) {
+    const int jl = r / 3, c = r - 3 * (r / 3);   // contact-free: proxies only (block 0)
+    str32[3 * (m.k0[0] + jl) + c] = v;
+  }
+}
+
+__global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -345,8 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_force_torque(const SphereMeta *__res
   const int k = blockIdx.x;
   const SphereMeta &m = meta[k];
   double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int j = threadIdx.x; j < m.kn[0]; j += kBlock) {
-    const int64_t p = m.k0[0] + j;
+  for (int j = threadIdx.x; j < m.kn[0] + m.kn[1]; j += kBlock) {
+    const int64_t p = j < m.kn[0] ? m.k0[0] + j : m.k0[1] + (j - m.kn[0]);
     const double f0 = lam[3 * p], f1 = lam[3 * p + 1], f2 = lam[3 * p + 2];
     const double y0 = src[3 * p] - m.c[0], y1 = src[3 * p + 1] - m.c[1], y2 = src[3 * p + 2] - m.c[2];
     v[0] += f0;
@@ -356,8 +518,8 @@ __global__ __launch_bounds__(kBlock) void k_force_torque(const SphereMeta *__res
     v[4] += y2 * f0 - y0 * f2;
     v[5] += y0 * f1 - y1 * f0;
   }
-  for (int j = threadIdx.x; j < m.kn[1]; j += kBlock) {
-    const int64_t p = m.k0[1] + j;
+  for (int j = threadIdx.x; j < m.kn[2]; j += kBlock) {
+    const int64_t p = m.k0[2] + j;
     v[3] += lam[3 * p];
     v[4] += lam[3 * p + 1];
     v[5] += lam[3 * p + 2];
@@ -460,11 +622,8 @@ __global__ void k_assemble(const double *__restrict__ tgt, const double *__restr
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t i = idx % M, jl = idx / M;
-  int kind;
-  int64_t p;
-  if (jl < m.kn[0]) { kind = 0; p = m.k0[0] + jl; }
-  else if (jl < m.kn[0] + m.kn[1]) { kind = 1; p = m.k0[1] + (jl - m.kn[0]); }
-  else { kind = 2; p = m.k0[2] + (jl - m.kn[0] - m.kn[1]); }
+  const int kind = block_kind(m, (int)jl);
+  const int64_t p = packed_index(m, (int)jl);
   const int64_t ti = m.t0 + i;
   const double r[3] = {tgt[3 * ti] - src[3 * p], tgt[3 * ti + 1] - src[3 * p + 1],
                        tgt[3 * ti + 2] - src[3 * p + 2]};
@@ -611,17 +770,49 @@ hipError_t launch_direct_f64(const DirectArgs &a, hipStream_t s) {
   // free points (no tile table) get their own instantiation so that kernel
   // statistics of the product with G_hat are not mixed with flow evaluation
   if (a.tiles)
-    hipLaunchKernelGGL((k_direct_f64<2, false>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_direct_f64<kDirectTpl, false>), grid, dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((k_direct_f64<2, true>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_direct_f64<kDirectTpl, true>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_epilogue(int64_t n3, int32_t ns, const double *part, const double *base,
-                                  const double *sw, double c0, double *y, hipStream_t s) {
+hipError_t launch_far_f32(const Far32Args &a, hipStream_t s) {
+  if (a.n_tiles == 0 || a.n_splits == 0) return hipSuccess;
+  dim3 grid((unsigned)((a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)a.n_splits);
+  hipLaunchKernelGGL((k_far_f32<kDirectTpl>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_epilogue(int64_t n3, int32_t ns, const double *part, int32_t ns32,
+                                  const float *part32, const double *base, const double *sw,
+                                  double c0, double *y, hipStream_t s) {
   if (n3 == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_epilogue, dim3(blocks_for(n3)), dim3(kBlock), 0, s, n3, ns, part,
-                     base, sw, c0, y);
+                     ns32, part32, base, sw, c0, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_pinv_u32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
+                           const FactorSlot *fs, const float *fac32, int64_t off0,
+                           const double *mu, float *sbuf, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pinv_u32, dim3(blocks_for(n, kWavesPerBlock)), dim3(kBlock), 0, s, tasks, n,
+                     meta, fs, fac32, off0, mu, sbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_pinv_v32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
+                           const FactorSlot *fs, const float *fac32, int64_t off0,
+                           const float *sbuf, float *str32, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pinv_v32, dim3(blocks_for(n, kWavesPerBlock)), dim3(kBlock), 0, s, tasks, n,
+                     meta, fs, fac32, off0, sbuf, str32);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, y);
   return hipGetLastError();
 }
 
@@ -636,10 +827,10 @@ hipError_t launch_pinv_u(const RowTask *tasks, int64_t n, const SphereMeta *meta
 
 hipError_t launch_pinv_v(const RowTask *tasks, int64_t n, const SphereMeta *meta,
                          const FactorSlot *fs, const double *fac, const double *sbuf, double *lam,
-                         hipStream_t s) {
+                         double dscale, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pinv_v, dim3(blocks_for(n, kWavesPerBlock)), dim3(kBlock), 0, s, tasks, n,
-                     meta, fs, fac, sbuf, lam);
+                     meta, fs, fac, sbuf, lam, dscale);
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ EXPORTED = [
     "smfs_params_default", "smfs_problem_create", "smfs_problem_destroy", "smfs_problem_sizes",
     "smfs_export_nodes", "smfs_sphere_factor", "smfs_factor_info", "smfs_bind", "smfs_setup",
     "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_force_torque",
-    "smfs_eval_velocity", "smfs_solve_resistance", "smfs_pairs_per_apply", "smfs_profile",
+    "smfs_eval_velocity", "smfs_solve_resistance", "smfs_set_solver", "smfs_pairs_per_apply",
+    "smfs_profile",
     "smfs_profile_read", "smfs_last_error",
 ]
 
@@ -58,6 +59,7 @@ class smfs_out(C.Structure):
         ("true_rel_residual", C.c_double), ("lambda_inf", C.c_double),
         ("eps_res_max", C.c_double), ("abs_res_max", C.c_double), ("t_rhs_ms", C.c_double),
         ("t_gmres_ms", C.c_double), ("t_post_ms", C.c_double), ("pair_evals", C.c_int64),
+        ("pair_evals_f32", C.c_int64), ("refinements", C.c_int32),
     ]
 
 
@@ -65,6 +67,8 @@ class smfs_kernel_stats(C.Structure):
     _fields_ = [
         ("direct_launches", C.c_int64), ("direct_ms", C.c_double), ("direct_flops", C.c_double),
         ("pinv_launches", C.c_int64), ("pinv_ms", C.c_double), ("pinv_bytes", C.c_double),
+        ("far32_launches", C.c_int64), ("far32_ms", C.c_double), ("far32_flops", C.c_double),
+        ("mixed64_launches", C.c_int64), ("mixed64_ms", C.c_double), ("mixed64_flops", C.c_double),
     ]
 
 
@@ -100,6 +104,7 @@ def lib():
         "smfs_eval_velocity": ([vp, vp, i64, vp, vp, vp], C.c_int),
         "smfs_solve_resistance": ([vp, vp, P(smfs_out), vp], C.c_int),
         "smfs_pairs_per_apply": ([vp], i64),
+        "smfs_set_solver": ([vp, i32, dbl, i32], C.c_int),
         "smfs_profile": ([vp, i32], C.c_int),
         "smfs_profile_read": ([vp, P(smfs_kernel_stats)], C.c_int),
         "smfs_last_error": ([], C.c_char_p),
@@ -205,6 +210,14 @@ class Problem:
     def pairs_per_apply(self):
         return int(lib().smfs_pairs_per_apply(self.h))
 
+    def set_solver(self, precision=None, tol=None, max_it=None):
+        p = self.params
+        precision = p.precision if precision is None else precision
+        tol = p.gmres_tol if tol is None else tol
+        max_it = p.gmres_max_it if max_it is None else max_it
+        _check(lib().smfs_set_solver(self.h, precision, tol, max_it), "smfs_set_solver")
+        p.precision, p.gmres_tol, p.gmres_max_it = precision, tol, max_it
+
     def profile(self, enable: bool):
         _check(lib().smfs_profile(self.h, 1 if enable else 0), "smfs_profile")
 
@@ -300,4 +313,5 @@ class Problem:
                     true_rel_residual=o.true_rel_residual, lambda_inf=o.lambda_inf,
                     eps_res_max=o.eps_res_max, abs_res_max=o.abs_res_max,
                     t_rhs_ms=o.t_rhs_ms, t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms,
-                    pair_evals=o.pair_evals)
+                    pair_evals=o.pair_evals, pair_evals_f32=o.pair_evals_f32,
+                    refinements=o.refinements)

@@ -107,6 +107,77 @@ def cluster(P: int, phi: float, gap_lo: float, gap_hi: float, seed: int,
                    anchor_gaps=np.asarray(gaps))
 
 
+def fluid_with_pairs(P: int, phi: float, gap_min: float, pair_frac: float, pair_lo: float,
+                     pair_hi: float, seed: int, sweeps: int = 40, radius: float = 1.0,
+                     pair_gap_min: float = 0.1) -> Packing:
+    """Random packing of ``P`` spheres in a cube at volume fraction ``phi``:
+    a hard-sphere Monte Carlo fluid (random displacements from a cubic
+    lattice start) in which every surface gap stays at least ``gap_min``;
+    then a fraction ``pair_frac`` of the spheres is pulled together in
+    nearest-neighbour pairs, each pair moved symmetrically along its line of
+    centres to a gap log-uniform in [pair_lo, pair_hi], keeping a gap of at
+    least ``pair_gap_min`` to every other sphere."""
+    rng = np.random.default_rng(seed)
+    a = radius
+    L = (P * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0) * a
+    n_side = int(math.ceil(P ** (1.0 / 3.0)))
+    s = (L - 2.0 * a) / max(1, n_side - 1)
+    if s < (2.0 + gap_min) * a:
+        raise ValueError("volume fraction too high for the lattice start")
+    idx = np.array([(i, j, k) for i in range(n_side) for j in range(n_side)
+                    for k in range(n_side)])
+    idx = idx[rng.permutation(len(idx))[:P]]
+    c = a + idx * s
+    dmin = (2.0 + gap_min) * a
+    step = 0.5 * (s - dmin) + 0.1 * a
+    for _ in range(sweeps):
+        for i in rng.permutation(P):
+            trial = c[i] + rng.uniform(-step, step, 3)
+            if np.any(trial < a) or np.any(trial > L - a):
+                continue
+            d2 = ((c - trial) ** 2).sum(1)
+            d2[i] = np.inf
+            if d2.min() >= dmin * dmin:
+                c[i] = trial
+    # pull nearest-neighbour pairs together
+    n_pairs = int(round(pair_frac * P / 2.0))
+    used = np.zeros(P, bool)
+    lg_lo, lg_hi = math.log10(pair_lo), math.log10(pair_hi)
+    made, tries = 0, 0
+    while made < n_pairs and tries < 100 * P:
+        tries += 1
+        i = int(rng.integers(P))
+        if used[i]:
+            continue
+        d = np.sqrt(((c - c[i]) ** 2).sum(1))
+        d[i] = np.inf
+        d[used] = np.inf
+        j = int(np.argmin(d))
+        if not np.isfinite(d[j]):
+            continue
+        g = 10.0 ** rng.uniform(lg_lo, lg_hi)
+        e = (c[j] - c[i]) / d[j]
+        mid = 0.5 * (c[i] + c[j])
+        ci, cj = mid - (1.0 + 0.5 * g) * a * e, mid + (1.0 + 0.5 * g) * a * e
+        ok = True
+        for cn, self_, other in ((ci, i, j), (cj, j, i)):
+            dd = np.sqrt(((c - cn) ** 2).sum(1)) / a - 2.0
+            dd[[self_, other]] = np.inf
+            if dd.min() < pair_gap_min:
+                ok = False
+        if not ok:
+            continue
+        c[i], c[j] = ci, cj
+        used[i] = used[j] = True
+        made += 1
+    return Packing(centers=c, radius=a, box=L)
+
+
+def random_ft(P: int, nrhs: int, seed: int) -> np.ndarray:
+    """Forces and torques, shape (nrhs, P, 6), every component N(0, 1)."""
+    return np.random.default_rng(seed).standard_normal((nrhs, P, 6))
+
+
 def random_rbm(P: int, nrhs: int, seed: int) -> np.ndarray:
     """Rigid-body velocities, shape (nrhs, P, 6) = (v_x, v_y, v_z, w_x, w_y,
     w_z), every component N(0, 1)."""
@@ -136,6 +207,14 @@ def random_vector(n: int, seed: int) -> np.ndarray:
 def workload_two_sphere_gap001():
     """Two unit spheres, gap 0.01 radius, separating at unit relative speed."""
     return two_sphere(0.01), separating_pair_rbm(1.0)
+
+
+def workload_packing2000(P: int = 2000, seed: int = 0):
+    """Unit spheres at volume fraction 0.3: a hard-sphere fluid with every
+    gap at least 0.2 (the image cutoff), with 5% of the spheres pulled into
+    near-contact pairs at gaps log-uniform in [1e-3, 1e-2].  ``P`` < 2000
+    gives a cut of the same recipe."""
+    return fluid_with_pairs(P, 0.3, 0.2, 0.05, 1e-3, 1e-2, seed=seed)
 
 
 def workload_cluster100(seed: int = 0):

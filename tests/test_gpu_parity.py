@@ -262,3 +262,62 @@ def test_full_size_cluster_sampled(dev, oracle_pairsum_built):
     crow = np.random.default_rng(24).choice(g.check.shape[0], 400, replace=False)
     uref = pairsum(g.check[crow], g.src_pos, g.src_kind, lam.reshape(-1, 3), 1.0)
     assert _rel(u[crow], uref) < 1e-10
+
+
+# -- mixed precision ------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def mixed_small(dev, oracle_pairsum_built):
+    """Twelve spheres, small discretisation: one near-contact pair (gap 2e-3,
+    FP64 throughout) and ten contact-free spheres (FP32 in mixed mode)."""
+    rng = np.random.default_rng(31)
+    c = [np.array([0.0, 0.0, 0.0]), np.array([2.002, 0.0, 0.0])]
+    while len(c) < 12:
+        x = rng.uniform(-6, 8, 3)
+        if all(np.linalg.norm(x - y) > 2.4 for y in c):
+            c.append(x)
+    c = np.array(c)
+    small = dict(n_proxy=120, n_colloc_base=160, n_image=6, n_check_base=80)
+    g = geo.build(c, 1.0, geo.Params(n_proxy=120, n_colloc_base=160, n_image=6, n_check_base=80))
+    pbo = mfs.Problem(g).setup()
+    libs = {}
+    for name, prec in (("fp64", dev.SMFS_FP64), ("mixed", dev.SMFS_MIXED)):
+        lib = dev.Problem(c, 1.0, precision=prec, gmres_tol=1e-10, **small).bind()
+        _import_oracle_factors(lib, pbo)
+        libs[name] = lib
+    return dict(g=g, pb=pbo, libs=libs)
+
+
+def test_mixed_apply_close_to_oracle(dev, mixed_small):
+    _say("mixed-precision product vs FP64 oracle")
+    pbo = mixed_small["pb"]
+    rbm = wl.random_rbm(pbo.g.P, 1, 32)[0]
+    b = pbo.rhs(rbm)
+    ref = pbo.apply(b)
+    y = _n(mixed_small["libs"]["mixed"].apply(_t(b), precision=dev.SMFS_MIXED))
+    y64 = _n(mixed_small["libs"]["mixed"].apply(_t(b), precision=dev.SMFS_FP64))
+    _say(f"  mixed rel diff {_rel(y, ref):.3e}; fp64 rel diff {_rel(y64, ref):.3e}")
+    assert _rel(y64, ref) < 1e-10
+    assert _rel(y, ref) < 1e-5
+    # rows of the near-contact pair see contact-free sources in FP32 only
+    # through far pairs; the pair's own interaction stays FP64
+
+
+def test_mixed_solve_within_stated_tolerances(dev, mixed_small):
+    """Mixed form against the FP64 oracle: surface velocity to 1e-3 and
+    forces/torques to 1e-5 (relative)."""
+    _say("mixed-precision solve vs FP64 oracle")
+    pbo, g = mixed_small["pb"], mixed_small["g"]
+    rbm = wl.random_rbm(g.P, 1, 33)[0]
+    ref = mfs.solve_resistance(pbo, rbm, tol=1e-10)
+    u_ref = pbo.velocity(ref["lam"], g.check)
+    out = mixed_small["libs"]["mixed"].solve_resistance(_t(rbm))
+    ft = _n(out["ft"]).reshape(-1, 6)
+    u = _n(out["u_check"]).reshape(-1, 3)
+    dF = np.abs(ft - ref["ft"]).max() / np.abs(ref["ft"]).max()
+    du = np.abs(u - u_ref).max() / np.abs(u_ref).max()
+    _say(f"  it {out['iterations']} (+{out['refinements']} refinements), true {out['true_rel_residual']:.2e}, "
+         f"F/T {dF:.2e}, u {du:.2e}, fp32 pairs {out['pair_evals_f32']:.3e} of {out['pair_evals']:.3e}")
+    assert out["pair_evals_f32"] > 0
+    assert dF < 1e-5
+    assert du < 1e-3
