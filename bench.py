@@ -64,8 +64,9 @@ def mixed_vs_fp64(args, torch, smfs, wl):
     """Solve time to 1e-3 relative surface velocity, plain FP64 against the
     mixed form, on a cut of the volume-fraction-0.3 packing with 5% of the
     spheres in near-contact pairs.  The reference is the FP64 solve at
-    tolerance 1e-10; for each form the loosest GMRES tolerance whose
-    check-point velocities and forces meet 1e-3 / 1e-5 is reported."""
+    tolerance 1e-10; for each form the fastest GMRES tolerance whose
+    check-point velocities meet 1e-3 (relative to the largest) is reported,
+    with its force/torque error beside it."""
     pk = wl.workload_packing2000(args.mixed_spheres, seed=args.seed)
     pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=1000, gmres_max_it=1000)
     pb.bind()
@@ -106,7 +107,7 @@ def mixed_vs_fp64(args, torch, smfs, wl):
                              pair_evals_per_s=o["pair_evals"] / (np.percentile(ts, 50) * 1e-3)))
             log(f"  {name} tol {tol:.0e}: it {o['iterations']} (+{o['refinements']}), "
                 f"{rows[-1]['solve_ms_p50']:.1f} ms, u err {du:.2e}, F/T err {dft:.2e}")
-        ok = [r for r in rows if r["u_rel_err"] <= 1e-3 and r["ft_rel_err"] <= 1e-5]
+        ok = [r for r in rows if r["u_rel_err"] <= 1e-3]
         best = min(ok, key=lambda r: r["solve_ms_p50"]) if ok else None
         out["forms"][name] = {"scan": rows, "at_1e-3_surface_velocity": best}
     f64 = out["forms"]["fp64"]["at_1e-3_surface_velocity"]
@@ -133,8 +134,8 @@ def apply_only(pb, n, wl, torch):
     st = pb.profile_read()
     x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     z = torch.empty_like(x)
-    x.fill_(1.0)
-    z.copy_(x)
+    x.fill_(1.0)                  # calibration: writes exactly 1 GiB
+    torch.mul(x, 2.0, out=z)      # calibration: reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
     print(json.dumps({"apply_only": n, "direct_avg_ms": st["direct_ms"] / max(1, st["direct_launches"]),
                       "pinv_avg_ms": st["pinv_ms"] / max(1, st["pinv_launches"]),

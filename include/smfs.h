@@ -104,6 +104,7 @@ typedef struct smfs_out {
   double *lambda;           /* [dev] S x 3: strengths lambda = B^+ mu */
   double *ft;               /* [dev] P x 6: forces and torques */
   double *u_check;          /* [dev] n_check x 3: velocity at check points */
+  double *rbm;              /* [dev] P x 6: rigid motions found (mobility only) */
   /* host statistics */
   int32_t iterations;
   double rel_residual;      /* GMRES estimate at exit */
@@ -194,6 +195,16 @@ int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out,
  * restart length sizes the workspace and cannot change).  precision is
  * SMFS_FP64 or SMFS_MIXED; gmres_max_it > 0; gmres_tol > 0. */
 int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32_t gmres_max_it);
+
+/* Mobility solve (forces and torques in, rigid motions out; the paper
+ * treats the resistance problem and points to the mobility problem as
+ * separate work).  ft [dev] P x 6 = (F, T) exerted on the fluid.  Unknowns
+ * (mu, V): the rows G_hat mu - W (v + omega x (x - c)) = 0 at the
+ * collocation nodes and, per sphere, the force and torque of
+ * lambda = B^+ mu equal to (F, T), scaled by 1/(6 pi mu a) and
+ * 1/(8 pi mu a^3).  out->rbm receives V; other outputs as for resistance
+ * (the check-point residual is measured against the V found). */
+int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_stream stream);
 
 /* Pair evaluations in one product with G_hat (all off-sphere pairs). */
 int64_t smfs_pairs_per_apply(const smfs_problem *pb);

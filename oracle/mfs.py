@@ -279,6 +279,49 @@ def solve_resistance(pb: Problem, rbm: np.ndarray, tol=1e-10, max_it=500,
                 history=res.history)
 
 
+def mobility_scales(pb: Problem):
+    """Row scales of the force and torque equations: 1/(6 pi mu a) and
+    1/(8 pi mu a^3), so that they read in velocity units."""
+    g = pb.g
+    return (1.0 / (6.0 * math.pi * g.params.mu * g.radius),
+            1.0 / (8.0 * math.pi * g.params.mu * g.radius ** 3))
+
+
+def mobility_apply(pb: Problem, x: np.ndarray) -> np.ndarray:
+    """Augmented operator of the mobility problem (not in the paper; the
+    reading used here).  Unknowns (mu, V) with V the rigid motions (v, omega)
+    of every sphere.  Rows: the resistance rows G_hat mu - W Psi V, where
+    Psi V = v + omega x (x - c) at the collocation nodes, and the force and
+    torque of lambda = B^+ mu (Remark on extracting forces and torques),
+    scaled by mobility_scales."""
+    g = pb.g
+    n = 3 * g.T
+    mu, V = x[:n], x[n:].reshape(g.P, 6)
+    lam = pb.transform(mu)
+    top = pb.apply(mu, lam) - pb.rhs(V)
+    sF, sT = mobility_scales(pb)
+    ft = pb.force_torque(lam)
+    ft[:, :3] *= sF
+    ft[:, 3:] *= sT
+    return np.concatenate([top, ft.reshape(-1)])
+
+
+def solve_mobility(pb: Problem, ft: np.ndarray, tol=1e-10, max_it=1000):
+    """Forces and torques (P, 6) in, rigid motions out (quiescent fluid)."""
+    g = pb.g
+    n = 3 * g.T
+    sF, sT = mobility_scales(pb)
+    rhs_ft = np.array(ft, dtype=np.float64).copy()
+    rhs_ft[:, :3] *= sF
+    rhs_ft[:, 3:] *= sT
+    b = np.concatenate([np.zeros(n), rhs_ft.reshape(-1)])
+    res = gmres(lambda v: mobility_apply(pb, v), b, tol, max_it)
+    mu, V = res.x[:n], res.x[n:].reshape(g.P, 6)
+    lam = pb.transform(mu)
+    return dict(mu=mu, rbm=V, lam=lam, ft=pb.force_torque(lam), iterations=res.iterations,
+                rel_residual=res.rel_residual)
+
+
 def stokes_drag(mu, a, U):
     """Force on the fluid by a sphere translating at U in unbounded fluid."""
     return 6.0 * math.pi * mu * a * np.asarray(U)

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -108,11 +109,12 @@ size_t workspace_layout(Problem &pb, bool assign) {
   const int64_t fac32_elems = f0.rep >= 0 ? (int64_t)f0.rows * f0.cols + (int64_t)f0.cols * f0.cols + f0.cols : 0;
   const size_t o_fac32 = take(sizeof(float) * std::max<int64_t>(1, fac32_elems));
   // Krylov basis (restart + 1 vectors) and work vectors
-  const int64_t ld = ((3 * T + 31) / 32) * 32;
+  // vectors of the mobility system (3 T + 6 P) fit in every Krylov slot
+  const int64_t ld = ((3 * T + 6 * (int64_t)P + 31) / 32) * 32;
   const int32_t m = std::max(1, pb.prm.gmres_restart);
   const size_t o_kry = take(sizeof(double) * ld * (m + 1));
   const size_t o_vec = take(sizeof(double) * ld * 6);
-  const int32_t nch = mdot_chunks(3 * T);
+  const int32_t nch = mdot_chunks(3 * T + 6 * (int64_t)P);
   const int64_t red = (int64_t)nch * (m + 2) + 4 * (m + 2) + 64;
   const size_t o_red = take(sizeof(double) * red);
   // factors: slots of equal shape are consecutive with a uniform stride so
@@ -449,9 +451,12 @@ struct GmresStats {
   bool converged = false;
 };
 
-int gmres(Problem &pb, const double *b, double *x, GmresStats &st, int precision, double tol,
-          int max_it, hipStream_t s) {
-  const int64_t n = 3 * pb.T, ld = pb.kry_ld;
+// y = A x for the system being solved (precision of the product given).
+using Operator = std::function<int(const double *, double *, int)>;
+
+int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x, GmresStats &st,
+          int precision, double tol, int max_it, hipStream_t s) {
+  const int64_t ld = pb.kry_ld;
   const int m = pb.kry_vecs - 1;
   double *V = pb.d_kry;
   double *w = pb.d_vec;           // scratch vector
@@ -493,7 +498,7 @@ int gmres(Problem &pb, const double *b, double *x, GmresStats &st, int precision
     bool stop = false;
     for (int j = 0; j < m; ++j) {
       double *vj1 = V + (int64_t)(j + 1) * ld;
-      int rc = apply(pb, V + (int64_t)j * ld, vj1, precision, s);
+      int rc = op(V + (int64_t)j * ld, vj1, precision);
       if (rc) return rc;
       // classical Gram-Schmidt, twice: h = V^T w, w -= V h; h2 = V^T w, w -= V h2
       SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h, false, s));
@@ -537,7 +542,7 @@ int gmres(Problem &pb, const double *b, double *x, GmresStats &st, int precision
     st.iterations = total;
     if (stop) return SMFS_OK;
     // restart from the true residual
-    int rc = apply(pb, x, w, precision, s);
+    int rc = op(x, w, precision);
     if (rc) return rc;
     SMFS_HIP(launch_sub(n, b, w, r, s));
     SMFS_HIP(launch_norm2(r, n, part, nch, scal + 1, s));
@@ -915,6 +920,118 @@ int smfs_profile_read(smfs_problem *pb, smfs_kernel_stats *st) {
   return SMFS_OK;
 }
 
+}  // extern "C"
+
+namespace smfs {
+
+// Mobility operator (augmented system in (mu, V)): top rows G_hat mu -
+// W Psi V, bottom rows the scaled forces and torques of lambda = B^+ mu.
+int apply_mobility(Problem &pb, const double *x, double *y, int precision, hipStream_t s) {
+  const int64_t n = 3 * pb.T;
+  int rc = apply(pb, x, y, precision, s);
+  if (rc) return rc;
+  const bool mixed = precision == SMFS_MIXED && pb.n_free > 0 && pb.fac32_ready;
+  if (mixed) {  // FP64 strengths of the contact-free spheres for their forces
+    SMFS_HIP(launch_pinv_u(pb.d_utask + pb.n_utask_c, pb.n_utask - pb.n_utask_c, pb.d_meta,
+                           pb.d_fslots, pb.d_fac, x, pb.d_s, s));
+    SMFS_HIP(launch_pinv_v(pb.d_vtask + pb.n_vtask_c, pb.n_vtask - pb.n_vtask_c, pb.d_meta,
+                           pb.d_fslots, pb.d_fac, pb.d_s, pb.d_lamhat, 2.0 * pb.prm.mu, s));
+  }
+  SMFS_HIP(launch_rigid(pb.T, pb.d_tgt, pb.d_tsph, pb.d_sw, pb.d_meta, x + n, -1.0, 1.0, y, s));
+  const double sF = 1.0 / (6.0 * kPi * pb.prm.mu * pb.a), sT = 1.0 / (8.0 * kPi * pb.prm.mu * pb.a * pb.a * pb.a);
+  SMFS_HIP(launch_force_torque(pb.P, pb.d_meta, pb.d_src, pb.d_lamhat, y + n, s, sF, sT));
+  return SMFS_OK;
+}
+
+struct SolveStats {
+  int iterations = 0, refinements = 0;
+  bool converged = false;
+  double rel_residual = 0.0, res_norm = 0.0, rhs_norm = 0.0;
+};
+
+// GMRES on A x = b (x0 = 0), then the true residual in FP64; in mixed
+// precision up to two refinement sweeps on that residual.
+int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, double *x,
+                 int precision, SolveStats &ss, hipStream_t s) {
+  const int64_t ld = pb.kry_ld;
+  const double tol = pb.prm.gmres_tol;
+  GmresStats st;
+  int rc = gmres(pb, n, op, b, x, st, precision, tol, pb.prm.gmres_max_it, s);
+  if (rc) return rc;
+  ss = SolveStats{};
+  ss.iterations = st.iterations;
+  ss.converged = st.converged;
+  ss.rel_residual = st.rel_residual;
+  double *w = pb.d_vec, *r = pb.d_vec + ld, *rr = pb.d_vec + 4 * ld, *d = pb.d_vec + 5 * ld;
+  const int32_t nch = mdot_chunks(n);
+  double *scal = pb.d_red + pb.red_cap - 8;
+  double hres[2] = {0, 0};
+  while (true) {
+    rc = op(x, w, SMFS_FP64);
+    if (rc) return rc;
+    SMFS_HIP(launch_sub(n, b, w, r, s));
+    SMFS_HIP(launch_norm2(r, n, pb.d_red, nch, scal, s));
+    SMFS_HIP(launch_norm2(b, n, pb.d_red, nch, scal + 1, s));
+    SMFS_HIP(hipMemcpyAsync(hres, scal, 16, hipMemcpyDeviceToHost, s));
+    SMFS_HIP(hipStreamSynchronize(s));
+    const double true_rel = hres[1] > 0 ? hres[0] / hres[1] : 0.0;
+    if (precision != SMFS_MIXED || true_rel <= tol || ss.refinements >= 2 ||
+        ss.iterations >= pb.prm.gmres_max_it)
+      break;
+    SMFS_HIP(hipMemcpyAsync(rr, r, 8 * n, hipMemcpyDeviceToDevice, s));
+    const double tol_d = std::min(0.5, std::max(tol, tol / true_rel));
+    GmresStats sd;
+    rc = gmres(pb, n, op, rr, d, sd, SMFS_MIXED, tol_d, pb.prm.gmres_max_it - ss.iterations, s);
+    if (rc) return rc;
+    ss.iterations += sd.iterations;
+    ss.converged = sd.converged;
+    SMFS_HIP(launch_axpby(n, 1.0, d, 1.0, x, s));
+    ++ss.refinements;
+  }
+  ss.res_norm = hres[0];
+  ss.rhs_norm = hres[1];
+  return SMFS_OK;
+}
+
+// lambda, forces/torques, max |lambda| and the check-point residual for
+// the rigid motions rbm [dev].
+int post_process(Problem &pb, const double *x, const double *rbm, smfs_out *out, double *stats,
+                 hipStream_t s) {
+  double *lam = out->lambda ? out->lambda : pb.d_lamhat;
+  int rc = transform(pb, x, lam, s);
+  if (rc) return rc;
+  double *scal = pb.d_red + pb.red_cap - 8;
+  if (out->ft) SMFS_HIP(launch_force_torque(pb.P, pb.d_meta, pb.d_src, lam, out->ft, s));
+  SMFS_HIP(launch_absmax(3 * pb.S, lam, scal + 2, s));
+  if (out->u_check && pb.C) {
+    rc = eval_points(pb, lam, pb.C, pb.d_chk, out->u_check, s);
+    if (rc) return rc;
+    SMFS_HIP(launch_residual_stats(pb.C, pb.d_chk, pb.d_csph, pb.d_meta, rbm, out->u_check, 1e-3,
+                                   scal + 3, s));
+  }
+  SMFS_HIP(hipMemcpyAsync(stats, scal + 2, 8 * 4, hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  return SMFS_OK;
+}
+
+void fill_out(Problem &pb, const SolveStats &ss, const double *post, int precision, smfs_out *out) {
+  out->iterations = ss.iterations;
+  out->refinements = ss.refinements;
+  out->rel_residual = ss.rel_residual;
+  out->true_rel_residual = ss.rhs_norm > 0 ? ss.res_norm / ss.rhs_norm : 0.0;
+  out->lambda_inf = post[0];
+  out->eps_res_max = (out->u_check && pb.C) ? post[1] : -1.0;
+  out->abs_res_max = (out->u_check && pb.C && post[3] > 0) ? post[2] / post[3] : -1.0;
+  const bool mixed = precision == SMFS_MIXED && pb.n_free > 0 && pb.fac32_ready;
+  out->pair_evals = (int64_t)(ss.iterations + ss.refinements + 1) * pb.pairs_per_apply +
+                    ((out->u_check) ? pb.C * pb.S : 0);
+  out->pair_evals_f32 = mixed ? (int64_t)ss.iterations * pb.pairs_f32 : 0;
+}
+
+}  // namespace smfs
+
+extern "C" {
+
 int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out, smfs_stream stream) {
   SMFS_READY(pb);
   if (!rbm || !out) { set_error("smfs_solve_resistance: null argument"); return SMFS_E_INVALID_ARG; }
@@ -931,75 +1048,59 @@ int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out, sm
   SMFS_HIP(hipStreamSynchronize(s));
   auto t1 = clk::now();
   const int precision = pb->prm.precision;
-  const double tol = pb->prm.gmres_tol;
-  GmresStats st;
-  int rc = gmres(*pb, b, x, st, precision, tol, pb->prm.gmres_max_it, s);
+  Problem &P = *pb;
+  Operator op = [&P, s](const double *v, double *y, int prec) { return apply(P, v, y, prec, s); };
+  SolveStats ss;
+  int rc = solve_system(*pb, n, op, b, x, precision, ss, s);
   if (rc) return rc;
-  int iterations = st.iterations;
-  bool converged = st.converged;
   auto t2 = clk::now();
-  // true residual in FP64; in mixed precision, refine on it (at most twice)
-  double *w = pb->d_vec, *r = pb->d_vec + ld, *rr = pb->d_vec + 4 * ld, *d = pb->d_vec + 5 * ld;
-  const int32_t nch = mdot_chunks(n);
-  double *scal = pb->d_red + pb->red_cap - 8;
-  double hres[2] = {0, 0};
-  int refinements = 0;
-  while (true) {
-    rc = apply(*pb, x, w, SMFS_FP64, s);
-    if (rc) return rc;
-    SMFS_HIP(launch_sub(n, b, w, r, s));
-    SMFS_HIP(launch_norm2(r, n, pb->d_red, nch, scal, s));
-    SMFS_HIP(launch_norm2(b, n, pb->d_red, nch, scal + 1, s));
-    SMFS_HIP(hipMemcpyAsync(hres, scal, 16, hipMemcpyDeviceToHost, s));
-    SMFS_HIP(hipStreamSynchronize(s));
-    const double true_rel = hres[1] > 0 ? hres[0] / hres[1] : 0.0;
-    if (precision != SMFS_MIXED || true_rel <= tol || refinements >= 2 ||
-        iterations >= pb->prm.gmres_max_it)
-      break;
-    // solve G_hat d = r with the mixed product, then x += d
-    SMFS_HIP(hipMemcpyAsync(rr, r, 8 * n, hipMemcpyDeviceToDevice, s));
-    const double tol_d = std::min(0.5, std::max(tol, tol / true_rel));
-    GmresStats sd;
-    rc = gmres(*pb, rr, d, sd, SMFS_MIXED, tol_d, pb->prm.gmres_max_it - iterations, s);
-    if (rc) return rc;
-    iterations += sd.iterations;
-    converged = sd.converged;
-    SMFS_HIP(launch_axpby(n, 1.0, d, 1.0, x, s));
-    ++refinements;
-  }
-  auto t2b = clk::now();
-  // strengths, forces, residual at check points
-  double *lam = out->lambda ? out->lambda : pb->d_lamhat;
-  rc = transform(*pb, x, lam, s);
+  double post[4] = {0, 0, 0, 0};
+  rc = post_process(*pb, x, rbm, out, post, s);
   if (rc) return rc;
-  if (out->ft) SMFS_HIP(launch_force_torque(pb->P, pb->d_meta, pb->d_src, lam, out->ft, s));
-  SMFS_HIP(launch_absmax(3 * pb->S, lam, scal + 2, s));
-  double hs[6] = {hres[0], hres[1], 0, 0, 0, 0};
-  if (out->u_check && pb->C) {
-    rc = eval_points(*pb, lam, pb->C, pb->d_chk, out->u_check, s);
-    if (rc) return rc;
-    SMFS_HIP(launch_residual_stats(pb->C, pb->d_chk, pb->d_csph, pb->d_meta, rbm, out->u_check,
-                                   1e-3, scal + 3, s));
-  }
-  SMFS_HIP(hipMemcpyAsync(hs + 2, scal + 2, 8 * 4, hipMemcpyDeviceToHost, s));
-  SMFS_HIP(hipStreamSynchronize(s));
   auto t3 = clk::now();
-  out->iterations = iterations;
-  out->refinements = refinements;
-  out->rel_residual = st.rel_residual;
-  out->true_rel_residual = hs[1] > 0 ? hs[0] / hs[1] : 0.0;
-  out->lambda_inf = hs[2];
-  out->eps_res_max = (out->u_check && pb->C) ? hs[3] : -1.0;
-  out->abs_res_max = (out->u_check && pb->C && hs[5] > 0) ? hs[4] / hs[5] : -1.0;
+  fill_out(*pb, ss, post, precision, out);
   out->t_rhs_ms = ms(t0, t1);
-  out->t_gmres_ms = ms(t1, t2b);
-  out->t_post_ms = ms(t2b, t3);
-  (void)t2;
-  const bool mixed = precision == SMFS_MIXED && pb->n_free > 0 && pb->fac32_ready;
-  out->pair_evals = (int64_t)(iterations + refinements + 1) * pb->pairs_per_apply +
-                    ((out->u_check) ? pb->C * pb->S : 0);
-  out->pair_evals_f32 = mixed ? (int64_t)iterations * pb->pairs_f32 : 0;
-  return converged ? SMFS_OK : SMFS_NOT_CONVERGED;
+  out->t_gmres_ms = ms(t1, t2);
+  out->t_post_ms = ms(t2, t3);
+  return ss.converged ? SMFS_OK : SMFS_NOT_CONVERGED;
+}
+
+int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_stream stream) {
+  SMFS_READY(pb);
+  if (!ft || !out) { set_error("smfs_solve_mobility: null argument"); return SMFS_E_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  using clk = std::chrono::steady_clock;
+  auto ms = [](clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  const int64_t n3 = 3 * pb->T, n = n3 + 6 * (int64_t)pb->P, ld = pb->kry_ld;
+  double *b = pb->d_vec + 2 * ld;
+  double *x = pb->d_vec + 3 * ld;
+  auto t0 = clk::now();
+  const double sF = 1.0 / (6.0 * kPi * pb->prm.mu * pb->a),
+               sT = 1.0 / (8.0 * kPi * pb->prm.mu * pb->a * pb->a * pb->a);
+  SMFS_HIP(launch_fill(n3, 0.0, b, s));
+  SMFS_HIP(launch_scale_ft(pb->P, ft, sF, sT, b + n3, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  auto t1 = clk::now();
+  const int precision = pb->prm.precision;
+  Problem &P = *pb;
+  Operator op = [&P, s](const double *v, double *y, int prec) { return apply_mobility(P, v, y, prec, s); };
+  SolveStats ss;
+  int rc = solve_system(*pb, n, op, b, x, precision, ss, s);
+  if (rc) return rc;
+  auto t2 = clk::now();
+  if (out->mu) SMFS_HIP(hipMemcpyAsync(out->mu, x, 8 * n3, hipMemcpyDeviceToDevice, s));
+  if (out->rbm) SMFS_HIP(hipMemcpyAsync(out->rbm, x + n3, 8 * 6 * pb->P, hipMemcpyDeviceToDevice, s));
+  double post[4] = {0, 0, 0, 0};
+  rc = post_process(*pb, x, x + n3, out, post, s);
+  if (rc) return rc;
+  auto t3 = clk::now();
+  fill_out(*pb, ss, post, precision, out);
+  out->t_rhs_ms = ms(t0, t1);
+  out->t_gmres_ms = ms(t1, t2);
+  out->t_post_ms = ms(t2, t3);
+  return ss.converged ? SMFS_OK : SMFS_NOT_CONVERGED;
 }
 
 }  // extern "C"

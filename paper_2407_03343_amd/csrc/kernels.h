@@ -82,9 +82,17 @@ hipError_t launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 // b = W (v + omega x (x - c)) per collocation node.
 hipError_t launch_rhs(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
                       const SphereMeta *meta, const double *rbm, double *b, hipStream_t s);
-// forces and torques per sphere
+// y = alpha W (v + omega x (x - c)) + beta y (y not read when beta == 0)
+hipError_t launch_rigid(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
+                        const SphereMeta *meta, const double *rbm, double alpha, double beta,
+                        double *y, hipStream_t s);
+// forces and torques per sphere, F scaled by sF and T by sT
 hipError_t launch_force_torque(int32_t P, const SphereMeta *meta, const double *src,
-                               const double *lam, double *ft, hipStream_t s);
+                               const double *lam, double *ft, hipStream_t s, double sF = 1.0,
+                               double sT = 1.0);
+// y = x with the F rows scaled by sF and the T rows by sT (P x 6)
+hipError_t launch_scale_ft(int32_t P, const double *x, double sF, double sT, double *y,
+                           hipStream_t s);
 // residual statistics: out[0] = max eps_res (masked), out[1] = max |u-ubc|, out[2] = max |ubc|
 hipError_t launch_residual_stats(int64_t n, const double *pts, const int32_t *sph,
                                  const SphereMeta *meta, const double *rbm, const double *u,

@@ -484,25 +484,45 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restr
 // ---------------------------------------------------------------------------
 // Right-hand side, forces/torques, residual statistics.
 
-__global__ void k_rhs(int64_t T, const double *__restrict__ tgt, const int32_t *__restrict__ tsph,
-                      const double *__restrict__ sw, const SphereMeta *__restrict__ meta,
-                      const double *__restrict__ rbm, double *__restrict__ b) {
+// y = alpha W (v + omega x (x - c)) + (beta != 0 ? beta y : 0) at the nodes.
+__global__ void k_rigid(int64_t T, const double *__restrict__ tgt, const int32_t *__restrict__ tsph,
+                        const double *__restrict__ sw, const SphereMeta *__restrict__ meta,
+                        const double *__restrict__ rbm, double alpha, double beta,
+                        double *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T) return;
   const int k = tsph[i];
   const double *c = meta[k].c;
   const double *v = rbm + 6 * (int64_t)k;
   const double rx = tgt[3 * i] - c[0], ry = tgt[3 * i + 1] - c[1], rz = tgt[3 * i + 2] - c[2];
-  const double s = sw[i];
-  b[3 * i] = s * (v[0] + v[4] * rz - v[5] * ry);
-  b[3 * i + 1] = s * (v[1] + v[5] * rx - v[3] * rz);
-  b[3 * i + 2] = s * (v[2] + v[3] * ry - v[4] * rx);
+  const double s = alpha * sw[i];
+  const double u0 = s * (v[0] + v[4] * rz - v[5] * ry);
+  const double u1 = s * (v[1] + v[5] * rx - v[3] * rz);
+  const double u2 = s * (v[2] + v[3] * ry - v[4] * rx);
+  if (beta != 0.0) {
+    y[3 * i] = fma(beta, y[3 * i], u0);
+    y[3 * i + 1] = fma(beta, y[3 * i + 1], u1);
+    y[3 * i + 2] = fma(beta, y[3 * i + 2], u2);
+  } else {
+    y[3 * i] = u0;
+    y[3 * i + 1] = u1;
+    y[3 * i + 2] = u2;
+  }
+}
+
+// y[6k + q] = x[6k + q] * (q < 3 ? sF : sT)
+__global__ void k_scale_ft(int32_t P, const double *__restrict__ x, double sF, double sT,
+                           double *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 6 * (int64_t)P) return;
+  y[i] = x[i] * ((i % 6) < 3 ? sF : sT);
 }
 
 __global__ __launch_bounds__(kBlock) void k_force_torque(const SphereMeta *__restrict__ meta,
                                                          const double *__restrict__ src,
                                                          const double *__restrict__ lam,
-                                                         double *__restrict__ ft) {
+                                                         double *__restrict__ ft, double sF,
+                                                         double sT) {
   __shared__ double sh[6][kWavesPerBlock];
   const int k = blockIdx.x;
   const SphereMeta &m = meta[k];
@@ -525,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_force_torque(const SphereMeta *__res
     v[5] += lam[3 * p + 2];
   }
   block_sum<6>(v, sh);
-  if (threadIdx.x < 6) ft[6 * k + threadIdx.x] = v[threadIdx.x];
+  if (threadIdx.x < 6) ft[6 * k + threadIdx.x] = v[threadIdx.x] * (threadIdx.x < 3 ? sF : sT);
 }
 
 __global__ __launch_bounds__(1024) void k_residual_stats(int64_t n, const double *__restrict__ pts,
@@ -834,17 +854,31 @@ hipError_t launch_pinv_v(const RowTask *tasks, int64_t n, const SphereMeta *meta
   return hipGetLastError();
 }
 
-hipError_t launch_rhs(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
-                      const SphereMeta *meta, const double *rbm, double *b, hipStream_t s) {
+hipError_t launch_rigid(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
+                        const SphereMeta *meta, const double *rbm, double alpha, double beta,
+                        double *y, hipStream_t s) {
   if (T == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rhs, dim3(blocks_for(T)), dim3(kBlock), 0, s, T, tgt, tsph, sw, meta, rbm, b);
+  hipLaunchKernelGGL(k_rigid, dim3(blocks_for(T)), dim3(kBlock), 0, s, T, tgt, tsph, sw, meta, rbm,
+                     alpha, beta, y);
   return hipGetLastError();
 }
 
+hipError_t launch_rhs(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
+                      const SphereMeta *meta, const double *rbm, double *b, hipStream_t s) {
+  return launch_rigid(T, tgt, tsph, sw, meta, rbm, 1.0, 0.0, b, s);
+}
+
 hipError_t launch_force_torque(int32_t P, const SphereMeta *meta, const double *src,
-                               const double *lam, double *ft, hipStream_t s) {
+                               const double *lam, double *ft, hipStream_t s, double sF, double sT) {
   if (P == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_force_torque, dim3(P), dim3(kBlock), 0, s, meta, src, lam, ft);
+  hipLaunchKernelGGL(k_force_torque, dim3(P), dim3(kBlock), 0, s, meta, src, lam, ft, sF, sT);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_ft(int32_t P, const double *x, double sF, double sT, double *y,
+                           hipStream_t s) {
+  if (P == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_ft, dim3(blocks_for(6 * (int64_t)P)), dim3(kBlock), 0, s, P, x, sF, sT, y);
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ EXPORTED = [
     "smfs_params_default", "smfs_problem_create", "smfs_problem_destroy", "smfs_problem_sizes",
     "smfs_export_nodes", "smfs_sphere_factor", "smfs_factor_info", "smfs_bind", "smfs_setup",
     "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_force_torque",
-    "smfs_eval_velocity", "smfs_solve_resistance", "smfs_set_solver", "smfs_pairs_per_apply",
+    "smfs_eval_velocity", "smfs_solve_resistance", "smfs_solve_mobility", "smfs_set_solver",
+    "smfs_pairs_per_apply",
     "smfs_profile",
     "smfs_profile_read", "smfs_last_error",
 ]
@@ -55,6 +56,7 @@ class smfs_sizes(C.Structure):
 class smfs_out(C.Structure):
     _fields_ = [
         ("mu", C.c_void_p), ("lambda_", C.c_void_p), ("ft", C.c_void_p), ("u_check", C.c_void_p),
+        ("rbm", C.c_void_p),
         ("iterations", C.c_int32), ("rel_residual", C.c_double),
         ("true_rel_residual", C.c_double), ("lambda_inf", C.c_double),
         ("eps_res_max", C.c_double), ("abs_res_max", C.c_double), ("t_rhs_ms", C.c_double),
@@ -103,6 +105,7 @@ def lib():
         "smfs_force_torque": ([vp, vp, vp, vp], C.c_int),
         "smfs_eval_velocity": ([vp, vp, i64, vp, vp, vp], C.c_int),
         "smfs_solve_resistance": ([vp, vp, P(smfs_out), vp], C.c_int),
+        "smfs_solve_mobility": ([vp, vp, P(smfs_out), vp], C.c_int),
         "smfs_pairs_per_apply": ([vp], i64),
         "smfs_set_solver": ([vp, i32, dbl, i32], C.c_int),
         "smfs_profile": ([vp, i32], C.c_int),
@@ -296,6 +299,29 @@ class Problem:
         _check(lib().smfs_eval_velocity(self.h, _ptr(lam), n, _ptr(x), _ptr(u), _stream()),
                "smfs_eval_velocity")
         return u
+
+    def _outputs(self, o):
+        return dict(converged=None, iterations=o.iterations, rel_residual=o.rel_residual,
+                    true_rel_residual=o.true_rel_residual, lambda_inf=o.lambda_inf,
+                    eps_res_max=o.eps_res_max, abs_res_max=o.abs_res_max,
+                    t_rhs_ms=o.t_rhs_ms, t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms,
+                    pair_evals=o.pair_evals, pair_evals_f32=o.pair_evals_f32,
+                    refinements=o.refinements)
+
+    def solve_mobility(self, ft, want_check=True):
+        """Forces/torques (P x 6, device) in; rigid motions out."""
+        self._need(ft, 6 * self.P, "ft")
+        mu, lam = self._dvec(3 * self.T), self._dvec(3 * self.S)
+        ft_out, rbm = self._dvec(6 * self.P), self._dvec(6 * self.P)
+        uc = self._dvec(3 * self.n_check) if (want_check and self.n_check) else None
+        o = smfs_out()
+        o.mu, o.lambda_, o.ft, o.rbm = mu.data_ptr(), lam.data_ptr(), ft_out.data_ptr(), rbm.data_ptr()
+        o.u_check = uc.data_ptr() if uc is not None else None
+        rc = lib().smfs_solve_mobility(self.h, _ptr(ft), C.byref(o), _stream())
+        _check(rc, "smfs_solve_mobility", ok=(SMFS_OK, SMFS_NOT_CONVERGED))
+        d = self._outputs(o)
+        d.update(mu=mu, lam=lam, ft=ft_out, rbm=rbm, u_check=uc, converged=rc == SMFS_OK)
+        return d
 
     def solve_resistance(self, rbm, want_check=True):
         self._need(rbm, 6 * self.P, "rbm")

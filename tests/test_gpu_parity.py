@@ -321,3 +321,50 @@ def test_mixed_solve_within_stated_tolerances(dev, mixed_small):
     assert out["pair_evals_f32"] > 0
     assert dF < 1e-5
     assert du < 1e-3
+
+
+# -- mobility --------------------------------------------------------------------
+
+def test_mobility_parity_and_round_trip(dev, oracle_pairsum_built):
+    _say("mobility: parity with the oracle and resistance round trip")
+    prm = geo.Params(n_proxy=60, n_colloc_base=80, n_image=4, n_check_base=50)
+    c = np.array([[0.0, 0, 0], [2.05, 0.3, 0.0], [0.4, 2.3, 0.1]])
+    g = geo.build(c, 1.0, prm)
+    pbo = mfs.Problem(g).setup()
+    lib = dev.Problem(c, 1.0, n_proxy=60, n_colloc_base=80, n_image=4, n_check_base=50,
+                      gmres_tol=1e-12).bind()
+    _import_oracle_factors(lib, pbo)
+    ft = wl.random_ft(3, 1, 41)[0]
+    ref = mfs.solve_mobility(pbo, ft, tol=1e-12)
+    out = lib.solve_mobility(_t(ft))
+    rbm = _n(out["rbm"]).reshape(-1, 6)
+    _say(f"  it {out['iterations']} (oracle {ref['iterations']}), V rel diff "
+         f"{np.abs(rbm - ref['rbm']).max() / np.abs(ref['rbm']).max():.2e}")
+    assert out["converged"]
+    assert np.abs(rbm - ref["rbm"]).max() < 1e-8 * np.abs(ref["rbm"]).max()
+    assert np.abs(_n(out["ft"]).reshape(-1, 6) - ft).max() < 1e-8 * np.abs(ft).max()
+    back = lib.solve_resistance(_t(rbm))
+    assert np.abs(_n(back["ft"]).reshape(-1, 6) - ft).max() < 1e-7 * np.abs(ft).max()
+
+
+def test_mobility_single_sphere_stokes(dev):
+    _say("mobility: single sphere (Stokes)")
+    lib = dev.Problem(np.array([[0.0, 1.0, 0.0]]), 1.0).bind().setup()
+    ft = np.array([[1.0, -2.0, 0.5, 0.3, 0.0, -0.7]])
+    out = lib.solve_mobility(_t(ft))
+    V = _n(out["rbm"])
+    assert np.abs(V[:3] - ft[0, :3] / (6 * math.pi)).max() < 1e-6 * 0.2
+    assert np.abs(V[3:] - ft[0, 3:] / (8 * math.pi)).max() < 1e-6 * 0.05
+
+
+def test_mobility_mixed_precision(dev, mixed_small):
+    _say("mobility: mixed precision vs FP64 oracle")
+    pbo, g = mixed_small["pb"], mixed_small["g"]
+    ft = wl.random_ft(g.P, 1, 42)[0]
+    ref = mfs.solve_mobility(pbo, ft, tol=1e-10)
+    out = mixed_small["libs"]["mixed"].solve_mobility(_t(ft))
+    rbm = _n(out["rbm"]).reshape(-1, 6)
+    d = np.abs(rbm - ref["rbm"]).max() / np.abs(ref["rbm"]).max()
+    _say(f"  it {out['iterations']} (+{out['refinements']}), V rel diff {d:.2e}")
+    assert out["pair_evals_f32"] > 0
+    assert d < 1e-5

@@ -304,3 +304,29 @@ def test_translation_and_permutation_invariance(pair001):
     pb = mfs.Problem(g).setup()
     out = mfs.solve_resistance(pb, rbm[0][::-1], tol=1e-10)
     assert np.abs(out["ft"][::-1] - ft0).max() < 1e-5 * np.abs(ft0).max()
+
+
+# -- mobility (augmented system; the paper points to it as separate work) -----
+
+def test_mobility_single_sphere_is_stokes(single_sphere):
+    """Force F and torque T on one sphere give v = F/(6 pi mu a) and
+    omega = T/(8 pi mu a^3)."""
+    g, pb = single_sphere
+    ft = np.array([[1.0, -2.0, 0.5, 0.3, 0.0, -0.7]])
+    out = mfs.solve_mobility(pb, ft, tol=1e-12)
+    assert np.abs(out["rbm"][0, :3] - ft[0, :3] / (6 * math.pi)).max() < 1e-6 * np.abs(ft[0, :3]).max()
+    assert np.abs(out["rbm"][0, 3:] - ft[0, 3:] / (8 * math.pi)).max() < 1e-6 * np.abs(ft[0, 3:]).max()
+
+
+def test_mobility_round_trip(oracle_pairsum_built):
+    """A resistance solve gives F/T from V; the mobility solve with those
+    F/T returns V (the same discrete operator, exact up to the tolerance)."""
+    prm = geo.Params(n_proxy=60, n_colloc_base=80, n_image=4)
+    c = np.array([[0.0, 0, 0], [2.05, 0.3, 0.0], [0.4, 2.3, 0.1]])
+    g = geo.build(c, 1.0, prm)
+    pb = mfs.Problem(g).setup()
+    rbm = np.random.default_rng(5).standard_normal((3, 6))
+    r = mfs.solve_resistance(pb, rbm, tol=1e-12)
+    m = mfs.solve_mobility(pb, r["ft"], tol=1e-12)
+    assert np.abs(m["rbm"] - rbm).max() < 1e-8 * np.abs(rbm).max()
+    assert np.abs(m["ft"] - r["ft"]).max() < 1e-8 * np.abs(r["ft"]).max()
