@@ -32,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X, FP64 vector
+PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X, FP64 dense matrix
 PEAK_HBM_GBS = 8000.0
 
 
@@ -117,7 +118,7 @@ def mixed_vs_fp64(args, torch, smfs, wl):
     return out
 
 
-def apply_only(pb, n, wl, torch):
+def apply_only(pb, n, wl, torch, block=0):
     for fid in range(pb.sizes.n_factors):
         info = pb.factor_info(fid)
         if info["sphere"] < 0:
@@ -137,10 +138,65 @@ def apply_only(pb, n, wl, torch):
     x.fill_(1.0)                  # calibration: writes exactly 1 GiB
     torch.mul(x, 2.0, out=z)      # calibration: reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
-    print(json.dumps({"apply_only": n, "direct_avg_ms": st["direct_ms"] / max(1, st["direct_launches"]),
-                      "pinv_avg_ms": st["pinv_ms"] / max(1, st["pinv_launches"]),
-                      "direct_flops": st["direct_flops"], "pinv_bytes": st["pinv_bytes"],
-                      "copy_bytes": 1 << 30}), flush=True)
+    del x, z
+    out = {"apply_only": n, "direct_avg_ms": st["direct_ms"] / max(1, st["direct_launches"]),
+           "pinv_avg_ms": st["pinv_ms"] / max(1, st["pinv_launches"]),
+           "direct_flops": st["direct_flops"], "pinv_bytes": st["pinv_bytes"],
+           "copy_bytes": 1 << 30}
+    if block:
+        out["block"] = block_vs_single(pb, torch, block, 2)
+    print(json.dumps(out), flush=True)
+
+
+def block_vs_single(pb, torch, nrhs: int, reps: int, seed: int = 7):
+    """Block product of nrhs vectors against nrhs single products on the
+    same problem and factors: per-kernel event timing of both forms."""
+    n = 3 * pb.T
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    M = torch.randn(nrhs, n, dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.empty_like(M)
+    pb.apply_block(M, out=Y)                       # warm-up (workspace, code load)
+    for q in range(nrhs):
+        pb.apply(M[q], out=Y[q])
+    torch.cuda.synchronize()
+    pb.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pb.apply_block(M, out=Y)
+    torch.cuda.synchronize()
+    t_block = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for q in range(nrhs):
+            pb.apply(M[q], out=Y[q])
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / reps
+    pb.profile(False)
+    st = pb.profile_read()
+    bd_s = st["bdirect_ms"] / max(1, st["bdirect_launches"]) * 1e-3
+    bp_s = st["bpinv_ms"] / max(1, st["bpinv_launches"]) * 1e-3
+    d_s = st["direct_ms"] / max(1, st["direct_launches"]) * 1e-3
+    p_s = st["pinv_ms"] / max(1, st["pinv_launches"]) * 1e-3
+    pair_rhs = pb.pairs_per_apply * nrhs
+    return {
+        "nrhs": nrhs,
+        "block_apply_ms": t_block * 1e3,
+        "single_applies_ms": t_single * 1e3,
+        "speedup_block_over_single": t_single / t_block,
+        "block_pair_rhs_evals_per_s": pair_rhs / t_block,
+        "single_pair_evals_per_s": pair_rhs / t_single,
+        "block_direct": {"kernel": "k_direct_block", "bound": "alu", "avg_launch_ms": bd_s * 1e3,
+                         "flops_per_launch": st["bdirect_flops"],
+                         "achieved": st["bdirect_flops"] / bd_s / 1e12 if bd_s > 0 else None,
+                         "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s"},
+        "block_pinv": {"kernel": "k_pinv_block_u + k_pinv_block_v (FP64 MFMA)", "bound": "mfma",
+                       "avg_launch_ms": bp_s * 1e3, "flops_per_launch": st["bpinv_flops"],
+                       "achieved": st["bpinv_flops"] / bp_s / 1e12 if bp_s > 0 else None,
+                       "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s"},
+        "single_direct_avg_ms": d_s * 1e3,
+        "single_pinv_avg_ms": p_s * 1e3,
+    }
 
 
 def main():
@@ -158,6 +214,8 @@ def main():
                     help="profiling aid: N products with G_hat on the same workload with "
                          "seeded full-rank factors instead of the SVD setup, then one plain "
                          "1 GiB device copy (the counter calibration kernel)")
+    ap.add_argument("--block", type=int, default=64, metavar="NRHS",
+                    help="right-hand sides of the block-product comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -175,7 +233,7 @@ def main():
     pb.bind()
     torch.cuda.synchronize()
     if args.apply_only:
-        apply_only(pb, args.apply_only, wl, torch)
+        apply_only(pb, args.apply_only, wl, torch, args.block)
         return
     t0 = time.perf_counter()
     pb.setup()
@@ -258,6 +316,9 @@ def main():
             "avg_launch_ms": pinv_avg_s * 1e3, "bytes_per_launch": st["pinv_bytes"],
         },
     }
+    if args.block:
+        log(f"block product of {args.block} vectors vs {args.block} single products ...")
+        result["block_vs_single"] = block_vs_single(pb, torch, args.block, 2)
     if not args.no_mixed:
         result["mixed_vs_fp64"] = mixed_vs_fp64(args, torch, smfs, wl)
     if not args.no_cpu_baseline:

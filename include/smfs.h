@@ -206,6 +206,52 @@ int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32
  * (the check-point residual is measured against the V found). */
 int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_stream stream);
 
+/* ---- Many right-hand sides ------------------------------------------
+ * The block forms run nrhs independent systems with one geometry: every
+ * source-target pair computed once serves a run of right-hand sides, and
+ * the per-sphere pseudo-inverse (eq. transform) becomes a pair of small
+ * GEMMs per sphere on the matrix cores.  A block workspace of device memory
+ * is allocated by the caller; its size depends on nrhs and the Krylov
+ * restart length.  Only the FP64 product exists in block form.
+ *
+ * Vectors of a block are stored one after another: vector q starts at
+ * q * ld (ld >= 3 T elements, the same for input and output blocks). */
+
+/* Bytes of block workspace for nrhs right-hand sides; restart = 0 sizes a
+ * workspace for smfs_apply_block only, restart > 0 for
+ * smfs_solve_resistance_block with that Krylov restart length. */
+int smfs_block_workspace_bytes(const smfs_problem *pb, int32_t nrhs, int32_t restart,
+                               size_t *bytes);
+
+/* y_q = G_hat mu_q for q < nrhs (eq. resistance with the identity self
+ * blocks of Section 2.4), FP64.  mu, y [dev]: nrhs vectors of stride
+ * ld >= 3 T; mu and y must not overlap.  ws [dev]: at least
+ * smfs_block_workspace_bytes(pb, nrhs, 0) bytes, 256-byte aligned. */
+int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y, int64_t ld,
+                     void *ws, size_t ws_bytes, smfs_stream stream);
+
+typedef struct smfs_block_out {
+  double *ft;                  /* [dev, out] nrhs x P x 6 forces/torques, or NULL */
+  double *mu;                  /* [dev, out] nrhs x 3T solutions (stride 3T), or NULL */
+  int32_t *iterations;         /* [host, out] nrhs GMRES iteration counts, or NULL */
+  double *true_rel_residual;   /* [host, out] nrhs values ||b - G_hat mu|| / ||b||, or NULL */
+  int32_t max_iterations;      /* out: block products in the Krylov iterations */
+  int32_t n_converged;         /* out: systems that met gmres_tol */
+  double t_gmres_ms, t_post_ms;
+  int64_t pair_evals;          /* out: pair x right-hand-side evaluations */
+} smfs_block_out;
+
+/* Resistance solves for nrhs rigid motions together: rbm [dev]
+ * nrhs x P x 6.  Every system runs its own GMRES(restart) with the
+ * problem's gmres_tol and gmres_max_it; the Krylov iterations of all
+ * systems advance in lock step through block products, a system that has
+ * converged stays frozen while the others go on.  ws as above with
+ * restart > 0.  Returns SMFS_NOT_CONVERGED when some system did not meet
+ * the tolerance. */
+int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rbm, int32_t restart,
+                                void *ws, size_t ws_bytes, smfs_block_out *out,
+                                smfs_stream stream);
+
 /* Pair evaluations in one product with G_hat (all off-sphere pairs). */
 int64_t smfs_pairs_per_apply(const smfs_problem *pb);
 
@@ -227,6 +273,13 @@ typedef struct smfs_kernel_stats {
   int64_t mixed64_launches; /* mixed precision: FP64 part of the direct sum */
   double mixed64_ms;
   double mixed64_flops;     /* FP64 direct-sum flops per mixed product */
+  int64_t bdirect_launches; /* block product: direct sum over nrhs vectors */
+  double bdirect_ms;
+  double bdirect_flops;     /* per launch: pairs x (geometry + nrhs x per-vector flops) */
+  int64_t bpinv_launches;   /* block product: MFMA pseudo-inverse GEMMs */
+  double bpinv_ms;
+  double bpinv_flops;       /* per launch: 2 nrhs (rank (rows + cols)) summed over spheres */
+  int32_t bnrhs;            /* right-hand sides of the last profiled block product */
 } smfs_kernel_stats;
 
 /* enable = 1 clears the counters and starts recording; 0 stops. */

@@ -24,7 +24,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-SOURCES = ["geometry.cpp", "kernels.hip", "api.hip"]
+SOURCES = ["geometry.cpp", "kernels.hip", "api.hip", "block.hip"]
 
 
 def _compile(src: str) -> str:

@@ -48,6 +48,8 @@ int64_t free_tiles(int64_t n) { return (n + kTileTargets - 1) / kTileTargets; }
 
 }  // namespace
 
+int32_t direct_splits(int64_t n_tiles, int64_t S) { return choose_splits(n_tiles, S); }
+
 void set_error(const std::string &msg) { g_err = msg; }
 
 void build_tiles(const Problem &pb, std::vector<int4> &tiles, int tt) {
@@ -86,6 +88,10 @@ size_t workspace_layout(Problem &pb, bool assign) {
   const size_t o_s = take(sizeof(double) * cols_total);
   const size_t o_ut = take(sizeof(RowTask) * cols_total);
   const size_t o_vt = take(sizeof(RowTask) * cols_total);
+  int64_t btasks = 0;
+  for (int k = 0; k < P; ++k) btasks += (pb.factors[pb.fid_of[k]].cols + 31) / 32;
+  const size_t o_bu = take(sizeof(int4) * std::max<int64_t>(1, btasks));
+  const size_t o_bv = take(sizeof(int4) * std::max<int64_t>(1, btasks));
   const int32_t sp_t = choose_splits((int64_t)tiles.size(), S);
   const int32_t sp_c = choose_splits(free_tiles(C), S);
   const int64_t part = std::max<int64_t>(3 * T * sp_t, 3 * C * sp_c);
@@ -150,6 +156,9 @@ size_t workspace_layout(Problem &pb, bool assign) {
     pb.d_s = (double *)(b + o_s);
     pb.d_utask = (RowTask *)(b + o_ut);
     pb.d_vtask = (RowTask *)(b + o_vt);
+    pb.d_btask_u = (int4 *)(b + o_bu);
+    pb.d_btask_v = (int4 *)(b + o_bv);
+    pb.cols_total = cols_total;
     pb.d_part = (double *)(b + o_part);
     pb.d_kry = (double *)(b + o_kry);
     pb.d_vec = (double *)(b + o_vec);
@@ -293,6 +302,16 @@ int rank_tables(Problem &pb, hipStream_t s) {
   }
   pb.n_utask = (int64_t)ut.size();
   pb.n_vtask = (int64_t)vt.size();
+  // 32-row tiles of the block (many right-hand sides) apply
+  std::vector<int4> bu, bv;
+  for (int k = 0; k < pb.P; ++k) {
+    const FactorSlot &f = pb.factors[pb.meta[k].fid];
+    if (f.rank <= 0) continue;
+    for (int j = 0; j < f.rank; j += 32) bu.push_back(int4{k, j, 0, 0});
+    for (int i = 0; i < f.cols; i += 32) bv.push_back(int4{k, i, 0, 0});
+  }
+  pb.n_btask_u = (int64_t)bu.size();
+  pb.n_btask_v = (int64_t)bv.size();
   // FP32 copy of the shared contact-free factor (mixed precision)
   pb.fac32_ready = false;
   const FactorSlot &f0 = pb.factors[0];
@@ -308,6 +327,10 @@ int rank_tables(Problem &pb, hipStream_t s) {
     SMFS_HIP(hipMemcpyAsync(pb.d_utask, ut.data(), sizeof(RowTask) * ut.size(), hipMemcpyHostToDevice, s));
   if (!vt.empty())
     SMFS_HIP(hipMemcpyAsync(pb.d_vtask, vt.data(), sizeof(RowTask) * vt.size(), hipMemcpyHostToDevice, s));
+  if (!bu.empty())
+    SMFS_HIP(hipMemcpyAsync(pb.d_btask_u, bu.data(), sizeof(int4) * bu.size(), hipMemcpyHostToDevice, s));
+  if (!bv.empty())
+    SMFS_HIP(hipMemcpyAsync(pb.d_btask_v, bv.data(), sizeof(int4) * bv.size(), hipMemcpyHostToDevice, s));
   SMFS_HIP(hipStreamSynchronize(s));
   bool ready = true;
   for (int k = 0; k < pb.P; ++k)
@@ -561,7 +584,6 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
 
 using namespace smfs;
 
-struct smfs_problem : Problem {};
 
 extern "C" {
 
@@ -809,11 +831,6 @@ int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double
   return rank_tables(*pb, s);
 }
 
-#define SMFS_READY(pb)                                                        \
-  do {                                                                        \
-    if (!(pb) || !(pb)->bound) { set_error("problem not bound"); return SMFS_E_STATE; } \
-    if (!(pb)->factors_ready) { set_error("factors not set up"); return SMFS_E_STATE; } \
-  } while (0)
 
 int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision, smfs_stream stream) {
   SMFS_READY(pb);
@@ -871,6 +888,9 @@ int smfs_profile(smfs_problem *pb, int32_t enable) {
     pb->ev_pinv.clear();
     pb->ev_mixed64.clear();
     pb->ev_far32.clear();
+    pb->ev_bdirect.clear();
+    pb->ev_bpinv.clear();
+    pb->prof_nrhs = 0;
   }
   pb->prof = enable != 0;
   return SMFS_OK;
@@ -879,38 +899,42 @@ int smfs_profile(smfs_problem *pb, int32_t enable) {
 int smfs_profile_read(smfs_problem *pb, smfs_kernel_stats *st) {
   if (!pb || !st) { set_error("null argument"); return SMFS_E_INVALID_ARG; }
   std::memset(st, 0, sizeof(*st));
-  for (auto &pr : pb->ev_direct) {
-    float ms = 0.f;
-    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
-    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
-    st->direct_ms += ms;
-  }
-  for (auto &pr : pb->ev_pinv) {
-    float ms = 0.f;
-    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
-    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
-    st->pinv_ms += ms;
-  }
-  for (auto &pr : pb->ev_mixed64) {
-    float ms = 0.f;
-    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
-    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
-    st->mixed64_ms += ms;
-  }
+  auto total = [pb](const std::vector<std::pair<size_t, size_t>> &ev, double &sum) -> int {
+    for (auto &pr : ev) {
+      float ms = 0.f;
+      SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
+      SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
+      sum += ms;
+    }
+    return (int)SMFS_OK;
+  };
+  int rc;
+  if ((rc = total(pb->ev_direct, st->direct_ms)) || (rc = total(pb->ev_pinv, st->pinv_ms)) ||
+      (rc = total(pb->ev_mixed64, st->mixed64_ms)) || (rc = total(pb->ev_far32, st->far32_ms)) ||
+      (rc = total(pb->ev_bdirect, st->bdirect_ms)) || (rc = total(pb->ev_bpinv, st->bpinv_ms)))
+    return rc;
   st->mixed64_launches = (int64_t)pb->ev_mixed64.size();
-  for (auto &pr : pb->ev_far32) {
-    float ms = 0.f;
-    SMFS_HIP(hipEventSynchronize(pb->ev_pool[pr.second]));
-    SMFS_HIP(hipEventElapsedTime(&ms, pb->ev_pool[pr.first], pb->ev_pool[pr.second]));
-    st->far32_ms += ms;
-  }
   st->direct_launches = (int64_t)pb->ev_direct.size();
   st->pinv_launches = (int64_t)pb->ev_pinv.size();
   st->far32_launches = (int64_t)pb->ev_far32.size();
+  st->bdirect_launches = (int64_t)pb->ev_bdirect.size();
+  st->bpinv_launches = (int64_t)pb->ev_bpinv.size();
+  st->bnrhs = pb->prof_nrhs;
   st->far32_flops = 28.0 * pb->pairs_f32;
   st->mixed64_flops = 28.0 * (pb->pairs_kind[0] - pb->pairs_f32) + 25.0 * pb->pairs_kind[1] +
                       30.0 * pb->pairs_kind[2];
   st->direct_flops = 28.0 * pb->pairs_kind[0] + 25.0 * pb->pairs_kind[1] + 30.0 * pb->pairs_kind[2];
+  // block direct sum: geometry once per pair (10, 10, 12 flops), then
+  // 18, 15, 18 flops per pair and right-hand side (sums to 28, 25, 30)
+  const double q = pb->prof_nrhs;
+  st->bdirect_flops = (10.0 + 18.0 * q) * pb->pairs_kind[0] + (10.0 + 15.0 * q) * pb->pairs_kind[1] +
+                      (12.0 + 18.0 * q) * pb->pairs_kind[2];
+  double gemm = 0.0;
+  for (int k = 0; k < pb->P; ++k) {
+    const FactorSlot &f = pb->factors[pb->fid_of[k]];
+    gemm += 2.0 * q * ((double)f.rows * f.rank + (double)f.cols * f.rank);
+  }
+  st->bpinv_flops = gemm;
   double bytes = 0.0;
   for (int k = 0; k < pb->P; ++k) {
     const FactorSlot &f = pb->factors[pb->fid_of[k]];

@@ -1,0 +1,381 @@
+// Many right-hand sides: block product with G_hat and lock-step GMRES.
+//
+// The preconditioned operator (Section 2.4, eq. resistance) is the same for
+// every right-hand side, so nrhs systems share one pass over the geometry:
+// the direct sum computes each pair's separation and 1/|r| once per run of
+// kBlockRun vectors, and the per-sphere pseudo-inverse (eq. transform)
+// becomes two small GEMMs per sphere on FP64 MFMA.  Each system keeps its
+// own Krylov basis, Hessenberg matrix and Givens rotations; the Arnoldi
+// steps of all systems run together in batched kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/smfs.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace smfs {
+namespace {
+
+constexpr double kPiB = 3.14159265358979323846;
+constexpr size_t kAlignB = 256;
+
+size_t up(size_t v) { return (v + kAlignB - 1) / kAlignB * kAlignB; }
+
+// Regions of a caller-provided block workspace.
+struct BlockLayout {
+  double *lamb = nullptr;   // S x nrhs x 3 strengths (source-major)
+  double *sblk = nullptr;   // nrhs x lds: Sigma^-1 U^T mu per sphere
+  double *part = nullptr;   // [split][nrhs][3T] partial sums
+  double *kry = nullptr;    // (m + 1) x nrhs x ld Krylov vectors
+  double *vec = nullptr;    // 4 x nrhs x ld: w, r, b, x
+  double *red = nullptr;    // reduction partials and small per-system arrays
+  int64_t lds = 0, ld = 0;
+  int32_t nsplit = 1, m = 0, nch = 1, ldh = 0;
+  size_t bytes = 0;
+};
+
+BlockLayout block_layout(const Problem &pb, int32_t nrhs, int32_t m, char *base) {
+  BlockLayout L;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = up(off + b);
+    return o;
+  };
+  const int64_t n = 3 * pb.T;
+  L.ld = (n + 31) / 32 * 32;
+  L.lds = (pb.cols_total + 31) / 32 * 32;
+  L.m = m;
+  const int64_t nz = (nrhs + kBlockRun - 1) / kBlockRun;
+  L.nsplit = direct_splits(pb.n_tiles * nz, pb.S);
+  L.nch = mdot_chunks(n);
+  L.ldh = m + 2;
+  // the last run of right-hand sides reads (and ignores) up to kBlockRun - 1
+  // strengths past the end of the block
+  const size_t o_lamb = take(sizeof(double) * (3 * pb.S * nrhs + 3 * kBlockRun));
+  const size_t o_s = take(sizeof(double) * L.lds * nrhs);
+  const size_t o_part = take(sizeof(double) * L.nsplit * nrhs * n);
+  size_t o_kry = 0, o_vec = 0, o_red = 0;
+  if (m > 0) {
+    o_kry = take(sizeof(double) * (size_t)(m + 1) * nrhs * L.ld);
+    o_vec = take(sizeof(double) * 4 * (size_t)nrhs * L.ld);
+    o_red = take(sizeof(double) * ((size_t)nrhs * (m + 1) * L.nch + 4 * (size_t)nrhs * L.ldh + 64));
+  }
+  L.bytes = off;
+  if (base) {
+    L.lamb = (double *)(base + o_lamb);
+    L.sblk = (double *)(base + o_s);
+    L.part = (double *)(base + o_part);
+    if (m > 0) {
+      L.kry = (double *)(base + o_kry);
+      L.vec = (double *)(base + o_vec);
+      L.red = (double *)(base + o_red);
+    }
+  }
+  return L;
+}
+
+int check_ws(const Problem &pb, int32_t nrhs, int32_t m, void *ws, size_t ws_bytes, BlockLayout &L) {
+  if (nrhs <= 0 || nrhs > 65535) { set_error("nrhs must be in [1, 65535]"); return SMFS_E_INVALID_ARG; }
+  if (!ws || ((uintptr_t)ws % kAlignB) != 0) {
+    set_error("block workspace must be a 256-byte aligned device pointer");
+    return SMFS_E_INVALID_ARG;
+  }
+  L = block_layout(pb, nrhs, m, (char *)ws);
+  if (ws_bytes < L.bytes) { set_error("block workspace too small"); return SMFS_E_NOMEM; }
+  return SMFS_OK;
+}
+
+// Y = G_hat M for the nrhs vectors of stride ld.
+int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *mu, double *y,
+                int64_t ld, hipStream_t s) {
+  size_t e0 = 0, e1 = 0, e2 = 0;
+  int rc;
+  if (pb.prof && (rc = record_event(pb, s, e0))) return rc;
+  SMFS_HIP(launch_pinv_block(pb.d_btask_u, pb.n_btask_u, pb.d_btask_v, pb.n_btask_v, pb.d_meta,
+                             pb.d_fslots, pb.d_fac, mu, ld, nrhs, L.sblk, L.lds, L.lamb,
+                             2.0 * pb.prm.mu, s));
+  if (pb.prof && (rc = record_event(pb, s, e1))) return rc;
+  BlockDirectArgs a;
+  a.tiles = pb.d_tiles;
+  a.n_tiles = pb.n_tiles;
+  a.tgt = pb.d_tgt;
+  a.T = pb.T;
+  a.src = pb.d_src;
+  a.lamb = L.lamb;
+  a.nrhs = nrhs;
+  a.meta = pb.d_meta;
+  a.ranges = pb.d_ranges;
+  a.n_ranges = pb.n_rng_plain;
+  a.range_total = pb.rng_total_plain;
+  a.n_splits = L.nsplit;
+  a.part = L.part;
+  SMFS_HIP(launch_direct_block(a, s));
+  if (pb.prof) {
+    if ((rc = record_event(pb, s, e2))) return rc;
+    pb.ev_bpinv.emplace_back(e0, e1);
+    pb.ev_bdirect.emplace_back(e1, e2);
+    pb.prof_nrhs = nrhs;
+  }
+  SMFS_HIP(launch_reduce_block(3 * pb.T, nrhs, L.nsplit, L.part, mu, ld, pb.d_sw,
+                               1.0 / (8.0 * kPiB * pb.prm.mu), y, ld, s));
+  return SMFS_OK;
+}
+
+struct BlockStats {
+  std::vector<int32_t> its;
+  std::vector<double> est;      // GMRES residual estimate per system
+  std::vector<char> conv;
+  int32_t steps = 0;            // block products in the Krylov iterations
+};
+
+// Pinned host buffer released on scope exit.
+struct Pinned {
+  double *p = nullptr;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// Lock-step GMRES(m) on G_hat x_q = b_q, x_q(0) = 0, for q < nrhs.  B and X
+// are blocks of stride L.ld.  Classical Gram-Schmidt applied twice, as in
+// the single-vector solver; a converged system is frozen (its restart
+// vector is zero, so its later Arnoldi columns are zero and ignored).
+int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B, double *X,
+                double tol, int max_it, BlockStats &st, hipStream_t s) {
+  const int64_t n = 3 * pb.T, ld = L.ld;
+  const int m = L.m, ldh = L.ldh, nch = L.nch;
+  const int64_t blk = (int64_t)nrhs * ld;   // one Krylov "column" of all systems
+  double *V = L.kry;
+  double *W = L.vec, *R = L.vec + blk;
+  double *part = L.red;
+  double *h = part + (int64_t)nrhs * (m + 1) * nch;
+  double *h2 = h + (int64_t)nrhs * ldh;
+  double *cf = h2 + (int64_t)nrhs * ldh;
+  double *beta = cf + (int64_t)nrhs * ldh;   // nrhs x ldh (first entry used)
+  Pinned hp;
+  const size_t hp_n = 3 * (size_t)nrhs * ldh;
+  SMFS_HIP(hipHostMalloc((void **)&hp.p, sizeof(double) * hp_n, hipHostMallocDefault));
+  double *hh = hp.p, *hh2 = hp.p + (size_t)nrhs * ldh, *hb = hp.p + 2 * (size_t)nrhs * ldh;
+
+  st.its.assign(nrhs, 0);
+  st.est.assign(nrhs, 0.0);
+  st.conv.assign(nrhs, 0);
+  st.steps = 0;
+  SMFS_HIP(launch_fill(blk, 0.0, X, s));
+  SMFS_HIP(launch_norm_scale_block(const_cast<double *>(B), ld, nrhs, n, part, nch, beta, ldh, false, s));
+  SMFS_HIP(hipMemcpyAsync(hb, beta, sizeof(double) * nrhs * ldh, hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  std::vector<double> bnorm(nrhs), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m), sn((size_t)nrhs * m);
+  std::vector<double> H((size_t)nrhs * (m + 1) * m), y(m), cfh((size_t)nrhs * ldh);
+  std::vector<int> jdone(nrhs, 0);
+  std::vector<char> active(nrhs, 0);
+  for (int q = 0; q < nrhs; ++q) {
+    bnorm[q] = hb[(size_t)q * ldh];
+    if (bnorm[q] == 0.0) st.conv[q] = 1;
+  }
+  SMFS_HIP(hipMemcpyAsync(R, B, sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
+  std::vector<double> rn(bnorm);   // residual norms at the start of a cycle
+  int total = 0;
+  while (true) {
+    // V_0 = R / beta for active systems, 0 for frozen ones
+    int n_act = 0;
+    for (int q = 0; q < nrhs; ++q) {
+      active[q] = !st.conv[q] && rn[q] > 0.0;
+      hb[(size_t)q * ldh] = active[q] ? rn[q] : 0.0;
+      n_act += active[q];
+      jdone[q] = 0;
+    }
+    if (n_act == 0) break;
+    SMFS_HIP(hipMemcpyAsync(V, R, sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
+    SMFS_HIP(hipMemcpyAsync(beta, hb, sizeof(double) * nrhs * ldh, hipMemcpyHostToDevice, s));
+    SMFS_HIP(launch_scale_block(V, ld, nrhs, n, beta, ldh, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    for (int q = 0; q < nrhs; ++q) g[(size_t)q * (m + 1)] = active[q] ? rn[q] : 0.0;
+    std::vector<char> running(active);
+    for (int j = 0; j < m; ++j) {
+      double *vj = V + (int64_t)j * blk, *vj1 = V + (int64_t)(j + 1) * blk;
+      int rc = apply_block(pb, L, nrhs, vj, vj1, ld, s);
+      if (rc) return rc;
+      ++st.steps;
+      SMFS_HIP(launch_arnoldi_block(V, ld, nrhs, j + 1, vj1, n, part, nch, h, ldh, s));
+      SMFS_HIP(launch_arnoldi_block(V, ld, nrhs, j + 1, vj1, n, part, nch, h2, ldh, s));
+      SMFS_HIP(launch_norm_scale_block(vj1, ld, nrhs, n, part, nch, h + (j + 1), ldh, true, s));
+      SMFS_HIP(hipMemcpyAsync(hh, h, sizeof(double) * nrhs * ldh, hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipMemcpyAsync(hh2, h2, sizeof(double) * nrhs * ldh, hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipStreamSynchronize(s));
+      ++total;
+      int n_run = 0;
+      for (int q = 0; q < nrhs; ++q) {
+        if (!running[q]) continue;
+        double *Hq = &H[(size_t)q * (m + 1) * m];
+        double *col = Hq + (size_t)j * (m + 1);
+        const double *a = hh + (size_t)q * ldh, *a2 = hh2 + (size_t)q * ldh;
+        for (int i = 0; i <= j + 1; ++i) col[i] = a[i] + (i <= j ? a2[i] : 0.0);
+        double *c = &cs[(size_t)q * m], *sv = &sn[(size_t)q * m], *gq = &g[(size_t)q * (m + 1)];
+        for (int i = 0; i < j; ++i) {
+          const double t = c[i] * col[i] + sv[i] * col[i + 1];
+          col[i + 1] = -sv[i] * col[i] + c[i] * col[i + 1];
+          col[i] = t;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        c[j] = den > 0 ? col[j] / den : 1.0;
+        sv[j] = den > 0 ? col[j + 1] / den : 0.0;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        gq[j + 1] = -sv[j] * gq[j];
+        gq[j] = c[j] * gq[j];
+        jdone[q] = j + 1;
+        st.its[q] += 1;
+        st.est[q] = std::fabs(gq[j + 1]) / bnorm[q];
+        if (st.est[q] <= tol) {
+          st.conv[q] = 1;
+          running[q] = 0;
+        } else if (a[j + 1] == 0.0 || total >= max_it) {
+          running[q] = 0;
+        }
+        n_run += running[q];
+      }
+      if (n_run == 0) break;
+    }
+    // y_q = H_q^-1 g_q, x_q += V_q y_q
+    std::fill(cfh.begin(), cfh.end(), 0.0);
+    int nv = 0;
+    for (int q = 0; q < nrhs; ++q) {
+      const int jd = jdone[q];
+      nv = std::max(nv, jd);
+      const double *Hq = &H[(size_t)q * (m + 1) * m];
+      const double *gq = &g[(size_t)q * (m + 1)];
+      for (int i = jd - 1; i >= 0; --i) {
+        double t = gq[i];
+        for (int c = i + 1; c < jd; ++c) t -= Hq[(size_t)c * (m + 1) + i] * y[c];
+        y[i] = t / Hq[(size_t)i * (m + 1) + i];
+      }
+      for (int i = 0; i < jd; ++i) cfh[(size_t)q * ldh + i] = y[i];
+    }
+    SMFS_HIP(hipMemcpyAsync(cf, cfh.data(), sizeof(double) * nrhs * ldh, hipMemcpyHostToDevice, s));
+    SMFS_HIP(launch_combine_block(V, ld, nrhs, nv, cf, ldh, X, ld, n, s));
+    SMFS_HIP(hipStreamSynchronize(s));
+    bool more = false;
+    for (int q = 0; q < nrhs; ++q) more = more || (!st.conv[q]);
+    if (!more || total >= max_it) break;
+    // restart from the true residuals
+    int rc = apply_block(pb, L, nrhs, X, W, ld, s);
+    if (rc) return rc;
+    ++st.steps;
+    SMFS_HIP(launch_sub(blk, B, W, R, s));
+    SMFS_HIP(launch_norm_scale_block(R, ld, nrhs, n, part, nch, beta, ldh, false, s));
+    SMFS_HIP(hipMemcpyAsync(hb, beta, sizeof(double) * nrhs * ldh, hipMemcpyDeviceToHost, s));
+    SMFS_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < nrhs; ++q) {
+      rn[q] = hb[(size_t)q * ldh];
+      if (!st.conv[q] && rn[q] / bnorm[q] <= tol) {
+        st.conv[q] = 1;
+        st.est[q] = rn[q] / bnorm[q];
+      }
+    }
+  }
+  return SMFS_OK;
+}
+
+}  // namespace
+}  // namespace smfs
+
+using namespace smfs;
+
+extern "C" {
+
+int smfs_block_workspace_bytes(const smfs_problem *pb, int32_t nrhs, int32_t restart, size_t *bytes) {
+  if (!pb || !bytes || nrhs <= 0 || nrhs > 65535 || restart < 0 || restart > 20000) {
+    set_error("smfs_block_workspace_bytes: bad argument");
+    return SMFS_E_INVALID_ARG;
+  }
+  if (!pb->bound) { set_error("problem not bound"); return SMFS_E_STATE; }
+  *bytes = block_layout(*pb, nrhs, restart, nullptr).bytes;
+  return SMFS_OK;
+}
+
+int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y, int64_t ld,
+                     void *ws, size_t ws_bytes, smfs_stream stream) {
+  SMFS_READY(pb);
+  if (!mu || !y || ld < 3 * pb->T) { set_error("smfs_apply_block: bad vectors"); return SMFS_E_INVALID_ARG; }
+  BlockLayout L;
+  int rc = check_ws(*pb, nrhs, 0, ws, ws_bytes, L);
+  if (rc) return rc;
+  const char *a0 = (const char *)mu, *a1 = a0 + 8 * (nrhs * ld);
+  const char *b0 = (const char *)y, *b1 = b0 + 8 * (nrhs * ld);
+  if (a0 < b1 && b0 < a1) { set_error("smfs_apply_block: mu and y overlap"); return SMFS_E_INVALID_ARG; }
+  return apply_block(*pb, L, nrhs, mu, y, ld, (hipStream_t)stream);
+}
+
+int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rbm, int32_t restart,
+                                void *ws, size_t ws_bytes, smfs_block_out *out, smfs_stream stream) {
+  SMFS_READY(pb);
+  if (!rbm || !out || restart <= 0 || restart > 20000) {
+    set_error("smfs_solve_resistance_block: bad argument");
+    return SMFS_E_INVALID_ARG;
+  }
+  BlockLayout L;
+  int rc = check_ws(*pb, nrhs, restart, ws, ws_bytes, L);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  using clk = std::chrono::steady_clock;
+  auto ms = [](clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  const int64_t n = 3 * pb->T, ld = L.ld, blk = (int64_t)nrhs * ld, P = pb->P;
+  double *W = L.vec, *R = L.vec + blk, *B = L.vec + 2 * blk, *X = L.vec + 3 * blk;
+  auto t0 = clk::now();
+  SMFS_HIP(launch_fill(blk, 0.0, B, s));
+  for (int q = 0; q < nrhs; ++q)
+    SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm + 6 * P * q,
+                        B + (int64_t)q * ld, s));
+  BlockStats st;
+  rc = gmres_block(*pb, L, nrhs, B, X, pb->prm.gmres_tol, pb->prm.gmres_max_it, st, s);
+  if (rc) return rc;
+  // true residuals in FP64
+  rc = apply_block(*pb, L, nrhs, X, W, ld, s);
+  if (rc) return rc;
+  SMFS_HIP(launch_sub(blk, B, W, R, s));
+  double *red = L.red + (int64_t)nrhs * (L.m + 1) * L.nch;
+  double *rn = red, *bn = red + nrhs;
+  SMFS_HIP(launch_norm_scale_block(R, ld, nrhs, n, L.red, L.nch, rn, 1, false, s));
+  SMFS_HIP(launch_norm_scale_block(B, ld, nrhs, n, L.red, L.nch, bn, 1, false, s));
+  std::vector<double> norms(2 * (size_t)nrhs);
+  SMFS_HIP(hipMemcpyAsync(norms.data(), red, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  auto t1 = clk::now();
+  // strengths, forces and torques per system (single-vector kernels)
+  for (int q = 0; q < nrhs; ++q) {
+    const double *xq = X + (int64_t)q * ld;
+    if (out->ft) {
+      rc = transform(*pb, xq, pb->d_lamhat, s);
+      if (rc) return rc;
+      SMFS_HIP(launch_force_torque(pb->P, pb->d_meta, pb->d_src, pb->d_lamhat, out->ft + 6 * P * q, s));
+    }
+    if (out->mu) SMFS_HIP(hipMemcpyAsync(out->mu + n * q, xq, 8 * n, hipMemcpyDeviceToDevice, s));
+  }
+  SMFS_HIP(hipStreamSynchronize(s));
+  auto t2 = clk::now();
+  int nconv = 0, maxit = 0;
+  for (int q = 0; q < nrhs; ++q) {
+    nconv += st.conv[q] ? 1 : 0;
+    maxit = std::max(maxit, st.its[q]);
+    if (out->iterations) out->iterations[q] = st.its[q];
+    if (out->true_rel_residual) out->true_rel_residual[q] = norms[nrhs + q] > 0 ? norms[q] / norms[nrhs + q] : 0.0;
+  }
+  out->max_iterations = maxit;
+  out->n_converged = nconv;
+  out->t_gmres_ms = ms(t0, t1);
+  out->t_post_ms = ms(t1, t2);
+  out->pair_evals = (int64_t)(st.steps + 1) * nrhs * pb->pairs_per_apply;
+  return nconv == nrhs ? SMFS_OK : SMFS_NOT_CONVERGED;
+}
+
+}  // extern "C"

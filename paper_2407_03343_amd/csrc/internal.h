@@ -122,6 +122,9 @@ struct Problem {
   FactorSlot *d_fslots = nullptr;
   RowTask *d_utask = nullptr, *d_vtask = nullptr;
   int32_t *d_vmap = nullptr;               // packed source index of local source j, per sphere
+  int4 *d_btask_u = nullptr, *d_btask_v = nullptr;  // block apply: (sphere, first row)
+  int64_t n_btask_u = 0, n_btask_v = 0;
+  int64_t cols_total = 0;                  // sum of factor columns over spheres
   double *d_kry = nullptr, *d_vec = nullptr, *d_red = nullptr;
   int64_t n_tiles = 0, n_utask = 0, n_vtask = 0, n_vmap = 0;
   int32_t n_splits = 1;
@@ -146,6 +149,8 @@ struct Problem {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<size_t, size_t>> ev_direct, ev_pinv, ev_mixed64, ev_far32;
+  std::vector<std::pair<size_t, size_t>> ev_bdirect, ev_bpinv;
+  int32_t prof_nrhs = 0;                   // right-hand sides of the profiled block products
 };
 
 // geometry.cpp
@@ -155,5 +160,17 @@ void build_tiles(const Problem &pb, std::vector<int4> &tiles, int tile_targets);
 size_t workspace_layout(Problem &pb, bool assign);
 int upload_tables(Problem &pb, hipStream_t s);
 int rank_tables(Problem &pb, hipStream_t s);
+// api.hip
+int transform(Problem &pb, const double *mu, double *lam, hipStream_t s);
+int record_event(Problem &pb, hipStream_t s, size_t &idx);
+int32_t direct_splits(int64_t n_tiles, int64_t S);
 
 }  // namespace smfs
+
+struct smfs_problem : smfs::Problem {};
+
+#define SMFS_READY(pb)                                                        \
+  do {                                                                        \
+    if (!(pb) || !(pb)->bound) { ::smfs::set_error("problem not bound"); return SMFS_E_STATE; } \
+    if (!(pb)->factors_ready) { ::smfs::set_error("factors not set up"); return SMFS_E_STATE; } \
+  } while (0)

@@ -126,4 +126,46 @@ hipError_t launch_norm2(const double *w, int64_t n, double *part, int32_t nchunk
 
 int32_t mdot_chunks(int64_t n);
 
+// ---- many right-hand sides ------------------------------------------------
+constexpr int kBlockRun = 4;   // right-hand sides sharing one pair geometry
+
+struct BlockDirectArgs {
+  const int4 *tiles;
+  int64_t n_tiles;
+  const double *tgt;
+  int64_t T;
+  const double *src;
+  const double *lamb;       // S x nrhs x 3 (source-major)
+  int32_t nrhs;
+  const SphereMeta *meta;
+  const SrcRange *ranges;
+  int32_t n_ranges;
+  int64_t range_total;
+  int32_t n_splits;
+  double *part;             // [split][q][T][3]
+};
+// Batched pseudo-inverse apply (eq. transform) for nrhs vectors on FP64
+// MFMA: S_q = Sigma^-1 U^T mu_q per sphere, then lamb = V S_q scattered to the
+// source-major block layout (dipoles times dscale).  Tasks are (sphere,
+// first row of a 32-row tile, -, -).
+hipError_t launch_pinv_block(const int4 *utasks, int64_t nu, const int4 *vtasks, int64_t nv,
+                             const SphereMeta *meta, const FactorSlot *fs, const double *fac,
+                             const double *mu, int64_t ldmu, int32_t nrhs, double *S, int64_t lds,
+                             double *lamb, double dscale, hipStream_t s);
+hipError_t launch_direct_block(const BlockDirectArgs &a, hipStream_t s);
+hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part,
+                               const double *base, int64_t ldb, const double *sw, double c0,
+                               double *y, int64_t ldy, hipStream_t s);
+hipError_t launch_arnoldi_block(const double *V, int64_t ld, int32_t nrhs, int32_t nv, double *W,
+                                int64_t n, double *part, int32_t nchunks, double *h, int32_t ldh,
+                                hipStream_t s);
+hipError_t launch_norm_scale_block(double *W, int64_t ld, int32_t nrhs, int64_t n, double *part,
+                                   int32_t nchunks, double *beta, int32_t ldb, bool scale,
+                                   hipStream_t s);
+hipError_t launch_scale_block(double *W, int64_t ld, int32_t nrhs, int64_t n, const double *beta,
+                              int32_t ldb, hipStream_t s);
+hipError_t launch_combine_block(const double *V, int64_t ld, int32_t nrhs, int32_t nv,
+                                const double *cf, int32_t ldc, double *X, int64_t ldx, int64_t n,
+                                hipStream_t s);
+
 }  // namespace smfs

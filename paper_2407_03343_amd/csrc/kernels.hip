@@ -965,3 +965,438 @@ hipError_t launch_sub(int64_t n, const double *x, const double *y, double *out, 
 }
 
 }  // namespace smfs
+
+// ===========================================================================
+// Many right-hand sides (block product).  Vectors of the block are stored
+// one after another (stride ld); strengths of the block are source-major,
+// lamb[(p * nrhs + q) * 3 + c], so one source's strengths for a run of
+// right-hand sides are contiguous.
+
+namespace smfs {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Tasks of the block pseudo-inverse apply are (sphere, first row of a
+// 32-row tile); blockIdx.y picks the 32-wide tile of right-hand sides.
+//
+// One 32 x 32 output tile per wave of C = A B (A row i contiguous over k,
+// B column j contiguous over k) on v_mfma_f64_16x16x4f64.  Lane l supplies
+// A[i0 + l%16][k] and B[k][j0 + l%16] for the k-slot l/16 of a step, and
+// after the sum holds C[i0 + 4v + l/16][j0 + l%16] in register v.  Each
+// lane loads four consecutive k per 16-wide k chunk and the four steps take
+// k = kc + 4 (l/16) + s, which covers the chunk.
+struct TileTN {
+  f64x4 acc[2][2];
+};
+
+__device__ __forceinline__ void mfma_tile_tn(const double *const arow[2], const bool aok[2],
+                                             const double *const bcol[2], const bool bok[2],
+                                             int64_t K, TileTN &t) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+#pragma unroll
+  for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) t.acc[ia][jb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kc = 0; kc < K; kc += 16) {
+    double a[2][4], b[2][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t k = kc + 4 * g + s;
+      const bool kin = k < K;
+#pragma unroll
+      for (int ia = 0; ia < 2; ++ia) a[ia][s] = (aok[ia] && kin) ? arow[ia][k] : 0.0;
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) b[jb][s] = (bok[jb] && kin) ? bcol[jb][k] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+          t.acc[ia][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ia][s], b[jb][s], t.acc[ia][jb], 0, 0, 0);
+  }
+}
+
+// S[q][s0 + r] = (U_k^T mu_q)_r / sigma_r for the rows r of the tile.
+__global__ __launch_bounds__(kBlock) void k_pinv_block_u(const int4 *__restrict__ tasks, int64_t n,
+                                                         const SphereMeta *__restrict__ meta,
+                                                         const FactorSlot *__restrict__ fs,
+                                                         const double *__restrict__ fac,
+                                                         const double *__restrict__ mu, int64_t ldmu,
+                                                         int32_t nrhs, double *__restrict__ S,
+                                                         int64_t lds) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (t >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int4 tk = tasks[t];
+  const int k = uniform(tk.x), r0 = uniform(tk.y), q0 = blockIdx.y * 32;
+  const SphereMeta &m = meta[k];
+  const FactorSlot &f = fs[m.fid];
+  const int rank = m.rank;
+  const int64_t K = f.rows;
+  const double *arow[2], *bcol[2];
+  bool aok[2], bok[2];
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
+    aok[h] = r < rank;
+    bok[h] = q < nrhs;
+    arow[h] = fac + f.u_off + (int64_t)(aok[h] ? r : 0) * f.rows;
+    bcol[h] = mu + (int64_t)(bok[h] ? q : 0) * ldmu + 3 * m.t0;
+  }
+  TileTN tile;
+  mfma_tile_tn(arow, aok, bcol, bok, K, tile);
+  const double *sig = fac + f.sig_off;
+  for (int ia = 0; ia < 2; ++ia)
+    for (int jb = 0; jb < 2; ++jb)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * ia + 4 * v + (lane >> 4), q = q0 + 16 * jb + (lane & 15);
+        if (r < rank && q < nrhs) S[(int64_t)q * lds + m.s0 + r] = tile.acc[ia][jb][v] / sig[r];
+      }
+}
+
+// lamb[packed(row)][q] = (V_k S_q)_row, dipoles multiplied by dscale.
+__global__ __launch_bounds__(kBlock) void k_pinv_block_v(const int4 *__restrict__ tasks, int64_t n,
+                                                         const SphereMeta *__restrict__ meta,
+                                                         const FactorSlot *__restrict__ fs,
+                                                         const double *__restrict__ fac,
+                                                         const double *__restrict__ S, int64_t lds,
+                                                         int32_t nrhs, double *__restrict__ lamb,
+                                                         double dscale) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (t >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int4 tk = tasks[t];
+  const int k = uniform(tk.x), r0 = uniform(tk.y), q0 = blockIdx.y * 32;
+  const SphereMeta &m = meta[k];
+  const FactorSlot &f = fs[m.fid];
+  const int64_t K = m.rank;
+  const int rows = f.cols;
+  const double *arow[2], *bcol[2];
+  bool aok[2], bok[2];
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
+    aok[h] = r < rows;
+    bok[h] = q < nrhs;
+    arow[h] = fac + f.vt_off + (int64_t)(aok[h] ? r : 0) * f.cols;
+    bcol[h] = S + (int64_t)(bok[h] ? q : 0) * lds + m.s0;
+  }
+  TileTN tile;
+  mfma_tile_tn(arow, aok, bcol, bok, K, tile);
+  const int nd0 = m.kn[0] + m.kn[1] + m.kn[2];
+  for (int ia = 0; ia < 2; ++ia)
+    for (int jb = 0; jb < 2; ++jb)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * ia + 4 * v + (lane >> 4), q = q0 + 16 * jb + (lane & 15);
+        if (r < rows && q < nrhs) {
+          const int jl = r / 3, c = r - 3 * (r / 3);
+          const double val = tile.acc[ia][jb][v];
+          lamb[(packed_index(m, jl) * nrhs + q) * 3 + c] = jl >= nd0 ? val * dscale : val;
+        }
+      }
+}
+
+// Block direct sum: as k_direct_f64 but every pair serves a run of kRun
+// right-hand sides (blockIdx.z picks the run); the geometry (r, 1/|r|) is
+// computed once per pair and run.
+template <int kTpl, int kRun>
+struct AccB {
+  double tx[kTpl], ty[kTpl], tz[kTpl];
+  double a[kTpl][kRun][3];
+};
+
+template <int kTpl, int kRun, int kKind>
+__device__ __forceinline__ void run_sources_block(const double *__restrict__ src,
+                                                  const double *__restrict__ lamb, int32_t nrhs,
+                                                  int q0, int64_t j0, int64_t j1,
+                                                  AccB<kTpl, kRun> &A) {
+  for (int64_t j = j0; j < j1; ++j) {
+    const double *ps = src + 3 * j;
+    const double *pf = lamb + (j * nrhs + q0) * 3;
+    const double sx = ps[0], sy = ps[1], sz = ps[2];
+    double f[kRun][3];
+#pragma unroll
+    for (int q = 0; q < kRun; ++q) {
+      f[q][0] = pf[3 * q];
+      f[q][1] = pf[3 * q + 1];
+      f[q][2] = pf[3 * q + 2];
+    }
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      const double rx = A.tx[p] - sx, ry = A.ty[p] - sy, rz = A.tz[p] - sz;
+      const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+      const double ri = rsqrt_f64(r2);
+      const double ri2 = ri * ri;
+      if (kKind == 0) {
+#pragma unroll
+        for (int q = 0; q < kRun; ++q) {
+          const double rf = fma(rx, f[q][0], fma(ry, f[q][1], rz * f[q][2]));
+          const double t = rf * ri2;
+          A.a[p][q][0] = fma(fma(rx, t, f[q][0]), ri, A.a[p][q][0]);
+          A.a[p][q][1] = fma(fma(ry, t, f[q][1]), ri, A.a[p][q][1]);
+          A.a[p][q][2] = fma(fma(rz, t, f[q][2]), ri, A.a[p][q][2]);
+        }
+      } else if (kKind == 1) {
+        const double c = ri2 * ri;
+#pragma unroll
+        for (int q = 0; q < kRun; ++q) {
+          A.a[p][q][0] = fma(c, fma(f[q][1], rz, -f[q][2] * ry), A.a[p][q][0]);
+          A.a[p][q][1] = fma(c, fma(f[q][2], rx, -f[q][0] * rz), A.a[p][q][1]);
+          A.a[p][q][2] = fma(c, fma(f[q][0], ry, -f[q][1] * rx), A.a[p][q][2]);
+        }
+      } else {
+        const double ri3 = ri2 * ri;
+        const double ri5x3 = 3.0 * ri3 * ri2;
+#pragma unroll
+        for (int q = 0; q < kRun; ++q) {
+          const double bb = fma(rx, f[q][0], fma(ry, f[q][1], rz * f[q][2])) * ri5x3;
+          A.a[p][q][0] = fma(-f[q][0], ri3, fma(rx, bb, A.a[p][q][0]));
+          A.a[p][q][1] = fma(-f[q][1], ri3, fma(ry, bb, A.a[p][q][1]));
+          A.a[p][q][2] = fma(-f[q][2], ri3, fma(rz, bb, A.a[p][q][2]));
+        }
+      }
+    }
+  }
+}
+
+template <int kTpl, int kRun>
+__device__ __forceinline__ void run_block_b(int block, const BlockDirectArgs &A, int q0, int64_t j0,
+                                            int64_t j1, AccB<kTpl, kRun> &acc) {
+  if (j0 >= j1) return;
+  if (block <= 1) run_sources_block<kTpl, kRun, 0>(A.src, A.lamb, A.nrhs, q0, j0, j1, acc);
+  else if (block == 2) run_sources_block<kTpl, kRun, 1>(A.src, A.lamb, A.nrhs, q0, j0, j1, acc);
+  else run_sources_block<kTpl, kRun, 2>(A.src, A.lamb, A.nrhs, q0, j0, j1, acc);
+}
+
+template <int kTpl, int kRun>
+__global__ __launch_bounds__(kBlock) void k_direct_block(BlockDirectArgs A) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (tile >= A.n_tiles) return;
+  const int4 tl = A.tiles[tile];
+  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  const int q0 = blockIdx.z * kRun;
+  AccB<kTpl, kRun> acc;
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
+    acc.tx[p] = A.tgt[3 * ti];
+    acc.ty[p] = A.tgt[3 * ti + 1];
+    acc.tz[p] = A.tgt[3 * ti + 2];
+#pragma unroll
+    for (int q = 0; q < kRun; ++q) acc.a[p][q][0] = acc.a[p][q][1] = acc.a[p][q][2] = 0.0;
+  }
+  const int64_t L = A.range_total;
+  const int64_t lo = L * blockIdx.y / A.n_splits, hi = L * (blockIdx.y + 1) / A.n_splits;
+  int64_t pos = 0;
+  for (int r = 0; r < A.n_ranges && pos < hi; ++r) {
+    const SrcRange R = A.ranges[r];
+    const int64_t len = R.end - R.begin;
+    const int64_t a = max<int64_t>(lo - pos, 0), b = min<int64_t>(hi - pos, len);
+    pos += len;
+    if (a >= b) continue;
+    const int64_t j0 = R.begin + a, j1 = R.begin + b;
+    const int64_t s0 = A.meta[k].k0[R.block], s1 = s0 + A.meta[k].kn[R.block];
+    run_block_b<kTpl, kRun>(R.block, A, q0, j0, min(j1, s0), acc);
+    run_block_b<kTpl, kRun>(R.block, A, q0, max(j0, s1), j1, acc);
+  }
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    if (i < tc) {
+#pragma unroll
+      for (int q = 0; q < kRun; ++q) {
+        if (q0 + q >= A.nrhs) break;
+        double *out = A.part + ((int64_t)blockIdx.y * A.nrhs + q0 + q) * A.T * 3;
+        const int64_t o = 3 * ((int64_t)t0 + i);
+        out[o] = acc.a[p][q][0];
+        out[o + 1] = acc.a[p][q][1];
+        out[o + 2] = acc.a[p][q][2];
+      }
+    }
+  }
+}
+
+// y_q = mu_q + W c0 sum_split part[split][q]
+__global__ void k_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *__restrict__ part,
+                               const double *__restrict__ base, int64_t ldb,
+                               const double *__restrict__ sw, double c0, double *__restrict__ y,
+                               int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= n3 || q >= nrhs) return;
+  double acc = 0.0;
+  for (int s = 0; s < ns; ++s) acc += part[((int64_t)s * nrhs + q) * n3 + i];
+  y[q * ldy + i] = base[q * ldb + i] + sw[i / 3] * c0 * acc;
+}
+
+// Batched GMRES helpers: blockIdx.z selects the right-hand side; vector j of
+// system q lives at V + (j * nrhs + q) * ld.
+__global__ __launch_bounds__(kBlock) void k_mdot_b(const double *__restrict__ V, int64_t ld,
+                                                   int32_t nrhs, int32_t nv,
+                                                   const double *__restrict__ W, int64_t ldw,
+                                                   int64_t n, int64_t chunk,
+                                                   double *__restrict__ part, int32_t nchunks) {
+  __shared__ double sh[kDotVecs][kWavesPerBlock];
+  const int c = blockIdx.x, q = blockIdx.z;
+  const int j0 = blockIdx.y * kDotVecs;
+  const double *w = W + q * ldw;
+  const int64_t b = (int64_t)c * chunk, e = min(n, b + chunk);
+  double acc[kDotVecs];
+#pragma unroll
+  for (int s = 0; s < kDotVecs; ++s) acc[s] = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
+    const double wi = w[i];
+#pragma unroll
+    for (int s = 0; s < kDotVecs; ++s)
+      if (j0 + s < nv) acc[s] = fma(V[((int64_t)(j0 + s) * nrhs + q) * ld + i], wi, acc[s]);
+  }
+  block_sum<kDotVecs>(acc, sh);
+  if (threadIdx.x < kDotVecs && j0 + (int)threadIdx.x < nv)
+    part[((int64_t)q * nv + j0 + threadIdx.x) * nchunks + c] = acc[threadIdx.x];
+}
+
+__global__ void k_mdot_final_b(int32_t nrhs, int32_t nv, const double *__restrict__ part,
+                               int32_t nchunks, double *__restrict__ h, int32_t ldh) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, q = blockIdx.y;
+  if (j >= nv) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += part[((int64_t)q * nv + j) * nchunks + c];
+  h[(int64_t)q * ldh + j] = s;
+}
+
+__global__ void k_mupdate_b(const double *__restrict__ V, int64_t ld, int32_t nrhs, int32_t nv,
+                            const double *__restrict__ h, int32_t ldh, double *__restrict__ W,
+                            int64_t ldw, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= n) return;
+  const double *hq = h + (int64_t)q * ldh;
+  double s = 0.0;
+  for (int j = 0; j < nv; ++j) s = fma(V[((int64_t)j * nrhs + q) * ld + i], hq[j], s);
+  W[q * ldw + i] -= s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sumsq_b(const double *__restrict__ W, int64_t ldw,
+                                                    int64_t n, int64_t chunk,
+                                                    double *__restrict__ part, int32_t nchunks) {
+  __shared__ double sh[1][kWavesPerBlock];
+  const int q = blockIdx.y;
+  const double *w = W + q * ldw;
+  const int64_t b = (int64_t)blockIdx.x * chunk, e = min(n, b + chunk);
+  double acc[1] = {0.0};
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) acc[0] = fma(w[i], w[i], acc[0]);
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t)q * nchunks + blockIdx.x] = acc[0];
+}
+
+// beta[q * ldb] = sqrt(sum of parts); then w_q /= beta_q (0 when beta = 0)
+__global__ void k_sqrt_final_b(int32_t nrhs, const double *__restrict__ part, int32_t nchunks,
+                               double *__restrict__ beta, int32_t ldb) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nrhs) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += part[(int64_t)q * nchunks + c];
+  beta[(int64_t)q * ldb] = sqrt(s);
+}
+
+__global__ void k_scale_b(double *__restrict__ W, int64_t ldw, int64_t n,
+                          const double *__restrict__ beta, int32_t ldb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= n) return;
+  const double b = beta[(int64_t)q * ldb];
+  W[q * ldw + i] = b > 0.0 ? W[q * ldw + i] / b : 0.0;
+}
+
+// x_q += sum_j V[j][q] c[q][j]
+__global__ void k_combine_b(const double *__restrict__ V, int64_t ld, int32_t nrhs, int32_t nv,
+                            const double *__restrict__ cf, int32_t ldc, double *__restrict__ X,
+                            int64_t ldx, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= n) return;
+  const double *c = cf + (int64_t)q * ldc;
+  double s = 0.0;
+  for (int j = 0; j < nv; ++j) s = fma(V[((int64_t)j * nrhs + q) * ld + i], c[j], s);
+  X[q * ldx + i] += s;
+}
+
+}  // namespace
+
+hipError_t launch_pinv_block(const int4 *utasks, int64_t nu, const int4 *vtasks, int64_t nv,
+                             const SphereMeta *meta, const FactorSlot *fs, const double *fac,
+                             const double *mu, int64_t ldmu, int32_t nrhs, double *S, int64_t lds,
+                             double *lamb, double dscale, hipStream_t s) {
+  const unsigned qt = (unsigned)((nrhs + 31) / 32);
+  if (nu > 0)
+    hipLaunchKernelGGL(k_pinv_block_u, dim3(blocks_for(nu, kWavesPerBlock), qt), dim3(kBlock), 0, s,
+                       utasks, nu, meta, fs, fac, mu, ldmu, nrhs, S, lds);
+  if (nv > 0)
+    hipLaunchKernelGGL(k_pinv_block_v, dim3(blocks_for(nv, kWavesPerBlock), qt), dim3(kBlock), 0, s,
+                       vtasks, nv, meta, fs, fac, S, lds, nrhs, lamb, dscale);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_block(const BlockDirectArgs &a, hipStream_t s) {
+  if (a.n_tiles == 0 || a.nrhs == 0) return hipSuccess;
+  dim3 grid((unsigned)((a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)a.n_splits,
+            (unsigned)((a.nrhs + kBlockRun - 1) / kBlockRun));
+  hipLaunchKernelGGL((k_direct_block<kDirectTpl, kBlockRun>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part,
+                               const double *base, int64_t ldb, const double *sw, double c0,
+                               double *y, int64_t ldy, hipStream_t s) {
+  if (n3 == 0 || nrhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_block, dim3(blocks_for(n3), nrhs), dim3(kBlock), 0, s, n3, nrhs, ns,
+                     part, base, ldb, sw, c0, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_block(const double *V, int64_t ld, int32_t nrhs, int32_t nv, double *W,
+                                int64_t n, double *part, int32_t nchunks, double *h, int32_t ldh,
+                                hipStream_t s) {
+  // h_q = V_q^T w_q ; w_q -= V_q h_q
+  const int64_t chunk = chunk_len(n, nchunks);
+  dim3 g1((unsigned)nchunks, (unsigned)((nv + kDotVecs - 1) / kDotVecs), (unsigned)nrhs);
+  hipLaunchKernelGGL(k_mdot_b, g1, dim3(kBlock), 0, s, V, ld, nrhs, nv, W, ld, n, chunk, part, nchunks);
+  hipLaunchKernelGGL(k_mdot_final_b, dim3(blocks_for(nv), nrhs), dim3(kBlock), 0, s, nrhs, nv, part,
+                     nchunks, h, ldh);
+  hipLaunchKernelGGL(k_mupdate_b, dim3(blocks_for(n), nrhs), dim3(kBlock), 0, s, V, ld, nrhs, nv, h,
+                     ldh, W, ld, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_scale_block(double *W, int64_t ld, int32_t nrhs, int64_t n, double *part,
+                                   int32_t nchunks, double *beta, int32_t ldb, bool scale,
+                                   hipStream_t s) {
+  const int64_t chunk = chunk_len(n, nchunks);
+  hipLaunchKernelGGL(k_sumsq_b, dim3(nchunks, nrhs), dim3(kBlock), 0, s, W, ld, n, chunk, part, nchunks);
+  hipLaunchKernelGGL(k_sqrt_final_b, dim3(blocks_for(nrhs)), dim3(kBlock), 0, s, nrhs, part, nchunks,
+                     beta, ldb);
+  if (scale)
+    hipLaunchKernelGGL(k_scale_b, dim3(blocks_for(n), nrhs), dim3(kBlock), 0, s, W, ld, n, beta, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_block(double *W, int64_t ld, int32_t nrhs, int64_t n, const double *beta,
+                              int32_t ldb, hipStream_t s) {
+  if (n == 0 || nrhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_b, dim3(blocks_for(n), nrhs), dim3(kBlock), 0, s, W, ld, n, beta, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_block(const double *V, int64_t ld, int32_t nrhs, int32_t nv,
+                                const double *cf, int32_t ldc, double *X, int64_t ldx, int64_t n,
+                                hipStream_t s) {
+  if (nv <= 0 || n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine_b, dim3(blocks_for(n), nrhs), dim3(kBlock), 0, s, V, ld, nrhs, nv, cf,
+                     ldc, X, ldx, n);
+  return hipGetLastError();
+}
+
+}  // namespace smfs

@@ -26,7 +26,8 @@ EXPORTED = [
     "smfs_export_nodes", "smfs_sphere_factor", "smfs_factor_info", "smfs_bind", "smfs_setup",
     "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_force_torque",
     "smfs_eval_velocity", "smfs_solve_resistance", "smfs_solve_mobility", "smfs_set_solver",
-    "smfs_pairs_per_apply",
+    "smfs_pairs_per_apply", "smfs_block_workspace_bytes", "smfs_apply_block",
+    "smfs_solve_resistance_block",
     "smfs_profile",
     "smfs_profile_read", "smfs_last_error",
 ]
@@ -71,6 +72,18 @@ class smfs_kernel_stats(C.Structure):
         ("pinv_launches", C.c_int64), ("pinv_ms", C.c_double), ("pinv_bytes", C.c_double),
         ("far32_launches", C.c_int64), ("far32_ms", C.c_double), ("far32_flops", C.c_double),
         ("mixed64_launches", C.c_int64), ("mixed64_ms", C.c_double), ("mixed64_flops", C.c_double),
+        ("bdirect_launches", C.c_int64), ("bdirect_ms", C.c_double), ("bdirect_flops", C.c_double),
+        ("bpinv_launches", C.c_int64), ("bpinv_ms", C.c_double), ("bpinv_flops", C.c_double),
+        ("bnrhs", C.c_int32),
+    ]
+
+
+class smfs_block_out(C.Structure):
+    _fields_ = [
+        ("ft", C.c_void_p), ("mu", C.c_void_p), ("iterations", C.c_void_p),
+        ("true_rel_residual", C.c_void_p), ("max_iterations", C.c_int32),
+        ("n_converged", C.c_int32), ("t_gmres_ms", C.c_double), ("t_post_ms", C.c_double),
+        ("pair_evals", C.c_int64),
     ]
 
 
@@ -107,6 +120,10 @@ def lib():
         "smfs_solve_resistance": ([vp, vp, P(smfs_out), vp], C.c_int),
         "smfs_solve_mobility": ([vp, vp, P(smfs_out), vp], C.c_int),
         "smfs_pairs_per_apply": ([vp], i64),
+        "smfs_block_workspace_bytes": ([vp, i32, i32, P(C.c_size_t)], C.c_int),
+        "smfs_apply_block": ([vp, i32, vp, vp, i64, vp, C.c_size_t, vp], C.c_int),
+        "smfs_solve_resistance_block": ([vp, i32, vp, i32, vp, C.c_size_t, P(smfs_block_out), vp],
+                                        C.c_int),
         "smfs_set_solver": ([vp, i32, dbl, i32], C.c_int),
         "smfs_profile": ([vp, i32], C.c_int),
         "smfs_profile_read": ([vp, P(smfs_kernel_stats)], C.c_int),
@@ -341,3 +358,59 @@ class Problem:
                     t_rhs_ms=o.t_rhs_ms, t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms,
                     pair_evals=o.pair_evals, pair_evals_f32=o.pair_evals_f32,
                     refinements=o.refinements)
+
+    # -- many right-hand sides ---------------------------------------------
+    def block_workspace_bytes(self, nrhs, restart=0):
+        n = C.c_size_t(0)
+        _check(lib().smfs_block_workspace_bytes(self.h, nrhs, restart, C.byref(n)),
+               "smfs_block_workspace_bytes")
+        return int(n.value)
+
+    def block_workspace(self, nrhs, restart=0):
+        """A device buffer for the block calls (kept on the object and reused
+        while large enough)."""
+        import torch
+        need = self.block_workspace_bytes(nrhs, restart)
+        old = getattr(self, "_bws", None)
+        if old is None or old.numel() - 256 < need:
+            self._bws = None
+            self._bws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        base = self._bws.data_ptr()
+        return (base + 255) // 256 * 256, self._bws.numel() - ((base + 255) // 256 * 256 - base)
+
+    def apply_block(self, mu, out=None):
+        """mu: (nrhs, 3T) contiguous float64 device tensor; returns G_hat mu_q per row."""
+        import torch
+        if mu.dim() != 2 or mu.shape[1] != 3 * self.T:
+            raise ValueError("mu: expected shape (nrhs, 3T)")
+        nrhs = mu.shape[0]
+        self._need(mu, nrhs * 3 * self.T, "mu")
+        y = out if out is not None else torch.empty_like(mu)
+        self._need(y, nrhs * 3 * self.T, "y")
+        ws, nb = self.block_workspace(nrhs, 0)
+        _check(lib().smfs_apply_block(self.h, nrhs, _ptr(mu), _ptr(y), 3 * self.T, C.c_void_p(ws),
+                                      nb, _stream()), "smfs_apply_block")
+        return y
+
+    def solve_resistance_block(self, rbm, restart=100):
+        """rbm: nrhs x P x 6 values (device, contiguous); returns ft (nrhs, P, 6), mu (nrhs, 3T),
+        per-system iterations and true relative residuals."""
+        import torch
+        nrhs = rbm.numel() // (6 * self.P)
+        if nrhs < 1:
+            raise ValueError("rbm: expected (nrhs, P, 6) values")
+        self._need(rbm, nrhs * 6 * self.P, "rbm")
+        ft = torch.empty(nrhs, self.P, 6, dtype=torch.float64, device="cuda")
+        mu = torch.empty(nrhs, 3 * self.T, dtype=torch.float64, device="cuda")
+        its = np.zeros(nrhs, np.int32)
+        tr = np.zeros(nrhs, np.float64)
+        ws, nb = self.block_workspace(nrhs, restart)
+        o = smfs_block_out()
+        o.ft, o.mu = ft.data_ptr(), mu.data_ptr()
+        o.iterations, o.true_rel_residual = its.ctypes.data, tr.ctypes.data
+        rc = lib().smfs_solve_resistance_block(self.h, nrhs, _ptr(rbm), restart, C.c_void_p(ws), nb,
+                                               C.byref(o), _stream())
+        _check(rc, "smfs_solve_resistance_block", ok=(SMFS_OK, SMFS_NOT_CONVERGED))
+        return dict(ft=ft, mu=mu, iterations=its, true_rel_residual=tr, converged=rc == SMFS_OK,
+                    max_iterations=o.max_iterations, n_converged=o.n_converged,
+                    t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms, pair_evals=o.pair_evals)

@@ -31,3 +31,15 @@ def pair001(oracle_pairsum_built):
     pb = mfs.Problem(g).setup()
     out = mfs.solve_resistance(pb, rbm[0], tol=1e-10)
     return dict(pk=pk, rbm=rbm, g=g, pb=pb, out=out)
+
+
+@pytest.fixture(scope="session")
+def dev():
+    """The HIP library's Python binding; a GPU test without a device fails
+    (it does not skip), and a missing libsmfs.so raises."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a HIP device")
+    from paper_2407_03343_amd import smfs
+    smfs.lib()
+    return smfs

@@ -1,0 +1,48 @@
+"""Helpers shared by the GPU test modules (host-side marshalling and the
+oracle's extended-precision rounding reference)."""
+import sys
+
+import numpy as np
+import torch
+
+TAG = "gpu"
+
+
+def _say(msg):
+    print(f"[{TAG}] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64).reshape(-1)).cuda()
+
+
+def _n(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _import_oracle_factors(lib, pbo):
+    for fid in range(lib.sizes.n_factors):
+        info = lib.factor_info(fid)
+        if info["sphere"] < 0:
+            continue
+        of = pbo.factors[int(pbo.factor_of[info["sphere"]])]
+        assert of.U.shape[0] == info["rows"] and of.V.shape[0] == info["cols"]
+        lib.import_factor(fid, of.U, of.s, of.V)
+
+
+def _transform_ext(pbo, vec):
+    """Oracle transform in extended precision (rounding reference)."""
+    g = pbo.g
+    lam = np.zeros((g.S, 3))
+    for k in range(g.P):
+        f = pbo.factors[int(pbo.factor_of[k])]
+        mk = vec[pbo.tslice(k)].astype(np.longdouble)
+        t = (f.U.astype(np.longdouble).T @ mk) / f.s.astype(np.longdouble)
+        lam[g.local_sources[k]] = (f.V.astype(np.longdouble) @ t).astype(np.float64).reshape(-1, 3)
+    return lam

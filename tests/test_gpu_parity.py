@@ -24,53 +24,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _say(msg):
-    print(f"[gpu-parity] {msg}", flush=True)
-    sys.stdout.flush()
-
-
-def _t(a):
-    return torch.from_numpy(np.ascontiguousarray(a, np.float64).reshape(-1)).cuda()
-
-
-def _n(t):
-    torch.cuda.synchronize()
-    return t.detach().cpu().numpy()
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
-
-
-def _import_oracle_factors(lib, pbo):
-    for fid in range(lib.sizes.n_factors):
-        info = lib.factor_info(fid)
-        if info["sphere"] < 0:
-            continue
-        of = pbo.factors[int(pbo.factor_of[info["sphere"]])]
-        assert of.U.shape[0] == info["rows"] and of.V.shape[0] == info["cols"]
-        lib.import_factor(fid, of.U, of.s, of.V)
-
-
-def _transform_ext(pbo, vec):
-    """Oracle transform in extended precision (rounding reference)."""
-    g = pbo.g
-    lam = np.zeros((g.S, 3))
-    for k in range(g.P):
-        f = pbo.factors[int(pbo.factor_of[k])]
-        mk = vec[pbo.tslice(k)].astype(np.longdouble)
-        t = (f.U.astype(np.longdouble).T @ mk) / f.s.astype(np.longdouble)
-        lam[g.local_sources[k]] = (f.V.astype(np.longdouble) @ t).astype(np.float64).reshape(-1, 3)
-    return lam
-
-
-@pytest.fixture(scope="module")
-def dev():
-    if not torch.cuda.is_available():
-        pytest.fail("GPU test run without a HIP device")
-    from paper_2407_03343_amd import smfs
-    smfs.lib()
-    return smfs
+from gpu_common import _say, _t, _n, _rel, _import_oracle_factors, _transform_ext  # noqa: E402
 
 
 @pytest.fixture(scope="module")
