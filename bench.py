@@ -199,6 +199,92 @@ def block_vs_single(pb, torch, nrhs: int, reps: int, seed: int = 7):
     }
 
 
+def _gen_request(args):
+    from paper_2407_03343_amd import workloads as wl
+    i, seed, kw = args
+    return wl.serving_stream(n=1, seed=seed * 100003 + i, **kw)[0]
+
+
+def serving_requests(args):
+    """The request stream (generated in worker processes before the GPU is
+    touched): packings and rigid motions, and Poisson arrival offsets."""
+    import multiprocessing as mp
+    n = args.serve_requests
+    rng = np.random.default_rng(args.seed + 77)
+    arrivals = np.concatenate([[0.0], np.cumsum(rng.exponential(1.0 / args.serve_rate, n - 1))])
+    log(f"serving: generating {n} requests ...")
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 4)) as pool:
+        reqs = pool.map(_gen_request, [(i, args.seed, dict(rate=args.serve_rate)) for i in range(n)])
+    return reqs, arrivals
+
+
+def serving(args, torch, smfs, reqs, arrivals):
+    """Poisson stream of independent resistance solves through the
+    continuous-batching server; p50/p99 latency from arrival to result and
+    solves/s, beside the same requests solved one after another with the
+    single-problem path (a sample of them, timed end to end)."""
+    n = len(reqs)
+    disc = dict(n_proxy=args.serve_proxy, n_colloc_base=args.serve_colloc, n_image=args.serve_image,
+                n_check_base=0)
+    solver = dict(gmres_tol=args.serve_tol, gmres_restart=100, gmres_max_it=3000)
+    srv = smfs.Server(arena_bytes=args.serve_arena << 30, max_active=args.serve_slots,
+                      setup_workers=args.serve_workers, **disc, **solver)
+    t0 = srv.clock() + 0.02
+    ids, i, last_log = [], 0, time.perf_counter()
+    while True:
+        now = srv.clock()
+        while i < n and t0 + arrivals[i] <= now:
+            ids.append(srv.submit(reqs[i]["centers"], reqs[i]["rbm"], t0 + arrivals[i]))
+            i += 1
+        a, w = srv.step()
+        st = srv.stats()
+        if st["completed"] + st["failed"] == n:
+            break
+        if a == 0:
+            time.sleep(0.0002)
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            log(f"  serving: submitted {i}, done {st['completed']}, resident {a}, waiting {w}")
+    res = [srv.poll(rid, r["P"]) for rid, r in zip(ids, reqs)]
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["t_done"] - r["t_arrival"] for r in res]) * 1e3
+    span = max(r["t_done"] for r in res) - t0
+    pairs = sum(r["pair_evals"] for r in res)
+    its = np.array([r["iterations"] for r in res])
+    out = {
+        "requests": n, "rate_per_s": args.serve_rate, "setup_workers": args.serve_workers,
+        "discretisation": disc, "tol": args.serve_tol, "slots": args.serve_slots,
+        "latency_ms_p50": float(np.percentile(lat, 50)),
+        "latency_ms_p99": float(np.percentile(lat, 99)),
+        "solves_per_s": n / span,
+        "pair_evals_per_s": pairs / span,
+        "makespan_s": span,
+        "iterations_p50": float(np.percentile(its, 50)),
+        "failed": int(st["failed"]),
+        "not_converged": int(sum(1 for r in res if r["status"] == 1)),
+        "max_true_rel_residual": float(max(r["true_rel_residual"] for r in res)),
+        "peak_active": st["peak_active"], "steps": st["steps"],
+        "mean_resident_per_step": st["request_iterations"] / max(1, st["steps"]),
+        "setup_ms_total": st["setup_ms"], "step_ms_total": st["step_ms"], "tick_ms_total": st["tick_ms"],
+        "setup_batches": st["setup_batches"],
+        "arena_peak_gib": st["arena_peak"] / 2**30,
+    }
+    # the same requests one after another through the single-problem path
+    k = min(n, args.serve_sequential)
+    t1 = time.perf_counter()
+    for r in reqs[:k]:
+        pb = smfs.Problem(r["centers"], 1.0, **disc, **solver).bind().setup()
+        o = pb.solve_resistance(torch.from_numpy(r["rbm"].reshape(-1)).cuda(), want_check=False)
+        torch.cuda.synchronize()
+        del pb
+    seq_s = time.perf_counter() - t1
+    out["sequential_sample"] = k
+    out["sequential_solves_per_s"] = k / seq_s
+    out["speedup_served_over_sequential"] = out["solves_per_s"] / out["sequential_solves_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +302,19 @@ def main():
                          "1 GiB device copy (the counter calibration kernel)")
     ap.add_argument("--block", type=int, default=64, metavar="NRHS",
                     help="right-hand sides of the block-product comparison (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving stream (the full stream is 512)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-arena", type=int, default=64, metavar="GIB")
+    ap.add_argument("--serve-proxy", type=int, default=120)
+    ap.add_argument("--serve-colloc", type=int, default=160)
+    ap.add_argument("--serve-image", type=int, default=6)
+    ap.add_argument("--serve-tol", type=float, default=1e-6)
+    ap.add_argument("--serve-workers", type=int, default=1, help="set-up worker threads")
+    ap.add_argument("--serve-sequential", type=int, default=4,
+                    help="requests solved one after another for the comparison")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -225,6 +324,12 @@ def main():
     import torch
     from paper_2407_03343_amd import smfs, workloads as wl
 
+    reqs = arrivals = None
+    if args.serve_requests > 0:
+        reqs, arrivals = serving_requests(args)
+    if args.serve_only:
+        print(json.dumps({"serving": serving(args, torch, smfs, reqs, arrivals)}), flush=True)
+        return
     pk, _ = wl.workload_cluster100(args.seed)
     log(f"workload: {pk.P} spheres, box {pk.box:.2f}, min gap {pk.min_gaps().min():.2e}")
     pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=2000, gmres_max_it=2000)
@@ -321,6 +426,10 @@ def main():
         result["block_vs_single"] = block_vs_single(pb, torch, args.block, 2)
     if not args.no_mixed:
         result["mixed_vs_fp64"] = mixed_vs_fp64(args, torch, smfs, wl)
+    if args.serve_requests > 0:
+        del pb
+        torch.cuda.empty_cache()
+        result["serving"] = serving(args, torch, smfs, reqs, arrivals)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(pk, args.cpu_stride)

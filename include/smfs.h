@@ -252,6 +252,90 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
                                 void *ws, size_t ws_bytes, smfs_block_out *out,
                                 smfs_stream stream);
 
+/* ---- Serving --------------------------------------------------------
+ * A server holds many independent resistance problems (different sphere
+ * counts and packings, one discretisation) resident on one GPU and
+ * advances them together.  Requests are admitted in arrival order when
+ * their workspace fits into the server's device arena and a slot is free;
+ * set-up worker threads build and factorise admitted requests in batches
+ * on their own streams while the resident requests keep iterating.  Every call of
+ * smfs_server_step performs one GMRES iteration of every resident request:
+ * one launch of each kernel of the product with G_hat and of the Arnoldi
+ * step covers all of them, and a request that arrives between steps joins
+ * at the next one (continuous batching).  A finished request leaves at once
+ * and its memory and slot go to the next waiting request.  The arithmetic
+ * per request is the FP64 product and GMRES of smfs_solve_resistance, so a
+ * result does not depend on which other requests share the launches.
+ *
+ * The shared factor of contact-free spheres (Section 2.4) depends only on
+ * the discretisation: the server factorises it once and copies it into each
+ * request.  Serving is FP64; params->precision must be SMFS_FP64. */
+typedef struct smfs_server smfs_server;
+
+/* p: discretisation and solver settings of every request (gmres_restart is
+ * the Krylov restart length, which sets each request's footprint).
+ * radius: the common sphere radius.  arena_bytes: device memory for the
+ * requests' workspaces (allocated once here).  max_active: slots (requests
+ * resident together, including those being set up), 1..4096.
+ * setup_workers: threads building admitted requests (1..64), each with its
+ * own stream, rocBLAS handle and 4 GiB of SVD scratch.  A worker takes every
+ * request that can be admitted at that moment (up to 64) and factorises the
+ * self blocks of all their contact spheres together: batched SVDs per block
+ * shape, each call of a fixed batch count for its shape. */
+int smfs_server_create(const smfs_params *p, double radius, size_t arena_bytes, int32_t max_active,
+                       int32_t setup_workers, smfs_server **out);
+/* Waits for the worker thread and frees every resource. */
+void smfs_server_destroy(smfs_server *srv);
+
+/* Seconds on the clock the server stamps requests with (monotonic). */
+double smfs_server_clock(void);
+
+/* Queue a request: P spheres with centres [host] P x 3 (all of radius
+ * `radius`), rigid motions rbm [host] P x 6.  t_arrival: its arrival time on
+ * smfs_server_clock (latency is measured from it); a negative value means
+ * now.  Geometry is built here, on the calling thread; *id receives the
+ * request's handle.  SMFS_E_NOMEM when the request alone does not fit into
+ * the arena. */
+int smfs_server_submit(smfs_server *srv, int32_t P, const double *centers, const double *rbm,
+                       double t_arrival, int64_t *id);
+
+/* One iteration of every resident request (see above); then finished
+ * requests are completed (true residual, forces and torques) and leave.
+ * *n_active: requests resident after the step; *n_waiting: requests
+ * queued or being set up.  Returns at once when nothing is resident. */
+int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting);
+
+typedef struct smfs_request_result {
+  int32_t status;              /* SMFS_OK, SMFS_NOT_CONVERGED or an error code */
+  int32_t P;
+  int32_t iterations;
+  int32_t restarts;
+  double rel_residual;         /* GMRES estimate */
+  double true_rel_residual;    /* ||b - G_hat mu|| / ||b|| in FP64 */
+  double t_arrival, t_admitted, t_started, t_done;   /* smfs_server_clock seconds */
+  int64_t pair_evals;
+} smfs_request_result;
+
+/* Result of request id: returns 0 and fills *res (and ft [host] P x 6
+ * forces/torques, when not NULL) once the request has finished, 1 while it
+ * is waiting or running, SMFS_E_INVALID_ARG for an unknown id.  A finished
+ * request's result stays available until smfs_server_release(id). */
+int smfs_server_poll(smfs_server *srv, int64_t id, smfs_request_result *res, double *ft);
+int smfs_server_release(smfs_server *srv, int64_t id);
+
+typedef struct smfs_server_stats {
+  int64_t steps;               /* calls of smfs_server_step that iterated */
+  int64_t request_iterations;  /* sum over steps of resident requests */
+  int64_t completed, failed;
+  size_t arena_bytes, arena_peak;
+  int32_t peak_active;
+  double step_ms;              /* wall time inside smfs_server_step */
+  double tick_ms;              /* of which the batched iteration (launches and readback) */
+  double setup_ms;             /* worker time building and factorising requests */
+  int64_t setup_batches;       /* admission batches set up */
+} smfs_server_stats;
+int smfs_server_stats_read(smfs_server *srv, smfs_server_stats *st);
+
 /* Pair evaluations in one product with G_hat (all off-sphere pairs). */
 int64_t smfs_pairs_per_apply(const smfs_problem *pb);
 

@@ -747,7 +747,7 @@ int smfs_setup(smfs_problem *pb, smfs_stream stream) {
   // groups of equal shape, consecutive in the workspace (see workspace_layout)
   std::vector<int> order;
   for (size_t f = 0; f < pb->factors.size(); ++f)
-    if (pb->factors[f].rep >= 0) order.push_back((int)f);
+    if (pb->factors[f].rep >= 0 && !(pb->skip_shared && f == 0)) order.push_back((int)f);
   std::sort(order.begin(), order.end(),
             [&](int x, int y) { return pb->factors[x].u_off < pb->factors[y].u_off; });
   size_t g0 = 0;
@@ -757,20 +757,32 @@ int smfs_setup(smfs_problem *pb, smfs_stream stream) {
     size_t g1 = g0 + 1;
     while (g1 < order.size() && pb->factors[order[g1]].rows == m && pb->factors[order[g1]].cols == n) ++g1;
     const int64_t stride = g1 - g0 > 1 ? pb->factors[order[g0 + 1]].u_off - first.u_off : 0;
-    // batches bounded by the scratch copy of the input blocks (<= 8 GiB, <= 32)
+    // batches bounded by the scratch copy of the input blocks (<= 8 GiB, <= 32);
+    // a caller-provided scratch buffer, when set, bounds them instead and
+    // no device memory is allocated here
     const size_t per = sizeof(double) * (size_t)m * n;
-    const size_t bmax = std::max<size_t>(1, std::min<size_t>(32, ((size_t)8 << 30) / per));
+    const size_t per_all = align_up(per) + align_up(sizeof(double) * (size_t)n) + align_up(sizeof(rocblas_int));
+    const bool own = pb->svd_scratch && pb->svd_scratch_bytes >= per_all;
+    const size_t cap = own ? pb->svd_scratch_bytes / per_all : ((size_t)8 << 30) / per;
+    const size_t bmax = std::max<size_t>(1, std::min<size_t>(32, cap));
     for (size_t b0 = g0; b0 < g1; b0 += bmax) {
       const int nb = (int)std::min(bmax, g1 - b0);
       double *A = nullptr, *E = nullptr;
       rocblas_int *info = nullptr;
-      SMFS_HIP(hipMalloc((void **)&A, per * nb));
-      SMFS_HIP(hipMalloc((void **)&E, sizeof(double) * (size_t)n * nb));
-      SMFS_HIP(hipMalloc((void **)&info, sizeof(rocblas_int) * nb));
+      if (own) {
+        char *base = (char *)pb->svd_scratch;
+        A = (double *)base;
+        E = (double *)(base + align_up(per * nb));
+        info = (rocblas_int *)(base + align_up(per * nb) + align_up(sizeof(double) * (size_t)n * nb));
+      } else {
+        SMFS_HIP(hipMalloc((void **)&A, per * nb));
+        SMFS_HIP(hipMalloc((void **)&E, sizeof(double) * (size_t)n * nb));
+        SMFS_HIP(hipMalloc((void **)&info, sizeof(rocblas_int) * nb));
+      }
       struct Free {
         void *a, *b, *c;
-        ~Free() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c); }
-      } guard{A, E, info};
+        ~Free() { if (a) (void)hipFree(a); if (b) (void)hipFree(b); if (c) (void)hipFree(c); }
+      } guard{own ? nullptr : A, own ? nullptr : E, own ? nullptr : info};
       for (int q = 0; q < nb; ++q) {
         const FactorSlot &fs = pb->factors[order[b0 + q]];
         const SphereMeta &mk = pb->meta[fs.rep];

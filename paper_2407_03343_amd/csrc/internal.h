@@ -125,6 +125,9 @@ struct Problem {
   int4 *d_btask_u = nullptr, *d_btask_v = nullptr;  // block apply: (sphere, first row)
   int64_t n_btask_u = 0, n_btask_v = 0;
   int64_t cols_total = 0;                  // sum of factor columns over spheres
+  bool skip_shared = false;                // setup leaves factor 0 (imported) alone
+  void *svd_scratch = nullptr;             // optional device scratch of the setup SVDs
+  size_t svd_scratch_bytes = 0;
   double *d_kry = nullptr, *d_vec = nullptr, *d_red = nullptr;
   int64_t n_tiles = 0, n_utask = 0, n_vtask = 0, n_vmap = 0;
   int32_t n_splits = 1;

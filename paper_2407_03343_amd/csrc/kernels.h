@@ -168,4 +168,33 @@ hipError_t launch_combine_block(const double *V, int64_t ld, int32_t nrhs, int32
                                 const double *cf, int32_t ldc, double *X, int64_t ldx, int64_t n,
                                 hipStream_t s);
 
+// ---- serving: many independent problems per launch ---------------------
+// One entry per resident problem; the product reads x and writes y, the
+// Arnoldi pass then orthogonalises y = V + nv ld against V[0..nv).
+struct ServeDesc {
+  DirectArgs da;            // direct sum of this problem (str = lam, own part buffer)
+  int64_t tile0;            // first tile of this problem in the launch
+  const RowTask *utask, *vtask;
+  int64_t n_utask, n_vtask, utask0, vtask0;
+  const FactorSlot *fs;
+  const double *fac;
+  double *sbuf;             // Sigma^-1 U^T x per sphere
+  double *lam;              // strengths (dipoles times 2 mu), same array as da.str
+  const double *x;          // input, 3T
+  double *y;                // output G_hat x, 3T
+  const double *sw;         // square-root weights, T
+  double c0;                // 1 / (8 pi mu)
+  int64_t n;                // 3T
+  const double *V;          // Krylov basis, stride ld
+  int64_t ld;
+  int32_t nv;               // vectors to orthogonalise against
+  int32_t nch;              // reduction chunks (mdot_chunks(n))
+  double *red;              // reduction partials, at least nv x nch
+  double *h, *h2;           // out: Gram-Schmidt coefficients; h[nv] = norm
+};
+hipError_t launch_serve_product(const ServeDesc *d, int32_t nprob, int64_t tiles, int64_t utasks,
+                                int64_t vtasks, int32_t max_splits, int64_t max_n, hipStream_t s);
+hipError_t launch_serve_arnoldi(const ServeDesc *d, int32_t nprob, int32_t max_nv, int32_t max_nch,
+                                int64_t max_n, hipStream_t s);
+
 }  // namespace smfs

@@ -178,10 +178,10 @@ __device__ __forceinline__ void run_block(int block, const DirectArgs &A, int64_
   else run_sources<kTpl, 2, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc);
 }
 
+// One wave: tile `tile` of A, source split `split`.
 template <int kTpl, bool kFree>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIRECT_WAVES, 8))) void k_direct_f64(DirectArgs A) {
+__device__ __forceinline__ void direct_wave(const DirectArgs &A, int64_t tile, int64_t split) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
   int k = -1, t0 = 0, tc = 0;
   if (tile < A.n_tiles) {
     if (!kFree) {
@@ -211,8 +211,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIR
   }
 
   const int64_t L = A.range_total;
-  const int64_t lo = L * blockIdx.y / A.n_splits;
-  const int64_t hi = L * (blockIdx.y + 1) / A.n_splits;
+  const int64_t lo = L * split / A.n_splits;
+  const int64_t hi = L * (split + 1) / A.n_splits;
   int64_t pos = 0;
   for (int r = 0; r < A.n_ranges && pos < hi; ++r) {
     const SrcRange R = A.ranges[r];
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIR
     }
   }
 
-  double *out = A.part + (int64_t)blockIdx.y * A.T * 3;
+  double *out = A.part + split * A.T * 3;
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
     const int i = lane + kWave * p;
@@ -241,6 +241,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIR
       out[o + 2] = acc.az[p];
     }
   }
+}
+
+template <int kTpl, bool kFree>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIRECT_WAVES, 8))) void k_direct_f64(DirectArgs A) {
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  direct_wave<kTpl, kFree>(A, tile, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,14 +356,12 @@ __device__ __forceinline__ int block_kind(const SphereMeta &m, int jl) {
 // Pseudo-inverse apply: one wave per output row, a dot product of a
 // contiguous factor row with a short vector.
 
-__global__ __launch_bounds__(kBlock) void k_pinv_u(const RowTask *__restrict__ tasks, int64_t n,
-                                                   const SphereMeta *__restrict__ meta,
-                                                   const FactorSlot *__restrict__ fs,
-                                                   const double *__restrict__ fac,
-                                                   const double *__restrict__ mu,
-                                                   double *__restrict__ sbuf) {
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (t >= n) return;
+// One wave per row j of U^T: sbuf[s0 + j] = (U_k^T mu)_j / sigma_j.
+__device__ __forceinline__ void pinv_u_row(const RowTask *__restrict__ tasks, int64_t t,
+                                           const SphereMeta *__restrict__ meta,
+                                           const FactorSlot *__restrict__ fs,
+                                           const double *__restrict__ fac,
+                                           const double *__restrict__ mu, double *__restrict__ sbuf) {
   const int lane = threadIdx.x & (kWave - 1);
   const int k = uniform(tasks[t].sphere), j = uniform(tasks[t].row);
   const SphereMeta &m = meta[k];
@@ -378,14 +382,13 @@ __global__ __launch_bounds__(kBlock) void k_pinv_u(const RowTask *__restrict__ t
   if (lane == 0) sbuf[m.s0 + j] = s / fac[f.sig_off + j];
 }
 
-__global__ __launch_bounds__(kBlock) void k_pinv_v(const RowTask *__restrict__ tasks, int64_t n,
-                                                   const SphereMeta *__restrict__ meta,
-                                                   const FactorSlot *__restrict__ fs,
-                                                   const double *__restrict__ fac,
-                                                   const double *__restrict__ sbuf,
-                                                   double *__restrict__ lam, double dscale) {
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (t >= n) return;
+// One wave per row r of V: lam[packed(r)] = (V_k s)_r, dipoles times dscale.
+__device__ __forceinline__ void pinv_v_row(const RowTask *__restrict__ tasks, int64_t t,
+                                           const SphereMeta *__restrict__ meta,
+                                           const FactorSlot *__restrict__ fs,
+                                           const double *__restrict__ fac,
+                                           const double *__restrict__ sbuf,
+                                           double *__restrict__ lam, double dscale) {
   const int lane = threadIdx.x & (kWave - 1);
   const int k = uniform(tasks[t].sphere), r = uniform(tasks[t].row);
   const SphereMeta &m = meta[k];
@@ -408,6 +411,28 @@ __global__ __launch_bounds__(kBlock) void k_pinv_v(const RowTask *__restrict__ t
     const bool dip = jl >= m.kn[0] + m.kn[1] + m.kn[2];
     lam[3 * packed_index(m, jl) + c] = dip ? s * dscale : s;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pinv_u(const RowTask *__restrict__ tasks, int64_t n,
+                                                   const SphereMeta *__restrict__ meta,
+                                                   const FactorSlot *__restrict__ fs,
+                                                   const double *__restrict__ fac,
+                                                   const double *__restrict__ mu,
+                                                   double *__restrict__ sbuf) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (t >= n) return;
+  pinv_u_row(tasks, t, meta, fs, fac, mu, sbuf);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pinv_v(const RowTask *__restrict__ tasks, int64_t n,
+                                                   const SphereMeta *__restrict__ meta,
+                                                   const FactorSlot *__restrict__ fs,
+                                                   const double *__restrict__ fac,
+                                                   const double *__restrict__ sbuf,
+                                                   double *__restrict__ lam, double dscale) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (t >= n) return;
+  pinv_v_row(tasks, t, meta, fs, fac, sbuf, lam, dscale);
 }
 
 // FP32 pseudo-inverse apply for contact-free spheres (mixed precision):
@@ -773,7 +798,7 @@ __global__ void k_sub(int64_t n, const double *__restrict__ x, const double *__r
 
 inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
-int64_t chunk_len(int64_t n, int32_t nchunks) { return (n + nchunks - 1) / nchunks; }
+__host__ __device__ inline int64_t chunk_len(int64_t n, int32_t nchunks) { return (n + nchunks - 1) / nchunks; }
 
 }  // namespace
 
@@ -1396,6 +1421,185 @@ hipError_t launch_combine_block(const double *V, int64_t ld, int32_t nrhs, int32
   if (nv <= 0 || n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine_b, dim3(blocks_for(n), nrhs), dim3(kBlock), 0, s, V, ld, nrhs, nv, cf,
                      ldc, X, ldx, n);
+  return hipGetLastError();
+}
+
+}  // namespace smfs
+
+// ===========================================================================
+// Serving: one launch covers the products (and the Arnoldi steps) of many
+// independent problems, each described by a ServeDesc.  Flat work indices
+// (tiles, pseudo-inverse rows) are mapped to their problem by a binary
+// search over the per-problem prefixes; per-problem element loops use the
+// problem index as a grid dimension.
+
+namespace smfs {
+namespace {
+
+// Largest r with key(r) <= t (prefixes are non-decreasing, key(0) = 0).
+template <typename Key>
+__device__ __forceinline__ int find_problem(int32_t nprob, int64_t t, Key key) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (key(mid) <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return uniform(lo);
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve_pinv_u(const ServeDesc *__restrict__ D,
+                                                         int32_t nprob, int64_t total) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (t >= total) return;
+  const int r = find_problem(nprob, t, [D](int i) { return D[i].utask0; });
+  const ServeDesc &d = D[r];
+  const int64_t tl = t - d.utask0;
+  if (tl >= d.n_utask) return;
+  pinv_u_row(d.utask, tl, d.da.meta, d.fs, d.fac, d.x, d.sbuf);
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve_pinv_v(const ServeDesc *__restrict__ D,
+                                                         int32_t nprob, int64_t total) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (t >= total) return;
+  const int r = find_problem(nprob, t, [D](int i) { return D[i].vtask0; });
+  const ServeDesc &d = D[r];
+  const int64_t tl = t - d.vtask0;
+  if (tl >= d.n_vtask) return;
+  pinv_v_row(d.vtask, tl, d.da.meta, d.fs, d.fac, d.sbuf, d.lam, d.da.dscale);
+}
+
+template <int kTpl>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIRECT_WAVES, 8))) void k_serve_direct(const ServeDesc *__restrict__ D, int32_t nprob,
+                                                                  int64_t total) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (t >= total) return;
+  const int r = find_problem(nprob, t, [D](int i) { return D[i].tile0; });
+  const ServeDesc &d = D[r];
+  if ((int)blockIdx.y >= d.da.n_splits) return;
+  direct_wave<kTpl, false>(d.da, t - d.tile0, blockIdx.y);
+}
+
+// y = x + W c0 sum_s part[s] (the same arithmetic as k_reduce_epilogue)
+__global__ void k_serve_reduce(const ServeDesc *__restrict__ D) {
+  const ServeDesc &d = D[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int32_t ns = d.da.n_splits;
+  double acc = 0.0;
+  for (int s = 0; s < ns; ++s) acc += d.da.part[(int64_t)s * d.n + i];
+  double v = d.c0 * acc;
+  v *= d.sw[i / 3];
+  v += d.x[i];
+  d.y[i] = v;
+}
+
+// Classical Gram-Schmidt pass against V[0..nv) of every problem (pass 0
+// writes h, pass 1 writes h2), with the chunking and summation order of
+// the single-problem kernels.
+__global__ __launch_bounds__(kBlock) void k_serve_mdot(const ServeDesc *__restrict__ D) {
+  __shared__ double sh[kDotVecs][kWavesPerBlock];
+  const ServeDesc &d = D[blockIdx.z];
+  const int c = blockIdx.x;
+  const int j0 = blockIdx.y * kDotVecs;
+  if (c >= d.nch || j0 >= d.nv) return;   // uniform over the block
+  const int64_t chunk = chunk_len(d.n, d.nch);
+  const int64_t b = (int64_t)c * chunk, e = min(d.n, b + chunk);
+  const double *w = d.y;
+  double acc[kDotVecs];
+#pragma unroll
+  for (int q = 0; q < kDotVecs; ++q) acc[q] = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
+    const double wi = w[i];
+#pragma unroll
+    for (int q = 0; q < kDotVecs; ++q)
+      if (j0 + q < d.nv) acc[q] = fma(d.V[(int64_t)(j0 + q) * d.ld + i], wi, acc[q]);
+  }
+  block_sum<kDotVecs>(acc, sh);
+  if (threadIdx.x < kDotVecs && j0 + (int)threadIdx.x < d.nv)
+    d.red[(int64_t)(j0 + threadIdx.x) * d.nch + c] = acc[threadIdx.x];
+}
+
+__global__ void k_serve_mdot_final(const ServeDesc *__restrict__ D, int pass) {
+  const ServeDesc &d = D[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.nv) return;
+  double s = 0.0;
+  for (int c = 0; c < d.nch; ++c) s += d.red[(int64_t)j * d.nch + c];
+  (pass ? d.h2 : d.h)[j] = s;
+}
+
+__global__ void k_serve_mupdate(const ServeDesc *__restrict__ D, int pass) {
+  const ServeDesc &d = D[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const double *h = pass ? d.h2 : d.h;
+  double s = 0.0;
+  for (int j = 0; j < d.nv; ++j) s = fma(d.V[(int64_t)j * d.ld + i], h[j], s);
+  d.y[i] -= s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve_sumsq(const ServeDesc *__restrict__ D) {
+  __shared__ double sh[1][kWavesPerBlock];
+  const ServeDesc &d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.nch) return;
+  const int64_t chunk = chunk_len(d.n, d.nch);
+  const int64_t b = (int64_t)blockIdx.x * chunk, e = min(d.n, b + chunk);
+  double acc[1] = {0.0};
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) acc[0] = fma(d.y[i], d.y[i], acc[0]);
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) d.red[blockIdx.x] = acc[0];
+}
+
+__global__ void k_serve_norm(const ServeDesc *__restrict__ D, int32_t nprob) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nprob) return;
+  const ServeDesc &d = D[r];
+  double s = 0.0;
+  for (int c = 0; c < d.nch; ++c) s += d.red[c];
+  d.h[d.nv] = sqrt(s);
+}
+
+__global__ void k_serve_scale(const ServeDesc *__restrict__ D) {
+  const ServeDesc &d = D[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const double b = d.h[d.nv];
+  d.y[i] = b > 0.0 ? d.y[i] / b : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_serve_product(const ServeDesc *d, int32_t nprob, int64_t tiles, int64_t utasks,
+                                int64_t vtasks, int32_t max_splits, int64_t max_n, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  if (utasks > 0)
+    hipLaunchKernelGGL(k_serve_pinv_u, dim3(blocks_for(utasks, kWavesPerBlock)), dim3(kBlock), 0, s,
+                       d, nprob, utasks);
+  if (vtasks > 0)
+    hipLaunchKernelGGL(k_serve_pinv_v, dim3(blocks_for(vtasks, kWavesPerBlock)), dim3(kBlock), 0, s,
+                       d, nprob, vtasks);
+  if (tiles > 0)
+    hipLaunchKernelGGL((k_serve_direct<kDirectTpl>),
+                       dim3(blocks_for(tiles, kWavesPerBlock), (unsigned)max_splits), dim3(kBlock), 0,
+                       s, d, nprob, tiles);
+  hipLaunchKernelGGL(k_serve_reduce, dim3(blocks_for(max_n), nprob), dim3(kBlock), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_serve_arnoldi(const ServeDesc *d, int32_t nprob, int32_t max_nv, int32_t max_nch,
+                                int64_t max_n, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  const dim3 gd((unsigned)max_nch, (unsigned)((max_nv + kDotVecs - 1) / kDotVecs), (unsigned)nprob);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_serve_mdot, gd, dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_serve_mdot_final, dim3(blocks_for(max_nv), nprob), dim3(kBlock), 0, s, d, pass);
+    hipLaunchKernelGGL(k_serve_mupdate, dim3(blocks_for(max_n), nprob), dim3(kBlock), 0, s, d, pass);
+  }
+  hipLaunchKernelGGL(k_serve_sumsq, dim3((unsigned)max_nch, nprob), dim3(kBlock), 0, s, d);
+  hipLaunchKernelGGL(k_serve_norm, dim3(blocks_for(nprob)), dim3(kBlock), 0, s, d, nprob);
+  hipLaunchKernelGGL(k_serve_scale, dim3(blocks_for(max_n), nprob), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }
 

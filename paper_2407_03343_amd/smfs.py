@@ -27,7 +27,9 @@ EXPORTED = [
     "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_force_torque",
     "smfs_eval_velocity", "smfs_solve_resistance", "smfs_solve_mobility", "smfs_set_solver",
     "smfs_pairs_per_apply", "smfs_block_workspace_bytes", "smfs_apply_block",
-    "smfs_solve_resistance_block",
+    "smfs_solve_resistance_block", "smfs_server_create", "smfs_server_destroy",
+    "smfs_server_clock", "smfs_server_submit", "smfs_server_step", "smfs_server_poll",
+    "smfs_server_release", "smfs_server_stats_read",
     "smfs_profile",
     "smfs_profile_read", "smfs_last_error",
 ]
@@ -78,6 +80,25 @@ class smfs_kernel_stats(C.Structure):
     ]
 
 
+class smfs_request_result(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("P", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
+        ("rel_residual", C.c_double), ("true_rel_residual", C.c_double),
+        ("t_arrival", C.c_double), ("t_admitted", C.c_double), ("t_started", C.c_double),
+        ("t_done", C.c_double), ("pair_evals", C.c_int64),
+    ]
+
+
+class smfs_server_stats(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int64), ("request_iterations", C.c_int64), ("completed", C.c_int64),
+        ("failed", C.c_int64), ("arena_bytes", C.c_size_t), ("arena_peak", C.c_size_t),
+        ("peak_active", C.c_int32), ("step_ms", C.c_double), ("tick_ms", C.c_double),
+        ("setup_ms", C.c_double),
+        ("setup_batches", C.c_int64),
+    ]
+
+
 class smfs_block_out(C.Structure):
     _fields_ = [
         ("ft", C.c_void_p), ("mu", C.c_void_p), ("iterations", C.c_void_p),
@@ -121,6 +142,14 @@ def lib():
         "smfs_solve_mobility": ([vp, vp, P(smfs_out), vp], C.c_int),
         "smfs_pairs_per_apply": ([vp], i64),
         "smfs_block_workspace_bytes": ([vp, i32, i32, P(C.c_size_t)], C.c_int),
+        "smfs_server_create": ([P(smfs_params), dbl, C.c_size_t, i32, i32, P(vp)], C.c_int),
+        "smfs_server_destroy": ([vp], None),
+        "smfs_server_clock": ([], dbl),
+        "smfs_server_submit": ([vp, i32, vp, vp, dbl, P(i64)], C.c_int),
+        "smfs_server_step": ([vp, P(i32), P(i32)], C.c_int),
+        "smfs_server_poll": ([vp, i64, P(smfs_request_result), vp], C.c_int),
+        "smfs_server_release": ([vp, i64], C.c_int),
+        "smfs_server_stats_read": ([vp, P(smfs_server_stats)], C.c_int),
         "smfs_apply_block": ([vp, i32, vp, vp, i64, vp, C.c_size_t, vp], C.c_int),
         "smfs_solve_resistance_block": ([vp, i32, vp, i32, vp, C.c_size_t, P(smfs_block_out), vp],
                                         C.c_int),
@@ -414,3 +443,83 @@ class Problem:
         return dict(ft=ft, mu=mu, iterations=its, true_rel_residual=tr, converged=rc == SMFS_OK,
                     max_iterations=o.max_iterations, n_converged=o.n_converged,
                     t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms, pair_evals=o.pair_evals)
+
+
+class Server:
+    """Continuous-batching server of independent resistance solves (see
+    smfs_server_* in include/smfs.h).  All requests share one discretisation
+    (keyword overrides of smfs_params) and the sphere radius."""
+
+    def __init__(self, radius=1.0, arena_bytes=8 << 30, max_active=64, setup_workers=1, **over):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("smfs.Server needs a HIP device")
+        torch.cuda.init()
+        self.params = params_default(**over)
+        h = C.c_void_p()
+        _check(lib().smfs_server_create(C.byref(self.params), radius, arena_bytes, max_active,
+                                        setup_workers, C.byref(h)), "smfs_server_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smfs_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def clock():
+        return lib().smfs_server_clock()
+
+    def submit(self, centers, rbm, t_arrival=-1.0):
+        c = np.ascontiguousarray(centers, np.float64).reshape(-1, 3)
+        r = np.ascontiguousarray(rbm, np.float64).reshape(-1, 6)
+        if r.shape[0] != c.shape[0]:
+            raise ValueError("rbm must have one row of 6 per sphere")
+        rid = C.c_int64()
+        _check(lib().smfs_server_submit(self.h, c.shape[0], _np_ptr(c), _np_ptr(r), float(t_arrival),
+                                        C.byref(rid)), "smfs_server_submit")
+        return int(rid.value)
+
+    def step(self):
+        a, w = C.c_int32(), C.c_int32()
+        _check(lib().smfs_server_step(self.h, C.byref(a), C.byref(w)), "smfs_server_step")
+        return int(a.value), int(w.value)
+
+    def poll(self, rid, P):
+        """None while the request runs; else a dict with forces/torques (P x 6)."""
+        res = smfs_request_result()
+        ft = np.zeros((P, 6))
+        rc = lib().smfs_server_poll(self.h, rid, C.byref(res), _np_ptr(ft))
+        if rc == 1:
+            return None
+        _check(rc, "smfs_server_poll")
+        d = {k: getattr(res, k) for k, _ in smfs_request_result._fields_}
+        d["ft"] = ft
+        return d
+
+    def release(self, rid):
+        _check(lib().smfs_server_release(self.h, rid), "smfs_server_release")
+
+    def stats(self):
+        st = smfs_server_stats()
+        _check(lib().smfs_server_stats_read(self.h, C.byref(st)), "smfs_server_stats_read")
+        return {k: getattr(st, k) for k, _ in smfs_server_stats._fields_}
+
+    def drain(self, timeout_s=600.0):
+        """Step until nothing is resident or waiting."""
+        import time
+        t0 = time.perf_counter()
+        while True:
+            a, w = self.step()
+            if a == 0 and w == 0:
+                return
+            if a == 0:
+                time.sleep(0.0005)
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError("server did not drain")

@@ -18,6 +18,14 @@ Workloads (all unit spheres, viscosity 1):
                         any other sphere.  Stands in for the paper's random
                         clusters (Sections 4 and 5.2), whose geometries are
                         not published.
+* ``serving_stream`` -- a Poisson stream of independent resistance requests:
+                        sphere counts uniform in [P_lo, P_hi], volume
+                        fractions uniform in [phi_lo, phi_hi], minimum gaps
+                        log-uniform in [gap_lo, gap_hi] (cluster growth with
+                        gaps log-uniform between the drawn minimum and one
+                        radius, in a cube of side at least 6 radii, enlarged
+                        by 10% steps when the growth gets stuck), rigid
+                        motions N(0, 1).
 * ``random_rbm``     -- rigid-body velocities (v, omega) drawn from N(0, 1).
 * ``random_factors`` -- arbitrary dense factors (U, sigma, V) of given
                         shapes, used only to exercise the matrix-vector
@@ -76,11 +84,13 @@ def _unit_vectors(rng: np.random.Generator, n: int) -> np.ndarray:
 
 def cluster(P: int, phi: float, gap_lo: float, gap_hi: float, seed: int,
             gap_min: float = 1e-3, radius: float = 1.0,
-            max_tries: int = 2_000_000) -> Packing:
-    """Cluster-growth packing of ``P`` spheres (see module docstring)."""
+            max_tries: int = 2_000_000, min_box: float = 0.0) -> Packing:
+    """Cluster-growth packing of ``P`` spheres (see module docstring); the
+    cube side is at least ``min_box`` radii (a few spheres at a high volume
+    fraction do not fit a cube of the nominal size)."""
     rng = np.random.default_rng(seed)
     a = radius
-    L = (P * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0) * a
+    L = max((P * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0), min_box) * a
     centers = np.empty((P, 3))
     centers[0] = 0.5 * L
     gaps = [0.0]
@@ -222,3 +232,30 @@ def workload_cluster100(seed: int = 0):
     [1e-3, 1e-1]; N(0,1) rigid-body velocities."""
     pk = cluster(100, 0.2, 1e-3, 1e-1, seed=seed)
     return pk, random_rbm(pk.P, 1, seed + 1000)
+
+
+def serving_stream(n: int = 512, rate: float = 200.0, P_lo: int = 2, P_hi: int = 200,
+                   phi_lo: float = 0.1, phi_hi: float = 0.3, gap_lo: float = 1e-3,
+                   gap_hi: float = 1e-1, seed: int = 0):
+    """``n`` requests with exponential inter-arrival times of mean 1/rate
+    (seconds from the first arrival); each a dict with keys t, P, phi,
+    gap_min, centers (P x 3), rbm (P x 6)."""
+    rng = np.random.default_rng(seed)
+    t = np.concatenate([[0.0], np.cumsum(rng.exponential(1.0 / rate, n - 1))])
+    out = []
+    for i in range(n):
+        P = int(rng.integers(P_lo, P_hi + 1))
+        phi = float(rng.uniform(phi_lo, phi_hi))
+        g = float(10.0 ** rng.uniform(math.log10(gap_lo), math.log10(gap_hi)))
+        cseed = int(rng.integers(1 << 31))
+        box = max((P * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0), 6.0)
+        while True:   # a cluster that gets stuck in its cube retries in a 10% larger one
+            try:
+                pk = cluster(P, phi, g, 1.0, seed=cseed, gap_min=g, min_box=box, max_tries=20000)
+                break
+            except RuntimeError:
+                box *= 1.1
+        out.append(dict(t=float(t[i]), P=P, phi=phi, gap_min=g, centers=pk.centers,
+                        phi_actual=P * 4.0 * math.pi / 3.0 / pk.box ** 3,
+                        rbm=rng.standard_normal((P, 6))))
+    return out
