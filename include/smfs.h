@@ -342,8 +342,10 @@ int64_t smfs_pairs_per_apply(const smfs_problem *pb);
 /* Per-launch timing of the two kernels of each product with G_hat, taken
  * with HIP events recorded on the caller's stream around every launch.
  * Algorithmic work per product: the direct sum does 28, 25 and 30 flops per
- * Stokeslet, rotlet and dipole pair; the pseudo-inverse apply reads its
- * factors once (8 bytes per kept entry of U and V). */
+ * Stokeslet, rotlet and dipole pair; the pseudo-inverse apply reads each
+ * distinct factor once (8 bytes per kept entry of U and V; the shared
+ * factor of the contact-free spheres once for all of them) plus mu and
+ * lambda. */
 typedef struct smfs_kernel_stats {
   int64_t direct_launches;
   double direct_ms;         /* summed over launches */

@@ -344,6 +344,8 @@ int rank_tables(Problem &pb, hipStream_t s) {
 
 // lambda = B^+ mu for every sphere, FP64 (n_u, n_v limit the task lists:
 // the contact-sphere prefix in a mixed-precision product).
+int free_transform64(Problem &pb, const double *mu, double *lam, double dscale, hipStream_t s);
+
 int transform_tasks(Problem &pb, const double *mu, double *lam, int64_t n_u, int64_t n_v,
                     double dscale, hipStream_t s) {
   SMFS_HIP(launch_pinv_u(pb.d_utask, n_u, pb.d_meta, pb.d_fslots, pb.d_fac, mu, pb.d_s, s));
@@ -351,9 +353,26 @@ int transform_tasks(Problem &pb, const double *mu, double *lam, int64_t n_u, int
   return SMFS_OK;
 }
 
+// FP64 lambda = B^+ mu for every sphere: contact spheres by per-row GEMV,
+// the contact-free spheres through the shared factor as one MFMA GEMM pair.
+int transform64(Problem &pb, const double *mu, double *lam, double dscale, hipStream_t s) {
+  int rc = transform_tasks(pb, mu, lam, pb.n_utask_c, pb.n_vtask_c, dscale, s);
+  if (rc) return rc;
+  return free_transform64(pb, mu, lam, dscale, s);
+}
+
+// The contact-free spheres only (shared factor, MFMA).
+int free_transform64(Problem &pb, const double *mu, double *lam, double dscale, hipStream_t s) {
+  const FactorSlot &f0 = pb.factors[0];
+  if (pb.n_free > 0 && f0.rep >= 0)
+    SMFS_HIP(launch_pinv_shared(pb.d_free, pb.n_free, f0.rank, f0.cols, pb.d_meta, pb.d_fslots, pb.d_fac,
+                                mu, pb.d_s, lam, dscale, s));
+  return SMFS_OK;
+}
+
 // physical strengths lambda = B^+ mu
 int transform(Problem &pb, const double *mu, double *lam, hipStream_t s) {
-  return transform_tasks(pb, mu, lam, pb.n_utask, pb.n_vtask, 1.0, s);
+  return transform64(pb, mu, lam, 1.0, s);
 }
 
 DirectArgs direct_args(Problem &pb, const double *str, bool mixed) {
@@ -398,7 +417,7 @@ int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s
   // dipole strengths pre-multiplied by 2 mu for the direct-sum kernel
   const double ds = 2.0 * pb.prm.mu;
   if (!mixed) {
-    rc = transform_tasks(pb, mu, pb.d_lamhat, pb.n_utask, pb.n_vtask, ds, s);
+    rc = transform64(pb, mu, pb.d_lamhat, ds, s);
   } else {
     rc = transform_tasks(pb, mu, pb.d_lamhat, pb.n_utask_c, pb.n_vtask_c, ds, s);
     const int64_t off0 = pb.factors[0].u_off;   // FP32 copy holds factor 0 only
@@ -947,10 +966,12 @@ int smfs_profile_read(smfs_problem *pb, smfs_kernel_stats *st) {
     gemm += 2.0 * q * ((double)f.rows * f.rank + (double)f.cols * f.rank);
   }
   st->bpinv_flops = gemm;
-  double bytes = 0.0;
-  for (int k = 0; k < pb->P; ++k) {
-    const FactorSlot &f = pb->factors[pb->fid_of[k]];
-    bytes += 8.0 * ((double)f.rows * f.rank + (double)f.cols * f.rank);
+  // minimal traffic of the FP64 apply: every contact sphere's factors, the
+  // shared factor once, mu read and lambda written
+  double bytes = 8.0 * (3.0 * pb->T + 3.0 * pb->S);
+  for (size_t f = 0; f < pb->factors.size(); ++f) {
+    const FactorSlot &fs = pb->factors[f];
+    if (fs.rep >= 0) bytes += 8.0 * ((double)fs.rows * fs.rank + (double)fs.cols * fs.rank);
   }
   st->pinv_bytes = bytes;
   return SMFS_OK;
@@ -968,10 +989,8 @@ int apply_mobility(Problem &pb, const double *x, double *y, int precision, hipSt
   if (rc) return rc;
   const bool mixed = precision == SMFS_MIXED && pb.n_free > 0 && pb.fac32_ready;
   if (mixed) {  // FP64 strengths of the contact-free spheres for their forces
-    SMFS_HIP(launch_pinv_u(pb.d_utask + pb.n_utask_c, pb.n_utask - pb.n_utask_c, pb.d_meta,
-                           pb.d_fslots, pb.d_fac, x, pb.d_s, s));
-    SMFS_HIP(launch_pinv_v(pb.d_vtask + pb.n_vtask_c, pb.n_vtask - pb.n_vtask_c, pb.d_meta,
-                           pb.d_fslots, pb.d_fac, pb.d_s, pb.d_lamhat, 2.0 * pb.prm.mu, s));
+    rc = free_transform64(pb, x, pb.d_lamhat, 2.0 * pb.prm.mu, s);
+    if (rc) return rc;
   }
   SMFS_HIP(launch_rigid(pb.T, pb.d_tgt, pb.d_tsph, pb.d_sw, pb.d_meta, x + n, -1.0, 1.0, y, s));
   const double sF = 1.0 / (6.0 * kPi * pb.prm.mu * pb.a), sT = 1.0 / (8.0 * kPi * pb.prm.mu * pb.a * pb.a * pb.a);

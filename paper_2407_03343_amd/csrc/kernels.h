@@ -197,4 +197,13 @@ hipError_t launch_serve_product(const ServeDesc *d, int32_t nprob, int64_t tiles
 hipError_t launch_serve_arnoldi(const ServeDesc *d, int32_t nprob, int32_t max_nv, int32_t max_nch,
                                 int64_t max_n, hipStream_t s);
 
+// The shared factor 0 applied to all n_free contact-free spheres (their
+// sphere ids in free_ids) as two GEMMs on FP64 MFMA; rank and cols are
+// factor 0's (host copies, for the grid).  Writes sbuf at each sphere's s0
+// and lam at its packed sources, dipoles times dscale.
+hipError_t launch_pinv_shared(const int32_t *free_ids, int32_t n_free, int32_t rank, int32_t cols,
+                              const SphereMeta *meta, const FactorSlot *fs, const double *fac,
+                              const double *mu, double *sbuf, double *lam, double dscale,
+                              hipStream_t s);
+
 }  // namespace smfs

@@ -1604,3 +1604,102 @@ hipError_t launch_serve_arnoldi(const ServeDesc *d, int32_t nprob, int32_t max_n
 }
 
 }  // namespace smfs
+
+// ===========================================================================
+// The shared factor of the contact-free spheres (eq. transform with one
+// B^+ for all of them) as two GEMMs on FP64 MFMA, the spheres as columns:
+// S_q = Sigma^-1 U_0^T mu_q, then lambda_q = V_0 S_q.  One wave per 32 x 32
+// tile (rows of U_0^T or V_0 by free spheres); the factor is read once per
+// 32 spheres instead of once per sphere.
+
+namespace smfs {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_pinv_shared_u(const int32_t *__restrict__ free_ids,
+                                                          int32_t n_free,
+                                                          const SphereMeta *__restrict__ meta,
+                                                          const FactorSlot *__restrict__ fs,
+                                                          const double *__restrict__ fac,
+                                                          const double *__restrict__ mu,
+                                                          double *__restrict__ sbuf) {
+  const int lane = threadIdx.x & 63;
+  const FactorSlot &f = fs[0];
+  const int rank = f.rank;
+  const int r0 = ((int)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave)) * 32;
+  const int q0 = blockIdx.y * 32;
+  if (r0 >= rank) return;
+  const double *arow[2], *bcol[2];
+  bool aok[2], bok[2];
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
+    aok[h] = r < rank;
+    bok[h] = q < n_free;
+    arow[h] = fac + f.u_off + (int64_t)(aok[h] ? r : 0) * f.rows;
+    bcol[h] = mu + 3 * meta[free_ids[bok[h] ? q : 0]].t0;
+  }
+  TileTN tile;
+  mfma_tile_tn(arow, aok, bcol, bok, f.rows, tile);
+  const double *sig = fac + f.sig_off;
+  for (int ia = 0; ia < 2; ++ia)
+    for (int jb = 0; jb < 2; ++jb)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * ia + 4 * v + (lane >> 4), q = q0 + 16 * jb + (lane & 15);
+        if (r < rank && q < n_free) sbuf[meta[free_ids[q]].s0 + r] = tile.acc[ia][jb][v] / sig[r];
+      }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pinv_shared_v(const int32_t *__restrict__ free_ids,
+                                                          int32_t n_free,
+                                                          const SphereMeta *__restrict__ meta,
+                                                          const FactorSlot *__restrict__ fs,
+                                                          const double *__restrict__ fac,
+                                                          const double *__restrict__ sbuf,
+                                                          double *__restrict__ lam, double dscale) {
+  const int lane = threadIdx.x & 63;
+  const FactorSlot &f = fs[0];
+  const int rows = f.cols;
+  const int r0 = ((int)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave)) * 32;
+  const int q0 = blockIdx.y * 32;
+  if (r0 >= rows) return;
+  const double *arow[2], *bcol[2];
+  bool aok[2], bok[2];
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
+    aok[h] = r < rows;
+    bok[h] = q < n_free;
+    arow[h] = fac + f.vt_off + (int64_t)(aok[h] ? r : 0) * f.cols;
+    bcol[h] = sbuf + meta[free_ids[bok[h] ? q : 0]].s0;
+  }
+  TileTN tile;
+  mfma_tile_tn(arow, aok, bcol, bok, f.rank, tile);
+  for (int ia = 0; ia < 2; ++ia)
+    for (int jb = 0; jb < 2; ++jb)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * ia + 4 * v + (lane >> 4), q = q0 + 16 * jb + (lane & 15);
+        if (r < rows && q < n_free) {
+          const SphereMeta &m = meta[free_ids[q]];
+          const int jl = r / 3, c = r - 3 * (r / 3);
+          const double val = tile.acc[ia][jb][v];
+          lam[3 * packed_index(m, jl) + c] = jl >= m.kn[0] + m.kn[1] + m.kn[2] ? val * dscale : val;
+        }
+      }
+}
+
+}  // namespace
+
+hipError_t launch_pinv_shared(const int32_t *free_ids, int32_t n_free, int32_t rank, int32_t cols,
+                              const SphereMeta *meta, const FactorSlot *fs, const double *fac,
+                              const double *mu, double *sbuf, double *lam, double dscale,
+                              hipStream_t s) {
+  if (n_free <= 0 || rank <= 0) return hipSuccess;
+  const unsigned qt = (unsigned)((n_free + 31) / 32);
+  const unsigned gu = (unsigned)(((rank + 31) / 32 + kWavesPerBlock - 1) / kWavesPerBlock);
+  const unsigned gv = (unsigned)(((cols + 31) / 32 + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(k_pinv_shared_u, dim3(gu, qt), dim3(kBlock), 0, s, free_ids, n_free, meta, fs, fac,
+                     mu, sbuf);
+  hipLaunchKernelGGL(k_pinv_shared_v, dim3(gv, qt), dim3(kBlock), 0, s, free_ids, n_free, meta, fs, fac,
+                     sbuf, lam, dscale);
+  return hipGetLastError();
+}
+
+}  // namespace smfs

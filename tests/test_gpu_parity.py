@@ -322,3 +322,26 @@ def test_mobility_mixed_precision(dev, mixed_small):
     _say(f"  it {out['iterations']} (+{out['refinements']}), V rel diff {d:.2e}")
     assert out["pair_evals_f32"] > 0
     assert d < 1e-5
+
+
+def test_shared_factor_gemm_many_free(dev, oracle_pairsum_built):
+    """45 spheres, 43 of them contact-free (two 32-column tiles of the
+    shared-factor GEMM, the second ragged) and one near-contact pair."""
+    _say("shared-factor MFMA GEMM: 43 contact-free spheres + one pair")
+    g3 = np.array([(i, j, k) for i in range(4) for j in range(4) for k in range(3)], float)[:44] * 2.6
+    c = np.vstack([g3, g3[-1] + np.array([2.01, 0.0, 0.0])])
+    prm = dict(n_proxy=60, n_colloc_base=80, n_image=4, n_check_base=0)
+    g = geo.build(c, 1.0, geo.Params(**prm))
+    pbo = mfs.Problem(g).setup()
+    lib = dev.Problem(c, 1.0, **prm).bind()
+    _import_oracle_factors(lib, pbo)
+    assert lib.sizes.n_factors == 3
+    rbm = wl.random_rbm(g.P, 1, 71)[0]
+    b = pbo.rhs(rbm)
+    assert _rel(_n(lib.apply(_t(b))), pbo.apply(b)) < 1e-10
+    mu = wl.random_vector(3 * g.T, 72)
+    ref = pbo.apply(mu)
+    sens = _rel(pbo.apply(mu, _transform_ext(pbo, mu)), ref)
+    assert _rel(_n(lib.apply(_t(mu))), ref) < max(1e-10, 20 * sens)
+    lam = _n(lib.transform(_t(b)))
+    assert _rel(lam, pbo.transform(b)) < 1e-10
