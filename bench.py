@@ -34,6 +34,10 @@ if ROOT not in sys.path:
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X, FP64 vector
 PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X, FP64 dense matrix
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the direct sum on the 100-sphere workload (62 source
+# splits): rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB elementwise
+# copy reads back) plus WRITE_SIZE (x1), profiles/k_direct_f64_cluster100_fp64_hbm_counters.md
+DIRECT_TRAFFIC_BYTES = (2 * 225710.8 + 387461.4) * 1024
 
 
 def log(msg):
@@ -57,8 +61,9 @@ def cpu_baseline(pk, stride: int):
     pairs = float(np.sum(g.S - own[g.target_sphere[rows]]))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=pairs / dt, unit="pair-evals/s", cores=cores, kind="oracle",
-                sample=f"oracle C direct sum, every {stride}th of {g.T} collocation nodes "
-                       f"({rows.size} targets) x {g.S} sources, {pairs:.3g} pairs in {dt:.1f} s")
+                sample=(f"oracle C direct sum (OpenMP), {rows.size} of {g.T} collocation nodes "
+                        f"(every {stride}) x {g.S} sources, same-sphere pairs skipped: "
+                        f"{pairs:.3g} pairs in {dt:.1f} s"))
 
 
 def mixed_vs_fp64(args, torch, smfs, wl):
@@ -87,12 +92,10 @@ def mixed_vs_fp64(args, torch, smfs, wl):
            "setup_s": setup_s, "forms": {}}
     for name, prec in (("fp64", smfs.SMFS_FP64), ("mixed", smfs.SMFS_MIXED)):
         rows = []
-        for tol in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
+        for tol in args.mixed_tols:
             pb.set_solver(prec, tol)
-            pb.solve_resistance(rbm)                       # warm
-            torch.cuda.synchronize()
             ts = []
-            for _ in range(3):
+            for _ in range(args.mixed_reps):
                 t1 = time.perf_counter()
                 o = pb.solve_resistance(rbm)
                 torch.cuda.synchronize()
@@ -111,6 +114,21 @@ def mixed_vs_fp64(args, torch, smfs, wl):
         ok = [r for r in rows if r["u_rel_err"] <= 1e-3]
         best = min(ok, key=lambda r: r["solve_ms_p50"]) if ok else None
         out["forms"][name] = {"scan": rows, "at_1e-3_surface_velocity": best}
+    # mobility (forces and torques in), each form at the tolerance that met
+    # the surface-velocity target above
+    ft = torch.from_numpy(wl.random_ft(pb.P, 1, 78)[0].reshape(-1)).cuda()
+    out["mobility"] = {}
+    for name, prec in (("fp64", smfs.SMFS_FP64), ("mixed", smfs.SMFS_MIXED)):
+        best = out["forms"][name]["at_1e-3_surface_velocity"]
+        tol = best["tol"] if best else 1e-6
+        pb.set_solver(prec, tol)
+        t1 = time.perf_counter()
+        o = pb.solve_mobility(ft)
+        torch.cuda.synchronize()
+        out["mobility"][name] = dict(tol=tol, iterations=o["iterations"], refinements=o["refinements"],
+                                     solve_ms=(time.perf_counter() - t1) * 1e3,
+                                     true_rel_residual=o["true_rel_residual"], converged=o["converged"])
+        log(f"  mobility {name} tol {tol:.0e}: it {o['iterations']}, {out['mobility'][name]['solve_ms']:.1f} ms")
     f64 = out["forms"]["fp64"]["at_1e-3_surface_velocity"]
     mx = out["forms"]["mixed"]["at_1e-3_surface_velocity"]
     if f64 and mx:
@@ -199,6 +217,54 @@ def block_vs_single(pb, torch, nrhs: int, reps: int, seed: int = 7):
     }
 
 
+def block_solve(args, torch, smfs, wl):
+    """Many-right-hand-side solve against the same systems solved one after
+    another: a cut of the volume-fraction-0.35 workload (40% of the spheres
+    in near-contact pairs), 64 rigid motions, both forms GMRES(m) with the
+    same restart length and tolerance in FP64.  The sequential time is
+    measured on a sample of the systems and scaled to all of them."""
+    pk, rbm = wl.workload_block500(args.block_spheres, seed=args.seed)
+    nrhs, m = rbm.shape[0], args.block_restart
+    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=m, gmres_max_it=args.block_max_it,
+                      gmres_tol=args.block_tol)
+    pb.bind()
+    t0 = time.perf_counter()
+    pb.setup()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"block solve: {pb.P} spheres, T={pb.T}, S={pb.S}, {nrhs} right-hand sides, setup {setup_s:.1f} s")
+    R = torch.from_numpy(np.ascontiguousarray(rbm)).cuda()
+    pb.solve_resistance_block(R[:4], restart=m)          # warm-up (code, workspace)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    blk = pb.solve_resistance_block(R, restart=m)
+    torch.cuda.synchronize()
+    t_block = time.perf_counter() - t1
+    ft_blk = blk["ft"].cpu().numpy()
+    k = min(nrhs, args.block_sequential)
+    its, dft = [], 0.0
+    t2 = time.perf_counter()
+    for q in range(k):
+        o = pb.solve_resistance(R[q].reshape(-1).contiguous(), want_check=False)
+        its.append(o["iterations"])
+        f = o["ft"].cpu().numpy().reshape(-1, 6)
+        dft = max(dft, float(np.abs(f - ft_blk[q]).max() / np.abs(f).max()))
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t2) / k * nrhs
+    return {
+        "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S, "nrhs": nrhs, "restart": m,
+        "tol": args.block_tol, "setup_s": setup_s,
+        "block_solve_s": t_block, "block_iterations_max": int(blk["max_iterations"]),
+        "block_converged": int(blk["n_converged"]),
+        "max_true_rel_residual": float(np.max(blk["true_rel_residual"])),
+        "sequential_sample": k, "sequential_iterations": its,
+        "sequential_solve_s_for_all": t_seq,
+        "speedup_block_over_sequential": t_seq / t_block,
+        "block_vs_sequential_ft_rel_diff": dft,
+        "block_pair_rhs_evals_per_s": blk["pair_evals"] / t_block,
+    }
+
+
 def _gen_request(args):
     from paper_2407_03343_amd import workloads as wl
     i, seed, kw = args
@@ -248,6 +314,9 @@ def serving(args, torch, smfs, reqs, arrivals):
     res = [srv.poll(rid, r["P"]) for rid, r in zip(ids, reqs)]
     st = srv.stats()
     srv.close()
+    errors = sorted({r["error"] for r in res if r["status"] < 0})
+    for e in errors:
+        log(f"  serving: failed requests report: {e}")
     lat = np.array([r["t_done"] - r["t_arrival"] for r in res]) * 1e3
     span = max(r["t_done"] for r in res) - t0
     pairs = sum(r["pair_evals"] for r in res)
@@ -261,7 +330,7 @@ def serving(args, torch, smfs, reqs, arrivals):
         "pair_evals_per_s": pairs / span,
         "makespan_s": span,
         "iterations_p50": float(np.percentile(its, 50)),
-        "failed": int(st["failed"]),
+        "failed": int(st["failed"]), "errors": errors,
         "not_converged": int(sum(1 for r in res if r["status"] == 1)),
         "max_true_rel_residual": float(max(r["true_rel_residual"] for r in res)),
         "peak_active": st["peak_active"], "steps": st["steps"],
@@ -288,21 +357,30 @@ def serving(args, torch, smfs, reqs, arrivals):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the volume-fraction-0.3 packing")
     ap.add_argument("--mixed-spheres", type=int, default=200)
+    ap.add_argument("--mixed-tols", type=float, nargs="+", default=[1e-4, 1e-5, 1e-6],
+                    help="GMRES tolerances scanned for the 1e-3 surface-velocity target")
+    ap.add_argument("--mixed-reps", type=int, default=2, help="timed solves per tolerance")
     ap.add_argument("--apply-only", type=int, default=0, metavar="N",
                     help="profiling aid: N products with G_hat on the same workload with "
                          "seeded full-rank factors instead of the SVD setup, then one plain "
                          "1 GiB device copy (the counter calibration kernel)")
     ap.add_argument("--block", type=int, default=64, metavar="NRHS",
                     help="right-hand sides of the block-product comparison (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--block-spheres", type=int, default=24,
+                    help="spheres of the many-right-hand-side solve comparison (0: skip)")
+    ap.add_argument("--block-restart", type=int, default=200)
+    ap.add_argument("--block-tol", type=float, default=1e-8)
+    ap.add_argument("--block-max-it", type=int, default=3000)
+    ap.add_argument("--block-sequential", type=int, default=4)
+    ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests of the serving stream (the full stream is 512)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=64)
@@ -312,7 +390,7 @@ def main():
     ap.add_argument("--serve-image", type=int, default=6)
     ap.add_argument("--serve-tol", type=float, default=1e-6)
     ap.add_argument("--serve-workers", type=int, default=1, help="set-up worker threads")
-    ap.add_argument("--serve-sequential", type=int, default=4,
+    ap.add_argument("--serve-sequential", type=int, default=3,
                     help="requests solved one after another for the comparison")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving comparison")
     args = ap.parse_args()
@@ -409,7 +487,8 @@ def main():
             "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": DIRECT_TRAFFIC_BYTES,
+            "traffic_unit": "bytes per launch",
             "avg_launch_ms": direct_avg_s * 1e3,
             "launches": st["direct_launches"],
             "flops_per_launch": st["direct_flops"],
@@ -424,11 +503,15 @@ def main():
     if args.block:
         log(f"block product of {args.block} vectors vs {args.block} single products ...")
         result["block_vs_single"] = block_vs_single(pb, torch, args.block, 2)
+    del pb
+    torch.cuda.empty_cache()
+    if args.block_spheres > 0:
+        result["block_solve"] = block_solve(args, torch, smfs, wl)
+        torch.cuda.empty_cache()
     if not args.no_mixed:
         result["mixed_vs_fp64"] = mixed_vs_fp64(args, torch, smfs, wl)
-    if args.serve_requests > 0:
-        del pb
         torch.cuda.empty_cache()
+    if args.serve_requests > 0:
         result["serving"] = serving(args, torch, smfs, reqs, arrivals)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -314,6 +314,7 @@ typedef struct smfs_request_result {
   double true_rel_residual;    /* ||b - G_hat mu|| / ||b|| in FP64 */
   double t_arrival, t_admitted, t_started, t_done;   /* smfs_server_clock seconds */
   int64_t pair_evals;
+  char error[160];             /* message of a failed request (empty otherwise) */
 } smfs_request_result;
 
 /* Result of request id: returns 0 and fills *res (and ft [host] P x 6

@@ -543,6 +543,9 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
       int rc = op(V + (int64_t)j * ld, vj1, precision);
       if (rc) return rc;
       // classical Gram-Schmidt, twice: h = V^T w, w -= V h; h2 = V^T w, w -= V h2
+      // (a second pass only when the norm drops below 1/sqrt(2), the DGKS
+      // criterion, was measured to need the second pass in all but one of
+      // 1575 iterations of the 100-sphere solve, so it is always taken)
       SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h, false, s));
       SMFS_HIP(launch_mupdate(V, ld, j + 1, h, vj1, n, s));
       SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h2, false, s));

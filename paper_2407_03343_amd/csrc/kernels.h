@@ -112,6 +112,8 @@ hipError_t launch_mupdate(const double *V, int64_t ld, int32_t nv, const double 
                           int64_t n, hipStream_t s);
 hipError_t launch_norm_scale(double *w, int64_t n, double *part, int32_t nchunks, double *beta,
                              double *out, hipStream_t s);
+// w /= beta[0] (w = 0 when beta[0] = 0); beta on the device
+hipError_t launch_scale(double *w, int64_t n, const double *beta, hipStream_t s);
 // y = a*x + b*y ; x,y length n (a, b host scalars)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 // y[i] = v

@@ -734,22 +734,36 @@ __global__ void k_mdot_final(int32_t nv, const double *__restrict__ part, int32_
   h[j] = acc ? h[j] + s : s;
 }
 
+// sum_j V[j][i] c[j] for element i of nv basis vectors (stride ld): eight
+// loads in flight per step and four partial sums, so that the loop is
+// bound by HBM bandwidth rather than by one load latency per vector.
+__device__ __forceinline__ double basis_row_dot(const double *__restrict__ V, int64_t ld, int nv,
+                                                const double *__restrict__ c, int64_t i) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = 0;
+  for (; j + 7 < nv; j += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(j + u) * ld + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u & 3] = fma(v[u], c[j + u], s[u & 3]);
+  }
+  for (; j < nv; ++j) s[0] = fma(V[(int64_t)j * ld + i], c[j], s[0]);
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 __global__ void k_mupdate(const double *__restrict__ V, int64_t ld, int32_t nv,
                           const double *__restrict__ h, double *__restrict__ w, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = 0.0;
-  for (int j = 0; j < nv; ++j) s = fma(V[(int64_t)j * ld + i], h[j], s);
-  w[i] -= s;
+  w[i] -= basis_row_dot(V, ld, nv, h, i);
 }
 
 __global__ void k_combine(const double *__restrict__ V, int64_t ld, int32_t nv,
                           const double *__restrict__ cf, double *__restrict__ x, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = 0.0;
-  for (int j = 0; j < nv; ++j) s = fma(V[(int64_t)j * ld + i], cf[j], s);
-  x[i] += s;
+  x[i] += basis_row_dot(V, ld, nv, cf, i);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sumsq(const double *__restrict__ w, int64_t n,
@@ -959,6 +973,12 @@ hipError_t launch_norm2(const double *w, int64_t n, double *part, int32_t nchunk
   const int64_t chunk = chunk_len(n, nchunks);
   hipLaunchKernelGGL(k_sumsq, dim3(nchunks), dim3(kBlock), 0, s, w, n, chunk, part);
   hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(64), 0, s, part, nchunks, (double *)nullptr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double *w, int64_t n, const double *beta, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, w, n, beta);
   return hipGetLastError();
 }
 
@@ -1298,10 +1318,7 @@ __global__ void k_mupdate_b(const double *__restrict__ V, int64_t ld, int32_t nr
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (i >= n) return;
-  const double *hq = h + (int64_t)q * ldh;
-  double s = 0.0;
-  for (int j = 0; j < nv; ++j) s = fma(V[((int64_t)j * nrhs + q) * ld + i], hq[j], s);
-  W[q * ldw + i] -= s;
+  W[q * ldw + i] -= basis_row_dot(V + (int64_t)q * ld, (int64_t)nrhs * ld, nv, h + (int64_t)q * ldh, i);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sumsq_b(const double *__restrict__ W, int64_t ldw,
@@ -1343,10 +1360,7 @@ __global__ void k_combine_b(const double *__restrict__ V, int64_t ld, int32_t nr
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (i >= n) return;
-  const double *c = cf + (int64_t)q * ldc;
-  double s = 0.0;
-  for (int j = 0; j < nv; ++j) s = fma(V[((int64_t)j * nrhs + q) * ld + i], c[j], s);
-  X[q * ldx + i] += s;
+  X[q * ldx + i] += basis_row_dot(V + (int64_t)q * ld, (int64_t)nrhs * ld, nv, cf + (int64_t)q * ldc, i);
 }
 
 }  // namespace
@@ -1534,10 +1548,7 @@ __global__ void k_serve_mupdate(const ServeDesc *__restrict__ D, int pass) {
   const ServeDesc &d = D[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  const double *h = pass ? d.h2 : d.h;
-  double s = 0.0;
-  for (int j = 0; j < d.nv; ++j) s = fma(d.V[(int64_t)j * d.ld + i], h[j], s);
-  d.y[i] -= s;
+  d.y[i] -= basis_row_dot(d.V, d.ld, d.nv, pass ? d.h2 : d.h, i);
 }
 
 __global__ __launch_bounds__(kBlock) void k_serve_sumsq(const ServeDesc *__restrict__ D) {

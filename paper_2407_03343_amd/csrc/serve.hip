@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -311,12 +312,16 @@ void factor_batch(Worker &wk, std::vector<Req *> &batch) {
           rc = SMFS_E_SVD;
         }
       }
-      if (!rc && (hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * nb, hipMemcpyDeviceToHost, s) ||
-                  hipMemcpy2DAsync(sv.data(), 8 * (size_t)n, Out + per + (size_t)n * n, 8 * slot,
-                                   8 * (size_t)n, nb, hipMemcpyDeviceToHost, s) ||
-                  hipStreamSynchronize(s))) {
-        set_error("serving: reading SVD results failed");
-        rc = SMFS_E_DEVICE;
+      if (!rc) {
+        hipError_t e = hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * nb, hipMemcpyDeviceToHost, s);
+        for (int q = 0; q < nb && e == hipSuccess; ++q)
+          e = hipMemcpyAsync(sv.data() + (size_t)q * n, Out + (size_t)q * slot + per + (size_t)n * n,
+                             8 * (size_t)n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+          set_error(std::string("serving: reading SVD results failed: ") + hipGetErrorString(e));
+          rc = SMFS_E_DEVICE;
+        }
       }
       for (int q = 0; q < nb; ++q) {
         const Job &jb = jobs[j0 + q];
@@ -324,7 +329,8 @@ void factor_batch(Worker &wk, std::vector<Req *> &batch) {
         if (rc) { fail(jb.r, rc); continue; }
         const double *sq = sv.data() + (size_t)q * n;
         if (hinfo[q] != 0 || !(sq[0] > 0)) {
-          set_error("SVD did not converge (info " + std::to_string(hinfo[q]) + ")");
+          set_error("SVD did not converge (info " + std::to_string(hinfo[q]) + ", sigma_1 " +
+                    std::to_string(sq[0]) + ")");
           fail(jb.r, SMFS_E_SVD);
           continue;
         }
@@ -819,6 +825,7 @@ int smfs_server_poll(smfs_server *srv, int64_t id, smfs_request_result *res, dou
   res->t_started = r->t_start;
   res->t_done = r->t_done;
   res->pair_evals = r->pair_evals;
+  std::snprintf(res->error, sizeof(res->error), "%s", r->err.c_str());
   if (ft && !r->ft.empty()) std::memcpy(ft, r->ft.data(), sizeof(double) * r->ft.size());
   return SMFS_OK;
 }

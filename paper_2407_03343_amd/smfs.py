@@ -85,7 +85,7 @@ class smfs_request_result(C.Structure):
         ("status", C.c_int32), ("P", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
         ("rel_residual", C.c_double), ("true_rel_residual", C.c_double),
         ("t_arrival", C.c_double), ("t_admitted", C.c_double), ("t_started", C.c_double),
-        ("t_done", C.c_double), ("pair_evals", C.c_int64),
+        ("t_done", C.c_double), ("pair_evals", C.c_int64), ("error", C.c_char * 160),
     ]
 
 
@@ -500,6 +500,7 @@ class Server:
             return None
         _check(rc, "smfs_server_poll")
         d = {k: getattr(res, k) for k, _ in smfs_request_result._fields_}
+        d["error"] = res.error.decode(errors="replace")
         d["ft"] = ft
         return d
 

@@ -27,6 +27,10 @@ Workloads (all unit spheres, viscosity 1):
                         by 10% steps when the growth gets stuck), rigid
                         motions N(0, 1).
 * ``random_rbm``     -- rigid-body velocities (v, omega) drawn from N(0, 1).
+* ``workload_block500`` -- the many-right-hand-side workload: hard-sphere
+                        fluid at volume fraction 0.35 with 40% of the spheres
+                        pulled into pairs at gaps log-uniform in
+                        [1e-3, 5e-2], 64 sets of rigid motions.
 * ``random_factors`` -- arbitrary dense factors (U, sigma, V) of given
                         shapes, used only to exercise the matrix-vector
                         product at full size with inputs that need no SVD.
@@ -84,10 +88,13 @@ def _unit_vectors(rng: np.random.Generator, n: int) -> np.ndarray:
 
 def cluster(P: int, phi: float, gap_lo: float, gap_hi: float, seed: int,
             gap_min: float = 1e-3, radius: float = 1.0,
-            max_tries: int = 2_000_000, min_box: float = 0.0) -> Packing:
+            max_tries: int = 2_000_000, min_box: float = 0.0,
+            far: tuple | None = None) -> Packing:
     """Cluster-growth packing of ``P`` spheres (see module docstring); the
     cube side is at least ``min_box`` radii (a few spheres at a high volume
-    fraction do not fit a cube of the nominal size)."""
+    fraction do not fit a cube of the nominal size).  With ``far = (frac,
+    lo, hi)`` a new sphere's gap to its anchor is drawn log-uniform in
+    [lo, hi] with probability ``frac`` instead of [gap_lo, gap_hi]."""
     rng = np.random.default_rng(seed)
     a = radius
     L = max((P * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0), min_box) * a
@@ -102,7 +109,10 @@ def cluster(P: int, phi: float, gap_lo: float, gap_hi: float, seed: int,
         if tries > max_tries:
             raise RuntimeError("cluster packing did not converge")
         anchor = int(rng.integers(n))
-        g = 10.0 ** rng.uniform(lg_lo, lg_hi)
+        if far is not None and rng.uniform() < far[0]:
+            g = 10.0 ** rng.uniform(math.log10(far[1]), math.log10(far[2]))
+        else:
+            g = 10.0 ** rng.uniform(lg_lo, lg_hi)
         d = _unit_vectors(rng, 1)[0]
         c = centers[anchor] + (2.0 + g) * a * d
         if np.any(c < a) or np.any(c > L - a):
@@ -259,3 +269,12 @@ def serving_stream(n: int = 512, rate: float = 200.0, P_lo: int = 2, P_hi: int =
                         phi_actual=P * 4.0 * math.pi / 3.0 / pk.box ** 3,
                         rbm=rng.standard_normal((P, 6))))
     return out
+
+
+def workload_block500(P: int = 500, seed: int = 0):
+    """Unit spheres at volume fraction 0.35: a hard-sphere fluid with every
+    gap at least 0.05, then 40% of the spheres pulled into nearest-neighbour
+    pairs at gaps log-uniform in [1e-3, 5e-2]; 64 sets of rigid-body
+    velocities N(0, 1).  ``P`` < 500 gives a cut of the same recipe."""
+    pk = fluid_with_pairs(P, 0.35, 0.05, 0.4, 1e-3, 5e-2, seed=seed, pair_gap_min=0.05)
+    return pk, random_rbm(pk.P, 64, seed + 2000)
