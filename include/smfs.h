@@ -72,7 +72,10 @@ typedef struct smfs_params {
   uint32_t image_kinds;     /* SMFS_KIND_* mask placed at image nodes */
   double image_offset;      /* Delta in eq. (tj) */
   double image_gap_cutoff;  /* pairs with gap below this get image lines */
-  double near_gap_cutoff;   /* mixed precision: pairs below this stay FP64 */
+  double near_gap_cutoff;   /* mixed precision: pairs below this stay FP64; must not
+                               exceed image_gap_cutoff (the FP32 class is the proxy
+                               sources of spheres without a contact), else
+                               SMFS_E_UNSUPPORTED at create */
   int32_t cap_alpha[2];     /* cap upsampling, eq. (colloc_nbr) */
   double cap_beta[2];       /* cap half-angles, eq. (thetacap) */
   int32_t left_weights;     /* row weights sqrt(area) (Remark left-precond) */

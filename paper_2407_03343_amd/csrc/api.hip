@@ -650,6 +650,10 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
     set_error("smfs_problem_create: invalid parameter");
     return SMFS_E_INVALID_ARG;
   }
+  if (p->near_gap_cutoff > p->image_gap_cutoff) {
+    set_error("smfs_problem_create: near_gap_cutoff above image_gap_cutoff is not supported");
+    return SMFS_E_UNSUPPORTED;
+  }
   for (int i = 0; i < 3 * P; ++i)
     if (!std::isfinite(centers[i])) {
       set_error("smfs_problem_create: non-finite centre");

@@ -81,6 +81,12 @@ def test_overlap_and_unequal_radii_rejected():
     rc = L.smfs_problem_create(C.byref(p), 2, c.ctypes.data_as(C.c_void_p),
                                r.ctypes.data_as(C.c_void_p), C.byref(h))
     assert rc == -1
+    # an FP64 class wider than the image cutoff is not supported
+    p2 = smfs.params_default(near_gap_cutoff=0.3)
+    c = np.array([[0.0, 0, 0], [5.0, 0, 0]])
+    rc = L.smfs_problem_create(C.byref(p2), 2, c.ctypes.data_as(C.c_void_p),
+                               r.ctypes.data_as(C.c_void_p), C.byref(h))
+    assert rc == -3 and "near_gap_cutoff" in L.smfs_last_error().decode()
 
 
 def test_small_gap_warning_and_state_errors():
