@@ -109,7 +109,7 @@ typedef struct smfs_out {
   double *u_check;          /* [dev] n_check x 3: velocity at check points */
   double *rbm;              /* [dev] P x 6: rigid motions found (mobility only) */
   /* host statistics */
-  int32_t iterations;
+  int32_t iterations;       /* GMRES iterations: Krylov dimension summed over restart cycles */
   double rel_residual;      /* GMRES estimate at exit */
   double true_rel_residual; /* ||b - G_hat mu|| / ||b||, recomputed in FP64 */
   double lambda_inf;        /* max |lambda| (stability indicator, Section 3) */

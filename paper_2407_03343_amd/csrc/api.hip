@@ -121,7 +121,7 @@ size_t workspace_layout(Problem &pb, bool assign) {
   const size_t o_kry = take(sizeof(double) * ld * (m + 1));
   const size_t o_vec = take(sizeof(double) * ld * 6);
   const int32_t nch = mdot_chunks(3 * T + 6 * (int64_t)P);
-  const int64_t red = (int64_t)nch * (m + 2) + 4 * (m + 2) + 64;
+  const int64_t red = 2 * (int64_t)nch * (m + 2) + 6 * (m + 2) + 1024 + 64;
   const size_t o_red = take(sizeof(double) * red);
   // factors: slots of equal shape are consecutive with a uniform stride so
   // that one strided-batched SVD can write a whole group in place
@@ -483,18 +483,30 @@ int eval_points(Problem &pb, const double *lam, int64_t n, const double *x, doub
 }
 
 // ---------------------------------------------------------------------------
-// GMRES on G_hat mu = b with x0 = 0; Arnoldi by classical Gram-Schmidt
-// applied twice, Givens rotations on the host (the Hessenberg column is
-// read back once per iteration), restarted every gmres_restart steps.
+// GMRES on G_hat mu = b with x0 = 0, restarted every gmres_restart steps,
+// Givens rotations on the host.  Arnoldi by classical Gram-Schmidt applied
+// twice in its delayed form: step j computes V^T [q_j, A q_j] in one pass
+// over the basis, which gives both the second-pass coefficients s of q_j
+// (whose first pass ran in step j-1) and the first-pass coefficients z of
+// A q_j; one more pass then reorthogonalises q_j and projects A q_j.  The
+// column of the Hessenberg matrix that q_j closes is corrected for the
+// change of q_j (H[:, j-1] += H[j, j-1] s, H[j, j-1] *= nu) and only then
+// rotated, so the residual estimate trails the newest product by one step.
+// In exact arithmetic this is the same basis and Hessenberg matrix as
+// Gram-Schmidt applied twice, with two passes over the basis per step
+// instead of four.
 
 struct GmresStats {
-  int iterations = 0;
+  int iterations = 0;           // Krylov dimension reached (summed over cycles)
+  int applies = 0;              // products with the operator
   double rel_residual = 0.0;
   bool converged = false;
 };
 
 // y = A x for the system being solved (precision of the product given).
 using Operator = std::function<int(const double *, double *, int)>;
+
+constexpr int32_t kUpdParts = 1024;   // partial sums of the fused update
 
 int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x, GmresStats &st,
           int precision, double tol, int max_it, hipStream_t s) {
@@ -504,18 +516,24 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
   double *w = pb.d_vec;           // scratch vector
   double *r = pb.d_vec + ld;      // residual
   const int32_t nch = mdot_chunks(n);
-  double *part = pb.d_red;
-  double *h = pb.d_red + (int64_t)nch * (m + 2);
-  double *h2 = h + (m + 2);
-  double *cf = h2 + (m + 2);
-  double *scal = cf + (m + 2);    // [0] = beta, [1] = norm out
-  std::vector<double> hh(m + 2), H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  double *part = pb.d_red;                                // 2 nch (m + 2)
+  double *hd = part + 2 * (int64_t)nch * (m + 2);         // V^T q_j | V^T w, 2 (m + 2)
+  double *coef = hd + 2 * (m + 2);                        // s | z, 2 (m + 2)
+  double *cf = coef + 2 * (m + 2);                        // solution coefficients, m + 2
+  double *scal = cf + (m + 2);                            // [0] norm of p, [1] other norms
+  double *upart = scal + 8;                               // kUpdParts
+  const size_t pin_n = 2 * (size_t)(m + 2) + 8;
   double *hpin = nullptr;
-  SMFS_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * (2 * m + 8), hipHostMallocDefault));
+  SMFS_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * pin_n, hipHostMallocDefault));
   struct Free {
     double *p;
     ~Free() { if (p) (void)hipHostFree(p); }
   } guard{hpin};
+  // Hraw: the Hessenberg matrix as built (column-major, m+1 rows); R: its
+  // rotated copy for the least-squares problem
+  std::vector<double> Hraw((size_t)(m + 1) * m, 0.0), R((size_t)(m + 1) * m, 0.0), cs(m), sn(m),
+      g(m + 1), y(m), cvec(m + 1), sz(2 * (size_t)(m + 2));
+  auto Hc = [&](std::vector<double> &M, int row, int col) -> double & { return M[(size_t)col * (m + 1) + row]; };
 
   SMFS_HIP(launch_fill(n, 0.0, x, s));
   SMFS_HIP(launch_norm2(b, n, part, nch, scal + 1, s));
@@ -529,66 +547,95 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
   }
   SMFS_HIP(hipMemcpyAsync(r, b, 8 * n, hipMemcpyDeviceToDevice, s));
   double beta = bnorm;
-  int total = 0;
   while (true) {
-    // V[0] = r / beta
+    // V[0] = r / beta (final: it needs no second pass)
     SMFS_HIP(hipMemcpyAsync(V, r, 8 * n, hipMemcpyDeviceToDevice, s));
-    SMFS_HIP(launch_norm_scale(V, n, part, nch, scal, scal + 1, s));
+    SMFS_HIP(launch_norm_scale(V, n, part, nch, scal + 1, scal + 2, s));
     std::fill(g.begin(), g.end(), 0.0);
+    std::fill(Hraw.begin(), Hraw.end(), 0.0);
     g[0] = beta;
-    int jdone = 0;
+    int jdone = 0;   // columns of H final in this cycle
     bool stop = false;
-    for (int j = 0; j < m; ++j) {
-      double *vj1 = V + (int64_t)(j + 1) * ld;
-      int rc = op(V + (int64_t)j * ld, vj1, precision);
-      if (rc) return rc;
-      // classical Gram-Schmidt, twice: h = V^T w, w -= V h; h2 = V^T w, w -= V h2
-      // (a second pass only when the norm drops below 1/sqrt(2), the DGKS
-      // criterion, was measured to need the second pass in all but one of
-      // 1575 iterations of the 100-sphere solve, so it is always taken)
-      SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h, false, s));
-      SMFS_HIP(launch_mupdate(V, ld, j + 1, h, vj1, n, s));
-      SMFS_HIP(launch_mdot(V, ld, j + 1, vj1, n, part, nch, h2, false, s));
-      SMFS_HIP(launch_mupdate(V, ld, j + 1, h2, vj1, n, s));
-      SMFS_HIP(launch_norm_scale(vj1, n, part, nch, h + (j + 1), scal + 1, s));
-      SMFS_HIP(hipMemcpyAsync(hpin, h, 8 * (j + 2), hipMemcpyDeviceToHost, s));
-      SMFS_HIP(hipMemcpyAsync(hpin + (m + 2), h2, 8 * (j + 1), hipMemcpyDeviceToHost, s));
-      SMFS_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i <= j + 1; ++i)
-        H[(size_t)j * (m + 1) + i] = hpin[i] + (i <= j ? hpin[m + 2 + i] : 0.0);
-      double *col = &H[(size_t)j * (m + 1)];
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
+    for (int j = 0;; ++j) {
+      const bool last = j == m || (st.applies >= max_it && j > 0);
+      double *qj = V + (int64_t)j * ld, *wj = V + (int64_t)(j + 1) * ld;
+      if (!last) {
+        int rc = op(qj, wj, precision);
+        if (rc) return rc;
+        ++st.applies;
       }
-      const double den = std::hypot(col[j], col[j + 1]);
-      cs[j] = den > 0 ? col[j] / den : 1.0;
-      sn[j] = den > 0 ? col[j + 1] / den : 0.0;
-      col[j] = den;
-      col[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++total;
-      jdone = j + 1;
-      st.rel_residual = std::fabs(g[j + 1]) / bnorm;
-      if (st.rel_residual <= tol) { st.converged = true; stop = true; break; }
-      if (total >= max_it || hpin[j + 1] == 0.0) { stop = true; break; }
+      const int nv = j + 1;
+      SMFS_HIP(launch_mdot2(V, ld, nv, qj, last ? qj : wj, n, part, nch, hd, s));
+      SMFS_HIP(hipMemcpyAsync(hpin, hd, 8 * 2 * (size_t)nv, hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipMemcpyAsync(hpin + 2 * (m + 2), scal, 8, hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipStreamSynchronize(s));
+      const double *sv = hpin, *zv = hpin + nv;   // V^T q_j, V^T w
+      double nu = 1.0;
+      if (j > 0) {
+        double ss = 0.0;
+        for (int i = 0; i < j; ++i) ss += sv[i] * sv[i];
+        const double nu2 = sv[j] - ss;
+        nu = nu2 > 0.0 ? std::sqrt(nu2) : 0.0;
+        // finalise column j-1 (q_j reorthogonalised), rotate it
+        Hc(Hraw, j, j - 1) = hpin[2 * (m + 2)];   // ||p|| of the previous step
+        for (int i = 0; i < j; ++i) Hc(Hraw, i, j - 1) += Hc(Hraw, j, j - 1) * sv[i];
+        Hc(Hraw, j, j - 1) *= nu;
+        const int c = j - 1;
+        for (int i = 0; i <= j; ++i) Hc(R, i, c) = Hc(Hraw, i, c);
+        double *col = &R[(size_t)c * (m + 1)];
+        for (int i = 0; i < c; ++i) {
+          const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+          col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+          col[i] = t;
+        }
+        const double den = std::hypot(col[c], col[c + 1]);
+        cs[c] = den > 0 ? col[c] / den : 1.0;
+        sn[c] = den > 0 ? col[c + 1] / den : 0.0;
+        col[c] = den;
+        col[c + 1] = 0.0;
+        g[c + 1] = -sn[c] * g[c];
+        g[c] = cs[c] * g[c];
+        jdone = j;
+        ++st.iterations;
+        st.rel_residual = std::fabs(g[c + 1]) / bnorm;
+        if (st.rel_residual <= tol) { st.converged = true; stop = true; break; }
+        if (nu == 0.0) { stop = true; break; }   // q_j lies in the span: exact solution
+        if (st.applies >= max_it && last) { stop = true; break; }
+        if (last) break;                          // end of the cycle
+      }
+      // coefficients of the step: s (second pass of q_j), z (first pass of w)
+      double sz_dot = 0.0;
+      for (int i = 0; i < j; ++i) sz_dot += sv[i] * zv[i];
+      const double gam = (zv[j] - sz_dot) / nu;
+      // c = Hraw[0..j, 0..j-1] s: the part of A q_j carried by the old q_j
+      std::fill(cvec.begin(), cvec.begin() + j + 1, 0.0);
+      for (int k = 0; k < j; ++k)
+        for (int i = 0; i <= k + 1; ++i) cvec[i] += Hc(Hraw, i, k) * sv[k];
+      for (int i = 0; i < j; ++i) Hc(Hraw, i, j) = (zv[i] - cvec[i]) / nu;
+      Hc(Hraw, j, j) = (gam - cvec[j]) / nu;
+      for (int i = 0; i < j; ++i) {
+        sz[i] = sv[i];
+        sz[(m + 2) + i] = zv[i];
+      }
+      if (j > 0) SMFS_HIP(hipMemcpyAsync(coef, sz.data(), 8 * 2 * (size_t)(m + 2), hipMemcpyHostToDevice, s));
+      SMFS_HIP(launch_dcgs_update(V, ld, j, coef, coef + (m + 2), qj, wj, nu, gam, n, upart, kUpdParts,
+                                  scal, s));
+      // the host copy of sz must outlive the upload: the next step synchronises first
     }
-    // y = H^-1 g (upper triangular), x += V y
+    // y = R^-1 g (upper triangular), x += V y
     for (int i = jdone - 1; i >= 0; --i) {
       double t = g[i];
-      for (int c = i + 1; c < jdone; ++c) t -= H[(size_t)c * (m + 1) + i] * y[c];
-      y[i] = t / H[(size_t)i * (m + 1) + i];
+      for (int c = i + 1; c < jdone; ++c) t -= Hc(R, i, c) * y[c];
+      y[i] = t / Hc(R, i, i);
     }
     SMFS_HIP(hipMemcpyAsync(cf, y.data(), 8 * jdone, hipMemcpyHostToDevice, s));
     SMFS_HIP(launch_combine(V, ld, jdone, cf, x, n, s));
     SMFS_HIP(hipStreamSynchronize(s));
-    st.iterations = total;
     if (stop) return SMFS_OK;
     // restart from the true residual
     int rc = op(x, w, precision);
     if (rc) return rc;
+    ++st.applies;
     SMFS_HIP(launch_sub(n, b, w, r, s));
     SMFS_HIP(launch_norm2(r, n, part, nch, scal + 1, s));
     SMFS_HIP(hipMemcpyAsync(hpin, scal + 1, 8, hipMemcpyDeviceToHost, s));
@@ -1007,6 +1054,8 @@ int apply_mobility(Problem &pb, const double *x, double *y, int precision, hipSt
 
 struct SolveStats {
   int iterations = 0, refinements = 0;
+  int applies = 0;              // products with the operator, in the solve's precision
+  int applies64 = 0;            // FP64 true-residual products
   bool converged = false;
   double rel_residual = 0.0, res_norm = 0.0, rhs_norm = 0.0;
 };
@@ -1022,6 +1071,7 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
   if (rc) return rc;
   ss = SolveStats{};
   ss.iterations = st.iterations;
+  ss.applies = st.applies;
   ss.converged = st.converged;
   ss.rel_residual = st.rel_residual;
   double *w = pb.d_vec, *r = pb.d_vec + ld, *rr = pb.d_vec + 4 * ld, *d = pb.d_vec + 5 * ld;
@@ -1031,6 +1081,7 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
   while (true) {
     rc = op(x, w, SMFS_FP64);
     if (rc) return rc;
+    ++ss.applies64;
     SMFS_HIP(launch_sub(n, b, w, r, s));
     SMFS_HIP(launch_norm2(r, n, pb.d_red, nch, scal, s));
     SMFS_HIP(launch_norm2(b, n, pb.d_red, nch, scal + 1, s));
@@ -1038,14 +1089,15 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
     SMFS_HIP(hipStreamSynchronize(s));
     const double true_rel = hres[1] > 0 ? hres[0] / hres[1] : 0.0;
     if (precision != SMFS_MIXED || true_rel <= tol || ss.refinements >= 2 ||
-        ss.iterations >= pb.prm.gmres_max_it)
+        ss.applies >= pb.prm.gmres_max_it)
       break;
     SMFS_HIP(hipMemcpyAsync(rr, r, 8 * n, hipMemcpyDeviceToDevice, s));
     const double tol_d = std::min(0.5, std::max(tol, tol / true_rel));
     GmresStats sd;
-    rc = gmres(pb, n, op, rr, d, sd, SMFS_MIXED, tol_d, pb.prm.gmres_max_it - ss.iterations, s);
+    rc = gmres(pb, n, op, rr, d, sd, SMFS_MIXED, tol_d, pb.prm.gmres_max_it - ss.applies, s);
     if (rc) return rc;
     ss.iterations += sd.iterations;
+    ss.applies += sd.applies;
     ss.converged = sd.converged;
     SMFS_HIP(launch_axpby(n, 1.0, d, 1.0, x, s));
     ++ss.refinements;
@@ -1085,9 +1137,9 @@ void fill_out(Problem &pb, const SolveStats &ss, const double *post, int precisi
   out->eps_res_max = (out->u_check && pb.C) ? post[1] : -1.0;
   out->abs_res_max = (out->u_check && pb.C && post[3] > 0) ? post[2] / post[3] : -1.0;
   const bool mixed = precision == SMFS_MIXED && pb.n_free > 0 && pb.fac32_ready;
-  out->pair_evals = (int64_t)(ss.iterations + ss.refinements + 1) * pb.pairs_per_apply +
+  out->pair_evals = (int64_t)(ss.applies + ss.applies64) * pb.pairs_per_apply +
                     ((out->u_check) ? pb.C * pb.S : 0);
-  out->pair_evals_f32 = mixed ? (int64_t)ss.iterations * pb.pairs_f32 : 0;
+  out->pair_evals_f32 = mixed ? (int64_t)ss.applies * pb.pairs_f32 : 0;
 }
 
 }  // namespace smfs

@@ -10,7 +10,10 @@
 namespace smfs {
 
 // Targets per lane of the direct-sum kernels (tiles hold 64 * kDirectTpl).
-constexpr int kDirectTpl = 2;
+#ifndef SMFS_DIRECT_TPL
+#define SMFS_DIRECT_TPL 2
+#endif
+constexpr int kDirectTpl = SMFS_DIRECT_TPL;
 
 // Direct sum over target tiles (Section 2.2, eq. uAll) in FP64: every source
 // in the given ranges of the packed source array, minus the tile's own
@@ -114,6 +117,15 @@ hipError_t launch_norm_scale(double *w, int64_t n, double *part, int32_t nchunks
                              double *out, hipStream_t s);
 // w /= beta[0] (w = 0 when beta[0] = 0); beta on the device
 hipError_t launch_scale(double *w, int64_t n, const double *beta, hipStream_t s);
+// Delayed classical Gram-Schmidt.  out[0..nv) = V^T a, out[nv..2nv) = V^T b
+// over V[0..nv) (part: at least 2 nv nchunks doubles).
+hipError_t launch_mdot2(const double *V, int64_t ld, int32_t nv, const double *a, const double *b,
+                        int64_t n, double *part, int32_t nchunks, double *out, hipStream_t s);
+// q <- (q - V cs) / nu, w <- (w - V cz - q gam) / nu over V[0..nb), then
+// norm[0] = ||w|| and w /= norm[0] (part: nparts doubles).
+hipError_t launch_dcgs_update(const double *V, int64_t ld, int32_t nb, const double *cs,
+                              const double *cz, double *q, double *w, double nu, double gam, int64_t n,
+                              double *part, int32_t nparts, double *norm, hipStream_t s);
 // y = a*x + b*y ; x,y length n (a, b host scalars)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 // y[i] = v

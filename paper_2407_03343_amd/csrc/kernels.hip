@@ -6,6 +6,8 @@
 // rotlets, potential dipoles), sphere-major inside a kind.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace smfs {
@@ -766,6 +768,78 @@ __global__ void k_combine(const double *__restrict__ V, int64_t ld, int32_t nv,
   x[i] += basis_row_dot(V, ld, nv, cf, i);
 }
 
+// Delayed classical Gram-Schmidt (one pass of dot products and one pass of
+// updates per Arnoldi step; the second Gram-Schmidt pass of the previous
+// vector rides along with the first pass of the new one).
+// part[(r * nv + j) * nchunks + c] = chunk c of V[j] . (r ? b : a)
+__global__ __launch_bounds__(kBlock) void k_mdot2(const double *__restrict__ V, int64_t ld,
+                                                  int32_t nv, const double *__restrict__ a,
+                                                  const double *__restrict__ b, int64_t n,
+                                                  int64_t chunk, double *__restrict__ part,
+                                                  int32_t nchunks) {
+  __shared__ double sh[2 * kDotVecs][kWavesPerBlock];
+  const int c = blockIdx.x;
+  const int j0 = blockIdx.y * kDotVecs;
+  const int64_t e0 = (int64_t)c * chunk, e1 = min(n, e0 + chunk);
+  double acc[2 * kDotVecs];
+#pragma unroll
+  for (int q = 0; q < 2 * kDotVecs; ++q) acc[q] = 0.0;
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += kBlock) {
+    const double ai = a[i], bi = b[i];
+#pragma unroll
+    for (int q = 0; q < kDotVecs; ++q)
+      if (j0 + q < nv) {
+        const double v = V[(int64_t)(j0 + q) * ld + i];
+        acc[q] = fma(v, ai, acc[q]);
+        acc[kDotVecs + q] = fma(v, bi, acc[kDotVecs + q]);
+      }
+  }
+  block_sum<2 * kDotVecs>(acc, sh);
+  if (threadIdx.x < 2 * kDotVecs) {
+    const int q = threadIdx.x % kDotVecs, r = threadIdx.x / kDotVecs;
+    if (j0 + q < nv) part[((int64_t)r * nv + j0 + q) * nchunks + c] = acc[threadIdx.x];
+  }
+}
+
+// q <- (q - V cs) / nu ;  w <- (w - V cz - q gam) / nu over V[0..nb), one
+// read of the basis; part[block] = sum of the new w^2 over the block.
+__global__ __launch_bounds__(kBlock) void k_dcgs_update(const double *__restrict__ V, int64_t ld,
+                                                        int32_t nb, const double *__restrict__ cs,
+                                                        const double *__restrict__ cz,
+                                                        double *__restrict__ q,
+                                                        double *__restrict__ w, double inv_nu,
+                                                        double gam, int64_t n,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[1][kWavesPerBlock];
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    double s1[2] = {0.0, 0.0}, s2[2] = {0.0, 0.0};
+    int j = 0;
+    for (; j + 7 < nb; j += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(j + u) * ld + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s1[u & 1] = fma(v[u], cs[j + u], s1[u & 1]);
+        s2[u & 1] = fma(v[u], cz[j + u], s2[u & 1]);
+      }
+    }
+    for (; j < nb; ++j) {
+      const double v = V[(int64_t)j * ld + i];
+      s1[0] = fma(v, cs[j], s1[0]);
+      s2[0] = fma(v, cz[j], s2[0]);
+    }
+    const double qt = (q[i] - (s1[0] + s1[1])) * inv_nu;
+    const double p = ((w[i] - (s2[0] + s2[1])) - qt * gam) * inv_nu;
+    q[i] = qt;
+    w[i] = p;
+    acc[0] = fma(p, p, acc[0]);
+  }
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
 __global__ __launch_bounds__(kBlock) void k_sumsq(const double *__restrict__ w, int64_t n,
                                                   int64_t chunk, double *__restrict__ part) {
   __shared__ double sh[1][kWavesPerBlock];
@@ -979,6 +1053,28 @@ hipError_t launch_norm2(const double *w, int64_t n, double *part, int32_t nchunk
 hipError_t launch_scale(double *w, int64_t n, const double *beta, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, w, n, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_mdot2(const double *V, int64_t ld, int32_t nv, const double *a, const double *b,
+                        int64_t n, double *part, int32_t nchunks, double *out, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  const int64_t chunk = chunk_len(n, nchunks);
+  dim3 grid((unsigned)nchunks, (unsigned)((nv + kDotVecs - 1) / kDotVecs));
+  hipLaunchKernelGGL(k_mdot2, grid, dim3(kBlock), 0, s, V, ld, nv, a, b, n, chunk, part, nchunks);
+  hipLaunchKernelGGL(k_mdot_final, dim3(blocks_for(2 * nv)), dim3(kBlock), 0, s, 2 * nv, part, nchunks,
+                     out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcgs_update(const double *V, int64_t ld, int32_t nb, const double *cs,
+                              const double *cz, double *q, double *w, double nu, double gam, int64_t n,
+                              double *part, int32_t nparts, double *norm, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<int64_t>(nparts, blocks_for(n));
+  hipLaunchKernelGGL(k_dcgs_update, dim3(g), dim3(kBlock), 0, s, V, ld, nb, cs, cz, q, w, 1.0 / nu, gam, n,
+                     part);
+  hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(64), 0, s, part, (int32_t)g, norm, nullptr);
+  hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, w, n, norm);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsmfs.so")
+LIB_PATH = os.environ.get("SMFS_LIB", os.path.join(HERE, "libsmfs.so"))
 
 SMFS_OK = 0
 SMFS_NOT_CONVERGED = 1
