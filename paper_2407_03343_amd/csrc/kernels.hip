@@ -415,15 +415,53 @@ __device__ __forceinline__ void pinv_v_row(const RowTask *__restrict__ tasks, in
   }
 }
 
+// Two consecutive rows j, j+1 of one sphere per wave: the slice of mu is
+// loaded once for both columns of U (same summation order per row as
+// pinv_u_row, so the results are identical).
 __global__ __launch_bounds__(kBlock) void k_pinv_u(const RowTask *__restrict__ tasks, int64_t n,
                                                    const SphereMeta *__restrict__ meta,
                                                    const FactorSlot *__restrict__ fs,
                                                    const double *__restrict__ fac,
                                                    const double *__restrict__ mu,
                                                    double *__restrict__ sbuf) {
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const int64_t t = 2 * ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   if (t >= n) return;
-  pinv_u_row(tasks, t, meta, fs, fac, mu, sbuf);
+  const int k0 = uniform(tasks[t].sphere), j0 = uniform(tasks[t].row);
+  const bool pair = t + 1 < n && uniform(tasks[t + 1].sphere) == k0 && uniform(tasks[t + 1].row) == j0 + 1;
+  if (!pair) {
+    pinv_u_row(tasks, t, meta, fs, fac, mu, sbuf);
+    if (t + 1 < n) pinv_u_row(tasks, t + 1, meta, fs, fac, mu, sbuf);
+    return;
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const SphereMeta &m = meta[k0];
+  const FactorSlot &f = fs[m.fid];
+  const int rows = f.rows;
+  const double *c0 = fac + f.u_off + (int64_t)j0 * rows, *c1 = c0 + rows;
+  const double *x = mu + 3 * m.t0;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  int i = lane;
+  for (; i + 3 * kWave < rows; i += 4 * kWave) {
+    const double x0 = x[i], x1 = x[i + kWave], x2 = x[i + 2 * kWave], x3 = x[i + 3 * kWave];
+    a0 = fma(c0[i], x0, a0);
+    a1 = fma(c0[i + kWave], x1, a1);
+    a2 = fma(c0[i + 2 * kWave], x2, a2);
+    a3 = fma(c0[i + 3 * kWave], x3, a3);
+    b0 = fma(c1[i], x0, b0);
+    b1 = fma(c1[i + kWave], x1, b1);
+    b2 = fma(c1[i + 2 * kWave], x2, b2);
+    b3 = fma(c1[i + 3 * kWave], x3, b3);
+  }
+  for (; i < rows; i += kWave) {
+    a0 = fma(c0[i], x[i], a0);
+    b0 = fma(c1[i], x[i], b0);
+  }
+  const double s0 = wave_sum((a0 + a1) + (a2 + a3));
+  const double s1 = wave_sum((b0 + b1) + (b2 + b3));
+  if (lane == 0) {
+    sbuf[m.s0 + j0] = s0 / fac[f.sig_off + j0];
+    sbuf[m.s0 + j0 + 1] = s1 / fac[f.sig_off + j0 + 1];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_pinv_v(const RowTask *__restrict__ tasks, int64_t n,
@@ -772,31 +810,33 @@ __global__ void k_combine(const double *__restrict__ V, int64_t ld, int32_t nv,
 // updates per Arnoldi step; the second Gram-Schmidt pass of the previous
 // vector rides along with the first pass of the new one).
 // part[(r * nv + j) * nchunks + c] = chunk c of V[j] . (r ? b : a)
+constexpr int kDot2Vecs = 16;   // basis vectors per block of the two-vector dot products
+
 __global__ __launch_bounds__(kBlock) void k_mdot2(const double *__restrict__ V, int64_t ld,
                                                   int32_t nv, const double *__restrict__ a,
                                                   const double *__restrict__ b, int64_t n,
                                                   int64_t chunk, double *__restrict__ part,
                                                   int32_t nchunks) {
-  __shared__ double sh[2 * kDotVecs][kWavesPerBlock];
+  __shared__ double sh[2 * kDot2Vecs][kWavesPerBlock];
   const int c = blockIdx.x;
-  const int j0 = blockIdx.y * kDotVecs;
+  const int j0 = blockIdx.y * kDot2Vecs;
   const int64_t e0 = (int64_t)c * chunk, e1 = min(n, e0 + chunk);
-  double acc[2 * kDotVecs];
+  double acc[2 * kDot2Vecs];
 #pragma unroll
-  for (int q = 0; q < 2 * kDotVecs; ++q) acc[q] = 0.0;
+  for (int q = 0; q < 2 * kDot2Vecs; ++q) acc[q] = 0.0;
   for (int64_t i = e0 + threadIdx.x; i < e1; i += kBlock) {
     const double ai = a[i], bi = b[i];
 #pragma unroll
-    for (int q = 0; q < kDotVecs; ++q)
+    for (int q = 0; q < kDot2Vecs; ++q)
       if (j0 + q < nv) {
         const double v = V[(int64_t)(j0 + q) * ld + i];
         acc[q] = fma(v, ai, acc[q]);
-        acc[kDotVecs + q] = fma(v, bi, acc[kDotVecs + q]);
+        acc[kDot2Vecs + q] = fma(v, bi, acc[kDot2Vecs + q]);
       }
   }
-  block_sum<2 * kDotVecs>(acc, sh);
-  if (threadIdx.x < 2 * kDotVecs) {
-    const int q = threadIdx.x % kDotVecs, r = threadIdx.x / kDotVecs;
+  block_sum<2 * kDot2Vecs>(acc, sh);
+  if (threadIdx.x < 2 * kDot2Vecs) {
+    const int q = threadIdx.x % kDot2Vecs, r = threadIdx.x / kDot2Vecs;
     if (j0 + q < nv) part[((int64_t)r * nv + j0 + q) * nchunks + c] = acc[threadIdx.x];
   }
 }
@@ -850,14 +890,18 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(const double *__restrict__ w, 
   if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
 }
 
-__global__ void k_sqrt_final(const double *__restrict__ part, int32_t nchunks, double *beta,
-                             double *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += part[c];
-  s = sqrt(s);
-  if (beta) beta[0] = s;
-  if (out) out[0] = s;
+// One block: beta[0] = out[0] = sqrt(sum of the nchunks partial sums).
+__global__ __launch_bounds__(kBlock) void k_sqrt_final(const double *__restrict__ part,
+                                                       int32_t nchunks, double *beta, double *out) {
+  __shared__ double sh[1][kWavesPerBlock];
+  double acc[1] = {0.0};
+  for (int c = threadIdx.x; c < nchunks; c += kBlock) acc[0] += part[c];
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) {
+    const double s = sqrt(acc[0]);
+    if (beta) beta[0] = s;
+    if (out) out[0] = s;
+  }
 }
 
 __global__ void k_scale(double *__restrict__ w, int64_t n, const double *__restrict__ beta) {
@@ -953,8 +997,8 @@ hipError_t launch_pinv_u(const RowTask *tasks, int64_t n, const SphereMeta *meta
                          const FactorSlot *fs, const double *fac, const double *mu, double *sbuf,
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pinv_u, dim3(blocks_for(n, kWavesPerBlock)), dim3(kBlock), 0, s, tasks, n,
-                     meta, fs, fac, mu, sbuf);
+  hipLaunchKernelGGL(k_pinv_u, dim3(blocks_for((n + 1) / 2, kWavesPerBlock)), dim3(kBlock), 0, s, tasks,
+                     n, meta, fs, fac, mu, sbuf);
   return hipGetLastError();
 }
 
@@ -1046,7 +1090,7 @@ hipError_t launch_norm2(const double *w, int64_t n, double *part, int32_t nchunk
                         hipStream_t s) {
   const int64_t chunk = chunk_len(n, nchunks);
   hipLaunchKernelGGL(k_sumsq, dim3(nchunks), dim3(kBlock), 0, s, w, n, chunk, part);
-  hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(64), 0, s, part, nchunks, (double *)nullptr, out);
+  hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(kBlock), 0, s, part, nchunks, (double *)nullptr, out);
   return hipGetLastError();
 }
 
@@ -1060,7 +1104,7 @@ hipError_t launch_mdot2(const double *V, int64_t ld, int32_t nv, const double *a
                         int64_t n, double *part, int32_t nchunks, double *out, hipStream_t s) {
   if (nv <= 0) return hipSuccess;
   const int64_t chunk = chunk_len(n, nchunks);
-  dim3 grid((unsigned)nchunks, (unsigned)((nv + kDotVecs - 1) / kDotVecs));
+  dim3 grid((unsigned)nchunks, (unsigned)((nv + kDot2Vecs - 1) / kDot2Vecs));
   hipLaunchKernelGGL(k_mdot2, grid, dim3(kBlock), 0, s, V, ld, nv, a, b, n, chunk, part, nchunks);
   hipLaunchKernelGGL(k_mdot_final, dim3(blocks_for(2 * nv)), dim3(kBlock), 0, s, 2 * nv, part, nchunks,
                      out, 0);
@@ -1073,7 +1117,7 @@ hipError_t launch_dcgs_update(const double *V, int64_t ld, int32_t nb, const dou
   const unsigned g = (unsigned)std::min<int64_t>(nparts, blocks_for(n));
   hipLaunchKernelGGL(k_dcgs_update, dim3(g), dim3(kBlock), 0, s, V, ld, nb, cs, cz, q, w, 1.0 / nu, gam, n,
                      part);
-  hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(64), 0, s, part, (int32_t)g, norm, nullptr);
+  hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(kBlock), 0, s, part, (int32_t)g, norm, nullptr);
   hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, w, n, norm);
   return hipGetLastError();
 }
@@ -1082,7 +1126,7 @@ hipError_t launch_norm_scale(double *w, int64_t n, double *part, int32_t nchunks
                              double *out, hipStream_t s) {
   const int64_t chunk = chunk_len(n, nchunks);
   hipLaunchKernelGGL(k_sumsq, dim3(nchunks), dim3(kBlock), 0, s, w, n, chunk, part);
-  hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(64), 0, s, part, nchunks, beta, out);
+  hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(kBlock), 0, s, part, nchunks, beta, out);
   hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, w, n, beta);
   return hipGetLastError();
 }
