@@ -66,9 +66,13 @@ def cpu_baseline(pk, stride: int):
                         f"{pairs:.3g} pairs in {dt:.1f} s"))
 
 
+FORMS = (("fp64", 0), ("mixed", 1), ("mixed_far", 2))   # SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR
+
+
 def mixed_vs_fp64(args, torch, smfs, wl):
     """Solve time to 1e-3 relative surface velocity, plain FP64 against the
-    mixed form, on a cut of the volume-fraction-0.3 packing with 5% of the
+    mixed forms (FP32 pseudo-inverse and far field; FP32 far field only), on
+    a cut of the volume-fraction-0.3 packing with 5% of the
     spheres in near-contact pairs.  The reference is the FP64 solve at
     tolerance 1e-10; for each form the fastest GMRES tolerance whose
     check-point velocities meet 1e-3 (relative to the largest) is reported,
@@ -90,7 +94,7 @@ def mixed_vs_fp64(args, torch, smfs, wl):
     out = {"spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S,
            "pairs_per_apply": pb.pairs_per_apply, "reference_iterations": ref["iterations"],
            "setup_s": setup_s, "forms": {}}
-    for name, prec in (("fp64", smfs.SMFS_FP64), ("mixed", smfs.SMFS_MIXED)):
+    for name, prec in FORMS:
         rows = []
         for tol in args.mixed_tols:
             pb.set_solver(prec, tol)
@@ -118,7 +122,7 @@ def mixed_vs_fp64(args, torch, smfs, wl):
     # the surface-velocity target above
     ft = torch.from_numpy(wl.random_ft(pb.P, 1, 78)[0].reshape(-1)).cuda()
     out["mobility"] = {}
-    for name, prec in (("fp64", smfs.SMFS_FP64), ("mixed", smfs.SMFS_MIXED)):
+    for name, prec in FORMS:
         best = out["forms"][name]["at_1e-3_surface_velocity"]
         tol = best["tol"] if best else 1e-6
         pb.set_solver(prec, tol)
@@ -130,9 +134,12 @@ def mixed_vs_fp64(args, torch, smfs, wl):
                                      true_rel_residual=o["true_rel_residual"], converged=o["converged"])
         log(f"  mobility {name} tol {tol:.0e}: it {o['iterations']}, {out['mobility'][name]['solve_ms']:.1f} ms")
     f64 = out["forms"]["fp64"]["at_1e-3_surface_velocity"]
-    mx = out["forms"]["mixed"]["at_1e-3_surface_velocity"]
-    if f64 and mx:
-        out["speedup_mixed_over_fp64"] = f64["solve_ms_p50"] / mx["solve_ms_p50"]
+    for name, _ in FORMS[1:]:
+        mx = out["forms"][name]["at_1e-3_surface_velocity"]
+        if f64 and mx:
+            out[f"speedup_{name}_over_fp64"] = f64["solve_ms_p50"] / mx["solve_ms_p50"]
+        mb = out["mobility"]
+        out[f"mobility_speedup_{name}_over_fp64"] = mb["fp64"]["solve_ms"] / mb[name]["solve_ms"]
     return out
 
 
@@ -393,6 +400,7 @@ def main():
     ap.add_argument("--serve-sequential", type=int, default=3,
                     help="requests solved one after another for the comparison")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving comparison")
+    ap.add_argument("--mixed-only", action="store_true", help="run only the mixed-vs-FP64 comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -407,6 +415,9 @@ def main():
         reqs, arrivals = serving_requests(args)
     if args.serve_only:
         print(json.dumps({"serving": serving(args, torch, smfs, reqs, arrivals)}), flush=True)
+        return
+    if args.mixed_only:
+        print(json.dumps({"mixed_vs_fp64": mixed_vs_fp64(args, torch, smfs, wl)}), flush=True)
         return
     pk, _ = wl.workload_cluster100(args.seed)
     log(f"workload: {pk.P} spheres, box {pk.box:.2f}, min gap {pk.min_gaps().min():.2e}")

@@ -60,7 +60,12 @@ enum {
   SMFS_E_STATE = -7                /* call out of order (e.g. apply before setup) */
 };
 
-enum { SMFS_FP64 = 0, SMFS_MIXED = 1 };
+/* Precision of the products inside GMRES.  SMFS_MIXED: the sources of
+ * contact-free spheres in FP32, both their pseudo-inverse apply (FP32 copy
+ * of the shared factor) and their pair sums.  SMFS_MIXED_FAR: their pair
+ * sums in FP32 from strengths computed in FP64 (the pseudo-inverse stays
+ * FP64).  Everything else is FP64 in all modes. */
+enum { SMFS_FP64 = 0, SMFS_MIXED = 1, SMFS_MIXED_FAR = 2 };
 enum { SMFS_KIND_S = 1, SMFS_KIND_R = 2, SMFS_KIND_D = 4 };
 
 /* Discretisation and solver parameters (lengths in radii). */
@@ -82,7 +87,7 @@ typedef struct smfs_params {
   double trunc_rel;         /* singular values kept if > trunc_rel * sigma_1 */
   double mu;                /* viscosity */
   int32_t n_check_base;     /* residual check points per sphere */
-  int32_t precision;        /* SMFS_FP64 or SMFS_MIXED */
+  int32_t precision;        /* SMFS_FP64, SMFS_MIXED or SMFS_MIXED_FAR */
   double gmres_tol;         /* relative residual target */
   int32_t gmres_max_it;
   int32_t gmres_restart;    /* Krylov vectors kept (sizes the workspace) */
@@ -166,7 +171,8 @@ int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double
 
 /* One product y = G_hat mu (eq. resistance): lambda_hat = V S^-1 U^T mu per
  * sphere, then y_k = mu_k + W_k sum_{k' != k} G^(kk') lambda_hat_k'.
- * mu, y [dev] 3 T (must not alias).  precision SMFS_FP64 or SMFS_MIXED. */
+ * mu, y [dev] 3 T (must not alias).  precision SMFS_FP64, SMFS_MIXED or
+ * SMFS_MIXED_FAR. */
 int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision,
                smfs_stream stream);
 
@@ -186,17 +192,17 @@ int smfs_eval_velocity(smfs_problem *pb, const double *lambda, int64_t n, const 
 
 /* Resistance solve: rbm [dev] P x 6 rigid-body velocities in, outputs per
  * smfs_out.  Returns NOT_CONVERGED (warning) if gmres_max_it is reached.
- * With params.precision = SMFS_MIXED the products inside GMRES take the
- * sources of contact-free spheres (pseudo-inverse and pair sums) in FP32
- * and everything else in FP64; Arnoldi, the true residual, up to two
- * refinement sweeps on the FP64 residual, the back-transform and the
- * forces stay in FP64. */
+ * With params.precision = SMFS_MIXED (or SMFS_MIXED_FAR) the products
+ * inside GMRES take the sources of contact-free spheres in FP32 as described
+ * at the precision modes, everything else in FP64; Arnoldi, the true
+ * residual, up to two refinement sweeps on the FP64 residual, the
+ * back-transform and the forces stay in FP64. */
 int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out,
                           smfs_stream stream);
 
 /* Change the solver settings of a problem after creation (the Krylov
  * restart length sizes the workspace and cannot change).  precision is
- * SMFS_FP64 or SMFS_MIXED; gmres_max_it > 0; gmres_tol > 0. */
+ * one of the modes above; gmres_max_it > 0; gmres_tol > 0. */
 int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32_t gmres_max_it);
 
 /* Mobility solve (forces and torques in, rigid motions out; the paper

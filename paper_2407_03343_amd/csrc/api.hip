@@ -52,6 +52,9 @@ int32_t direct_splits(int64_t n_tiles, int64_t S) { return choose_splits(n_tiles
 
 void set_error(const std::string &msg) { g_err = msg; }
 
+bool valid_precision(int p) { return p == SMFS_FP64 || p == SMFS_MIXED || p == SMFS_MIXED_FAR; }
+bool is_mixed(int p) { return p == SMFS_MIXED || p == SMFS_MIXED_FAR; }
+
 void build_tiles(const Problem &pb, std::vector<int4> &tiles, int tt) {
   tiles.clear();
   for (int k = 0; k < pb.P; ++k) {
@@ -410,7 +413,7 @@ int record_event(Problem &pb, hipStream_t s, size_t &idx) {
 // FP32 pseudo-inverse and the FP32 far-field kernel; contact spheres, with
 // their image lines, stay FP64 throughout.
 int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s) {
-  const bool mixed = precision == SMFS_MIXED && pb.n_free > 0 && pb.fac32_ready;
+  const bool mixed = is_mixed(precision) && pb.n_free > 0 && pb.fac32_ready;
   size_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
   int rc;
   if (pb.prof && (rc = record_event(pb, s, e0))) return rc;
@@ -418,6 +421,11 @@ int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s
   const double ds = 2.0 * pb.prm.mu;
   if (!mixed) {
     rc = transform64(pb, mu, pb.d_lamhat, ds, s);
+  } else if (precision == SMFS_MIXED_FAR) {
+    // FP64 strengths everywhere, then an FP32 copy of the proxy strengths
+    // (block 0) for the far-field kernel
+    rc = transform64(pb, mu, pb.d_lamhat, ds, s);
+    SMFS_HIP(launch_to_f32(3 * pb.nb[0], pb.d_lamhat, pb.d_str32, s));
   } else {
     rc = transform_tasks(pb, mu, pb.d_lamhat, pb.n_utask_c, pb.n_vtask_c, ds, s);
     const int64_t off0 = pb.factors[0].u_off;   // FP32 copy holds factor 0 only
@@ -693,7 +701,7 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
   if (p->n_proxy <= 0 || p->n_colloc_base <= 0 || p->gmres_restart > 20000 || !(p->proxy_radius > 0 && p->proxy_radius < 1) ||
       !(p->mu > 0) || !(p->trunc_rel >= 0) || p->gmres_restart <= 0 || p->gmres_max_it <= 0 ||
       p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 ||
-      (p->precision != SMFS_FP64 && p->precision != SMFS_MIXED)) {
+      !valid_precision(p->precision)) {
     set_error("smfs_problem_create: invalid parameter");
     return SMFS_E_INVALID_ARG;
   }
@@ -920,7 +928,7 @@ int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double
 int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision, smfs_stream stream) {
   SMFS_READY(pb);
   if (!mu || !y || mu == y) { set_error("smfs_apply: bad vectors"); return SMFS_E_INVALID_ARG; }
-  if (precision != SMFS_FP64 && precision != SMFS_MIXED) { set_error("bad precision"); return SMFS_E_INVALID_ARG; }
+  if (!valid_precision(precision)) { set_error("bad precision"); return SMFS_E_INVALID_ARG; }
   return apply(*pb, mu, y, precision, (hipStream_t)stream);
 }
 
@@ -954,7 +962,7 @@ int smfs_eval_velocity(smfs_problem *pb, const double *lam, int64_t n, const dou
 int64_t smfs_pairs_per_apply(const smfs_problem *pb) { return pb ? pb->pairs_per_apply : 0; }
 
 int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32_t gmres_max_it) {
-  if (!pb || (precision != SMFS_FP64 && precision != SMFS_MIXED) || !(gmres_tol > 0) ||
+  if (!pb || !valid_precision(precision) || !(gmres_tol > 0) ||
       gmres_max_it <= 0) {
     set_error("smfs_set_solver: bad argument");
     return SMFS_E_INVALID_ARG;
@@ -1088,13 +1096,13 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
     SMFS_HIP(hipMemcpyAsync(hres, scal, 16, hipMemcpyDeviceToHost, s));
     SMFS_HIP(hipStreamSynchronize(s));
     const double true_rel = hres[1] > 0 ? hres[0] / hres[1] : 0.0;
-    if (precision != SMFS_MIXED || true_rel <= tol || ss.refinements >= 2 ||
+    if (!is_mixed(precision) || true_rel <= tol || ss.refinements >= 2 ||
         ss.applies >= pb.prm.gmres_max_it)
       break;
     SMFS_HIP(hipMemcpyAsync(rr, r, 8 * n, hipMemcpyDeviceToDevice, s));
     const double tol_d = std::min(0.5, std::max(tol, tol / true_rel));
     GmresStats sd;
-    rc = gmres(pb, n, op, rr, d, sd, SMFS_MIXED, tol_d, pb.prm.gmres_max_it - ss.applies, s);
+    rc = gmres(pb, n, op, rr, d, sd, precision, tol_d, pb.prm.gmres_max_it - ss.applies, s);
     if (rc) return rc;
     ss.iterations += sd.iterations;
     ss.applies += sd.applies;
@@ -1136,7 +1144,7 @@ void fill_out(Problem &pb, const SolveStats &ss, const double *post, int precisi
   out->lambda_inf = post[0];
   out->eps_res_max = (out->u_check && pb.C) ? post[1] : -1.0;
   out->abs_res_max = (out->u_check && pb.C && post[3] > 0) ? post[2] / post[3] : -1.0;
-  const bool mixed = precision == SMFS_MIXED && pb.n_free > 0 && pb.fac32_ready;
+  const bool mixed = is_mixed(precision) && pb.n_free > 0 && pb.fac32_ready;
   out->pair_evals = (int64_t)(ss.applies + ss.applies64) * pb.pairs_per_apply +
                     ((out->u_check) ? pb.C * pb.S : 0);
   out->pair_evals_f32 = mixed ? (int64_t)ss.applies * pb.pairs_f32 : 0;

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("SMFS_LIB", os.path.join(HERE, "libsmfs.so"))
 SMFS_OK = 0
 SMFS_NOT_CONVERGED = 1
 SMFS_GAP_BELOW_VALIDATED = 2
-SMFS_FP64, SMFS_MIXED = 0, 1
+SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR = 0, 1, 2
 KIND_S, KIND_R, KIND_D = 1, 2, 4
 
 EXPORTED = [
