@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the volume-fraction-0.3 packing")
     ap.add_argument("--mixed-spheres", type=int, default=200)
-    ap.add_argument("--mixed-tols", type=float, nargs="+", default=[1e-4, 3e-5, 1e-5, 3e-6, 1e-6],
+    ap.add_argument("--mixed-tols", type=float, nargs="+", default=[3e-5, 1e-5, 3e-6, 1e-6],
                     help="GMRES tolerances scanned for the 1e-3 surface-velocity target")
     ap.add_argument("--mixed-reps", type=int, default=1, help="timed solves per tolerance")
     ap.add_argument("--apply-only", type=int, default=0, metavar="N",
@@ -387,7 +387,7 @@ def main():
     ap.add_argument("--block-tol", type=float, default=1e-8)
     ap.add_argument("--block-max-it", type=int, default=3000)
     ap.add_argument("--block-sequential", type=int, default=4)
-    ap.add_argument("--serve-requests", type=int, default=24,
+    ap.add_argument("--serve-requests", type=int, default=20,
                     help="requests of the serving stream (the full stream is 512)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=64)
