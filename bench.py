@@ -119,8 +119,11 @@ def mixed_vs_fp64(args, torch, smfs, wl):
         best = min(ok, key=lambda r: r["solve_ms_p50"]) if ok else None
         out["forms"][name] = {"scan": rows, "at_1e-3_surface_velocity": best}
     # mobility (forces and torques in), each form at the tolerance that met
-    # the surface-velocity target above
+    # the surface-velocity target above; error of the rigid motions against
+    # the FP64 mobility solve at 1e-10
     ft = torch.from_numpy(wl.random_ft(pb.P, 1, 78)[0].reshape(-1)).cuda()
+    pb.set_solver(smfs.SMFS_FP64, 1e-10)
+    v_ref = pb.solve_mobility(ft)["rbm"].cpu().numpy()
     out["mobility"] = {}
     for name, prec in FORMS:
         best = out["forms"][name]["at_1e-3_surface_velocity"]
@@ -129,10 +132,13 @@ def mixed_vs_fp64(args, torch, smfs, wl):
         t1 = time.perf_counter()
         o = pb.solve_mobility(ft)
         torch.cuda.synchronize()
+        solve_ms = (time.perf_counter() - t1) * 1e3
+        dv = float(np.abs(o["rbm"].cpu().numpy() - v_ref).max() / np.abs(v_ref).max())
         out["mobility"][name] = dict(tol=tol, iterations=o["iterations"], refinements=o["refinements"],
-                                     solve_ms=(time.perf_counter() - t1) * 1e3,
-                                     true_rel_residual=o["true_rel_residual"], converged=o["converged"])
-        log(f"  mobility {name} tol {tol:.0e}: it {o['iterations']}, {out['mobility'][name]['solve_ms']:.1f} ms")
+                                     solve_ms=solve_ms,
+                                     true_rel_residual=o["true_rel_residual"], converged=o["converged"],
+                                     rbm_rel_err=dv)
+        log(f"  mobility {name} tol {tol:.0e}: it {o['iterations']}, {solve_ms:.1f} ms, V err {dv:.2e}")
     f64 = out["forms"]["fp64"]["at_1e-3_surface_velocity"]
     for name, _ in FORMS[1:]:
         mx = out["forms"][name]["at_1e-3_surface_velocity"]
