@@ -107,16 +107,11 @@ hipError_t launch_assemble_block(const double *tgt, const double *sw, const doub
                                  const SphereMeta *meta, int32_t k, int64_t M, int64_t N, double mu,
                                  double *B, hipStream_t s);
 
-// GMRES helpers on a Krylov basis stored as nv vectors of stride ld.
-// part must hold nchunks * nv doubles; h gets nv entries (added when acc).
-hipError_t launch_mdot(const double *V, int64_t ld, int32_t nv, const double *w, int64_t n,
-                       double *part, int32_t nchunks, double *h, bool acc, hipStream_t s);
-hipError_t launch_mupdate(const double *V, int64_t ld, int32_t nv, const double *h, double *w,
-                          int64_t n, hipStream_t s);
+// GMRES helpers on a Krylov basis stored as vectors of stride ld.
+// beta[0] = ||w|| (and out[0], unless null), then w /= ||w||, or w = 0 when
+// ||w|| = 0 (part: nchunks doubles).
 hipError_t launch_norm_scale(double *w, int64_t n, double *part, int32_t nchunks, double *beta,
                              double *out, hipStream_t s);
-// w /= beta[0] (w = 0 when beta[0] = 0); beta on the device
-hipError_t launch_scale(double *w, int64_t n, const double *beta, hipStream_t s);
 // Delayed classical Gram-Schmidt.  out[0..nv) = V^T a, out[nv..2nv) = V^T b
 // over V[0..nv) (part: at least 2 nv nchunks doubles).
 hipError_t launch_mdot2(const double *V, int64_t ld, int32_t nv, const double *a, const double *b,

@@ -743,28 +743,6 @@ __global__ void k_assemble(const double *__restrict__ tgt, const double *__restr
 
 constexpr int kDotVecs = 8;
 
-__global__ __launch_bounds__(kBlock) void k_mdot(const double *__restrict__ V, int64_t ld,
-                                                 int32_t nv, const double *__restrict__ w,
-                                                 int64_t n, int64_t chunk,
-                                                 double *__restrict__ part, int32_t nchunks) {
-  __shared__ double sh[kDotVecs][kWavesPerBlock];
-  const int c = blockIdx.x;
-  const int j0 = blockIdx.y * kDotVecs;
-  const int64_t b = (int64_t)c * chunk, e = min(n, b + chunk);
-  double acc[kDotVecs];
-#pragma unroll
-  for (int q = 0; q < kDotVecs; ++q) acc[q] = 0.0;
-  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
-    const double wi = w[i];
-#pragma unroll
-    for (int q = 0; q < kDotVecs; ++q)
-      if (j0 + q < nv) acc[q] = fma(V[(int64_t)(j0 + q) * ld + i], wi, acc[q]);
-  }
-  block_sum<kDotVecs>(acc, sh);
-  if (threadIdx.x < kDotVecs && j0 + (int)threadIdx.x < nv)
-    part[(int64_t)(j0 + threadIdx.x) * nchunks + c] = acc[threadIdx.x];
-}
-
 __global__ void k_mdot_final(int32_t nv, const double *__restrict__ part, int32_t nchunks,
                              double *__restrict__ h, int acc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -790,13 +768,6 @@ __device__ __forceinline__ double basis_row_dot(const double *__restrict__ V, in
   }
   for (; j < nv; ++j) s[0] = fma(V[(int64_t)j * ld + i], c[j], s[0]);
   return (s[0] + s[1]) + (s[2] + s[3]);
-}
-
-__global__ void k_mupdate(const double *__restrict__ V, int64_t ld, int32_t nv,
-                          const double *__restrict__ h, double *__restrict__ w, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  w[i] -= basis_row_dot(V, ld, nv, h, i);
 }
 
 __global__ void k_combine(const double *__restrict__ V, int64_t ld, int32_t nv,
@@ -1061,24 +1032,6 @@ hipError_t launch_assemble_block(const double *tgt, const double *sw, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_mdot(const double *V, int64_t ld, int32_t nv, const double *w, int64_t n,
-                       double *part, int32_t nchunks, double *h, bool acc, hipStream_t s) {
-  if (nv <= 0) return hipSuccess;
-  const int64_t chunk = chunk_len(n, nchunks);
-  dim3 grid((unsigned)nchunks, (unsigned)((nv + kDotVecs - 1) / kDotVecs));
-  hipLaunchKernelGGL(k_mdot, grid, dim3(kBlock), 0, s, V, ld, nv, w, n, chunk, part, nchunks);
-  hipLaunchKernelGGL(k_mdot_final, dim3(blocks_for(nv)), dim3(kBlock), 0, s, nv, part, nchunks, h,
-                     acc ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_mupdate(const double *V, int64_t ld, int32_t nv, const double *h, double *w,
-                          int64_t n, hipStream_t s) {
-  if (nv <= 0 || n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mupdate, dim3(blocks_for(n)), dim3(kBlock), 0, s, V, ld, nv, h, w, n);
-  return hipGetLastError();
-}
-
 hipError_t launch_combine(const double *V, int64_t ld, int32_t nv, const double *c, double *x,
                           int64_t n, hipStream_t s) {
   if (nv <= 0 || n == 0) return hipSuccess;
@@ -1091,12 +1044,6 @@ hipError_t launch_norm2(const double *w, int64_t n, double *part, int32_t nchunk
   const int64_t chunk = chunk_len(n, nchunks);
   hipLaunchKernelGGL(k_sumsq, dim3(nchunks), dim3(kBlock), 0, s, w, n, chunk, part);
   hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(kBlock), 0, s, part, nchunks, (double *)nullptr, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale(double *w, int64_t n, const double *beta, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, w, n, beta);
   return hipGetLastError();
 }
 
