@@ -415,52 +415,59 @@ __device__ __forceinline__ void pinv_v_row(const RowTask *__restrict__ tasks, in
   }
 }
 
-// Two consecutive rows j, j+1 of one sphere per wave: the slice of mu is
-// loaded once for both columns of U (same summation order per row as
-// pinv_u_row, so the results are identical).
+// kPinvRows consecutive rows j.. of one sphere per wave: the slice of mu is
+// loaded once for all of them (same summation order per row as
+// pinv_u_row, so the results are identical).  Groups that straddle a sphere
+// fall back to one row at a time.
+constexpr int kPinvRows = 2;   // 4 measured no faster
+
 __global__ __launch_bounds__(kBlock) void k_pinv_u(const RowTask *__restrict__ tasks, int64_t n,
                                                    const SphereMeta *__restrict__ meta,
                                                    const FactorSlot *__restrict__ fs,
                                                    const double *__restrict__ fac,
                                                    const double *__restrict__ mu,
                                                    double *__restrict__ sbuf) {
-  const int64_t t = 2 * ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  const int64_t t = kPinvRows * ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   if (t >= n) return;
   const int k0 = uniform(tasks[t].sphere), j0 = uniform(tasks[t].row);
-  const bool pair = t + 1 < n && uniform(tasks[t + 1].sphere) == k0 && uniform(tasks[t + 1].row) == j0 + 1;
-  if (!pair) {
-    pinv_u_row(tasks, t, meta, fs, fac, mu, sbuf);
-    if (t + 1 < n) pinv_u_row(tasks, t + 1, meta, fs, fac, mu, sbuf);
+  bool fused = t + kPinvRows <= n;
+  if (fused) {
+    const RowTask last = tasks[t + kPinvRows - 1];
+    fused = uniform(last.sphere) == k0 && uniform(last.row) == j0 + kPinvRows - 1;
+  }
+  if (!fused) {
+    for (int r = 0; r < kPinvRows && t + r < n; ++r) pinv_u_row(tasks, t + r, meta, fs, fac, mu, sbuf);
     return;
   }
   const int lane = threadIdx.x & (kWave - 1);
   const SphereMeta &m = meta[k0];
   const FactorSlot &f = fs[m.fid];
   const int rows = f.rows;
-  const double *c0 = fac + f.u_off + (int64_t)j0 * rows, *c1 = c0 + rows;
+  const double *c0 = fac + f.u_off + (int64_t)j0 * rows;
   const double *x = mu + 3 * m.t0;
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  double a[kPinvRows][4];
+#pragma unroll
+  for (int r = 0; r < kPinvRows; ++r) a[r][0] = a[r][1] = a[r][2] = a[r][3] = 0.0;
   int i = lane;
   for (; i + 3 * kWave < rows; i += 4 * kWave) {
-    const double x0 = x[i], x1 = x[i + kWave], x2 = x[i + 2 * kWave], x3 = x[i + 3 * kWave];
-    a0 = fma(c0[i], x0, a0);
-    a1 = fma(c0[i + kWave], x1, a1);
-    a2 = fma(c0[i + 2 * kWave], x2, a2);
-    a3 = fma(c0[i + 3 * kWave], x3, a3);
-    b0 = fma(c1[i], x0, b0);
-    b1 = fma(c1[i + kWave], x1, b1);
-    b2 = fma(c1[i + 2 * kWave], x2, b2);
-    b3 = fma(c1[i + 3 * kWave], x3, b3);
+    double xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = x[i + u * kWave];
+#pragma unroll
+    for (int r = 0; r < kPinvRows; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[r][u] = fma(c0[(int64_t)r * rows + i + u * kWave], xv[u], a[r][u]);
   }
   for (; i < rows; i += kWave) {
-    a0 = fma(c0[i], x[i], a0);
-    b0 = fma(c1[i], x[i], b0);
+    const double xi = x[i];
+#pragma unroll
+    for (int r = 0; r < kPinvRows; ++r) a[r][0] = fma(c0[(int64_t)r * rows + i], xi, a[r][0]);
   }
-  const double s0 = wave_sum((a0 + a1) + (a2 + a3));
-  const double s1 = wave_sum((b0 + b1) + (b2 + b3));
-  if (lane == 0) {
-    sbuf[m.s0 + j0] = s0 / fac[f.sig_off + j0];
-    sbuf[m.s0 + j0 + 1] = s1 / fac[f.sig_off + j0 + 1];
+#pragma unroll
+  for (int r = 0; r < kPinvRows; ++r) {
+    // rows whose tasks were checked: j0 .. j0 + kPinvRows - 1 of sphere k0
+    const double sr = wave_sum((a[r][0] + a[r][1]) + (a[r][2] + a[r][3]));
+    if (lane == 0) sbuf[m.s0 + j0 + r] = sr / fac[f.sig_off + j0 + r];
   }
 }
 
@@ -968,8 +975,8 @@ hipError_t launch_pinv_u(const RowTask *tasks, int64_t n, const SphereMeta *meta
                          const FactorSlot *fs, const double *fac, const double *mu, double *sbuf,
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pinv_u, dim3(blocks_for((n + 1) / 2, kWavesPerBlock)), dim3(kBlock), 0, s, tasks,
-                     n, meta, fs, fac, mu, sbuf);
+  hipLaunchKernelGGL(k_pinv_u, dim3(blocks_for((n + kPinvRows - 1) / kPinvRows, kWavesPerBlock)),
+                     dim3(kBlock), 0, s, tasks, n, meta, fs, fac, mu, sbuf);
   return hipGetLastError();
 }
 
