@@ -129,8 +129,11 @@ struct Acc {
 template <int kTpl, int kKind, bool kScaleD>
 __device__ __forceinline__ void run_sources(const double *__restrict__ src,
                                             const double *__restrict__ str, double dscale,
-                                            int64_t j0, int64_t j1, Acc<kTpl> &A) {
-  int64_t j = j0;
+                                            int64_t j0_, int64_t j1_, Acc<kTpl> &A) {
+  // source indices fit in 32 bits; wave-uniform bounds keep the loop test on
+  // the scalar unit
+  int j = uniform((int)j0_);
+  const int j1 = uniform((int)j1_);
   // two Stokeslets per step (rotlet and dipole ranges are short: one per step)
   for (; kKind == 0 && j + 1 < j1; j += 2) {
     const double *p0 = src + 3 * j, *q0 = str + 3 * j;
