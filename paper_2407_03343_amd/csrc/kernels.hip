@@ -75,49 +75,74 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // concatenated ranges (split over sources), and the tile's own sphere is
 // cut out of each range (the identity self blocks of G_hat).
 
-// Stokeslet: u += (f + r (r.f)/|r|^2) / |r|, written as ri (f + r t) with
-// t = (r.f) ri^2: 21 VALU operations plus one rsq per pair.
-__device__ __forceinline__ void pair_s(double sx, double sy, double sz, double fx, double fy,
-                                       double fz, double tx, double ty, double tz, double &ax,
-                                       double &ay, double &az) {
-  const double rx = tx - sx, ry = ty - sy, rz = tz - sz;
-  const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-  const double ri = rsqrt_f64(r2);
-  const double rf = fma(rx, fx, fma(ry, fy, rz * fz));
-  const double t = rf * (ri * ri);
-  ax = fma(fma(rx, t, fx), ri, ax);
-  ay = fma(fma(ry, t, fy), ri, ay);
-  az = fma(fma(rz, t, fz), ri, az);
+// 2/sqrt(x): the Newton step y (3 - x y^2) from the hardware estimate y,
+// without its halving (3 VALU operations besides the rsq instead of 4).
+// Relative error as rsqrt_f64's.
+__device__ __forceinline__ double rsq2_f64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-x, y * y, 3.0);
 }
 
-// Rotlet: u += (t x r) / |r|^3.
+// f/4 for a wave-uniform f, as integer operations on the high word (they
+// stay on the scalar unit): the exponent field E becomes E - min(E, 2).
+// Exact for normal results; zero stays zero, and |f| below 2^-1020 gives a
+// value off by less than 2^-1022.
+__device__ __forceinline__ double quarter(double f) {
+  typedef unsigned Words __attribute__((ext_vector_type(2)));  // (low, high)
+  Words w = __builtin_bit_cast(Words, f);
+  w.y -= min(w.y & 0x7ff00000u, 0x00200000u);
+  return __builtin_bit_cast(double, w);
+}
+
+// The pair functions below add TWICE the velocity of one source (the factor
+// of two is what rsq2_f64 leaves; the tile's sums are halved once at the
+// end).
+//
+// Stokeslet: u = (f + r (r.f)/|r|^2) / |r|.  With Y = 2/|r| and g = f/4:
+// 2u = Y (f + r t), t = (r.g) Y^2 = (r.f)/|r|^2 -- 20 VALU operations plus
+// one rsq per pair.
+__device__ __forceinline__ void pair_s(double sx, double sy, double sz, double fx, double fy,
+                                       double fz, double gx, double gy, double gz, double tx,
+                                       double ty, double tz, double &ax, double &ay, double &az) {
+  const double rx = tx - sx, ry = ty - sy, rz = tz - sz;
+  const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+  const double Y = rsq2_f64(r2);
+  const double rg = fma(rx, gx, fma(ry, gy, rz * gz));
+  const double t = rg * (Y * Y);
+  ax = fma(fma(rx, t, fx), Y, ax);
+  ay = fma(fma(ry, t, fy), Y, ay);
+  az = fma(fma(rz, t, fz), Y, az);
+}
+
+// Rotlet: u = (t x r) / |r|^3; 2/|r|^3 = Y^3/4.
 __device__ __forceinline__ void pair_r(double sx, double sy, double sz, double t0, double t1,
                                        double t2, double tx, double ty, double tz, double &ax,
                                        double &ay, double &az) {
   const double rx = tx - sx, ry = ty - sy, rz = tz - sz;
   const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-  const double ri = rsqrt_f64(r2);
-  const double c = ri * ri * ri;
+  const double Y = rsq2_f64(r2);
+  const double c = (0.25 * Y) * (Y * Y);
   ax = fma(c, fma(t1, rz, -t2 * ry), ax);
   ay = fma(c, fma(t2, rx, -t0 * rz), ay);
   az = fma(c, fma(t0, ry, -t1 * rx), az);
 }
 
 // Potential dipole (strength pre-multiplied by 2 mu so that the common
-// factor 1/(8 pi mu) applies): u += -d/|r|^3 + 3 r (r.d)/|r|^5.
+// factor 1/(8 pi mu) applies): u = -d/|r|^3 + 3 r (r.d)/|r|^5;
+// 2/|r|^3 = Y^3/4 and 6/|r|^5 = (3/4) (Y^3/4) Y^2.
 __device__ __forceinline__ void pair_d(double sx, double sy, double sz, double d0, double d1,
                                        double d2, double tx, double ty, double tz, double &ax,
                                        double &ay, double &az) {
   const double rx = tx - sx, ry = ty - sy, rz = tz - sz;
   const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-  const double ri = rsqrt_f64(r2);
-  const double ri2 = ri * ri;
-  const double ri3 = ri2 * ri;
+  const double Y = rsq2_f64(r2);
+  const double Y2 = Y * Y;
+  const double c3 = 0.25 * (Y2 * Y);
   const double rd = fma(rx, d0, fma(ry, d1, rz * d2));
-  const double bb = 3.0 * rd * ri3 * ri2;
-  ax = fma(-d0, ri3, fma(rx, bb, ax));
-  ay = fma(-d1, ri3, fma(ry, bb, ay));
-  az = fma(-d2, ri3, fma(rz, bb, az));
+  const double bb = (0.75 * rd) * c3 * Y2;
+  ax = fma(-d0, c3, fma(rx, bb, ax));
+  ay = fma(-d1, c3, fma(ry, bb, ay));
+  az = fma(-d2, c3, fma(rz, bb, az));
 }
 
 template <int kTpl>
@@ -126,28 +151,39 @@ struct Acc {
 };
 
 // Sources [j0, j1) of one kind; j0, j1 wave-uniform.
+// Source positions and strengths do not change during a direct-sum launch;
+// reading them through the constant address space lets the compiler use
+// scalar loads for the wave-uniform addresses also where the pointers come
+// from a descriptor in memory (the serving kernel), not from kernel arguments.
+typedef __attribute__((address_space(4))) const double *ConstPtr;
+
 template <int kTpl, int kKind, bool kScaleD>
-__device__ __forceinline__ void run_sources(const double *__restrict__ src,
-                                            const double *__restrict__ str, double dscale,
+__device__ __forceinline__ void run_sources(const double *__restrict__ src_,
+                                            const double *__restrict__ str_, double dscale,
                                             int64_t j0_, int64_t j1_, Acc<kTpl> &A) {
+  const ConstPtr src = (ConstPtr)src_, str = (ConstPtr)str_;
   // source indices fit in 32 bits; wave-uniform bounds keep the loop test on
   // the scalar unit
   int j = uniform((int)j0_);
   const int j1 = uniform((int)j1_);
   // two Stokeslets per step (rotlet and dipole ranges are short: one per step)
   for (; kKind == 0 && j + 1 < j1; j += 2) {
-    const double *p0 = src + 3 * j, *q0 = str + 3 * j;
+    const ConstPtr p0 = src + 3 * j, q0 = str + 3 * j;
     const double s0x = p0[0], s0y = p0[1], s0z = p0[2], s1x = p0[3], s1y = p0[4], s1z = p0[5];
     double f0x = q0[0], f0y = q0[1], f0z = q0[2], f1x = q0[3], f1y = q0[4], f1z = q0[5];
     if (kKind == 2 && kScaleD) {
       f0x *= dscale; f0y *= dscale; f0z *= dscale;
       f1x *= dscale; f1y *= dscale; f1z *= dscale;
     }
+    const double g0x = quarter(f0x), g0y = quarter(f0y), g0z = quarter(f0z);
+    const double g1x = quarter(f1x), g1y = quarter(f1y), g1z = quarter(f1z);
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
       if (kKind == 0) {
-        pair_s(s0x, s0y, s0z, f0x, f0y, f0z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
-        pair_s(s1x, s1y, s1z, f1x, f1y, f1z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+        pair_s(s0x, s0y, s0z, f0x, f0y, f0z, g0x, g0y, g0z, A.tx[p], A.ty[p], A.tz[p], A.ax[p],
+               A.ay[p], A.az[p]);
+        pair_s(s1x, s1y, s1z, f1x, f1y, f1z, g1x, g1y, g1z, A.tx[p], A.ty[p], A.tz[p], A.ax[p],
+               A.ay[p], A.az[p]);
       } else if (kKind == 1) {
         pair_r(s0x, s0y, s0z, f0x, f0y, f0z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
         pair_r(s1x, s1y, s1z, f1x, f1y, f1z, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
@@ -158,13 +194,16 @@ __device__ __forceinline__ void run_sources(const double *__restrict__ src,
     }
   }
   for (; j < j1; ++j) {
-    const double *p0 = src + 3 * j, *q0 = str + 3 * j;
+    const ConstPtr p0 = src + 3 * j, q0 = str + 3 * j;
     const double sx = p0[0], sy = p0[1], sz = p0[2];
     double fx = q0[0], fy = q0[1], fz = q0[2];
     if (kKind == 2 && kScaleD) { fx *= dscale; fy *= dscale; fz *= dscale; }
+    const double gx = quarter(fx), gy = quarter(fy), gz = quarter(fz);
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
-      if (kKind == 0) pair_s(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
+      if (kKind == 0)
+        pair_s(sx, sy, sz, fx, fy, fz, gx, gy, gz, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p],
+               A.az[p]);
       else if (kKind == 1) pair_r(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
       else pair_d(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], A.ax[p], A.ay[p], A.az[p]);
     }
@@ -241,9 +280,9 @@ __device__ __forceinline__ void direct_wave(const DirectArgs &A, int64_t tile, i
     const int i = lane + kWave * p;
     if (i < tc) {
       const int64_t o = 3 * ((int64_t)t0 + i);
-      out[o] = acc.ax[p];
-      out[o + 1] = acc.ay[p];
-      out[o + 2] = acc.az[p];
+      out[o] = 0.5 * acc.ax[p];  // the pair functions add twice the velocity
+      out[o + 1] = 0.5 * acc.ay[p];
+      out[o + 2] = 0.5 * acc.az[p];
     }
   }
 }
