@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X, FP64 vector
 PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X, FP64 dense matrix
+PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X, FP32 vector (counts packed FP32)
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the direct sum on the 100-sphere workload (62 source
 # splits): rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB elementwise
@@ -96,6 +97,7 @@ def mixed_vs_fp64(args, torch, smfs, wl):
            "setup_s": setup_s, "forms": {}}
     for name, prec in FORMS:
         rows = []
+        pb.profile(True)
         for tol in args.mixed_tols:
             pb.set_solver(prec, tol)
             ts = []
@@ -115,9 +117,11 @@ def mixed_vs_fp64(args, torch, smfs, wl):
                              pair_evals_per_s=o["pair_evals"] / (np.percentile(ts, 50) * 1e-3)))
             log(f"  {name} tol {tol:.0e}: it {o['iterations']} (+{o['refinements']}), "
                 f"{rows[-1]['solve_ms_p50']:.1f} ms, u err {du:.2e}, F/T err {dft:.2e}")
+        pb.profile(False)
         ok = [r for r in rows if r["u_rel_err"] <= 1e-3]
         best = min(ok, key=lambda r: r["solve_ms_p50"]) if ok else None
-        out["forms"][name] = {"scan": rows, "at_1e-3_surface_velocity": best}
+        out["forms"][name] = {"scan": rows, "at_1e-3_surface_velocity": best,
+                              "kernels": mixed_kernel_rates(pb.profile_read())}
     # mobility (forces and torques in), each form at the tolerance that met
     # the surface-velocity target above; error of the rigid motions against
     # the FP64 mobility solve at 1e-10
@@ -146,6 +150,28 @@ def mixed_vs_fp64(args, torch, smfs, wl):
             out[f"speedup_{name}_over_fp64"] = f64["solve_ms_p50"] / mx["solve_ms_p50"]
         mb = out["mobility"]
         out[f"mobility_speedup_{name}_over_fp64"] = mb["fp64"]["solve_ms"] / mb[name]["solve_ms"]
+    return out
+
+
+def mixed_kernel_rates(st):
+    """Per-kernel rates over the profiled products of one form: the FP32 far
+    field against the FP32 vector peak (the published figure counts packed
+    FP32 operations, which this build does not emit, so half of it is the
+    ceiling of its scalar FP32 code), the FP64 direct sum (all of the sum
+    in the FP64 form, the near part in the mixed forms) against the FP64
+    vector peak."""
+    out = {}
+    for key, label, peak in (("far32", "k_far_f32", PEAK_FP32_VALU_TFLOPS),
+                             ("mixed64", "k_direct_f64 (near part)", PEAK_FP64_VALU_TFLOPS),
+                             ("direct", "k_direct_f64", PEAK_FP64_VALU_TFLOPS)):
+        n = st[f"{key}_launches"]
+        if not n:
+            continue
+        ms = st[f"{key}_ms"] / n
+        tf = st[f"{key}_flops"] / (ms * 1e-3) / 1e12
+        out[key] = dict(kernel=label, launches=n, avg_launch_ms=ms,
+                        flops_per_launch=st[f"{key}_flops"], achieved=tf, peak=peak,
+                        unit="TFLOP/s", frac=tf / peak)
     return out
 
 
