@@ -37,8 +37,9 @@ PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X, FP32 vector (counts packed FP32)
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the direct sum on the 100-sphere workload (62 source
 # splits): rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB elementwise
-# copy reads back) plus WRITE_SIZE (x1), profiles/k_direct_f64_cluster100_fp64_hbm_counters.md
-DIRECT_TRAFFIC_BYTES = (2 * 225710.8 + 387461.4) * 1024
+# copy reads back) plus WRITE_SIZE (x1), KiB per dispatch, from the counter
+# summary of this kernel under profiles/
+DIRECT_TRAFFIC_BYTES = (2 * 225712.4 + 387462.0) * 1024
 
 
 def log(msg):
