@@ -179,8 +179,26 @@ int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision,
 /* lambda [dev] S x 3 = B^+ mu, eq. (transform), in FP64. */
 int smfs_transform(smfs_problem *pb, const double *mu, double *lambda, smfs_stream stream);
 
-/* b [dev] 3 T = W (v + omega x (x - c)) from rbm [dev] P x 6, eq. (bc). */
+/* b [dev] 3 T = W (v + omega x (x - c) - u_inf(x)) from rbm [dev] P x 6,
+ * eq. (bc); u_inf is the background flow set by smfs_set_background (zero
+ * unless set). */
 int smfs_rhs(smfs_problem *pb, const double *rbm, double *b, smfs_stream stream);
+
+/* Background flow of the boundary data, eq. (bc) (Section 1; the paper's
+ * examples of fixed clusters in a shear and in a uniform flow): a linear
+ * flow u_inf(x) = U + L x with U [host] 3 and the constant velocity
+ * gradient L [host] 3 x 3 row-major, L[3 i + j] = d u_inf_i / d x_j
+ * (absolute coordinates x).  Either pointer may be NULL (that part is zero);
+ * both NULL restores the quiescent fluid, the default.  From this call on,
+ * smfs_rhs, the resistance solves (single and block), the mobility solve
+ * (whose velocity rows then carry -W u_inf) and the check-point residuals of
+ * this problem use v + omega x (x - c) - u_inf(x); lambda, forces and
+ * torques are those of the disturbance flow.  Serving requests are always
+ * in a quiescent fluid.  Host-side only, no device work.  Errors:
+ * SMFS_E_INVALID_ARG for a non-finite entry or a gradient that is not
+ * trace-free (|L00 + L11 + L22| > 1e-12 max |L_ij|: a linear flow solves
+ * the homogeneous Stokes equations only when divergence-free). */
+int smfs_set_background(smfs_problem *pb, const double *U, const double *L);
 
 /* ft [dev] P x 6 from lambda [dev] S x 3. */
 int smfs_force_torque(smfs_problem *pb, const double *lambda, double *ft, smfs_stream stream);

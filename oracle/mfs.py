@@ -306,15 +306,28 @@ def mobility_apply(pb: Problem, x: np.ndarray) -> np.ndarray:
     return np.concatenate([top, ft.reshape(-1)])
 
 
-def solve_mobility(pb: Problem, ft: np.ndarray, tol=1e-10, max_it=1000):
-    """Forces and torques (P, 6) in, rigid motions out (quiescent fluid)."""
+def linear_flow(U=None, L=None):
+    """u_inf(x) = U + L x for points x (n, 3), L[i][j] = d u_inf_i / d x_j:
+    the background flows of the paper's fixed-cluster examples (uniform and
+    shear) are of this form; a trace-free L makes it a Stokes solution."""
+    U = np.zeros(3) if U is None else np.asarray(U, np.float64)
+    L = np.zeros((3, 3)) if L is None else np.asarray(L, np.float64)
+    return lambda x: U[None, :] + np.asarray(x) @ L.T
+
+
+def solve_mobility(pb: Problem, ft: np.ndarray, tol=1e-10, max_it=1000, u_inf=None):
+    """Forces and torques (P, 6) in, rigid motions out.  In a background
+    flow u_inf the velocity rows of the right-hand side are the boundary
+    data of spheres at rest, -W u_inf (eq. bc with v = omega = 0, the
+    unknown motion being on the left)."""
     g = pb.g
     n = 3 * g.T
     sF, sT = mobility_scales(pb)
     rhs_ft = np.array(ft, dtype=np.float64).copy()
     rhs_ft[:, :3] *= sF
     rhs_ft[:, 3:] *= sT
-    b = np.concatenate([np.zeros(n), rhs_ft.reshape(-1)])
+    top = np.zeros(n) if u_inf is None else pb.rhs(np.zeros((g.P, 6)), u_inf)
+    b = np.concatenate([top, rhs_ft.reshape(-1)])
     res = gmres(lambda v: mobility_apply(pb, v), b, tol, max_it)
     mu, V = res.x[:n], res.x[n:].reshape(g.P, 6)
     lam = pb.transform(mu)

@@ -941,7 +941,32 @@ int smfs_transform(smfs_problem *pb, const double *mu, double *lam, smfs_stream 
 int smfs_rhs(smfs_problem *pb, const double *rbm, double *b, smfs_stream stream) {
   if (!pb || !pb->bound) { set_error("problem not bound"); return SMFS_E_STATE; }
   if (!rbm || !b) { set_error("smfs_rhs: null vector"); return SMFS_E_INVALID_ARG; }
-  SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm, b, (hipStream_t)stream));
+  SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm, b, (hipStream_t)stream,
+                      &pb->bg));
+  return SMFS_OK;
+}
+
+int smfs_set_background(smfs_problem *pb, const double *U, const double *L) {
+  if (!pb) { set_error("null problem"); return SMFS_E_INVALID_ARG; }
+  BgFlow bg{};
+  double lmax = 0.0;
+  for (int q = 0; q < 3; ++q) bg.U[q] = U ? U[q] : 0.0;
+  for (int q = 0; q < 9; ++q) {
+    bg.L[q] = L ? L[q] : 0.0;
+    lmax = std::max(lmax, std::fabs(bg.L[q]));
+  }
+  for (int q = 0; q < 3; ++q)
+    if (!std::isfinite(bg.U[q])) { set_error("background flow: non-finite U"); return SMFS_E_INVALID_ARG; }
+  for (int q = 0; q < 9; ++q)
+    if (!std::isfinite(bg.L[q])) { set_error("background flow: non-finite gradient"); return SMFS_E_INVALID_ARG; }
+  // a linear flow solves the homogeneous Stokes equations only if it is
+  // divergence-free
+  if (std::fabs(bg.L[0] + bg.L[4] + bg.L[8]) > 1e-12 * lmax) {
+    set_error("background flow: velocity gradient is not trace-free");
+    return SMFS_E_INVALID_ARG;
+  }
+  bg.on = (U != nullptr || L != nullptr) ? 1 : 0;
+  pb->bg = bg;
   return SMFS_OK;
 }
 
@@ -1129,7 +1154,7 @@ int post_process(Problem &pb, const double *x, const double *rbm, smfs_out *out,
     rc = eval_points(pb, lam, pb.C, pb.d_chk, out->u_check, s);
     if (rc) return rc;
     SMFS_HIP(launch_residual_stats(pb.C, pb.d_chk, pb.d_csph, pb.d_meta, rbm, out->u_check, 1e-3,
-                                   scal + 3, s));
+                                   scal + 3, s, &pb.bg));
   }
   SMFS_HIP(hipMemcpyAsync(stats, scal + 2, 8 * 4, hipMemcpyDeviceToHost, s));
   SMFS_HIP(hipStreamSynchronize(s));
@@ -1166,7 +1191,7 @@ int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out, sm
   double *b = pb->d_vec + 2 * ld;
   double *x = out->mu ? out->mu : pb->d_vec + 3 * ld;
   auto t0 = clk::now();
-  SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm, b, s));
+  SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm, b, s, &pb->bg));
   SMFS_HIP(hipStreamSynchronize(s));
   auto t1 = clk::now();
   const int precision = pb->prm.precision;
@@ -1201,7 +1226,9 @@ int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_
   auto t0 = clk::now();
   const double sF = 1.0 / (6.0 * kPi * pb->prm.mu * pb->a),
                sT = 1.0 / (8.0 * kPi * pb->prm.mu * pb->a * pb->a * pb->a);
-  SMFS_HIP(launch_fill(n3, 0.0, b, s));
+  // velocity rows: the spheres' own motion is unknown, so only -W u_inf
+  // (zero in a quiescent fluid)
+  SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, nullptr, b, s, &pb->bg));
   SMFS_HIP(launch_scale_ft(pb->P, ft, sF, sT, b + n3, s));
   SMFS_HIP(hipStreamSynchronize(s));
   auto t1 = clk::now();

@@ -335,7 +335,7 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
   SMFS_HIP(launch_fill(blk, 0.0, B, s));
   for (int q = 0; q < nrhs; ++q)
     SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm + 6 * P * q,
-                        B + (int64_t)q * ld, s));
+                        B + (int64_t)q * ld, s, &pb->bg));
   BlockStats st;
   rc = gmres_block(*pb, L, nrhs, B, X, pb->prm.gmres_tol, pb->prm.gmres_max_it, st, s);
   if (rc) return rc;

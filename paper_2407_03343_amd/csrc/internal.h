@@ -35,6 +35,14 @@ struct Contact {
 // rotlets, potential dipoles (each sphere-major).
 constexpr int kBlocks = 4;
 
+// Background flow u_inf(x) = U + L x (eq. bc), L row-major: L[3i + j] =
+// d u_inf_i / d x_j.  Passed by value to the kernels; on == 0: quiescent.
+struct BgFlow {
+  double U[3];
+  double L[9];
+  int32_t on;
+};
+
 // Per-sphere table entry read by the kernels.
 struct SphereMeta {
   int64_t t0;             // first collocation node
@@ -126,6 +134,7 @@ struct Problem {
   int64_t n_btask_u = 0, n_btask_v = 0;
   int64_t cols_total = 0;                  // sum of factor columns over spheres
   bool skip_shared = false;                // setup leaves factor 0 (imported) alone
+  BgFlow bg{};                             // background flow of the boundary data (off: quiescent)
   void *svd_scratch = nullptr;             // optional device scratch of the setup SVDs
   size_t svd_scratch_bytes = 0;
   double *d_kry = nullptr, *d_vec = nullptr, *d_red = nullptr;

@@ -82,13 +82,16 @@ hipError_t launch_pinv_v32(const RowTask *tasks, int64_t n, const SphereMeta *me
                            const float *sbuf, float *str32, hipStream_t s);
 hipError_t launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 
-// b = W (v + omega x (x - c)) per collocation node.
+// b = W (v + omega x (x - c) - u_inf(x)) per collocation node (bg nullable:
+// no background flow; rbm nullable: spheres at rest).
 hipError_t launch_rhs(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
-                      const SphereMeta *meta, const double *rbm, double *b, hipStream_t s);
-// y = alpha W (v + omega x (x - c)) + beta y (y not read when beta == 0)
+                      const SphereMeta *meta, const double *rbm, double *b, hipStream_t s,
+                      const BgFlow *bg = nullptr);
+// y = alpha W (v + omega x (x - c) - u_inf(x)) + beta y (y not read when
+// beta == 0; bg and rbm nullable as above)
 hipError_t launch_rigid(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
                         const SphereMeta *meta, const double *rbm, double alpha, double beta,
-                        double *y, hipStream_t s);
+                        double *y, hipStream_t s, const BgFlow *bg = nullptr);
 // forces and torques per sphere, F scaled by sF and T by sT
 hipError_t launch_force_torque(int32_t P, const SphereMeta *meta, const double *src,
                                const double *lam, double *ft, hipStream_t s, double sF = 1.0,
@@ -97,9 +100,11 @@ hipError_t launch_force_torque(int32_t P, const SphereMeta *meta, const double *
 hipError_t launch_scale_ft(int32_t P, const double *x, double sF, double sT, double *y,
                            hipStream_t s);
 // residual statistics: out[0] = max eps_res (masked), out[1] = max |u-ubc|, out[2] = max |ubc|
+// with ubc the boundary data of eq. (bc), background flow included (bg nullable)
 hipError_t launch_residual_stats(int64_t n, const double *pts, const int32_t *sph,
                                  const SphereMeta *meta, const double *rbm, const double *u,
-                                 double floor_rel, double *out, hipStream_t s);
+                                 double floor_rel, double *out, hipStream_t s,
+                                 const BgFlow *bg = nullptr);
 hipError_t launch_absmax(int64_t n, const double *x, double *out, hipStream_t s);
 
 // Self block B = W G^(kk) of sphere k, column-major rows x cols.

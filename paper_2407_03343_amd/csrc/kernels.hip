@@ -623,21 +623,41 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restr
 // ---------------------------------------------------------------------------
 // Right-hand side, forces/torques, residual statistics.
 
-// y = alpha W (v + omega x (x - c)) + (beta != 0 ? beta y : 0) at the nodes.
+// Boundary data of eq. (bc) at point x of sphere k: v + omega x (x - c) minus
+// the background flow U + L x (when bg.on); rbm == NULL means rest.
+__device__ __forceinline__ void boundary_data(const double *__restrict__ x,
+                                              const SphereMeta &m, const double *__restrict__ rbm,
+                                              int k, const BgFlow &bg, double (&w)[3]) {
+  w[0] = w[1] = w[2] = 0.0;
+  if (rbm) {
+    const double *v = rbm + 6 * (int64_t)k;
+    const double rx = x[0] - m.c[0], ry = x[1] - m.c[1], rz = x[2] - m.c[2];
+    w[0] = v[0] + v[4] * rz - v[5] * ry;
+    w[1] = v[1] + v[5] * rx - v[3] * rz;
+    w[2] = v[2] + v[3] * ry - v[4] * rx;
+  }
+  if (bg.on) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      w[q] -= bg.U[q] + bg.L[3 * q] * x[0] + bg.L[3 * q + 1] * x[1] + bg.L[3 * q + 2] * x[2];
+  }
+}
+
+// y = alpha W u_bc + (beta != 0 ? beta y : 0) at the nodes, u_bc the
+// boundary data above.
 __global__ void k_rigid(int64_t T, const double *__restrict__ tgt, const int32_t *__restrict__ tsph,
                         const double *__restrict__ sw, const SphereMeta *__restrict__ meta,
-                        const double *__restrict__ rbm, double alpha, double beta,
+                        const double *__restrict__ rbm, BgFlow bg, double alpha, double beta,
                         double *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T) return;
   const int k = tsph[i];
-  const double *c = meta[k].c;
-  const double *v = rbm + 6 * (int64_t)k;
-  const double rx = tgt[3 * i] - c[0], ry = tgt[3 * i + 1] - c[1], rz = tgt[3 * i + 2] - c[2];
+  double w[3];
+  boundary_data(tgt + 3 * i, meta[k], rbm, k, bg, w);
   const double s = alpha * sw[i];
-  const double u0 = s * (v[0] + v[4] * rz - v[5] * ry);
-  const double u1 = s * (v[1] + v[5] * rx - v[3] * rz);
-  const double u2 = s * (v[2] + v[3] * ry - v[4] * rx);
+  const double u0 = s * w[0];
+  const double u1 = s * w[1];
+  const double u2 = s * w[2];
   if (beta != 0.0) {
     y[3 * i] = fma(beta, y[3 * i], u0);
     y[3 * i + 1] = fma(beta, y[3 * i + 1], u1);
@@ -691,18 +711,14 @@ __global__ __launch_bounds__(1024) void k_residual_stats(int64_t n, const double
                                                          const int32_t *__restrict__ sph,
                                                          const SphereMeta *__restrict__ meta,
                                                          const double *__restrict__ rbm,
+                                                         BgFlow bg,
                                                          const double *__restrict__ u,
                                                          double floor_rel, double *out) {
   __shared__ double sh[16];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   auto ubc = [&](int64_t i, double (&w)[3]) {
     const int k = sph[i];
-    const double *c = meta[k].c;
-    const double *v = rbm + 6 * (int64_t)k;
-    const double rx = pts[3 * i] - c[0], ry = pts[3 * i + 1] - c[1], rz = pts[3 * i + 2] - c[2];
-    w[0] = v[0] + v[4] * rz - v[5] * ry;
-    w[1] = v[1] + v[5] * rx - v[3] * rz;
-    w[2] = v[2] + v[3] * ry - v[4] * rx;
+    boundary_data(pts + 3 * i, meta[k], rbm, k, bg, w);
   };
   // pass 1: max |u_bc| and max |u - u_bc|
   double mb = 0.0, me = 0.0;
@@ -1056,18 +1072,27 @@ hipError_t launch_pinv_v(const RowTask *tasks, int64_t n, const SphereMeta *meta
   return hipGetLastError();
 }
 
+namespace {
+BgFlow bg_or_rest(const BgFlow *bg) {
+  BgFlow r{};
+  if (bg && bg->on) r = *bg;
+  return r;
+}
+}  // namespace
+
 hipError_t launch_rigid(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
                         const SphereMeta *meta, const double *rbm, double alpha, double beta,
-                        double *y, hipStream_t s) {
+                        double *y, hipStream_t s, const BgFlow *bg) {
   if (T == 0) return hipSuccess;
   hipLaunchKernelGGL(k_rigid, dim3(blocks_for(T)), dim3(kBlock), 0, s, T, tgt, tsph, sw, meta, rbm,
-                     alpha, beta, y);
+                     bg_or_rest(bg), alpha, beta, y);
   return hipGetLastError();
 }
 
 hipError_t launch_rhs(int64_t T, const double *tgt, const int32_t *tsph, const double *sw,
-                      const SphereMeta *meta, const double *rbm, double *b, hipStream_t s) {
-  return launch_rigid(T, tgt, tsph, sw, meta, rbm, 1.0, 0.0, b, s);
+                      const SphereMeta *meta, const double *rbm, double *b, hipStream_t s,
+                      const BgFlow *bg) {
+  return launch_rigid(T, tgt, tsph, sw, meta, rbm, 1.0, 0.0, b, s, bg);
 }
 
 hipError_t launch_force_torque(int32_t P, const SphereMeta *meta, const double *src,
@@ -1086,9 +1111,9 @@ hipError_t launch_scale_ft(int32_t P, const double *x, double sF, double sT, dou
 
 hipError_t launch_residual_stats(int64_t n, const double *pts, const int32_t *sph,
                                  const SphereMeta *meta, const double *rbm, const double *u,
-                                 double floor_rel, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual_stats, dim3(1), dim3(1024), 0, s, n, pts, sph, meta, rbm, u,
-                     floor_rel, out);
+                                 double floor_rel, double *out, hipStream_t s, const BgFlow *bg) {
+  hipLaunchKernelGGL(k_residual_stats, dim3(1), dim3(1024), 0, s, n, pts, sph, meta, rbm,
+                     bg_or_rest(bg), u, floor_rel, out);
   return hipGetLastError();
 }
 

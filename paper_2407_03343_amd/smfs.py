@@ -24,7 +24,8 @@ KIND_S, KIND_R, KIND_D = 1, 2, 4
 EXPORTED = [
     "smfs_params_default", "smfs_problem_create", "smfs_problem_destroy", "smfs_problem_sizes",
     "smfs_export_nodes", "smfs_sphere_factor", "smfs_factor_info", "smfs_bind", "smfs_setup",
-    "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_force_torque",
+    "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_set_background",
+    "smfs_force_torque",
     "smfs_eval_velocity", "smfs_solve_resistance", "smfs_solve_mobility", "smfs_set_solver",
     "smfs_pairs_per_apply", "smfs_block_workspace_bytes", "smfs_apply_block",
     "smfs_solve_resistance_block", "smfs_server_create", "smfs_server_destroy",
@@ -136,6 +137,7 @@ def lib():
         "smfs_apply": ([vp, vp, vp, i32, vp], C.c_int),
         "smfs_transform": ([vp, vp, vp, vp], C.c_int),
         "smfs_rhs": ([vp, vp, vp, vp], C.c_int),
+        "smfs_set_background": ([vp, vp, vp], C.c_int),
         "smfs_force_torque": ([vp, vp, vp, vp], C.c_int),
         "smfs_eval_velocity": ([vp, vp, i64, vp, vp, vp], C.c_int),
         "smfs_solve_resistance": ([vp, vp, P(smfs_out), vp], C.c_int),
@@ -266,6 +268,14 @@ class Problem:
         max_it = p.gmres_max_it if max_it is None else max_it
         _check(lib().smfs_set_solver(self.h, precision, tol, max_it), "smfs_set_solver")
         p.precision, p.gmres_tol, p.gmres_max_it = precision, tol, max_it
+
+    def set_background(self, U=None, L=None):
+        """Background flow u_inf(x) = U + L x of the boundary data (eq. bc);
+        L[i][j] = d u_inf_i / d x_j.  No arguments: quiescent fluid."""
+        u = None if U is None else np.ascontiguousarray(U, np.float64).reshape(3)
+        g = None if L is None else np.ascontiguousarray(L, np.float64).reshape(9)
+        _check(lib().smfs_set_background(self.h, None if u is None else _np_ptr(u),
+                                         None if g is None else _np_ptr(g)), "smfs_set_background")
 
     def profile(self, enable: bool):
         _check(lib().smfs_profile(self.h, 1 if enable else 0), "smfs_profile")

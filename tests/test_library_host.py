@@ -110,3 +110,20 @@ def test_contact_free_spheres_share_one_factor():
     assert fids[0] != 0 and fids[3] != 0 and fids[0] != fids[3]
     info = pb.factor_info(0)
     assert info["rows"] == 3 * 780 and info["cols"] == 3 * 600
+
+
+def test_set_background_validation():
+    """Background flow (eq. bc): a linear flow must be trace-free and
+    finite; both arguments absent restore the quiescent fluid."""
+    pb = smfs.Problem(np.array([[0.0, 0, 0], [2.5, 0, 0]]), 1.0)
+    shear = np.array([[0.0, 5.0, 0], [0, 0, 0], [0, 0, 0]])
+    pb.set_background(U=[5.0, 0, 0])
+    pb.set_background(L=shear)
+    pb.set_background(U=[1.0, -2.0, 0.5], L=shear)
+    pb.set_background()
+    with pytest.raises(smfs.SmfsError):
+        pb.set_background(L=np.diag([1.0, 1.0, 0.0]))          # divergence 2
+    with pytest.raises(smfs.SmfsError):
+        pb.set_background(U=[np.nan, 0.0, 0.0])
+    L = smfs.lib()
+    assert L.smfs_set_background(None, None, None) != 0

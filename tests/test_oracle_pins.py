@@ -330,3 +330,63 @@ def test_mobility_round_trip(oracle_pairsum_built):
     m = mfs.solve_mobility(pb, r["ft"], tol=1e-12)
     assert np.abs(m["rbm"] - rbm).max() < 1e-8 * np.abs(rbm).max()
     assert np.abs(m["ft"] - r["ft"]).max() < 1e-8 * np.abs(r["ft"]).max()
+
+
+# -- background flow (eq. bc with u_inf; the paper's fixed clusters in a
+# uniform and in a shear flow) -------------------------------------------------
+
+def _rel_err(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def test_fixed_sphere_in_uniform_flow(single_sphere):
+    """A sphere held fixed in a uniform stream U feels the Stokes drag: the
+    force it exerts on the fluid is -6 pi mu a U, and no torque."""
+    g, pb = single_sphere
+    U = np.array([5.0, -1.0, 2.0])
+    out = mfs.solve_resistance(pb, np.zeros((1, 6)), tol=1e-12, u_inf=mfs.linear_flow(U=U))
+    F, T = out["ft"][0, :3], out["ft"][0, 3:]
+    assert _rel_err(F, -mfs.stokes_drag(1.0, 1.0, U)) < 1e-6
+    assert np.abs(T).max() < 1e-6 * np.abs(F).max()
+
+
+def test_fixed_sphere_in_rotational_flow(single_sphere):
+    """u_inf = w x x about the origin, sphere centred at c != 0: relative to
+    the sphere the fluid translates with w x c and rotates with w, so
+    F = -6 pi mu a (w x c) and T = -8 pi mu a^3 w (absolute coordinates, and
+    the sign of the gradient's antisymmetric part, both pinned)."""
+    g, pb = single_sphere
+    w = np.array([0.3, -0.7, 1.1])
+    L = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])   # L x = w x x
+    c = g.centers[0]
+    out = mfs.solve_resistance(pb, np.zeros((1, 6)), tol=1e-12, u_inf=mfs.linear_flow(L=L))
+    assert _rel_err(out["ft"][0, :3], -mfs.stokes_drag(1.0, 1.0, np.cross(w, c))) < 1e-6
+    assert _rel_err(out["ft"][0, 3:], -mfs.stokes_torque(1.0, 1.0, w)) < 1e-6
+
+
+def test_fixed_sphere_in_strain(single_sphere):
+    """A pure strain E (symmetric, trace-free) about the origin: the sphere
+    at c sees the uniform part E c (force -6 pi mu a E c) and a strain that
+    exerts no torque on a sphere."""
+    g, pb = single_sphere
+    E = np.array([[0.4, 1.2, -0.3], [1.2, -0.9, 0.5], [-0.3, 0.5, 0.5]])
+    c = g.centers[0]
+    out = mfs.solve_resistance(pb, np.zeros((1, 6)), tol=1e-12, u_inf=mfs.linear_flow(L=E))
+    F = out["ft"][0, :3]
+    assert _rel_err(F, -mfs.stokes_drag(1.0, 1.0, E @ c)) < 1e-6
+    assert np.abs(out["ft"][0, 3:]).max() < 1e-6 * np.abs(F).max()
+
+
+def test_free_sphere_follows_linear_flow(single_sphere):
+    """Force- and torque-free sphere in u_inf = U + L x: it moves with the
+    local flow at its centre, v = U + L c, and spins with half the vorticity,
+    omega_i = eps_ijk L_kj / 2 (Faxen's laws; exact for a linear flow)."""
+    g, pb = single_sphere
+    U = np.array([0.5, 1.5, -0.2])
+    L = np.array([[0.2, 1.0, -0.4], [0.3, -0.5, 0.8], [0.6, -0.1, 0.3]])
+    c = g.centers[0]
+    out = mfs.solve_mobility(pb, np.zeros((1, 6)), tol=1e-12, u_inf=mfs.linear_flow(U, L))
+    v_ref = U + L @ c
+    om_ref = 0.5 * np.array([L[2, 1] - L[1, 2], L[0, 2] - L[2, 0], L[1, 0] - L[0, 1]])
+    assert _rel_err(out["rbm"][0, :3], v_ref) < 1e-6
+    assert _rel_err(out["rbm"][0, 3:], om_ref) < 1e-6
