@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X, FP64 vector
 PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X, FP64 dense matrix
-PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X, FP32 vector (counts packed FP32)
+PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X, FP32 vector
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the direct sum on the 100-sphere workload (62 source
 # splits): rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB elementwise
@@ -154,11 +154,44 @@ def mixed_vs_fp64(args, torch, smfs, wl):
     return out
 
 
+def two_sphere(args, torch, smfs, wl):
+    """The paper's two-sphere case (Section 5, the comparison with Brenner's
+    series): unit spheres at gap 0.01 moving apart at unit relative speed,
+    FP64, GMRES to 1e-10.  Set-up once (timed), then repeated complete
+    solves (right-hand side, GMRES, back-transform, forces and torques,
+    check-point velocities) for p50/p99."""
+    pk, rbm = wl.workload_two_sphere_gap001()
+    pb = smfs.Problem(pk.centers, pk.radius)
+    pb.bind()
+    t0 = time.perf_counter()
+    pb.setup()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    r = torch.from_numpy(rbm[0].reshape(-1)).cuda()
+    o = pb.solve_resistance(r)                     # warm-up
+    torch.cuda.synchronize()
+    ts, pairs = [], 0
+    for _ in range(args.two_sphere_reps):
+        t1 = time.perf_counter()
+        o = pb.solve_resistance(r)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t1) * 1e3)
+        pairs += o["pair_evals"]
+    ft = o["ft"].cpu().numpy().reshape(-1, 6)
+    out = dict(spheres=2, gap=0.01, collocation_nodes=pb.T, sources=pb.S, setup_s=setup_s,
+               reps=len(ts), solve_ms_p50=float(np.percentile(ts, 50)),
+               solve_ms_p99=float(np.percentile(ts, 99)), iterations=o["iterations"],
+               true_rel_residual=o["true_rel_residual"], eps_res_max=o["eps_res_max"],
+               force_sphere0=[float(x) for x in ft[0, :3]],
+               pair_evals_per_s=pairs / (sum(ts) * 1e-3))
+    log(f"two spheres, gap 0.01: setup {setup_s:.2f} s, solve p50 {out['solve_ms_p50']:.2f} ms "
+        f"p99 {out['solve_ms_p99']:.2f} ms, it {o['iterations']}, |F| {np.linalg.norm(ft[0, :3]):.6f}")
+    return out
+
+
 def mixed_kernel_rates(st):
     """Per-kernel rates over the profiled products of one form: the FP32 far
-    field against the FP32 vector peak (the published figure counts packed
-    FP32 operations, which this build does not emit, so half of it is the
-    ceiling of its scalar FP32 code), the FP64 direct sum (all of the sum
+    field against the FP32 vector peak, the FP64 direct sum (all of the sum
     in the FP64 form, the near part in the mixed forms) against the FP64
     vector peak."""
     out = {}
@@ -434,10 +467,14 @@ def main():
                     help="requests solved one after another for the comparison")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving comparison")
     ap.add_argument("--mixed-only", action="store_true", help="run only the mixed-vs-FP64 comparison")
+    ap.add_argument("--two-sphere-reps", type=int, default=50,
+                    help="timed solves of the two-sphere case at gap 0.01 (0: skip)")
+    ap.add_argument("--two-sphere-only", action="store_true", help="run only the two-sphere case")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(how it would shard is written up in the design notes); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -451,6 +488,9 @@ def main():
         return
     if args.mixed_only:
         print(json.dumps({"mixed_vs_fp64": mixed_vs_fp64(args, torch, smfs, wl)}), flush=True)
+        return
+    if args.two_sphere_only:
+        print(json.dumps({"two_sphere": two_sphere(args, torch, smfs, wl)}), flush=True)
         return
     pk, _ = wl.workload_cluster100(args.seed)
     log(f"workload: {pk.P} spheres, box {pk.box:.2f}, min gap {pk.min_gaps().min():.2e}")
@@ -549,6 +589,9 @@ def main():
         result["block_vs_single"] = block_vs_single(pb, torch, args.block, 2)
     del pb
     torch.cuda.empty_cache()
+    if args.two_sphere_reps > 0:
+        result["two_sphere"] = two_sphere(args, torch, smfs, wl)
+        torch.cuda.empty_cache()
     if args.block_spheres > 0:
         result["block_solve"] = block_solve(args, torch, smfs, wl)
         torch.cuda.empty_cache()

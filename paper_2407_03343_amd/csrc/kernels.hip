@@ -425,6 +425,13 @@ __device__ __forceinline__ int block_kind(const SphereMeta &m, int jl) {
 // Pseudo-inverse apply: one wave per output row, a dot product of a
 // contiguous factor row with a short vector.
 
+// A factor entry read once per product: a non-temporal load, so that the
+// streamed factor does not evict the vector slice that the waves of the
+// same sphere share in the cache.
+__device__ __forceinline__ double stream_load(const double *p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // One wave per row j of U^T: sbuf[s0 + j] = (U_k^T mu)_j / sigma_j.
 __device__ __forceinline__ void pinv_u_row(const RowTask *__restrict__ tasks, int64_t t,
                                            const SphereMeta *__restrict__ meta,
@@ -441,12 +448,12 @@ __device__ __forceinline__ void pinv_u_row(const RowTask *__restrict__ tasks, in
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int i = lane;
   for (; i + 3 * kWave < rows; i += 4 * kWave) {
-    a0 = fma(col[i], x[i], a0);
-    a1 = fma(col[i + kWave], x[i + kWave], a1);
-    a2 = fma(col[i + 2 * kWave], x[i + 2 * kWave], a2);
-    a3 = fma(col[i + 3 * kWave], x[i + 3 * kWave], a3);
+    a0 = fma(stream_load(col + i), x[i], a0);
+    a1 = fma(stream_load(col + i + kWave), x[i + kWave], a1);
+    a2 = fma(stream_load(col + i + 2 * kWave), x[i + 2 * kWave], a2);
+    a3 = fma(stream_load(col + i + 3 * kWave), x[i + 3 * kWave], a3);
   }
-  for (; i < rows; i += kWave) a0 = fma(col[i], x[i], a0);
+  for (; i < rows; i += kWave) a0 = fma(stream_load(col + i), x[i], a0);
   const double s = wave_sum((a0 + a1) + (a2 + a3));
   if (lane == 0) sbuf[m.s0 + j] = s / fac[f.sig_off + j];
 }
@@ -468,12 +475,12 @@ __device__ __forceinline__ void pinv_v_row(const RowTask *__restrict__ tasks, in
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int i = lane;
   for (; i + 3 * kWave < rank; i += 4 * kWave) {
-    a0 = fma(row[i], x[i], a0);
-    a1 = fma(row[i + kWave], x[i + kWave], a1);
-    a2 = fma(row[i + 2 * kWave], x[i + 2 * kWave], a2);
-    a3 = fma(row[i + 3 * kWave], x[i + 3 * kWave], a3);
+    a0 = fma(stream_load(row + i), x[i], a0);
+    a1 = fma(stream_load(row + i + kWave), x[i + kWave], a1);
+    a2 = fma(stream_load(row + i + 2 * kWave), x[i + 2 * kWave], a2);
+    a3 = fma(stream_load(row + i + 3 * kWave), x[i + 3 * kWave], a3);
   }
-  for (; i < rank; i += kWave) a0 = fma(row[i], x[i], a0);
+  for (; i < rank; i += kWave) a0 = fma(stream_load(row + i), x[i], a0);
   const double s = wave_sum((a0 + a1) + (a2 + a3));
   if (lane == 0) {
     const int jl = r / 3, c = r - 3 * (r / 3);
@@ -523,12 +530,13 @@ __global__ __launch_bounds__(kBlock) void k_pinv_u(const RowTask *__restrict__ t
 #pragma unroll
     for (int r = 0; r < kPinvRows; ++r)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[r][u] = fma(c0[(int64_t)r * rows + i + u * kWave], xv[u], a[r][u]);
+      for (int u = 0; u < 4; ++u)
+        a[r][u] = fma(stream_load(c0 + (int64_t)r * rows + i + u * kWave), xv[u], a[r][u]);
   }
   for (; i < rows; i += kWave) {
     const double xi = x[i];
 #pragma unroll
-    for (int r = 0; r < kPinvRows; ++r) a[r][0] = fma(c0[(int64_t)r * rows + i], xi, a[r][0]);
+    for (int r = 0; r < kPinvRows; ++r) a[r][0] = fma(stream_load(c0 + (int64_t)r * rows + i), xi, a[r][0]);
   }
 #pragma unroll
   for (int r = 0; r < kPinvRows; ++r) {
