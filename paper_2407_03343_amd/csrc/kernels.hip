@@ -898,7 +898,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot2(const double *__restrict__ V, 
 #pragma unroll
     for (int q = 0; q < kDot2Vecs; ++q)
       if (j0 + q < nv) {
-        const double v = V[(int64_t)(j0 + q) * ld + i];
+        const double v = stream_load(V + (int64_t)(j0 + q) * ld + i);
         acc[q] = fma(v, ai, acc[q]);
         acc[kDot2Vecs + q] = fma(v, bi, acc[kDot2Vecs + q]);
       }
@@ -927,7 +927,7 @@ __global__ __launch_bounds__(kBlock) void k_dcgs_update(const double *__restrict
     for (; j + 7 < nb; j += 8) {
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(j + u) * ld + i];
+      for (int u = 0; u < 8; ++u) v[u] = stream_load(V + (int64_t)(j + u) * ld + i);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         s1[u & 1] = fma(v[u], cs[j + u], s1[u & 1]);
@@ -935,7 +935,7 @@ __global__ __launch_bounds__(kBlock) void k_dcgs_update(const double *__restrict
       }
     }
     for (; j < nb; ++j) {
-      const double v = V[(int64_t)j * ld + i];
+      const double v = stream_load(V + (int64_t)j * ld + i);
       s1[0] = fma(v, cs[j], s1[0]);
       s2[0] = fma(v, cz[j], s2[0]);
     }
