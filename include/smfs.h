@@ -209,7 +209,9 @@ int smfs_eval_velocity(smfs_problem *pb, const double *lambda, int64_t n, const 
                        double *u, smfs_stream stream);
 
 /* Resistance solve: rbm [dev] P x 6 rigid-body velocities in, outputs per
- * smfs_out.  Returns NOT_CONVERGED (warning) if gmres_max_it is reached.
+ * smfs_out; the boundary data include the background flow if one is set
+ * (smfs_set_background).  Returns NOT_CONVERGED (warning) if gmres_max_it
+ * is reached.
  * With params.precision = SMFS_MIXED (or SMFS_MIXED_FAR) the products
  * inside GMRES take the sources of contact-free spheres in FP32 as described
  * at the precision modes, everything else in FP64; Arnoldi, the true
@@ -226,8 +228,9 @@ int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32
 /* Mobility solve (forces and torques in, rigid motions out; the paper
  * treats the resistance problem and points to the mobility problem as
  * separate work).  ft [dev] P x 6 = (F, T) exerted on the fluid.  Unknowns
- * (mu, V): the rows G_hat mu - W (v + omega x (x - c)) = 0 at the
- * collocation nodes and, per sphere, the force and torque of
+ * (mu, V): the rows G_hat mu - W (v + omega x (x - c)) = -W u_inf at the
+ * collocation nodes (u_inf = 0 unless set by smfs_set_background) and, per
+ * sphere, the force and torque of
  * lambda = B^+ mu equal to (F, T), scaled by 1/(6 pi mu a) and
  * 1/(8 pi mu a^3).  out->rbm receives V; other outputs as for resistance
  * (the check-point residual is measured against the V found). */
