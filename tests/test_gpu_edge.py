@@ -1,0 +1,99 @@
+"""Degenerate and ragged cases through the C-ABI: zero right-hand sides and
+vectors, a vector living on one sphere only, a single sphere (the product
+is the identity), flow evaluation at 0, 1 and ragged numbers of points."""
+import numpy as np
+import pytest
+
+from oracle import geometry as geo, mfs
+from oracle.pairsum import pairsum
+from paper_2407_03343_amd import workloads as wl
+
+from gpu_common import _say, _t, _n, _rel, _import_oracle_factors
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SMALL = dict(n_proxy=60, n_colloc_base=80, n_image=4, n_check_base=50)
+
+
+@pytest.fixture(scope="module")
+def three(dev, oracle_pairsum_built):
+    _say("edge cases: three spheres, small discretisation, oracle factors")
+    prm = geo.Params(**SMALL)
+    c = np.array([[0.0, 0, 0], [2.05, 0.3, 0.0], [0.4, 2.3, 0.1]])
+    g = geo.build(c, 1.0, prm)
+    pbo = mfs.Problem(g).setup()
+    lib = dev.Problem(c, 1.0, gmres_tol=1e-12, **SMALL).bind()
+    _import_oracle_factors(lib, pbo)
+    return g, pbo, lib
+
+
+def test_zero_right_hand_side(three):
+    g, pbo, lib = three
+    _say("edge: resistance solve with zero rigid motions")
+    out = lib.solve_resistance(_t(np.zeros((g.P, 6))))
+    assert out["converged"] and out["iterations"] == 0
+    assert not np.any(_n(out["ft"])) and not np.any(_n(out["mu"]))
+
+
+def test_zero_vector_products(dev, three):
+    g, pbo, lib = three
+    _say("edge: products of the zero vector (FP64 and mixed forms)")
+    z = _t(np.zeros(3 * g.T))
+    for prec in (dev.SMFS_FP64, dev.SMFS_MIXED, dev.SMFS_MIXED_FAR):
+        assert not np.any(_n(lib.apply(z, precision=prec))), prec
+
+
+def test_vector_on_one_sphere(three):
+    """mu nonzero on sphere 0 only: the other spheres' strengths are zero,
+    so sphere 0's rows of the product are mu itself (identity self block,
+    every pair adding an exact zero) and the rest match the oracle."""
+    g, pbo, lib = three
+    _say("edge: vector living on one sphere")
+    rbm = np.zeros((g.P, 6))
+    rbm[0] = [0.3, -0.8, 0.5, 0.2, 0.9, -0.4]
+    mu = pbo.rhs(rbm)
+    assert np.any(mu[: 3 * g.M(0)]) and not np.any(mu[3 * g.M(0):])
+    y = _n(lib.apply(_t(mu)))
+    n0 = 3 * g.M(0)
+    assert np.array_equal(y[:n0], mu[:n0])
+    assert _rel(y, pbo.apply(mu)) < 1e-10
+
+
+def test_single_sphere_product_is_identity(dev):
+    """One sphere: no off-sphere pair exists, so the product returns mu
+    bitwise (every partial sum is an exact zero)."""
+    _say("edge: one sphere, the product is the identity")
+    lib = dev.Problem(np.array([[0.25, 0.5, -1.0]]), 1.0, **SMALL).bind()
+    for fid in range(lib.sizes.n_factors):
+        info = lib.factor_info(fid)
+        if info["sphere"] < 0:
+            continue
+        U, sig, V = wl.random_factors(info["rows"], info["cols"], info["cols"], seed=5 + fid)
+        lib.import_factor(fid, U, sig, V)
+    mu = wl.random_vector(3 * lib.T, 9)
+    assert np.array_equal(_n(lib.apply(_t(mu))), mu)
+
+
+def test_eval_velocity_no_points(three):
+    g, pbo, lib = three
+    _say("edge: flow at no points")
+    lam = _t(np.ones((g.S, 3)))
+    u = lib.eval_velocity(lam, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert u.numel() == 0
+
+
+@pytest.mark.parametrize("npts", [1, 65, 129])
+def test_eval_velocity_ragged(three, npts):
+    """Free points come in tiles of 128: one point, a partial tile, one
+    point past a full tile."""
+    g, pbo, lib = three
+    _say(f"edge: flow at {npts} points")
+    rng = np.random.default_rng(npts)
+    lam = rng.standard_normal((g.S, 3))
+    d = rng.standard_normal((npts, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts = g.centers[rng.integers(0, g.P, npts)] + d * rng.uniform(1.05, 3.0, (npts, 1))
+    u = _n(lib.eval_velocity(_t(lam), _t(pts))).reshape(-1, 3)
+    ref = pairsum(pts, g.src_pos, g.src_kind, lam, g.params.mu)
+    assert _rel(u, ref) < 1e-11
