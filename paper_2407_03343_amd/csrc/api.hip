@@ -427,12 +427,12 @@ int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s
     rc = transform64(pb, mu, pb.d_lamhat, ds, s);
     SMFS_HIP(launch_to_f32(3 * pb.nb[0], pb.d_lamhat, pb.d_str32, s));
   } else {
+    // contact spheres in FP64; the contact-free ones by the FP32 GEMMs of
+    // the shared factor (its FP32 copy holds factor 0 only)
     rc = transform_tasks(pb, mu, pb.d_lamhat, pb.n_utask_c, pb.n_vtask_c, ds, s);
-    const int64_t off0 = pb.factors[0].u_off;   // FP32 copy holds factor 0 only
-    SMFS_HIP(launch_pinv_u32(pb.d_utask + pb.n_utask_c, pb.n_utask - pb.n_utask_c, pb.d_meta,
-                             pb.d_fslots, pb.d_fac32, off0, mu, pb.d_s32, s));
-    SMFS_HIP(launch_pinv_v32(pb.d_vtask + pb.n_vtask_c, pb.n_vtask - pb.n_vtask_c, pb.d_meta,
-                             pb.d_fslots, pb.d_fac32, off0, pb.d_s32, pb.d_str32, s));
+    const FactorSlot &f0 = pb.factors[0];
+    SMFS_HIP(launch_pinv_shared32(pb.d_free, pb.n_free, f0.rank, f0.cols, pb.d_meta, pb.d_fslots,
+                                  pb.d_fac32, f0.u_off, mu, pb.d_s32, pb.d_str32, s));
   }
   if (rc) return rc;
   if (pb.prof && (rc = record_event(pb, s, e1))) return rc;

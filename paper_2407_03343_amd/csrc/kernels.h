@@ -72,14 +72,6 @@ hipError_t launch_pinv_v(const RowTask *tasks, int64_t n, const SphereMeta *meta
                          const FactorSlot *fs, const double *fac, const double *sbuf,
                          double *lam, double dscale, hipStream_t s);
 
-// FP32 copy of the shared factor: fac32 holds factor slot 0, whose FP64
-// offsets start at off0.
-hipError_t launch_pinv_u32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
-                           const FactorSlot *fs, const float *fac32, int64_t off0,
-                           const double *mu, float *sbuf, hipStream_t s);
-hipError_t launch_pinv_v32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
-                           const FactorSlot *fs, const float *fac32, int64_t off0,
-                           const float *sbuf, float *str32, hipStream_t s);
 hipError_t launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 
 // b = W (v + omega x (x - c) - u_inf(x)) per collocation node (bg nullable:
@@ -219,5 +211,14 @@ hipError_t launch_pinv_shared(const int32_t *free_ids, int32_t n_free, int32_t r
                               const SphereMeta *meta, const FactorSlot *fs, const double *fac,
                               const double *mu, double *sbuf, double *lam, double dscale,
                               hipStream_t s);
+
+// FP32 form of launch_pinv_shared for the mixed precision mode, on FP32 MFMA
+// with FP32 accumulation: fac32 is the FP32 copy of factor 0 (FP64 offsets
+// start at off0), mu is rounded to FP32 as it is read; writes s32 at each
+// free sphere's s0 and the FP32 proxy strengths str32 (P*n_proxy x 3).
+hipError_t launch_pinv_shared32(const int32_t *free_ids, int32_t n_free, int32_t rank, int32_t cols,
+                                const SphereMeta *meta, const FactorSlot *fs, const float *fac32,
+                                int64_t off0, const double *mu, float *s32, float *str32,
+                                hipStream_t s);
 
 }  // namespace smfs

@@ -557,71 +557,6 @@ __global__ __launch_bounds__(kBlock) void k_pinv_v(const RowTask *__restrict__ t
   pinv_v_row(tasks, t, meta, fs, fac, sbuf, lam, dscale);
 }
 
-// FP32 pseudo-inverse apply for contact-free spheres (mixed precision):
-// FP32 copies of the shared factor, FP32 accumulation; the strengths are
-// written to the FP32 proxy array read by k_far_f32.
-__global__ __launch_bounds__(kBlock) void k_pinv_u32(const RowTask *__restrict__ tasks, int64_t n,
-                                                     const SphereMeta *__restrict__ meta,
-                                                     const FactorSlot *__restrict__ fs,
-                                                     const float *__restrict__ fac32, int64_t off0,
-                                                     const double *__restrict__ mu,
-                                                     float *__restrict__ sbuf) {
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (t >= n) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int k = uniform(tasks[t].sphere), j = uniform(tasks[t].row);
-  const SphereMeta &m = meta[k];
-  const FactorSlot &f = fs[m.fid];
-  const int rows = f.rows;
-  const float *col = fac32 + (f.u_off - off0) + (int64_t)j * rows;
-  const double *x = mu + 3 * m.t0;
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  int i = lane;
-  for (; i + 3 * kWave < rows; i += 4 * kWave) {
-    a0 = fmaf(col[i], (float)x[i], a0);
-    a1 = fmaf(col[i + kWave], (float)x[i + kWave], a1);
-    a2 = fmaf(col[i + 2 * kWave], (float)x[i + 2 * kWave], a2);
-    a3 = fmaf(col[i + 3 * kWave], (float)x[i + 3 * kWave], a3);
-  }
-  for (; i < rows; i += kWave) a0 = fmaf(col[i], (float)x[i], a0);
-  float v = (a0 + a1) + (a2 + a3);
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if (lane == 0) sbuf[m.s0 + j] = v / fac32[(f.sig_off - off0) + j];
-}
-
-__global__ __launch_bounds__(kBlock) void k_pinv_v32(const RowTask *__restrict__ tasks, int64_t n,
-                                                     const SphereMeta *__restrict__ meta,
-                                                     const FactorSlot *__restrict__ fs,
-                                                     const float *__restrict__ fac32, int64_t off0,
-                                                     const float *__restrict__ sbuf,
-                                                     float *__restrict__ str32) {
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (t >= n) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int k = uniform(tasks[t].sphere), r = uniform(tasks[t].row);
-  const SphereMeta &m = meta[k];
-  const FactorSlot &f = fs[m.fid];
-  const int rank = m.rank;
-  const float *row = fac32 + (f.vt_off - off0) + (int64_t)r * f.cols;
-  const float *x = sbuf + m.s0;
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  int i = lane;
-  for (; i + 3 * kWave < rank; i += 4 * kWave) {
-    a0 = fmaf(row[i], x[i], a0);
-    a1 = fmaf(row[i + kWave], x[i + kWave], a1);
-    a2 = fmaf(row[i + 2 * kWave], x[i + 2 * kWave], a2);
-    a3 = fmaf(row[i + 3 * kWave], x[i + 3 * kWave], a3);
-  }
-  for (; i < rank; i += kWave) a0 = fmaf(row[i], x[i], a0);
-  float v = (a0 + a1) + (a2 + a3);
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if (lane == 0) {
-    const int jl = r / 3, c = r - 3 * (r / 3);   // contact-free: proxies only (block 0)
-    str32[3 * (m.k0[0] + jl) + c] = v;
-  }
-}
 
 __global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1038,23 +973,6 @@ hipError_t launch_reduce_epilogue(int64_t n3, int32_t ns, const double *part, in
   return hipGetLastError();
 }
 
-hipError_t launch_pinv_u32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
-                           const FactorSlot *fs, const float *fac32, int64_t off0,
-                           const double *mu, float *sbuf, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pinv_u32, dim3(blocks_for(n, kWavesPerBlock)), dim3(kBlock), 0, s, tasks, n,
-                     meta, fs, fac32, off0, mu, sbuf);
-  return hipGetLastError();
-}
-
-hipError_t launch_pinv_v32(const RowTask *tasks, int64_t n, const SphereMeta *meta,
-                           const FactorSlot *fs, const float *fac32, int64_t off0,
-                           const float *sbuf, float *str32, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pinv_v32, dim3(blocks_for(n, kWavesPerBlock)), dim3(kBlock), 0, s, tasks, n,
-                     meta, fs, fac32, off0, sbuf, str32);
-  return hipGetLastError();
-}
 
 hipError_t launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -1890,7 +1808,156 @@ __global__ __launch_bounds__(kBlock) void k_pinv_shared_v(const int32_t *__restr
       }
 }
 
+// The same two GEMMs in FP32 for the mixed form, on v_mfma_f32_16x16x4f32
+// with FP32 accumulation.  Its operands take the layout of the FP64 form
+// (lane l supplies A[i0 + l%16][k] and B[k][j0 + l%16] for k-slot l/16), but
+// its result differs (measured on the device): register v of lane l holds
+// C[i0 + 4 (l/16) + v][j0 + l%16].  B columns of another type are rounded
+// to FP32 as they are loaded.  Successive 16-wide k chunks go to four
+// accumulator sets in turn, added pairwise at the end: the shared factor's
+// small singular values amplify rounding, and four shorter FP32 sums keep
+// it near that of a strided dot product rather than one K/4-long chain.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kAccSets = 4;
+
+struct TileTN32 {
+  f32x4 acc[2][2];
+};
+
+template <typename TB>
+__device__ __forceinline__ void mfma_tile_tn32(const float *const arow[2], const bool aok[2],
+                                               const TB *const bcol[2], const bool bok[2],
+                                               int64_t K, TileTN32 &t) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  f32x4 acc[kAccSets][2][2];
+#pragma unroll
+  for (int u = 0; u < kAccSets; ++u)
+#pragma unroll
+    for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) acc[u][ia][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t kb = 0; kb < K; kb += 16 * kAccSets) {
+#pragma unroll
+    for (int u = 0; u < kAccSets; ++u) {
+      const int64_t kc = kb + 16 * u;
+      float a[2][4], b[2][4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t k = kc + 4 * g + s;
+        const bool kin = k < K;
+#pragma unroll
+        for (int ia = 0; ia < 2; ++ia) a[ia][s] = (aok[ia] && kin) ? arow[ia][k] : 0.f;
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) b[jb][s] = (bok[jb] && kin) ? (float)bcol[jb][k] : 0.f;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+          for (int jb = 0; jb < 2; ++jb)
+            acc[u][ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ia][s], b[jb][s], acc[u][ia][jb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+      t.acc[ia][jb] = (acc[0][ia][jb] + acc[1][ia][jb]) + (acc[2][ia][jb] + acc[3][ia][jb]);
+}
+
+// s32 at each free sphere's s0 = Sigma^-1 U_0^T mu (FP32 copy fac32 of
+// factor 0, whose FP64 offsets start at off0).
+__global__ __launch_bounds__(kBlock) void k_pinv_shared_u32(const int32_t *__restrict__ free_ids,
+                                                            int32_t n_free,
+                                                            const SphereMeta *__restrict__ meta,
+                                                            const FactorSlot *__restrict__ fs,
+                                                            const float *__restrict__ fac32,
+                                                            int64_t off0,
+                                                            const double *__restrict__ mu,
+                                                            float *__restrict__ s32) {
+  const int lane = threadIdx.x & 63;
+  const FactorSlot &f = fs[0];
+  const int rank = f.rank;
+  const int r0 = ((int)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave)) * 32;
+  const int q0 = blockIdx.y * 32;
+  if (r0 >= rank) return;
+  const float *arow[2];
+  const double *bcol[2];
+  bool aok[2], bok[2];
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
+    aok[h] = r < rank;
+    bok[h] = q < n_free;
+    arow[h] = fac32 + (f.u_off - off0) + (int64_t)(aok[h] ? r : 0) * f.rows;
+    bcol[h] = mu + 3 * meta[free_ids[bok[h] ? q : 0]].t0;
+  }
+  TileTN32 tile;
+  mfma_tile_tn32(arow, aok, bcol, bok, f.rows, tile);
+  const float *sig = fac32 + (f.sig_off - off0);
+  for (int ia = 0; ia < 2; ++ia)
+    for (int jb = 0; jb < 2; ++jb)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * ia + 4 * (lane >> 4) + v, q = q0 + 16 * jb + (lane & 15);
+        if (r < rank && q < n_free) s32[meta[free_ids[q]].s0 + r] = tile.acc[ia][jb][v] / sig[r];
+      }
+}
+
+// FP32 proxy strengths of every free sphere: str32 = V_0 s32 (contact-free
+// spheres have proxies only).
+__global__ __launch_bounds__(kBlock) void k_pinv_shared_v32(const int32_t *__restrict__ free_ids,
+                                                            int32_t n_free,
+                                                            const SphereMeta *__restrict__ meta,
+                                                            const FactorSlot *__restrict__ fs,
+                                                            const float *__restrict__ fac32,
+                                                            int64_t off0,
+                                                            const float *__restrict__ s32,
+                                                            float *__restrict__ str32) {
+  const int lane = threadIdx.x & 63;
+  const FactorSlot &f = fs[0];
+  const int rows = f.cols;
+  const int r0 = ((int)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave)) * 32;
+  const int q0 = blockIdx.y * 32;
+  if (r0 >= rows) return;
+  const float *arow[2], *bcol[2];
+  bool aok[2], bok[2];
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
+    aok[h] = r < rows;
+    bok[h] = q < n_free;
+    arow[h] = fac32 + (f.vt_off - off0) + (int64_t)(aok[h] ? r : 0) * f.cols;
+    bcol[h] = s32 + meta[free_ids[bok[h] ? q : 0]].s0;
+  }
+  TileTN32 tile;
+  mfma_tile_tn32(arow, aok, bcol, bok, f.rank, tile);
+  for (int ia = 0; ia < 2; ++ia)
+    for (int jb = 0; jb < 2; ++jb)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * ia + 4 * (lane >> 4) + v, q = q0 + 16 * jb + (lane & 15);
+        if (r < rows && q < n_free) {
+          const SphereMeta &m = meta[free_ids[q]];
+          str32[3 * (m.k0[0] + r / 3) + r % 3] = tile.acc[ia][jb][v];
+        }
+      }
+}
+
 }  // namespace
+
+hipError_t launch_pinv_shared32(const int32_t *free_ids, int32_t n_free, int32_t rank, int32_t cols,
+                                const SphereMeta *meta, const FactorSlot *fs, const float *fac32,
+                                int64_t off0, const double *mu, float *s32, float *str32,
+                                hipStream_t s) {
+  if (n_free <= 0 || rank <= 0) return hipSuccess;
+  const unsigned qt = (unsigned)((n_free + 31) / 32);
+  const unsigned gu = (unsigned)(((rank + 31) / 32 + kWavesPerBlock - 1) / kWavesPerBlock);
+  const unsigned gv = (unsigned)(((cols + 31) / 32 + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(k_pinv_shared_u32, dim3(gu, qt), dim3(kBlock), 0, s, free_ids, n_free, meta, fs,
+                     fac32, off0, mu, s32);
+  hipLaunchKernelGGL(k_pinv_shared_v32, dim3(gv, qt), dim3(kBlock), 0, s, free_ids, n_free, meta, fs,
+                     fac32, off0, s32, str32);
+  return hipGetLastError();
+}
 
 hipError_t launch_pinv_shared(const int32_t *free_ids, int32_t n_free, int32_t rank, int32_t cols,
                               const SphereMeta *meta, const FactorSlot *fs, const double *fac,
