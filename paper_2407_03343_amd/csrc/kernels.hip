@@ -1263,39 +1263,47 @@ struct AccB {
   double a[kTpl][kRun][3];
 };
 
+// As the pair functions of the single-vector sum, every pair adds twice its
+// velocity (Y = 2/|r| from rsq2_f64; the Stokeslet's r.f is formed with
+// g = f/4), and the tile's sums are halved once when stored.  Source indices
+// fit in 32 bits and the bounds are wave-uniform, so the loop test runs on
+// the scalar unit.
 template <int kTpl, int kRun, int kKind>
-__device__ __forceinline__ void run_sources_block(const double *__restrict__ src,
-                                                  const double *__restrict__ lamb, int32_t nrhs,
-                                                  int q0, int64_t j0, int64_t j1,
+__device__ __forceinline__ void run_sources_block(const double *__restrict__ src_,
+                                                  const double *__restrict__ lamb_, int32_t nrhs,
+                                                  int q0, int64_t j0_, int64_t j1_,
                                                   AccB<kTpl, kRun> &A) {
-  for (int64_t j = j0; j < j1; ++j) {
-    const double *ps = src + 3 * j;
-    const double *pf = lamb + (j * nrhs + q0) * 3;
+  const ConstPtr src = (ConstPtr)src_, lamb = (ConstPtr)lamb_;
+  const int j1 = uniform((int)j1_);
+  for (int j = uniform((int)j0_); j < j1; ++j) {
+    const ConstPtr ps = src + 3 * j;
+    const ConstPtr pf = lamb + ((int64_t)j * nrhs + q0) * 3;
     const double sx = ps[0], sy = ps[1], sz = ps[2];
-    double f[kRun][3];
+    double f[kRun][3], g[kRun][3];
 #pragma unroll
-    for (int q = 0; q < kRun; ++q) {
-      f[q][0] = pf[3 * q];
-      f[q][1] = pf[3 * q + 1];
-      f[q][2] = pf[3 * q + 2];
-    }
+    for (int q = 0; q < kRun; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        f[q][c] = pf[3 * q + c];
+        g[q][c] = quarter(f[q][c]);
+      }
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
       const double rx = A.tx[p] - sx, ry = A.ty[p] - sy, rz = A.tz[p] - sz;
       const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const double ri = rsqrt_f64(r2);
-      const double ri2 = ri * ri;
+      const double Y = rsq2_f64(r2);
+      const double Y2 = Y * Y;
       if (kKind == 0) {
 #pragma unroll
         for (int q = 0; q < kRun; ++q) {
-          const double rf = fma(rx, f[q][0], fma(ry, f[q][1], rz * f[q][2]));
-          const double t = rf * ri2;
-          A.a[p][q][0] = fma(fma(rx, t, f[q][0]), ri, A.a[p][q][0]);
-          A.a[p][q][1] = fma(fma(ry, t, f[q][1]), ri, A.a[p][q][1]);
-          A.a[p][q][2] = fma(fma(rz, t, f[q][2]), ri, A.a[p][q][2]);
+          const double rg = fma(rx, g[q][0], fma(ry, g[q][1], rz * g[q][2]));
+          const double t = rg * Y2;
+          A.a[p][q][0] = fma(fma(rx, t, f[q][0]), Y, A.a[p][q][0]);
+          A.a[p][q][1] = fma(fma(ry, t, f[q][1]), Y, A.a[p][q][1]);
+          A.a[p][q][2] = fma(fma(rz, t, f[q][2]), Y, A.a[p][q][2]);
         }
       } else if (kKind == 1) {
-        const double c = ri2 * ri;
+        const double c = (0.25 * Y) * Y2;                 // 2/|r|^3
 #pragma unroll
         for (int q = 0; q < kRun; ++q) {
           A.a[p][q][0] = fma(c, fma(f[q][1], rz, -f[q][2] * ry), A.a[p][q][0]);
@@ -1303,14 +1311,14 @@ __device__ __forceinline__ void run_sources_block(const double *__restrict__ src
           A.a[p][q][2] = fma(c, fma(f[q][0], ry, -f[q][1] * rx), A.a[p][q][2]);
         }
       } else {
-        const double ri3 = ri2 * ri;
-        const double ri5x3 = 3.0 * ri3 * ri2;
+        const double c3 = 0.25 * (Y2 * Y);               // 2/|r|^3
+        const double c5 = (0.75 * c3) * Y2;              // 6/|r|^5
 #pragma unroll
         for (int q = 0; q < kRun; ++q) {
-          const double bb = fma(rx, f[q][0], fma(ry, f[q][1], rz * f[q][2])) * ri5x3;
-          A.a[p][q][0] = fma(-f[q][0], ri3, fma(rx, bb, A.a[p][q][0]));
-          A.a[p][q][1] = fma(-f[q][1], ri3, fma(ry, bb, A.a[p][q][1]));
-          A.a[p][q][2] = fma(-f[q][2], ri3, fma(rz, bb, A.a[p][q][2]));
+          const double bb = fma(rx, f[q][0], fma(ry, f[q][1], rz * f[q][2])) * c5;
+          A.a[p][q][0] = fma(-f[q][0], c3, fma(rx, bb, A.a[p][q][0]));
+          A.a[p][q][1] = fma(-f[q][1], c3, fma(ry, bb, A.a[p][q][1]));
+          A.a[p][q][2] = fma(-f[q][2], c3, fma(rz, bb, A.a[p][q][2]));
         }
       }
     }
@@ -1368,9 +1376,9 @@ __global__ __launch_bounds__(kBlock) void k_direct_block(BlockDirectArgs A) {
         if (q0 + q >= A.nrhs) break;
         double *out = A.part + ((int64_t)blockIdx.y * A.nrhs + q0 + q) * A.T * 3;
         const int64_t o = 3 * ((int64_t)t0 + i);
-        out[o] = acc.a[p][q][0];
-        out[o + 1] = acc.a[p][q][1];
-        out[o + 2] = acc.a[p][q][2];
+        out[o] = 0.5 * acc.a[p][q][0];   // the pairs add twice the velocity
+        out[o + 1] = 0.5 * acc.a[p][q][1];
+        out[o + 2] = 0.5 * acc.a[p][q][2];
       }
     }
   }
