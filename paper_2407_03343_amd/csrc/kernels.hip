@@ -56,15 +56,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[kWavesPe
   for (int q = 0; q < NV; ++q) v[q] = sh[q][0];
 }
 
-// 1/sqrt(x) in FP64: the hardware estimate (about 24 correct bits) refined
-// by one Newton step y <- y + (y/2)(1 - x y^2), which leaves a relative
-// error of 1.5 e^2 (about 4e-15).
-__device__ __forceinline__ double rsqrt_f64(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double h = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, h, y);
-}
-
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
@@ -77,9 +68,10 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // concatenated ranges (split over sources), and the tile's own sphere is
 // cut out of each range (the identity self blocks of G_hat).
 
-// 2/sqrt(x): the Newton step y (3 - x y^2) from the hardware estimate y,
-// without its halving (3 VALU operations besides the rsq instead of 4).
-// Relative error as rsqrt_f64's.
+// 2/sqrt(x) in FP64: the hardware estimate y of 1/sqrt(x) (about 24 correct
+// bits) refined by one Newton step y (3 - x y^2) / 2 without its halving
+// (3 VALU operations besides the rsq instead of 4); relative error
+// 1.5 e^2 + a few ulp, about 4e-15.
 __device__ __forceinline__ double rsq2_f64(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   return y * fma(-x, y * y, 3.0);
