@@ -46,10 +46,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pk, stride: int):
+def cpu_baseline(pk, stride: int, two_sphere: bool = True):
     """The FP64 oracle's direct sum (its dominant step) on a bounded sample:
     every stride-th collocation node of the same workload against all
-    sources, same-sphere pairs skipped.  Returns pair-evals/s."""
+    sources, same-sphere pairs skipped.  Returns pair-evals/s, and with
+    two_sphere the oracle's two-sphere solve times."""
     from oracle import geometry as geo
     from oracle.pairsum import pairsum, build
     build(force=False)
@@ -62,10 +63,29 @@ def cpu_baseline(pk, stride: int):
     own = np.bincount(g.src_sphere, minlength=g.P)
     pairs = float(np.sum(g.S - own[g.target_sphere[rows]]))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=pairs / dt, unit="pair-evals/s", cores=cores, kind="oracle",
-                sample=(f"oracle C direct sum (OpenMP), {rows.size} of {g.T} collocation nodes "
-                        f"(every {stride}) x {g.S} sources, same-sphere pairs skipped: "
-                        f"{pairs:.3g} pairs in {dt:.1f} s"))
+    out = dict(value=pairs / dt, unit="pair-evals/s", cores=cores, kind="oracle",
+               sample=(f"oracle C direct sum (OpenMP), {rows.size} of {g.T} collocation nodes "
+                       f"(every {stride}) x {g.S} sources, same-sphere pairs skipped: "
+                       f"{pairs:.3g} pairs in {dt:.1f} s"))
+    if two_sphere:
+        out["two_sphere_solve"] = oracle_two_sphere()
+    return out
+
+
+def oracle_two_sphere():
+    """The oracle's complete solve of the two-sphere case (gap 0.01, FP64 to
+    1e-10), set-up (LAPACK SVDs) and solve timed apart: the CPU counterpart
+    of the benchmark's two-sphere section."""
+    from oracle import geometry as geo, mfs
+    from paper_2407_03343_amd import workloads as wl
+    pk, rbm = wl.workload_two_sphere_gap001()
+    t0 = time.perf_counter()
+    pb = mfs.Problem(geo.build(pk.centers, pk.radius)).setup()
+    t1 = time.perf_counter()
+    o = mfs.solve_resistance(pb, rbm[0], tol=1e-10)
+    t2 = time.perf_counter()
+    return dict(setup_s=t1 - t0, solve_ms=(t2 - t1) * 1e3, iterations=int(o["iterations"]),
+                force_sphere0=[float(x) for x in o["ft"][0, :3]])
 
 
 FORMS = (("fp64", 0), ("mixed", 1), ("mixed_far", 2))   # SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR
@@ -603,7 +623,7 @@ def main():
         result["serving"] = serving(args, torch, smfs, reqs, arrivals)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(pk, args.cpu_stride)
+        result["cpu_baseline"] = cpu_baseline(pk, args.cpu_stride, two_sphere=args.two_sphere_reps > 0)
     print(json.dumps(result), flush=True)
 
 
