@@ -526,21 +526,34 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
   const int32_t nch = mdot_chunks(n);
   double *part = pb.d_red;                                // 2 nch (m + 2)
   double *hd = part + 2 * (int64_t)nch * (m + 2);         // V^T q_j | V^T w, 2 (m + 2)
-  double *coef = hd + 2 * (m + 2);                        // s | z, 2 (m + 2)
+  double *coef = hd + 2 * (m + 2);                        // [1/nu, gam, nu] of the step
   double *cf = coef + 2 * (m + 2);                        // solution coefficients, m + 2
   double *scal = cf + (m + 2);                            // [0] norm of p, [1] other norms
   double *upart = scal + 8;                               // kUpdParts
-  const size_t pin_n = 2 * (size_t)(m + 2) + 8;
+  // The host keeps up to kAhead steps behind the device: each step's dot
+  // products, its (nu, gam) and the norm of the previous p go to a pinned
+  // ring slot, and the Hessenberg column and Givens rotations of a step are
+  // formed from its slot once its copy has landed.  Steps enqueued past the
+  // one that stops the cycle only touch basis vectors beyond the solution.
+  constexpr int kAhead = 2, kRing = kAhead + 2;
+  const size_t slot_n = 2 * (size_t)(m + 2) + 8;
   double *hpin = nullptr;
-  SMFS_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * pin_n, hipHostMallocDefault));
+  SMFS_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * slot_n * kRing, hipHostMallocDefault));
+  std::vector<hipEvent_t> ev(kRing, nullptr);
   struct Free {
     double *p;
-    ~Free() { if (p) (void)hipHostFree(p); }
-  } guard{hpin};
+    std::vector<hipEvent_t> *e;
+    ~Free() {
+      if (p) (void)hipHostFree(p);
+      for (hipEvent_t x : *e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } guard{hpin, &ev};
+  for (auto &e : ev) SMFS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   // Hraw: the Hessenberg matrix as built (column-major, m+1 rows); R: its
   // rotated copy for the least-squares problem
   std::vector<double> Hraw((size_t)(m + 1) * m, 0.0), R((size_t)(m + 1) * m, 0.0), cs(m), sn(m),
-      g(m + 1), y(m), cvec(m + 1), sz(2 * (size_t)(m + 2));
+      g(m + 1), y(m), cvec(m + 1);
   auto Hc = [&](std::vector<double> &M, int row, int col) -> double & { return M[(size_t)col * (m + 1) + row]; };
 
   SMFS_HIP(launch_fill(n, 0.0, x, s));
@@ -555,6 +568,7 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
   }
   SMFS_HIP(hipMemcpyAsync(r, b, 8 * n, hipMemcpyDeviceToDevice, s));
   double beta = bnorm;
+  int enq_applies = 0;   // products enqueued (st.applies counts those the solve used)
   while (true) {
     // V[0] = r / beta (final: it needs no second pass)
     SMFS_HIP(hipMemcpyAsync(V, r, 8 * n, hipMemcpyDeviceToDevice, s));
@@ -563,33 +577,26 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
     std::fill(Hraw.begin(), Hraw.end(), 0.0);
     g[0] = beta;
     int jdone = 0;   // columns of H final in this cycle
-    bool stop = false;
-    for (int j = 0;; ++j) {
-      const bool last = j == m || (st.applies >= max_it && j > 0);
-      double *qj = V + (int64_t)j * ld, *wj = V + (int64_t)(j + 1) * ld;
-      if (!last) {
-        int rc = op(qj, wj, precision);
-        if (rc) return rc;
-        ++st.applies;
-      }
-      const int nv = j + 1;
-      SMFS_HIP(launch_mdot2(V, ld, nv, qj, last ? qj : wj, n, part, nch, hd, s));
-      SMFS_HIP(hipMemcpyAsync(hpin, hd, 8 * 2 * (size_t)nv, hipMemcpyDeviceToHost, s));
-      SMFS_HIP(hipMemcpyAsync(hpin + 2 * (m + 2), scal, 8, hipMemcpyDeviceToHost, s));
-      SMFS_HIP(hipStreamSynchronize(s));
-      const double *sv = hpin, *zv = hpin + nv;   // V^T q_j, V^T w
-      double nu = 1.0;
-      if (j > 0) {
-        double ss = 0.0;
-        for (int i = 0; i < j; ++i) ss += sv[i] * sv[i];
-        const double nu2 = sv[j] - ss;
-        nu = nu2 > 0.0 ? std::sqrt(nu2) : 0.0;
-        // finalise column j-1 (q_j reorthogonalised), rotate it
-        Hc(Hraw, j, j - 1) = hpin[2 * (m + 2)];   // ||p|| of the previous step
-        for (int i = 0; i < j; ++i) Hc(Hraw, i, j - 1) += Hc(Hraw, j, j - 1) * sv[i];
-        Hc(Hraw, j, j - 1) *= nu;
-        const int c = j - 1;
-        for (int i = 0; i <= j; ++i) Hc(R, i, c) = Hc(Hraw, i, c);
+    bool stop = false, cycle_end = false;
+    int next = 0;    // next step to process on the host
+    int last_j = -1; // the step that closes the cycle, once enqueued
+    std::vector<int> applies_at(m + 2, 0);
+    // host side of step jp (the arithmetic of the synchronous form)
+    auto process = [&](int jp) -> int {
+      double *slot = hpin + (size_t)(jp % kRing) * slot_n;
+      SMFS_HIP(hipEventSynchronize(ev[jp % kRing]));
+      const int nv = jp + 1;
+      const double *sv = slot, *zv = slot + nv;   // V^T q_j, V^T w
+      const double pnorm = slot[2 * (m + 2)], inv_nu = slot[2 * (m + 2) + 1],
+                   gam = slot[2 * (m + 2) + 2], nu = slot[2 * (m + 2) + 3];
+      (void)inv_nu;
+      if (jp > 0) {
+        // finalise column jp-1 (q_jp reorthogonalised), rotate it
+        Hc(Hraw, jp, jp - 1) = pnorm;   // ||p|| of the previous step
+        for (int i = 0; i < jp; ++i) Hc(Hraw, i, jp - 1) += Hc(Hraw, jp, jp - 1) * sv[i];
+        Hc(Hraw, jp, jp - 1) *= nu;
+        const int c = jp - 1;
+        for (int i = 0; i <= jp; ++i) Hc(R, i, c) = Hc(Hraw, i, c);
         double *col = &R[(size_t)c * (m + 1)];
         for (int i = 0; i < c; ++i) {
           const double t = cs[i] * col[i] + sn[i] * col[i + 1];
@@ -603,32 +610,56 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
         col[c + 1] = 0.0;
         g[c + 1] = -sn[c] * g[c];
         g[c] = cs[c] * g[c];
-        jdone = j;
+        jdone = jp;
         ++st.iterations;
+        st.applies = applies_at[jp];
         st.rel_residual = std::fabs(g[c + 1]) / bnorm;
-        if (st.rel_residual <= tol) { st.converged = true; stop = true; break; }
-        if (nu == 0.0) { stop = true; break; }   // q_j lies in the span: exact solution
-        if (st.applies >= max_it && last) { stop = true; break; }
-        if (last) break;                          // end of the cycle
+        if (st.rel_residual <= tol) { st.converged = true; stop = true; return SMFS_OK; }
+        if (nu == 0.0) { stop = true; return SMFS_OK; }   // q_j lies in the span: exact solution
+        if (jp == last_j) {
+          if (st.applies >= max_it) stop = true;
+          cycle_end = true;                                // end of the cycle
+          return SMFS_OK;
+        }
       }
-      // coefficients of the step: s (second pass of q_j), z (first pass of w)
-      double sz_dot = 0.0;
-      for (int i = 0; i < j; ++i) sz_dot += sv[i] * zv[i];
-      const double gam = (zv[j] - sz_dot) / nu;
-      // c = Hraw[0..j, 0..j-1] s: the part of A q_j carried by the old q_j
-      std::fill(cvec.begin(), cvec.begin() + j + 1, 0.0);
-      for (int k = 0; k < j; ++k)
+      // column jp of Hraw: c = Hraw[0..jp, 0..jp-1] s, the part of A q_jp
+      // carried by the old q_jp
+      std::fill(cvec.begin(), cvec.begin() + jp + 1, 0.0);
+      for (int k = 0; k < jp; ++k)
         for (int i = 0; i <= k + 1; ++i) cvec[i] += Hc(Hraw, i, k) * sv[k];
-      for (int i = 0; i < j; ++i) Hc(Hraw, i, j) = (zv[i] - cvec[i]) / nu;
-      Hc(Hraw, j, j) = (gam - cvec[j]) / nu;
-      for (int i = 0; i < j; ++i) {
-        sz[i] = sv[i];
-        sz[(m + 2) + i] = zv[i];
+      for (int i = 0; i < jp; ++i) Hc(Hraw, i, jp) = (zv[i] - cvec[i]) / nu;
+      Hc(Hraw, jp, jp) = (gam - cvec[jp]) / nu;
+      return SMFS_OK;
+    };
+    for (int j = 0; !stop && !cycle_end; ++j) {
+      const bool last = j == m || (enq_applies >= max_it && j > 0);
+      double *qj = V + (int64_t)j * ld, *wj = V + (int64_t)(j + 1) * ld;
+      if (!last) {
+        int rc = op(qj, wj, precision);
+        if (rc) return rc;
+        ++enq_applies;
       }
-      if (j > 0) SMFS_HIP(hipMemcpyAsync(coef, sz.data(), 8 * 2 * (size_t)(m + 2), hipMemcpyHostToDevice, s));
-      SMFS_HIP(launch_dcgs_update(V, ld, j, coef, coef + (m + 2), qj, wj, nu, gam, n, upart, kUpdParts,
-                                  scal, s));
-      // the host copy of sz must outlive the upload: the next step synchronises first
+      applies_at[j] = enq_applies;
+      // the slot of step j is free: step j - kRing was processed (the host
+      // stays at most kAhead steps behind)
+      const int nv = j + 1;
+      double *slot = hpin + (size_t)(j % kRing) * slot_n;
+      SMFS_HIP(launch_mdot2(V, ld, nv, qj, last ? qj : wj, n, part, nch, hd, s));
+      SMFS_HIP(launch_dcgs_coeffs(hd, j, coef, s));
+      SMFS_HIP(hipMemcpyAsync(slot, hd, 8 * 2 * (size_t)nv, hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipMemcpyAsync(slot + 2 * (m + 2), scal, 8, hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipMemcpyAsync(slot + 2 * (m + 2) + 1, coef, 8 * 3, hipMemcpyDeviceToHost, s));
+      SMFS_HIP(hipEventRecord(ev[j % kRing], s));
+      if (last) last_j = j;
+      else
+        SMFS_HIP(launch_dcgs_update(V, ld, j, hd, hd + nv, qj, wj, coef, n, upart, kUpdParts, scal, s));
+      // process what the device has (or must have) finished
+      while (next <= j && !stop && !cycle_end &&
+             (last || j - next >= kAhead || hipEventQuery(ev[next % kRing]) == hipSuccess)) {
+        int rc = process(next);
+        if (rc) return rc;
+        ++next;
+      }
     }
     // y = R^-1 g (upper triangular), x += V y
     for (int i = jdone - 1; i >= 0; --i) {
@@ -644,6 +675,7 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
     int rc = op(x, w, precision);
     if (rc) return rc;
     ++st.applies;
+    enq_applies = st.applies;
     SMFS_HIP(launch_sub(n, b, w, r, s));
     SMFS_HIP(launch_norm2(r, n, part, nch, scal + 1, s));
     SMFS_HIP(hipMemcpyAsync(hpin, scal + 1, 8, hipMemcpyDeviceToHost, s));

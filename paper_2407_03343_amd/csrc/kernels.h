@@ -113,10 +113,15 @@ hipError_t launch_norm_scale(double *w, int64_t n, double *part, int32_t nchunks
 // over V[0..nv) (part: at least 2 nv nchunks doubles).
 hipError_t launch_mdot2(const double *V, int64_t ld, int32_t nv, const double *a, const double *b,
                         int64_t n, double *part, int32_t nchunks, double *out, hipStream_t s);
-// q <- (q - V cs) / nu, w <- (w - V cz - q gam) / nu over V[0..nb), then
-// norm[0] = ||w|| and w /= norm[0] (part: nparts doubles).
+// From h = [V^T q | V^T w] over V[0..j] (2 (j+1) values): out = [1/nu, gam, nu]
+// with nu = sqrt(h_j - sum_{i<j} h_i^2) (1 for j = 0; 0 if not positive)
+// and gam = (h_{j+1+j} - sum_{i<j} h_i h_{j+1+i}) / nu.
+hipError_t launch_dcgs_coeffs(const double *h, int32_t j, double *out, hipStream_t s);
+// q <- (q - V cs) / nu, w <- (w - V cz - q gam) / nu over V[0..nb) with
+// coeffs = [1/nu, gam] on the device, then norm[0] = ||w|| and w /= norm[0]
+// (part: nparts doubles).
 hipError_t launch_dcgs_update(const double *V, int64_t ld, int32_t nb, const double *cs,
-                              const double *cz, double *q, double *w, double nu, double gam, int64_t n,
+                              const double *cz, double *q, double *w, const double *coeffs, int64_t n,
                               double *part, int32_t nparts, double *norm, hipStream_t s);
 // y = a*x + b*y ; x,y length n (a, b host scalars)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);

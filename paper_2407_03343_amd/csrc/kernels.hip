@@ -837,16 +837,40 @@ __global__ __launch_bounds__(kBlock) void k_mdot2(const double *__restrict__ V, 
   }
 }
 
+// The scalars of a delayed Gram-Schmidt step from the dot products
+// h = [V^T q (nv) | V^T w (nv)] with nv = j + 1 (one thread, the sums in
+// index order): nu = sqrt(h_j - sum_{i<j} h_i^2) (1 for j = 0, 0 if the
+// difference is not positive), gam = (h_{nv+j} - sum_{i<j} h_i h_{nv+i}) / nu;
+// out = [1/nu, gam, nu].
+__global__ void k_dcgs_coeffs(const double *__restrict__ h, int32_t j, double *__restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const int nv = j + 1;
+  double nu = 1.0;
+  if (j > 0) {
+    double ss = 0.0;
+    for (int i = 0; i < j; ++i) ss += h[i] * h[i];
+    const double nu2 = h[j] - ss;
+    nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+  }
+  double sz = 0.0;
+  for (int i = 0; i < j; ++i) sz += h[i] * h[nv + i];
+  out[0] = 1.0 / nu;
+  out[1] = (h[nv + j] - sz) / nu;
+  out[2] = nu;
+}
+
 // q <- (q - V cs) / nu ;  w <- (w - V cz - q gam) / nu over V[0..nb), one
-// read of the basis; part[block] = sum of the new w^2 over the block.
+// read of the basis (coeffs = [1/nu, gam] on the device); part[block] = sum
+// of the new w^2 over the block.
 __global__ __launch_bounds__(kBlock) void k_dcgs_update(const double *__restrict__ V, int64_t ld,
                                                         int32_t nb, const double *__restrict__ cs,
                                                         const double *__restrict__ cz,
                                                         double *__restrict__ q,
-                                                        double *__restrict__ w, double inv_nu,
-                                                        double gam, int64_t n,
-                                                        double *__restrict__ part) {
+                                                        double *__restrict__ w,
+                                                        const double *__restrict__ coeffs,
+                                                        int64_t n, double *__restrict__ part) {
   __shared__ double sh[1][kWavesPerBlock];
+  const double inv_nu = coeffs[0], gam = coeffs[1];
   double acc[1] = {0.0};
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     double s1[2] = {0.0, 0.0}, s2[2] = {0.0, 0.0};
@@ -1075,11 +1099,16 @@ hipError_t launch_mdot2(const double *V, int64_t ld, int32_t nv, const double *a
   return hipGetLastError();
 }
 
+hipError_t launch_dcgs_coeffs(const double *h, int32_t j, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_coeffs, dim3(1), dim3(kWave), 0, s, h, j, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_dcgs_update(const double *V, int64_t ld, int32_t nb, const double *cs,
-                              const double *cz, double *q, double *w, double nu, double gam, int64_t n,
+                              const double *cz, double *q, double *w, const double *coeffs, int64_t n,
                               double *part, int32_t nparts, double *norm, hipStream_t s) {
   const unsigned g = (unsigned)std::min<int64_t>(nparts, blocks_for(n));
-  hipLaunchKernelGGL(k_dcgs_update, dim3(g), dim3(kBlock), 0, s, V, ld, nb, cs, cz, q, w, 1.0 / nu, gam, n,
+  hipLaunchKernelGGL(k_dcgs_update, dim3(g), dim3(kBlock), 0, s, V, ld, nb, cs, cz, q, w, coeffs, n,
                      part);
   hipLaunchKernelGGL(k_sqrt_final, dim3(1), dim3(kBlock), 0, s, part, (int32_t)g, norm, nullptr);
   hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, w, n, norm);
