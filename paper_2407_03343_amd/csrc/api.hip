@@ -31,7 +31,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Source splits of the direct sum: enough blocks (about 32768, i.e. 128 per
 // CU; measured best among 8192/16384/32768) to keep every SIMD busy to the
 // end of the launch and balance the tail, while each split still streams at
-// least 1024 sources.
+// least 64 sources (small problems, e.g. two spheres with 1320 sources,
+// would otherwise run on one wave per tile).
 int32_t choose_splits(int64_t n_tiles, int64_t S) {
   const int64_t blocks = std::max<int64_t>(1, (n_tiles + 3) / 4);
   static const int64_t target = [] {
@@ -39,7 +40,7 @@ int32_t choose_splits(int64_t n_tiles, int64_t S) {
     return e ? std::max<int64_t>(256, std::atoll(e)) : (int64_t)32768;
   }();
   int64_t sp = (target + blocks - 1) / blocks;
-  sp = std::min<int64_t>(sp, std::max<int64_t>(1, S / 1024));
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, S / 64));
   sp = std::max<int64_t>(1, std::min<int64_t>(sp, 64));
   return (int32_t)sp;
 }
