@@ -1,0 +1,42 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU contract and the rate
+arithmetic of its kernel summaries."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_kernel_rates():
+    st = {"far32_launches": 4, "far32_ms": 30.0, "far32_flops": 5.0e11,
+          "mixed64_launches": 4, "mixed64_ms": 4.0, "mixed64_flops": 3.0e10,
+          "direct_launches": 0, "direct_ms": 0.0, "direct_flops": 0.0}
+    out = bench.mixed_kernel_rates(st)
+    assert set(out) == {"far32", "mixed64"}
+    far = out["far32"]
+    assert far["avg_launch_ms"] == pytest.approx(7.5)
+    assert far["achieved"] == pytest.approx(5.0e11 / 7.5e-3 / 1e12)
+    assert far["frac"] == pytest.approx(far["achieved"] / bench.PEAK_FP32_VALU_TFLOPS)
+    assert out["mixed64"]["peak"] == bench.PEAK_FP64_VALU_TFLOPS
+
+
+def test_traffic_constant_matches_counter_summary():
+    """The HBM traffic reported for the direct sum comes from the committed
+    rocprofv3 counter summary (FETCH_SIZE x 2 + WRITE_SIZE, KiB)."""
+    path = os.path.join(ROOT, "profiles", "k_direct_f64_cluster100_fp64_hbm_counters.md")
+    row = next(l for l in open(path) if l.startswith("| `k_direct_f64<2, false>`"))
+    fetch, write = (float(c.replace(" ", "")) for c in row.split("|")[2:4])
+    assert bench.DIRECT_TRAFFIC_BYTES == pytest.approx((2 * fetch + write) * 1024, rel=1e-5)
