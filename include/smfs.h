@@ -51,6 +51,9 @@ enum {
   SMFS_OK = 0,
   SMFS_NOT_CONVERGED = 1,          /* warning: statistics still filled in */
   SMFS_GAP_BELOW_VALIDATED = 2,    /* warning: some gap < 1e-3 radii */
+  SMFS_STAGNATED = 3,              /* warning: the FP64 true residual stopped falling above
+                                      gmres_tol (statistics filled in, the best iterate
+                                      returned) */
   SMFS_E_INVALID_ARG = -1,
   SMFS_E_OVERLAP = -2,             /* two spheres touch or overlap */
   SMFS_E_UNSUPPORTED = -3,         /* e.g. unequal radii */
@@ -91,6 +94,9 @@ typedef struct smfs_params {
   double gmres_tol;         /* relative residual target */
   int32_t gmres_max_it;
   int32_t gmres_restart;    /* Krylov vectors kept (sizes the workspace) */
+  int32_t gmres_check_every;/* true-residual guard period in iterations, active once the
+                               recursive estimate is below 1e-3; 0 = off.  Each check
+                               forms the iterate and costs one product with G_hat */
 } smfs_params;
 
 typedef struct smfs_sizes {
@@ -124,12 +130,15 @@ typedef struct smfs_out {
   int64_t pair_evals;       /* pair evaluations performed by the solve */
   int64_t pair_evals_f32;   /* of which evaluated in FP32 (mixed precision) */
   int32_t refinements;      /* FP64 residual refinement sweeps (mixed precision) */
+  int32_t true_checks;      /* true residuals taken by the guard (restarts included) */
+  int32_t floor_iteration;  /* iteration of the smallest true residual the guard saw, -1 if none */
+  double floor_rel_residual;/* that relative residual, -1 if none */
 } smfs_out;
 
 /* Defaults: N = 600, R_p = 0.7, 780 base nodes, 20 images of kinds S|R|D,
  * Delta = 0.05, image and near cutoffs 0.2, alpha = 6, beta = pi/5, pi/60,
  * left weights on, trunc 5e-12, mu = 1, 500 check points, FP64, tol 1e-10,
- * 1000 iterations, restart 400. */
+ * 1000 iterations, restart 400, true-residual guard every 25 iterations. */
 int smfs_params_default(smfs_params *p);
 
 /* Build the node sets on the host (Sections 2.1, 2.3, 5.1).
@@ -210,8 +219,13 @@ int smfs_eval_velocity(smfs_problem *pb, const double *lambda, int64_t n, const 
 
 /* Resistance solve: rbm [dev] P x 6 rigid-body velocities in, outputs per
  * smfs_out; the boundary data include the background flow if one is set
- * (smfs_set_background).  Returns NOT_CONVERGED (warning) if gmres_max_it
- * is reached.
+ * (smfs_set_background).  Returns SMFS_OK only when the FP64 true residual
+ * ||b - G_hat mu|| / ||b|| meets gmres_tol; SMFS_STAGNATED (warning) when it
+ * stopped falling above the tolerance (GMRES with a true-residual check,
+ * Section 2.2: the rounding of the truncated pseudo-inverses, Section 5,
+ * leaves a floor that the recursive estimate does not show); SMFS_NOT_CONVERGED
+ * (warning) when gmres_max_it is reached first.  Statistics are filled in for
+ * every warning.
  * With params.precision = SMFS_MIXED (or SMFS_MIXED_FAR) the products
  * inside GMRES take the sources of contact-free spheres in FP32 as described
  * at the precision modes, everything else in FP64; Arnoldi, the true
@@ -254,7 +268,7 @@ int smfs_block_workspace_bytes(const smfs_problem *pb, int32_t nrhs, int32_t res
                                size_t *bytes);
 
 /* y_q = G_hat mu_q for q < nrhs (eq. resistance with the identity self
- * blocks of Section 2.4), FP64.  mu, y [dev]: nrhs vectors of stride
+ * blocks of Section 2.2), FP64.  mu, y [dev]: nrhs vectors of stride
  * ld >= 3 T; mu and y must not overlap.  ws [dev]: at least
  * smfs_block_workspace_bytes(pb, nrhs, 0) bytes, 256-byte aligned. */
 int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y, int64_t ld,
@@ -297,7 +311,7 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
  * per request is the FP64 product and GMRES of smfs_solve_resistance, so a
  * result does not depend on which other requests share the launches.
  *
- * The shared factor of contact-free spheres (Section 2.4) depends only on
+ * The shared factor of contact-free spheres (Section 2.2, eq. transform) depends only on
  * the discretisation: the server factorises it once and copies it into each
  * request.  Serving is FP64; params->precision must be SMFS_FP64. */
 typedef struct smfs_server smfs_server;

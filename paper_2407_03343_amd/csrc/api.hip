@@ -123,7 +123,7 @@ size_t workspace_layout(Problem &pb, bool assign) {
   const int64_t ld = ((3 * T + 6 * (int64_t)P + 31) / 32) * 32;
   const int32_t m = std::max(1, pb.prm.gmres_restart);
   const size_t o_kry = take(sizeof(double) * ld * (m + 1));
-  const size_t o_vec = take(sizeof(double) * ld * 6);
+  const size_t o_vec = take(sizeof(double) * ld * 9);
   const int32_t nch = mdot_chunks(3 * T + 6 * (int64_t)P);
   const int64_t red = 2 * (int64_t)nch * (m + 2) + 6 * (m + 2) + 1024 + 64;
   const size_t o_red = take(sizeof(double) * red);
@@ -508,9 +508,18 @@ int eval_points(Problem &pb, const double *lam, int64_t n, const double *x, doub
 struct GmresStats {
   int iterations = 0;           // Krylov dimension reached (summed over cycles)
   int applies = 0;              // products with the operator
+  int check_applies = 0;        // products spent on true-residual checks
   double rel_residual = 0.0;
   bool converged = false;
+  bool stagnated = false;       // stopped: the true residual no longer falls
+  int true_checks = 0;          // true-residual checks made
+  int floor_it = -1;            // iteration of the smallest true residual checked
+  double floor_rel = -1.0;      // that residual (relative)
 };
+
+// The true-residual guard starts once the recursive estimate is below this
+// level: above it the estimate and the true residual agree to many digits.
+constexpr double kGuardStart = 1e-3;
 
 // y = A x for the system being solved (precision of the product given).
 using Operator = std::function<int(const double *, double *, int)>;
@@ -518,12 +527,14 @@ using Operator = std::function<int(const double *, double *, int)>;
 constexpr int32_t kUpdParts = 1024;   // partial sums of the fused update
 
 int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x, GmresStats &st,
-          int precision, double tol, int max_it, hipStream_t s) {
+          int precision, double tol, int max_it, int check_every, hipStream_t s) {
   const int64_t ld = pb.kry_ld;
   const int m = pb.kry_vecs - 1;
   double *V = pb.d_kry;
   double *w = pb.d_vec;           // scratch vector
   double *r = pb.d_vec + ld;      // residual
+  // true-residual guard: trial iterate, its residual, best iterate so far
+  double *xt = pb.d_vec + 6 * ld, *wt = pb.d_vec + 7 * ld, *xbest = pb.d_vec + 8 * ld;
   const int32_t nch = mdot_chunks(n);
   double *part = pb.d_red;                                // 2 nch (m + 2)
   double *hd = part + 2 * (int64_t)nch * (m + 2);         // V^T q_j | V^T w, 2 (m + 2)
@@ -539,7 +550,9 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
   constexpr int kAhead = 2, kRing = kAhead + 2;
   const size_t slot_n = 2 * (size_t)(m + 2) + 8;
   double *hpin = nullptr;
-  SMFS_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * slot_n * kRing, hipHostMallocDefault));
+  // kRing step slots, then the guard's coefficients (m + 2) and its norm
+  SMFS_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * (slot_n * kRing + m + 3), hipHostMallocDefault));
+  double *hchk = hpin + slot_n * kRing;
   std::vector<hipEvent_t> ev(kRing, nullptr);
   struct Free {
     double *p;
@@ -570,6 +583,20 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
   SMFS_HIP(hipMemcpyAsync(r, b, 8 * n, hipMemcpyDeviceToDevice, s));
   double beta = bnorm;
   int enq_applies = 0;   // products enqueued (st.applies counts those the solve used)
+  double prev_check = -1.0;   // true residual at the previous in-cycle check
+  int last_check_it = 0;
+  bool use_best = false;      // the solve ends on xbest rather than on x + V y
+  // Records a true residual tr of the iterate in xt (or in x when at_x);
+  // keeps the best iterate in xbest.
+  auto record_true = [&](double tr, bool at_x) -> int {
+    ++st.true_checks;
+    if (st.floor_rel < 0 || tr < st.floor_rel) {
+      st.floor_rel = tr;
+      st.floor_it = st.iterations;
+      SMFS_HIP(hipMemcpyAsync(xbest, at_x ? x : xt, 8 * n, hipMemcpyDeviceToDevice, s));
+    }
+    return SMFS_OK;
+  };
   while (true) {
     // V[0] = r / beta (final: it needs no second pass)
     SMFS_HIP(hipMemcpyAsync(V, r, 8 * n, hipMemcpyDeviceToDevice, s));
@@ -617,6 +644,42 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
         st.rel_residual = std::fabs(g[c + 1]) / bnorm;
         if (st.rel_residual <= tol) { st.converged = true; stop = true; return SMFS_OK; }
         if (nu == 0.0) { stop = true; return SMFS_OK; }   // q_j lies in the span: exact solution
+        // Guard: every check_every iterations once the estimate is small,
+        // form the iterate, apply the operator and take the true residual.
+        // Rounding of the truncated pseudo-inverses leaves a floor that the
+        // recursive estimate does not see; once the true residual stops
+        // falling (less than halved since the last check) while the
+        // estimate runs ahead of it by a factor of ten, the solve stops on
+        // the best iterate checked.
+        if (check_every > 0 && st.rel_residual <= kGuardStart &&
+            st.iterations - last_check_it >= check_every) {
+          last_check_it = st.iterations;
+          const int nj = jdone;
+          for (int i = nj - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int c2 = i + 1; c2 < nj; ++c2) t -= Hc(R, i, c2) * hchk[c2];
+            hchk[i] = t / Hc(R, i, i);
+          }
+          SMFS_HIP(hipMemcpyAsync(cf, hchk, 8 * (size_t)nj, hipMemcpyHostToDevice, s));
+          SMFS_HIP(hipMemcpyAsync(xt, x, 8 * n, hipMemcpyDeviceToDevice, s));
+          SMFS_HIP(launch_combine(V, ld, nj, cf, xt, n, s));
+          int rc = op(xt, wt, precision);
+          if (rc) return rc;
+          ++st.check_applies;
+          SMFS_HIP(launch_sub(n, b, wt, wt, s));
+          SMFS_HIP(launch_norm2(wt, n, part, nch, scal + 4, s));
+          SMFS_HIP(hipMemcpyAsync(hchk + m + 2, scal + 4, 8, hipMemcpyDeviceToHost, s));
+          SMFS_HIP(hipStreamSynchronize(s));
+          const double tr = hchk[m + 2] / bnorm;
+          if ((rc = record_true(tr, false))) return rc;
+          if (tr <= tol) { st.converged = true; stop = use_best = true; return SMFS_OK; }
+          if (prev_check > 0 && tr > 0.5 * prev_check && st.rel_residual < 0.1 * tr) {
+            st.stagnated = true;
+            stop = use_best = true;
+            return SMFS_OK;
+          }
+          prev_check = tr;
+        }
         if (jp == last_j) {
           if (st.applies >= max_it) stop = true;
           cycle_end = true;                                // end of the cycle
@@ -662,6 +725,11 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
         ++next;
       }
     }
+    if (use_best) {   // the guard ended the solve on a checked iterate
+      SMFS_HIP(hipMemcpyAsync(x, xbest, 8 * n, hipMemcpyDeviceToDevice, s));
+      SMFS_HIP(hipStreamSynchronize(s));
+      return SMFS_OK;
+    }
     // y = R^-1 g (upper triangular), x += V y
     for (int i = jdone - 1; i >= 0; --i) {
       double t = g[i];
@@ -686,6 +754,20 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
       st.converged = true;
       st.rel_residual = beta / bnorm;
       return SMFS_OK;
+    }
+    if (check_every > 0) {
+      // a restart is a true-residual check: a cycle that brought it no
+      // lower than 0.9 of the best seen ends the solve on the best iterate
+      const double tr = beta / bnorm, best = st.floor_rel;
+      int rc = record_true(tr, true);
+      if (rc) return rc;
+      if (best > 0 && tr > 0.9 * best) {
+        st.stagnated = true;
+        st.rel_residual = tr;
+        SMFS_HIP(hipMemcpyAsync(x, xbest, 8 * n, hipMemcpyDeviceToDevice, s));
+        SMFS_HIP(hipStreamSynchronize(s));
+        return SMFS_OK;
+      }
     }
   }
 }
@@ -721,6 +803,7 @@ int smfs_params_default(smfs_params *p) {
   p->gmres_tol = 1e-10;
   p->gmres_max_it = 1000;
   p->gmres_restart = 400;
+  p->gmres_check_every = 25;
   return SMFS_OK;
 }
 
@@ -733,7 +816,7 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
   *out = nullptr;
   if (p->n_proxy <= 0 || p->n_colloc_base <= 0 || p->gmres_restart > 20000 || !(p->proxy_radius > 0 && p->proxy_radius < 1) ||
       !(p->mu > 0) || !(p->trunc_rel >= 0) || p->gmres_restart <= 0 || p->gmres_max_it <= 0 ||
-      p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 ||
+      p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 || p->gmres_check_every < 0 ||
       !valid_precision(p->precision)) {
     set_error("smfs_problem_create: invalid parameter");
     return SMFS_E_INVALID_ARG;
@@ -1122,9 +1205,21 @@ struct SolveStats {
   int iterations = 0, refinements = 0;
   int applies = 0;              // products with the operator, in the solve's precision
   int applies64 = 0;            // FP64 true-residual products
-  bool converged = false;
+  bool converged = false;       // the FP64 true residual meets gmres_tol
+  bool stagnated = false;       // stopped at the true-residual floor above gmres_tol
+  int true_checks = 0, floor_it = -1;
+  double floor_rel = -1.0;
   double rel_residual = 0.0, res_norm = 0.0, rhs_norm = 0.0;
 };
+
+// Status of a finished solve: OK only when the FP64 true residual meets the
+// tolerance; STAGNATED when it stopped falling above it (the guard, or the
+// recursive estimate met the tolerance while the true residual did not);
+// NOT_CONVERGED when the iteration limit came first.
+int solve_status(const SolveStats &ss) {
+  if (ss.converged) return SMFS_OK;
+  return ss.stagnated ? SMFS_STAGNATED : SMFS_NOT_CONVERGED;
+}
 
 // GMRES on A x = b (x0 = 0), then the true residual in FP64; in mixed
 // precision up to two refinement sweeps on that residual.
@@ -1132,14 +1227,19 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
                  int precision, SolveStats &ss, hipStream_t s) {
   const int64_t ld = pb.kry_ld;
   const double tol = pb.prm.gmres_tol;
+  const int every = pb.prm.gmres_check_every;
   GmresStats st;
-  int rc = gmres(pb, n, op, b, x, st, precision, tol, pb.prm.gmres_max_it, s);
+  int rc = gmres(pb, n, op, b, x, st, precision, tol, pb.prm.gmres_max_it, every, s);
   if (rc) return rc;
   ss = SolveStats{};
   ss.iterations = st.iterations;
-  ss.applies = st.applies;
-  ss.converged = st.converged;
+  ss.applies = st.applies + st.check_applies;
   ss.rel_residual = st.rel_residual;
+  ss.true_checks = st.true_checks;
+  ss.floor_it = st.floor_it;
+  ss.floor_rel = st.floor_rel;
+  // the estimate met the tolerance, or the guard stopped the iteration
+  bool stopped = st.converged || st.stagnated;
   double *w = pb.d_vec, *r = pb.d_vec + ld, *rr = pb.d_vec + 4 * ld, *d = pb.d_vec + 5 * ld;
   const int32_t nch = mdot_chunks(n);
   double *scal = pb.d_red + pb.red_cap - 8;
@@ -1154,17 +1254,20 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
     SMFS_HIP(hipMemcpyAsync(hres, scal, 16, hipMemcpyDeviceToHost, s));
     SMFS_HIP(hipStreamSynchronize(s));
     const double true_rel = hres[1] > 0 ? hres[0] / hres[1] : 0.0;
-    if (!is_mixed(precision) || true_rel <= tol || ss.refinements >= 2 ||
+    ss.converged = true_rel <= tol;
+    ss.stagnated = !ss.converged && stopped;
+    if (!is_mixed(precision) || ss.converged || ss.refinements >= 2 ||
         ss.applies >= pb.prm.gmres_max_it)
       break;
     SMFS_HIP(hipMemcpyAsync(rr, r, 8 * n, hipMemcpyDeviceToDevice, s));
     const double tol_d = std::min(0.5, std::max(tol, tol / true_rel));
     GmresStats sd;
-    rc = gmres(pb, n, op, rr, d, sd, precision, tol_d, pb.prm.gmres_max_it - ss.applies, s);
+    rc = gmres(pb, n, op, rr, d, sd, precision, tol_d, pb.prm.gmres_max_it - ss.applies, every, s);
     if (rc) return rc;
     ss.iterations += sd.iterations;
-    ss.applies += sd.applies;
-    ss.converged = sd.converged;
+    ss.applies += sd.applies + sd.check_applies;
+    ss.true_checks += sd.true_checks;
+    stopped = sd.converged || sd.stagnated;
     SMFS_HIP(launch_axpby(n, 1.0, d, 1.0, x, s));
     ++ss.refinements;
   }
@@ -1196,6 +1299,9 @@ int post_process(Problem &pb, const double *x, const double *rbm, smfs_out *out,
 
 void fill_out(Problem &pb, const SolveStats &ss, const double *post, int precision, smfs_out *out) {
   out->iterations = ss.iterations;
+  out->true_checks = ss.true_checks;
+  out->floor_iteration = ss.floor_it;
+  out->floor_rel_residual = ss.floor_rel;
   out->refinements = ss.refinements;
   out->rel_residual = ss.rel_residual;
   out->true_rel_residual = ss.rhs_norm > 0 ? ss.res_norm / ss.rhs_norm : 0.0;
@@ -1242,7 +1348,7 @@ int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out, sm
   out->t_rhs_ms = ms(t0, t1);
   out->t_gmres_ms = ms(t1, t2);
   out->t_post_ms = ms(t2, t3);
-  return ss.converged ? SMFS_OK : SMFS_NOT_CONVERGED;
+  return solve_status(ss);
 }
 
 int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_stream stream) {
@@ -1282,7 +1388,7 @@ int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_
   out->t_rhs_ms = ms(t0, t1);
   out->t_gmres_ms = ms(t1, t2);
   out->t_post_ms = ms(t2, t3);
-  return ss.converged ? SMFS_OK : SMFS_NOT_CONVERGED;
+  return solve_status(ss);
 }
 
 }  // extern "C"

@@ -1,6 +1,6 @@
 // Many right-hand sides: block product with G_hat and lock-step GMRES.
 //
-// The preconditioned operator (Section 2.4, eq. resistance) is the same for
+// The preconditioned operator (Section 2.2, eq. resistance) is the same for
 // every right-hand side, so nrhs systems share one pass over the geometry:
 // the direct sum computes each pair's separation and 1/|r| once per run of
 // kBlockRun vectors, and the per-sphere pseudo-inverse (eq. transform)
@@ -285,6 +285,7 @@ int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B
 }
 
 }  // namespace
+
 }  // namespace smfs
 
 using namespace smfs;

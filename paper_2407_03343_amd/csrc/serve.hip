@@ -242,7 +242,7 @@ int prepare_request(Worker &wk, Req *r) {
   return SMFS_OK;
 }
 
-// The self-block factorisations (Section 2.4) of every contact sphere of a
+// The self-block factorisations (Section 2.2, eq. transform) of every contact sphere of a
 // batch of requests, grouped by block shape across requests: batched SVDs
 // per shape, because a batched SVD of small blocks costs little more than a
 // single one.  Every call has the same batch count for a given shape (the

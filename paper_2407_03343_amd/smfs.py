@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("SMFS_LIB", os.path.join(HERE, "libsmfs.so"))
 SMFS_OK = 0
 SMFS_NOT_CONVERGED = 1
 SMFS_GAP_BELOW_VALIDATED = 2
+SMFS_STAGNATED = 3
+SOLVE_WARNINGS = (SMFS_OK, SMFS_NOT_CONVERGED, SMFS_STAGNATED)
 SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR = 0, 1, 2
 KIND_S, KIND_R, KIND_D = 1, 2, 4
 
@@ -44,7 +46,7 @@ class smfs_params(C.Structure):
         ("cap_alpha", C.c_int32 * 2), ("cap_beta", C.c_double * 2), ("left_weights", C.c_int32),
         ("trunc_rel", C.c_double), ("mu", C.c_double), ("n_check_base", C.c_int32),
         ("precision", C.c_int32), ("gmres_tol", C.c_double), ("gmres_max_it", C.c_int32),
-        ("gmres_restart", C.c_int32),
+        ("gmres_restart", C.c_int32), ("gmres_check_every", C.c_int32),
     ]
 
 
@@ -66,6 +68,7 @@ class smfs_out(C.Structure):
         ("eps_res_max", C.c_double), ("abs_res_max", C.c_double), ("t_rhs_ms", C.c_double),
         ("t_gmres_ms", C.c_double), ("t_post_ms", C.c_double), ("pair_evals", C.c_int64),
         ("pair_evals_f32", C.c_int64), ("refinements", C.c_int32),
+        ("true_checks", C.c_int32), ("floor_iteration", C.c_int32), ("floor_rel_residual", C.c_double),
     ]
 
 
@@ -356,13 +359,18 @@ class Problem:
                "smfs_eval_velocity")
         return u
 
-    def _outputs(self, o):
-        return dict(converged=None, iterations=o.iterations, rel_residual=o.rel_residual,
+    @staticmethod
+    def _outputs(o, rc):
+        """Host statistics of a solve; status is SMFS_OK (true residual met
+        the tolerance), SMFS_STAGNATED or SMFS_NOT_CONVERGED."""
+        return dict(status=rc, converged=rc == SMFS_OK, stagnated=rc == SMFS_STAGNATED,
+                    iterations=o.iterations, rel_residual=o.rel_residual,
                     true_rel_residual=o.true_rel_residual, lambda_inf=o.lambda_inf,
                     eps_res_max=o.eps_res_max, abs_res_max=o.abs_res_max,
                     t_rhs_ms=o.t_rhs_ms, t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms,
                     pair_evals=o.pair_evals, pair_evals_f32=o.pair_evals_f32,
-                    refinements=o.refinements)
+                    refinements=o.refinements, true_checks=o.true_checks,
+                    floor_iteration=o.floor_iteration, floor_rel_residual=o.floor_rel_residual)
 
     def solve_mobility(self, ft, want_check=True):
         """Forces/torques (P x 6, device) in; rigid motions out."""
@@ -374,9 +382,9 @@ class Problem:
         o.mu, o.lambda_, o.ft, o.rbm = mu.data_ptr(), lam.data_ptr(), ft_out.data_ptr(), rbm.data_ptr()
         o.u_check = uc.data_ptr() if uc is not None else None
         rc = lib().smfs_solve_mobility(self.h, _ptr(ft), C.byref(o), _stream())
-        _check(rc, "smfs_solve_mobility", ok=(SMFS_OK, SMFS_NOT_CONVERGED))
-        d = self._outputs(o)
-        d.update(mu=mu, lam=lam, ft=ft_out, rbm=rbm, u_check=uc, converged=rc == SMFS_OK)
+        _check(rc, "smfs_solve_mobility", ok=SOLVE_WARNINGS)
+        d = self._outputs(o, rc)
+        d.update(mu=mu, lam=lam, ft=ft_out, rbm=rbm, u_check=uc)
         return d
 
     def solve_resistance(self, rbm, want_check=True):
@@ -389,14 +397,10 @@ class Problem:
         o.mu, o.lambda_, o.ft = mu.data_ptr(), lam.data_ptr(), ft.data_ptr()
         o.u_check = uc.data_ptr() if uc is not None else None
         rc = lib().smfs_solve_resistance(self.h, _ptr(rbm), C.byref(o), _stream())
-        _check(rc, "smfs_solve_resistance", ok=(SMFS_OK, SMFS_NOT_CONVERGED))
-        return dict(mu=mu, lam=lam, ft=ft, u_check=uc, converged=rc == SMFS_OK,
-                    iterations=o.iterations, rel_residual=o.rel_residual,
-                    true_rel_residual=o.true_rel_residual, lambda_inf=o.lambda_inf,
-                    eps_res_max=o.eps_res_max, abs_res_max=o.abs_res_max,
-                    t_rhs_ms=o.t_rhs_ms, t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms,
-                    pair_evals=o.pair_evals, pair_evals_f32=o.pair_evals_f32,
-                    refinements=o.refinements)
+        _check(rc, "smfs_solve_resistance", ok=SOLVE_WARNINGS)
+        d = self._outputs(o, rc)
+        d.update(mu=mu, lam=lam, ft=ft, u_check=uc)
+        return d
 
     # -- many right-hand sides ---------------------------------------------
     def block_workspace_bytes(self, nrhs, restart=0):

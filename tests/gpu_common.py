@@ -22,6 +22,19 @@ def _n(t):
     return t.detach().cpu().numpy()
 
 
+# Solver settings that keep a solve on the oracle's iteration path: the
+# true-residual guard off, so GMRES stops on its recursive estimate as the
+# oracle's GMRES does.
+NOGUARD = dict(gmres_check_every=0)
+
+
+def _finished(out):
+    """A solve that ended on its tolerance or on the true-residual floor
+    (not on the iteration limit); the status must be honest: OK only when
+    the FP64 true residual met the tolerance."""
+    return out["status"] in (0, 3)
+
+
 def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 

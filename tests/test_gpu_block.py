@@ -15,7 +15,7 @@ import pytest
 from oracle import geometry as geo, mfs
 from paper_2407_03343_amd import workloads as wl
 
-from gpu_common import _say, _t, _n, _rel, _import_oracle_factors, _transform_ext
+from gpu_common import NOGUARD, _say, _t, _n, _rel, _import_oracle_factors, _transform_ext
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -37,7 +37,7 @@ def small12(dev, oracle_pairsum_built):
     c = np.array(c)
     g = geo.build(c, 1.0, geo.Params(**SMALL))
     pbo = mfs.Problem(g).setup()
-    lib = dev.Problem(c, 1.0, gmres_tol=1e-11, **SMALL).bind()
+    lib = dev.Problem(c, 1.0, gmres_tol=1e-11, **SMALL, **NOGUARD).bind()
     _import_oracle_factors(lib, pbo)
     return dict(c=c, g=g, pb=pbo, lib=lib)
 
@@ -139,7 +139,8 @@ def test_block_solve_restarted(dev, oracle_pairsum_built):
     c = np.array([[0.0, 0, 0], [2.05, 0.3, 0.0], [0.4, 2.3, 0.1]])
     g = geo.build(c, 1.0, geo.Params(**prm))
     pbo = mfs.Problem(g).setup()
-    lib = dev.Problem(c, 1.0, gmres_tol=1e-10, gmres_restart=12, gmres_max_it=3000, **prm).bind()
+    lib = dev.Problem(c, 1.0, gmres_tol=1e-10, gmres_restart=12, gmres_max_it=3000, **prm,
+                      **NOGUARD).bind()
     _import_oracle_factors(lib, pbo)
     nrhs = 9
     rbm = wl.random_rbm(3, nrhs, 44)
