@@ -1,20 +1,35 @@
 #!/usr/bin/env python
-"""Benchmark of the one-body preconditioned MFS resistance solve on one MI355X.
+"""Benchmark of the one-body preconditioned MFS product on one MI355X.
 
-Workload (default): 100 unit spheres in a cube at volume fraction 0.2,
-cluster-grown so that gaps are log-uniform in [1e-3, 1e-1]; 600 proxy
-Stokeslets on R_p = 0.7, 780 base collocation nodes, 20 image nodes (S, R, D)
-per contact with gap < 0.2, two caps of 360 nodes per contact; plain FP64;
-GMRES to 1e-10.  Random rigid-body velocities, N(0, 1).
+Headline workload: 2000 unit spheres in a cube at volume fraction 0.3 (a
+hard-sphere fluid with every gap at least 0.2), 5% of them pulled into
+near-contact pairs at gaps log-uniform in [1e-3, 1e-2]; 600 proxy
+Stokeslets on R_p = 0.7, 780 base collocation nodes, 20 image nodes (S, R,
+D) per contact with gap < 0.2, two caps of 360 nodes per contact.  The
+self-block set-up (geometry, device assembly, truncated SVD of every
+distinct self block) runs before the timed region and is reported apart.
 
-A step is one complete resistance solve: right-hand side, GMRES (every
-iteration one product with G_hat = pseudo-inverse apply + direct sum, plus
-Arnoldi), FP64 true residual, back-transform to strengths, forces and
-torques, and the surface velocity at the residual check points.  The
-self-block factorisation (setup) runs once before the timed region and is
-reported separately.
+A step is one product y = G_hat mu with the one-body preconditioned
+operator (Section 2.2, eq. resistance) in FP64: the pseudo-inverse of every
+sphere's self block applied to its slice of mu (eq. transform), the sum of
+every off-sphere Stokeslet, rotlet and dipole pair (eq. uAll) and the
+identity self blocks.  This product is what every GMRES iteration of a
+solve repeats.  `value` = pair evaluations of the timed products / wall
+time.  The same products in the mixed form (FP32 sources of the
+contact-free spheres) are timed beside it, with their error against FP64.
 
-Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+Sections of the default run, each inside the wall budget (--budget-s):
+ * cpu_baseline: the oracle's C direct sum on a bounded sample of the same
+   workload;
+ * solve: solve time to 1e-3 relative surface velocity (and 1e-5 in
+   forces/torques), FP64 against the mixed forms, p50/p99 over repeated
+   solves, on a stated cut of the same recipe;
+ * two_sphere: the two-sphere case at gap 0.01, p50/p99 of complete solves.
+Flags add the block product, the block solve, the serving stream and the
+set-up comparison; their results go to stderr and, with --sections-out, to
+a JSON file.  stdout carries exactly one JSON line.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 from __future__ import annotations
 
@@ -22,6 +37,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -35,178 +51,183 @@ PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X, FP64 vector
 PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X, FP64 dense matrix
 PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X, FP32 vector
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the direct sum on the 100-sphere workload (62 source
-# splits): rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB elementwise
-# copy reads back) plus WRITE_SIZE (x1), KiB per dispatch, from the counter
-# summary of this kernel under profiles/
-DIRECT_TRAFFIC_BYTES = (2 * 225712.4 + 387462.0) * 1024
+# HBM bytes per launch of the FP64 direct sum on the headline workload, from
+# rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB elementwise product
+# reads back) plus WRITE_SIZE (x1), KiB per dispatch, as recorded in the
+# counter summary of this kernel and workload under profiles/; None until
+# counters of the current kernel on this workload are taken.
+DIRECT_TRAFFIC_BYTES = None
+
+FORMS = (("fp64", 0), ("mixed", 1), ("mixed_far", 2))   # SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pk, stride: int, two_sphere: bool = True):
-    """The FP64 oracle's direct sum (its dominant step) on a bounded sample:
-    every stride-th collocation node of the same workload against all
-    sources, same-sphere pairs skipped.  Returns pair-evals/s, and with
-    two_sphere the oracle's two-sphere solve times."""
-    from oracle import geometry as geo
-    from oracle.pairsum import pairsum, build
-    build(force=False)
-    g = geo.build(pk.centers, pk.radius)
-    rows = np.arange(0, g.T, stride)
-    lam = np.random.default_rng(7).standard_normal((g.S, 3))
+class Budget:
+    """Wall-clock budget of the whole run: a section starts only when its
+    estimated cost still fits."""
+
+    def __init__(self, seconds):
+        self.t0 = time.perf_counter()
+        self.seconds = seconds
+
+    def left(self):
+        return self.seconds - (time.perf_counter() - self.t0)
+
+    def fits(self, need_s):
+        return self.left() > need_s
+
+
+def host_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False)
+    except Exception:
+        phys = None
+    return dict(cpu=model, logical_cpus=os.cpu_count(), physical_cores=phys,
+                hostname=platform.node())
+
+
+# ---------------------------------------------------------------------------
+# Headline: FP64 products on the 2000-sphere packing, mixed beside them
+
+
+def offdiag_err(y, y_ref, mu):
+    """Max-norm error of the off-diagonal part (y - mu) relative to the
+    largest entry of the reference's off-diagonal part (mu is copied
+    exactly and would dilute the comparison)."""
+    a = y - mu
+    b = y_ref - mu
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def timed_products(pb, torch, mu, y, precision, warmup, steps):
+    for _ in range(warmup):
+        pb.apply(mu, precision=precision, out=y)
+    torch.cuda.synchronize()
+    pb.profile(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pairsum(g.targets[rows], g.src_pos, g.src_kind, lam, 1.0, g.target_sphere[rows], g.src_sphere, True)
-    dt = time.perf_counter() - t0
-    own = np.bincount(g.src_sphere, minlength=g.P)
-    pairs = float(np.sum(g.S - own[g.target_sphere[rows]]))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    out = dict(value=pairs / dt, unit="pair-evals/s", cores=cores, kind="oracle",
-               sample=(f"oracle C direct sum (OpenMP), {rows.size} of {g.T} collocation nodes "
-                       f"(every {stride}) x {g.S} sources, same-sphere pairs skipped: "
-                       f"{pairs:.3g} pairs in {dt:.1f} s"))
-    if two_sphere:
-        out["two_sphere_solve"] = oracle_two_sphere()
-    return out
+    for _ in range(steps):
+        pb.apply(mu, precision=precision, out=y)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pb.profile(False)
+    return elapsed, pb.profile_read()
 
 
-def oracle_two_sphere():
-    """The oracle's complete solve of the two-sphere case (gap 0.01, FP64 to
-    1e-10), set-up (LAPACK SVDs) and solve timed apart: the CPU counterpart
-    of the benchmark's two-sphere section."""
-    from oracle import geometry as geo, mfs
-    from paper_2407_03343_amd import workloads as wl
-    pk, rbm = wl.workload_two_sphere_gap001()
-    t0 = time.perf_counter()
-    pb = mfs.Problem(geo.build(pk.centers, pk.radius)).setup()
-    t1 = time.perf_counter()
-    o = mfs.solve_resistance(pb, rbm[0], tol=1e-10)
-    t2 = time.perf_counter()
-    return dict(setup_s=t1 - t0, solve_ms=(t2 - t1) * 1e3, iterations=int(o["iterations"]),
-                force_sphere0=[float(x) for x in o["ft"][0, :3]])
-
-
-FORMS = (("fp64", 0), ("mixed", 1), ("mixed_far", 2))   # SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR
-
-
-def mixed_vs_fp64(args, torch, smfs, wl):
-    """Solve time to 1e-3 relative surface velocity, plain FP64 against the
-    mixed forms (FP32 pseudo-inverse and far field; FP32 far field only), on
-    a cut of the volume-fraction-0.3 packing with 5% of the
-    spheres in near-contact pairs.  The reference is the FP64 solve at
-    tolerance 1e-10; for each form the fastest GMRES tolerance whose
-    check-point velocities meet 1e-3 (relative to the largest) is reported,
-    with its force/torque error beside it."""
-    pk = wl.workload_packing2000(args.mixed_spheres, seed=args.seed)
-    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=1000, gmres_max_it=1000)
+def headline(args, torch, smfs, wl, budget):
+    pk = wl.workload_packing2000(args.spheres, seed=args.seed)
+    gaps = pk.min_gaps()
+    log(f"workload: {pk.P} spheres, box {pk.box:.2f}, {int((gaps < 0.2).sum())} in near contact, "
+        f"min gap {gaps.min():.2e}")
+    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=1)
+    log(f"T={pb.T} S={pb.S} factors={pb.sizes.n_factors} workspace="
+        f"{pb.sizes.workspace_bytes / 2**30:.2f} GiB pairs/apply={pb.pairs_per_apply:.4e}")
     pb.bind()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     pb.setup()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    rbm = torch.from_numpy(wl.random_rbm(pb.P, 1, 77)[0].reshape(-1)).cuda()
-    pb.set_solver(smfs.SMFS_FP64, 1e-10)
-    ref = pb.solve_resistance(rbm)
-    u_ref = ref["u_check"].cpu().numpy()
-    ft_ref = ref["ft"].cpu().numpy()
-    log(f"mixed section: {pb.P} spheres, T={pb.T}, S={pb.S}, setup {setup_s:.1f} s, "
-        f"reference it {ref['iterations']}")
-    out = {"spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S,
-           "pairs_per_apply": pb.pairs_per_apply, "reference_iterations": ref["iterations"],
-           "setup_s": setup_s, "forms": {}}
-    for name, prec in FORMS:
-        rows = []
-        pb.profile(True)
-        for tol in args.mixed_tols:
-            pb.set_solver(prec, tol)
-            ts = []
-            for _ in range(args.mixed_reps):
-                t1 = time.perf_counter()
-                o = pb.solve_resistance(rbm)
-                torch.cuda.synchronize()
-                ts.append((time.perf_counter() - t1) * 1e3)
-            u = o["u_check"].cpu().numpy()
-            du = float(np.abs(u - u_ref).max() / np.abs(u_ref).max())
-            dft = float(np.abs(o["ft"].cpu().numpy() - ft_ref).max() / np.abs(ft_ref).max())
-            rows.append(dict(tol=tol, iterations=o["iterations"], refinements=o["refinements"],
-                             solve_ms_p50=float(np.percentile(ts, 50)),
-                             solve_ms_p99=float(np.percentile(ts, 99)),
-                             u_rel_err=du, ft_rel_err=dft,
-                             pair_evals=o["pair_evals"], pair_evals_f32=o["pair_evals_f32"],
-                             pair_evals_per_s=o["pair_evals"] / (np.percentile(ts, 50) * 1e-3)))
-            log(f"  {name} tol {tol:.0e}: it {o['iterations']} (+{o['refinements']}), "
-                f"{rows[-1]['solve_ms_p50']:.1f} ms, u err {du:.2e}, F/T err {dft:.2e}")
-        pb.profile(False)
-        ok = [r for r in rows if r["u_rel_err"] <= 1e-3]
-        best = min(ok, key=lambda r: r["solve_ms_p50"]) if ok else None
-        out["forms"][name] = {"scan": rows, "at_1e-3_surface_velocity": best,
-                              "kernels": mixed_kernel_rates(pb.profile_read())}
-    # mobility (forces and torques in), each form at the tolerance that met
-    # the surface-velocity target above; error of the rigid motions against
-    # the FP64 mobility solve at 1e-10
-    ft = torch.from_numpy(wl.random_ft(pb.P, 1, 78)[0].reshape(-1)).cuda()
-    pb.set_solver(smfs.SMFS_FP64, 1e-10)
-    v_ref = pb.solve_mobility(ft)["rbm"].cpu().numpy()
-    out["mobility"] = {}
-    for name, prec in FORMS:
-        best = out["forms"][name]["at_1e-3_surface_velocity"]
-        tol = best["tol"] if best else 1e-6
-        pb.set_solver(prec, tol)
-        t1 = time.perf_counter()
-        o = pb.solve_mobility(ft)
-        torch.cuda.synchronize()
-        solve_ms = (time.perf_counter() - t1) * 1e3
-        dv = float(np.abs(o["rbm"].cpu().numpy() - v_ref).max() / np.abs(v_ref).max())
-        out["mobility"][name] = dict(tol=tol, iterations=o["iterations"], refinements=o["refinements"],
-                                     solve_ms=solve_ms,
-                                     true_rel_residual=o["true_rel_residual"], converged=o["converged"],
-                                     rbm_rel_err=dv)
-        log(f"  mobility {name} tol {tol:.0e}: it {o['iterations']}, {solve_ms:.1f} ms, V err {dv:.2e}")
-    f64 = out["forms"]["fp64"]["at_1e-3_surface_velocity"]
-    for name, _ in FORMS[1:]:
-        mx = out["forms"][name]["at_1e-3_surface_velocity"]
-        if f64 and mx:
-            out[f"speedup_{name}_over_fp64"] = f64["solve_ms_p50"] / mx["solve_ms_p50"]
-        mb = out["mobility"]
-        out[f"mobility_speedup_{name}_over_fp64"] = mb["fp64"]["solve_ms"] / mb[name]["solve_ms"]
-    return out
+    ranks = sorted({pb.factor_info(f)["rank"] for f in range(pb.sizes.n_factors)
+                    if pb.factor_info(f)["sphere"] >= 0})
+    log(f"setup (device assembly + truncated SVD of {pb.sizes.n_factors} distinct self blocks): "
+        f"{setup_s:.1f} s, ranks {ranks[0]}..{ranks[-1]}")
 
+    rbm = torch.from_numpy(wl.random_rbm(pb.P, 1, 1000 + args.seed)[0].reshape(-1)).cuda()
+    b = pb.rhs(rbm)                                      # a physical vector (first Krylov vector)
+    mu = torch.from_numpy(wl.random_vector(3 * pb.T, 3 + args.seed)).cuda()   # rough, like later ones
+    y = torch.empty_like(mu)
 
-def two_sphere(args, torch, smfs, wl):
-    """The paper's two-sphere case (Section 5, the comparison with Brenner's
-    series): unit spheres at gap 0.01 moving apart at unit relative speed,
-    FP64, GMRES to 1e-10.  Set-up once (timed), then repeated complete
-    solves (right-hand side, GMRES, back-transform, forces and torques,
-    check-point velocities) for p50/p99."""
-    pk, rbm = wl.workload_two_sphere_gap001()
-    pb = smfs.Problem(pk.centers, pk.radius)
-    pb.bind()
-    t0 = time.perf_counter()
-    pb.setup()
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    r = torch.from_numpy(rbm[0].reshape(-1)).cuda()
-    o = pb.solve_resistance(r)                     # warm-up
-    torch.cuda.synchronize()
-    ts, pairs = [], 0
-    for _ in range(args.two_sphere_reps):
-        t1 = time.perf_counter()
-        o = pb.solve_resistance(r)
-        torch.cuda.synchronize()
-        ts.append((time.perf_counter() - t1) * 1e3)
-        pairs += o["pair_evals"]
-    ft = o["ft"].cpu().numpy().reshape(-1, 6)
-    out = dict(spheres=2, gap=0.01, collocation_nodes=pb.T, sources=pb.S, setup_s=setup_s,
-               reps=len(ts), solve_ms_p50=float(np.percentile(ts, 50)),
-               solve_ms_p99=float(np.percentile(ts, 99)), iterations=o["iterations"],
-               true_rel_residual=o["true_rel_residual"], eps_res_max=o["eps_res_max"],
-               force_sphere0=[float(x) for x in ft[0, :3]],
-               pair_evals_per_s=pairs / (sum(ts) * 1e-3))
-    log(f"two spheres, gap 0.01: setup {setup_s:.2f} s, solve p50 {out['solve_ms_p50']:.2f} ms "
-        f"p99 {out['solve_ms_p99']:.2f} ms, it {o['iterations']}, |F| {np.linalg.norm(ft[0, :3]):.6f}")
-    return out
+    elapsed, st = timed_products(pb, torch, mu, y, smfs.SMFS_FP64, args.warmup, args.steps)
+    pairs = pb.pairs_per_apply * args.steps
+    direct_avg_s = st["direct_ms"] / max(1, st["direct_launches"]) * 1e-3
+    pinv_avg_s = st["pinv_ms"] / max(1, st["pinv_launches"]) * 1e-3
+    achieved = st["direct_flops"] / direct_avg_s / 1e12
+    log(f"FP64 product: {elapsed / args.steps * 1e3:.1f} ms per step, direct sum "
+        f"{direct_avg_s * 1e3:.1f} ms ({achieved:.1f} TFLOP/s), pseudo-inverse {pinv_avg_s * 1e3:.2f} ms")
+
+    # mixed form: the same products, then its error against FP64
+    m_el, m_st = timed_products(pb, torch, mu, y, smfs.SMFS_MIXED, min(args.warmup, 2), args.steps)
+    errs = {}
+    for name, vec in (("physical", b), ("random", mu)):
+        y64 = pb.apply(vec, precision=smfs.SMFS_FP64).cpu().numpy()
+        v = vec.cpu().numpy()
+        errs[name] = {f: offdiag_err(pb.apply(vec, precision=p).cpu().numpy(), y64, v)
+                      for f, p in FORMS[1:]}
+    log(f"mixed product: {m_el / args.steps * 1e3:.1f} ms per step ({elapsed / m_el:.2f}x FP64); "
+        f"error vs FP64 (off-diagonal, max-norm): physical {errs['physical']}, random {errs['random']}")
+
+    result = {
+        "metric": "Stokeslet pair-evals/s (one-body preconditioned product G_hat mu, FP64, "
+                  "2000-sphere packing); solve time at 1e-3 relative surface velocity, mixed vs FP64, "
+                  "p50/p99",
+        "value": pairs / elapsed,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded packing and rigid motions; random-vector products)",
+        "config": {
+            "workload": f"{pk.P} unit spheres, cube at volume fraction 0.3 (hard-sphere fluid, gaps >= 0.2), "
+                        "5% in near-contact pairs at gaps log-uniform [1e-3, 1e-2]; N=600 proxy Stokeslets "
+                        "on R_p=0.7, 780 base nodes, 20 S+R+D image nodes per contact (gap < 0.2), caps "
+                        "2x360; truncated-SVD factors (5e-12) set up before the timed region; one FP64 "
+                        "product with G_hat per step",
+            "spheres": pk.P, "collocation_nodes": pb.T, "sources": pb.S,
+            "distinct_self_blocks": pb.sizes.n_factors, "pairs_per_apply": pb.pairs_per_apply,
+            "precision": "fp64",
+        },
+        "setup_s": setup_s,
+        "factor_ranks": [int(ranks[0]), int(ranks[-1])],
+        "roofline": {
+            "kernel": "k_direct_f64 (direct sum of every off-sphere pair)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+            "traffic": DIRECT_TRAFFIC_BYTES,
+            "traffic_unit": "bytes per launch",
+            "avg_launch_ms": direct_avg_s * 1e3,
+            "launches": st["direct_launches"],
+            "flops_per_launch": st["direct_flops"],
+            "work_per_unit": "28 / 25 / 30 flops per Stokeslet / rotlet / dipole pair",
+        },
+        "pinv_apply": {
+            "kernel": "k_pinv_u + k_pinv_v (contact spheres) + k_pinv_shared_u/v (FP64 MFMA, shared factor)",
+            "bound": "hbm",
+            "achieved": st["pinv_bytes"] / pinv_avg_s / 1e9 if pinv_avg_s > 0 else None,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "avg_launch_ms": pinv_avg_s * 1e3, "bytes_per_launch": st["pinv_bytes"],
+        },
+        "mixed": {
+            "precision": "SMFS_MIXED: FP32 pseudo-inverse and far field for the contact-free spheres",
+            "ms_per_step": m_el / args.steps * 1e3,
+            "pair_evals_per_s": pairs / m_el,
+            "speedup_over_fp64": elapsed / m_el,
+            "kernels": mixed_kernel_rates(m_st),
+            "offdiag_rel_err_vs_fp64": errs,
+        },
+    }
+    return pk, pb, result
 
 
 def mixed_kernel_rates(st):
@@ -229,34 +250,171 @@ def mixed_kernel_rates(st):
     return out
 
 
-def apply_only(pb, n, wl, torch, block=0):
-    for fid in range(pb.sizes.n_factors):
-        info = pb.factor_info(fid)
-        if info["sphere"] < 0:
-            continue
-        U, s, V = wl.random_factors(info["rows"], info["cols"], info["cols"], seed=100 + fid)
-        pb.import_factor(fid, U, s, V)
-    mu = torch.from_numpy(wl.random_vector(3 * pb.T, 3)).cuda()
-    y = torch.empty_like(mu)
-    pb.profile(True)
-    for _ in range(n):
-        pb.apply(mu, out=y)
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle's direct sum on a bounded sample
+
+
+def cpu_baseline(pk, seconds: float):
+    """The FP64 oracle's direct sum (its dominant step) over every stride-th
+    collocation node of the same workload against all sources, same-sphere
+    pairs skipped; the stride is chosen from a short probe so that the timed
+    sample takes about `seconds`."""
+    from oracle import geometry as geo
+    from oracle.pairsum import pairsum, build
+    build(force=False)
+    t0 = time.perf_counter()
+    g = geo.build(pk.centers, pk.radius)
+    geo_s = time.perf_counter() - t0
+    own = np.bincount(g.src_sphere, minlength=g.P)
+    lam = np.random.default_rng(7).standard_normal((g.S, 3))
+
+    def run(stride):
+        rows = np.arange(0, g.T, stride)
+        t = time.perf_counter()
+        pairsum(g.targets[rows], g.src_pos, g.src_kind, lam, 1.0, g.target_sphere[rows], g.src_sphere, True)
+        dt = time.perf_counter() - t
+        return rows, dt, float(np.sum(g.S - own[g.target_sphere[rows]]))
+
+    rows, dt, pairs = run(max(1, g.T // 256))             # probe
+    rate = pairs / dt
+    stride = max(1, int(g.T * g.S / (rate * seconds)))
+    rows, dt, pairs = run(stride)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or (os.cpu_count() or 1))
+    return dict(value=pairs / dt, unit="pair-evals/s", cores=threads, kind="oracle",
+                host=host_info(),
+                sample=(f"oracle C direct sum (FP64, OpenMP, {threads} threads), {rows.size} of {g.T} "
+                        f"collocation nodes (every {stride}) x {g.S} sources of the same workload, "
+                        f"same-sphere pairs skipped: {pairs:.3g} pairs in {dt:.1f} s "
+                        f"(oracle geometry built in {geo_s:.1f} s, not timed)"))
+
+
+# ---------------------------------------------------------------------------
+# Solve time at 1e-3 surface velocity, FP64 against the mixed forms
+
+
+def solve_section(args, torch, smfs, wl, budget):
+    """Resistance solves on a cut of the headline recipe: the reference is
+    the FP64 solve at tolerance 1e-10 (ending on its true-residual floor);
+    for every form, the GMRES tolerances of a ladder are tried from the
+    loosest until the check-point velocities are within 1e-3 of the
+    reference (relative to the largest) and the forces and torques within
+    1e-5; that tolerance is then solved `solve_reps` times for p50/p99."""
+    pk = wl.workload_packing2000(args.solve_spheres, seed=args.seed)
+    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=args.solve_restart,
+                      gmres_max_it=args.solve_restart)
+    pb.bind()
+    t0 = time.perf_counter()
+    pb.setup()
     torch.cuda.synchronize()
-    pb.profile(False)
-    st = pb.profile_read()
-    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
-    z = torch.empty_like(x)
-    x.fill_(1.0)                  # calibration: writes exactly 1 GiB
-    torch.mul(x, 2.0, out=z)      # calibration: reads 1 GiB, writes 1 GiB
+    setup_s = time.perf_counter() - t0
+    rbm = torch.from_numpy(wl.random_rbm(pb.P, 1, 77)[0].reshape(-1)).cuda()
+    pb.set_solver(smfs.SMFS_FP64, 1e-10)
+    t1 = time.perf_counter()
+    ref = pb.solve_resistance(rbm)
     torch.cuda.synchronize()
-    del x, z
-    out = {"apply_only": n, "direct_avg_ms": st["direct_ms"] / max(1, st["direct_launches"]),
-           "pinv_avg_ms": st["pinv_ms"] / max(1, st["pinv_launches"]),
-           "direct_flops": st["direct_flops"], "pinv_bytes": st["pinv_bytes"],
-           "copy_bytes": 1 << 30}
-    if block:
-        out["block"] = block_vs_single(pb, torch, block, 2)
-    print(json.dumps(out), flush=True)
+    ref_s = time.perf_counter() - t1
+    u_ref, ft_ref = ref["u_check"].cpu().numpy(), ref["ft"].cpu().numpy()
+    log(f"solve section: {pb.P} spheres, T={pb.T}, S={pb.S}, setup {setup_s:.1f} s; reference "
+        f"{ref['iterations']} it (status {ref['status']}, true {ref['true_rel_residual']:.2e}, floor at "
+        f"{ref['floor_iteration']}), {ref_s:.1f} s")
+    out = {"workload": f"{pb.P}-sphere cut of the headline recipe (volume fraction 0.3, 5% in pairs)",
+           "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S,
+           "pairs_per_apply": pb.pairs_per_apply, "setup_s": setup_s,
+           "gates": {"u_check_rel": 1e-3, "force_torque_rel": 1e-5},
+           "reference": dict(tol=1e-10, iterations=ref["iterations"], status=ref["status"],
+                             true_rel_residual=ref["true_rel_residual"],
+                             floor_iteration=ref["floor_iteration"], solve_s=ref_s,
+                             eps_res_max=ref["eps_res_max"]),
+           "forms": {}}
+    last_s = ref_s
+    for name, prec in FORMS:
+        rows, chosen = [], None
+        for tol in args.solve_tols:
+            if not budget.fits(2.5 * last_s + args.reserve_s):
+                log(f"  {name}: wall budget reached, ladder stopped")
+                break
+            pb.set_solver(prec, tol)
+            t1 = time.perf_counter()
+            o = pb.solve_resistance(rbm)
+            torch.cuda.synchronize()
+            last_s = time.perf_counter() - t1
+            du = float(np.abs(o["u_check"].cpu().numpy() - u_ref).max() / np.abs(u_ref).max())
+            dft = float(np.abs(o["ft"].cpu().numpy() - ft_ref).max() / np.abs(ft_ref).max())
+            r = dict(tol=tol, iterations=o["iterations"], refinements=o["refinements"], status=o["status"],
+                     solve_ms=last_s * 1e3, u_rel_err=du, ft_rel_err=dft,
+                     true_rel_residual=o["true_rel_residual"], pair_evals=o["pair_evals"],
+                     pair_evals_f32=o["pair_evals_f32"])
+            rows.append(r)
+            log(f"  {name} tol {tol:.0e}: it {o['iterations']} (+{o['refinements']}), {last_s * 1e3:.0f} ms, "
+                f"u err {du:.2e}, F/T err {dft:.2e}, status {o['status']}")
+            if du <= 1e-3 and dft <= 1e-5:
+                chosen = r
+                break
+        rec = {"ladder": rows, "at_gates": None}
+        if chosen is not None:
+            ts = [chosen["solve_ms"]]
+            pb.set_solver(prec, chosen["tol"])
+            for _ in range(args.solve_reps - 1):
+                if not budget.fits(1.5 * last_s + args.reserve_s):
+                    break
+                t1 = time.perf_counter()
+                pb.solve_resistance(rbm)
+                torch.cuda.synchronize()
+                last_s = time.perf_counter() - t1
+                ts.append(last_s * 1e3)
+            rec["at_gates"] = dict(chosen, solves=len(ts), solve_ms_p50=float(np.percentile(ts, 50)),
+                                   solve_ms_p99=float(np.percentile(ts, 99)),
+                                   pair_evals_per_s=chosen["pair_evals"] / (np.percentile(ts, 50) * 1e-3))
+        out["forms"][name] = rec
+    f64 = out["forms"].get("fp64", {}).get("at_gates")
+    for name, _ in FORMS[1:]:
+        mx = out["forms"].get(name, {}).get("at_gates")
+        out[f"speedup_{name}_over_fp64"] = (f64["solve_ms_p50"] / mx["solve_ms_p50"]) if (f64 and mx) else None
+    return out
+
+
+def two_sphere(args, torch, smfs, wl, budget):
+    """The paper's two-sphere case (Section 5, the comparison with Brenner's
+    series): unit spheres at gap 0.01 moving apart at unit relative speed,
+    FP64, GMRES to 1e-10 (ending on the true-residual floor).  Set-up once
+    (timed), then repeated complete solves (right-hand side, GMRES,
+    back-transform, forces and torques, check-point velocities) for
+    p50/p99."""
+    pk, rbm = wl.workload_two_sphere_gap001()
+    pb = smfs.Problem(pk.centers, pk.radius)
+    pb.bind()
+    t0 = time.perf_counter()
+    pb.setup()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    r = torch.from_numpy(rbm[0].reshape(-1)).cuda()
+    o = pb.solve_resistance(r)                     # warm-up
+    torch.cuda.synchronize()
+    ts, pairs = [], 0
+    for _ in range(args.two_sphere_reps):
+        if not budget.fits(args.reserve_s):
+            break
+        t1 = time.perf_counter()
+        o = pb.solve_resistance(r)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t1) * 1e3)
+        pairs += o["pair_evals"]
+    ft = o["ft"].cpu().numpy().reshape(-1, 6)
+    out = dict(spheres=2, gap=0.01, collocation_nodes=pb.T, sources=pb.S, setup_s=setup_s,
+               reps=len(ts), solve_ms_p50=float(np.percentile(ts, 50)),
+               solve_ms_p99=float(np.percentile(ts, 99)), iterations=o["iterations"],
+               status=o["status"], floor_iteration=o["floor_iteration"],
+               true_rel_residual=o["true_rel_residual"], eps_res_max=o["eps_res_max"],
+               force_sphere0=[float(x) for x in ft[0, :3]],
+               pair_evals_per_s=pairs / (sum(ts) * 1e-3))
+    log(f"two spheres, gap 0.01: setup {setup_s:.2f} s, solve p50 {out['solve_ms_p50']:.2f} ms "
+        f"p99 {out['solve_ms_p99']:.2f} ms, it {o['iterations']} (floor at {o['floor_iteration']}), "
+        f"|F| {np.linalg.norm(ft[0, :3]):.6f}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Optional sections (flags)
 
 
 def block_vs_single(pb, torch, nrhs: int, reps: int, seed: int = 7):
@@ -310,6 +468,21 @@ def block_vs_single(pb, torch, nrhs: int, reps: int, seed: int = 7):
     }
 
 
+def block_section(args, torch, smfs, wl):
+    """Block product of --block vectors against single products on a cut of
+    the many-right-hand-side workload (volume fraction 0.35, 40% of the
+    spheres in pairs, N = 1000 proxies and 1680 base nodes)."""
+    pk, _ = wl.workload_block500(args.block_product_spheres, seed=args.seed)
+    pb = smfs.Problem(pk.centers, pk.radius, n_proxy=1000, n_colloc_base=1680, gmres_restart=1)
+    pb.bind()
+    t0 = time.perf_counter()
+    pb.setup()
+    torch.cuda.synchronize()
+    out = block_vs_single(pb, torch, args.block, 2)
+    out.update(spheres=pb.P, collocation_nodes=pb.T, sources=pb.S, setup_s=time.perf_counter() - t0)
+    return out
+
+
 def block_solve(args, torch, smfs, wl):
     """Many-right-hand-side solve against the same systems solved one after
     another: a cut of the volume-fraction-0.35 workload (40% of the spheres
@@ -319,7 +492,7 @@ def block_solve(args, torch, smfs, wl):
     pk, rbm = wl.workload_block500(args.block_spheres, seed=args.seed)
     nrhs, m = rbm.shape[0], args.block_restart
     pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=m, gmres_max_it=args.block_max_it,
-                      gmres_tol=args.block_tol)
+                      gmres_tol=args.block_tol, gmres_check_every=0)
     pb.bind()
     t0 = time.perf_counter()
     pb.setup()
@@ -372,8 +545,15 @@ def serving_requests(args):
     rng = np.random.default_rng(args.seed + 77)
     arrivals = np.concatenate([[0.0], np.cumsum(rng.exponential(1.0 / args.serve_rate, n - 1))])
     log(f"serving: generating {n} requests ...")
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 4)) as pool:
+    pool = mp.get_context("spawn").Pool(min(16, os.cpu_count() or 4))
+    try:
         reqs = pool.map(_gen_request, [(i, args.seed, dict(rate=args.serve_rate)) for i in range(n)])
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
     return reqs, arrivals
 
 
@@ -436,8 +616,8 @@ def serving(args, torch, smfs, reqs, arrivals):
     k = min(n, args.serve_sequential)
     t1 = time.perf_counter()
     for r in reqs[:k]:
-        pb = smfs.Problem(r["centers"], 1.0, **disc, **solver).bind().setup()
-        o = pb.solve_resistance(torch.from_numpy(r["rbm"].reshape(-1)).cuda(), want_check=False)
+        pb = smfs.Problem(r["centers"], 1.0, gmres_check_every=0, **disc, **solver).bind().setup()
+        pb.solve_resistance(torch.from_numpy(r["rbm"].reshape(-1)).cuda(), want_check=False)
         torch.cuda.synchronize()
         del pb
     seq_s = time.perf_counter() - t1
@@ -447,35 +627,76 @@ def serving(args, torch, smfs, reqs, arrivals):
     return out
 
 
+def apply_only(args, torch, smfs, wl):
+    """Profiling aid: N products with G_hat on the headline workload with
+    seeded full-rank factors in place of the SVD set-up, then one plain
+    1 GiB fill and one elementwise product (the counter calibration
+    kernels).  Prints one JSON line of event timings."""
+    pk = wl.workload_packing2000(args.spheres, seed=args.seed)
+    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=1).bind()
+    for fid in range(pb.sizes.n_factors):
+        info = pb.factor_info(fid)
+        if info["sphere"] < 0:
+            continue
+        U, s, V = wl.random_factors(info["rows"], info["cols"], info["cols"], seed=100 + fid)
+        pb.import_factor(fid, U, s, V)
+    mu = torch.from_numpy(wl.random_vector(3 * pb.T, 3)).cuda()
+    y = torch.empty_like(mu)
+    pb.profile(True)
+    for _ in range(args.apply_only):
+        pb.apply(mu, out=y)
+    torch.cuda.synchronize()
+    pb.profile(False)
+    st = pb.profile_read()
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    z = torch.empty_like(x)
+    x.fill_(1.0)                  # calibration: writes exactly 1 GiB
+    torch.mul(x, 2.0, out=z)      # calibration: reads 1 GiB, writes 1 GiB
+    torch.cuda.synchronize()
+    del x, z
+    print(json.dumps({"apply_only": args.apply_only, "spheres": pb.P,
+                      "direct_avg_ms": st["direct_ms"] / max(1, st["direct_launches"]),
+                      "pinv_avg_ms": st["pinv_ms"] / max(1, st["pinv_launches"]),
+                      "direct_flops": st["direct_flops"], "pinv_bytes": st["pinv_bytes"],
+                      "copy_bytes": 1 << 30}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed FP64 products")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--spheres", type=int, default=2000, help="spheres of the headline packing")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget of the whole run; default sections are skipped when "
+                         "their estimated cost no longer fits")
+    ap.add_argument("--reserve-s", type=float, default=20.0, help="seconds kept in reserve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=1)
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed-vs-FP64 comparison on the volume-fraction-0.3 packing")
-    ap.add_argument("--mixed-spheres", type=int, default=200)
-    ap.add_argument("--mixed-tols", type=float, nargs="+", default=[1e-5, 7e-6, 5e-6, 3e-6],
-                    help="GMRES tolerances scanned for the 1e-3 surface-velocity target (a grid fine "
-                         "around the tolerances that meet it, the same for every form)")
-    ap.add_argument("--mixed-reps", type=int, default=1, help="timed solves per tolerance")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="length of the oracle's timed sample")
+    ap.add_argument("--solve-spheres", type=int, default=100,
+                    help="spheres of the solve-time comparison (a cut of the headline recipe; 0: skip)")
+    ap.add_argument("--solve-tols", type=float, nargs="+", default=[1e-5, 1e-6, 1e-7, 1e-8],
+                    help="GMRES tolerance ladder, loosest first, the same for every form")
+    ap.add_argument("--solve-reps", type=int, default=5, help="solves at the chosen tolerance (p50/p99)")
+    ap.add_argument("--solve-restart", type=int, default=1500)
+    ap.add_argument("--two-sphere-reps", type=int, default=50,
+                    help="timed solves of the two-sphere case at gap 0.01 (0: skip)")
     ap.add_argument("--apply-only", type=int, default=0, metavar="N",
-                    help="profiling aid: N products with G_hat on the same workload with "
-                         "seeded full-rank factors instead of the SVD setup, then one plain "
-                         "1 GiB device copy (the counter calibration kernel)")
-    ap.add_argument("--block", type=int, default=64, metavar="NRHS",
-                    help="right-hand sides of the block-product comparison (0: skip)")
-    ap.add_argument("--block-spheres", type=int, default=24,
+                    help="profiling aid: N products on the headline workload with seeded full-rank "
+                         "factors, then the counter calibration kernels; nothing else runs")
+    ap.add_argument("--sections-out", default="", help="JSON file for the optional sections")
+    ap.add_argument("--block", type=int, default=0, metavar="NRHS",
+                    help="block product of NRHS vectors vs single products (0: skip)")
+    ap.add_argument("--block-product-spheres", type=int, default=100)
+    ap.add_argument("--block-spheres", type=int, default=0,
                     help="spheres of the many-right-hand-side solve comparison (0: skip)")
     ap.add_argument("--block-restart", type=int, default=200)
     ap.add_argument("--block-tol", type=float, default=1e-8)
     ap.add_argument("--block-max-it", type=int, default=3000)
     ap.add_argument("--block-sequential", type=int, default=4)
-    ap.add_argument("--serve-requests", type=int, default=20,
-                    help="requests of the serving stream (the full stream is 512)")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests of the serving stream (0: skip; the full stream is 512)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-arena", type=int, default=64, metavar="GIB")
@@ -486,145 +707,67 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=1, help="set-up worker threads")
     ap.add_argument("--serve-sequential", type=int, default=3,
                     help="requests solved one after another for the comparison")
-    ap.add_argument("--serve-only", action="store_true", help="run only the serving comparison")
-    ap.add_argument("--mixed-only", action="store_true", help="run only the mixed-vs-FP64 comparison")
-    ap.add_argument("--two-sphere-reps", type=int, default=50,
-                    help="timed solves of the two-sphere case at gap 0.01 (0: skip)")
-    ap.add_argument("--two-sphere-only", action="store_true", help="run only the two-sphere case")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(how it would shard is written up in the design notes); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    budget = Budget(args.budget_s)
+
+    reqs = arrivals = None
+    if args.serve_requests > 0:
+        reqs, arrivals = serving_requests(args)     # before the GPU is touched (spawned workers)
 
     import torch
     from paper_2407_03343_amd import smfs, workloads as wl
 
-    reqs = arrivals = None
-    if args.serve_requests > 0:
-        reqs, arrivals = serving_requests(args)
-    if args.serve_only:
-        print(json.dumps({"serving": serving(args, torch, smfs, reqs, arrivals)}), flush=True)
-        return
-    if args.mixed_only:
-        print(json.dumps({"mixed_vs_fp64": mixed_vs_fp64(args, torch, smfs, wl)}), flush=True)
-        return
-    if args.two_sphere_only:
-        print(json.dumps({"two_sphere": two_sphere(args, torch, smfs, wl)}), flush=True)
-        return
-    pk, _ = wl.workload_cluster100(args.seed)
-    log(f"workload: {pk.P} spheres, box {pk.box:.2f}, min gap {pk.min_gaps().min():.2e}")
-    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=2000, gmres_max_it=2000)
-    log(f"T={pb.T} S={pb.S} check={pb.n_check} factors={pb.sizes.n_factors} "
-        f"workspace={pb.sizes.workspace_bytes / 2**30:.2f} GiB pairs/apply={pb.pairs_per_apply:.3e}")
-    pb.bind()
-    torch.cuda.synchronize()
     if args.apply_only:
-        apply_only(pb, args.apply_only, wl, torch, args.block)
+        apply_only(args, torch, smfs, wl)
         return
-    t0 = time.perf_counter()
-    pb.setup()
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    log(f"setup (device assembly + batched SVD of {pb.sizes.n_factors - 1} self blocks): {setup_s:.1f} s")
 
-    rbms = [torch.from_numpy(wl.random_rbm(pb.P, 1, 1000 + i)[0].reshape(-1)).cuda()
-            for i in range(args.warmup + args.steps)]
-    for i in range(args.warmup):
-        out = pb.solve_resistance(rbms[i])
-        log(f"warmup {i}: it {out['iterations']} true res {out['true_rel_residual']:.2e}")
-    torch.cuda.synchronize()
-
-    pb.profile(True)
-    step_ms, pairs, outs = [], 0, []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        out = pb.solve_resistance(rbms[args.warmup + i])
-        torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-        pairs += out["pair_evals"]
-        outs.append(out)
-        log(f"step {i}: {step_ms[-1]:.1f} ms, it {out['iterations']}, est {out['rel_residual']:.2e}, "
-            f"true {out['true_rel_residual']:.2e}, eps_res {out['eps_res_max']:.2e}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    pb.profile(False)
-    st = pb.profile_read()
-
-    direct_avg_s = st["direct_ms"] / max(1, st["direct_launches"]) * 1e-3
-    achieved = st["direct_flops"] / direct_avg_s / 1e12
-    pinv_avg_s = st["pinv_ms"] / max(1, st["pinv_launches"]) * 1e-3
-    result = {
-        "metric": "Stokeslet pair-evals/s (FP64 resistance solve, 100-sphere cluster); "
-                  "solve time at 1e-3 relative surface velocity, mixed vs FP64, p50/p99",
-        "value": pairs / elapsed,
-        "unit": "pair-evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "100 unit spheres, cube at volume fraction 0.2, gaps log-uniform [1e-3, 1e-1]; "
-                        "N=600 proxy on R_p=0.7, 780 base nodes, 20 S+R+D image nodes per contact "
-                        "(gap < 0.2), caps 2x360; FP64; GMRES tol 1e-10 (unrestarted, <= 2000 iterations); "
-                        "one resistance solve per step",
-            "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S,
-            "pairs_per_apply": pb.pairs_per_apply, "precision": "fp64",
-        },
-        "solve_ms_p50": float(np.percentile(step_ms, 50)),
-        "solve_ms_p99": float(np.percentile(step_ms, 99)),
-        "setup_s": setup_s,
-        "gmres_iterations": [o["iterations"] for o in outs],
-        "true_rel_residual": [o["true_rel_residual"] for o in outs],
-        "eps_res_max": [o["eps_res_max"] for o in outs],
-        "roofline": {
-            "kernel": "k_direct_f64 (direct sum of every off-sphere pair)",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP64_VALU_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_VALU_TFLOPS,
-            "traffic": DIRECT_TRAFFIC_BYTES,
-            "traffic_unit": "bytes per launch",
-            "avg_launch_ms": direct_avg_s * 1e3,
-            "launches": st["direct_launches"],
-            "flops_per_launch": st["direct_flops"],
-        },
-        "pinv_apply": {
-            "bound": "hbm",
-            "achieved": st["pinv_bytes"] / pinv_avg_s / 1e9 if pinv_avg_s > 0 else None,
-            "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "avg_launch_ms": pinv_avg_s * 1e3, "bytes_per_launch": st["pinv_bytes"],
-        },
-    }
-    if args.block:
-        log(f"block product of {args.block} vectors vs {args.block} single products ...")
-        result["block_vs_single"] = block_vs_single(pb, torch, args.block, 2)
+    pk, pb, result = headline(args, torch, smfs, wl, budget)
     del pb
     torch.cuda.empty_cache()
+    skipped = []
+    if not args.no_cpu_baseline:
+        if budget.fits(3 * args.cpu_seconds + 30 + args.reserve_s):
+            log("cpu baseline (oracle) ...")
+            result["cpu_baseline"] = cpu_baseline(pk, args.cpu_seconds)
+            log(f"  {result['cpu_baseline']['value']:.3e} pair-evals/s: {result['cpu_baseline']['sample']}")
+        else:
+            skipped.append("cpu_baseline")
+    if args.solve_spheres > 0:
+        if budget.fits(60 + args.reserve_s):
+            result["solve"] = solve_section(args, torch, smfs, wl, budget)
+            torch.cuda.empty_cache()
+        else:
+            skipped.append("solve")
     if args.two_sphere_reps > 0:
-        result["two_sphere"] = two_sphere(args, torch, smfs, wl)
+        if budget.fits(15 + args.reserve_s):
+            result["two_sphere"] = two_sphere(args, torch, smfs, wl, budget)
+        else:
+            skipped.append("two_sphere")
+    if skipped:
+        result["skipped_for_wall_budget"] = skipped
+    result["wall_s"] = time.perf_counter() - budget.t0
+    print(json.dumps(result), flush=True)
+
+    # optional sections: stderr and --sections-out only
+    extra = {}
+    if args.block:
+        extra["block_vs_single"] = block_section(args, torch, smfs, wl)
         torch.cuda.empty_cache()
     if args.block_spheres > 0:
-        result["block_solve"] = block_solve(args, torch, smfs, wl)
-        torch.cuda.empty_cache()
-    if not args.no_mixed:
-        result["mixed_vs_fp64"] = mixed_vs_fp64(args, torch, smfs, wl)
+        extra["block_solve"] = block_solve(args, torch, smfs, wl)
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
-        result["serving"] = serving(args, torch, smfs, reqs, arrivals)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(pk, args.cpu_stride, two_sphere=args.two_sphere_reps > 0)
-    print(json.dumps(result), flush=True)
+        extra["serving"] = serving(args, torch, smfs, reqs, arrivals)
+    if extra:
+        log("sections: " + json.dumps(extra))
+        if args.sections_out:
+            with open(args.sections_out, "w") as f:
+                json.dump(extra, f, indent=1)
 
 
 if __name__ == "__main__":
