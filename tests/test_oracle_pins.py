@@ -390,3 +390,104 @@ def test_free_sphere_follows_linear_flow(single_sphere):
     om_ref = 0.5 * np.array([L[2, 1] - L[1, 2], L[0, 2] - L[2, 0], L[1, 0] - L[0, 1]])
     assert _rel_err(out["rbm"][0, :3], v_ref) < 1e-6
     assert _rel_err(out["rbm"][0, 3:], om_ref) < 1e-6
+
+
+# -- residuals (eqs. residual_x, residual) and the floor rule ---------------
+
+def _point_source_problem(c, kinds, a=1.0, mu=1.0):
+    """An oracle Problem whose only sources sit at the sphere centre (one
+    per entry of kinds): the exact single-sphere solutions are sums of
+    such centre singularities, so the residual routine can be checked on
+    fields that satisfy the boundary data exactly."""
+    from types import SimpleNamespace
+    g = SimpleNamespace(src_pos=np.repeat(np.asarray(c, float)[None, :], len(kinds), 0),
+                        src_kind=np.asarray(kinds, np.int32), centers=np.asarray(c, float)[None, :],
+                        params=SimpleNamespace(mu=mu), radius=a)
+    pb = mfs.Problem.__new__(mfs.Problem)
+    pb.g = g
+    return pb
+
+
+def test_residuals_vanish_for_exact_single_sphere_fields():
+    """Translation: Stokeslet 6 pi mu a U plus dipole -pi a^3 U at the centre;
+    rotation: rotlet 8 pi mu a^3 omega; both reproduce the rigid motion on
+    the sphere exactly, so eps_res and the absolute form are rounding only."""
+    rng = np.random.default_rng(11)
+    for a, mu in ((1.0, 1.0), (1.4, 0.6)):
+        c = np.array([0.4, -1.0, 2.0])
+        pts = c + a * _sphere_points(300, rng)
+        sph = np.zeros(len(pts), int)
+        U, w = np.array([0.3, -0.9, 0.4]), np.array([-0.5, 0.2, 0.8])
+        pb = _point_source_problem(c, [geo.KIND_S, geo.KIND_D, geo.KIND_R], a, mu)
+        lam = np.array([6 * math.pi * mu * a * U, -math.pi * a ** 3 * U, 8 * math.pi * mu * a ** 3 * w])
+        rbm = np.concatenate([U, w])[None, :]
+        eps, absr = pb.residuals(lam, rbm, pts, sph)
+        assert eps < 1e-14 and absr < 1e-14
+
+
+def test_residuals_planted_mismatch_and_floor():
+    """A field of pure rotation omega = w e_z about the centre against
+    boundary data with an extra translation dU (perpendicular to the field at
+    the equator point).  Equator point: |u - u_bc| = |dU|, |u_bc| =
+    sqrt(w^2 a^2 + |dU|^2).  Pole point: u_bc = dU, a relative residual of 1,
+    which the floor rule (read: leave out points with |u_bc| <= 1e-3 max
+    |u_bc|) drops when |dU| is below 1e-3 of the largest boundary speed and
+    keeps when above.  Euclidean norms per point: dU has two nonzero
+    components, so a max-norm would give other values."""
+    a, w = 1.0, 2.0
+    c = np.array([1.0, 0.0, -0.5])
+    pts = c + np.array([[a, 0.0, 0.0], [0.0, 0.0, a]])      # equator (on x), pole (on z)
+    sph = np.zeros(2, int)
+    pb = _point_source_problem(c, [geo.KIND_R], a)
+    lam = np.array([[0.0, 0.0, 8 * math.pi * a ** 3 * w]])  # rotation about z
+    # omega x r at the equator point is along +y; dU along x and z is perpendicular to it
+    for s, expect_eps in ((5e-4, None), (4e-3, 1.0)):
+        dU = s * w * a * np.array([0.6, 0.0, 0.8])
+        rbm = np.concatenate([dU, [0.0, 0.0, w]])[None, :]
+        eps, absr = pb.residuals(lam, rbm, pts, sph)
+        d = np.linalg.norm(dU)
+        eq = d / math.sqrt((w * a) ** 2 + d * d)
+        assert abs(absr - eq) < 1e-14                     # max |u - u_bc| / max |u_bc|
+        if expect_eps is None:                            # pole below the floor: left out
+            assert abs(eps - eq) < 1e-14
+        else:                                             # pole above the floor: ratio 1
+            assert abs(eps - 1.0) < 1e-14
+
+
+# -- the adaptive image count, eq. (image_est) -------------------------------
+
+@pytest.mark.parametrize("delta,n", [(1e-3, 21), (1e-2, 12), (0.1, 3), (0.1499, 2), (0.15, 0), (0.5, 0),
+                                     (2e-3, 18), (5e-2, 6)])
+def test_image_rule_values(delta, n):
+    """Hand-evaluated: -8.72 log10(delta) - 6.15 is 20.01 at 1e-3 (21 after
+    the ceiling), 11.29 at 1e-2, 2.57 at 0.1, 1.04 at 0.1499, 17.39 at 2e-3,
+    5.20 at 5e-2; zero at and above 0.15."""
+    assert geo.n_image_rule(delta) == n
+
+
+def test_image_rule_ceiling_boundary():
+    """Where the fitted line crosses an integer the count steps up just past
+    it: the value 5 is reached at log10(delta) = -11.15 / 8.72."""
+    d5 = 10.0 ** (-11.15 / 8.72)
+    assert geo.n_image_rule(d5 * (1 + 1e-9)) == 5
+    assert geo.n_image_rule(d5 * (1 - 1e-9)) == 6
+
+
+# -- GMRES: the true residual it reports ------------------------------------
+
+def test_gmres_reports_true_residual():
+    """On a well-conditioned dense system the reported true residual is
+    ||b - A x|| / ||b|| of the returned x, it agrees with the recursive
+    estimate far above the rounding floor, and n steps solve an n x n
+    system to rounding."""
+    rng = np.random.default_rng(5)
+    n = 40
+    A = np.eye(n) + 0.3 * rng.standard_normal((n, n)) / math.sqrt(n)
+    b = rng.standard_normal(n)
+    res = mfs.gmres(lambda v: A @ v, b, 1e-6, 200)
+    direct = np.linalg.norm(b - A @ res.x) / np.linalg.norm(b)
+    assert res.true_rel_residual == pytest.approx(direct, rel=1e-10)
+    assert res.rel_residual <= 1e-6
+    assert abs(res.true_rel_residual - res.rel_residual) < 1e-9
+    full = mfs.gmres(lambda v: A @ v, b, 0.0, n)
+    assert full.iterations == n and full.true_rel_residual < 1e-13
