@@ -274,6 +274,22 @@ int smfs_block_workspace_bytes(const smfs_problem *pb, int32_t nrhs, int32_t res
 int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y, int64_t ld,
                      void *ws, size_t ws_bytes, smfs_stream stream);
 
+/* smfs_apply_block for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the block workspace is a library-held device array of
+ * smfs_noalloc_scratch_bytes() bytes (64 MiB) per GPU, kept until the
+ * process ends; nothing is allocated by this call.  Inputs and outputs as
+ * for smfs_apply_block (mu, y [dev], nrhs vectors of stride ld >= 3 T, not
+ * overlapping); the result is bitwise that of smfs_apply_block.  Returns
+ * SMFS_E_NOMEM, launching nothing, when the problem and nrhs need more
+ * scratch than that (smfs_block_workspace_bytes(pb, nrhs, 0) tells).  All
+ * calls on one GPU share its array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.  Not
+ * profiled by smfs_profile. */
+int smfs_apply_block_noalloc(smfs_problem *pb, int32_t nrhs, const double *mu, double *y,
+                             int64_t ld, smfs_stream stream);
+size_t smfs_noalloc_scratch_bytes(void);
+
 typedef struct smfs_block_out {
   double *ft;                  /* [dev, out] nrhs x P x 6 forces/torques, or NULL */
   double *mu;                  /* [dev, out] nrhs x 3T solutions (stride 3T), or NULL */

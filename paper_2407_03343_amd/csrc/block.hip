@@ -286,6 +286,16 @@ int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B
 
 }  // namespace
 
+// Block product on a workspace at base (at least block_apply_bytes bytes,
+// 256-byte aligned), for other entry points of the library.
+size_t block_apply_bytes(const Problem &pb, int32_t nrhs) { return block_layout(pb, nrhs, 0, nullptr).bytes; }
+
+int block_apply_on(Problem &pb, int32_t nrhs, const double *mu, double *y, int64_t ld, char *base,
+                   hipStream_t s) {
+  const BlockLayout L = block_layout(pb, nrhs, 0, base);
+  return apply_block(pb, L, nrhs, mu, y, ld, s);
+}
+
 }  // namespace smfs
 
 using namespace smfs;

@@ -176,6 +176,10 @@ int rank_tables(Problem &pb, hipStream_t s);
 int transform(Problem &pb, const double *mu, double *lam, hipStream_t s);
 int record_event(Problem &pb, hipStream_t s, size_t &idx);
 int32_t direct_splits(int64_t n_tiles, int64_t S);
+// block.hip
+size_t block_apply_bytes(const Problem &pb, int32_t nrhs);
+int block_apply_on(Problem &pb, int32_t nrhs, const double *mu, double *y, int64_t ld, char *base,
+                   hipStream_t s);
 
 }  // namespace smfs
 

@@ -30,6 +30,7 @@ EXPORTED = [
     "smfs_force_torque",
     "smfs_eval_velocity", "smfs_solve_resistance", "smfs_solve_mobility", "smfs_set_solver",
     "smfs_pairs_per_apply", "smfs_block_workspace_bytes", "smfs_apply_block",
+    "smfs_apply_block_noalloc", "smfs_noalloc_scratch_bytes",
     "smfs_solve_resistance_block", "smfs_server_create", "smfs_server_destroy",
     "smfs_server_clock", "smfs_server_submit", "smfs_server_step", "smfs_server_poll",
     "smfs_server_release", "smfs_server_stats_read",
@@ -156,6 +157,8 @@ def lib():
         "smfs_server_release": ([vp, i64], C.c_int),
         "smfs_server_stats_read": ([vp, P(smfs_server_stats)], C.c_int),
         "smfs_apply_block": ([vp, i32, vp, vp, i64, vp, C.c_size_t, vp], C.c_int),
+        "smfs_apply_block_noalloc": ([vp, i32, vp, vp, i64, vp], C.c_int),
+        "smfs_noalloc_scratch_bytes": ([], C.c_size_t),
         "smfs_solve_resistance_block": ([vp, i32, vp, i32, vp, C.c_size_t, P(smfs_block_out), vp],
                                         C.c_int),
         "smfs_set_solver": ([vp, i32, dbl, i32], C.c_int),
