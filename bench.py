@@ -56,7 +56,7 @@ PEAK_HBM_GBS = 8000.0
 # reads back) plus WRITE_SIZE (x1), KiB per dispatch, as recorded in the
 # counter summary of this kernel and workload under profiles/; None until
 # counters of the current kernel on this workload are taken.
-DIRECT_TRAFFIC_BYTES = None
+DIRECT_TRAFFIC_BYTES = (2 * 6230207.7 + 422606.2) * 1024
 
 FORMS = (("fp64", 0), ("mixed", 1), ("mixed_far", 2))   # SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR
 
@@ -159,6 +159,8 @@ def headline(args, torch, smfs, wl, budget):
     log(f"FP64 product: {elapsed / args.steps * 1e3:.1f} ms per step, direct sum "
         f"{direct_avg_s * 1e3:.1f} ms ({achieved:.1f} TFLOP/s), pseudo-inverse {pinv_avg_s * 1e3:.2f} ms")
 
+    if args.no_mixed:
+        return pk, pb, headline_result(args, pk, pb, elapsed, st, setup_s, ranks, None)
     # mixed form: the same products, then its error against FP64
     m_el, m_st = timed_products(pb, torch, mu, y, smfs.SMFS_MIXED, min(args.warmup, 2), args.steps)
     errs = {}
@@ -169,7 +171,22 @@ def headline(args, torch, smfs, wl, budget):
                       for f, p in FORMS[1:]}
     log(f"mixed product: {m_el / args.steps * 1e3:.1f} ms per step ({elapsed / m_el:.2f}x FP64); "
         f"error vs FP64 (off-diagonal, max-norm): physical {errs['physical']}, random {errs['random']}")
+    mixed = {
+        "precision": "SMFS_MIXED: FP32 pseudo-inverse and far field for the contact-free spheres",
+        "ms_per_step": m_el / args.steps * 1e3,
+        "pair_evals_per_s": pb.pairs_per_apply * args.steps / m_el,
+        "speedup_over_fp64": elapsed / m_el,
+        "kernels": mixed_kernel_rates(m_st),
+        "offdiag_rel_err_vs_fp64": errs,
+    }
+    return pk, pb, headline_result(args, pk, pb, elapsed, st, setup_s, ranks, mixed)
 
+
+def headline_result(args, pk, pb, elapsed, st, setup_s, ranks, mixed):
+    pairs = pb.pairs_per_apply * args.steps
+    direct_avg_s = st["direct_ms"] / max(1, st["direct_launches"]) * 1e-3
+    pinv_avg_s = st["pinv_ms"] / max(1, st["pinv_launches"]) * 1e-3
+    achieved = st["direct_flops"] / direct_avg_s / 1e12
     result = {
         "metric": "Stokeslet pair-evals/s (one-body preconditioned product G_hat mu, FP64, "
                   "2000-sphere packing); solve time at 1e-3 relative surface velocity, mixed vs FP64, "
@@ -218,16 +235,10 @@ def headline(args, torch, smfs, wl, budget):
             "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "avg_launch_ms": pinv_avg_s * 1e3, "bytes_per_launch": st["pinv_bytes"],
         },
-        "mixed": {
-            "precision": "SMFS_MIXED: FP32 pseudo-inverse and far field for the contact-free spheres",
-            "ms_per_step": m_el / args.steps * 1e3,
-            "pair_evals_per_s": pairs / m_el,
-            "speedup_over_fp64": elapsed / m_el,
-            "kernels": mixed_kernel_rates(m_st),
-            "offdiag_rel_err_vs_fp64": errs,
-        },
     }
-    return pk, pb, result
+    if mixed is not None:
+        result["mixed"] = mixed
+    return result
 
 
 def mixed_kernel_rates(st):
@@ -485,14 +496,18 @@ def block_section(args, torch, smfs, wl):
 
 def block_solve(args, torch, smfs, wl):
     """Many-right-hand-side solve against the same systems solved one after
-    another: a cut of the volume-fraction-0.35 workload (40% of the spheres
-    in near-contact pairs), 64 rigid motions, both forms GMRES(m) with the
-    same restart length and tolerance in FP64.  The sequential time is
-    measured on a sample of the systems and scaled to all of them."""
+    another in FP64: a cut of the volume-fraction-0.35 workload (40% of the
+    spheres in near-contact pairs; 1000 proxies and 1680 base nodes), 64
+    rigid motions, GMRES(m) with the same restart length and tolerance; the
+    block solve in --block-precision (mixed: FP32 far field in the cycles,
+    FP64 restarts).  The sequential time is measured on a sample of the
+    systems and scaled to all of them."""
     pk, rbm = wl.workload_block500(args.block_spheres, seed=args.seed)
     nrhs, m = rbm.shape[0], args.block_restart
-    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=m, gmres_max_it=args.block_max_it,
-                      gmres_tol=args.block_tol, gmres_check_every=0)
+    prec = smfs.SMFS_MIXED_FAR if args.block_precision == "mixed_far" else smfs.SMFS_FP64
+    pb = smfs.Problem(pk.centers, pk.radius, n_proxy=1000, n_colloc_base=1680, gmres_restart=m,
+                      gmres_max_it=args.block_max_it, gmres_tol=args.block_tol, gmres_check_every=0,
+                      precision=prec)
     pb.bind()
     t0 = time.perf_counter()
     pb.setup()
@@ -509,6 +524,7 @@ def block_solve(args, torch, smfs, wl):
     ft_blk = blk["ft"].cpu().numpy()
     k = min(nrhs, args.block_sequential)
     its, dft = [], 0.0
+    pb.set_solver(smfs.SMFS_FP64, args.block_tol)
     t2 = time.perf_counter()
     for q in range(k):
         o = pb.solve_resistance(R[q].reshape(-1).contiguous(), want_check=False)
@@ -519,7 +535,9 @@ def block_solve(args, torch, smfs, wl):
     t_seq = (time.perf_counter() - t2) / k * nrhs
     return {
         "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S, "nrhs": nrhs, "restart": m,
-        "tol": args.block_tol, "setup_s": setup_s,
+        "tol": args.block_tol, "setup_s": setup_s, "block_precision": args.block_precision,
+        "block_status": int(blk["status"]), "block_refinements": int(blk["refinements"]),
+        "block_pair_evals_f32": int(blk["pair_evals_f32"]),
         "block_solve_s": t_block, "block_iterations_max": int(blk["max_iterations"]),
         "block_converged": int(blk["n_converged"]),
         "max_true_rel_residual": float(np.max(blk["true_rel_residual"])),
@@ -566,8 +584,9 @@ def serving(args, torch, smfs, reqs, arrivals):
     disc = dict(n_proxy=args.serve_proxy, n_colloc_base=args.serve_colloc, n_image=args.serve_image,
                 n_check_base=0)
     solver = dict(gmres_tol=args.serve_tol, gmres_restart=100, gmres_max_it=3000)
+    prec = smfs.SMFS_MIXED_FAR if args.serve_precision == "mixed_far" else smfs.SMFS_FP64
     srv = smfs.Server(arena_bytes=args.serve_arena << 30, max_active=args.serve_slots,
-                      setup_workers=args.serve_workers, **disc, **solver)
+                      setup_workers=args.serve_workers, server_precision=prec, **disc, **solver)
     t0 = srv.clock() + 0.02
     ids, i, last_log = [], 0, time.perf_counter()
     while True:
@@ -596,6 +615,10 @@ def serving(args, torch, smfs, reqs, arrivals):
     its = np.array([r["iterations"] for r in res])
     out = {
         "requests": n, "rate_per_s": args.serve_rate, "setup_workers": args.serve_workers,
+        "precision": args.serve_precision,
+        "pair_evals_f32": int(sum(r["pair_evals_f32"] for r in res)),
+        "refinements_max": int(max(r["refinements"] for r in res)),
+        "stagnated": int(sum(1 for r in res if r["status"] == 3)),
         "discretisation": disc, "tol": args.serve_tol, "slots": args.serve_slots,
         "latency_ms_p50": float(np.percentile(lat, 50)),
         "latency_ms_p99": float(np.percentile(lat, 99)),
@@ -629,7 +652,8 @@ def serving(args, torch, smfs, reqs, arrivals):
 
 def apply_only(args, torch, smfs, wl):
     """Profiling aid: N products with G_hat on the headline workload with
-    seeded full-rank factors in place of the SVD set-up, then one plain
+    seeded rank-48 factors in place of the SVD set-up (the direct sum, the
+    kernel counted here, does not depend on the factors), then one plain
     1 GiB fill and one elementwise product (the counter calibration
     kernels).  Prints one JSON line of event timings."""
     pk = wl.workload_packing2000(args.spheres, seed=args.seed)
@@ -638,7 +662,7 @@ def apply_only(args, torch, smfs, wl):
         info = pb.factor_info(fid)
         if info["sphere"] < 0:
             continue
-        U, s, V = wl.random_factors(info["rows"], info["cols"], info["cols"], seed=100 + fid)
+        U, s, V = wl.random_factors(info["rows"], info["cols"], 48, seed=100 + fid)
         pb.import_factor(fid, U, s, V)
     mu = torch.from_numpy(wl.random_vector(3 * pb.T, 3)).cuda()
     y = torch.empty_like(mu)
@@ -673,6 +697,7 @@ def main():
                          "their estimated cost no longer fits")
     ap.add_argument("--reserve-s", type=float, default=20.0, help="seconds kept in reserve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed products beside the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="length of the oracle's timed sample")
     ap.add_argument("--solve-spheres", type=int, default=100,
                     help="spheres of the solve-time comparison (a cut of the headline recipe; 0: skip)")
@@ -695,6 +720,8 @@ def main():
     ap.add_argument("--block-tol", type=float, default=1e-8)
     ap.add_argument("--block-max-it", type=int, default=3000)
     ap.add_argument("--block-sequential", type=int, default=4)
+    ap.add_argument("--block-precision", choices=["fp64", "mixed_far"], default="mixed_far",
+                    help="products of the block solve (the sequential solves are FP64)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving stream (0: skip; the full stream is 512)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -705,6 +732,8 @@ def main():
     ap.add_argument("--serve-image", type=int, default=6)
     ap.add_argument("--serve-tol", type=float, default=1e-6)
     ap.add_argument("--serve-workers", type=int, default=1, help="set-up worker threads")
+    ap.add_argument("--serve-precision", choices=["fp64", "mixed_far"], default="fp64",
+                    help="products inside the served GMRES iterations")
     ap.add_argument("--serve-sequential", type=int, default=3,
                     help="requests solved one after another for the comparison")
     args = ap.parse_args()

@@ -15,9 +15,10 @@
  * Conventions
  *  - Memory: arrays marked [host] are ordinary host memory; arrays marked
  *    [dev] are device memory of the current HIP device.  The library never
- *    allocates device memory for the solver itself: the caller allocates
+ *    allocates device memory for a problem: the caller allocates
  *    smfs_sizes.workspace_bytes of device memory and binds it with
- *    smfs_bind().  (smfs_setup() lets rocSOLVER take its own scratch.)
+ *    smfs_bind(), and passes the set-up scratch (smfs_setup_workspace_bytes)
+ *    and the block workspaces to the calls that need them.
  *  - Streams: every device call is ordered on the hipStream_t passed in
  *    (NULL = the null stream).  Calls that return host statistics
  *    synchronise that stream before returning.
@@ -60,7 +61,8 @@ enum {
   SMFS_E_NOMEM = -4,               /* workspace too small */
   SMFS_E_SVD = -5,
   SMFS_E_DEVICE = -6,              /* HIP error */
-  SMFS_E_STATE = -7                /* call out of order (e.g. apply before setup) */
+  SMFS_E_STATE = -7,               /* call out of order (e.g. apply before setup) */
+  SMFS_E_AGAIN = -8                /* the server's queue is full: submit again later */
 };
 
 /* Precision of the products inside GMRES.  SMFS_MIXED: the sources of
@@ -70,6 +72,10 @@ enum {
  * FP64).  Everything else is FP64 in all modes. */
 enum { SMFS_FP64 = 0, SMFS_MIXED = 1, SMFS_MIXED_FAR = 2 };
 enum { SMFS_KIND_S = 1, SMFS_KIND_R = 2, SMFS_KIND_D = 4 };
+/* SVD of the self blocks at set-up: SMFS_SVD_JACOBI = Householder QR, then
+ * one-sided Jacobi on R in the library's kernels, then U = Q U_R;
+ * SMFS_SVD_ROCSOLVER = rocSOLVER's bidiagonal gesvd. */
+enum { SMFS_SVD_JACOBI = 0, SMFS_SVD_ROCSOLVER = 1 };
 
 /* Discretisation and solver parameters (lengths in radii). */
 typedef struct smfs_params {
@@ -97,6 +103,7 @@ typedef struct smfs_params {
   int32_t gmres_check_every;/* true-residual guard period in iterations, active once the
                                recursive estimate is below 1e-3; 0 = off.  Each check
                                forms the iterate and costs one product with G_hat */
+  int32_t svd_method;       /* SMFS_SVD_ROCSOLVER (default) or SMFS_SVD_JACOBI */
 } smfs_params;
 
 typedef struct smfs_sizes {
@@ -168,10 +175,21 @@ int smfs_factor_info(const smfs_problem *pb, int32_t fid, int32_t *rows, int32_t
 /* Bind caller-provided device workspace and upload the node sets. */
 int smfs_bind(smfs_problem *pb, void *dev_workspace, size_t bytes, smfs_stream stream);
 
+/* Device scratch bytes smfs_setup needs for this problem: one batch of
+ * assembled self blocks of the largest shape group, the SVD's status words
+ * and the SVD's own work arrays (rocSOLVER's size query).  Host only. */
+int smfs_setup_workspace_bytes(smfs_problem *pb, size_t *bytes);
+
 /* Assemble every distinct self block B = W G^(kk) on the device and factor
- * it with a thin SVD (rocSOLVER), keeping sigma_i > trunc_rel * sigma_1
- * (Section 5, eps_trunc).  Synchronises the stream. */
-int smfs_setup(smfs_problem *pb, smfs_stream stream);
+ * it with a thin SVD (rocSOLVER, one batched call per group of equal shape),
+ * keeping sigma_i > trunc_rel * sigma_1 (Section 2.2, eq. transform; the
+ * truncation eps_trunc of Section 5).  scratch [dev]: at least
+ * smfs_setup_workspace_bytes bytes, 256-byte aligned, owned by the caller
+ * and free again when the call returns; the library allocates no device
+ * memory here (rocSOLVER works in the scratch).  Errors: SMFS_E_STATE if not
+ * bound, SMFS_E_NOMEM if the scratch is too small, SMFS_E_SVD if an SVD
+ * fails.  Synchronises the stream. */
+int smfs_setup(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream);
 
 /* Install a factor computed elsewhere.  U [host] rows x rank column-major,
  * sigma [host] rank, V [host] cols x rank row-major.  Synchronises. */
@@ -256,7 +274,9 @@ int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_
  * the per-sphere pseudo-inverse (eq. transform) becomes a pair of small
  * GEMMs per sphere on the matrix cores.  A block workspace of device memory
  * is allocated by the caller; its size depends on nrhs and the Krylov
- * restart length.  Only the FP64 product exists in block form.
+ * restart length.  Block products come in FP64 and in a mixed form (the
+ * proxies of contact-free spheres summed in FP32 from FP32 copies of their
+ * FP64 strengths, the block pseudo-inverse and every other pair in FP64).
  *
  * Vectors of a block are stored one after another: vector q starts at
  * q * ld (ld >= 3 T elements, the same for input and output blocks). */
@@ -268,11 +288,12 @@ int smfs_block_workspace_bytes(const smfs_problem *pb, int32_t nrhs, int32_t res
                                size_t *bytes);
 
 /* y_q = G_hat mu_q for q < nrhs (eq. resistance with the identity self
- * blocks of Section 2.2), FP64.  mu, y [dev]: nrhs vectors of stride
- * ld >= 3 T; mu and y must not overlap.  ws [dev]: at least
- * smfs_block_workspace_bytes(pb, nrhs, 0) bytes, 256-byte aligned. */
+ * blocks of Section 2.2).  precision SMFS_FP64, or SMFS_MIXED /
+ * SMFS_MIXED_FAR (both the mixed block form above).  mu, y [dev]: nrhs
+ * vectors of stride ld >= 3 T; mu and y must not overlap.  ws [dev]: at
+ * least smfs_block_workspace_bytes(pb, nrhs, 0) bytes, 256-byte aligned. */
 int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y, int64_t ld,
-                     void *ws, size_t ws_bytes, smfs_stream stream);
+                     int32_t precision, void *ws, size_t ws_bytes, smfs_stream stream);
 
 /* smfs_apply_block for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
@@ -296,18 +317,25 @@ typedef struct smfs_block_out {
   int32_t *iterations;         /* [host, out] nrhs GMRES iteration counts, or NULL */
   double *true_rel_residual;   /* [host, out] nrhs values ||b - G_hat mu|| / ||b||, or NULL */
   int32_t max_iterations;      /* out: block products in the Krylov iterations */
-  int32_t n_converged;         /* out: systems that met gmres_tol */
+  int32_t n_converged;         /* out: systems whose GMRES estimate met gmres_tol */
   double t_gmres_ms, t_post_ms;
   int64_t pair_evals;          /* out: pair x right-hand-side evaluations */
+  int64_t pair_evals_f32;      /* out: of which in FP32 (mixed precision) */
+  int32_t refinements;         /* out: mixed precision: restarts from FP64 true residuals
+                                  after every estimate met the tolerance */
 } smfs_block_out;
 
 /* Resistance solves for nrhs rigid motions together: rbm [dev]
  * nrhs x P x 6.  Every system runs its own GMRES(restart) with the
  * problem's gmres_tol and gmres_max_it; the Krylov iterations of all
  * systems advance in lock step through block products, a system that has
- * converged stays frozen while the others go on.  ws as above with
- * restart > 0.  Returns SMFS_NOT_CONVERGED when some system did not meet
- * the tolerance. */
+ * converged stays frozen while the others go on.  The products follow
+ * params.precision: in a mixed form every restart takes the FP64 true
+ * residuals, and once every estimate met the tolerance the systems restart
+ * from them up to twice (those above the tolerance go on).  ws as above
+ * with restart > 0.  Returns SMFS_OK when every FP64 true residual met
+ * gmres_tol, SMFS_STAGNATED when every estimate did but some true residual
+ * did not, SMFS_NOT_CONVERGED otherwise. */
 int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rbm, int32_t restart,
                                 void *ws, size_t ws_bytes, smfs_block_out *out,
                                 smfs_stream stream);
@@ -323,28 +351,68 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
  * one launch of each kernel of the product with G_hat and of the Arnoldi
  * step covers all of them, and a request that arrives between steps joins
  * at the next one (continuous batching).  A finished request leaves at once
- * and its memory and slot go to the next waiting request.  The arithmetic
- * per request is the FP64 product and GMRES of smfs_solve_resistance, so a
- * result does not depend on which other requests share the launches.
+ * and its memory and slot go to the next waiting request.  Every request
+ * keeps the chunking and summation order of its own problem in every
+ * kernel, so a result does not depend on which other requests share the
+ * launches.
  *
- * The shared factor of contact-free spheres (Section 2.2, eq. transform) depends only on
- * the discretisation: the server factorises it once and copies it into each
- * request.  Serving is FP64; params->precision must be SMFS_FP64. */
+ * The shared factor of contact-free spheres (Section 2.2, eq. transform)
+ * depends only on the discretisation: the server factorises it once and
+ * copies it into each request.
+ *
+ * Precision: SMFS_FP64, or SMFS_MIXED_FAR (the far field of each request's
+ * contact-free proxies summed in FP32 from FP64 strengths inside the
+ * Krylov iterations; pseudo-inverses, contact spheres, image lines, Arnoldi
+ * and every restart's true residual in FP64).  A cycle whose estimate meets
+ * the tolerance restarts from the FP64 true residual (up to two such
+ * refinements) before the request finishes, so the FP32 far field costs no
+ * accuracy beyond the tolerance.
+ *
+ * Memory: the caller gives the server one block of device memory, kept
+ * until smfs_server_destroy: a fixed part (smfs_server_memory_bytes: the
+ * shared factor, per-slot descriptors, every set-up worker's scratch) and
+ * an arena (the rest) that holds the requests' workspaces.  The server
+ * allocates no device memory; rocSOLVER works in the workers' scratch. */
 typedef struct smfs_server smfs_server;
 
+typedef struct smfs_server_config {
+  double radius;                /* the common sphere radius of every request */
+  int32_t max_active;           /* slots: requests resident together, including those
+                                   being set up, 1..4096 */
+  int32_t setup_workers;        /* threads building admitted requests, 1..64, each with
+                                   its own stream and rocBLAS handle */
+  int32_t max_queued;           /* requests waiting for admission; smfs_server_submit returns
+                                   SMFS_E_AGAIN when this many wait (0: no limit) */
+  int32_t precision;            /* SMFS_FP64 or SMFS_MIXED_FAR */
+  size_t worker_scratch_bytes;  /* device scratch per set-up worker: a quarter (at least
+                                   64 MiB) for rocSOLVER's work arrays, the rest for the
+                                   batched SVD inputs and outputs (0: 4 GiB) */
+} smfs_server_config;
+
+/* Defaults: radius 1, 64 slots, 1 worker, no queue limit, FP64, 4 GiB. */
+int smfs_server_config_default(smfs_server_config *c);
+
+/* Bytes of the fixed part of the server's device memory for these
+ * settings (host only); the arena is whatever the caller adds to it. */
+int smfs_server_memory_bytes(const smfs_params *p, const smfs_server_config *c, size_t *fixed_bytes);
+
 /* p: discretisation and solver settings of every request (gmres_restart is
- * the Krylov restart length, which sets each request's footprint).
- * radius: the common sphere radius.  arena_bytes: device memory for the
- * requests' workspaces (allocated once here).  max_active: slots (requests
- * resident together, including those being set up), 1..4096.
- * setup_workers: threads building admitted requests (1..64), each with its
- * own stream, rocBLAS handle and 4 GiB of SVD scratch.  A worker takes every
- * request that can be admitted at that moment (up to 64) and factorises the
- * self blocks of all their contact spheres together: batched SVDs per block
- * shape, each call of a fixed batch count for its shape. */
-int smfs_server_create(const smfs_params *p, double radius, size_t arena_bytes, int32_t max_active,
-                       int32_t setup_workers, smfs_server **out);
-/* Waits for the worker thread and frees every resource. */
+ * the Krylov restart length, which sets each request's footprint;
+ * p->precision is replaced by c->precision).  dev_mem [dev]: dev_bytes of
+ * device memory, 256-byte aligned, owned by the caller and used by the
+ * server until smfs_server_destroy; the part beyond
+ * smfs_server_memory_bytes is the arena.  A worker takes every request that
+ * can be admitted at that moment (up to 64) and factorises the self blocks
+ * of all their contact spheres together: batched SVDs per block shape, each
+ * call of a fixed batch count for its shape (set by the shape and the
+ * worker's scratch alone, so that a request's factors do not depend on its
+ * neighbours).  Errors: SMFS_E_INVALID_ARG (bad settings or pointer),
+ * SMFS_E_UNSUPPORTED (precision), SMFS_E_NOMEM (no room for an arena that
+ * holds a one-sphere request). */
+int smfs_server_create(const smfs_params *p, const smfs_server_config *c, void *dev_mem, size_t dev_bytes,
+                       smfs_server **out);
+/* Waits for the worker threads and releases the server's host resources;
+ * the caller's device memory is free again afterwards. */
 void smfs_server_destroy(smfs_server *srv);
 
 /* Seconds on the clock the server stamps requests with (monotonic). */
@@ -355,7 +423,8 @@ double smfs_server_clock(void);
  * smfs_server_clock (latency is measured from it); a negative value means
  * now.  Geometry is built here, on the calling thread; *id receives the
  * request's handle.  SMFS_E_NOMEM when the request alone does not fit into
- * the arena. */
+ * the arena; SMFS_E_AGAIN (nothing queued) when max_queued requests are
+ * already waiting for admission. */
 int smfs_server_submit(smfs_server *srv, int32_t P, const double *centers, const double *rbm,
                        double t_arrival, int64_t *id);
 
@@ -366,7 +435,9 @@ int smfs_server_submit(smfs_server *srv, int32_t P, const double *centers, const
 int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting);
 
 typedef struct smfs_request_result {
-  int32_t status;              /* SMFS_OK, SMFS_NOT_CONVERGED or an error code */
+  int32_t status;              /* SMFS_OK (FP64 true residual met gmres_tol), SMFS_STAGNATED
+                                  (it stopped above), SMFS_NOT_CONVERGED (iteration limit)
+                                  or an error code */
   int32_t P;
   int32_t iterations;
   int32_t restarts;
@@ -374,6 +445,9 @@ typedef struct smfs_request_result {
   double true_rel_residual;    /* ||b - G_hat mu|| / ||b|| in FP64 */
   double t_arrival, t_admitted, t_started, t_done;   /* smfs_server_clock seconds */
   int64_t pair_evals;
+  int64_t pair_evals_f32;      /* of which in FP32 (SMFS_MIXED_FAR) */
+  int32_t refinements;         /* restarts from the FP64 true residual after the estimate met
+                                  the tolerance */
   char error[160];             /* message of a failed request (empty otherwise) */
 } smfs_request_result;
 

@@ -56,12 +56,27 @@ void set_error(const std::string &msg) { g_err = msg; }
 bool valid_precision(int p) { return p == SMFS_FP64 || p == SMFS_MIXED || p == SMFS_MIXED_FAR; }
 bool is_mixed(int p) { return p == SMFS_MIXED || p == SMFS_MIXED_FAR; }
 
+// Tiles of the FP64 direct sums: tt consecutive targets each, whatever
+// sphere they belong to, as (first sphere, first target, count, last
+// sphere); only the last tile is short.
 void build_tiles(const Problem &pb, std::vector<int4> &tiles, int tt) {
+  tiles.clear();
+  for (int64_t t0 = 0; t0 < pb.T; t0 += tt) {
+    const int64_t tc = std::min<int64_t>(tt, pb.T - t0);
+    tiles.push_back(make_int4(pb.tsph[t0], (int)t0, (int)tc, pb.tsph[t0 + tc - 1]));
+  }
+}
+
+// One-sphere tiles, (k, t0, count, k): the FP32 far-field sum (its
+// coordinates are relative to the tile's sphere centre) and the block sum
+// over many right-hand sides (whose accumulators leave no room for the
+// masked pass of a tile across spheres).
+void build_sphere_tiles(const Problem &pb, std::vector<int4> &tiles, int tt) {
   tiles.clear();
   for (int k = 0; k < pb.P; ++k) {
     const int64_t t0 = pb.toff[k], M = pb.toff[k + 1] - pb.toff[k];
     for (int64_t o = 0; o < M; o += tt)
-      tiles.push_back(make_int4(k, (int)(t0 + o), (int)std::min<int64_t>(tt, M - o), 0));
+      tiles.push_back(make_int4(k, (int)(t0 + o), (int)std::min<int64_t>(tt, M - o), k));
   }
 }
 
@@ -84,9 +99,11 @@ size_t workspace_layout(Problem &pb, bool assign) {
   const size_t o_csph = take(sizeof(int32_t) * C);
   const size_t o_meta = take(sizeof(SphereMeta) * P);
   const size_t o_fs = take(sizeof(FactorSlot) * pb.factors.size());
-  std::vector<int4> tiles;
+  std::vector<int4> tiles, stiles;
   build_tiles(pb, tiles, kTileTargets);
+  build_sphere_tiles(pb, stiles, kTileTargets);
   const size_t o_tiles = take(sizeof(int4) * tiles.size());
+  const size_t o_stiles = take(sizeof(int4) * stiles.size());
   int64_t cols_total = 0;
   for (int k = 0; k < P; ++k) cols_total += pb.factors[pb.fid_of[k]].cols;
   const size_t o_s = take(sizeof(double) * cols_total);
@@ -104,7 +121,7 @@ size_t workspace_layout(Problem &pb, bool assign) {
   int32_t n_free = 0;
   for (int k = 0; k < P; ++k) n_free += pb.contacts[k].empty() ? 1 : 0;
   const int64_t nprox = pb.nb[0];
-  const int32_t sp32 = n_free > 0 ? std::min<int32_t>(choose_splits((int64_t)tiles.size(),
+  const int32_t sp32 = n_free > 0 ? std::min<int32_t>(choose_splits((int64_t)stiles.size(),
                                                                    (int64_t)n_free * pb.prm.n_proxy),
                                                       std::max(1, n_free)) : 0;
   const size_t o_tgt32 = take(sizeof(float) * 3 * T);
@@ -157,6 +174,7 @@ size_t workspace_layout(Problem &pb, bool assign) {
     pb.d_meta = (SphereMeta *)(b + o_meta);
     pb.d_fslots = (FactorSlot *)(b + o_fs);
     pb.d_tiles = (int4 *)(b + o_tiles);
+    pb.d_stiles = (int4 *)(b + o_stiles);
     pb.d_s = (double *)(b + o_s);
     pb.d_utask = (RowTask *)(b + o_ut);
     pb.d_vtask = (RowTask *)(b + o_vt);
@@ -181,6 +199,8 @@ size_t workspace_layout(Problem &pb, bool assign) {
     pb.n_splits32 = sp32;
     pb.tiles = tiles;
     pb.n_tiles = (int64_t)tiles.size();
+    pb.stiles = stiles;
+    pb.n_stiles = (int64_t)stiles.size();
     pb.n_splits = sp_t;
     pb.n_splits_chk = sp_c;
     pb.part_cap = part;
@@ -231,6 +251,8 @@ int upload_tables(Problem &pb, hipStream_t s) {
     SMFS_HIP(hipMemcpyAsync(pb.d_csph, pb.csph.data(), 4 * pb.csph.size(), hipMemcpyHostToDevice, s));
   }
   SMFS_HIP(hipMemcpyAsync(pb.d_tiles, pb.tiles.data(), sizeof(int4) * pb.tiles.size(),
+                          hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(pb.d_stiles, pb.stiles.data(), sizeof(int4) * pb.stiles.size(),
                           hipMemcpyHostToDevice, s));
   // mixed precision: coordinates relative to each sphere's centre in FP32
   std::vector<float> t32(3 * pb.T), s32(3 * pb.nb[0]);
@@ -382,6 +404,7 @@ int transform(Problem &pb, const double *mu, double *lam, hipStream_t s) {
 DirectArgs direct_args(Problem &pb, const double *str, bool mixed) {
   DirectArgs a;
   a.tiles = pb.d_tiles;
+  a.tsph = pb.d_tsph;
   a.n_tiles = pb.n_tiles;
   a.tgt = pb.d_tgt;
   a.T = pb.T;
@@ -395,6 +418,24 @@ DirectArgs direct_args(Problem &pb, const double *str, bool mixed) {
   a.n_splits = pb.n_splits;
   a.part = pb.d_part;
   return a;
+}
+
+// The FP32 far field of the contact-free proxies (mixed precision).
+Far32Args far32_args(Problem &pb) {
+  Far32Args f;
+  f.tiles = pb.d_stiles;
+  f.n_tiles = pb.n_stiles;
+  f.tgt32 = pb.d_tgt32;
+  f.src32 = pb.d_src32;
+  f.str32 = pb.d_str32;
+  f.free_ids = pb.d_free;
+  f.n_free = pb.n_free;
+  f.n_proxy = pb.prm.n_proxy;
+  f.n_splits = pb.n_splits32;
+  f.T = pb.T;
+  f.part32 = pb.d_part32;
+  f.centers = pb.d_centers;
+  return f;
 }
 
 // Event pool for smfs_profile: returns the index of a recorded event.
@@ -442,20 +483,7 @@ int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s
   if (pb.prof && (rc = record_event(pb, s, e2))) return rc;
   int32_t ns32 = 0;
   if (mixed) {
-    Far32Args f;
-    f.tiles = pb.d_tiles;
-    f.n_tiles = pb.n_tiles;
-    f.tgt32 = pb.d_tgt32;
-    f.src32 = pb.d_src32;
-    f.str32 = pb.d_str32;
-    f.free_ids = pb.d_free;
-    f.n_free = pb.n_free;
-    f.n_proxy = pb.prm.n_proxy;
-    f.n_splits = pb.n_splits32;
-    f.T = pb.T;
-    f.part32 = pb.d_part32;
-    f.centers = pb.d_centers;
-    SMFS_HIP(launch_far_f32(f, s));
+    SMFS_HIP(launch_far_f32(far32_args(pb), s));
     ns32 = pb.n_splits32;
     if (pb.prof && (rc = record_event(pb, s, e3))) return rc;
   }
@@ -804,6 +832,7 @@ int smfs_params_default(smfs_params *p) {
   p->gmres_max_it = 1000;
   p->gmres_restart = 400;
   p->gmres_check_every = 25;
+  p->svd_method = SMFS_SVD_ROCSOLVER;
   return SMFS_OK;
 }
 
@@ -817,6 +846,7 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
   if (p->n_proxy <= 0 || p->n_colloc_base <= 0 || p->gmres_restart > 20000 || !(p->proxy_radius > 0 && p->proxy_radius < 1) ||
       !(p->mu > 0) || !(p->trunc_rel >= 0) || p->gmres_restart <= 0 || p->gmres_max_it <= 0 ||
       p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 || p->gmres_check_every < 0 ||
+      (p->svd_method != SMFS_SVD_JACOBI && p->svd_method != SMFS_SVD_ROCSOLVER) ||
       !valid_precision(p->precision)) {
     set_error("smfs_problem_create: invalid parameter");
     return SMFS_E_INVALID_ARG;
@@ -928,95 +958,241 @@ int smfs_bind(smfs_problem *pb, void *ws, size_t bytes, smfs_stream stream) {
   return SMFS_OK;
 }
 
-int smfs_setup(smfs_problem *pb, smfs_stream stream) {
-  if (!pb || !pb->bound) { set_error("smfs_setup: problem not bound"); return SMFS_E_STATE; }
-  hipStream_t s = (hipStream_t)stream;
-  if (!pb->rocblas) {
+}  // extern "C"
+
+namespace smfs {
+
+// Shape groups of the distinct self blocks (consecutive in the workspace,
+// see workspace_layout): factor ids sorted by slot, split where the shape
+// changes.  Factor 0 is left out when it was imported (skip_shared).
+struct ShapeGroup {
+  std::vector<int> fids;
+  int m = 0, n = 0;
+  int64_t stride = 0;      // elements between consecutive slots of the group
+  int nb = 1;              // blocks per batched SVD call
+};
+
+constexpr int kSvdBatchMax = 32;
+
+std::vector<ShapeGroup> shape_groups(const Problem &pb) {
+  std::vector<int> order;
+  for (size_t f = 0; f < pb.factors.size(); ++f)
+    if (pb.factors[f].rep >= 0 && !(pb.skip_shared && f == 0)) order.push_back((int)f);
+  std::sort(order.begin(), order.end(),
+            [&](int x, int y) { return pb.factors[x].u_off < pb.factors[y].u_off; });
+  std::vector<ShapeGroup> out;
+  for (int f : order) {
+    const FactorSlot &fs = pb.factors[f];
+    if (out.empty() || out.back().m != fs.rows || out.back().n != fs.cols) {
+      out.emplace_back();
+      out.back().m = fs.rows;
+      out.back().n = fs.cols;
+    }
+    out.back().fids.push_back(f);
+  }
+  for (ShapeGroup &g : out) {
+    g.nb = (int)std::min<size_t>(kSvdBatchMax, g.fids.size());
+    g.stride = g.fids.size() > 1 ? pb.factors[g.fids[1]].u_off - pb.factors[g.fids[0]].u_off : 0;
+  }
+  return out;
+}
+
+int ensure_rocblas(Problem &pb) {
+  if (!pb.rocblas) {
     rocblas_handle h;
     if (rocblas_create_handle(&h) != rocblas_status_success) {
       set_error("rocblas_create_handle failed");
       return SMFS_E_DEVICE;
     }
-    pb->rocblas = h;
+    pb.rocblas = h;
   }
-  rocblas_handle h = (rocblas_handle)pb->rocblas;
+  return SMFS_OK;
+}
+
+// Scratch of one batched SVD call of group g: [SVD work | A copies | E | info].
+struct SvdScratch {
+  size_t work = 0, a = 0, e = 0, info = 0, total = 0;
+};
+
+int svd_scratch_plan(Problem &pb, const ShapeGroup &g, SvdScratch &sc) {
+  int rc = ensure_rocblas(pb);
+  if (rc) return rc;
+  rocblas_handle h = (rocblas_handle)pb.rocblas;
+  // size query: nothing runs and no pointer is dereferenced
+  double *fake = reinterpret_cast<double *>((uintptr_t)4096);
+  rocblas_int *ifake = reinterpret_cast<rocblas_int *>((uintptr_t)4096);
+  size_t work = 0;
+  if (rocblas_start_device_memory_size_query(h) != rocblas_status_success) {
+    set_error("rocblas_start_device_memory_size_query failed");
+    return SMFS_E_DEVICE;
+  }
+  const rocblas_stride st = std::max<int64_t>(g.stride, 1);
+  rocblas_status q = rocsolver_dgesvd_strided_batched(
+      h, rocblas_svect_singular, rocblas_svect_singular, g.m, g.n, fake, g.m,
+      (rocblas_stride)g.m * g.n, fake, st, fake, g.m, st, fake, g.n, st, fake, g.n,
+      rocblas_outofplace, ifake, g.nb);
+  rocblas_status q2 = rocblas_stop_device_memory_size_query(h, &work);
+  if ((q != rocblas_status_success && q != rocblas_status_size_increased &&
+       q != rocblas_status_size_unchanged) || q2 != rocblas_status_success) {
+    set_error("SVD workspace query failed with status " + std::to_string((int)q));
+    return SMFS_E_SVD;
+  }
+  sc.work = align_up(work);
+  sc.a = align_up(sizeof(double) * (size_t)g.m * g.n * g.nb);
+  sc.e = align_up(sizeof(double) * (size_t)g.n * g.nb);
+  sc.info = align_up(sizeof(rocblas_int) * g.nb);
+  sc.total = sc.work + sc.a + sc.e + sc.info;
+  return SMFS_OK;
+}
+
+int setup_scratch_bytes(Problem &pb, size_t &bytes) {
+  bytes = 0;
+  for (const ShapeGroup &g : shape_groups(pb)) {
+    if (pb.prm.svd_method == SMFS_SVD_JACOBI) {
+      int rc = ensure_rocblas(pb);
+      if (rc) return rc;
+      JacPlan jp;
+      if ((rc = jacobi_plan((rocblas_handle)pb.rocblas, g.m, g.n, g.nb, jp))) return rc;
+      bytes = std::max(bytes, jp.total);
+    } else {
+      SvdScratch sc;
+      int rc = svd_scratch_plan(pb, g, sc);
+      if (rc) return rc;
+      bytes = std::max(bytes, sc.total);
+    }
+  }
+  return SMFS_OK;
+}
+
+// The device Jacobi SVD of every shape group (QR, one-sided Jacobi on R,
+// U = Q U_R), the blocks assembled into the plan's input region.
+int setup_factors_jacobi(Problem &pb, char *scratch, size_t scratch_bytes, hipStream_t s) {
+  rocblas_handle h = (rocblas_handle)pb.rocblas;
+  for (const ShapeGroup &g : shape_groups(pb)) {
+    JacPlan jp;
+    int rc = jacobi_plan(h, g.m, g.n, g.nb, jp);
+    if (rc) return rc;
+    if (scratch_bytes < jp.total) {
+      set_error("smfs_setup: scratch of " + std::to_string(scratch_bytes) + " bytes, need " +
+                std::to_string(jp.total));
+      return SMFS_E_NOMEM;
+    }
+    double *A = (double *)(scratch + jp.work);
+    const int m = g.m, n = g.n;
+    for (size_t b0 = 0; b0 < g.fids.size(); b0 += g.nb) {
+      const int real = (int)std::min<size_t>(g.nb, g.fids.size() - b0);
+      std::vector<double *> U(real), V(real), S(real);
+      for (int q = 0; q < real; ++q) {
+        const FactorSlot &fs = pb.factors[g.fids[b0 + q]];
+        const SphereMeta &mk = pb.meta[fs.rep];
+        SMFS_HIP(launch_assemble_block(pb.d_tgt, pb.d_sw, pb.d_src, pb.d_meta, fs.rep, mk.M, mk.N,
+                                       pb.prm.mu, A + (size_t)q * m * n, s));
+        U[q] = pb.d_fac + fs.u_off;
+        V[q] = pb.d_fac + fs.vt_off;
+        S[q] = pb.d_fac + fs.sig_off;
+      }
+      JacPlan jr;   // the plan of this call's batch count (no larger than jp)
+      if ((rc = jacobi_plan(h, m, n, real, jr))) return rc;
+      jr.work = jp.work;   // the same layout start: the input region stays where it was assembled
+      std::vector<int> ranks(real, 0);
+      int sweeps = 0;
+      rc = jacobi_svd_batch(h, jr, scratch, m, n, real, U.data(), V.data(), S.data(), pb.prm.trunc_rel,
+                            ranks.data(), &sweeps, s);
+      if (rc) return rc;
+      pb.svd_sweeps = std::max(pb.svd_sweeps, sweeps);
+      for (int q = 0; q < real; ++q) pb.factors[g.fids[b0 + q]].rank = ranks[q];
+    }
+  }
+  (void)rocblas_set_workspace(h, nullptr, 0);
+  return rank_tables(pb, s);
+}
+
+// Assemble and factor every distinct self block with scratch memory given
+// by the caller (no device memory is allocated here: rocSOLVER works in the
+// scratch through the handle's user workspace).
+int setup_factors(Problem &pb, char *scratch, size_t scratch_bytes, hipStream_t s) {
+  int rc = ensure_rocblas(pb);
+  if (rc) return rc;
+  rocblas_handle h = (rocblas_handle)pb.rocblas;
   rocblas_set_stream(h, s);
-  // groups of equal shape, consecutive in the workspace (see workspace_layout)
-  std::vector<int> order;
-  for (size_t f = 0; f < pb->factors.size(); ++f)
-    if (pb->factors[f].rep >= 0 && !(pb->skip_shared && f == 0)) order.push_back((int)f);
-  std::sort(order.begin(), order.end(),
-            [&](int x, int y) { return pb->factors[x].u_off < pb->factors[y].u_off; });
-  size_t g0 = 0;
-  while (g0 < order.size()) {
-    const FactorSlot &first = pb->factors[order[g0]];
-    const int m = first.rows, n = first.cols;
-    size_t g1 = g0 + 1;
-    while (g1 < order.size() && pb->factors[order[g1]].rows == m && pb->factors[order[g1]].cols == n) ++g1;
-    const int64_t stride = g1 - g0 > 1 ? pb->factors[order[g0 + 1]].u_off - first.u_off : 0;
-    // batches bounded by the scratch copy of the input blocks (<= 8 GiB, <= 32);
-    // a caller-provided scratch buffer, when set, bounds them instead and
-    // no device memory is allocated here
-    const size_t per = sizeof(double) * (size_t)m * n;
-    const size_t per_all = align_up(per) + align_up(sizeof(double) * (size_t)n) + align_up(sizeof(rocblas_int));
-    const bool own = pb->svd_scratch && pb->svd_scratch_bytes >= per_all;
-    const size_t cap = own ? pb->svd_scratch_bytes / per_all : ((size_t)8 << 30) / per;
-    const size_t bmax = std::max<size_t>(1, std::min<size_t>(32, cap));
-    for (size_t b0 = g0; b0 < g1; b0 += bmax) {
-      const int nb = (int)std::min(bmax, g1 - b0);
-      double *A = nullptr, *E = nullptr;
-      rocblas_int *info = nullptr;
-      if (own) {
-        char *base = (char *)pb->svd_scratch;
-        A = (double *)base;
-        E = (double *)(base + align_up(per * nb));
-        info = (rocblas_int *)(base + align_up(per * nb) + align_up(sizeof(double) * (size_t)n * nb));
-      } else {
-        SMFS_HIP(hipMalloc((void **)&A, per * nb));
-        SMFS_HIP(hipMalloc((void **)&E, sizeof(double) * (size_t)n * nb));
-        SMFS_HIP(hipMalloc((void **)&info, sizeof(rocblas_int) * nb));
+  pb.svd_sweeps = 0;
+  if (pb.prm.svd_method == SMFS_SVD_JACOBI) return setup_factors_jacobi(pb, scratch, scratch_bytes, s);
+  for (const ShapeGroup &g : shape_groups(pb)) {
+    SvdScratch sc;
+    if ((rc = svd_scratch_plan(pb, g, sc))) return rc;
+    if (scratch_bytes < sc.total) {
+      set_error("smfs_setup: scratch of " + std::to_string(scratch_bytes) + " bytes, need " +
+                std::to_string(sc.total));
+      return SMFS_E_NOMEM;
+    }
+    if (rocblas_set_workspace(h, scratch, sc.work) != rocblas_status_success) {
+      set_error("rocblas_set_workspace failed");
+      return SMFS_E_DEVICE;
+    }
+    double *A = (double *)(scratch + sc.work);
+    double *E = (double *)(scratch + sc.work + sc.a);
+    rocblas_int *info = (rocblas_int *)(scratch + sc.work + sc.a + sc.e);
+    const int m = g.m, n = g.n;
+    for (size_t b0 = 0; b0 < g.fids.size(); b0 += g.nb) {
+      // the last call of a group may be shorter (its scratch need is no larger)
+      const int real = (int)std::min<size_t>(g.nb, g.fids.size() - b0);
+      for (int q = 0; q < real; ++q) {
+        const FactorSlot &fs = pb.factors[g.fids[b0 + q]];
+        const SphereMeta &mk = pb.meta[fs.rep];
+        SMFS_HIP(launch_assemble_block(pb.d_tgt, pb.d_sw, pb.d_src, pb.d_meta, fs.rep, mk.M, mk.N,
+                                       pb.prm.mu, A + (size_t)q * m * n, s));
       }
-      struct Free {
-        void *a, *b, *c;
-        ~Free() { if (a) (void)hipFree(a); if (b) (void)hipFree(b); if (c) (void)hipFree(c); }
-      } guard{own ? nullptr : A, own ? nullptr : E, own ? nullptr : info};
-      for (int q = 0; q < nb; ++q) {
-        const FactorSlot &fs = pb->factors[order[b0 + q]];
-        const SphereMeta &mk = pb->meta[fs.rep];
-        SMFS_HIP(launch_assemble_block(pb->d_tgt, pb->d_sw, pb->d_src, pb->d_meta, fs.rep, mk.M, mk.N,
-                                       pb->prm.mu, A + (size_t)q * m * n, s));
-      }
-      const FactorSlot &fb = pb->factors[order[b0]];
-      double *U = pb->d_fac + fb.u_off, *VT = pb->d_fac + fb.vt_off, *sig = pb->d_fac + fb.sig_off;
-      rocblas_status st = rocsolver_dgesvd_strided_batched(
+      const FactorSlot &fb = pb.factors[g.fids[b0]];
+      double *U = pb.d_fac + fb.u_off, *VT = pb.d_fac + fb.vt_off, *sig = pb.d_fac + fb.sig_off;
+      const rocblas_stride st = std::max<int64_t>(g.stride, 1);
+      rocblas_status stt = rocsolver_dgesvd_strided_batched(
           h, rocblas_svect_singular, rocblas_svect_singular, m, n, A, m, (rocblas_stride)m * n, sig,
-          (rocblas_stride)stride, U, m, (rocblas_stride)stride, VT, n, (rocblas_stride)stride, E, n,
-          rocblas_outofplace, info, nb);
-      if (st != rocblas_status_success) {
-        set_error("rocsolver_dgesvd_strided_batched failed with status " + std::to_string((int)st));
+          st, U, m, st, VT, n, st, E, n, rocblas_outofplace, info, real);
+      if (stt != rocblas_status_success) {
+        (void)rocblas_set_workspace(h, nullptr, 0);
+        set_error("rocsolver_dgesvd_strided_batched failed with status " + std::to_string((int)stt));
         return SMFS_E_SVD;
       }
-      std::vector<rocblas_int> hinfo(nb);
-      std::vector<double> sv((size_t)n * nb);
-      SMFS_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * nb, hipMemcpyDeviceToHost, s));
-      for (int q = 0; q < nb; ++q)
-        SMFS_HIP(hipMemcpyAsync(sv.data() + (size_t)q * n, sig + (size_t)q * stride, 8 * (size_t)n,
+      std::vector<rocblas_int> hinfo(real);
+      std::vector<double> sv((size_t)n * real);
+      SMFS_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * real, hipMemcpyDeviceToHost, s));
+      for (int q = 0; q < real; ++q)
+        SMFS_HIP(hipMemcpyAsync(sv.data() + (size_t)q * n, sig + (size_t)q * g.stride, 8 * (size_t)n,
                                 hipMemcpyDeviceToHost, s));
       SMFS_HIP(hipStreamSynchronize(s));
-      for (int q = 0; q < nb; ++q) {
+      for (int q = 0; q < real; ++q) {
         const double *sq = sv.data() + (size_t)q * n;
         if (hinfo[q] != 0 || !(sq[0] > 0)) {
+          (void)rocblas_set_workspace(h, nullptr, 0);
           set_error("SVD did not converge (info " + std::to_string(hinfo[q]) + ")");
           return SMFS_E_SVD;
         }
         int r = 0;
-        while (r < n && sq[r] > pb->prm.trunc_rel * sq[0]) ++r;
-        pb->factors[order[b0 + q]].rank = r;
+        while (r < n && sq[r] > pb.prm.trunc_rel * sq[0]) ++r;
+        pb.factors[g.fids[b0 + q]].rank = r;
       }
     }
-    g0 = g1;
   }
-  return rank_tables(*pb, s);
+  (void)rocblas_set_workspace(h, nullptr, 0);
+  return rank_tables(pb, s);
+}
+
+}  // namespace smfs
+
+extern "C" {
+
+int smfs_setup_workspace_bytes(smfs_problem *pb, size_t *bytes) {
+  if (!pb || !bytes) { set_error("smfs_setup_workspace_bytes: null argument"); return SMFS_E_INVALID_ARG; }
+  return setup_scratch_bytes(*pb, *bytes);
+}
+
+int smfs_setup(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream) {
+  if (!pb || !pb->bound) { set_error("smfs_setup: problem not bound"); return SMFS_E_STATE; }
+  if (!scratch || ((uintptr_t)scratch) % kAlign) {
+    set_error("smfs_setup: scratch must be a 256-byte aligned device pointer");
+    return SMFS_E_INVALID_ARG;
+  }
+  return setup_factors(*pb, (char *)scratch, scratch_bytes, (hipStream_t)stream);
 }
 
 int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double *U,

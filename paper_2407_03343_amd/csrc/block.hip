@@ -32,11 +32,14 @@ struct BlockLayout {
   double *lamb = nullptr;   // S x nrhs x 3 strengths (source-major)
   double *sblk = nullptr;   // nrhs x lds: Sigma^-1 U^T mu per sphere
   double *part = nullptr;   // [split][nrhs][3T] partial sums
+  float *str32 = nullptr;   // mixed: FP32 proxy strengths [proxy][nrhs][3]
+  float *part32 = nullptr;  // mixed: FP32 partial sums [split32][nrhs][3T]
   double *kry = nullptr;    // (m + 1) x nrhs x ld Krylov vectors
   double *vec = nullptr;    // 4 x nrhs x ld: w, r, b, x
   double *red = nullptr;    // reduction partials and small per-system arrays
   int64_t lds = 0, ld = 0;
   int32_t nsplit = 1, m = 0, nch = 1, ldh = 0;
+  int32_t nsplit32 = 0;     // FP32 far-field splits (0: no contact-free sphere)
   size_t bytes = 0;
 };
 
@@ -53,7 +56,7 @@ BlockLayout block_layout(const Problem &pb, int32_t nrhs, int32_t m, char *base)
   L.lds = (pb.cols_total + 31) / 32 * 32;
   L.m = m;
   const int64_t nz = (nrhs + kBlockRun - 1) / kBlockRun;
-  L.nsplit = direct_splits(pb.n_tiles * nz, pb.S);
+  L.nsplit = direct_splits(pb.n_stiles * nz, pb.S);
   L.nch = mdot_chunks(n);
   L.ldh = m + 2;
   // the last run of right-hand sides reads (and ignores) up to kBlockRun - 1
@@ -61,6 +64,13 @@ BlockLayout block_layout(const Problem &pb, int32_t nrhs, int32_t m, char *base)
   const size_t o_lamb = take(sizeof(double) * (3 * pb.S * nrhs + 3 * kBlockRun));
   const size_t o_s = take(sizeof(double) * L.lds * nrhs);
   const size_t o_part = take(sizeof(double) * L.nsplit * nrhs * n);
+  // mixed precision: FP32 strengths of the proxies (the last run reads up to
+  // kBlockRun - 1 past the end) and FP32 partial sums of the far field
+  if (pb.n_free > 0)
+    L.nsplit32 = std::min<int32_t>(direct_splits(pb.n_stiles * nz, (int64_t)pb.n_free * pb.prm.n_proxy),
+                                   std::max(1, pb.n_free));
+  const size_t o_str32 = take(sizeof(float) * (3 * pb.nb[0] * nrhs + 3 * kBlockRun));
+  const size_t o_part32 = take(sizeof(float) * std::max<int64_t>(1, (int64_t)L.nsplit32 * nrhs * n));
   size_t o_kry = 0, o_vec = 0, o_red = 0;
   if (m > 0) {
     o_kry = take(sizeof(double) * (size_t)(m + 1) * nrhs * L.ld);
@@ -72,6 +82,8 @@ BlockLayout block_layout(const Problem &pb, int32_t nrhs, int32_t m, char *base)
     L.lamb = (double *)(base + o_lamb);
     L.sblk = (double *)(base + o_s);
     L.part = (double *)(base + o_part);
+    L.str32 = (float *)(base + o_str32);
+    L.part32 = (float *)(base + o_part32);
     if (m > 0) {
       L.kry = (double *)(base + o_kry);
       L.vec = (double *)(base + o_vec);
@@ -92,9 +104,14 @@ int check_ws(const Problem &pb, int32_t nrhs, int32_t m, void *ws, size_t ws_byt
   return SMFS_OK;
 }
 
-// Y = G_hat M for the nrhs vectors of stride ld.
+// Y = G_hat M for the nrhs vectors of stride ld.  Mixed precision
+// (SMFS_MIXED_FAR, or SMFS_MIXED: the block pseudo-inverse is FP64 in both):
+// the proxies of contact-free spheres are summed in FP32 from FP32 copies of
+// their FP64 strengths, every other pair in FP64.
+
 int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *mu, double *y,
-                int64_t ld, hipStream_t s) {
+                int64_t ld, hipStream_t s, int precision = SMFS_FP64) {
+  const bool mixed = is_mixed(precision) && L.nsplit32 > 0;
   size_t e0 = 0, e1 = 0, e2 = 0;
   int rc;
   if (pb.prof && (rc = record_event(pb, s, e0))) return rc;
@@ -103,28 +120,34 @@ int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *m
                              2.0 * pb.prm.mu, s));
   if (pb.prof && (rc = record_event(pb, s, e1))) return rc;
   BlockDirectArgs a;
-  a.tiles = pb.d_tiles;
-  a.n_tiles = pb.n_tiles;
+  a.tiles = pb.d_stiles;
+  a.n_tiles = pb.n_stiles;
   a.tgt = pb.d_tgt;
   a.T = pb.T;
   a.src = pb.d_src;
   a.lamb = L.lamb;
   a.nrhs = nrhs;
   a.meta = pb.d_meta;
-  a.ranges = pb.d_ranges;
-  a.n_ranges = pb.n_rng_plain;
-  a.range_total = pb.rng_total_plain;
+  a.ranges = mixed ? pb.d_ranges + pb.n_rng_plain : pb.d_ranges;
+  a.n_ranges = mixed ? pb.n_rng_mixed : pb.n_rng_plain;
+  a.range_total = mixed ? pb.rng_total_mixed : pb.rng_total_plain;
   a.n_splits = L.nsplit;
   a.part = L.part;
   SMFS_HIP(launch_direct_block(a, s));
+  if (mixed) {
+    SMFS_HIP(launch_to_f32(3 * pb.nb[0] * nrhs, L.lamb, L.str32, s));
+    Far32Args f = far32_args(pb);
+    f.n_splits = L.nsplit32;
+    SMFS_HIP(launch_far_block_f32(f, L.str32, nrhs, L.part32, s));
+  }
   if (pb.prof) {
     if ((rc = record_event(pb, s, e2))) return rc;
     pb.ev_bpinv.emplace_back(e0, e1);
     pb.ev_bdirect.emplace_back(e1, e2);
     pb.prof_nrhs = nrhs;
   }
-  SMFS_HIP(launch_reduce_block(3 * pb.T, nrhs, L.nsplit, L.part, mu, ld, pb.d_sw,
-                               1.0 / (8.0 * kPiB * pb.prm.mu), y, ld, s));
+  SMFS_HIP(launch_reduce_block(3 * pb.T, nrhs, L.nsplit, L.part, mixed ? L.nsplit32 : 0, L.part32, mu, ld,
+                               pb.d_sw, 1.0 / (8.0 * kPiB * pb.prm.mu), y, ld, s));
   return SMFS_OK;
 }
 
@@ -133,6 +156,7 @@ struct BlockStats {
   std::vector<double> est;      // GMRES residual estimate per system
   std::vector<char> conv;
   int32_t steps = 0;            // block products in the Krylov iterations
+  int32_t refinements = 0;      // mixed: restarts from FP64 residuals after the estimates met tol
 };
 
 // Pinned host buffer released on scope exit.
@@ -148,7 +172,12 @@ struct Pinned {
 // the single-vector solver; a converged system is frozen (its restart
 // vector is zero, so its later Arnoldi columns are zero and ignored).
 int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B, double *X,
-                double tol, int max_it, BlockStats &st, hipStream_t s) {
+                double tol, int max_it, BlockStats &st, hipStream_t s, int precision = SMFS_FP64) {
+  // mixed products inside the cycles; every restart takes the FP64 true
+  // residual, and a mixed solve whose estimates all met the tolerance
+  // restarts from it up to twice (systems above the tolerance go on)
+  const bool mixed = is_mixed(precision) && L.nsplit32 > 0;
+  int refinements = 0;
   const int64_t n = 3 * pb.T, ld = L.ld;
   const int m = L.m, ldh = L.ldh, nch = L.nch;
   const int64_t blk = (int64_t)nrhs * ld;   // one Krylov "column" of all systems
@@ -201,7 +230,7 @@ int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B
     std::vector<char> running(active);
     for (int j = 0; j < m; ++j) {
       double *vj = V + (int64_t)j * blk, *vj1 = V + (int64_t)(j + 1) * blk;
-      int rc = apply_block(pb, L, nrhs, vj, vj1, ld, s);
+      int rc = apply_block(pb, L, nrhs, vj, vj1, ld, s, precision);
       if (rc) return rc;
       ++st.steps;
       SMFS_HIP(launch_arnoldi_block(V, ld, nrhs, j + 1, vj1, n, part, nch, h, ldh, s));
@@ -264,7 +293,9 @@ int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B
     SMFS_HIP(hipStreamSynchronize(s));
     bool more = false;
     for (int q = 0; q < nrhs; ++q) more = more || (!st.conv[q]);
-    if (!more || total >= max_it) break;
+    const bool refine = mixed && !more && refinements < 2;
+    if ((!more && !refine) || total >= max_it) break;
+    if (refine) ++refinements;
     // restart from the true residuals
     int rc = apply_block(pb, L, nrhs, X, W, ld, s);
     if (rc) return rc;
@@ -275,11 +306,13 @@ int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B
     SMFS_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < nrhs; ++q) {
       rn[q] = hb[(size_t)q * ldh];
-      if (!st.conv[q] && rn[q] / bnorm[q] <= tol) {
-        st.conv[q] = 1;
-        st.est[q] = rn[q] / bnorm[q];
-      }
+      if (bnorm[q] == 0.0) continue;
+      const bool met = rn[q] / bnorm[q] <= tol;
+      if (refine) st.conv[q] = met ? 1 : 0;       // checked against the FP64 residual
+      if (met && !st.conv[q]) st.conv[q] = 1;
+      if (met) st.est[q] = rn[q] / bnorm[q];
     }
+    st.refinements = refinements;
   }
   return SMFS_OK;
 }
@@ -293,7 +326,7 @@ size_t block_apply_bytes(const Problem &pb, int32_t nrhs) { return block_layout(
 int block_apply_on(Problem &pb, int32_t nrhs, const double *mu, double *y, int64_t ld, char *base,
                    hipStream_t s) {
   const BlockLayout L = block_layout(pb, nrhs, 0, base);
-  return apply_block(pb, L, nrhs, mu, y, ld, s);
+  return apply_block(pb, L, nrhs, mu, y, ld, s, SMFS_FP64);
 }
 
 }  // namespace smfs
@@ -313,16 +346,17 @@ int smfs_block_workspace_bytes(const smfs_problem *pb, int32_t nrhs, int32_t res
 }
 
 int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y, int64_t ld,
-                     void *ws, size_t ws_bytes, smfs_stream stream) {
+                     int32_t precision, void *ws, size_t ws_bytes, smfs_stream stream) {
   SMFS_READY(pb);
   if (!mu || !y || ld < 3 * pb->T) { set_error("smfs_apply_block: bad vectors"); return SMFS_E_INVALID_ARG; }
+  if (!valid_precision(precision)) { set_error("smfs_apply_block: bad precision"); return SMFS_E_INVALID_ARG; }
   BlockLayout L;
   int rc = check_ws(*pb, nrhs, 0, ws, ws_bytes, L);
   if (rc) return rc;
   const char *a0 = (const char *)mu, *a1 = a0 + 8 * (nrhs * ld);
   const char *b0 = (const char *)y, *b1 = b0 + 8 * (nrhs * ld);
   if (a0 < b1 && b0 < a1) { set_error("smfs_apply_block: mu and y overlap"); return SMFS_E_INVALID_ARG; }
-  return apply_block(*pb, L, nrhs, mu, y, ld, (hipStream_t)stream);
+  return apply_block(*pb, L, nrhs, mu, y, ld, (hipStream_t)stream, precision);
 }
 
 int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rbm, int32_t restart,
@@ -348,7 +382,7 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
     SMFS_HIP(launch_rhs(pb->T, pb->d_tgt, pb->d_tsph, pb->d_sw, pb->d_meta, rbm + 6 * P * q,
                         B + (int64_t)q * ld, s, &pb->bg));
   BlockStats st;
-  rc = gmres_block(*pb, L, nrhs, B, X, pb->prm.gmres_tol, pb->prm.gmres_max_it, st, s);
+  rc = gmres_block(*pb, L, nrhs, B, X, pb->prm.gmres_tol, pb->prm.gmres_max_it, st, s, pb->prm.precision);
   if (rc) return rc;
   // true residuals in FP64
   rc = apply_block(*pb, L, nrhs, X, W, ld, s);
@@ -374,19 +408,26 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
   }
   SMFS_HIP(hipStreamSynchronize(s));
   auto t2 = clk::now();
-  int nconv = 0, maxit = 0;
+  int nconv = 0, maxit = 0, ntrue = 0;
   for (int q = 0; q < nrhs; ++q) {
     nconv += st.conv[q] ? 1 : 0;
     maxit = std::max(maxit, st.its[q]);
     if (out->iterations) out->iterations[q] = st.its[q];
-    if (out->true_rel_residual) out->true_rel_residual[q] = norms[nrhs + q] > 0 ? norms[q] / norms[nrhs + q] : 0.0;
+    const double tr = norms[nrhs + q] > 0 ? norms[q] / norms[nrhs + q] : 0.0;
+    if (out->true_rel_residual) out->true_rel_residual[q] = tr;
+    ntrue += tr <= pb->prm.gmres_tol ? 1 : 0;
   }
+  out->refinements = st.refinements;
+  if (is_mixed(pb->prm.precision))
+    out->pair_evals_f32 = (int64_t)st.steps * nrhs * pb->pairs_f32;
   out->max_iterations = maxit;
   out->n_converged = nconv;
   out->t_gmres_ms = ms(t0, t1);
   out->t_post_ms = ms(t1, t2);
   out->pair_evals = (int64_t)(st.steps + 1) * nrhs * pb->pairs_per_apply;
-  return nconv == nrhs ? SMFS_OK : SMFS_NOT_CONVERGED;
+  // OK only when every FP64 true residual met the tolerance
+  if (ntrue == nrhs) return SMFS_OK;
+  return nconv == nrhs ? SMFS_STAGNATED : SMFS_NOT_CONVERGED;
 }
 
 }  // extern "C"

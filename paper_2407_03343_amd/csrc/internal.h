@@ -115,6 +115,7 @@ struct Problem {
   double *d_chk = nullptr, *d_fac = nullptr, *d_part = nullptr, *d_s = nullptr;
   int32_t *d_tsph = nullptr, *d_csph = nullptr;
   int4 *d_tiles = nullptr, *d_eval_tiles = nullptr;
+  int4 *d_stiles = nullptr;                // one-sphere tiles (FP32 far field, block sum)
   // mixed precision arrays
   float *d_tgt32 = nullptr, *d_src32 = nullptr, *d_str32 = nullptr, *d_part32 = nullptr;
   float *d_s32 = nullptr, *d_fac32 = nullptr;
@@ -134,11 +135,11 @@ struct Problem {
   int64_t n_btask_u = 0, n_btask_v = 0;
   int64_t cols_total = 0;                  // sum of factor columns over spheres
   bool skip_shared = false;                // setup leaves factor 0 (imported) alone
+  int32_t svd_sweeps = 0;                  // Jacobi sweeps of the last set-up (largest over calls)
   BgFlow bg{};                             // background flow of the boundary data (off: quiescent)
-  void *svd_scratch = nullptr;             // optional device scratch of the setup SVDs
-  size_t svd_scratch_bytes = 0;
   double *d_kry = nullptr, *d_vec = nullptr, *d_red = nullptr;
   int64_t n_tiles = 0, n_utask = 0, n_vtask = 0, n_vmap = 0;
+  int64_t n_stiles = 0;
   int32_t n_splits = 1;
   int32_t n_splits_chk = 1;
   int64_t kry_ld = 0;
@@ -148,7 +149,7 @@ struct Problem {
 
   // host mirrors of tables
   std::vector<SphereMeta> meta;
-  std::vector<int4> tiles;
+  std::vector<int4> tiles, stiles;
   std::vector<int32_t> vmap_off;           // P + 1 (offsets into d_vmap)
 
   void *rocblas = nullptr;                 // rocblas_handle for setup
@@ -176,6 +177,22 @@ int rank_tables(Problem &pb, hipStream_t s);
 int transform(Problem &pb, const double *mu, double *lam, hipStream_t s);
 int record_event(Problem &pb, hipStream_t s, size_t &idx);
 int32_t direct_splits(int64_t n_tiles, int64_t S);
+bool valid_precision(int p);
+bool is_mixed(int p);
+// svd.hip: the device Jacobi SVD (QR, one-sided Jacobi on R, U = Q U_R)
+struct JacPlan {
+  int w = 8, rows = 4, npad = 0, nbk = 0, npairs = 0;
+  size_t work = 0;
+  size_t a = 0, tau = 0, x = 0, v = 0, wbuf = 0, off = 0, sig = 0, perm = 0, rank = 0, ptrs = 0, sched = 0;
+  size_t total = 0;
+};
+}  // namespace smfs
+typedef struct _rocblas_handle *rocblas_handle;
+namespace smfs {
+int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p);
+int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, int n, int nb,
+                     double *const *U, double *const *Vs, double *const *Ss, double trunc, int *ranks,
+                     int *sweeps_out, hipStream_t s);
 // block.hip
 size_t block_apply_bytes(const Problem &pb, int32_t nrhs);
 int block_apply_on(Problem &pb, int32_t nrhs, const double *mu, double *y, int64_t ld, char *base,

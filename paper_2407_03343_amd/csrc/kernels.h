@@ -20,7 +20,8 @@ constexpr int kDirectTpl = SMFS_DIRECT_TPL;
 // sphere (the identity self blocks).  Writes per-split partial sums
 // part[split][T][3] without the common factor 1/(8 pi mu).
 struct DirectArgs {
-  const int4 *tiles;        // (sphere, first target, count); NULL: free points
+  const int4 *tiles;        // (first sphere, first target, count, last sphere); NULL: free points
+  const int32_t *tsph;      // sphere of every target (tiles that span spheres)
   int64_t n_tiles;
   const double *tgt;        // targets x 3
   int64_t T;                // targets (partial stride)
@@ -39,7 +40,7 @@ hipError_t launch_direct_f64(const DirectArgs &a, hipStream_t s);
 // Mixed precision: FP32 sum of the proxy Stokeslets of contact-free
 // spheres over the tiles, coordinates relative to sphere centres.
 struct Far32Args {
-  const int4 *tiles;
+  const int4 *tiles;        // (sphere, first target, count, sphere): one sphere per tile
   int64_t n_tiles;
   const float *tgt32;       // targets minus own centre, T x 3
   const float *src32;       // proxies minus own centre, P*n_proxy x 3 (block 0 order)
@@ -53,6 +54,8 @@ struct Far32Args {
   float *part32;            // [split][T][3]
 };
 hipError_t launch_far_f32(const Far32Args &a, hipStream_t s);
+// The far-field arguments of a bound problem (api.hip).
+Far32Args far32_args(Problem &pb);
 
 // y[i] = base[i] + sw[i/3] * c0 * (sum_s part[s][i] + sum_s part32[s][i])
 // (base, sw, part32 nullable)
@@ -141,7 +144,7 @@ int32_t mdot_chunks(int64_t n);
 constexpr int kBlockRun = 4;   // right-hand sides sharing one pair geometry
 
 struct BlockDirectArgs {
-  const int4 *tiles;
+  const int4 *tiles;        // one-sphere tiles (sphere, first target, count, sphere)
   int64_t n_tiles;
   const double *tgt;
   int64_t T;
@@ -164,9 +167,14 @@ hipError_t launch_pinv_block(const int4 *utasks, int64_t nu, const int4 *vtasks,
                              const double *mu, int64_t ldmu, int32_t nrhs, double *S, int64_t lds,
                              double *lamb, double dscale, hipStream_t s);
 hipError_t launch_direct_block(const BlockDirectArgs &a, hipStream_t s);
-hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part,
-                               const double *base, int64_t ldb, const double *sw, double c0,
-                               double *y, int64_t ldy, hipStream_t s);
+hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part, int32_t ns32,
+                               const float *part32, const double *base, int64_t ldb, const double *sw,
+                               double c0, double *y, int64_t ldy, hipStream_t s);
+// Mixed precision, many right-hand sides: FP32 far field of the contact-free
+// proxies (a.str32 unused; strengths str32b [proxy][nrhs][3], partial sums
+// part32b [split][nrhs][T][3], a.n_splits splits over the free spheres).
+hipError_t launch_far_block_f32(const Far32Args &a, const float *str32b, int32_t nrhs, float *part32b,
+                                hipStream_t s);
 hipError_t launch_arnoldi_block(const double *V, int64_t ld, int32_t nrhs, int32_t nv, double *W,
                                 int64_t n, double *part, int32_t nchunks, double *h, int32_t ldh,
                                 hipStream_t s);
@@ -185,6 +193,10 @@ hipError_t launch_combine_block(const double *V, int64_t ld, int32_t nrhs, int32
 struct ServeDesc {
   DirectArgs da;            // direct sum of this problem (str = lam, own part buffer)
   int64_t tile0;            // first tile of this problem in the launch
+  Far32Args fa;             // mixed precision: FP32 far field (n_splits = 0: FP64 product)
+  int64_t stile0;           // first one-sphere tile of this problem in the far-field launch
+  float *str32;             // FP32 copy of the proxy strengths (the first n_str32 of lam)
+  int64_t n_str32;
   const RowTask *utask, *vtask;
   int64_t n_utask, n_vtask, utask0, vtask0;
   const FactorSlot *fs;
@@ -204,7 +216,8 @@ struct ServeDesc {
   double *h, *h2;           // out: Gram-Schmidt coefficients; h[nv] = norm
 };
 hipError_t launch_serve_product(const ServeDesc *d, int32_t nprob, int64_t tiles, int64_t utasks,
-                                int64_t vtasks, int32_t max_splits, int64_t max_n, hipStream_t s);
+                                int64_t vtasks, int32_t max_splits, int64_t max_n, int64_t stiles,
+                                int32_t max_splits32, int64_t max_str32, hipStream_t s);
 hipError_t launch_serve_arnoldi(const ServeDesc *d, int32_t nprob, int32_t max_nv, int32_t max_nch,
                                 int64_t max_n, hipStream_t s);
 

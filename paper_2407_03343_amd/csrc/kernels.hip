@@ -216,26 +216,78 @@ __device__ __forceinline__ void run_block(int block, const DirectArgs &A, int64_
   else run_sources<kTpl, 2, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc);
 }
 
-// One wave: tile `tile` of A, source split `split`.
+// Sources [j0, j1) of one kind for the target slots with on[p] set only:
+// in a tile that spans several spheres, each member sphere's own sources
+// reach the targets of the other members.  One source per step; a masked
+// slot's new sum is discarded by a select, so it stays unchanged bitwise.
+template <int kTpl, int kKind, bool kScaleD>
+__device__ __forceinline__ void run_sources_masked(const double *__restrict__ src_,
+                                                   const double *__restrict__ str_, double dscale,
+                                                   int64_t j0_, int64_t j1_, Acc<kTpl> &A,
+                                                   const bool (&on)[kTpl]) {
+  const ConstPtr src = (ConstPtr)src_, str = (ConstPtr)str_;
+  const int j1 = uniform((int)j1_);
+  for (int j = uniform((int)j0_); j < j1; ++j) {
+    const ConstPtr p0 = src + 3 * j, q0 = str + 3 * j;
+    const double sx = p0[0], sy = p0[1], sz = p0[2];
+    double fx = q0[0], fy = q0[1], fz = q0[2];
+    if (kKind == 2 && kScaleD) { fx *= dscale; fy *= dscale; fz *= dscale; }
+    const double gx = quarter(fx), gy = quarter(fy), gz = quarter(fz);
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      double bx = A.ax[p], by = A.ay[p], bz = A.az[p];
+      if (kKind == 0) pair_s(sx, sy, sz, fx, fy, fz, gx, gy, gz, A.tx[p], A.ty[p], A.tz[p], bx, by, bz);
+      else if (kKind == 1) pair_r(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], bx, by, bz);
+      else pair_d(sx, sy, sz, fx, fy, fz, A.tx[p], A.ty[p], A.tz[p], bx, by, bz);
+      A.ax[p] = on[p] ? bx : A.ax[p];
+      A.ay[p] = on[p] ? by : A.ay[p];
+      A.az[p] = on[p] ? bz : A.az[p];
+    }
+  }
+}
+
+template <int kTpl, bool kScaleD>
+__device__ __forceinline__ void run_block_masked(int block, const DirectArgs &A, int64_t j0, int64_t j1,
+                                                 Acc<kTpl> &acc, const bool (&on)[kTpl]) {
+  if (j0 >= j1) return;
+  if (block <= 1) run_sources_masked<kTpl, 0, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc, on);
+  else if (block == 2) run_sources_masked<kTpl, 1, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc, on);
+  else run_sources_masked<kTpl, 2, kScaleD>(A.src, A.str, A.dscale, j0, j1, acc, on);
+}
+
+// One wave: tile `tile` of A, source split `split`.  A tile holds up to
+// 64 kTpl consecutive targets, which may belong to consecutive spheres
+// ka..kb (every wave then has a full tile of work, whatever the node count
+// of a sphere).  The sources of ka..kb are contiguous in every block
+// (sphere-major packing): the main loops cut them out, and a masked pass
+// gives each member's sources to the other members' targets.
 template <int kTpl, bool kFree>
 __device__ __forceinline__ void direct_wave(const DirectArgs &A, int64_t tile, int64_t split) {
   const int lane = threadIdx.x & (kWave - 1);
-  int k = -1, t0 = 0, tc = 0;
+  int ka = -1, kb = -1, t0 = 0, tc = 0;
   if (tile < A.n_tiles) {
     if (!kFree) {
       const int4 tl = A.tiles[tile];
-      k = tl.x;
+      ka = tl.x;
       t0 = tl.y;
       tc = tl.z;
+      kb = tl.w;
     } else {  // consecutive free points, no source skipped
       t0 = (int)(tile * kWave * kTpl);
       tc = (int)min<int64_t>(kWave * kTpl, A.T - t0);
     }
   }
-  k = uniform(k);
+  ka = uniform(ka);
+  kb = uniform(kb);
   t0 = uniform(t0);
   tc = uniform(tc);
   if (tc <= 0) return;  // whole wave idle (no barriers in this kernel)
+  int own[kTpl];        // sphere of each target slot (multi-sphere tiles)
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    own[p] = (!kFree && ka != kb && i < tc) ? A.tsph[t0 + i] : -1;
+  }
 
   Acc<kTpl> acc;
 #pragma unroll
@@ -259,10 +311,17 @@ __device__ __forceinline__ void direct_wave(const DirectArgs &A, int64_t tile, i
     pos += len;
     if (a >= b) continue;
     const int64_t j0 = R.begin + a, j1 = R.begin + b;
-    if (k >= 0) {  // cut the tile's own sphere out of this block
-      const int64_t s0 = A.meta[k].k0[R.block], s1 = s0 + A.meta[k].kn[R.block];
+    if (ka >= 0) {  // cut the tile's spheres out of this block
+      const int64_t s0 = A.meta[ka].k0[R.block], s1 = A.meta[kb].k0[R.block] + A.meta[kb].kn[R.block];
       run_block<kTpl, kFree>(R.block, A, j0, min(j1, s0), acc);
       run_block<kTpl, kFree>(R.block, A, max(j0, s1), j1, acc);
+      for (int q = ka; q <= kb && ka != kb; ++q) {
+        const int64_t m0 = A.meta[q].k0[R.block], m1 = m0 + A.meta[q].kn[R.block];
+        bool on[kTpl];
+#pragma unroll
+        for (int p = 0; p < kTpl; ++p) on[p] = own[p] != q;
+        run_block_masked<kTpl, kFree>(R.block, A, max(j0, m0), min(j1, m1), acc, on);
+      }
     } else {
       run_block<kTpl, kFree>(R.block, A, j0, j1, acc);
     }
@@ -317,10 +376,10 @@ __device__ __forceinline__ void far_pair(float sx, float sy, float sz, float fx,
   }
 }
 
+// One wave of the FP32 far-field sum: tile `tile` of A, split `split`.
 template <int kTpl>
-__global__ __launch_bounds__(kBlock) void k_far_f32(Far32Args A) {
+__device__ __forceinline__ void far_wave(const Far32Args &A, int64_t tile, int split) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
   if (tile >= A.n_tiles) return;
   const int4 tl = A.tiles[tile];
   const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
@@ -337,8 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_far_f32(Far32Args A) {
   }
   const ConstPtr32 src = (ConstPtr32)A.src32, str = (ConstPtr32)A.str32;
   const double ckx = A.centers[3 * k], cky = A.centers[3 * k + 1], ckz = A.centers[3 * k + 2];
-  const int q0 = uniform((int)((int64_t)A.n_free * blockIdx.y / A.n_splits));
-  const int q1 = uniform((int)((int64_t)A.n_free * (blockIdx.y + 1) / A.n_splits));
+  const int q0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
+  const int q1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
   const int np = A.n_proxy;
   for (int q = q0; q < q1; ++q) {
     const int ks = A.free_ids[q];
@@ -368,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_far_f32(Far32Args A) {
       far_pair<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az);
     }
   }
-  float *out = A.part32 + (int64_t)blockIdx.y * A.T * 3;
+  float *out = A.part32 + (int64_t)split * A.T * 3;
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
     const int i = lane + kWave * p;
@@ -379,6 +438,12 @@ __global__ __launch_bounds__(kBlock) void k_far_f32(Far32Args A) {
       out[o + 2] = az[p];
     }
   }
+}
+
+template <int kTpl>
+__global__ __launch_bounds__(kBlock) void k_far_f32(Far32Args A) {
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  far_wave<kTpl>(A, tile, blockIdx.y);
 }
 
 __global__ void k_reduce_epilogue(int64_t n3, int32_t ns, const double *__restrict__ part,
@@ -1405,8 +1470,94 @@ __global__ __launch_bounds__(kBlock) void k_direct_block(BlockDirectArgs A) {
   }
 }
 
-// y_q = mu_q + W c0 sum_split part[split][q]
+// Mixed precision, many right-hand sides: the FP32 far field of the
+// contact-free proxies for a run of kRun vectors (blockIdx.z), one-sphere
+// tiles, the free spheres split over blockIdx.y.  Coordinates relative to
+// sphere centres as in far_wave; every pair's separation and 1/|r| serve the
+// whole run.  Strengths str32 are source-major, [proxy][nrhs][3].
+template <int kTpl, int kRun>
+__global__ __launch_bounds__(kBlock) void k_far_block_f32(Far32Args A, const float *__restrict__ str32b,
+                                                          int32_t nrhs, float *__restrict__ part32b) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (tile >= A.n_tiles) return;
+  const int4 tl = A.tiles[tile];
+  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  const int q0 = blockIdx.z * kRun;
+  const int split = blockIdx.y;
+  float tx[kTpl], ty[kTpl], tz[kTpl], a[kTpl][kRun][3];
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
+    tx[p] = A.tgt32[3 * ti];
+    ty[p] = A.tgt32[3 * ti + 1];
+    tz[p] = A.tgt32[3 * ti + 2];
+#pragma unroll
+    for (int q = 0; q < kRun; ++q) a[p][q][0] = a[p][q][1] = a[p][q][2] = 0.f;
+  }
+  const ConstPtr32 src = (ConstPtr32)A.src32, str = (ConstPtr32)str32b;
+  const double ckx = A.centers[3 * k], cky = A.centers[3 * k + 1], ckz = A.centers[3 * k + 2];
+  const int f0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
+  const int f1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
+  const int np = A.n_proxy;
+  for (int fq = f0; fq < f1; ++fq) {
+    const int ks = A.free_ids[fq];
+    if (ks == k) continue;
+    const float dx = (float)(A.centers[3 * ks] - ckx), dy = (float)(A.centers[3 * ks + 1] - cky),
+                dz = (float)(A.centers[3 * ks + 2] - ckz);
+    float ux[kTpl], uy[kTpl], uz[kTpl];
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      ux[p] = tx[p] - dx;
+      uy[p] = ty[p] - dy;
+      uz[p] = tz[p] - dz;
+    }
+    const int j1 = uniform(ks * np + np);
+    for (int j = uniform(ks * np); j < j1; ++j) {
+      const ConstPtr32 ps = src + 3 * j, pf = str + ((int64_t)j * nrhs + q0) * 3;
+      const float sx = ps[0], sy = ps[1], sz = ps[2];
+      float f[kRun][3];
+#pragma unroll
+      for (int q = 0; q < kRun; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[q][c] = pf[3 * q + c];
+#pragma unroll
+      for (int p = 0; p < kTpl; ++p) {
+        const float rx = ux[p] - sx, ry = uy[p] - sy, rz = uz[p] - sz;
+        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri2 = ri * ri;
+#pragma unroll
+        for (int q = 0; q < kRun; ++q) {
+          const float t = fmaf(rx, f[q][0], fmaf(ry, f[q][1], rz * f[q][2])) * ri2;
+          a[p][q][0] = fmaf(fmaf(rx, t, f[q][0]), ri, a[p][q][0]);
+          a[p][q][1] = fmaf(fmaf(ry, t, f[q][1]), ri, a[p][q][1]);
+          a[p][q][2] = fmaf(fmaf(rz, t, f[q][2]), ri, a[p][q][2]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    if (i < tc) {
+#pragma unroll
+      for (int q = 0; q < kRun; ++q) {
+        if (q0 + q >= nrhs) break;
+        float *out = part32b + ((int64_t)split * nrhs + q0 + q) * A.T * 3;
+        const int64_t o = 3 * ((int64_t)t0 + i);
+        out[o] = a[p][q][0];
+        out[o + 1] = a[p][q][1];
+        out[o + 2] = a[p][q][2];
+      }
+    }
+  }
+}
+
+// y_q = mu_q + W c0 (sum_split part[split][q] + sum_split part32[split][q])
 __global__ void k_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *__restrict__ part,
+                               int32_t ns32, const float *__restrict__ part32,
                                const double *__restrict__ base, int64_t ldb,
                                const double *__restrict__ sw, double c0, double *__restrict__ y,
                                int64_t ldy) {
@@ -1415,6 +1566,7 @@ __global__ void k_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const doubl
   if (i >= n3 || q >= nrhs) return;
   double acc = 0.0;
   for (int s = 0; s < ns; ++s) acc += part[((int64_t)s * nrhs + q) * n3 + i];
+  for (int s = 0; s < ns32; ++s) acc += (double)part32[((int64_t)s * nrhs + q) * n3 + i];
   y[q * ldy + i] = base[q * ldb + i] + sw[i / 3] * c0 * acc;
 }
 
@@ -1528,12 +1680,22 @@ hipError_t launch_direct_block(const BlockDirectArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part,
-                               const double *base, int64_t ldb, const double *sw, double c0,
-                               double *y, int64_t ldy, hipStream_t s) {
+hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part, int32_t ns32,
+                               const float *part32, const double *base, int64_t ldb, const double *sw,
+                               double c0, double *y, int64_t ldy, hipStream_t s) {
   if (n3 == 0 || nrhs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_block, dim3(blocks_for(n3), nrhs), dim3(kBlock), 0, s, n3, nrhs, ns,
-                     part, base, ldb, sw, c0, y, ldy);
+                     part, ns32, part32, base, ldb, sw, c0, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_far_block_f32(const Far32Args &a, const float *str32b, int32_t nrhs, float *part32b,
+                                hipStream_t s) {
+  if (a.n_tiles == 0 || a.n_splits == 0 || nrhs == 0) return hipSuccess;
+  dim3 grid((unsigned)((a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)a.n_splits,
+            (unsigned)((nrhs + kBlockRun - 1) / kBlockRun));
+  hipLaunchKernelGGL((k_far_block_f32<kDirectTpl, kBlockRun>), grid, dim3(kBlock), 0, s, a, str32b, nrhs,
+                     part32b);
   return hipGetLastError();
 }
 
@@ -1636,7 +1798,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIR
   direct_wave<kTpl, false>(d.da, t - d.tile0, blockIdx.y);
 }
 
-// y = x + W c0 sum_s part[s] (the same arithmetic as k_reduce_epilogue)
+// Mixed precision: FP32 copies of the proxy strengths of every problem.
+__global__ void k_serve_to32(const ServeDesc *__restrict__ D) {
+  const ServeDesc &d = D[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d.fa.n_splits == 0 || i >= d.n_str32) return;
+  d.str32[i] = (float)d.lam[i];
+}
+
+// Mixed precision: FP32 far field of the contact-free proxies, every
+// problem's one-sphere tiles in one launch (flat index over the problems'
+// tiles, split in blockIdx.y).
+template <int kTpl>
+__global__ __launch_bounds__(kBlock) void k_serve_far32(const ServeDesc *__restrict__ D, int32_t nprob,
+                                                        int64_t total) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (t >= total) return;
+  const int r = find_problem(nprob, t, [D](int i) { return D[i].stile0; });
+  const ServeDesc &d = D[r];
+  if ((int)blockIdx.y >= d.fa.n_splits) return;
+  far_wave<kTpl>(d.fa, t - d.stile0, blockIdx.y);
+}
+
+// y = x + W c0 (sum_s part[s] + sum_s part32[s]) (the same arithmetic as
+// k_reduce_epilogue)
 __global__ void k_serve_reduce(const ServeDesc *__restrict__ D) {
   const ServeDesc &d = D[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1644,6 +1829,7 @@ __global__ void k_serve_reduce(const ServeDesc *__restrict__ D) {
   const int32_t ns = d.da.n_splits;
   double acc = 0.0;
   for (int s = 0; s < ns; ++s) acc += d.da.part[(int64_t)s * d.n + i];
+  for (int s = 0; s < d.fa.n_splits; ++s) acc += (double)d.fa.part32[(int64_t)s * d.n + i];
   double v = d.c0 * acc;
   v *= d.sw[i / 3];
   v += d.x[i];
@@ -1724,7 +1910,8 @@ __global__ void k_serve_scale(const ServeDesc *__restrict__ D) {
 }  // namespace
 
 hipError_t launch_serve_product(const ServeDesc *d, int32_t nprob, int64_t tiles, int64_t utasks,
-                                int64_t vtasks, int32_t max_splits, int64_t max_n, hipStream_t s) {
+                                int64_t vtasks, int32_t max_splits, int64_t max_n, int64_t stiles,
+                                int32_t max_splits32, int64_t max_str32, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   if (utasks > 0)
     hipLaunchKernelGGL(k_serve_pinv_u, dim3(blocks_for(utasks, kWavesPerBlock)), dim3(kBlock), 0, s,
@@ -1736,6 +1923,12 @@ hipError_t launch_serve_product(const ServeDesc *d, int32_t nprob, int64_t tiles
     hipLaunchKernelGGL((k_serve_direct<kDirectTpl>),
                        dim3(blocks_for(tiles, kWavesPerBlock), (unsigned)max_splits), dim3(kBlock), 0,
                        s, d, nprob, tiles);
+  if (stiles > 0 && max_splits32 > 0) {
+    hipLaunchKernelGGL(k_serve_to32, dim3(blocks_for(max_str32), nprob), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL((k_serve_far32<kDirectTpl>),
+                       dim3(blocks_for(stiles, kWavesPerBlock), (unsigned)max_splits32), dim3(kBlock), 0,
+                       s, d, nprob, stiles);
+  }
   hipLaunchKernelGGL(k_serve_reduce, dim3(blocks_for(max_n), nprob), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }

@@ -38,6 +38,7 @@
 namespace smfs {
 
 DirectArgs direct_args(Problem &pb, const double *str, bool mixed);
+int setup_factors(Problem &pb, char *scratch, size_t scratch_bytes, hipStream_t s);
 int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s);
 
 namespace {
@@ -117,13 +118,14 @@ struct Req {
   size_t off = 0, bytes = 0;
   bool has_mem = false;
   // GMRES state (one restart cycle)
-  int m = 0, j = 0, total = 0, restarts = 0;
+  int m = 0, j = 0, total = 0, restarts = 0, refinements = 0;
   bool converged = false;
   double bnorm = 0.0, est = 0.0;
   std::vector<double> H, cs, sn, g;
   // results
   std::vector<double> ft;
   double true_rel = 0.0;
+  int64_t pair_evals_f32 = 0;
   double t_arrival = 0, t_admit = 0, t_start = 0, t_done = 0;
   int64_t pair_evals = 0;
 };
@@ -135,16 +137,21 @@ using namespace smfs;
 
 namespace smfs {
 namespace {
-// A set-up worker: its own thread, stream, rocBLAS handle and SVD scratch.
+// A set-up worker: its own thread, stream, rocBLAS handle and SVD scratch
+// (a slice of the caller's memory: rocSOLVER's work arrays, then the
+// batched SVD inputs and outputs).
 struct Worker {
   hipStream_t s = nullptr;
   rocblas_handle rb = nullptr;
-  void *scratch = nullptr;
+  void *work = nullptr;              // rocSOLVER's work arrays (the handle's user workspace)
+  size_t work_bytes = 0;
+  void *scratch = nullptr;           // batched SVD inputs, outputs, status words
   size_t scratch_bytes = 0;
+  std::map<std::pair<int, int>, int> cap;   // SVD batch count per block shape
   std::thread th;
 };
-constexpr size_t kSvdScratch = (size_t)4 << 30;
-constexpr size_t kSvdBatch = 256;    // blocks per batched SVD call (fixed per shape)
+constexpr size_t kSvdScratch = (size_t)4 << 30;   // default per worker
+constexpr size_t kSvdBatch = 256;    // most blocks per batched SVD call (fixed per shape)
 }  // namespace
 }  // namespace smfs
 
@@ -152,7 +159,8 @@ struct smfs_server {
   smfs_params prm{};
   double radius = 1.0;
   int device = 0;
-  char *arena = nullptr;
+  int32_t max_queued = 0;        // 0: no limit
+  char *arena = nullptr;         // part of the caller's memory
   size_t arena_bytes = 0;
   Arena alloc;
   int32_t max_active = 1;
@@ -273,7 +281,35 @@ void factor_batch(Worker &wk, std::vector<Req *> &batch) {
     const size_t per = (size_t)m * n;
     const size_t slot = ((size_t)m * n + (size_t)n * n + n + 31) / 32 * 32;
     const size_t each = 8 * (per + slot + n) + 4 + 3 * kAl;
-    const size_t cap = std::max<size_t>(1, std::min<size_t>(kSvdBatch, wk.scratch_bytes / each));
+    size_t cap = 0;
+    {
+      // blocks per call for this shape: as many as the scratch holds (at most
+      // kSvdBatch) whose SVD work arrays also fit the worker's workspace; it
+      // depends on the shape and the worker's memory only, so every call of
+      // a shape has the same batch count
+      auto it = wk.cap.find({m, n});
+      if (it != wk.cap.end()) {
+        cap = (size_t)it->second;
+      } else {
+        cap = std::max<size_t>(1, std::min<size_t>(kSvdBatch, wk.scratch_bytes / each));
+        double *fake = reinterpret_cast<double *>((uintptr_t)4096);
+        rocblas_int *ifake = reinterpret_cast<rocblas_int *>((uintptr_t)4096);
+        while (true) {
+          size_t need = 0;
+          rocblas_start_device_memory_size_query(wk.rb);
+          const rocblas_status q = rocsolver_dgesvd_strided_batched(
+              wk.rb, rocblas_svect_singular, rocblas_svect_singular, m, n, fake, m, (rocblas_stride)per,
+              fake, (rocblas_stride)slot, fake, m, (rocblas_stride)slot, fake, n, (rocblas_stride)slot,
+              fake, n, rocblas_outofplace, ifake, (rocblas_int)cap);
+          rocblas_stop_device_memory_size_query(wk.rb, &need);
+          const bool ok = q == rocblas_status_success || q == rocblas_status_size_increased ||
+                          q == rocblas_status_size_unchanged;
+          if ((ok && need <= wk.work_bytes) || cap == 1) break;
+          cap = std::max<size_t>(1, cap / 2);
+        }
+        wk.cap[{m, n}] = (int)cap;
+      }
+    }
     std::vector<Job> &jobs = grp.second;
     for (size_t j0 = 0; j0 < jobs.size(); j0 += cap) {
       const int nb = (int)std::min(cap, jobs.size() - j0);   // real blocks in this call
@@ -444,6 +480,7 @@ int complete_request(smfs_server *srv, Req *r) {
   SMFS_HIP(hipStreamSynchronize(s));
   r->true_rel = r->bnorm > 0 ? rn / r->bnorm : 0.0;
   r->pair_evals = (int64_t)(r->total + r->restarts + 1) * pb.pairs_per_apply;
+  if (is_mixed(srv->prm.precision) && pb.n_free > 0) r->pair_evals_f32 = (int64_t)r->total * pb.pairs_f32;
   return SMFS_OK;
 }
 
@@ -502,80 +539,176 @@ extern "C" {
 
 double smfs_server_clock(void) { return clock_s(); }
 
-int smfs_server_create(const smfs_params *p, double radius, size_t arena_bytes, int32_t max_active,
-                       int32_t setup_workers, smfs_server **out) {
-  if (!p || !out || !(radius > 0) || arena_bytes == 0 || max_active < 1 || max_active > 4096 ||
-      setup_workers < 1 || setup_workers > 64) {
-    set_error("smfs_server_create: bad argument");
+int smfs_server_config_default(smfs_server_config *c) {
+  if (!c) { set_error("null config"); return SMFS_E_INVALID_ARG; }
+  std::memset(c, 0, sizeof(*c));
+  c->radius = 1.0;
+  c->max_active = 64;
+  c->setup_workers = 1;
+  c->max_queued = 0;
+  c->precision = SMFS_FP64;
+  c->worker_scratch_bytes = kSvdScratch;
+  return SMFS_OK;
+}
+
+}  // extern "C"
+
+namespace smfs {
+namespace {
+
+// Fixed part of the server's device memory (before the arena): the shared
+// factor, descriptors and Hessenberg readback of the slots, every worker's
+// scratch.  Offsets from the start of the caller's memory.
+struct ServerLayout {
+  size_t f0 = 0, desc = 0, tick = 0, workers = 0, arena = 0;
+  size_t worker_bytes = 0, work_bytes = 0;
+  int64_t f0_elems = 0;
+  int32_t ldt = 0;
+};
+
+int server_layout(const smfs_params *p, const smfs_server_config *c, ServerLayout &L) {
+  if (!p || !c || !(c->radius > 0) || c->max_active < 1 || c->max_active > 4096 || c->setup_workers < 1 ||
+      c->setup_workers > 64 || c->max_queued < 0) {
+    set_error("smfs_server: bad configuration");
     return SMFS_E_INVALID_ARG;
   }
-  if (p->precision != SMFS_FP64) {
-    set_error("smfs_server_create: serving runs the FP64 product");
+  if (c->precision != SMFS_FP64 && c->precision != SMFS_MIXED_FAR) {
+    set_error("smfs_server: serving runs SMFS_FP64 or SMFS_MIXED_FAR products");
     return SMFS_E_UNSUPPORTED;
   }
+  // the shared factor's shape from a one-sphere problem (host geometry only)
+  const double c0[3] = {0.0, 0.0, 0.0};
+  double radius = c->radius;
+  smfs_problem *t = nullptr;
+  int rc = smfs_problem_create(p, 1, c0, &radius, &t);
+  if (rc < 0) return rc;
+  const FactorSlot &f = t->factors[0];
+  L.f0_elems = (int64_t)f.rows * f.cols + (int64_t)f.cols * f.cols + f.cols;
+  smfs_problem_destroy(t);
+  L.ldt = 2 * (std::max(1, p->gmres_restart) + 2);
+  L.worker_bytes = al(c->worker_scratch_bytes ? c->worker_scratch_bytes : kSvdScratch);
+  // a quarter of each worker's scratch (at least 64 MiB) for rocSOLVER's work arrays
+  L.work_bytes = al(std::max<size_t>((size_t)64 << 20, L.worker_bytes / 4));
+  if (L.work_bytes >= L.worker_bytes) {
+    set_error("smfs_server: worker scratch too small (at least 128 MiB)");
+    return SMFS_E_INVALID_ARG;
+  }
+  size_t off = 0;
+  L.f0 = off;
+  off = al(off + sizeof(double) * (size_t)L.f0_elems);
+  L.desc = off;
+  off = al(off + sizeof(ServeDesc) * (size_t)c->max_active);
+  L.tick = off;
+  off = al(off + sizeof(double) * (size_t)L.ldt * c->max_active);
+  L.workers = off;
+  off += L.worker_bytes * (size_t)c->setup_workers;
+  L.arena = off;
+  return SMFS_OK;
+}
+
+}  // namespace
+}  // namespace smfs
+
+extern "C" {
+
+int smfs_server_memory_bytes(const smfs_params *p, const smfs_server_config *c, size_t *fixed_bytes) {
+  if (!fixed_bytes) { set_error("null argument"); return SMFS_E_INVALID_ARG; }
+  ServerLayout L;
+  int rc = server_layout(p, c, L);
+  if (rc) return rc;
+  *fixed_bytes = L.arena;
+  return SMFS_OK;
+}
+
+int smfs_server_create(const smfs_params *p, const smfs_server_config *c, void *dev_mem, size_t dev_bytes,
+                       smfs_server **out) {
+  if (!out || !dev_mem || ((uintptr_t)dev_mem) % kAl) {
+    set_error("smfs_server_create: null argument or device memory not 256-byte aligned");
+    return SMFS_E_INVALID_ARG;
+  }
   *out = nullptr;
+  ServerLayout L;
+  int rc = server_layout(p, c, L);
+  if (rc) return rc;
+  if (dev_bytes <= L.arena) {
+    set_error("smfs_server_create: " + std::to_string(dev_bytes) + " bytes of device memory leave no arena (" +
+              std::to_string(L.arena) + " needed before it)");
+    return SMFS_E_NOMEM;
+  }
   smfs_server *srv = new smfs_server();
   srv->prm = *p;
-  srv->radius = radius;
-  srv->max_active = max_active;
-  srv->arena_bytes = arena_bytes;
+  srv->prm.precision = c->precision;
+  srv->radius = c->radius;
+  srv->max_active = c->max_active;
+  srv->max_queued = c->max_queued;
+  char *base = (char *)dev_mem;
+  srv->arena = base + L.arena;
+  srv->arena_bytes = dev_bytes - L.arena;
   struct Guard {
     smfs_server *s;
     ~Guard() { if (s) smfs_server_destroy(s); }
   } guard{srv};
   SMFS_HIP(hipGetDevice(&srv->device));
-  SMFS_HIP(hipMalloc((void **)&srv->arena, arena_bytes));
-  srv->alloc.init(arena_bytes);
+  srv->alloc.init(srv->arena_bytes);
   SMFS_HIP(hipStreamCreate(&srv->s_main));
-  srv->workers.resize(setup_workers);
-  for (Worker &w : srv->workers) {
+  srv->workers.resize(c->setup_workers);
+  for (size_t i = 0; i < srv->workers.size(); ++i) {
+    Worker &w = srv->workers[i];
     SMFS_HIP(hipStreamCreate(&w.s));
     if (rocblas_create_handle(&w.rb) != rocblas_status_success) {
       set_error("rocblas_create_handle failed");
       return SMFS_E_DEVICE;
     }
     rocblas_set_stream(w.rb, w.s);
-    SMFS_HIP(hipMalloc(&w.scratch, kSvdScratch));
-    w.scratch_bytes = kSvdScratch;
+    char *wb = base + L.workers + i * L.worker_bytes;
+    w.work = wb;
+    w.work_bytes = L.work_bytes;
+    w.scratch = wb + L.work_bytes;
+    w.scratch_bytes = L.worker_bytes - L.work_bytes;
   }
   Worker &w0 = srv->workers[0];
-  // the shared factor from a single contact-free sphere
+  // the shared factor from a single contact-free sphere, set up in the (still
+  // empty) arena with worker 0's scratch
   {
-    const double c[3] = {0.0, 0.0, 0.0};
+    const double c0[3] = {0.0, 0.0, 0.0};
+    double radius = c->radius;
     smfs_problem *t = nullptr;
-    int rc = smfs_problem_create(p, 1, c, &radius, &t);
+    rc = smfs_problem_create(&srv->prm, 1, c0, &radius, &t);
     if (rc < 0) return rc;
     struct Drop {
       smfs_problem *t;
-      void *ws;
-      ~Drop() {
-        if (t) { t->rocblas = nullptr; smfs_problem_destroy(t); }
-        if (ws) (void)hipFree(ws);
-      }
-    } drop{t, nullptr};
-    SMFS_HIP(hipMalloc(&drop.ws, t->need_bytes));
-    if ((rc = smfs_bind(t, drop.ws, t->need_bytes, w0.s))) return rc;
+      ~Drop() { if (t) { t->rocblas = nullptr; smfs_problem_destroy(t); } }
+    } drop{t};
+    if (t->need_bytes > srv->arena_bytes) {
+      set_error("smfs_server_create: the arena does not hold a one-sphere request");
+      return SMFS_E_NOMEM;
+    }
+    if ((rc = smfs_bind(t, srv->arena, t->need_bytes, w0.s))) return rc;
     t->rocblas = w0.rb;
-    t->svd_scratch = w0.scratch;
-    t->svd_scratch_bytes = w0.scratch_bytes;
-    if ((rc = smfs_setup(t, w0.s))) return rc;
+    if ((rc = setup_factors(*t, (char *)w0.work, L.worker_bytes, w0.s))) return rc;
     const FactorSlot &f = t->factors[0];
     srv->f0_rows = f.rows;
     srv->f0_cols = f.cols;
     srv->f0_rank = f.rank;
-    srv->f0_elems = (int64_t)f.rows * f.cols + (int64_t)f.cols * f.cols + f.cols;
-    SMFS_HIP(hipMalloc((void **)&srv->f0, sizeof(double) * srv->f0_elems));
+    srv->f0_elems = L.f0_elems;
+    srv->f0 = (double *)(base + L.f0);
     SMFS_HIP(hipMemcpyAsync(srv->f0, t->d_fac + f.u_off, sizeof(double) * srv->f0_elems,
                             hipMemcpyDeviceToDevice, w0.s));
     SMFS_HIP(hipStreamSynchronize(w0.s));
   }
-  srv->ldt = 2 * (std::max(1, p->gmres_restart) + 2);
-  SMFS_HIP(hipMalloc((void **)&srv->d_desc, sizeof(ServeDesc) * max_active));
-  SMFS_HIP(hipHostMalloc((void **)&srv->h_desc, sizeof(ServeDesc) * max_active, hipHostMallocDefault));
-  SMFS_HIP(hipMalloc((void **)&srv->d_tick, sizeof(double) * srv->ldt * max_active));
-  SMFS_HIP(hipHostMalloc((void **)&srv->h_tick, sizeof(double) * srv->ldt * max_active, hipHostMallocDefault));
-  srv->st.arena_bytes = arena_bytes;
-  for (int i = 0; i < setup_workers; ++i) srv->workers[i].th = std::thread(worker_main, srv, i);
+  // from here on rocSOLVER works in each worker's own slice
+  for (Worker &w : srv->workers)
+    if (rocblas_set_workspace(w.rb, w.work, w.work_bytes) != rocblas_status_success) {
+      set_error("rocblas_set_workspace failed");
+      return SMFS_E_DEVICE;
+    }
+  srv->ldt = L.ldt;
+  srv->d_desc = (ServeDesc *)(base + L.desc);
+  SMFS_HIP(hipHostMalloc((void **)&srv->h_desc, sizeof(ServeDesc) * c->max_active, hipHostMallocDefault));
+  srv->d_tick = (double *)(base + L.tick);
+  SMFS_HIP(hipHostMalloc((void **)&srv->h_tick, sizeof(double) * srv->ldt * c->max_active, hipHostMallocDefault));
+  srv->st.arena_bytes = srv->arena_bytes;
+  for (int i = 0; i < c->setup_workers; ++i) srv->workers[i].th = std::thread(worker_main, srv, i);
   guard.s = nullptr;
   *out = srv;
   return SMFS_OK;
@@ -597,15 +730,11 @@ void smfs_server_destroy(smfs_server *srv) {
     drop_problem(kv.second);
     delete kv.second;
   }
-  if (srv->arena) (void)hipFree(srv->arena);
-  if (srv->f0) (void)hipFree(srv->f0);
-  if (srv->d_desc) (void)hipFree(srv->d_desc);
-  if (srv->d_tick) (void)hipFree(srv->d_tick);
+  // the device memory is the caller's; host buffers, streams and handles are ours
   if (srv->h_desc) (void)hipHostFree(srv->h_desc);
   if (srv->h_tick) (void)hipHostFree(srv->h_tick);
   for (Worker &w : srv->workers) {
     if (w.rb) rocblas_destroy_handle(w.rb);
-    if (w.scratch) (void)hipFree(w.scratch);
     if (w.s) (void)hipStreamDestroy(w.s);
   }
   if (srv->s_main) (void)hipStreamDestroy(srv->s_main);
@@ -623,6 +752,13 @@ int smfs_server_submit(smfs_server *srv, int32_t P, const double *centers, const
       set_error("smfs_server_submit: non-finite rigid motion");
       return SMFS_E_INVALID_ARG;
     }
+  if (srv->max_queued > 0) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if ((int32_t)srv->queue.size() >= srv->max_queued) {
+      set_error("smfs_server_submit: queue full");
+      return SMFS_E_AGAIN;
+    }
+  }
   const double now = clock_s();
   std::vector<double> radii(P, srv->radius);
   smfs_problem *pb = nullptr;
@@ -678,15 +814,26 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
   }
   const int32_t nprob = (int32_t)run.size();
   if (nprob > 0) {
-    int64_t tiles = 0, ut = 0, vt = 0, max_n = 0;
-    int32_t max_splits = 1, max_nv = 1, max_nch = 1;
+    int64_t tiles = 0, ut = 0, vt = 0, max_n = 0, stiles = 0, max_str32 = 0;
+    int32_t max_splits = 1, max_nv = 1, max_nch = 1, max_splits32 = 0;
     const int mh = srv->ldt / 2;
     for (int32_t i = 0; i < nprob; ++i) {
       Req *r = run[i];
       Problem &pb = *r->pb;
       ServeDesc &d = srv->h_desc[i];
-      d.da = direct_args(pb, pb.d_lamhat, false);
+      const bool mixed = is_mixed(srv->prm.precision) && pb.n_free > 0;
+      d.da = direct_args(pb, pb.d_lamhat, mixed);
       d.tile0 = tiles;
+      d.fa = Far32Args{};
+      d.stile0 = stiles;
+      d.str32 = pb.d_str32;
+      d.n_str32 = 3 * pb.nb[0];
+      if (mixed) {
+        d.fa = far32_args(pb);
+        stiles += pb.n_stiles;
+        max_splits32 = std::max(max_splits32, pb.n_splits32);
+        max_str32 = std::max(max_str32, d.n_str32);
+      }
       d.utask = pb.d_utask;
       d.vtask = pb.d_vtask;
       d.n_utask = pb.n_utask;
@@ -718,7 +865,8 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
       max_nch = std::max(max_nch, d.nch);
     }
     SMFS_HIP(hipMemcpyAsync(srv->d_desc, srv->h_desc, sizeof(ServeDesc) * nprob, hipMemcpyHostToDevice, s));
-    SMFS_HIP(launch_serve_product(srv->d_desc, nprob, tiles, ut, vt, max_splits, max_n, s));
+    SMFS_HIP(launch_serve_product(srv->d_desc, nprob, tiles, ut, vt, max_splits, max_n, stiles, max_splits32,
+                                  max_str32, s));
     SMFS_HIP(launch_serve_arnoldi(srv->d_desc, nprob, max_nv, max_nch, max_n, s));
     SMFS_HIP(hipMemcpyAsync(srv->h_tick, srv->d_tick, sizeof(double) * srv->ldt * nprob,
                             hipMemcpyDeviceToHost, s));
@@ -748,16 +896,30 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
       r->j = j + 1;
       ++r->total;
       r->est = std::fabs(r->g[j + 1]) / r->bnorm;
-      bool done = false;
+      bool done = false, refine = false;
       if (r->est <= tol) {
         r->converged = true;
         done = true;
+        // mixed products: restart from the FP64 true residual (at most two
+        // refinements); the request goes on when that residual is above tol
+        refine = is_mixed(srv->prm.precision) && r->refinements < 2 &&
+                 r->total < srv->prm.gmres_max_it;
       } else if (r->total >= srv->prm.gmres_max_it || a[j + 1] == 0.0) {
         done = true;
       }
       if (done || r->j == m) {
         int rc = combine_cycle(srv, r);
-        if (!rc && !done) rc = restart_cycle(srv, r, &done);
+        if (!rc && (!done || refine)) {
+          bool met = false;
+          rc = restart_cycle(srv, r, &met);
+          if (refine) {
+            ++r->refinements;
+            done = met;
+            r->converged = met;
+          } else {
+            done = met;
+          }
+        }
         if (rc) {
           r->status = rc;
           r->err = smfs_last_error();
@@ -773,8 +935,9 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
       if (rc) {
         r->status = rc;
         r->err = smfs_last_error();
-      } else if (!r->converged) {
-        r->status = SMFS_NOT_CONVERGED;
+      } else if (r->true_rel > srv->prm.gmres_tol) {
+        // honest status: OK only when the FP64 true residual meets the tolerance
+        r->status = r->converged ? SMFS_STAGNATED : SMFS_NOT_CONVERGED;
       }
     }
     r->t_done = clock_s();
@@ -786,7 +949,7 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
       r->state = St::kDone;
       free_request_memory(srv, r);
       drop_problem(r);
-      if (r->status == SMFS_OK || r->status == SMFS_NOT_CONVERGED) ++srv->st.completed;
+      if (r->status >= 0) ++srv->st.completed;
       else ++srv->st.failed;
     }
     if (!finished.empty()) {
@@ -825,6 +988,8 @@ int smfs_server_poll(smfs_server *srv, int64_t id, smfs_request_result *res, dou
   res->t_started = r->t_start;
   res->t_done = r->t_done;
   res->pair_evals = r->pair_evals;
+  res->pair_evals_f32 = r->pair_evals_f32;
+  res->refinements = r->refinements;
   std::snprintf(res->error, sizeof(res->error), "%s", r->err.c_str());
   if (ft && !r->ft.empty()) std::memcpy(ft, r->ft.data(), sizeof(double) * r->ft.size());
   return SMFS_OK;

@@ -1,0 +1,507 @@
+// Truncated SVD of the self blocks B = W G^(kk) on the device (Section 2.2,
+// eq. transform; truncation eps_trunc of Section 5): Householder QR of every
+// block (rocSOLVER geqrf), one-sided Jacobi (Hestenes) on the triangular
+// factor R in HIP, then U = Q [U_R; 0] (rocSOLVER ormqr).
+//
+// One-sided Jacobi orthogonalises the columns of X = R V by plane rotations,
+// each computed from fresh dot products of the two columns it rotates, so
+// the singular values come out with the accuracy of the data (the Gram
+// matrix is never formed, which would square the condition number and lose
+// everything below sqrt(eps) sigma_1, far above the 5e-12 truncation).  The
+// columns are processed in blocks of w: a sweep visits every pair of column
+// blocks once (round-robin schedule, disjoint pairs in parallel); a pair
+// task holds its 2w columns in registers across a 512-thread workgroup and
+// runs one round-robin sweep over the 2w columns, accumulating its
+// rotations in a 2w x 2w matrix that a second kernel applies to V.  Sweeps
+// repeat until no pair of columns has a cosine above 1e-13.  Every block is
+// processed on its own, whatever else shares the launch.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/smfs.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace smfs {
+
+namespace {
+
+constexpr int kJacThreads = 512;         // threads of a pair task (8 waves)
+constexpr int kJacWaves = kJacThreads / 64;
+constexpr double kRotTol = 1e-15;        // rotate when |x_a.x_b| > tol |x_a| |x_b|
+constexpr double kSweepTol = 1e-13;      // sweeps end when every cosine is below this
+constexpr int kMaxSweeps = 30;
+
+size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Round-robin pairing of 2w players: player 0 stays, the others rotate.
+__host__ __device__ constexpr int rr_a(int q, int i, int n) { return i == 0 ? 0 : 1 + (q + i) % (n - 1); }
+__host__ __device__ constexpr int rr_b(int q, int i, int n) {
+  return i == 0 ? 1 + q % (n - 1) : 1 + (q + n - 1 - i) % (n - 1);
+}
+
+struct JacArgs {
+  double *X;            // per block: n rows x npad columns, column-major (ld n)
+  int64_t x_stride;     // elements between blocks
+  int32_t n, npad, w;   // rows, padded columns, columns per column block
+  const int2 *pairs;    // column-block pairs of this round (npairs), (-1, -1) = none
+  int32_t npairs;
+  double *Wout;         // per block and pair task: 2w x 2w rotation product (column-major)
+  double *off;          // per block and pair task: largest cosine seen before rotation
+};
+
+// Shared memory of a pair task.
+template <int kW2>
+struct JacShared {
+  double red[kJacWaves][3 * kW2 / 2];
+  double rot[kW2 / 2][2];
+  double W[kW2][kW2];
+};
+
+// Round q of the inner sweep over the 2w columns held in x (q is a template
+// argument so that every column index below is a compile-time constant and
+// x stays in registers): dot products of the round's w disjoint pairs,
+// reduced over the workgroup, rotations computed by w threads, applied to
+// every thread's rows and to W.
+template <int kRows, int kW2, int q>
+__device__ __forceinline__ void jac_round(double (&x)[kRows][kW2], JacShared<kW2> &sh, double &offmax) {
+  constexpr int w = kW2 / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double s[3 * w];
+#pragma unroll
+  for (int i = 0; i < w; ++i) {
+    const int ca = rr_a(q, i, kW2), cb = rr_b(q, i, kW2);
+    double aa = 0.0, bb = 0.0, ab = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      aa = fma(x[k][ca], x[k][ca], aa);
+      bb = fma(x[k][cb], x[k][cb], bb);
+      ab = fma(x[k][ca], x[k][cb], ab);
+    }
+    s[3 * i] = aa;
+    s[3 * i + 1] = bb;
+    s[3 * i + 2] = ab;
+  }
+#pragma unroll
+  for (int v = 0; v < 3 * w; ++v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s[v] += __shfl_xor(s[v], o);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < 3 * w; ++v) sh.red[wave][v] = s[v];
+  }
+  __syncthreads();
+  if (tid < w) {
+    double aa = 0.0, bb = 0.0, ab = 0.0;
+    for (int u = 0; u < kJacWaves; ++u) {
+      aa += sh.red[u][3 * tid];
+      bb += sh.red[u][3 * tid + 1];
+      ab += sh.red[u][3 * tid + 2];
+    }
+    double c = 1.0, sn = 0.0;
+    if (aa > 0.0 && bb > 0.0) {
+      const double cosv = fabs(ab) / (sqrt(aa) * sqrt(bb));
+      offmax = fmax(offmax, cosv);
+      if (cosv > kRotTol) {
+        // x_a' = c x_a - s x_b, x_b' = s x_a + c x_b with x_a'.x_b' = 0
+        const double zeta = (bb - aa) / (2.0 * ab);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = 1.0 / sqrt(1.0 + t * t);
+        sn = c * t;
+      }
+    }
+    sh.rot[tid][0] = c;
+    sh.rot[tid][1] = sn;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < w; ++i) {
+    const int ca = rr_a(q, i, kW2), cb = rr_b(q, i, kW2);
+    const double c = sh.rot[i][0], sn = sh.rot[i][1];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const double xa = x[k][ca], xb = x[k][cb];
+      x[k][ca] = c * xa - sn * xb;
+      x[k][cb] = sn * xa + c * xb;
+    }
+  }
+  // the same column rotations on W (one row of W per thread)
+  if (tid < kW2 * w) {
+    const int i = tid / kW2, r = tid % kW2;
+    int ca = 0, cb = 0;
+#pragma unroll
+    for (int ii = 0; ii < w; ++ii)
+      if (ii == i) { ca = rr_a(q, ii, kW2); cb = rr_b(q, ii, kW2); }
+    const double c = sh.rot[i][0], sn = sh.rot[i][1];
+    const double wa = sh.W[r][ca], wb = sh.W[r][cb];
+    sh.W[r][ca] = c * wa - sn * wb;
+    sh.W[r][cb] = sn * wa + c * wb;
+  }
+  __syncthreads();
+}
+
+template <int kRows, int kW2, int... Q>
+__device__ __forceinline__ void jac_rounds(double (&x)[kRows][kW2], JacShared<kW2> &sh, double &offmax,
+                                           std::integer_sequence<int, Q...>) {
+  (jac_round<kRows, kW2, Q>(x, sh, offmax), ...);
+}
+
+// One pair task: columns of blocks I and J of matrix blockIdx.y.  Each
+// thread holds rows tid, tid + 512, ... (kRows of them) of the 2w columns.
+template <int kRows, int kW2>
+__global__ __launch_bounds__(kJacThreads) void k_jac_pairs(JacArgs a) {
+  __shared__ JacShared<kW2> sh;
+  const int tid = threadIdx.x;
+  const int task = blockIdx.x, b = blockIdx.y;
+  const int2 pr = a.pairs[task];
+  double *Wo = a.Wout + ((int64_t)b * a.npairs + task) * kW2 * kW2;
+  double *offo = a.off + (int64_t)b * a.npairs + task;
+  if (pr.x < 0) {
+    if (tid == 0) *offo = 0.0;
+    return;
+  }
+  constexpr int w = kW2 / 2;
+  double *X = a.X + (int64_t)b * a.x_stride;
+  double x[kRows][kW2];
+#pragma unroll
+  for (int c = 0; c < kW2; ++c) {
+    const int64_t gc = c < w ? (int64_t)pr.x * w + c : (int64_t)pr.y * w + (c - w);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int r = tid + k * kJacThreads;
+      x[k][c] = r < a.n ? X[gc * a.n + r] : 0.0;
+    }
+  }
+  for (int e = tid; e < kW2 * kW2; e += kJacThreads) sh.W[e % kW2][e / kW2] = (e % kW2 == e / kW2) ? 1.0 : 0.0;
+  __syncthreads();
+  double offmax = 0.0;
+  jac_rounds<kRows, kW2>(x, sh, offmax, std::make_integer_sequence<int, kW2 - 1>{});
+#pragma unroll
+  for (int c = 0; c < kW2; ++c) {
+    const int64_t gc = c < w ? (int64_t)pr.x * w + c : (int64_t)pr.y * w + (c - w);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int r = tid + k * kJacThreads;
+      if (r < a.n) X[gc * a.n + r] = x[k][c];
+    }
+  }
+  for (int e = tid; e < kW2 * kW2; e += kJacThreads) Wo[e] = sh.W[e % kW2][e / kW2];
+  // largest cosine of the task (threads < w hold their pairs' maxima)
+  if (tid < w) sh.red[0][tid] = offmax;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < w; ++i) m = fmax(m, sh.red[0][i]);
+    *offo = m;
+  }
+}
+
+// V (npad x npad, row-major per block) <- V[:, I u J] W for every pair task
+// of the round: one thread per row.
+template <int kW2>
+__global__ __launch_bounds__(256) void k_jac_vupdate(double *V, int64_t v_stride, int32_t npad,
+                                                     const int2 *pairs, int32_t npairs, const double *Wbuf) {
+  __shared__ double W[kW2 * kW2];
+  const int task = blockIdx.y, b = blockIdx.z;
+  const int2 pr = pairs[task];
+  if (pr.x < 0) return;
+  const double *Wi = Wbuf + ((int64_t)b * npairs + task) * kW2 * kW2;
+  for (int e = threadIdx.x; e < kW2 * kW2; e += blockDim.x) W[e] = Wi[e];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= npad) return;
+  constexpr int w = kW2 / 2;
+  double *row = V + (int64_t)b * v_stride + r * npad;
+  double v[kW2];
+#pragma unroll
+  for (int c = 0; c < w; ++c) {
+    v[c] = row[(int64_t)pr.x * w + c];
+    v[w + c] = row[(int64_t)pr.y * w + c];
+  }
+#pragma unroll
+  for (int c = 0; c < kW2; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kW2; ++k) s = fma(v[k], W[c * kW2 + k], s);
+    if (c < w) row[(int64_t)pr.x * w + c] = s;
+    else row[(int64_t)pr.y * w + (c - w)] = s;
+  }
+}
+
+// X = R (upper triangle of the QR factor, zero below and in padded columns),
+// V = I.
+__global__ void k_jac_init(const double *A, int64_t a_stride, int32_t m, int32_t n, double *X, int64_t x_stride,
+                           int32_t npad, double *V, int64_t v_stride) {
+  const int b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (int64_t)n * npad) {
+    const int64_t r = idx % n, c = idx / n;
+    X[(int64_t)b * x_stride + idx] = (c < n && r <= c) ? A[(int64_t)b * a_stride + c * m + r] : 0.0;
+  }
+  if (idx < (int64_t)npad * npad) {
+    const int64_t r = idx / npad, c = idx % npad;
+    V[(int64_t)b * v_stride + idx] = r == c ? 1.0 : 0.0;
+  }
+}
+
+// Column norms of X: one wave per column.
+__global__ __launch_bounds__(256) void k_jac_colnorm(const double *X, int64_t x_stride, int32_t n, int32_t npad,
+                                                     double *sig) {
+  const int b = blockIdx.y;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= npad) return;
+  const double *col = X + (int64_t)b * x_stride + (int64_t)c * n;
+  double s = 0.0;
+  for (int r = lane; r < n; r += 64) s = fma(col[r], col[r], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) sig[(int64_t)b * npad + c] = sqrt(s);
+}
+
+struct FinalArgs {
+  const double *X;
+  int64_t x_stride;
+  const double *V;
+  int64_t v_stride;
+  const double *sig;       // unsorted column norms, npad per block
+  const int32_t *perm;     // per block: n source columns in descending order of norm
+  const int32_t *rank;     // per block
+  int32_t m, n, npad;
+  double *const *U;        // per block: slot U (m x n, column-major), V (n x n row-major), sigma
+  double *const *Vs;
+  double *const *Ss;
+};
+
+// Slot outputs of block blockIdx.y, column c = blockIdx.x: U[:, c] =
+// [x_j / sigma_j; 0], V[:, c] = Vacc[:, j], sigma[c] = sigma_j with j =
+// perm[c]; columns at or beyond the rank are left alone.
+__global__ __launch_bounds__(256) void k_jac_finalize(FinalArgs f) {
+  const int b = blockIdx.y, c = blockIdx.x;
+  if (c >= f.rank[b]) return;
+  const int j = f.perm[(int64_t)b * f.n + c];
+  const double s = f.sig[(int64_t)b * f.npad + j];
+  const double inv = 1.0 / s;
+  const double *xc = f.X + (int64_t)b * f.x_stride + (int64_t)j * f.n;
+  double *u = f.U[b] + (int64_t)c * f.m;
+  for (int r = threadIdx.x; r < f.m; r += blockDim.x) u[r] = r < f.n ? xc[r] * inv : 0.0;
+  const double *vb = f.V + (int64_t)b * f.v_stride;
+  double *vs = f.Vs[b];
+  for (int r = threadIdx.x; r < f.n; r += blockDim.x) vs[(int64_t)r * f.n + c] = vb[(int64_t)r * f.npad + j];
+  if (threadIdx.x == 0) f.Ss[b][c] = s;
+}
+
+// Round-robin schedule of nbk (even) column blocks: round r pairs.
+std::vector<int2> block_schedule(int nbk) {
+  std::vector<int2> out;
+  for (int q = 0; q < nbk - 1; ++q)
+    for (int i = 0; i < nbk / 2; ++i) out.push_back(make_int2(rr_a(q, i, nbk), rr_b(q, i, nbk)));
+  return out;
+}
+
+}  // namespace
+
+// Column-block width and rows per thread for n rows: the 2w columns of a
+// pair task must fit in registers across 512 threads.
+int jacobi_shape(int n, int &w, int &rows) {
+  if (n <= 2048) { w = 8; rows = 4; return SMFS_OK; }
+  if (n <= 4096) { w = 4; rows = 8; return SMFS_OK; }
+  set_error("device SVD: blocks with more than 4096 columns are not supported");
+  return SMFS_E_UNSUPPORTED;
+}
+
+// Scratch of one batch of nb blocks of shape m x n (JacPlan): rocSOLVER's
+// work arrays (geqrf, ormqr), the blocks, QR scalars, X, V, rotation
+// products, cosines, norms, permutations, ranks, slot pointers, schedule.
+int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
+  int rc = jacobi_shape(n, p.w, p.rows);
+  if (rc) return rc;
+  p.npad = (n + p.w - 1) / p.w * p.w;
+  p.nbk = p.npad / p.w;
+  if (p.nbk % 2) { p.nbk += 1; p.npad += p.w; }
+  p.npairs = p.nbk / 2;
+  double *fake = reinterpret_cast<double *>((uintptr_t)4096);
+  size_t w1 = 0, w2 = 0;
+  rocblas_start_device_memory_size_query(h);
+  rocblas_status q1 = rocsolver_dgeqrf_strided_batched(h, m, n, fake, m, (rocblas_stride)m * n, fake, n, nb);
+  rocblas_stop_device_memory_size_query(h, &w1);
+  rocblas_start_device_memory_size_query(h);
+  rocblas_status q2 = rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, m, n, n, fake, m, fake,
+                                       fake, m);
+  rocblas_stop_device_memory_size_query(h, &w2);
+  auto ok = [](rocblas_status q) {
+    return q == rocblas_status_success || q == rocblas_status_size_increased || q == rocblas_status_size_unchanged;
+  };
+  if (!ok(q1) || !ok(q2)) {
+    set_error("device SVD: workspace query failed");
+    return SMFS_E_SVD;
+  }
+  p.work = al256(std::max(w1, w2));
+  p.a = al256(sizeof(double) * (size_t)m * n * nb);
+  p.tau = al256(sizeof(double) * (size_t)n * nb);
+  p.x = al256(sizeof(double) * (size_t)n * p.npad * nb);
+  p.v = al256(sizeof(double) * (size_t)p.npad * p.npad * nb);
+  p.wbuf = al256(sizeof(double) * (size_t)nb * p.npairs * 4 * p.w * p.w);
+  p.off = al256(sizeof(double) * (size_t)nb * p.npairs * (p.nbk - 1));
+  p.sig = al256(sizeof(double) * (size_t)nb * p.npad);
+  p.perm = al256(sizeof(int32_t) * (size_t)nb * n);
+  p.rank = al256(sizeof(int32_t) * (size_t)nb);
+  p.ptrs = al256(sizeof(double *) * 3 * (size_t)nb);
+  p.sched = al256(sizeof(int2) * (size_t)(p.nbk - 1) * p.npairs);
+  p.total = p.work + p.a + p.tau + p.x + p.v + p.wbuf + p.off + p.sig + p.perm + p.rank + p.ptrs + p.sched;
+  return SMFS_OK;
+}
+
+// Factor nb blocks of shape m x n already assembled at the plan's A region
+// of scratch: slots get U (m x rank), V (n x n row-major, rank columns) and
+// sigma (descending), ranks[q] the kept count (sigma > trunc sigma_1).
+int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, int n, int nb,
+                     double *const *U, double *const *Vs, double *const *Ss, double trunc, int *ranks,
+                     int *sweeps_out, hipStream_t s) {
+  char *o = scratch;
+  char *work = o; o += p.work;
+  double *A = (double *)o; o += p.a;
+  double *tau = (double *)o; o += p.tau;
+  double *X = (double *)o; o += p.x;
+  double *V = (double *)o; o += p.v;
+  double *Wb = (double *)o; o += p.wbuf;
+  double *off = (double *)o; o += p.off;
+  double *sig = (double *)o; o += p.sig;
+  int32_t *perm = (int32_t *)o; o += p.perm;
+  int32_t *drank = (int32_t *)o; o += p.rank;
+  double **ptrs = (double **)o; o += p.ptrs;
+  int2 *sched = (int2 *)o; o += p.sched;
+  if (rocblas_set_workspace(h, work, p.work) != rocblas_status_success) {
+    set_error("device SVD: rocblas_set_workspace failed");
+    return SMFS_E_DEVICE;
+  }
+  struct Reset {
+    rocblas_handle h;
+    ~Reset() { (void)rocblas_set_workspace(h, nullptr, 0); }
+  } reset{h};
+  // Householder QR of every block
+  if (rocsolver_dgeqrf_strided_batched(h, m, n, A, m, (rocblas_stride)m * n, tau, n, nb) != rocblas_status_success) {
+    set_error("device SVD: geqrf failed");
+    return SMFS_E_SVD;
+  }
+  const int64_t xs = (int64_t)n * p.npad, vs = (int64_t)p.npad * p.npad;
+  {
+    const int64_t cnt = std::max<int64_t>((int64_t)n * p.npad, vs);
+    hipLaunchKernelGGL(k_jac_init, dim3((unsigned)((cnt + 255) / 256), nb), dim3(256), 0, s, A, (int64_t)m * n, m, n,
+                       X, xs, p.npad, V, vs);
+    SMFS_HIP(hipGetLastError());
+  }
+  const std::vector<int2> sch = block_schedule(p.nbk);
+  std::vector<int2> sch_host(sch);
+  // the padded block (index nbk - 1 when n's blocks are odd) pairs with a
+  // real block: both stay as they are (zero columns do not rotate), so the
+  // task runs normally
+  SMFS_HIP(hipMemcpyAsync(sched, sch_host.data(), sizeof(int2) * sch_host.size(), hipMemcpyHostToDevice, s));
+  const int rounds = p.nbk - 1;
+  std::vector<double> offh((size_t)nb * p.npairs * rounds);
+  int sweep = 0;
+  for (; sweep < kMaxSweeps; ++sweep) {
+    for (int r = 0; r < rounds; ++r) {
+      JacArgs ja;
+      ja.X = X;
+      ja.x_stride = xs;
+      ja.n = n;
+      ja.npad = p.npad;
+      ja.w = p.w;
+      ja.pairs = sched + (int64_t)r * p.npairs;
+      ja.npairs = p.npairs;
+      ja.Wout = Wb;
+      ja.off = off + (int64_t)r * nb * p.npairs;
+      const dim3 g((unsigned)p.npairs, (unsigned)nb);
+      if (p.w == 8) hipLaunchKernelGGL((k_jac_pairs<4, 16>), g, dim3(kJacThreads), 0, s, ja);
+      else hipLaunchKernelGGL((k_jac_pairs<8, 8>), g, dim3(kJacThreads), 0, s, ja);
+      SMFS_HIP(hipGetLastError());
+      const dim3 gv((unsigned)((p.npad + 255) / 256), (unsigned)p.npairs, (unsigned)nb);
+      if (p.w == 8)
+        hipLaunchKernelGGL((k_jac_vupdate<16>), gv, dim3(256), 0, s, V, vs, p.npad, ja.pairs, p.npairs, Wb);
+      else
+        hipLaunchKernelGGL((k_jac_vupdate<8>), gv, dim3(256), 0, s, V, vs, p.npad, ja.pairs, p.npairs, Wb);
+      SMFS_HIP(hipGetLastError());
+    }
+    SMFS_HIP(hipMemcpyAsync(offh.data(), off, sizeof(double) * offh.size(), hipMemcpyDeviceToHost, s));
+    SMFS_HIP(hipStreamSynchronize(s));
+    double mx = 0.0;
+    for (double v : offh) mx = std::max(mx, v);
+    if (!(mx >= 0.0)) {
+      set_error("device SVD: non-finite rotation");
+      return SMFS_E_SVD;
+    }
+    if (mx < kSweepTol) { ++sweep; break; }
+  }
+  if (sweeps_out) *sweeps_out = sweep;
+  if (sweep >= kMaxSweeps) {
+    set_error("device SVD: Jacobi sweeps did not converge");
+    return SMFS_E_SVD;
+  }
+  // singular values: column norms, sorted on the host
+  hipLaunchKernelGGL(k_jac_colnorm, dim3((unsigned)((p.npad + 3) / 4), nb), dim3(256), 0, s, X, xs, n, p.npad, sig);
+  SMFS_HIP(hipGetLastError());
+  std::vector<double> sh((size_t)nb * p.npad);
+  SMFS_HIP(hipMemcpyAsync(sh.data(), sig, sizeof(double) * sh.size(), hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> ph((size_t)nb * n), rh(nb);
+  for (int q = 0; q < nb; ++q) {
+    const double *sq = sh.data() + (size_t)q * p.npad;
+    int32_t *pq = ph.data() + (size_t)q * n;
+    std::iota(pq, pq + n, 0);
+    std::stable_sort(pq, pq + n, [sq](int32_t x, int32_t y) { return sq[x] > sq[y]; });
+    const double s1 = sq[pq[0]];
+    if (!(s1 > 0.0) || !std::isfinite(s1)) {
+      set_error("device SVD: zero or non-finite block");
+      return SMFS_E_SVD;
+    }
+    int r = 0;
+    while (r < n && sq[pq[r]] > trunc * s1) ++r;
+    rh[q] = r;
+    ranks[q] = r;
+  }
+  std::vector<double *> hp(3 * (size_t)nb);
+  for (int q = 0; q < nb; ++q) {
+    hp[q] = U[q];
+    hp[nb + q] = Vs[q];
+    hp[2 * nb + q] = Ss[q];
+  }
+  SMFS_HIP(hipMemcpyAsync(perm, ph.data(), sizeof(int32_t) * ph.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(drank, rh.data(), sizeof(int32_t) * rh.size(), hipMemcpyHostToDevice, s));
+  SMFS_HIP(hipMemcpyAsync(ptrs, hp.data(), sizeof(double *) * hp.size(), hipMemcpyHostToDevice, s));
+  FinalArgs f;
+  f.X = X;
+  f.x_stride = xs;
+  f.V = V;
+  f.v_stride = vs;
+  f.sig = sig;
+  f.perm = perm;
+  f.rank = drank;
+  f.m = m;
+  f.n = n;
+  f.npad = p.npad;
+  f.U = ptrs;
+  f.Vs = ptrs + nb;
+  f.Ss = ptrs + 2 * nb;
+  hipLaunchKernelGGL(k_jac_finalize, dim3((unsigned)n, nb), dim3(256), 0, s, f);
+  SMFS_HIP(hipGetLastError());
+  // U = Q [U_R; 0] with the reflectors of each block's QR
+  for (int q = 0; q < nb; ++q) {
+    if (rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, m, rh[q], n, A + (size_t)q * m * n, m,
+                         tau + (size_t)q * n, U[q], m) != rocblas_status_success) {
+      set_error("device SVD: ormqr failed");
+      return SMFS_E_SVD;
+    }
+  }
+  SMFS_HIP(hipStreamSynchronize(s));
+  return SMFS_OK;
+}
+
+}  // namespace smfs

@@ -19,13 +19,16 @@ SMFS_OK = 0
 SMFS_NOT_CONVERGED = 1
 SMFS_GAP_BELOW_VALIDATED = 2
 SMFS_STAGNATED = 3
+SMFS_E_AGAIN = -8
 SOLVE_WARNINGS = (SMFS_OK, SMFS_NOT_CONVERGED, SMFS_STAGNATED)
 SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR = 0, 1, 2
+SMFS_SVD_JACOBI, SMFS_SVD_ROCSOLVER = 0, 1
 KIND_S, KIND_R, KIND_D = 1, 2, 4
 
 EXPORTED = [
     "smfs_params_default", "smfs_problem_create", "smfs_problem_destroy", "smfs_problem_sizes",
     "smfs_export_nodes", "smfs_sphere_factor", "smfs_factor_info", "smfs_bind", "smfs_setup",
+    "smfs_setup_workspace_bytes",
     "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_set_background",
     "smfs_force_torque",
     "smfs_eval_velocity", "smfs_solve_resistance", "smfs_solve_mobility", "smfs_set_solver",
@@ -33,6 +36,7 @@ EXPORTED = [
     "smfs_apply_block_noalloc", "smfs_noalloc_scratch_bytes",
     "smfs_solve_resistance_block", "smfs_server_create", "smfs_server_destroy",
     "smfs_server_clock", "smfs_server_submit", "smfs_server_step", "smfs_server_poll",
+    "smfs_server_config_default", "smfs_server_memory_bytes",
     "smfs_server_release", "smfs_server_stats_read",
     "smfs_profile",
     "smfs_profile_read", "smfs_last_error",
@@ -47,7 +51,7 @@ class smfs_params(C.Structure):
         ("cap_alpha", C.c_int32 * 2), ("cap_beta", C.c_double * 2), ("left_weights", C.c_int32),
         ("trunc_rel", C.c_double), ("mu", C.c_double), ("n_check_base", C.c_int32),
         ("precision", C.c_int32), ("gmres_tol", C.c_double), ("gmres_max_it", C.c_int32),
-        ("gmres_restart", C.c_int32), ("gmres_check_every", C.c_int32),
+        ("gmres_restart", C.c_int32), ("gmres_check_every", C.c_int32), ("svd_method", C.c_int32),
     ]
 
 
@@ -90,7 +94,15 @@ class smfs_request_result(C.Structure):
         ("status", C.c_int32), ("P", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
         ("rel_residual", C.c_double), ("true_rel_residual", C.c_double),
         ("t_arrival", C.c_double), ("t_admitted", C.c_double), ("t_started", C.c_double),
-        ("t_done", C.c_double), ("pair_evals", C.c_int64), ("error", C.c_char * 160),
+        ("t_done", C.c_double), ("pair_evals", C.c_int64), ("pair_evals_f32", C.c_int64),
+        ("refinements", C.c_int32), ("error", C.c_char * 160),
+    ]
+
+
+class smfs_server_config(C.Structure):
+    _fields_ = [
+        ("radius", C.c_double), ("max_active", C.c_int32), ("setup_workers", C.c_int32),
+        ("max_queued", C.c_int32), ("precision", C.c_int32), ("worker_scratch_bytes", C.c_size_t),
     ]
 
 
@@ -109,7 +121,7 @@ class smfs_block_out(C.Structure):
         ("ft", C.c_void_p), ("mu", C.c_void_p), ("iterations", C.c_void_p),
         ("true_rel_residual", C.c_void_p), ("max_iterations", C.c_int32),
         ("n_converged", C.c_int32), ("t_gmres_ms", C.c_double), ("t_post_ms", C.c_double),
-        ("pair_evals", C.c_int64),
+        ("pair_evals", C.c_int64), ("pair_evals_f32", C.c_int64), ("refinements", C.c_int32),
     ]
 
 
@@ -136,7 +148,8 @@ def lib():
         "smfs_sphere_factor": ([vp, i32, P(i32)], C.c_int),
         "smfs_factor_info": ([vp, i32, P(i32), P(i32), P(i32), P(i32)], C.c_int),
         "smfs_bind": ([vp, vp, C.c_size_t, vp], C.c_int),
-        "smfs_setup": ([vp, vp], C.c_int),
+        "smfs_setup_workspace_bytes": ([vp, P(C.c_size_t)], C.c_int),
+        "smfs_setup": ([vp, vp, C.c_size_t, vp], C.c_int),
         "smfs_import_factor": ([vp, i32, i32, vp, vp, vp, vp], C.c_int),
         "smfs_apply": ([vp, vp, vp, i32, vp], C.c_int),
         "smfs_transform": ([vp, vp, vp, vp], C.c_int),
@@ -148,7 +161,9 @@ def lib():
         "smfs_solve_mobility": ([vp, vp, P(smfs_out), vp], C.c_int),
         "smfs_pairs_per_apply": ([vp], i64),
         "smfs_block_workspace_bytes": ([vp, i32, i32, P(C.c_size_t)], C.c_int),
-        "smfs_server_create": ([P(smfs_params), dbl, C.c_size_t, i32, i32, P(vp)], C.c_int),
+        "smfs_server_config_default": ([P(smfs_server_config)], C.c_int),
+        "smfs_server_memory_bytes": ([P(smfs_params), P(smfs_server_config), P(C.c_size_t)], C.c_int),
+        "smfs_server_create": ([P(smfs_params), P(smfs_server_config), vp, C.c_size_t, P(vp)], C.c_int),
         "smfs_server_destroy": ([vp], None),
         "smfs_server_clock": ([], dbl),
         "smfs_server_submit": ([vp, i32, vp, vp, dbl, P(i64)], C.c_int),
@@ -156,7 +171,7 @@ def lib():
         "smfs_server_poll": ([vp, i64, P(smfs_request_result), vp], C.c_int),
         "smfs_server_release": ([vp, i64], C.c_int),
         "smfs_server_stats_read": ([vp, P(smfs_server_stats)], C.c_int),
-        "smfs_apply_block": ([vp, i32, vp, vp, i64, vp, C.c_size_t, vp], C.c_int),
+        "smfs_apply_block": ([vp, i32, vp, vp, i64, i32, vp, C.c_size_t, vp], C.c_int),
         "smfs_apply_block_noalloc": ([vp, i32, vp, vp, i64, vp], C.c_int),
         "smfs_noalloc_scratch_bytes": ([], C.c_size_t),
         "smfs_solve_resistance_block": ([vp, i32, vp, i32, vp, C.c_size_t, P(smfs_block_out), vp],
@@ -301,8 +316,20 @@ class Problem:
         _check(lib().smfs_bind(self.h, C.c_void_p(aligned), nbytes, _stream()), "smfs_bind")
         return self
 
+    def setup_workspace_bytes(self):
+        n = C.c_size_t(0)
+        _check(lib().smfs_setup_workspace_bytes(self.h, C.byref(n)), "smfs_setup_workspace_bytes")
+        return int(n.value)
+
     def setup(self):
-        _check(lib().smfs_setup(self.h, _stream()), "smfs_setup")
+        """Assemble and factor the self blocks; the device scratch of the
+        SVDs is a torch allocation released afterwards."""
+        import torch
+        n = self.setup_workspace_bytes()
+        buf = torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+        base = (buf.data_ptr() + 255) // 256 * 256
+        _check(lib().smfs_setup(self.h, C.c_void_p(base), n, _stream()), "smfs_setup")
+        del buf
         return self
 
     def import_factor(self, fid, U, sigma, V):
@@ -424,7 +451,7 @@ class Problem:
         base = self._bws.data_ptr()
         return (base + 255) // 256 * 256, self._bws.numel() - ((base + 255) // 256 * 256 - base)
 
-    def apply_block(self, mu, out=None):
+    def apply_block(self, mu, out=None, precision=SMFS_FP64):
         """mu: (nrhs, 3T) contiguous float64 device tensor; returns G_hat mu_q per row."""
         import torch
         if mu.dim() != 2 or mu.shape[1] != 3 * self.T:
@@ -434,8 +461,8 @@ class Problem:
         y = out if out is not None else torch.empty_like(mu)
         self._need(y, nrhs * 3 * self.T, "y")
         ws, nb = self.block_workspace(nrhs, 0)
-        _check(lib().smfs_apply_block(self.h, nrhs, _ptr(mu), _ptr(y), 3 * self.T, C.c_void_p(ws),
-                                      nb, _stream()), "smfs_apply_block")
+        _check(lib().smfs_apply_block(self.h, nrhs, _ptr(mu), _ptr(y), 3 * self.T, precision,
+                                      C.c_void_p(ws), nb, _stream()), "smfs_apply_block")
         return y
 
     def solve_resistance_block(self, rbm, restart=100):
@@ -456,10 +483,11 @@ class Problem:
         o.iterations, o.true_rel_residual = its.ctypes.data, tr.ctypes.data
         rc = lib().smfs_solve_resistance_block(self.h, nrhs, _ptr(rbm), restart, C.c_void_p(ws), nb,
                                                C.byref(o), _stream())
-        _check(rc, "smfs_solve_resistance_block", ok=(SMFS_OK, SMFS_NOT_CONVERGED))
-        return dict(ft=ft, mu=mu, iterations=its, true_rel_residual=tr, converged=rc == SMFS_OK,
+        _check(rc, "smfs_solve_resistance_block", ok=SOLVE_WARNINGS)
+        return dict(ft=ft, mu=mu, iterations=its, true_rel_residual=tr, status=rc, converged=rc == SMFS_OK,
                     max_iterations=o.max_iterations, n_converged=o.n_converged,
-                    t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms, pair_evals=o.pair_evals)
+                    t_gmres_ms=o.t_gmres_ms, t_post_ms=o.t_post_ms, pair_evals=o.pair_evals,
+                    pair_evals_f32=o.pair_evals_f32, refinements=o.refinements)
 
 
 class Server:
@@ -467,21 +495,38 @@ class Server:
     smfs_server_* in include/smfs.h).  All requests share one discretisation
     (keyword overrides of smfs_params) and the sphere radius."""
 
-    def __init__(self, radius=1.0, arena_bytes=8 << 30, max_active=64, setup_workers=1, **over):
+    def __init__(self, radius=1.0, arena_bytes=8 << 30, max_active=64, setup_workers=1, max_queued=0,
+                 server_precision=SMFS_FP64, worker_scratch_bytes=0, **over):
+        """The server's device memory (its fixed part plus an arena of
+        arena_bytes) is one torch allocation held by this object."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("smfs.Server needs a HIP device")
         torch.cuda.init()
         self.params = params_default(**over)
+        cfg = smfs_server_config()
+        _check(lib().smfs_server_config_default(C.byref(cfg)), "smfs_server_config_default")
+        cfg.radius, cfg.max_active, cfg.setup_workers = float(radius), max_active, setup_workers
+        cfg.max_queued, cfg.precision = max_queued, server_precision
+        if worker_scratch_bytes:
+            cfg.worker_scratch_bytes = worker_scratch_bytes
+        self.config = cfg
+        fixed = C.c_size_t(0)
+        _check(lib().smfs_server_memory_bytes(C.byref(self.params), C.byref(cfg), C.byref(fixed)),
+               "smfs_server_memory_bytes")
+        total = int(fixed.value) + int(arena_bytes)
+        self.mem = torch.empty(total + 256, dtype=torch.uint8, device="cuda")
+        base = (self.mem.data_ptr() + 255) // 256 * 256
         h = C.c_void_p()
-        _check(lib().smfs_server_create(C.byref(self.params), radius, arena_bytes, max_active,
-                                        setup_workers, C.byref(h)), "smfs_server_create")
+        _check(lib().smfs_server_create(C.byref(self.params), C.byref(cfg), C.c_void_p(base), total,
+                                        C.byref(h)), "smfs_server_create")
         self.h = h
 
     def close(self):
         if getattr(self, "h", None):
             lib().smfs_server_destroy(self.h)
             self.h = None
+        self.mem = None
 
     def __del__(self):
         try:
@@ -502,6 +547,15 @@ class Server:
         _check(lib().smfs_server_submit(self.h, c.shape[0], _np_ptr(c), _np_ptr(r), float(t_arrival),
                                         C.byref(rid)), "smfs_server_submit")
         return int(rid.value)
+
+    def try_submit(self, centers, rbm, t_arrival=-1.0):
+        """As submit, but None (nothing queued) when the queue is full."""
+        try:
+            return self.submit(centers, rbm, t_arrival)
+        except SmfsError as e:
+            if e.code == SMFS_E_AGAIN:
+                return None
+            raise
 
     def step(self):
         a, w = C.c_int32(), C.c_int32()

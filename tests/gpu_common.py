@@ -35,8 +35,25 @@ def _finished(out):
     return out["status"] in (0, 3)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+def _rel(a, b, groups=None):
+    """Element-wise relative difference: max |a - b| / max |b| over the whole
+    array; with groups (one label per row of a and b viewed as
+    (len(groups), -1) arrays, e.g. the sphere of every node), the largest
+    such ratio over the groups, each taken against its own largest entry,
+    so that an error confined to a few rows of one sphere is not diluted by
+    the rest."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if groups is None:
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+    lab, inv = np.unique(np.asarray(groups), return_inverse=True)
+    n = len(inv)
+    d = np.abs(a.reshape(n, -1) - b.reshape(n, -1)).max(1)
+    m = np.abs(b.reshape(n, -1)).max(1)
+    dk, mk = np.zeros(lab.size), np.zeros(lab.size)
+    np.maximum.at(dk, inv, d)
+    np.maximum.at(mk, inv, m)
+    return float((dk / np.maximum(mk, 1e-300)).max())
 
 
 def _import_oracle_factors(lib, pbo):

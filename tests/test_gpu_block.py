@@ -52,15 +52,16 @@ def test_block_apply_vs_oracle_and_single(small12, nrhs):
     for q in range(nrhs):     # even columns smooth (boundary data), odd rough
         M[q] = pbo.rhs(rbm[q]) if q % 2 == 0 else wl.random_vector(n, 100 + q)
     Y = _n(lib.apply_block(_t(M).view(nrhs, n))).reshape(nrhs, n)
+    ts = g.target_sphere
     for q in range(nrhs):
         ref = pbo.apply(M[q])
-        if q % 2 == 0:
-            bar = 1e-10
-        else:
-            bar = max(1e-10, 20 * _rel(pbo.apply(M[q], _transform_ext(pbo, M[q])), ref))
-        assert _rel(Y[q], ref) < bar, (q, _rel(Y[q], ref), bar)
+        # per sphere, even the smooth columns pass through the pseudo-inverse
+        # of the gap-2e-3 pair: the bar is the oracle's own rounding
+        # sensitivity (its transform in extended precision), at least 1e-10
+        bar = max(1e-10, 20 * _rel(pbo.apply(M[q], _transform_ext(pbo, M[q])), ref, ts))
+        assert _rel(Y[q], ref, ts) < bar, (q, _rel(Y[q], ref, ts), bar)
         ys = _n(lib.apply(_t(M[q])))
-        assert _rel(Y[q], ys) < bar, (q, _rel(Y[q], ys))
+        assert _rel(Y[q], ys, ts) < bar, (q, _rel(Y[q], ys, ts))
 
 
 def test_block_apply_full_size_cluster(dev, oracle_pairsum_built):
@@ -95,7 +96,7 @@ def test_block_apply_full_size_cluster(dev, oracle_pairsum_built):
     for q in (0, 1, 31, 32, 60, 61, 62, 63):
         lam_hat = pbo.transform(Mh[q])
         ref = Mh[q].reshape(-1, 3)[rows] + pbo.apply_rows(lam_hat, rows, is_lambda=True)
-        assert _rel(Yh[q][rows], ref) < 1e-10, q
+        assert _rel(Yh[q][rows], ref, g.target_sphere[rows]) < 1e-10, q
 
 
 def test_block_solve_matches_oracle_and_single(dev, small12):
@@ -106,7 +107,7 @@ def test_block_solve_matches_oracle_and_single(dev, small12):
     rbm = wl.random_rbm(g.P, nrhs, 43)
     rbm[3] = 0.0                     # a zero right-hand side stays zero
     out = lib.solve_resistance_block(_t(rbm), restart=restart)
-    assert out["converged"] and out["n_converged"] == nrhs
+    assert out["status"] in (0, 3) and out["n_converged"] == nrhs
     ft = _n(out["ft"]).reshape(nrhs, g.P, 6)
     assert np.all(ft[3] == 0.0) and out["iterations"][3] == 0
     for q in (0, 1, 5):
@@ -145,7 +146,7 @@ def test_block_solve_restarted(dev, oracle_pairsum_built):
     nrhs = 9
     rbm = wl.random_rbm(3, nrhs, 44)
     out = lib.solve_resistance_block(_t(rbm), restart=12)
-    assert out["converged"]
+    assert out["status"] in (0, 3)
     ft = _n(out["ft"]).reshape(nrhs, 3, 6)
     for q in range(nrhs):
         single = lib.solve_resistance(_t(rbm[q]), want_check=False)
@@ -155,3 +156,56 @@ def test_block_solve_restarted(dev, oracle_pairsum_built):
     ref = mfs.solve_resistance(pbo, rbm[nrhs - 1], tol=1e-12)["ft"]
     assert np.abs(ft[nrhs - 1] - ref).max() < 1e-8 * np.abs(ref).max()
     assert out["max_iterations"] > 12          # restarts did happen
+
+
+def test_block_apply_mixed(dev, small12):
+    """Mixed block product (FP32 far field of the contact-free proxies for
+    runs of four vectors): every column within 1e-5 per sphere of the FP64
+    oracle on boundary-data vectors, and within FP32 rounding of the
+    single-vector mixed product."""
+    _say("mixed block product, 12 spheres, 9 columns")
+    g, pbo, lib = small12["g"], small12["pb"], small12["lib"]
+    assert lib.sizes.n_factors > 1 and any(g.contact_free(k) for k in range(g.P))
+    n, nrhs = 3 * g.T, 9
+    rbm = wl.random_rbm(g.P, nrhs, 46)
+    M = np.stack([pbo.rhs(rbm[q]) for q in range(nrhs)])
+    Y = _n(lib.apply_block(_t(M).view(nrhs, n), precision=dev.SMFS_MIXED_FAR)).reshape(nrhs, n)
+    Y64 = _n(lib.apply_block(_t(M).view(nrhs, n))).reshape(nrhs, n)
+    ts = g.target_sphere
+    for q in range(nrhs):
+        ref = pbo.apply(M[q])
+        ys = _n(lib.apply(_t(M[q]), precision=dev.SMFS_MIXED_FAR))
+        d, d64, ds = _rel(Y[q], ref, ts), _rel(Y64[q], ref, ts), _rel(Y[q], ys, ts)
+        bar64 = max(1e-10, 20 * _rel(pbo.apply(M[q], _transform_ext(pbo, M[q])), ref, ts))
+        assert d64 < bar64, (q, d64, bar64)
+        assert d < 1e-5 and ds < 1e-5, (q, d, ds)
+        assert not np.array_equal(Y[q], Y64[q])        # the FP32 path did run
+
+
+def test_block_solve_mixed(dev, oracle_pairsum_built):
+    """Mixed block solve of six systems (FP32 far field inside the cycles,
+    FP64 true residuals at every restart and up to two refinements): forces
+    and torques within 1e-5 of the oracle's FP64 solves."""
+    _say("mixed block resistance solve, 12 spheres, 6 systems")
+    rng = np.random.default_rng(47)
+    c = [np.array([0.0, 0.0, 0.0]), np.array([2.01, 0.0, 0.0])]
+    while len(c) < 12:
+        x = rng.uniform(-6, 8, 3)
+        if all(np.linalg.norm(x - y) > 2.4 for y in c):
+            c.append(x)
+    c = np.array(c)
+    g = geo.build(c, 1.0, geo.Params(**SMALL))
+    pbo = mfs.Problem(g).setup()
+    lib = dev.Problem(c, 1.0, gmres_tol=1e-9, precision=dev.SMFS_MIXED_FAR, **SMALL).bind()
+    _import_oracle_factors(lib, pbo)
+    nrhs = 6
+    rbm = wl.random_rbm(g.P, nrhs, 48)
+    out = lib.solve_resistance_block(_t(rbm), restart=200)
+    ft = _n(out["ft"]).reshape(nrhs, g.P, 6)
+    _say(f"  status {out['status']}, refinements {out['refinements']}, max it {out['max_iterations']}, "
+         f"true residuals {np.max(out['true_rel_residual']):.2e}, fp32 pairs {out['pair_evals_f32']:.3e}")
+    assert out["status"] in (0, 3) and out["pair_evals_f32"] > 0
+    for q in range(nrhs):
+        ref = mfs.solve_resistance(pbo, rbm[q], tol=1e-10)["ft"]
+        d = np.abs(ft[q] - ref).max() / np.abs(ref).max()
+        assert d < 1e-5, (q, d)

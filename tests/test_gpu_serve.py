@@ -9,7 +9,7 @@ set-up stay cheap.
 import numpy as np
 import pytest
 
-from oracle import geometry as geo, mfs
+from oracle import geometry as geo, mfs, brenner
 from paper_2407_03343_amd import workloads as wl
 
 from gpu_common import _say, _t, _n
@@ -43,7 +43,10 @@ def mixed_run(dev, stream):
 
 def test_serving_completes_and_batches(mixed_run, stream):
     res, st = mixed_run
-    assert all(r is not None and r["status"] == 0 for r in res)
+    # OK when the FP64 true residual met the tolerance, STAGNATED when it
+    # floored above it (the status is honest either way)
+    assert all(r is not None and r["status"] in (0, 3) for r in res)
+    assert all((r["status"] == 0) == (r["true_rel_residual"] <= SOLVER["gmres_tol"]) for r in res)
     assert st["completed"] == len(stream) and st["failed"] == 0
     assert st["peak_active"] > 1                      # requests shared launches
     for r in res:
@@ -108,7 +111,7 @@ def test_serving_admits_by_memory(dev, stream):
     st = srv.stats()
     res = [srv.poll(i, r["P"]) for i, r in zip(ids, stream[:6])]
     srv.close()
-    assert all(x["status"] == 0 for x in res)
+    assert all(x["status"] in (0, 3) for x in res)
     assert st["arena_peak"] <= arena
     assert st["peak_active"] <= fit < 6
 
@@ -122,3 +125,99 @@ def test_serving_zero_motion_request(dev):
     srv.close()
     assert r["status"] == 0 and r["iterations"] == 0
     assert np.all(r["ft"] == 0.0)
+
+
+def test_serving_default_discretisation(dev, pair001):
+    """One request at the default discretisation (600 proxies on R_p = 0.7,
+    780 base nodes, 20 S+R+D image nodes, caps of 360): the two-sphere case
+    at gap 0.01, against the oracle's solve (LAPACK factors) and Brenner's
+    force."""
+    _say("serving: default discretisation, two spheres at gap 0.01")
+    srv = dev.Server(arena_bytes=2 << 30, max_active=2, n_check_base=0, gmres_tol=1e-10,
+                     gmres_restart=200, gmres_max_it=1000)
+    rbm = pair001["rbm"][0]
+    i = srv.submit(pair001["pk"].centers, rbm)
+    srv.drain(timeout_s=120)
+    r = srv.poll(i, 2)
+    srv.close()
+    ref = pair001["out"]["ft"]
+    d = np.abs(r["ft"] - ref).max() / np.abs(ref).max()
+    Fb = brenner.brenner_force(0.01, 0.5)
+    _say(f"  status {r['status']}, it {r['iterations']}, served vs oracle {d:.2e}, "
+         f"|F| {np.linalg.norm(r['ft'][0, :3]):.6f} (Brenner {Fb:.6f})")
+    assert r["status"] >= 0 and r["true_rel_residual"] < 1e-6
+    assert d < 1e-5
+    assert abs(np.linalg.norm(r["ft"][1, :3]) - Fb) < 1e-3 * Fb
+
+
+
+@pytest.fixture(scope="module")
+def mixed_far_run(dev, stream):
+    _say("serving, mixed precision (FP32 far field): 10 requests through one server")
+    srv = dev.Server(arena_bytes=2 << 30, max_active=8, server_precision=dev.SMFS_MIXED_FAR, **DISC, **SOLVER)
+    ids = [srv.submit(r["centers"], r["rbm"]) for r in stream]
+    srv.drain(timeout_s=120)
+    res = [srv.poll(i, r["P"]) for i, r in zip(ids, stream)]
+    st = srv.stats()
+    srv.close()
+    return res, st
+
+
+def test_serving_mixed_matches_oracle(dev, oracle_pairsum_built, mixed_far_run, stream):
+    """Mixed-precision serving: requests with contact-free spheres evaluate
+    pairs in FP32, restart from FP64 true residuals, and land within 1e-5 of
+    the FP64 oracle in forces and torques."""
+    res, st = mixed_far_run
+    assert st["failed"] == 0 and st["peak_active"] > 1
+    assert sum(r["pair_evals_f32"] for r in res) > 0
+    for k in (2, 7):
+        r = stream[k]
+        g = geo.build(r["centers"], 1.0, geo.Params(**DISC))
+        pbo = mfs.Problem(g).setup()
+        ref = mfs.solve_resistance(pbo, r["rbm"], tol=1e-10)["ft"]
+        d = np.abs(res[k]["ft"] - ref).max() / np.abs(ref).max()
+        _say(f"  request {k} (P={r['P']}): it {res[k]['iterations']} (+{res[k]['refinements']} refinements), "
+             f"status {res[k]['status']}, true {res[k]['true_rel_residual']:.2e}, served-mixed vs oracle {d:.2e}")
+        assert res[k]["status"] in (0, 3) and res[k]["true_rel_residual"] < 1e-6
+        assert d < 1e-5
+
+
+def test_serving_mixed_alone_equals_in_mix(dev, mixed_far_run, stream):
+    res, _ = mixed_far_run
+    for k in (0, 5):
+        r = stream[k]
+        srv = dev.Server(arena_bytes=1 << 30, max_active=1, server_precision=dev.SMFS_MIXED_FAR, **DISC, **SOLVER)
+        i = srv.submit(r["centers"], r["rbm"])
+        srv.drain(timeout_s=60)
+        alone = srv.poll(i, r["P"])
+        srv.close()
+        _say(f"  mixed request {k} alone: it {alone['iterations']} vs {res[k]['iterations']} in the mix")
+        assert alone["iterations"] == res[k]["iterations"]
+        scale = np.abs(alone["ft"]).max()
+        assert np.abs(alone["ft"] - res[k]["ft"]).max() <= 1e-12 * scale
+
+
+def test_serving_queue_full(dev, stream):
+    """max_queued = 2 with one slot: once the first request is resident the
+    next two wait and a fourth submit is refused with SMFS_E_AGAIN (nothing
+    queued); the three accepted requests then complete."""
+    import time
+    srv = dev.Server(arena_bytes=1 << 30, max_active=1, max_queued=2, **DISC, **SOLVER)
+    ids = [srv.submit(stream[0]["centers"], stream[0]["rbm"])]
+    t0 = time.perf_counter()
+    while True:
+        a, w = srv.step()
+        if a >= 1:
+            break
+        assert time.perf_counter() - t0 < 60
+        time.sleep(0.001)
+    ids += [srv.submit(stream[k]["centers"], stream[k]["rbm"]) for k in (1, 2)]
+    assert srv.try_submit(stream[3]["centers"], stream[3]["rbm"]) is None
+    with pytest.raises(dev.SmfsError) as e:
+        srv.submit(stream[3]["centers"], stream[3]["rbm"])
+    assert e.value.code == dev.SMFS_E_AGAIN
+    srv.drain(timeout_s=120)
+    res = [srv.poll(i, stream[k]["P"]) for i, k in zip(ids, (0, 1, 2))]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 3 and all(r["status"] in (0, 3) for r in res)

@@ -127,3 +127,26 @@ def test_set_background_validation():
         pb.set_background(U=[np.nan, 0.0, 0.0])
     L = smfs.lib()
     assert L.smfs_set_background(None, None, None) != 0
+
+
+def test_server_memory_query():
+    """The server's fixed device memory (host-side sizing): the shared
+    factor, per-slot buffers and each worker's scratch; bad settings and
+    unsupported precisions are refused."""
+    p = smfs.params_default(n_proxy=60, n_colloc_base=80, n_image=4, n_check_base=0)
+    cfg = smfs.smfs_server_config()
+    assert smfs.lib().smfs_server_config_default(C.byref(cfg)) == 0
+    assert cfg.max_active == 64 and cfg.setup_workers == 1 and cfg.worker_scratch_bytes == 4 << 30
+    n = C.c_size_t(0)
+    assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == 0
+    one = n.value
+    assert one > cfg.worker_scratch_bytes
+    cfg.setup_workers = 3
+    assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == 0
+    assert n.value - one == 2 * (4 << 30)
+    cfg.precision = smfs.SMFS_MIXED
+    assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -3
+    cfg.precision = smfs.SMFS_MIXED_FAR
+    assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == 0
+    cfg.max_active = 0
+    assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -1
