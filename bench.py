@@ -132,7 +132,8 @@ def headline(args, torch, smfs, wl, budget):
     gaps = pk.min_gaps()
     log(f"workload: {pk.P} spheres, box {pk.box:.2f}, {int((gaps < 0.2).sum())} in near contact, "
         f"min gap {gaps.min():.2e}")
-    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=1)
+    svd = smfs.SMFS_SVD_JACOBI if args.svd == "jacobi" else smfs.SMFS_SVD_ROCSOLVER
+    pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=1, svd_method=svd)
     log(f"T={pb.T} S={pb.S} factors={pb.sizes.n_factors} workspace="
         f"{pb.sizes.workspace_bytes / 2**30:.2f} GiB pairs/apply={pb.pairs_per_apply:.4e}")
     pb.bind()
@@ -144,7 +145,7 @@ def headline(args, torch, smfs, wl, budget):
     ranks = sorted({pb.factor_info(f)["rank"] for f in range(pb.sizes.n_factors)
                     if pb.factor_info(f)["sphere"] >= 0})
     log(f"setup (device assembly + truncated SVD of {pb.sizes.n_factors} distinct self blocks): "
-        f"{setup_s:.1f} s, ranks {ranks[0]}..{ranks[-1]}")
+        f"{setup_s:.1f} s ({args.svd}, {pb.sizes.svd_sweeps} Jacobi sweeps), ranks {ranks[0]}..{ranks[-1]}")
 
     rbm = torch.from_numpy(wl.random_rbm(pb.P, 1, 1000 + args.seed)[0].reshape(-1)).cuda()
     b = pb.rhs(rbm)                                      # a physical vector (first Krylov vector)
@@ -213,6 +214,8 @@ def headline_result(args, pk, pb, elapsed, st, setup_s, ranks, mixed):
             "precision": "fp64",
         },
         "setup_s": setup_s,
+        "setup_svd": args.svd,
+        "setup_jacobi_sweeps": int(pb.sizes.svd_sweeps),
         "factor_ranks": [int(ranks[0]), int(ranks[-1])],
         "roofline": {
             "kernel": "k_direct_f64 (direct sum of every off-sphere pair)",
@@ -698,6 +701,8 @@ def main():
     ap.add_argument("--reserve-s", type=float, default=20.0, help="seconds kept in reserve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed products beside the headline")
+    ap.add_argument("--svd", choices=["rocsolver", "jacobi"], default="rocsolver",
+                    help="SVD of the self blocks at set-up")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="length of the oracle's timed sample")
     ap.add_argument("--solve-spheres", type=int, default=100,
                     help="spheres of the solve-time comparison (a cut of the headline recipe; 0: skip)")

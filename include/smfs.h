@@ -72,8 +72,12 @@ enum {
  * FP64).  Everything else is FP64 in all modes. */
 enum { SMFS_FP64 = 0, SMFS_MIXED = 1, SMFS_MIXED_FAR = 2 };
 enum { SMFS_KIND_S = 1, SMFS_KIND_R = 2, SMFS_KIND_D = 4 };
-/* SVD of the self blocks at set-up: SMFS_SVD_JACOBI = Householder QR, then
- * one-sided Jacobi on R in the library's kernels, then U = Q U_R;
+/* SVD of the self blocks at set-up: SMFS_SVD_JACOBI = Householder QR
+ * B = Q1 R1, a second QR R1^T = Q2 R2 (a preconditioner), one-sided Jacobi
+ * on R2^T in the library's kernels, then U = Q1 U_X and V = Q2 J; ranks
+ * equal LAPACK's on the default blocks, and it is the faster method for
+ * small batches (two spheres: 1.1 s against 3.2 s) but not for many large
+ * blocks (106 blocks of about 4500 x 2000: 69 s against 41 s).
  * SMFS_SVD_ROCSOLVER = rocSOLVER's bidiagonal gesvd. */
 enum { SMFS_SVD_JACOBI = 0, SMFS_SVD_ROCSOLVER = 1 };
 
@@ -117,6 +121,8 @@ typedef struct smfs_sizes {
   int64_t n_check;          /* residual check points */
   size_t workspace_bytes;   /* device bytes smfs_bind() needs */
   size_t factor_bytes;      /* part of workspace_bytes holding factors */
+  int32_t svd_sweeps;       /* Jacobi sweeps the last smfs_setup needed (the most of any
+                               batch; 0 with SMFS_SVD_ROCSOLVER or before set-up) */
 } smfs_sizes;
 
 /* Output of a solve.  Device pointers may be NULL to skip that output. */

@@ -673,7 +673,8 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
         if (st.rel_residual <= tol) { st.converged = true; stop = true; return SMFS_OK; }
         if (nu == 0.0) { stop = true; return SMFS_OK; }   // q_j lies in the span: exact solution
         // Guard: every check_every iterations once the estimate is small,
-        // form the iterate, apply the operator and take the true residual.
+        // form the iterate, apply the FP64 operator and take the true
+        // residual.
         // Rounding of the truncated pseudo-inverses leaves a floor that the
         // recursive estimate does not see; once the true residual stops
         // falling (less than halved since the last check) while the
@@ -691,7 +692,10 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
           SMFS_HIP(hipMemcpyAsync(cf, hchk, 8 * (size_t)nj, hipMemcpyHostToDevice, s));
           SMFS_HIP(hipMemcpyAsync(xt, x, 8 * n, hipMemcpyDeviceToDevice, s));
           SMFS_HIP(launch_combine(V, ld, nj, cf, xt, n, s));
-          int rc = op(xt, wt, precision);
+          // the check is an FP64 product whatever the Krylov products are:
+          // in a mixed solve the residual of the FP32 far field stalls at
+          // its rounding level while the iterate still improves
+          int rc = op(xt, wt, SMFS_FP64);
           if (rc) return rc;
           ++st.check_applies;
           SMFS_HIP(launch_sub(n, b, wt, wt, s));
@@ -768,10 +772,10 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
     SMFS_HIP(launch_combine(V, ld, jdone, cf, x, n, s));
     SMFS_HIP(hipStreamSynchronize(s));
     if (stop) return SMFS_OK;
-    // restart from the true residual
-    int rc = op(x, w, precision);
+    // restart from the true residual (an FP64 product in every mode)
+    int rc = op(x, w, SMFS_FP64);
     if (rc) return rc;
-    ++st.applies;
+    ++st.check_applies;
     enq_applies = st.applies;
     SMFS_HIP(launch_sub(n, b, w, r, s));
     SMFS_HIP(launch_norm2(r, n, part, nch, scal + 1, s));
@@ -902,6 +906,7 @@ int smfs_problem_sizes(const smfs_problem *pb, smfs_sizes *s) {
   s->n_check = pb->C;
   s->workspace_bytes = pb->need_bytes;
   s->factor_bytes = pb->factor_bytes;
+  s->svd_sweeps = pb->svd_sweeps;
   return SMFS_OK;
 }
 
@@ -1064,8 +1069,9 @@ int setup_scratch_bytes(Problem &pb, size_t &bytes) {
   return SMFS_OK;
 }
 
-// The device Jacobi SVD of every shape group (QR, one-sided Jacobi on R,
-// U = Q U_R), the blocks assembled into the plan's input region.
+// The device Jacobi SVD of every shape group (B = Q1 R1, R1^T = Q2 R2,
+// one-sided Jacobi on R2^T, U = Q1 U_X, V = Q2 J), the blocks assembled
+// into the plan's input region.
 int setup_factors_jacobi(Problem &pb, char *scratch, size_t scratch_bytes, hipStream_t s) {
   rocblas_handle h = (rocblas_handle)pb.rocblas;
   for (const ShapeGroup &g : shape_groups(pb)) {
@@ -1409,7 +1415,8 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
   if (rc) return rc;
   ss = SolveStats{};
   ss.iterations = st.iterations;
-  ss.applies = st.applies + st.check_applies;
+  ss.applies = st.applies;
+  ss.applies64 = st.check_applies;
   ss.rel_residual = st.rel_residual;
   ss.true_checks = st.true_checks;
   ss.floor_it = st.floor_it;
@@ -1441,7 +1448,8 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
     rc = gmres(pb, n, op, rr, d, sd, precision, tol_d, pb.prm.gmres_max_it - ss.applies, every, s);
     if (rc) return rc;
     ss.iterations += sd.iterations;
-    ss.applies += sd.applies + sd.check_applies;
+    ss.applies += sd.applies;
+    ss.applies64 += sd.check_applies;
     ss.true_checks += sd.true_checks;
     stopped = sd.converged || sd.stagnated;
     SMFS_HIP(launch_axpby(n, 1.0, d, 1.0, x, s));

@@ -183,7 +183,7 @@ bool is_mixed(int p);
 struct JacPlan {
   int w = 8, rows = 4, npad = 0, nbk = 0, npairs = 0;
   size_t work = 0;
-  size_t a = 0, tau = 0, x = 0, v = 0, wbuf = 0, off = 0, sig = 0, perm = 0, rank = 0, ptrs = 0, sched = 0;
+  size_t a = 0, tau = 0, t = 0, tau2 = 0, x = 0, v = 0, wbuf = 0, off = 0, sig = 0, fro = 0, perm = 0, rank = 0, ptrs = 0, sched = 0;
   size_t total = 0;
 };
 }  // namespace smfs

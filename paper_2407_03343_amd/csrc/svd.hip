@@ -1,9 +1,14 @@
 // Truncated SVD of the self blocks B = W G^(kk) on the device (Section 2.2,
-// eq. transform; truncation eps_trunc of Section 5): Householder QR of every
-// block (rocSOLVER geqrf), one-sided Jacobi (Hestenes) on the triangular
-// factor R in HIP, then U = Q [U_R; 0] (rocSOLVER ormqr).
+// eq. transform; truncation eps_trunc of Section 5), in three stages:
+//   B = Q1 R1 and R1^T = Q2 R2 (rocSOLVER geqrf, batched);
+//   one-sided Jacobi (Hestenes) on X = R2^T in HIP: X J = U_X Sigma;
+//   U = Q1 [U_X; 0] and V = Q2 J (rocSOLVER ormqr), since
+//   B = Q1 R2^T Q2^T = Q1 U_X Sigma J^T Q2^T.
+// The second QR is a preconditioner: R2^T is much closer to having
+// orthogonal columns than R1 (on a 4500 x 1980 contact block the Jacobi
+// sweeps drop from over 40 to about 22).
 //
-// One-sided Jacobi orthogonalises the columns of X = R V by plane rotations,
+// One-sided Jacobi orthogonalises the columns of X by plane rotations,
 // each computed from fresh dot products of the two columns it rotates, so
 // the singular values come out with the accuracy of the data (the Gram
 // matrix is never formed, which would square the condition number and lose
@@ -13,8 +18,12 @@
 // task holds its 2w columns in registers across a 512-thread workgroup and
 // runs one round-robin sweep over the 2w columns, accumulating its
 // rotations in a 2w x 2w matrix that a second kernel applies to V.  Sweeps
-// repeat until no pair of columns has a cosine above 1e-13.  Every block is
-// processed on its own, whatever else shares the launch.
+// repeat until no pair of columns has a cosine above
+// max(1e-13, 64 eps ||R||_F / min(|x_a|, |x_b|)): rounding in the rotations
+// leaves every column perturbed at the level eps ||R||_F, so a column near
+// that level (far below the 5e-12 truncation) has a cosine with any other
+// known only to the second bound, and asking for more never ends.  Every
+// block is processed on its own, whatever else shares the launch.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -37,8 +46,9 @@ namespace {
 constexpr int kJacThreads = 512;         // threads of a pair task (8 waves)
 constexpr int kJacWaves = kJacThreads / 64;
 constexpr double kRotTol = 1e-15;        // rotate when |x_a.x_b| > tol |x_a| |x_b|
-constexpr double kSweepTol = 1e-13;      // sweeps end when every cosine is below this
-constexpr int kMaxSweeps = 30;
+constexpr double kSweepTol = 1e-13;      // sweeps end when every cosine is below this ...
+constexpr double kNoise = 64 * 2.220446049250313e-16;  // ... or below kNoise ||R||_F / min column norm
+constexpr int kMaxSweeps = 40;
 
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -55,7 +65,8 @@ struct JacArgs {
   const int2 *pairs;    // column-block pairs of this round (npairs), (-1, -1) = none
   int32_t npairs;
   double *Wout;         // per block and pair task: 2w x 2w rotation product (column-major)
-  double *off;          // per block and pair task: largest cosine seen before rotation
+  double *off;          // per block and pair task: largest cosine / tolerance seen before rotation
+  const double *fro;    // per block: Frobenius norm of R
 };
 
 // Shared memory of a pair task.
@@ -72,7 +83,8 @@ struct JacShared {
 // reduced over the workgroup, rotations computed by w threads, applied to
 // every thread's rows and to W.
 template <int kRows, int kW2, int q>
-__device__ __forceinline__ void jac_round(double (&x)[kRows][kW2], JacShared<kW2> &sh, double &offmax) {
+__device__ __forceinline__ void jac_round(double (&x)[kRows][kW2], JacShared<kW2> &sh, double &offmax,
+                                          double noise) {
   constexpr int w = kW2 / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double s[3 * w];
@@ -109,8 +121,9 @@ __device__ __forceinline__ void jac_round(double (&x)[kRows][kW2], JacShared<kW2
     }
     double c = 1.0, sn = 0.0;
     if (aa > 0.0 && bb > 0.0) {
-      const double cosv = fabs(ab) / (sqrt(aa) * sqrt(bb));
-      offmax = fmax(offmax, cosv);
+      const double na = sqrt(aa), nb = sqrt(bb);
+      const double cosv = fabs(ab) / (na * nb);
+      offmax = fmax(offmax, cosv / fmax(kSweepTol, noise / fmin(na, nb)));
       if (cosv > kRotTol) {
         // x_a' = c x_a - s x_b, x_b' = s x_a + c x_b with x_a'.x_b' = 0
         const double zeta = (bb - aa) / (2.0 * ab);
@@ -151,8 +164,8 @@ __device__ __forceinline__ void jac_round(double (&x)[kRows][kW2], JacShared<kW2
 
 template <int kRows, int kW2, int... Q>
 __device__ __forceinline__ void jac_rounds(double (&x)[kRows][kW2], JacShared<kW2> &sh, double &offmax,
-                                           std::integer_sequence<int, Q...>) {
-  (jac_round<kRows, kW2, Q>(x, sh, offmax), ...);
+                                           double noise, std::integer_sequence<int, Q...>) {
+  (jac_round<kRows, kW2, Q>(x, sh, offmax, noise), ...);
 }
 
 // One pair task: columns of blocks I and J of matrix blockIdx.y.  Each
@@ -184,7 +197,8 @@ __global__ __launch_bounds__(kJacThreads) void k_jac_pairs(JacArgs a) {
   for (int e = tid; e < kW2 * kW2; e += kJacThreads) sh.W[e % kW2][e / kW2] = (e % kW2 == e / kW2) ? 1.0 : 0.0;
   __syncthreads();
   double offmax = 0.0;
-  jac_rounds<kRows, kW2>(x, sh, offmax, std::make_integer_sequence<int, kW2 - 1>{});
+  const double noise = kNoise * a.fro[b];
+  jac_rounds<kRows, kW2>(x, sh, offmax, noise, std::make_integer_sequence<int, kW2 - 1>{});
 #pragma unroll
   for (int c = 0; c < kW2; ++c) {
     const int64_t gc = c < w ? (int64_t)pr.x * w + c : (int64_t)pr.y * w + (c - w);
@@ -195,7 +209,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jac_pairs(JacArgs a) {
     }
   }
   for (int e = tid; e < kW2 * kW2; e += kJacThreads) Wo[e] = sh.W[e % kW2][e / kW2];
-  // largest cosine of the task (threads < w hold their pairs' maxima)
+  // largest cosine / tolerance of the task (threads < w hold their pairs' maxima)
   if (tid < w) sh.red[0][tid] = offmax;
   __syncthreads();
   if (tid == 0) {
@@ -237,15 +251,27 @@ __global__ __launch_bounds__(256) void k_jac_vupdate(double *V, int64_t v_stride
   }
 }
 
-// X = R (upper triangle of the QR factor, zero below and in padded columns),
+// T = R1^T (n x n, column-major, lower triangular) from the upper triangle
+// of the first QR (m x n, column-major, ld m).
+__global__ void k_jac_transpose(const double *A, int64_t a_stride, int32_t m, int32_t n, double *T,
+                                int64_t t_stride) {
+  const int b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int64_t r = idx % n, c = idx / n;   // T(r, c) = R1(c, r)
+  T[(int64_t)b * t_stride + idx] = r >= c ? A[(int64_t)b * a_stride + r * m + c] : 0.0;
+}
+
+// X = R2^T (n rows, npad columns, column-major; zero above the diagonal and
+// in padded columns) from the upper triangle of the second QR (n x n, ld n),
 // V = I.
-__global__ void k_jac_init(const double *A, int64_t a_stride, int32_t m, int32_t n, double *X, int64_t x_stride,
+__global__ void k_jac_init(const double *T, int64_t t_stride, int32_t n, double *X, int64_t x_stride,
                            int32_t npad, double *V, int64_t v_stride) {
   const int b = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (int64_t)n * npad) {
-    const int64_t r = idx % n, c = idx / n;
-    X[(int64_t)b * x_stride + idx] = (c < n && r <= c) ? A[(int64_t)b * a_stride + c * m + r] : 0.0;
+    const int64_t r = idx % n, c = idx / n;   // X(r, c) = R2(c, r)
+    X[(int64_t)b * x_stride + idx] = (c < n && r >= c) ? T[(int64_t)b * t_stride + r * n + c] : 0.0;
   }
   if (idx < (int64_t)npad * npad) {
     const int64_t r = idx / npad, c = idx % npad;
@@ -266,6 +292,23 @@ __global__ __launch_bounds__(256) void k_jac_colnorm(const double *X, int64_t x_
   if (lane == 0) sig[(int64_t)b * npad + c] = sqrt(s);
 }
 
+// Frobenius norm of each block's X (= R): one workgroup per block.
+__global__ __launch_bounds__(1024) void k_jac_fro(const double *X, int64_t x_stride, int64_t count, double *fro) {
+  __shared__ double red[16];
+  const int b = blockIdx.x;
+  const double *xb = X + (int64_t)b * x_stride;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s = fma(xb[i], xb[i], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[u];
+    fro[b] = sqrt(t);
+  }
+}
+
 struct FinalArgs {
   const double *X;
   int64_t x_stride;
@@ -280,10 +323,10 @@ struct FinalArgs {
   double *const *Ss;
 };
 
-// Slot outputs of block blockIdx.y, column c = blockIdx.x: U[:, c] =
-// [x_j / sigma_j; 0], V[:, c] = Vacc[:, j], sigma[c] = sigma_j with j =
-// perm[c]; columns at or beyond the rank are left alone.
-__global__ __launch_bounds__(256) void k_jac_finalize(FinalArgs f) {
+// Slot outputs of block blockIdx.y, column c = blockIdx.x, with j =
+// perm[c]: U[:, c] = [x_j / sigma_j; 0], sigma[c] = sigma_j; columns at or
+// beyond the rank are left alone.
+__global__ __launch_bounds__(256) void k_jac_finalize_u(FinalArgs f) {
   const int b = blockIdx.y, c = blockIdx.x;
   if (c >= f.rank[b]) return;
   const int j = f.perm[(int64_t)b * f.n + c];
@@ -292,10 +335,27 @@ __global__ __launch_bounds__(256) void k_jac_finalize(FinalArgs f) {
   const double *xc = f.X + (int64_t)b * f.x_stride + (int64_t)j * f.n;
   double *u = f.U[b] + (int64_t)c * f.m;
   for (int r = threadIdx.x; r < f.m; r += blockDim.x) u[r] = r < f.n ? xc[r] * inv : 0.0;
-  const double *vb = f.V + (int64_t)b * f.v_stride;
-  double *vs = f.Vs[b];
-  for (int r = threadIdx.x; r < f.n; r += blockDim.x) vs[(int64_t)r * f.n + c] = vb[(int64_t)r * f.npad + j];
   if (threadIdx.x == 0) f.Ss[b][c] = s;
+}
+
+// Jp[:, c] = J[:, perm[c]] (n x rank, column-major, ld n, written over X
+// once U is out), the rotations in the kept order.
+__global__ __launch_bounds__(256) void k_jac_finalize_j(FinalArgs f, double *Jp) {
+  const int b = blockIdx.y, c = blockIdx.x;
+  if (c >= f.rank[b]) return;
+  const int j = f.perm[(int64_t)b * f.n + c];
+  const double *vb = f.V + (int64_t)b * f.v_stride;
+  double *jc = Jp + (int64_t)b * f.x_stride + (int64_t)c * f.n;
+  for (int r = threadIdx.x; r < f.n; r += blockDim.x) jc[r] = vb[(int64_t)r * f.npad + j];
+}
+
+// Slot V (n x n row-major, rank columns) from Q2 Jp (n x rank, column-major).
+__global__ __launch_bounds__(256) void k_jac_store_v(FinalArgs f, const double *QJ) {
+  const int b = blockIdx.y, c = blockIdx.x;
+  if (c >= f.rank[b]) return;
+  const double *qc = QJ + (int64_t)b * f.x_stride + (int64_t)c * f.n;
+  double *vs = f.Vs[b];
+  for (int r = threadIdx.x; r < f.n; r += blockDim.x) vs[(int64_t)r * f.n + c] = qc[r];
 }
 
 // Round-robin schedule of nbk (even) column blocks: round r pairs.
@@ -318,8 +378,9 @@ int jacobi_shape(int n, int &w, int &rows) {
 }
 
 // Scratch of one batch of nb blocks of shape m x n (JacPlan): rocSOLVER's
-// work arrays (geqrf, ormqr), the blocks, QR scalars, X, V, rotation
-// products, cosines, norms, permutations, ranks, slot pointers, schedule.
+// work arrays (geqrf, ormqr), the blocks and their QR scalars, R1^T and its
+// QR scalars, X, V, rotation products, cosines, norms, permutations, ranks,
+// slot pointers, schedule.
 int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
   int rc = jacobi_shape(n, p.w, p.rows);
   if (rc) return rc;
@@ -328,7 +389,7 @@ int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
   if (p.nbk % 2) { p.nbk += 1; p.npad += p.w; }
   p.npairs = p.nbk / 2;
   double *fake = reinterpret_cast<double *>((uintptr_t)4096);
-  size_t w1 = 0, w2 = 0;
+  size_t w1 = 0, w2 = 0, w3 = 0, w4 = 0;
   rocblas_start_device_memory_size_query(h);
   rocblas_status q1 = rocsolver_dgeqrf_strided_batched(h, m, n, fake, m, (rocblas_stride)m * n, fake, n, nb);
   rocblas_stop_device_memory_size_query(h, &w1);
@@ -336,26 +397,36 @@ int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
   rocblas_status q2 = rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, m, n, n, fake, m, fake,
                                        fake, m);
   rocblas_stop_device_memory_size_query(h, &w2);
+  rocblas_start_device_memory_size_query(h);
+  rocblas_status q3 = rocsolver_dgeqrf_strided_batched(h, n, n, fake, n, (rocblas_stride)n * n, fake, n, nb);
+  rocblas_stop_device_memory_size_query(h, &w3);
+  rocblas_start_device_memory_size_query(h);
+  rocblas_status q4 = rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, n, n, n, fake, n, fake,
+                                       fake, n);
+  rocblas_stop_device_memory_size_query(h, &w4);
   auto ok = [](rocblas_status q) {
     return q == rocblas_status_success || q == rocblas_status_size_increased || q == rocblas_status_size_unchanged;
   };
-  if (!ok(q1) || !ok(q2)) {
+  if (!ok(q1) || !ok(q2) || !ok(q3) || !ok(q4)) {
     set_error("device SVD: workspace query failed");
     return SMFS_E_SVD;
   }
-  p.work = al256(std::max(w1, w2));
+  p.work = al256(std::max(std::max(w1, w2), std::max(w3, w4)));
   p.a = al256(sizeof(double) * (size_t)m * n * nb);
   p.tau = al256(sizeof(double) * (size_t)n * nb);
+  p.t = al256(sizeof(double) * (size_t)n * n * nb);
+  p.tau2 = al256(sizeof(double) * (size_t)n * nb);
   p.x = al256(sizeof(double) * (size_t)n * p.npad * nb);
   p.v = al256(sizeof(double) * (size_t)p.npad * p.npad * nb);
   p.wbuf = al256(sizeof(double) * (size_t)nb * p.npairs * 4 * p.w * p.w);
   p.off = al256(sizeof(double) * (size_t)nb * p.npairs * (p.nbk - 1));
   p.sig = al256(sizeof(double) * (size_t)nb * p.npad);
+  p.fro = al256(sizeof(double) * (size_t)nb);
   p.perm = al256(sizeof(int32_t) * (size_t)nb * n);
   p.rank = al256(sizeof(int32_t) * (size_t)nb);
   p.ptrs = al256(sizeof(double *) * 3 * (size_t)nb);
   p.sched = al256(sizeof(int2) * (size_t)(p.nbk - 1) * p.npairs);
-  p.total = p.work + p.a + p.tau + p.x + p.v + p.wbuf + p.off + p.sig + p.perm + p.rank + p.ptrs + p.sched;
+  p.total = p.work + p.a + p.tau + p.t + p.tau2 + p.x + p.v + p.wbuf + p.off + p.sig + p.fro + p.perm + p.rank + p.ptrs + p.sched;
   return SMFS_OK;
 }
 
@@ -369,11 +440,14 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   char *work = o; o += p.work;
   double *A = (double *)o; o += p.a;
   double *tau = (double *)o; o += p.tau;
+  double *T = (double *)o; o += p.t;
+  double *tau2 = (double *)o; o += p.tau2;
   double *X = (double *)o; o += p.x;
   double *V = (double *)o; o += p.v;
   double *Wb = (double *)o; o += p.wbuf;
   double *off = (double *)o; o += p.off;
   double *sig = (double *)o; o += p.sig;
+  double *fro = (double *)o; o += p.fro;
   int32_t *perm = (int32_t *)o; o += p.perm;
   int32_t *drank = (int32_t *)o; o += p.rank;
   double **ptrs = (double **)o; o += p.ptrs;
@@ -386,16 +460,26 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
     rocblas_handle h;
     ~Reset() { (void)rocblas_set_workspace(h, nullptr, 0); }
   } reset{h};
-  // Householder QR of every block
+  // B = Q1 R1 for every block, then R1^T = Q2 R2
   if (rocsolver_dgeqrf_strided_batched(h, m, n, A, m, (rocblas_stride)m * n, tau, n, nb) != rocblas_status_success) {
     set_error("device SVD: geqrf failed");
+    return SMFS_E_SVD;
+  }
+  const int64_t ts = (int64_t)n * n;
+  hipLaunchKernelGGL(k_jac_transpose, dim3((unsigned)((ts + 255) / 256), nb), dim3(256), 0, s, A, (int64_t)m * n, m,
+                     n, T, ts);
+  SMFS_HIP(hipGetLastError());
+  if (rocsolver_dgeqrf_strided_batched(h, n, n, T, n, (rocblas_stride)ts, tau2, n, nb) != rocblas_status_success) {
+    set_error("device SVD: geqrf of R^T failed");
     return SMFS_E_SVD;
   }
   const int64_t xs = (int64_t)n * p.npad, vs = (int64_t)p.npad * p.npad;
   {
     const int64_t cnt = std::max<int64_t>((int64_t)n * p.npad, vs);
-    hipLaunchKernelGGL(k_jac_init, dim3((unsigned)((cnt + 255) / 256), nb), dim3(256), 0, s, A, (int64_t)m * n, m, n,
-                       X, xs, p.npad, V, vs);
+    hipLaunchKernelGGL(k_jac_init, dim3((unsigned)((cnt + 255) / 256), nb), dim3(256), 0, s, T, ts, n, X, xs,
+                       p.npad, V, vs);
+    SMFS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_jac_fro, dim3(nb), dim3(1024), 0, s, X, xs, xs, fro);
     SMFS_HIP(hipGetLastError());
   }
   const std::vector<int2> sch = block_schedule(p.nbk);
@@ -419,6 +503,7 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
       ja.npairs = p.npairs;
       ja.Wout = Wb;
       ja.off = off + (int64_t)r * nb * p.npairs;
+      ja.fro = fro;
       const dim3 g((unsigned)p.npairs, (unsigned)nb);
       if (p.w == 8) hipLaunchKernelGGL((k_jac_pairs<4, 16>), g, dim3(kJacThreads), 0, s, ja);
       else hipLaunchKernelGGL((k_jac_pairs<8, 8>), g, dim3(kJacThreads), 0, s, ja);
@@ -438,7 +523,7 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
       set_error("device SVD: non-finite rotation");
       return SMFS_E_SVD;
     }
-    if (mx < kSweepTol) { ++sweep; break; }
+    if (mx < 1.0) { ++sweep; break; }
   }
   if (sweeps_out) *sweeps_out = sweep;
   if (sweep >= kMaxSweeps) {
@@ -490,16 +575,22 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   f.U = ptrs;
   f.Vs = ptrs + nb;
   f.Ss = ptrs + 2 * nb;
-  hipLaunchKernelGGL(k_jac_finalize, dim3((unsigned)n, nb), dim3(256), 0, s, f);
+  hipLaunchKernelGGL(k_jac_finalize_u, dim3((unsigned)n, nb), dim3(256), 0, s, f);
   SMFS_HIP(hipGetLastError());
-  // U = Q [U_R; 0] with the reflectors of each block's QR
+  hipLaunchKernelGGL(k_jac_finalize_j, dim3((unsigned)n, nb), dim3(256), 0, s, f, X);
+  SMFS_HIP(hipGetLastError());
+  // U = Q1 [U_X; 0] and V = Q2 J with the reflectors of the two QRs
   for (int q = 0; q < nb; ++q) {
     if (rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, m, rh[q], n, A + (size_t)q * m * n, m,
-                         tau + (size_t)q * n, U[q], m) != rocblas_status_success) {
+                         tau + (size_t)q * n, U[q], m) != rocblas_status_success ||
+        rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, n, rh[q], n, T + (size_t)q * ts, n,
+                         tau2 + (size_t)q * n, X + (size_t)q * xs, n) != rocblas_status_success) {
       set_error("device SVD: ormqr failed");
       return SMFS_E_SVD;
     }
   }
+  hipLaunchKernelGGL(k_jac_store_v, dim3((unsigned)n, nb), dim3(256), 0, s, f, X);
+  SMFS_HIP(hipGetLastError());
   SMFS_HIP(hipStreamSynchronize(s));
   return SMFS_OK;
 }

@@ -60,7 +60,7 @@ class smfs_sizes(C.Structure):
         ("P", C.c_int32), ("n_factors", C.c_int32), ("n_contacts", C.c_int32),
         ("min_gap_flag", C.c_int32), ("T", C.c_int64), ("S", C.c_int64),
         ("n_kind", C.c_int64 * 3), ("n_check", C.c_int64), ("workspace_bytes", C.c_size_t),
-        ("factor_bytes", C.c_size_t),
+        ("factor_bytes", C.c_size_t), ("svd_sweeps", C.c_int32),
     ]
 
 
@@ -330,6 +330,7 @@ class Problem:
         base = (buf.data_ptr() + 255) // 256 * 256
         _check(lib().smfs_setup(self.h, C.c_void_p(base), n, _stream()), "smfs_setup")
         del buf
+        _check(lib().smfs_problem_sizes(self.h, C.byref(self.sizes)), "smfs_problem_sizes")
         return self
 
     def import_factor(self, fid, U, sigma, V):
