@@ -15,15 +15,18 @@ sphere's self block applied to its slice of mu (eq. transform), the sum of
 every off-sphere Stokeslet, rotlet and dipole pair (eq. uAll) and the
 identity self blocks.  This product is what every GMRES iteration of a
 solve repeats.  `value` = pair evaluations of the timed products / wall
-time.  The same products in the mixed form (FP32 sources of the
-contact-free spheres) are timed beside it, with their error against FP64.
+time.  The same products in the mixed forms are timed beside it, with
+their error against FP64: SMFS_MIXED (FP32 sources of the contact-free
+spheres) and SMFS_MIXED_EQ (the far field of the contact-free spheres
+through FP64-fitted equivalent Stokeslets summed in FP32).
 
 Sections of the default run, each inside the wall budget (--budget-s):
  * cpu_baseline: the oracle's C direct sum on a bounded sample of the same
    workload;
  * solve: solve time to 1e-3 relative surface velocity (and 1e-5 in
-   forces/torques), FP64 against the mixed forms, p50/p99 over repeated
-   solves, on a stated cut of the same recipe;
+   forces/torques), FP64 against SMFS_MIXED_EQ (the other mixed forms on
+   request), p50/p99 over repeated solves, on a 300-sphere cut of the same
+   recipe;
  * two_sphere: the two-sphere case at gap 0.01, p50/p99 of complete solves.
 Flags add the block product, the block solve, the serving stream and the
 set-up comparison; their results go to stderr and, with --sections-out, to
@@ -58,7 +61,8 @@ PEAK_HBM_GBS = 8000.0
 # counters of the current kernel on this workload are taken.
 DIRECT_TRAFFIC_BYTES = (2 * 6230207.7 + 422606.2) * 1024
 
-FORMS = (("fp64", 0), ("mixed", 1), ("mixed_far", 2))   # SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR
+# SMFS_FP64, SMFS_MIXED_EQ, SMFS_MIXED, SMFS_MIXED_FAR
+FORMS = (("fp64", 0), ("mixed_eq", 3), ("mixed", 1), ("mixed_far", 2))
 
 
 def log(msg):
@@ -172,6 +176,13 @@ def headline(args, torch, smfs, wl, budget):
                       for f, p in FORMS[1:]}
     log(f"mixed product: {m_el / args.steps * 1e3:.1f} ms per step ({elapsed / m_el:.2f}x FP64); "
         f"error vs FP64 (off-diagonal, max-norm): physical {errs['physical']}, random {errs['random']}")
+    e_el, e_st = timed_products(pb, torch, mu, y, smfs.SMFS_MIXED_EQ, min(args.warmup, 2), args.steps)
+    s = pb.sizes
+    log(f"equivalent-source product: {e_el / args.steps * 1e3:.1f} ms per step ({elapsed / e_el:.2f}x FP64), "
+        f"far FP32 {e_st['eq_far_ms'] / max(1, e_st['eq_launches']):.1f} ms, near FP64 "
+        f"{e_st['eq_near_ms'] / max(1, e_st['eq_launches']):.1f} ms, contact sources FP64 "
+        f"{e_st['mixed64_ms'] / max(1, e_st['mixed64_launches']):.1f} ms, strengths "
+        f"{e_st['eq_strength_ms'] / max(1, e_st['eq_launches']):.2f} ms")
     mixed = {
         "precision": "SMFS_MIXED: FP32 pseudo-inverse and far field for the contact-free spheres",
         "ms_per_step": m_el / args.steps * 1e3,
@@ -179,6 +190,18 @@ def headline(args, torch, smfs, wl, budget):
         "speedup_over_fp64": elapsed / m_el,
         "kernels": mixed_kernel_rates(m_st),
         "offdiag_rel_err_vs_fp64": errs,
+        "equivalent_sources": {
+            "precision": "SMFS_MIXED_EQ: far field of contact-free spheres through 200 equivalent "
+                         "Stokeslets fitted in FP64, summed in FP32; pairs closer than 3.5 radii "
+                         "between centres and every contact-sphere source exact in FP64",
+            "ms_per_step": e_el / args.steps * 1e3,
+            "speedup_over_fp64": elapsed / e_el,
+            "equivalent_pairs": int(s.eq_far_pairs),
+            "exact_pairs": int(s.eq_exact_pairs),
+            "near_list_entries": int(s.eq_near_spheres),
+            "kernels": mixed_kernel_rates(e_st),
+            "strength_ms": e_st["eq_strength_ms"] / max(1, e_st["eq_launches"]),
+        },
     }
     return pk, pb, headline_result(args, pk, pb, elapsed, st, setup_s, ranks, mixed)
 
@@ -252,8 +275,10 @@ def mixed_kernel_rates(st):
     out = {}
     for key, label, peak in (("far32", "k_far_f32", PEAK_FP32_VALU_TFLOPS),
                              ("mixed64", "k_direct_f64 (near part)", PEAK_FP64_VALU_TFLOPS),
-                             ("direct", "k_direct_f64", PEAK_FP64_VALU_TFLOPS)):
-        n = st[f"{key}_launches"]
+                             ("direct", "k_direct_f64", PEAK_FP64_VALU_TFLOPS),
+                             ("eq_far", "k_far_eq_f32 (equivalent sources)", PEAK_FP32_VALU_TFLOPS),
+                             ("eq_near", "k_near_f64 (near contact-free proxies)", PEAK_FP64_VALU_TFLOPS)):
+        n = st.get("eq_launches", 0) if key.startswith("eq_") else st[f"{key}_launches"]
         if not n:
             continue
         ms = st[f"{key}_ms"] / n
@@ -342,6 +367,8 @@ def solve_section(args, torch, smfs, wl, budget):
            "forms": {}}
     last_s = ref_s
     for name, prec in FORMS:
+        if name not in args.solve_forms:
+            continue
         rows, chosen = [], None
         for tol in args.solve_tols:
             if not budget.fits(2.5 * last_s + args.reserve_s):
@@ -667,11 +694,14 @@ def apply_only(args, torch, smfs, wl):
             continue
         U, s, V = wl.random_factors(info["rows"], info["cols"], 48, seed=100 + fid)
         pb.import_factor(fid, U, s, V)
+    prec = smfs.SMFS_MIXED_EQ if args.apply_precision == "mixed_eq" else smfs.SMFS_FP64
+    if prec == smfs.SMFS_MIXED_EQ:
+        pb.setup_far_field()
     mu = torch.from_numpy(wl.random_vector(3 * pb.T, 3)).cuda()
     y = torch.empty_like(mu)
     pb.profile(True)
     for _ in range(args.apply_only):
-        pb.apply(mu, out=y)
+        pb.apply(mu, precision=prec, out=y)
     torch.cuda.synchronize()
     pb.profile(False)
     st = pb.profile_read()
@@ -681,7 +711,11 @@ def apply_only(args, torch, smfs, wl):
     torch.mul(x, 2.0, out=z)      # calibration: reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
     del x, z
-    print(json.dumps({"apply_only": args.apply_only, "spheres": pb.P,
+    n_eq = max(1, st["eq_launches"])
+    print(json.dumps({"apply_only": args.apply_only, "spheres": pb.P, "precision": args.apply_precision,
+                      "eq_far_avg_ms": st["eq_far_ms"] / n_eq, "eq_near_avg_ms": st["eq_near_ms"] / n_eq,
+                      "eq_far_flops": st["eq_far_flops"], "eq_near_flops": st["eq_near_flops"],
+                      "contact_fp64_avg_ms": st["mixed64_ms"] / max(1, st["mixed64_launches"]),
                       "direct_avg_ms": st["direct_ms"] / max(1, st["direct_launches"]),
                       "pinv_avg_ms": st["pinv_ms"] / max(1, st["pinv_launches"]),
                       "direct_flops": st["direct_flops"], "pinv_bytes": st["pinv_bytes"],
@@ -704,7 +738,11 @@ def main():
     ap.add_argument("--svd", choices=["rocsolver", "jacobi"], default="rocsolver",
                     help="SVD of the self blocks at set-up")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="length of the oracle's timed sample")
-    ap.add_argument("--solve-spheres", type=int, default=100,
+    ap.add_argument("--solve-forms", nargs="+", default=["fp64", "mixed_eq"],
+                    choices=[f for f, _ in FORMS],
+                    help="forms of the solve section (SMFS_MIXED and SMFS_MIXED_FAR stop on their "
+                         "true-residual floor above the gates on this workload)")
+    ap.add_argument("--solve-spheres", type=int, default=300,
                     help="spheres of the solve-time comparison (a cut of the headline recipe; 0: skip)")
     ap.add_argument("--solve-tols", type=float, nargs="+", default=[1e-5, 1e-6, 1e-7, 1e-8],
                     help="GMRES tolerance ladder, loosest first, the same for every form")
@@ -715,6 +753,8 @@ def main():
     ap.add_argument("--apply-only", type=int, default=0, metavar="N",
                     help="profiling aid: N products on the headline workload with seeded full-rank "
                          "factors, then the counter calibration kernels; nothing else runs")
+    ap.add_argument("--apply-precision", choices=["fp64", "mixed_eq"], default="fp64",
+                    help="form of the --apply-only products")
     ap.add_argument("--sections-out", default="", help="JSON file for the optional sections")
     ap.add_argument("--block", type=int, default=0, metavar="NRHS",
                     help="block product of NRHS vectors vs single products (0: skip)")

@@ -69,8 +69,18 @@ enum {
  * contact-free spheres in FP32, both their pseudo-inverse apply (FP32 copy
  * of the shared factor) and their pair sums.  SMFS_MIXED_FAR: their pair
  * sums in FP32 from strengths computed in FP64 (the pseudo-inverse stays
- * FP64).  Everything else is FP64 in all modes. */
-enum { SMFS_FP64 = 0, SMFS_MIXED = 1, SMFS_MIXED_FAR = 2 };
+ * FP64).  SMFS_MIXED_EQ: the far field of every contact-free sphere through
+ * eq_points equivalent Stokeslets, fitted in FP64 and summed in FP32, for
+ * target spheres at centre separation >= eq_separation; closer pairs of a
+ * contact-free source, and every source of a contact sphere, exact in FP64
+ * (a one-level equivalent-source replacement of the fast multipole
+ * evaluation of eq. uAll, Section 2.2; needs smfs_setup_far_field, which
+ * smfs_setup runs).  The proxies' strengths of a rough vector cancel by up
+ * to 1e5 in their far field, which an FP32 sum of them cannot resolve; the
+ * equivalent strengths are of the size of the field.  Everything else is
+ * FP64 in all modes; the true-residual checks, restarts and refinement
+ * residuals of a solve are FP64 products. */
+enum { SMFS_FP64 = 0, SMFS_MIXED = 1, SMFS_MIXED_FAR = 2, SMFS_MIXED_EQ = 3 };
 enum { SMFS_KIND_S = 1, SMFS_KIND_R = 2, SMFS_KIND_D = 4 };
 /* SVD of the self blocks at set-up: SMFS_SVD_JACOBI = Householder QR
  * B = Q1 R1, a second QR R1^T = Q2 R2 (a preconditioner), one-sided Jacobi
@@ -108,6 +118,18 @@ typedef struct smfs_params {
                                recursive estimate is below 1e-3; 0 = off.  Each check
                                forms the iterate and costs one product with G_hat */
   int32_t svd_method;       /* SMFS_SVD_ROCSOLVER (default) or SMFS_SVD_JACOBI */
+  /* equivalent-source far field (SMFS_MIXED_EQ): eq_points Stokeslets on the
+   * Fibonacci spiral of radius eq_radius (radii) around a sphere's centre,
+   * fitted to its proxies' field at 2 eq_points check points of radius
+   * eq_check_radius by a pseudo-inverse keeping singular values above
+   * eq_rcond sigma_1; used for target spheres at centre separation
+   * >= eq_separation, which must be at least eq_check_radius + 1 (every
+   * target then lies outside the check sphere).  eq_points = 0: off. */
+  int32_t eq_points;        /* default 200 */
+  double eq_radius;         /* default 1.0 */
+  double eq_check_radius;   /* default 2.5 */
+  double eq_separation;     /* default 3.5 */
+  double eq_rcond;          /* default 1e-12 */
 } smfs_params;
 
 typedef struct smfs_sizes {
@@ -123,6 +145,10 @@ typedef struct smfs_sizes {
   size_t factor_bytes;      /* part of workspace_bytes holding factors */
   int32_t svd_sweeps;       /* Jacobi sweeps the last smfs_setup needed (the most of any
                                batch; 0 with SMFS_SVD_ROCSOLVER or before set-up) */
+  int64_t eq_far_pairs;     /* SMFS_MIXED_EQ product: target x equivalent-source pairs */
+  int64_t eq_exact_pairs;   /* its exact FP64 pairs (contact sources, near proxies) */
+  int64_t eq_near_spheres;  /* entries of all near lists (contact-free source spheres
+                               closer than eq_separation to a target sphere) */
 } smfs_sizes;
 
 /* Output of a solve.  Device pointers may be NULL to skip that output. */
@@ -189,13 +215,27 @@ int smfs_setup_workspace_bytes(smfs_problem *pb, size_t *bytes);
 /* Assemble every distinct self block B = W G^(kk) on the device and factor
  * it with a thin SVD (rocSOLVER, one batched call per group of equal shape),
  * keeping sigma_i > trunc_rel * sigma_1 (Section 2.2, eq. transform; the
- * truncation eps_trunc of Section 5).  scratch [dev]: at least
+ * truncation eps_trunc of Section 5); then, with eq_points > 0, fit the
+ * equivalent sources (smfs_setup_far_field).  scratch [dev]: at least
  * smfs_setup_workspace_bytes bytes, 256-byte aligned, owned by the caller
  * and free again when the call returns; the library allocates no device
  * memory here (rocSOLVER works in the scratch).  Errors: SMFS_E_STATE if not
  * bound, SMFS_E_NOMEM if the scratch is too small, SMFS_E_SVD if an SVD
  * fails.  Synchronises the stream. */
 int smfs_setup(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream);
+
+/* Equivalent sources of the contact-free spheres for SMFS_MIXED_EQ (eq_*
+ * parameters): assembles the Stokeslet matrices K(check, equivalent) and
+ * K(check, proxies) of one sphere on the device, takes the SVD of the first
+ * (rocSOLVER) and stores E = K_ce^+ K_cp (3 eq_points x 3 n_proxy, FP64) in
+ * the workspace.  E depends on the node sets only, not on the factors, so a
+ * caller that imports factors runs this alone.  scratch [dev]: at least
+ * smfs_far_field_workspace_bytes bytes, 256-byte aligned, caller-owned and
+ * free again on return.  Nothing to do (SMFS_OK) without contact-free
+ * spheres or with eq_points = 0.  Errors: SMFS_E_STATE if not bound,
+ * SMFS_E_NOMEM, SMFS_E_SVD.  Synchronises the stream. */
+int smfs_far_field_workspace_bytes(smfs_problem *pb, size_t *bytes);
+int smfs_setup_far_field(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream);
 
 /* Install a factor computed elsewhere.  U [host] rows x rank column-major,
  * sigma [host] rank, V [host] cols x rank row-major.  Synchronises. */
@@ -507,6 +547,12 @@ typedef struct smfs_kernel_stats {
   double bpinv_ms;
   double bpinv_flops;       /* per launch: 2 nrhs (rank (rows + cols)) summed over spheres */
   int32_t bnrhs;            /* right-hand sides of the last profiled block product */
+  int64_t eq_launches;      /* SMFS_MIXED_EQ products */
+  double eq_far_ms;         /* FP32 equivalent-source sum */
+  double eq_far_flops;      /* per launch: 28 per pair */
+  double eq_near_ms;        /* FP64 sum of the near contact-free proxies */
+  double eq_near_flops;     /* per launch: 28 per pair */
+  double eq_strength_ms;    /* equivalent strengths q = E lambda_hat */
 } smfs_kernel_stats;
 
 /* enable = 1 clears the counters and starts recording; 0 stops. */

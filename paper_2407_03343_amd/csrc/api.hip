@@ -53,8 +53,12 @@ int32_t direct_splits(int64_t n_tiles, int64_t S) { return choose_splits(n_tiles
 
 void set_error(const std::string &msg) { g_err = msg; }
 
-bool valid_precision(int p) { return p == SMFS_FP64 || p == SMFS_MIXED || p == SMFS_MIXED_FAR; }
-bool is_mixed(int p) { return p == SMFS_MIXED || p == SMFS_MIXED_FAR; }
+bool valid_precision(int p) {
+  return p == SMFS_FP64 || p == SMFS_MIXED || p == SMFS_MIXED_FAR || p == SMFS_MIXED_EQ;
+}
+bool is_mixed(int p) { return p == SMFS_MIXED || p == SMFS_MIXED_FAR || p == SMFS_MIXED_EQ; }
+// The equivalent-source far field has contact-free spheres to serve.
+bool eq_enabled(const Problem &pb) { return pb.n_eq > 0 && pb.n_free > 0; }
 
 // Tiles of the FP64 direct sums: tt consecutive targets each, whatever
 // sphere they belong to, as (first sphere, first target, count, last
@@ -115,19 +119,31 @@ size_t workspace_layout(Problem &pb, bool assign) {
   const size_t o_bv = take(sizeof(int4) * std::max<int64_t>(1, btasks));
   const int32_t sp_t = choose_splits((int64_t)tiles.size(), S);
   const int32_t sp_c = choose_splits(free_tiles(C), S);
-  const int64_t part = std::max<int64_t>(3 * T * sp_t, 3 * C * sp_c);
-  const size_t o_part = take(sizeof(double) * part);
-  // mixed precision: FP32 coordinates/strengths of proxies, FP32 partials
   int32_t n_free = 0;
   for (int k = 0; k < P; ++k) n_free += pb.contacts[k].empty() ? 1 : 0;
+  const bool eq = pb.prm.eq_points > 0 && n_free > 0;
+  // with the equivalent-source far field, one more slice for the near proxies
+  const int64_t part = std::max<int64_t>(3 * T * (sp_t + (eq ? 1 : 0)), 3 * C * sp_c);
+  const size_t o_part = take(sizeof(double) * part);
+  // mixed precision: FP32 coordinates/strengths of proxies, FP32 partials
   const int64_t nprox = pb.nb[0];
   const int32_t sp32 = n_free > 0 ? std::min<int32_t>(choose_splits((int64_t)stiles.size(),
                                                                    (int64_t)n_free * pb.prm.n_proxy),
                                                       std::max(1, n_free)) : 0;
+  const int32_t ne = eq ? pb.prm.eq_points : 0;
+  const int32_t sp_eq = eq ? std::min<int32_t>(choose_splits((int64_t)stiles.size(), (int64_t)n_free * ne),
+                                               std::max(1, n_free)) : 0;
+  pb.n_eq = ne;
+  if (eq) build_near_lists(pb, pb.prm.eq_separation * pb.a);
+  const size_t o_eqE = take(sizeof(double) * std::max<int64_t>(1, (int64_t)9 * ne * pb.prm.n_proxy));
+  const size_t o_eqq = take(sizeof(float) * std::max<int64_t>(1, (int64_t)3 * ne * n_free));
+  const size_t o_eqpt = take(sizeof(float) * std::max<int64_t>(1, (int64_t)3 * ne));
+  const size_t o_noff = take(sizeof(int32_t) * (P + 1));
+  const size_t o_nidx = take(sizeof(int32_t) * std::max<size_t>(1, eq ? pb.near_idx.size() : 0));
   const size_t o_tgt32 = take(sizeof(float) * 3 * T);
   const size_t o_src32 = take(sizeof(float) * 3 * nprox);
   const size_t o_str32 = take(sizeof(float) * 3 * nprox);
-  const size_t o_part32 = take(sizeof(float) * 3 * T * std::max(sp32, 1));
+  const size_t o_part32 = take(sizeof(float) * 3 * T * std::max(std::max(sp32, sp_eq), 1));
   const size_t o_s32 = take(sizeof(float) * cols_total);
   const size_t o_free = take(sizeof(int32_t) * std::max(1, P));
   const size_t o_cen = take(sizeof(double) * 3 * P);
@@ -197,6 +213,13 @@ size_t workspace_layout(Problem &pb, bool assign) {
     pb.d_fac32 = (float *)(b + o_fac32);
     pb.n_free = n_free;
     pb.n_splits32 = sp32;
+    pb.d_eqE = (double *)(b + o_eqE);
+    pb.d_eqq32 = (float *)(b + o_eqq);
+    pb.d_eqpt32 = (float *)(b + o_eqpt);
+    pb.d_near_off = (int32_t *)(b + o_noff);
+    pb.d_near_idx = (int32_t *)(b + o_nidx);
+    pb.n_splits_eq = sp_eq;
+    pb.eq_ready = false;
     pb.tiles = tiles;
     pb.n_tiles = (int64_t)tiles.size();
     pb.stiles = stiles;
@@ -295,6 +318,17 @@ int upload_tables(Problem &pb, hipStream_t s) {
   if (!free_ids.empty())
     SMFS_HIP(hipMemcpyAsync(pb.d_free, free_ids.data(), 4 * free_ids.size(), hipMemcpyHostToDevice, s));
   SMFS_HIP(hipMemcpyAsync(pb.d_ranges, rng.data(), sizeof(SrcRange) * rng.size(), hipMemcpyHostToDevice, s));
+  std::vector<float> eqpt;
+  if (eq_enabled(pb)) {
+    std::vector<double> pts;
+    spiral_points(pb.n_eq, pb.prm.eq_radius * pb.a, pts);
+    eqpt.assign(pts.begin(), pts.end());
+    SMFS_HIP(hipMemcpyAsync(pb.d_eqpt32, eqpt.data(), 4 * eqpt.size(), hipMemcpyHostToDevice, s));
+    SMFS_HIP(hipMemcpyAsync(pb.d_near_off, pb.near_off.data(), 4 * pb.near_off.size(), hipMemcpyHostToDevice, s));
+    if (!pb.near_idx.empty())
+      SMFS_HIP(hipMemcpyAsync(pb.d_near_idx, pb.near_idx.data(), 4 * pb.near_idx.size(), hipMemcpyHostToDevice,
+                              s));
+  }
   SMFS_HIP(hipStreamSynchronize(s));
   return rank_tables(pb, s);
 }
@@ -454,7 +488,77 @@ int record_event(Problem &pb, hipStream_t s, size_t &idx) {
 // pair in FP64.  Mixed: contact-free spheres (shared factor) go through the
 // FP32 pseudo-inverse and the FP32 far-field kernel; contact spheres, with
 // their image lines, stay FP64 throughout.
+// y = G_hat mu with the equivalent-source far field (SMFS_MIXED_EQ): FP64
+// strengths of every sphere; equivalent strengths of the contact-free
+// spheres; the FP64 sum over contact spheres' sources (images included),
+// the FP64 sum over each target sphere's near contact-free proxies (one
+// more partial slice), the FP32 sum over every other contact-free sphere's
+// equivalent sources; one epilogue.
+int apply_eq(Problem &pb, const double *mu, double *y, hipStream_t s) {
+  if (!pb.eq_ready) {
+    set_error("SMFS_MIXED_EQ product before smfs_setup_far_field");
+    return SMFS_E_STATE;
+  }
+  size_t e[6] = {0, 0, 0, 0, 0, 0};
+  int rc;
+  if (pb.prof && (rc = record_event(pb, s, e[0]))) return rc;
+  if ((rc = transform64(pb, mu, pb.d_lamhat, 2.0 * pb.prm.mu, s))) return rc;
+  if (pb.prof && (rc = record_event(pb, s, e[1]))) return rc;
+  SMFS_HIP(launch_eq_strengths(pb.d_eqE, 3 * pb.n_eq, 3 * pb.prm.n_proxy, pb.d_lamhat, pb.d_meta, pb.d_free,
+                               pb.n_free, pb.d_eqq32, s));
+  if (pb.prof && (rc = record_event(pb, s, e[2]))) return rc;
+  DirectArgs a = direct_args(pb, pb.d_lamhat, true);
+  SMFS_HIP(launch_direct_f64(a, s));
+  if (pb.prof && (rc = record_event(pb, s, e[3]))) return rc;
+  NearArgs n;
+  n.d = a;
+  n.tiles = pb.d_stiles;
+  n.n_tiles = pb.n_stiles;
+  n.free_ids = pb.d_free;
+  n.near_off = pb.d_near_off;
+  n.near_idx = pb.d_near_idx;
+  n.out = pb.d_part + 3 * pb.T * (int64_t)pb.n_splits;
+  SMFS_HIP(launch_near_f64(n, s));
+  if (pb.prof && (rc = record_event(pb, s, e[4]))) return rc;
+  EqArgs f;
+  f.tiles = pb.d_stiles;
+  f.n_tiles = pb.n_stiles;
+  f.tgt32 = pb.d_tgt32;
+  f.eqpt32 = pb.d_eqpt32;
+  f.q32 = pb.d_eqq32;
+  f.centers = pb.d_centers;
+  f.free_ids = pb.d_free;
+  f.near_off = pb.d_near_off;
+  f.near_idx = pb.d_near_idx;
+  f.n_free = pb.n_free;
+  f.n_eq = pb.n_eq;
+  f.n_splits = pb.n_splits_eq;
+  f.T = pb.T;
+  f.part32 = pb.d_part32;
+  SMFS_HIP(launch_far_eq_f32(f, s));
+  if (pb.prof && (rc = record_event(pb, s, e[5]))) return rc;
+  if (pb.prof) {
+    pb.ev_pinv.emplace_back(e[0], e[1]);
+    pb.ev_eqq.emplace_back(e[1], e[2]);
+    pb.ev_mixed64.emplace_back(e[2], e[3]);
+    pb.ev_eqnear.emplace_back(e[3], e[4]);
+    pb.ev_eqfar.emplace_back(e[4], e[5]);
+  }
+  SMFS_HIP(launch_reduce_epilogue(3 * pb.T, pb.n_splits + 1, pb.d_part, pb.n_splits_eq, pb.d_part32, mu, pb.d_sw,
+                                  1.0 / (8.0 * kPi * pb.prm.mu), y, s));
+  return SMFS_OK;
+}
+
 int apply(Problem &pb, const double *mu, double *y, int precision, hipStream_t s) {
+  if (precision == SMFS_MIXED_EQ) {
+    if (pb.prm.eq_points <= 0) {
+      set_error("SMFS_MIXED_EQ needs eq_points > 0");
+      return SMFS_E_INVALID_ARG;
+    }
+    // without contact-free spheres nothing is approximated: the FP64 product
+    if (eq_enabled(pb)) return apply_eq(pb, mu, y, s);
+    precision = SMFS_FP64;
+  }
   const bool mixed = is_mixed(precision) && pb.n_free > 0 && pb.fac32_ready;
   size_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
   int rc;
@@ -837,6 +941,11 @@ int smfs_params_default(smfs_params *p) {
   p->gmres_restart = 400;
   p->gmres_check_every = 25;
   p->svd_method = SMFS_SVD_ROCSOLVER;
+  p->eq_points = 200;
+  p->eq_radius = 1.0;
+  p->eq_check_radius = 2.5;
+  p->eq_separation = 3.5;
+  p->eq_rcond = 1e-12;
   return SMFS_OK;
 }
 
@@ -851,6 +960,10 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
       !(p->mu > 0) || !(p->trunc_rel >= 0) || p->gmres_restart <= 0 || p->gmres_max_it <= 0 ||
       p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 || p->gmres_check_every < 0 ||
       (p->svd_method != SMFS_SVD_JACOBI && p->svd_method != SMFS_SVD_ROCSOLVER) ||
+      p->eq_points < 0 || p->eq_points > 4096 ||
+      (p->eq_points > 0 && !(p->eq_radius > 0 && p->eq_check_radius > p->eq_radius &&
+                             p->eq_separation >= p->eq_check_radius + 1.0 && p->eq_rcond > 0 &&
+                             p->eq_rcond < 1)) ||
       !valid_precision(p->precision)) {
     set_error("smfs_problem_create: invalid parameter");
     return SMFS_E_INVALID_ARG;
@@ -907,6 +1020,11 @@ int smfs_problem_sizes(const smfs_problem *pb, smfs_sizes *s) {
   s->workspace_bytes = pb->need_bytes;
   s->factor_bytes = pb->factor_bytes;
   s->svd_sweeps = pb->svd_sweeps;
+  if (pb->n_eq > 0) {   // set when the form is on and some sphere is contact-free
+    s->eq_far_pairs = pb->pairs_eq_far;
+    s->eq_exact_pairs = pb->pairs_eq_exact;
+    s->eq_near_spheres = (int64_t)pb->near_idx.size();
+  }
   return SMFS_OK;
 }
 
@@ -1183,13 +1301,153 @@ int setup_factors(Problem &pb, char *scratch, size_t scratch_bytes, hipStream_t 
   return rank_tables(pb, s);
 }
 
+// Scratch regions of the equivalent-source fit (bytes, 256-aligned each):
+// rocSOLVER/rocBLAS work, the point sets, K(check, equivalent) (m x n),
+// K(check, proxies) (m x cp), sigma, U, V^T, the superdiagonal, info and
+// the intermediate product (n x cp); m = 6 n_eq, n = 3 n_eq, cp = 3 N.
+struct EqPlan {
+  size_t work = 0, pts = 0, kce = 0, kcp = 0, sv = 0, u = 0, vt = 0, e = 0, info = 0, t1 = 0, total = 0;
+};
+
+int eq_plan(Problem &pb, EqPlan &q) {
+  q = EqPlan{};
+  if (!eq_enabled(pb)) return SMFS_OK;
+  int rc = ensure_rocblas(pb);
+  if (rc) return rc;
+  rocblas_handle h = (rocblas_handle)pb.rocblas;
+  const int ne = pb.n_eq, nc = 2 * ne, np = pb.prm.n_proxy;
+  const int m = 3 * nc, n = 3 * ne, cp = 3 * np;
+  double *fake = reinterpret_cast<double *>((uintptr_t)4096);
+  size_t w1 = 0, w2 = 0;
+  rocblas_start_device_memory_size_query(h);
+  rocblas_status q1 = rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_singular, m, n, fake, m, fake, fake,
+                                       m, fake, n, fake, rocblas_outofplace, reinterpret_cast<rocblas_int *>(fake));
+  rocblas_stop_device_memory_size_query(h, &w1);
+  const double one = 1.0, zero = 0.0;
+  rocblas_start_device_memory_size_query(h);
+  rocblas_status q2 = rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, cp, m, &one, fake, m,
+                                    fake, m, &zero, fake, n);
+  rocblas_stop_device_memory_size_query(h, &w2);
+  auto ok = [](rocblas_status x) {
+    return x == rocblas_status_success || x == rocblas_status_size_increased || x == rocblas_status_size_unchanged;
+  };
+  if (!ok(q1) || !ok(q2)) {
+    set_error("far-field set-up: workspace query failed");
+    return SMFS_E_SVD;
+  }
+  q.work = align_up(std::max(w1, w2));
+  q.pts = align_up(sizeof(double) * 3 * (size_t)(nc + ne + np));
+  q.kce = align_up(sizeof(double) * (size_t)m * n);
+  q.kcp = align_up(sizeof(double) * (size_t)m * cp);
+  q.sv = align_up(sizeof(double) * (size_t)n);
+  q.u = align_up(sizeof(double) * (size_t)m * n);
+  q.vt = align_up(sizeof(double) * (size_t)n * n);
+  q.e = align_up(sizeof(double) * (size_t)n);
+  q.info = align_up(sizeof(rocblas_int));
+  q.t1 = align_up(sizeof(double) * (size_t)n * cp);
+  q.total = q.work + q.pts + q.kce + q.kcp + q.sv + q.u + q.vt + q.e + q.info + q.t1;
+  return SMFS_OK;
+}
+
+// E = K_ce^+ K_cp for the contact-free proxies (the map from proxy to
+// equivalent strengths), into the workspace; the pseudo-inverse keeps the
+// singular values of K_ce above eq_rcond sigma_1.
+int setup_far_field(Problem &pb, char *scratch, size_t scratch_bytes, hipStream_t s) {
+  pb.eq_ready = false;
+  if (!eq_enabled(pb)) return SMFS_OK;
+  EqPlan q;
+  int rc = eq_plan(pb, q);
+  if (rc) return rc;
+  if (scratch_bytes < q.total) {
+    set_error("smfs_setup_far_field: scratch of " + std::to_string(scratch_bytes) + " bytes, need " +
+              std::to_string(q.total));
+    return SMFS_E_NOMEM;
+  }
+  rocblas_handle h = (rocblas_handle)pb.rocblas;
+  const int ne = pb.n_eq, nc = 2 * ne, np = pb.prm.n_proxy;
+  const int m = 3 * nc, n = 3 * ne, cp = 3 * np;
+  char *o = scratch;
+  char *work = o; o += q.work;
+  double *pts = (double *)o; o += q.pts;
+  double *Kce = (double *)o; o += q.kce;
+  double *Kcp = (double *)o; o += q.kcp;
+  double *sv = (double *)o; o += q.sv;
+  double *U = (double *)o; o += q.u;
+  double *Vt = (double *)o; o += q.vt;
+  double *E = (double *)o; o += q.e;
+  rocblas_int *info = (rocblas_int *)o; o += q.info;
+  double *T1 = (double *)o; o += q.t1;
+  // check points, equivalent points, the proxies of a contact-free sphere
+  // relative to its centre (host)
+  std::vector<double> xc, ye, h_pts;
+  spiral_points(nc, pb.prm.eq_check_radius * pb.a, xc);
+  spiral_points(ne, pb.prm.eq_radius * pb.a, ye);
+  int kf = 0;
+  while (!pb.contacts[kf].empty()) ++kf;
+  if (pb.koff[0][kf + 1] - pb.koff[0][kf] != np) {
+    set_error("far-field set-up: a contact-free sphere without n_proxy proxies");
+    return SMFS_E_INVALID_ARG;
+  }
+  h_pts.insert(h_pts.end(), xc.begin(), xc.end());
+  h_pts.insert(h_pts.end(), ye.begin(), ye.end());
+  for (int64_t j = pb.koff[0][kf]; j < pb.koff[0][kf + 1]; ++j)
+    for (int c = 0; c < 3; ++c) h_pts.push_back(pb.src[3 * j + c] - pb.centers[3 * kf + c]);
+  SMFS_HIP(hipMemcpyAsync(pts, h_pts.data(), 8 * h_pts.size(), hipMemcpyHostToDevice, s));
+  const double *dxc = pts, *dye = pts + 3 * nc, *dyp = pts + 3 * (nc + ne);
+  SMFS_HIP(launch_stokeslet_matrix(dxc, nc, dye, ne, Kce, s));
+  SMFS_HIP(launch_stokeslet_matrix(dxc, nc, dyp, np, Kcp, s));
+  rocblas_set_stream(h, s);
+  if (rocblas_set_workspace(h, work, q.work) != rocblas_status_success) {
+    set_error("far-field set-up: rocblas_set_workspace failed");
+    return SMFS_E_DEVICE;
+  }
+  struct Reset {
+    rocblas_handle h;
+    ~Reset() { (void)rocblas_set_workspace(h, nullptr, 0); }
+  } reset{h};
+  if (rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_singular, m, n, Kce, m, sv, U, m, Vt, n, E,
+                       rocblas_outofplace, info) != rocblas_status_success) {
+    set_error("far-field set-up: gesvd failed");
+    return SMFS_E_SVD;
+  }
+  std::vector<double> hs(n);
+  rocblas_int hinfo = 0;
+  SMFS_HIP(hipMemcpyAsync(hs.data(), sv, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  SMFS_HIP(hipStreamSynchronize(s));
+  if (hinfo != 0 || !(hs[0] > 0) || !std::isfinite(hs[0])) {
+    set_error("far-field set-up: SVD did not converge");
+    return SMFS_E_SVD;
+  }
+  int r = 0;
+  while (r < n && hs[r] > pb.prm.eq_rcond * hs[0]) ++r;
+  // T1 = (U_r Sigma_r^-1)^T K_cp (r x cp, ld n), E = V_r T1 (n x cp, ld n)
+  SMFS_HIP(launch_scale_cols(U, m, r, sv, s));
+  const double one = 1.0, zero = 0.0;
+  if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, r, cp, m, &one, U, m, Kcp, m, &zero,
+                    T1, n) != rocblas_status_success ||
+      rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, cp, r, &one, Vt, n, T1, n, &zero,
+                    pb.d_eqE, n) != rocblas_status_success) {
+    set_error("far-field set-up: gemm failed");
+    return SMFS_E_DEVICE;
+  }
+  SMFS_HIP(hipStreamSynchronize(s));
+  pb.eq_ready = true;
+  return SMFS_OK;
+}
+
 }  // namespace smfs
 
 extern "C" {
 
 int smfs_setup_workspace_bytes(smfs_problem *pb, size_t *bytes) {
   if (!pb || !bytes) { set_error("smfs_setup_workspace_bytes: null argument"); return SMFS_E_INVALID_ARG; }
-  return setup_scratch_bytes(*pb, *bytes);
+  int rc = setup_scratch_bytes(*pb, *bytes);
+  if (rc) return rc;
+  EqPlan q;
+  if ((rc = eq_plan(*pb, q))) return rc;
+  *bytes = std::max(*bytes, q.total);
+  return SMFS_OK;
 }
 
 int smfs_setup(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream) {
@@ -1198,7 +1456,27 @@ int smfs_setup(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_strea
     set_error("smfs_setup: scratch must be a 256-byte aligned device pointer");
     return SMFS_E_INVALID_ARG;
   }
-  return setup_factors(*pb, (char *)scratch, scratch_bytes, (hipStream_t)stream);
+  int rc = setup_factors(*pb, (char *)scratch, scratch_bytes, (hipStream_t)stream);
+  if (rc) return rc;
+  return setup_far_field(*pb, (char *)scratch, scratch_bytes, (hipStream_t)stream);
+}
+
+int smfs_far_field_workspace_bytes(smfs_problem *pb, size_t *bytes) {
+  if (!pb || !bytes) { set_error("smfs_far_field_workspace_bytes: null argument"); return SMFS_E_INVALID_ARG; }
+  EqPlan q;
+  int rc = eq_plan(*pb, q);
+  *bytes = q.total;
+  return rc;
+}
+
+int smfs_setup_far_field(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream) {
+  if (!pb || !pb->bound) { set_error("smfs_setup_far_field: problem not bound"); return SMFS_E_STATE; }
+  if (!eq_enabled(*pb)) return SMFS_OK;
+  if (!scratch || ((uintptr_t)scratch) % kAlign) {
+    set_error("smfs_setup_far_field: scratch must be a 256-byte aligned device pointer");
+    return SMFS_E_INVALID_ARG;
+  }
+  return setup_far_field(*pb, (char *)scratch, scratch_bytes, (hipStream_t)stream);
 }
 
 int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double *U,
@@ -1306,6 +1584,9 @@ int smfs_profile(smfs_problem *pb, int32_t enable) {
     pb->ev_far32.clear();
     pb->ev_bdirect.clear();
     pb->ev_bpinv.clear();
+    pb->ev_eqfar.clear();
+    pb->ev_eqnear.clear();
+    pb->ev_eqq.clear();
     pb->prof_nrhs = 0;
   }
   pb->prof = enable != 0;
@@ -1327,8 +1608,20 @@ int smfs_profile_read(smfs_problem *pb, smfs_kernel_stats *st) {
   int rc;
   if ((rc = total(pb->ev_direct, st->direct_ms)) || (rc = total(pb->ev_pinv, st->pinv_ms)) ||
       (rc = total(pb->ev_mixed64, st->mixed64_ms)) || (rc = total(pb->ev_far32, st->far32_ms)) ||
-      (rc = total(pb->ev_bdirect, st->bdirect_ms)) || (rc = total(pb->ev_bpinv, st->bpinv_ms)))
+      (rc = total(pb->ev_bdirect, st->bdirect_ms)) || (rc = total(pb->ev_bpinv, st->bpinv_ms)) ||
+      (rc = total(pb->ev_eqfar, st->eq_far_ms)) || (rc = total(pb->ev_eqnear, st->eq_near_ms)) ||
+      (rc = total(pb->ev_eqq, st->eq_strength_ms)))
     return rc;
+  st->eq_launches = (int64_t)pb->ev_eqfar.size();
+  st->eq_far_flops = 28.0 * pb->pairs_eq_far;
+  {
+    // near proxies: every target sphere against its near list's proxies
+    double nearp = 0.0;
+    for (int k = 0; k < pb->P && !pb->near_off.empty(); ++k)
+      nearp += (double)(pb->toff[k + 1] - pb->toff[k]) * (pb->near_off[k + 1] - pb->near_off[k]) *
+               pb->prm.n_proxy;
+    st->eq_near_flops = 28.0 * nearp;
+  }
   st->mixed64_launches = (int64_t)pb->ev_mixed64.size();
   st->direct_launches = (int64_t)pb->ev_direct.size();
   st->pinv_launches = (int64_t)pb->ev_pinv.size();
@@ -1496,6 +1789,12 @@ void fill_out(Problem &pb, const SolveStats &ss, const double *post, int precisi
   out->pair_evals = (int64_t)(ss.applies + ss.applies64) * pb.pairs_per_apply +
                     ((out->u_check) ? pb.C * pb.S : 0);
   out->pair_evals_f32 = mixed ? (int64_t)ss.applies * pb.pairs_f32 : 0;
+  if (precision == SMFS_MIXED_EQ && eq_enabled(pb)) {
+    // exact FP64 pairs and FP32 equivalent-source pairs of the EQ products
+    out->pair_evals = (int64_t)ss.applies64 * pb.pairs_per_apply + (int64_t)ss.applies * pb.pairs_eq_exact +
+                      ((out->u_check) ? pb.C * pb.S : 0);
+    out->pair_evals_f32 = (int64_t)ss.applies * pb.pairs_eq_far;
+  }
 }
 
 }  // namespace smfs

@@ -350,6 +350,10 @@ int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y
   SMFS_READY(pb);
   if (!mu || !y || ld < 3 * pb->T) { set_error("smfs_apply_block: bad vectors"); return SMFS_E_INVALID_ARG; }
   if (!valid_precision(precision)) { set_error("smfs_apply_block: bad precision"); return SMFS_E_INVALID_ARG; }
+  if (precision == SMFS_MIXED_EQ) {
+    set_error("smfs_apply_block: SMFS_MIXED_EQ has no block form");
+    return SMFS_E_UNSUPPORTED;
+  }
   BlockLayout L;
   int rc = check_ws(*pb, nrhs, 0, ws, ws_bytes, L);
   if (rc) return rc;
@@ -365,6 +369,10 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
   if (!rbm || !out || restart <= 0 || restart > 20000) {
     set_error("smfs_solve_resistance_block: bad argument");
     return SMFS_E_INVALID_ARG;
+  }
+  if (pb->prm.precision == SMFS_MIXED_EQ) {
+    set_error("smfs_solve_resistance_block: SMFS_MIXED_EQ has no block form");
+    return SMFS_E_UNSUPPORTED;
   }
   BlockLayout L;
   int rc = check_ws(*pb, nrhs, restart, ws, ws_bytes, L);

@@ -11,6 +11,7 @@
 //    cos(theta_j) = 1 - j (1 - cos beta) / M_cap (the printed eq. thetacap
 //    does not give caps of half-angle beta);
 //  - weight of a node = area of its set / node count (Remark left-precond).
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -248,6 +249,61 @@ int build_geometry(Problem &pb) {
   }
   pb.pairs_per_apply = pb.pairs_kind[0] + pb.pairs_kind[1] + pb.pairs_kind[2];
   return SMFS_OK;
+}
+
+// n points of the Fibonacci spiral on the sphere of radius r about the
+// origin (the proxies' spiral), n x 3.
+void spiral_points(int n, double r, std::vector<double> &out) {
+  out.assign(3 * (size_t)n, 0.0);
+  for (int j = 1; j <= n; ++j) {
+    double u[3];
+    spiral(j, n, 0.0, u);
+    for (int c = 0; c < 3; ++c) out[3 * (size_t)(j - 1) + c] = r * u[c];
+  }
+}
+
+// Near lists of the equivalent-source far field: for every sphere k, the
+// contact-free spheres k' != k (as free indices, ascending) whose centres
+// lie closer than sep; the pair counts of the SMFS_MIXED_EQ product.
+// Spheres are swept in order of x, so only candidates within sep in x are
+// tested.
+void build_near_lists(Problem &pb, double sep) {
+  const int P = pb.P;
+  std::vector<int32_t> free_of(P, -1);
+  int32_t nf = 0;
+  for (int k = 0; k < P; ++k)
+    if (pb.contacts[k].empty()) free_of[k] = nf++;
+  std::vector<int> ord(P);
+  for (int k = 0; k < P; ++k) ord[k] = k;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return pb.centers[3 * x] < pb.centers[3 * y]; });
+  std::vector<std::vector<int32_t>> lists(P);
+  const double s2 = sep * sep;
+  for (int a = 0; a < P; ++a) {
+    const int k = ord[a];
+    const double *ck = &pb.centers[3 * k];
+    for (int b = a + 1; b < P; ++b) {
+      const int ks = ord[b];
+      const double *cs = &pb.centers[3 * ks];
+      if (cs[0] - ck[0] >= sep) break;
+      const double dx = ck[0] - cs[0], dy = ck[1] - cs[1], dz = ck[2] - cs[2];
+      if (dx * dx + dy * dy + dz * dz >= s2) continue;
+      if (free_of[ks] >= 0) lists[k].push_back(free_of[ks]);
+      if (free_of[k] >= 0) lists[ks].push_back(free_of[k]);
+    }
+  }
+  pb.near_off.assign(P + 1, 0);
+  pb.near_idx.clear();
+  pb.pairs_eq_far = pb.pairs_eq_exact = 0;
+  for (int k = 0; k < P; ++k) {
+    std::sort(lists[k].begin(), lists[k].end());
+    pb.near_idx.insert(pb.near_idx.end(), lists[k].begin(), lists[k].end());
+    pb.near_off[k + 1] = (int32_t)pb.near_idx.size();
+    const int64_t Mk = pb.toff[k + 1] - pb.toff[k];
+    const int64_t far = nf - (free_of[k] >= 0 ? 1 : 0) - (int64_t)lists[k].size();
+    pb.pairs_eq_far += Mk * far * pb.n_eq;
+    pb.pairs_eq_exact += Mk * far * pb.prm.n_proxy;   // subtracted below
+  }
+  pb.pairs_eq_exact = pb.pairs_per_apply - pb.pairs_eq_exact;
 }
 
 }  // namespace smfs

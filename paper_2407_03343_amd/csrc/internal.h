@@ -137,6 +137,16 @@ struct Problem {
   bool skip_shared = false;                // setup leaves factor 0 (imported) alone
   int32_t svd_sweeps = 0;                  // Jacobi sweeps of the last set-up (largest over calls)
   BgFlow bg{};                             // background flow of the boundary data (off: quiescent)
+  // equivalent-source far field (SMFS_MIXED_EQ)
+  int32_t n_eq = 0;                        // equivalent points per sphere (0: off)
+  std::vector<int32_t> near_off, near_idx; // per sphere: near contact-free spheres (free indices)
+  double *d_eqE = nullptr;                 // 3 n_eq x 3 n_proxy, column-major
+  float *d_eqq32 = nullptr;                // n_free x 3 n_eq equivalent strengths
+  float *d_eqpt32 = nullptr;               // n_eq x 3 points relative to a centre
+  int32_t *d_near_off = nullptr, *d_near_idx = nullptr;
+  int32_t n_splits_eq = 0;
+  bool eq_ready = false;
+  int64_t pairs_eq_far = 0, pairs_eq_exact = 0;
   double *d_kry = nullptr, *d_vec = nullptr, *d_red = nullptr;
   int64_t n_tiles = 0, n_utask = 0, n_vtask = 0, n_vmap = 0;
   int64_t n_stiles = 0;
@@ -163,11 +173,14 @@ struct Problem {
   size_t ev_used = 0;
   std::vector<std::pair<size_t, size_t>> ev_direct, ev_pinv, ev_mixed64, ev_far32;
   std::vector<std::pair<size_t, size_t>> ev_bdirect, ev_bpinv;
+  std::vector<std::pair<size_t, size_t>> ev_eqfar, ev_eqnear, ev_eqq;
   int32_t prof_nrhs = 0;                   // right-hand sides of the profiled block products
 };
 
 // geometry.cpp
 int build_geometry(Problem &pb);
+void spiral_points(int n, double r, std::vector<double> &out);
+void build_near_lists(Problem &pb, double sep);
 // tables.cpp
 void build_tiles(const Problem &pb, std::vector<int4> &tiles, int tile_targets);
 size_t workspace_layout(Problem &pb, bool assign);
@@ -179,6 +192,7 @@ int record_event(Problem &pb, hipStream_t s, size_t &idx);
 int32_t direct_splits(int64_t n_tiles, int64_t S);
 bool valid_precision(int p);
 bool is_mixed(int p);
+bool eq_enabled(const Problem &pb);
 // svd.hip: the device Jacobi SVD (QR, one-sided Jacobi on R, U = Q U_R)
 struct JacPlan {
   int w = 8, rows = 4, npad = 0, nbk = 0, npairs = 0;

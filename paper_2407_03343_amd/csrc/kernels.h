@@ -57,6 +57,46 @@ hipError_t launch_far_f32(const Far32Args &a, hipStream_t s);
 // The far-field arguments of a bound problem (api.hip).
 Far32Args far32_args(Problem &pb);
 
+// Equivalent-source far field (SMFS_MIXED_EQ): FP32 sum over the
+// equivalent Stokeslets of every contact-free sphere that is neither the
+// tile's own sphere nor in its near list.
+struct EqArgs {
+  const int4 *tiles;        // one-sphere tiles
+  int64_t n_tiles;
+  const float *tgt32;       // targets minus own centre, T x 3
+  const float *eqpt32;      // equivalent points relative to a centre, n_eq x 3
+  const float *q32;         // equivalent strengths, free index major: n_free x n_eq x 3
+  const double *centers;    // P x 3
+  const int32_t *free_ids;  // free index -> sphere
+  const int32_t *near_off;  // P + 1: near list of each target sphere
+  const int32_t *near_idx;  // free indices, ascending per sphere
+  int32_t n_free, n_eq, n_splits;
+  int64_t T;
+  float *part32;            // [split][T][3]
+};
+hipError_t launch_far_eq_f32(const EqArgs &a, hipStream_t s);
+// FP64 sum of the proxies of each tile's near contact-free spheres into one
+// partial slice (out, T x 3); d supplies targets, sources, strengths, meta.
+struct NearArgs {
+  DirectArgs d;
+  const int4 *tiles;        // one-sphere tiles
+  int64_t n_tiles;
+  const int32_t *free_ids;
+  const int32_t *near_off;
+  const int32_t *near_idx;
+  double *out;
+};
+hipError_t launch_near_f64(const NearArgs &a, hipStream_t s);
+// q32[q][r] = (float) sum_i E[r + i rows] lambda_hat(proxies of free sphere q)[i]
+hipError_t launch_eq_strengths(const double *E, int32_t rows, int32_t cols, const double *lam,
+                               const SphereMeta *meta, const int32_t *free_ids, int32_t n_free, float *q32,
+                               hipStream_t s);
+// Stokeslet matrix without 1/(8 pi mu), 3 nx x 3 ny column-major (set-up)
+hipError_t launch_stokeslet_matrix(const double *x, int32_t nx, const double *y, int32_t ny, double *out,
+                                   hipStream_t s);
+// A[:, c] /= s[c] (column-major, ld rows)
+hipError_t launch_scale_cols(double *A, int32_t rows, int32_t cols, const double *sv, hipStream_t s);
+
 // y[i] = base[i] + sw[i/3] * c0 * (sum_s part[s][i] + sum_s part32[s][i])
 // (base, sw, part32 nullable)
 hipError_t launch_reduce_epilogue(int64_t n3, int32_t n_splits, const double *part, int32_t ns32,

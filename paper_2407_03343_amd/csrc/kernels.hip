@@ -461,6 +461,192 @@ __global__ void k_reduce_epilogue(int64_t n3, int32_t ns, const double *__restri
   y[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Equivalent-source far field (the SMFS_MIXED_EQ product).  For a target
+// sphere k and a contact-free source sphere k' at centre separation of at
+// least eq_separation radii, the field of the N proxy Stokeslets of k' is
+// replaced by that of n_eq equivalent Stokeslets q = E lambda_hat_k' (E
+// fitted in FP64 at set-up on a check sphere around k'; the same for every
+// contact-free sphere).  Pairs with a contact-free source closer than that
+// (the near list of k) stay exact, in FP64.  The equivalent strengths are
+// of the size of the field itself, not of the proxies' cancelling
+// strengths, so their FP32 sum keeps FP32's relative accuracy.
+
+// q32[q][r] = (float) sum_i E[r + i rows] lambda_hat(proxies of free sphere q)[i]:
+// one thread per row r and four spheres; the strengths are wave-uniform.
+__global__ __launch_bounds__(256) void k_eq_strengths(const double *__restrict__ E, int32_t rows, int32_t cols,
+                                                      const double *__restrict__ lam,
+                                                      const SphereMeta *__restrict__ meta,
+                                                      const int32_t *__restrict__ free_ids, int32_t n_free,
+                                                      float *__restrict__ q32) {
+  constexpr int kQ = 4;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int qb = blockIdx.y * kQ;
+  ConstPtr l[kQ];
+#pragma unroll
+  for (int u = 0; u < kQ; ++u) {
+    const int q = min(qb + u, n_free - 1);
+    const int ks = uniform(free_ids[q]);
+    l[u] = (ConstPtr)(lam + 3 * meta[ks].k0[0]);
+  }
+  double acc[kQ] = {0.0, 0.0, 0.0, 0.0};
+  const int rr = r < rows ? r : 0;
+  for (int i = 0; i < cols; ++i) {
+    const double e = E[(int64_t)i * rows + rr];
+#pragma unroll
+    for (int u = 0; u < kQ; ++u) acc[u] = fma(e, l[u][i], acc[u]);
+  }
+  if (r >= rows) return;
+#pragma unroll
+  for (int u = 0; u < kQ; ++u)
+    if (qb + u < n_free) q32[(int64_t)(qb + u) * rows + r] = (float)acc[u];
+}
+
+// One wave of the FP32 equivalent-source sum: tile `tile`, split `split`
+// of the contact-free spheres (in free-index order, skipping the tile's own
+// sphere and its near list).
+template <int kTpl>
+__device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int split) {
+  const int lane = threadIdx.x & (kWave - 1);
+  if (tile >= A.n_tiles) return;
+  const int4 tl = A.tiles[tile];
+  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  if (tc <= 0) return;
+  float tx[kTpl], ty[kTpl], tz[kTpl], ax[kTpl], ay[kTpl], az[kTpl];
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
+    tx[p] = A.tgt32[3 * ti];
+    ty[p] = A.tgt32[3 * ti + 1];
+    tz[p] = A.tgt32[3 * ti + 2];
+    ax[p] = ay[p] = az[p] = 0.f;
+  }
+  const ConstPtr32 pts = (ConstPtr32)A.eqpt32;
+  const double ckx = A.centers[3 * k], cky = A.centers[3 * k + 1], ckz = A.centers[3 * k + 2];
+  const int q0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
+  const int q1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
+  // the near list of k is ascending: skip its entries below q0
+  int e = uniform(A.near_off[k]);
+  const int e1 = uniform(A.near_off[k + 1]);
+  while (e < e1 && uniform(A.near_idx[e]) < q0) ++e;
+  int next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
+  const int ne = A.n_eq;
+  for (int q = q0; q < q1; ++q) {
+    if (q == next) {
+      ++e;
+      next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
+      continue;
+    }
+    const int ks = uniform(A.free_ids[q]);
+    if (ks == k) continue;
+    const float dx = (float)(A.centers[3 * ks] - ckx), dy = (float)(A.centers[3 * ks + 1] - cky),
+                dz = (float)(A.centers[3 * ks + 2] - ckz);
+    float ux[kTpl], uy[kTpl], uz[kTpl];
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      ux[p] = tx[p] - dx;
+      uy[p] = ty[p] - dy;
+      uz[p] = tz[p] - dz;
+    }
+    const ConstPtr32 str = (ConstPtr32)(A.q32 + (int64_t)q * 3 * ne);
+    int j = 0;
+    for (; j + 1 < ne; j += 2) {
+      const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
+      const float s0x = ps[0], s0y = ps[1], s0z = ps[2], s1x = ps[3], s1y = ps[4], s1z = ps[5];
+      const float f0x = pf[0], f0y = pf[1], f0z = pf[2], f1x = pf[3], f1y = pf[4], f1z = pf[5];
+      far_pair<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az);
+      far_pair<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az);
+    }
+    if (j < ne) {
+      const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
+      far_pair<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az);
+    }
+  }
+  float *out = A.part32 + (int64_t)split * A.T * 3;
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    if (i < tc) {
+      const int64_t o = 3 * ((int64_t)t0 + i);
+      out[o] = ax[p];
+      out[o + 1] = ay[p];
+      out[o + 2] = az[p];
+    }
+  }
+}
+
+template <int kTpl>
+__global__ __launch_bounds__(kBlock) void k_far_eq_f32(EqArgs A) {
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  far_eq_wave<kTpl>(A, tile, blockIdx.y);
+}
+
+// FP64 sum of the proxies of the near contact-free spheres of each tile's
+// sphere (its near list), one partial slice: the same pair arithmetic as
+// the direct sum.
+template <int kTpl>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIRECT_WAVES, 8))) void k_near_f64(
+    NearArgs N) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (tile >= N.n_tiles) return;
+  const int4 tl = N.tiles[tile];
+  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  if (tc <= 0) return;
+  Acc<kTpl> acc;
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
+    acc.tx[p] = N.d.tgt[3 * ti];
+    acc.ty[p] = N.d.tgt[3 * ti + 1];
+    acc.tz[p] = N.d.tgt[3 * ti + 2];
+    acc.ax[p] = acc.ay[p] = acc.az[p] = 0.0;
+  }
+  const int e0 = uniform(N.near_off[k]), e1 = uniform(N.near_off[k + 1]);
+  for (int e = e0; e < e1; ++e) {
+    const int ks = uniform(N.free_ids[uniform(N.near_idx[e])]);
+    const int j0 = uniform((int)N.d.meta[ks].k0[0]);
+    const int j1 = j0 + uniform(N.d.meta[ks].kn[0]);
+    run_block<kTpl, false>(0, N.d, j0, j1, acc);
+  }
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    if (i < tc) {
+      const int64_t o = 3 * ((int64_t)t0 + i);
+      N.out[o] = 0.5 * acc.ax[p];  // the pair functions add twice the velocity
+      N.out[o + 1] = 0.5 * acc.ay[p];
+      N.out[o + 2] = 0.5 * acc.az[p];
+    }
+  }
+}
+
+// Set-up of the equivalent sources: the Stokeslet matrix K(x, y) without
+// the factor 1/(8 pi mu) (3 nx x 3 ny, column-major, ld 3 nx); one thread
+// per point pair.
+__global__ void k_stokeslet_matrix(const double *__restrict__ x, int32_t nx, const double *__restrict__ y,
+                                   int32_t ny, double *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nx * ny) return;
+  const int i = (int)(idx % nx), j = (int)(idx / nx);
+  const double r[3] = {x[3 * i] - y[3 * j], x[3 * i + 1] - y[3 * j + 1], x[3 * i + 2] - y[3 * j + 2]};
+  const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const double ri = 1.0 / sqrt(r2);
+  const int64_t ld = 3 * (int64_t)nx;
+  for (int b = 0; b < 3; ++b)
+    for (int a = 0; a < 3; ++a)
+      out[(3 * (int64_t)j + b) * ld + 3 * i + a] = ((a == b ? 1.0 : 0.0) + r[a] * r[b] / r2) * ri;
+}
+
+// A[:, c] /= s[c] for c < cols (column-major, ld rows).
+__global__ void k_scale_cols(double *A, int32_t rows, int32_t cols, const double *s) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)rows * cols) return;
+  A[idx] /= s[idx / rows];
+}
+
 // Packed index of local source jl of sphere m (local order: proxy
 // Stokeslets, image Stokeslets, rotlets, dipoles).
 __device__ __forceinline__ int64_t packed_index(const SphereMeta &m, int jl) {
@@ -1042,6 +1228,44 @@ hipError_t launch_far_f32(const Far32Args &a, hipStream_t s) {
   if (a.n_tiles == 0 || a.n_splits == 0) return hipSuccess;
   dim3 grid((unsigned)((a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)a.n_splits);
   hipLaunchKernelGGL((k_far_f32<kDirectTpl>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_eq_strengths(const double *E, int32_t rows, int32_t cols, const double *lam,
+                               const SphereMeta *meta, const int32_t *free_ids, int32_t n_free, float *q32,
+                               hipStream_t s) {
+  if (n_free <= 0 || rows <= 0) return hipSuccess;
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)((n_free + 3) / 4));
+  hipLaunchKernelGGL(k_eq_strengths, grid, dim3(256), 0, s, E, rows, cols, lam, meta, free_ids, n_free, q32);
+  return hipGetLastError();
+}
+
+hipError_t launch_far_eq_f32(const EqArgs &a, hipStream_t s) {
+  if (a.n_tiles == 0 || a.n_splits == 0) return hipSuccess;
+  dim3 grid((unsigned)((a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)a.n_splits);
+  hipLaunchKernelGGL((k_far_eq_f32<kDirectTpl>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_near_f64(const NearArgs &a, hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  dim3 grid((unsigned)((a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipLaunchKernelGGL((k_near_f64<kDirectTpl>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stokeslet_matrix(const double *x, int32_t nx, const double *y, int32_t ny, double *out,
+                                   hipStream_t s) {
+  const int64_t n = (int64_t)nx * ny;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stokeslet_matrix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, nx, y, ny, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(double *A, int32_t rows, int32_t cols, const double *sv, hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, rows, cols, sv);
   return hipGetLastError();
 }
 

@@ -21,14 +21,14 @@ SMFS_GAP_BELOW_VALIDATED = 2
 SMFS_STAGNATED = 3
 SMFS_E_AGAIN = -8
 SOLVE_WARNINGS = (SMFS_OK, SMFS_NOT_CONVERGED, SMFS_STAGNATED)
-SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR = 0, 1, 2
+SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR, SMFS_MIXED_EQ = 0, 1, 2, 3
 SMFS_SVD_JACOBI, SMFS_SVD_ROCSOLVER = 0, 1
 KIND_S, KIND_R, KIND_D = 1, 2, 4
 
 EXPORTED = [
     "smfs_params_default", "smfs_problem_create", "smfs_problem_destroy", "smfs_problem_sizes",
     "smfs_export_nodes", "smfs_sphere_factor", "smfs_factor_info", "smfs_bind", "smfs_setup",
-    "smfs_setup_workspace_bytes",
+    "smfs_setup_workspace_bytes", "smfs_far_field_workspace_bytes", "smfs_setup_far_field",
     "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs", "smfs_set_background",
     "smfs_force_torque",
     "smfs_eval_velocity", "smfs_solve_resistance", "smfs_solve_mobility", "smfs_set_solver",
@@ -52,6 +52,8 @@ class smfs_params(C.Structure):
         ("trunc_rel", C.c_double), ("mu", C.c_double), ("n_check_base", C.c_int32),
         ("precision", C.c_int32), ("gmres_tol", C.c_double), ("gmres_max_it", C.c_int32),
         ("gmres_restart", C.c_int32), ("gmres_check_every", C.c_int32), ("svd_method", C.c_int32),
+        ("eq_points", C.c_int32), ("eq_radius", C.c_double), ("eq_check_radius", C.c_double),
+        ("eq_separation", C.c_double), ("eq_rcond", C.c_double),
     ]
 
 
@@ -61,6 +63,7 @@ class smfs_sizes(C.Structure):
         ("min_gap_flag", C.c_int32), ("T", C.c_int64), ("S", C.c_int64),
         ("n_kind", C.c_int64 * 3), ("n_check", C.c_int64), ("workspace_bytes", C.c_size_t),
         ("factor_bytes", C.c_size_t), ("svd_sweeps", C.c_int32),
+        ("eq_far_pairs", C.c_int64), ("eq_exact_pairs", C.c_int64), ("eq_near_spheres", C.c_int64),
     ]
 
 
@@ -86,6 +89,8 @@ class smfs_kernel_stats(C.Structure):
         ("bdirect_launches", C.c_int64), ("bdirect_ms", C.c_double), ("bdirect_flops", C.c_double),
         ("bpinv_launches", C.c_int64), ("bpinv_ms", C.c_double), ("bpinv_flops", C.c_double),
         ("bnrhs", C.c_int32),
+        ("eq_launches", C.c_int64), ("eq_far_ms", C.c_double), ("eq_far_flops", C.c_double),
+        ("eq_near_ms", C.c_double), ("eq_near_flops", C.c_double), ("eq_strength_ms", C.c_double),
     ]
 
 
@@ -150,6 +155,8 @@ def lib():
         "smfs_bind": ([vp, vp, C.c_size_t, vp], C.c_int),
         "smfs_setup_workspace_bytes": ([vp, P(C.c_size_t)], C.c_int),
         "smfs_setup": ([vp, vp, C.c_size_t, vp], C.c_int),
+        "smfs_far_field_workspace_bytes": ([vp, P(C.c_size_t)], C.c_int),
+        "smfs_setup_far_field": ([vp, vp, C.c_size_t, vp], C.c_int),
         "smfs_import_factor": ([vp, i32, i32, vp, vp, vp, vp], C.c_int),
         "smfs_apply": ([vp, vp, vp, i32, vp], C.c_int),
         "smfs_transform": ([vp, vp, vp, vp], C.c_int),
@@ -331,6 +338,19 @@ class Problem:
         _check(lib().smfs_setup(self.h, C.c_void_p(base), n, _stream()), "smfs_setup")
         del buf
         _check(lib().smfs_problem_sizes(self.h, C.byref(self.sizes)), "smfs_problem_sizes")
+        return self
+
+    def setup_far_field(self):
+        """Fit the equivalent sources of the contact-free spheres (needed by
+        SMFS_MIXED_EQ products; smfs_setup runs it too)."""
+        import torch
+        n = C.c_size_t(0)
+        _check(lib().smfs_far_field_workspace_bytes(self.h, C.byref(n)), "smfs_far_field_workspace_bytes")
+        buf = torch.empty(int(n.value) + 256, dtype=torch.uint8, device="cuda")
+        base = (buf.data_ptr() + 255) // 256 * 256
+        _check(lib().smfs_setup_far_field(self.h, C.c_void_p(base), int(n.value), _stream()),
+               "smfs_setup_far_field")
+        del buf
         return self
 
     def import_factor(self, fid, U, sigma, V):

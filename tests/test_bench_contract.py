@@ -32,6 +32,12 @@ def test_kernel_rates():
     assert far["achieved"] == pytest.approx(5.0e11 / 7.5e-3 / 1e12)
     assert far["frac"] == pytest.approx(far["achieved"] / bench.PEAK_FP32_VALU_TFLOPS)
     assert out["mixed64"]["peak"] == bench.PEAK_FP64_VALU_TFLOPS
+    st.update(eq_launches=2, eq_far_ms=8.0, eq_far_flops=1.0e11, eq_near_ms=1.0, eq_near_flops=1.0e10)
+    out = bench.mixed_kernel_rates(st)
+    assert set(out) == {"far32", "mixed64", "eq_far", "eq_near"}
+    assert out["eq_far"]["avg_launch_ms"] == pytest.approx(4.0)
+    assert out["eq_far"]["peak"] == bench.PEAK_FP32_VALU_TFLOPS
+    assert out["eq_near"]["peak"] == bench.PEAK_FP64_VALU_TFLOPS
 
 
 def test_traffic_constant_matches_counter_summary():

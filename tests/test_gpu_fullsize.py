@@ -42,9 +42,10 @@ def _rows(g, n, seed):
 
 def test_packing2000_products_sampled(dev, oracle_pairsum_built):
     """2000 spheres at volume fraction 0.3, 5% in near-contact pairs: FP64
-    product to 1e-10 and both mixed products to 2e-4 per sphere on sampled
+    product to 1e-10 and the mixed products to 2e-4 per sphere on sampled
     rows (a random vector: the FP32 far field of 1.2 million sources with
-    cancellation, measured 7.3e-5 per sphere, 3e-6 over the whole vector)."""
+    cancellation, measured 7.3e-5 per sphere, 3e-6 over the whole vector;
+    the equivalent-source far field is held to the same bar)."""
     _say("2000-sphere packing: full-size products (FP64, mixed, mixed far), sampled rows")
     pk = wl.workload_packing2000(2000, seed=0)
     g = geo.build(pk.centers, 1.0)
@@ -52,12 +53,13 @@ def test_packing2000_products_sampled(dev, oracle_pairsum_built):
     assert (lib.T, lib.S) == (g.T, g.S)
     pbo = mfs.Problem(g)
     _random_factors(lib, pbo, 300)
+    lib.setup_far_field()
     mu = wl.random_vector(3 * g.T, 51)
     mu_d = torch.from_numpy(mu).cuda()
     rows = _rows(g, 400, 52)
     ref = mu.reshape(-1, 3)[rows] + pbo.apply_rows(pbo.transform(mu), rows, is_lambda=True)
     for name, prec, bar in (("fp64", dev.SMFS_FP64, 1e-10), ("mixed", dev.SMFS_MIXED, 2e-4),
-                            ("mixed_far", dev.SMFS_MIXED_FAR, 2e-4)):
+                            ("mixed_far", dev.SMFS_MIXED_FAR, 2e-4), ("mixed_eq", dev.SMFS_MIXED_EQ, 2e-4)):
         y = lib.apply(mu_d, precision=prec).cpu().numpy().reshape(-1, 3)
         d = _rel(y[rows], ref, g.target_sphere[rows])
         _say(f"  {name}: per-sphere rel diff {d:.3e}, whole-vector {_rel(y[rows], ref):.3e} on {rows.size} rows")
@@ -102,7 +104,7 @@ def test_packing2000_real_ranks_physical(dev, oracle_pairsum_built):
     the 1e-14 level): FP64 product to 1e-10 per sphere on sampled rows, the
     mixed products to 1e-3 per sphere (the surface-velocity bar of the mixed
     form: the FP32 far field from the rough strengths of the full-rank
-    shared factor, measured 1.5e-4)."""
+    shared factor, measured 1.5e-4), the equivalent-source form to 1e-4."""
     _say("2000-sphere packing: products with factors of the real truncated ranks")
     pk = wl.workload_packing2000(2000, seed=0)
     g = geo.build(pk.centers, 1.0)
@@ -126,13 +128,14 @@ def test_packing2000_real_ranks_physical(dev, oracle_pairsum_built):
         assert lib.factor_info(fid)["rank"] == s.size
         pbo.factors[int(pbo.factor_of[k])] = mfs.Factor(U, s, V, float(s[0]), info["cols"])
     assert contact_rank is not None and contact_rank > 1800
+    lib.setup_far_field()
     rbm = wl.random_rbm(g.P, 1, 55)[0]
     b = pbo.rhs(rbm)
     b_d = torch.from_numpy(b).cuda()
     rows = _rows(g, 400, 56)
     ref = b.reshape(-1, 3)[rows] + pbo.apply_rows(pbo.transform(b), rows, is_lambda=True)
     for name, prec, bar in (("fp64", dev.SMFS_FP64, 1e-10), ("mixed", dev.SMFS_MIXED, 1e-3),
-                            ("mixed_far", dev.SMFS_MIXED_FAR, 1e-3)):
+                            ("mixed_far", dev.SMFS_MIXED_FAR, 1e-3), ("mixed_eq", dev.SMFS_MIXED_EQ, 1e-4)):
         y = lib.apply(b_d, precision=prec).cpu().numpy().reshape(-1, 3)
         d = _rel(y[rows], ref, g.target_sphere[rows])
         _say(f"  {name}: per-sphere rel diff {d:.3e} on {rows.size} rows")

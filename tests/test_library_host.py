@@ -150,3 +150,34 @@ def test_server_memory_query():
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == 0
     cfg.max_active = 0
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -1
+
+
+def test_far_field_near_lists_and_pair_counts():
+    """The library's near lists of the equivalent-source far field (host
+    tables, no GPU) against the oracle's classification of far pairs on a
+    lattice with near and far pairs and one contact pair."""
+    from oracle import farfield as ff, geometry as geo
+    cs = np.array([[i * 3.2, j * 3.2, k * 3.2] for i in range(2) for j in range(3) for k in range(2)]
+                  + [[0.0, 0.0, -2.01]])
+    g = geo.build(cs, 1.0)
+    ep = ff.EqParams()
+    pb = smfs.Problem(cs, 1.0)
+    s = pb.sizes
+    near = far = 0
+    for k in range(g.P):
+        for ks in range(g.P):
+            if ks == k or not g.contact_free(ks):
+                continue
+            if ff.is_far(g, ep, k, ks):
+                far += g.M(k) * ep.n_eq
+            else:
+                near += 1
+    assert s.eq_near_spheres == near
+    assert s.eq_far_pairs == far
+    # exact pairs: every pair but the far proxies
+    far_proxy = far // ep.n_eq * g.params.n_proxy
+    assert s.eq_exact_pairs == pb.pairs_per_apply - far_proxy
+    # the form is off without contact-free spheres or with eq_points = 0
+    assert smfs.Problem(cs, 1.0, eq_points=0).sizes.eq_far_pairs == 0
+    with pytest.raises(smfs.SmfsError):
+        smfs.Problem(cs, 1.0, eq_separation=3.0)     # below eq_check_radius + 1
