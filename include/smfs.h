@@ -168,7 +168,7 @@ typedef struct smfs_out {
   double t_rhs_ms, t_gmres_ms, t_post_ms;
   int64_t pair_evals;       /* pair evaluations performed by the solve */
   int64_t pair_evals_f32;   /* of which evaluated in FP32 (mixed precision) */
-  int32_t refinements;      /* FP64 residual refinement sweeps (mixed precision) */
+  int32_t refinements;      /* refinement sweeps on the FP64 true residual */
   int32_t true_checks;      /* true residuals taken by the guard (restarts included) */
   int32_t floor_iteration;  /* iteration of the smallest true residual the guard saw, -1 if none */
   double floor_rel_residual;/* that relative residual, -1 if none */
@@ -290,11 +290,16 @@ int smfs_eval_velocity(smfs_problem *pb, const double *lambda, int64_t n, const 
  * leaves a floor that the recursive estimate does not show); SMFS_NOT_CONVERGED
  * (warning) when gmres_max_it is reached first.  Statistics are filled in for
  * every warning.
- * With params.precision = SMFS_MIXED (or SMFS_MIXED_FAR) the products
- * inside GMRES take the sources of contact-free spheres in FP32 as described
- * at the precision modes, everything else in FP64; Arnoldi, the true
- * residual, up to two refinement sweeps on the FP64 residual, the
- * back-transform and the forces stay in FP64. */
+ * Refinement: when the FP64 true residual misses the tolerance, up to two
+ * sweeps solve G_hat d = r on the FP64 residual r and add d (a new Krylov
+ * process starts below the rounding floor of the first); in FP64 only after
+ * the iteration stopped (estimate or guard), in the mixed forms always; a
+ * sweep that does not lower the true residual is taken back.
+ * With params.precision = SMFS_MIXED, SMFS_MIXED_FAR or SMFS_MIXED_EQ the
+ * products inside GMRES take the contact-free spheres' far field in reduced
+ * precision as described at the precision modes, everything else in FP64;
+ * Arnoldi, the true residual, the refinement residuals, the back-transform
+ * and the forces stay in FP64. */
 int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out,
                           smfs_stream stream);
 

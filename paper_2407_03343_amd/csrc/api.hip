@@ -362,13 +362,13 @@ int rank_tables(Problem &pb, hipStream_t s) {
   }
   pb.n_utask = (int64_t)ut.size();
   pb.n_vtask = (int64_t)vt.size();
-  // 32-row tiles of the block (many right-hand sides) apply
+  // 64-row tiles of the block (many right-hand sides) apply
   std::vector<int4> bu, bv;
   for (int k = 0; k < pb.P; ++k) {
     const FactorSlot &f = pb.factors[pb.meta[k].fid];
     if (f.rank <= 0) continue;
-    for (int j = 0; j < f.rank; j += 32) bu.push_back(int4{k, j, 0, 0});
-    for (int i = 0; i < f.cols; i += 32) bv.push_back(int4{k, i, 0, 0});
+    for (int j = 0; j < f.rank; j += 64) bu.push_back(int4{k, j, 0, 0});
+    for (int i = 0; i < f.cols; i += 64) bv.push_back(int4{k, i, 0, 0});
   }
   pb.n_btask_u = (int64_t)bu.size();
   pb.n_btask_v = (int64_t)bv.size();
@@ -1696,8 +1696,13 @@ int solve_status(const SolveStats &ss) {
   return ss.stagnated ? SMFS_STAGNATED : SMFS_NOT_CONVERGED;
 }
 
-// GMRES on A x = b (x0 = 0), then the true residual in FP64; in mixed
-// precision up to two refinement sweeps on that residual.
+// GMRES on A x = b (x0 = 0), then the true residual in FP64 and up to two
+// refinement sweeps on it: GMRES on A d = r, x += d.  Mixed products refine
+// whenever the FP64 residual misses the tolerance; FP64 products once the
+// iteration stopped above it (the estimate or the guard ended a Krylov
+// process whose rounding left a residual floor; a fresh process on the
+// residual starts below that floor).  A sweep that leaves a larger true
+// residual is taken back.
 int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, double *x,
                  int precision, SolveStats &ss, hipStream_t s) {
   const int64_t ld = pb.kry_ld;
@@ -1719,7 +1724,8 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
   double *w = pb.d_vec, *r = pb.d_vec + ld, *rr = pb.d_vec + 4 * ld, *d = pb.d_vec + 5 * ld;
   const int32_t nch = mdot_chunks(n);
   double *scal = pb.d_red + pb.red_cap - 8;
-  double hres[2] = {0, 0};
+  double hres[2] = {0, 0}, prev_res[2] = {0, 0};
+  double prev_true = -1.0;
   while (true) {
     rc = op(x, w, SMFS_FP64);
     if (rc) return rc;
@@ -1730,11 +1736,23 @@ int solve_system(Problem &pb, int64_t n, const Operator &op, const double *b, do
     SMFS_HIP(hipMemcpyAsync(hres, scal, 16, hipMemcpyDeviceToHost, s));
     SMFS_HIP(hipStreamSynchronize(s));
     const double true_rel = hres[1] > 0 ? hres[0] / hres[1] : 0.0;
+    if (ss.refinements > 0 && !(true_rel <= prev_true)) {
+      // the last sweep did not lower the true residual: take it back
+      SMFS_HIP(launch_axpby(n, -1.0, d, 1.0, x, s));
+      hres[0] = prev_res[0];
+      hres[1] = prev_res[1];
+      ss.converged = prev_true <= tol;
+      ss.stagnated = !ss.converged;
+      break;
+    }
     ss.converged = true_rel <= tol;
     ss.stagnated = !ss.converged && stopped;
-    if (!is_mixed(precision) || ss.converged || ss.refinements >= 2 ||
-        ss.applies >= pb.prm.gmres_max_it)
+    if (ss.converged || ss.refinements >= 2 || ss.applies >= pb.prm.gmres_max_it ||
+        (!is_mixed(precision) && !ss.stagnated))
       break;
+    prev_true = true_rel;
+    prev_res[0] = hres[0];
+    prev_res[1] = hres[1];
     SMFS_HIP(hipMemcpyAsync(rr, r, 8 * n, hipMemcpyDeviceToDevice, s));
     const double tol_d = std::min(0.5, std::max(tol, tol / true_rel));
     GmresStats sd;

@@ -1486,7 +1486,82 @@ __device__ __forceinline__ void mfma_tile_tn(const double *const arow[2], const 
   }
 }
 
-// S[q][s0 + r] = (U_k^T mu_q)_r / sigma_r for the rows r of the tile.
+// One 64 x 64 tile of C = A B per workgroup of four waves, each wave a
+// 32 x 32 quarter as in mfma_tile_tn.  A rows (rowsA of them, stride lda)
+// and B columns (colsB, stride ldb) are contiguous over k; chunks of 16 k of
+// both are staged through LDS, so every element is read from memory once
+// per workgroup (the factor once per 64 right-hand sides, the vectors once
+// per 64 rows), and double-buffered: the global loads of the next chunk are
+// in flight while the MFMAs run on this one.  The k order of every sum is
+// that of mfma_tile_tn.
+constexpr int kGT = 64, kGK = 16, kGP = kGK + 2;   // tile, k chunk, padded LDS row
+struct GemmLds {
+  double a[2][kGT][kGP];
+  double b[2][kGT][kGP];
+};
+
+__device__ __forceinline__ void gemm_tile_lds(const double *__restrict__ A, int64_t lda, int rowsA,
+                                              const double *__restrict__ B, int64_t ldb, int colsB, int64_t K,
+                                              GemmLds &sh, TileTN &t) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int lr = tid >> 2, lk = (tid & 3) * 4;    // this thread's staging row and k offset
+  const bool aok = lr < rowsA, bok = lr < colsB;
+  const double *ap = A + (int64_t)(aok ? lr : 0) * lda;
+  const double *bp = B + (int64_t)(bok ? lr : 0) * ldb;
+#pragma unroll
+  for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) t.acc[ia][jb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double ra[4], rb[4];
+  auto fetch = [&](int64_t kc) {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int64_t k = kc + lk + s2;
+      ra[s2] = (aok && k < K) ? ap[k] : 0.0;
+      rb[s2] = (bok && k < K) ? bp[k] : 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      sh.a[buf][lr][lk + s2] = ra[s2];
+      sh.b[buf][lr][lk + s2] = rb[s2];
+    }
+  };
+  const int64_t nch = (K + kGK - 1) / kGK;
+  if (nch > 0) {
+    fetch(0);
+    stage(0);
+  }
+  __syncthreads();
+  for (int64_t c = 0; c < nch; ++c) {
+    const int cur = (int)(c & 1);
+    if (c + 1 < nch) fetch((c + 1) * kGK);
+    double a[2][4], b[2][4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+#pragma unroll
+      for (int ia = 0; ia < 2; ++ia) a[ia][s2] = sh.a[cur][wr + 16 * ia + li][4 * g + s2];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) b[jb][s2] = sh.b[cur][wc + 16 * jb + li][4 * g + s2];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+      for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+          t.acc[ia][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ia][s2], b[jb][s2], t.acc[ia][jb], 0, 0, 0);
+    if (c + 1 < nch) stage(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+// S[q][s0 + r] = (U_k^T mu_q)_r / sigma_r for the rows r of the tile
+// (tasks: sphere and first row of a 64-row tile; blockIdx.y: 64 right-hand
+// sides).
 __global__ __launch_bounds__(kBlock) void k_pinv_block_u(const int4 *__restrict__ tasks, int64_t n,
                                                          const SphereMeta *__restrict__ meta,
                                                          const FactorSlot *__restrict__ fs,
@@ -1494,31 +1569,24 @@ __global__ __launch_bounds__(kBlock) void k_pinv_block_u(const int4 *__restrict_
                                                          const double *__restrict__ mu, int64_t ldmu,
                                                          int32_t nrhs, double *__restrict__ S,
                                                          int64_t lds) {
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  __shared__ GemmLds sh;
+  const int64_t t = blockIdx.x;
   if (t >= n) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int4 tk = tasks[t];
-  const int k = uniform(tk.x), r0 = uniform(tk.y), q0 = blockIdx.y * 32;
+  const int k = tk.x, r0 = tk.y, q0 = blockIdx.y * kGT;
   const SphereMeta &m = meta[k];
   const FactorSlot &f = fs[m.fid];
   const int rank = m.rank;
-  const int64_t K = f.rows;
-  const double *arow[2], *bcol[2];
-  bool aok[2], bok[2];
-  for (int h = 0; h < 2; ++h) {
-    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
-    aok[h] = r < rank;
-    bok[h] = q < nrhs;
-    arow[h] = fac + f.u_off + (int64_t)(aok[h] ? r : 0) * f.rows;
-    bcol[h] = mu + (int64_t)(bok[h] ? q : 0) * ldmu + 3 * m.t0;
-  }
   TileTN tile;
-  mfma_tile_tn(arow, aok, bcol, bok, K, tile);
+  gemm_tile_lds(fac + f.u_off + (int64_t)r0 * f.rows, f.rows, rank - r0, mu + (int64_t)q0 * ldmu + 3 * m.t0, ldmu,
+                nrhs - q0, f.rows, sh, tile);
   const double *sig = fac + f.sig_off;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   for (int ia = 0; ia < 2; ++ia)
     for (int jb = 0; jb < 2; ++jb)
       for (int v = 0; v < 4; ++v) {
-        const int r = r0 + 16 * ia + 4 * v + (lane >> 4), q = q0 + 16 * jb + (lane & 15);
+        const int r = r0 + wr + 16 * ia + 4 * v + (lane >> 4), q = q0 + wc + 16 * jb + (lane & 15);
         if (r < rank && q < nrhs) S[(int64_t)q * lds + m.s0 + r] = tile.acc[ia][jb][v] / sig[r];
       }
 }
@@ -1531,31 +1599,24 @@ __global__ __launch_bounds__(kBlock) void k_pinv_block_v(const int4 *__restrict_
                                                          const double *__restrict__ S, int64_t lds,
                                                          int32_t nrhs, double *__restrict__ lamb,
                                                          double dscale) {
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  __shared__ GemmLds sh;
+  const int64_t t = blockIdx.x;
   if (t >= n) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int4 tk = tasks[t];
-  const int k = uniform(tk.x), r0 = uniform(tk.y), q0 = blockIdx.y * 32;
+  const int k = tk.x, r0 = tk.y, q0 = blockIdx.y * kGT;
   const SphereMeta &m = meta[k];
   const FactorSlot &f = fs[m.fid];
-  const int64_t K = m.rank;
   const int rows = f.cols;
-  const double *arow[2], *bcol[2];
-  bool aok[2], bok[2];
-  for (int h = 0; h < 2; ++h) {
-    const int r = r0 + 16 * h + (lane & 15), q = q0 + 16 * h + (lane & 15);
-    aok[h] = r < rows;
-    bok[h] = q < nrhs;
-    arow[h] = fac + f.vt_off + (int64_t)(aok[h] ? r : 0) * f.cols;
-    bcol[h] = S + (int64_t)(bok[h] ? q : 0) * lds + m.s0;
-  }
   TileTN tile;
-  mfma_tile_tn(arow, aok, bcol, bok, K, tile);
+  gemm_tile_lds(fac + f.vt_off + (int64_t)r0 * f.cols, f.cols, rows - r0, S + (int64_t)q0 * lds + m.s0, lds,
+                nrhs - q0, m.rank, sh, tile);
   const int nd0 = m.kn[0] + m.kn[1] + m.kn[2];
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   for (int ia = 0; ia < 2; ++ia)
     for (int jb = 0; jb < 2; ++jb)
       for (int v = 0; v < 4; ++v) {
-        const int r = r0 + 16 * ia + 4 * v + (lane >> 4), q = q0 + 16 * jb + (lane & 15);
+        const int r = r0 + wr + 16 * ia + 4 * v + (lane >> 4), q = q0 + wc + 16 * jb + (lane & 15);
         if (r < rows && q < nrhs) {
           const int jl = r / 3, c = r - 3 * (r / 3);
           const double val = tile.acc[ia][jb][v];
@@ -1886,13 +1947,14 @@ hipError_t launch_pinv_block(const int4 *utasks, int64_t nu, const int4 *vtasks,
                              const SphereMeta *meta, const FactorSlot *fs, const double *fac,
                              const double *mu, int64_t ldmu, int32_t nrhs, double *S, int64_t lds,
                              double *lamb, double dscale, hipStream_t s) {
-  const unsigned qt = (unsigned)((nrhs + 31) / 32);
+  // one workgroup per 64-row task and 64 right-hand sides
+  const unsigned qt = (unsigned)((nrhs + kGT - 1) / kGT);
   if (nu > 0)
-    hipLaunchKernelGGL(k_pinv_block_u, dim3(blocks_for(nu, kWavesPerBlock), qt), dim3(kBlock), 0, s,
-                       utasks, nu, meta, fs, fac, mu, ldmu, nrhs, S, lds);
+    hipLaunchKernelGGL(k_pinv_block_u, dim3((unsigned)nu, qt), dim3(kBlock), 0, s, utasks, nu, meta, fs, fac, mu,
+                       ldmu, nrhs, S, lds);
   if (nv > 0)
-    hipLaunchKernelGGL(k_pinv_block_v, dim3(blocks_for(nv, kWavesPerBlock), qt), dim3(kBlock), 0, s,
-                       vtasks, nv, meta, fs, fac, S, lds, nrhs, lamb, dscale);
+    hipLaunchKernelGGL(k_pinv_block_v, dim3((unsigned)nv, qt), dim3(kBlock), 0, s, vtasks, nv, meta, fs, fac, S,
+                       lds, nrhs, lamb, dscale);
   return hipGetLastError();
 }
 

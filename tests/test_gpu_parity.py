@@ -138,26 +138,26 @@ def test_solve_parity_pair(pair_lib, pair001, pair_ext):
 
 def test_guard_reports_floor(dev, pair001, pair_ext):
     """Tolerance 1e-12 on the two-sphere case at gap 0.01: the FP64 true
-    residual floors near 3e-7 (rounding amplified by the truncated
-    pseudo-inverses), so the solve must end STAGNATED on its best checked
-    iterate instead of reporting convergence, with the floor's iteration
-    and residual reported; its forces still match the oracle to 20 times
-    the oracle's own rounding sensitivity."""
+    residual of a Krylov process floors near 3e-7 (rounding amplified by
+    the truncated pseudo-inverses), so the solve must end STAGNATED instead
+    of reporting convergence, with the first floor's iteration and residual
+    reported; the refinement sweeps on the true residual may lower it, never
+    raise it; the forces still match the oracle to 20 times the oracle's
+    own rounding sensitivity."""
     _say("true-residual guard: two spheres at tolerance 1e-12")
     lib = dev.Problem(pair001["pk"].centers, 1.0, gmres_tol=1e-12).bind()
     _import_oracle_factors(lib, pair001["pb"])
     out = lib.solve_resistance(_t(pair001["rbm"][0]))
     ref = pair001["out"]
-    _say(f"  status {out['status']}, it {out['iterations']}, checks {out['true_checks']}, floor at "
-         f"{out['floor_iteration']} ({out['floor_rel_residual']:.2e}), true {out['true_rel_residual']:.2e}, "
-         f"est {out['rel_residual']:.2e}")
+    _say(f"  status {out['status']}, it {out['iterations']} (+{out['refinements']} refinements), checks "
+         f"{out['true_checks']}, first floor at {out['floor_iteration']} ({out['floor_rel_residual']:.2e}), "
+         f"true {out['true_rel_residual']:.2e}, est {out['rel_residual']:.2e}")
     assert out["status"] == dev.SMFS_STAGNATED and not out["converged"]
     assert out["true_checks"] >= 2
     assert 0 < out["floor_iteration"] <= out["iterations"] < 1000
     assert out["true_rel_residual"] > 1e-12
-    # the returned iterate is the best one checked: its residual, recomputed
-    # after the solve, is the floor the guard recorded
-    assert abs(out["true_rel_residual"] - out["floor_rel_residual"]) <= 1e-6 * out["floor_rel_residual"]
+    # the returned iterate is no worse than the best one the guard checked
+    assert out["true_rel_residual"] <= (1 + 1e-6) * out["floor_rel_residual"]
     assert out["true_rel_residual"] < 1e-6
     ft = _n(out["ft"]).reshape(-1, 6)
     scale = np.abs(ref["ft"]).max()
