@@ -110,7 +110,7 @@ typedef struct smfs_params {
   double trunc_rel;         /* singular values kept if > trunc_rel * sigma_1 */
   double mu;                /* viscosity */
   int32_t n_check_base;     /* residual check points per sphere */
-  int32_t precision;        /* SMFS_FP64, SMFS_MIXED or SMFS_MIXED_FAR */
+  int32_t precision;        /* SMFS_FP64, SMFS_MIXED, SMFS_MIXED_FAR or SMFS_MIXED_EQ */
   double gmres_tol;         /* relative residual target */
   int32_t gmres_max_it;
   int32_t gmres_restart;    /* Krylov vectors kept (sizes the workspace) */
@@ -244,8 +244,9 @@ int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double
 
 /* One product y = G_hat mu (eq. resistance): lambda_hat = V S^-1 U^T mu per
  * sphere, then y_k = mu_k + W_k sum_{k' != k} G^(kk') lambda_hat_k'.
- * mu, y [dev] 3 T (must not alias).  precision SMFS_FP64, SMFS_MIXED or
- * SMFS_MIXED_FAR. */
+ * mu, y [dev] 3 T (must not alias).  precision SMFS_FP64, SMFS_MIXED,
+ * SMFS_MIXED_FAR or SMFS_MIXED_EQ (SMFS_E_STATE before the far-field
+ * set-up). */
 int smfs_apply(smfs_problem *pb, const double *mu, double *y, int32_t precision,
                smfs_stream stream);
 
@@ -325,9 +326,12 @@ int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_
  * the per-sphere pseudo-inverse (eq. transform) becomes a pair of small
  * GEMMs per sphere on the matrix cores.  A block workspace of device memory
  * is allocated by the caller; its size depends on nrhs and the Krylov
- * restart length.  Block products come in FP64 and in a mixed form (the
+ * restart length.  Block products come in FP64 and in two mixed forms: the
  * proxies of contact-free spheres summed in FP32 from FP32 copies of their
- * FP64 strengths, the block pseudo-inverse and every other pair in FP64).
+ * FP64 strengths (SMFS_MIXED, SMFS_MIXED_FAR), or their far field through
+ * the equivalent sources (SMFS_MIXED_EQ: strengths for every vector, FP32
+ * sums for runs of vectors, near proxies in FP64); the block pseudo-inverse
+ * and every other pair in FP64.
  *
  * Vectors of a block are stored one after another: vector q starts at
  * q * ld (ld >= 3 T elements, the same for input and output blocks). */
@@ -339,8 +343,8 @@ int smfs_block_workspace_bytes(const smfs_problem *pb, int32_t nrhs, int32_t res
                                size_t *bytes);
 
 /* y_q = G_hat mu_q for q < nrhs (eq. resistance with the identity self
- * blocks of Section 2.2).  precision SMFS_FP64, or SMFS_MIXED /
- * SMFS_MIXED_FAR (both the mixed block form above).  mu, y [dev]: nrhs
+ * blocks of Section 2.2).  precision SMFS_FP64, SMFS_MIXED / SMFS_MIXED_FAR
+ * or SMFS_MIXED_EQ (the mixed block forms above).  mu, y [dev]: nrhs
  * vectors of stride ld >= 3 T; mu and y must not overlap.  ws [dev]: at
  * least smfs_block_workspace_bytes(pb, nrhs, 0) bytes, 256-byte aligned. */
 int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y, int64_t ld,
@@ -383,7 +387,8 @@ typedef struct smfs_block_out {
  * converged stays frozen while the others go on.  The products follow
  * params.precision: in a mixed form every restart takes the FP64 true
  * residuals, and once every estimate met the tolerance the systems restart
- * from them up to twice (those above the tolerance go on).  ws as above
+ * from them up to twice (those above the tolerance go on); FP64 block
+ * solves take no such refinement (unlike smfs_solve_resistance).  ws as above
  * with restart > 0.  Returns SMFS_OK when every FP64 true residual met
  * gmres_tol, SMFS_STAGNATED when every estimate did but some true residual
  * did not, SMFS_NOT_CONVERGED otherwise. */

@@ -31,15 +31,17 @@ size_t up(size_t v) { return (v + kAlignB - 1) / kAlignB * kAlignB; }
 struct BlockLayout {
   double *lamb = nullptr;   // S x nrhs x 3 strengths (source-major)
   double *sblk = nullptr;   // nrhs x lds: Sigma^-1 U^T mu per sphere
-  double *part = nullptr;   // [split][nrhs][3T] partial sums
+  double *part = nullptr;   // [split][nrhs][3T] partial sums (one more slice: near proxies)
   float *str32 = nullptr;   // mixed: FP32 proxy strengths [proxy][nrhs][3]
   float *part32 = nullptr;  // mixed: FP32 partial sums [split32][nrhs][3T]
+  float *q32b = nullptr;    // SMFS_MIXED_EQ: equivalent strengths [free][n_eq][nrhs][3]
   double *kry = nullptr;    // (m + 1) x nrhs x ld Krylov vectors
   double *vec = nullptr;    // 4 x nrhs x ld: w, r, b, x
   double *red = nullptr;    // reduction partials and small per-system arrays
   int64_t lds = 0, ld = 0;
   int32_t nsplit = 1, m = 0, nch = 1, ldh = 0;
   int32_t nsplit32 = 0;     // FP32 far-field splits (0: no contact-free sphere)
+  int32_t nsplit_eq = 0;    // equivalent-source splits (0: form off)
   size_t bytes = 0;
 };
 
@@ -63,14 +65,21 @@ BlockLayout block_layout(const Problem &pb, int32_t nrhs, int32_t m, char *base)
   // strengths past the end of the block
   const size_t o_lamb = take(sizeof(double) * (3 * pb.S * nrhs + 3 * kBlockRun));
   const size_t o_s = take(sizeof(double) * L.lds * nrhs);
-  const size_t o_part = take(sizeof(double) * L.nsplit * nrhs * n);
+  const bool eq = eq_enabled(pb);
+  const size_t o_part = take(sizeof(double) * (L.nsplit + (eq ? 1 : 0)) * nrhs * n);
   // mixed precision: FP32 strengths of the proxies (the last run reads up to
   // kBlockRun - 1 past the end) and FP32 partial sums of the far field
   if (pb.n_free > 0)
     L.nsplit32 = std::min<int32_t>(direct_splits(pb.n_stiles * nz, (int64_t)pb.n_free * pb.prm.n_proxy),
                                    std::max(1, pb.n_free));
+  if (eq)
+    L.nsplit_eq = std::min<int32_t>(direct_splits(pb.n_stiles * nz, (int64_t)pb.n_free * pb.n_eq),
+                                    std::max(1, pb.n_free));
   const size_t o_str32 = take(sizeof(float) * (3 * pb.nb[0] * nrhs + 3 * kBlockRun));
-  const size_t o_part32 = take(sizeof(float) * std::max<int64_t>(1, (int64_t)L.nsplit32 * nrhs * n));
+  const size_t o_part32 =
+      take(sizeof(float) * std::max<int64_t>(1, (int64_t)std::max(L.nsplit32, L.nsplit_eq) * nrhs * n));
+  // the last run of right-hand sides reads up to kBlockRun - 1 past the end
+  const size_t o_q32b = take(sizeof(float) * (eq ? (size_t)3 * pb.n_free * pb.n_eq * nrhs + 3 * kBlockRun : 1));
   size_t o_kry = 0, o_vec = 0, o_red = 0;
   if (m > 0) {
     o_kry = take(sizeof(double) * (size_t)(m + 1) * nrhs * L.ld);
@@ -84,6 +93,7 @@ BlockLayout block_layout(const Problem &pb, int32_t nrhs, int32_t m, char *base)
     L.part = (double *)(base + o_part);
     L.str32 = (float *)(base + o_str32);
     L.part32 = (float *)(base + o_part32);
+    L.q32b = (float *)(base + o_q32b);
     if (m > 0) {
       L.kry = (double *)(base + o_kry);
       L.vec = (double *)(base + o_vec);
@@ -111,6 +121,12 @@ int check_ws(const Problem &pb, int32_t nrhs, int32_t m, void *ws, size_t ws_byt
 
 int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *mu, double *y,
                 int64_t ld, hipStream_t s, int precision = SMFS_FP64) {
+  if (precision == SMFS_MIXED_EQ && !eq_enabled(pb)) precision = SMFS_FP64;   // nothing to approximate
+  if (precision == SMFS_MIXED_EQ && !pb.eq_ready) {
+    set_error("SMFS_MIXED_EQ block product before smfs_setup_far_field");
+    return SMFS_E_STATE;
+  }
+  const bool eqf = precision == SMFS_MIXED_EQ;
   const bool mixed = is_mixed(precision) && L.nsplit32 > 0;
   size_t e0 = 0, e1 = 0, e2 = 0;
   int rc;
@@ -134,7 +150,31 @@ int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *m
   a.n_splits = L.nsplit;
   a.part = L.part;
   SMFS_HIP(launch_direct_block(a, s));
-  if (mixed) {
+  int32_t ns64 = L.nsplit, ns32 = mixed ? L.nsplit32 : 0;
+  if (eqf) {
+    // the contact spheres' sources are in the FP64 sum above; the near
+    // contact-free proxies into one more FP64 slice, every other
+    // contact-free sphere through its equivalent sources
+    EqArgs f;
+    f.tiles = pb.d_stiles;
+    f.n_tiles = pb.n_stiles;
+    f.tgt32 = pb.d_tgt32;
+    f.eqpt32 = pb.d_eqpt32;
+    f.q32 = nullptr;
+    f.centers = pb.d_centers;
+    f.free_ids = pb.d_free;
+    f.near_off = pb.d_near_off;
+    f.near_idx = pb.d_near_idx;
+    f.n_free = pb.n_free;
+    f.n_eq = pb.n_eq;
+    f.n_splits = L.nsplit_eq;
+    f.T = pb.T;
+    f.part32 = L.part32;
+    SMFS_HIP(launch_eq_block(a, f, pb.d_eqE, pb.prm.n_proxy, L.q32b, L.part + (int64_t)L.nsplit * nrhs * 3 * pb.T,
+                             L.part32, s));
+    ns64 = L.nsplit + 1;
+    ns32 = L.nsplit_eq;
+  } else if (mixed) {
     SMFS_HIP(launch_to_f32(3 * pb.nb[0] * nrhs, L.lamb, L.str32, s));
     Far32Args f = far32_args(pb);
     f.n_splits = L.nsplit32;
@@ -146,8 +186,8 @@ int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *m
     pb.ev_bdirect.emplace_back(e1, e2);
     pb.prof_nrhs = nrhs;
   }
-  SMFS_HIP(launch_reduce_block(3 * pb.T, nrhs, L.nsplit, L.part, mixed ? L.nsplit32 : 0, L.part32, mu, ld,
-                               pb.d_sw, 1.0 / (8.0 * kPiB * pb.prm.mu), y, ld, s));
+  SMFS_HIP(launch_reduce_block(3 * pb.T, nrhs, ns64, L.part, ns32, L.part32, mu, ld, pb.d_sw,
+                               1.0 / (8.0 * kPiB * pb.prm.mu), y, ld, s));
   return SMFS_OK;
 }
 
@@ -350,10 +390,6 @@ int smfs_apply_block(smfs_problem *pb, int32_t nrhs, const double *mu, double *y
   SMFS_READY(pb);
   if (!mu || !y || ld < 3 * pb->T) { set_error("smfs_apply_block: bad vectors"); return SMFS_E_INVALID_ARG; }
   if (!valid_precision(precision)) { set_error("smfs_apply_block: bad precision"); return SMFS_E_INVALID_ARG; }
-  if (precision == SMFS_MIXED_EQ) {
-    set_error("smfs_apply_block: SMFS_MIXED_EQ has no block form");
-    return SMFS_E_UNSUPPORTED;
-  }
   BlockLayout L;
   int rc = check_ws(*pb, nrhs, 0, ws, ws_bytes, L);
   if (rc) return rc;
@@ -369,10 +405,6 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
   if (!rbm || !out || restart <= 0 || restart > 20000) {
     set_error("smfs_solve_resistance_block: bad argument");
     return SMFS_E_INVALID_ARG;
-  }
-  if (pb->prm.precision == SMFS_MIXED_EQ) {
-    set_error("smfs_solve_resistance_block: SMFS_MIXED_EQ has no block form");
-    return SMFS_E_UNSUPPORTED;
   }
   BlockLayout L;
   int rc = check_ws(*pb, nrhs, restart, ws, ws_bytes, L);
@@ -433,6 +465,11 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
   out->t_gmres_ms = ms(t0, t1);
   out->t_post_ms = ms(t1, t2);
   out->pair_evals = (int64_t)(st.steps + 1) * nrhs * pb->pairs_per_apply;
+  if (pb->prm.precision == SMFS_MIXED_EQ && eq_enabled(*pb)) {
+    // exact and equivalent-source pairs of the EQ products, FP64 residuals
+    out->pair_evals = (int64_t)st.steps * nrhs * pb->pairs_eq_exact + (int64_t)nrhs * pb->pairs_per_apply;
+    out->pair_evals_f32 = (int64_t)st.steps * nrhs * pb->pairs_eq_far;
+  }
   // OK only when every FP64 true residual met the tolerance
   if (ntrue == nrhs) return SMFS_OK;
   return nconv == nrhs ? SMFS_STAGNATED : SMFS_NOT_CONVERGED;

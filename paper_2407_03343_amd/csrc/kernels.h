@@ -207,6 +207,13 @@ hipError_t launch_pinv_block(const int4 *utasks, int64_t nu, const int4 *vtasks,
                              const double *mu, int64_t ldmu, int32_t nrhs, double *S, int64_t lds,
                              double *lamb, double dscale, hipStream_t s);
 hipError_t launch_direct_block(const BlockDirectArgs &a, hipStream_t s);
+// SMFS_MIXED_EQ for a block of vectors: equivalent strengths of every
+// contact-free sphere (q32b [free][n_eq][nrhs][3]), the FP64 near proxies
+// into near_out [nrhs][T][3] and the FP32 equivalent-source sum into
+// part32b [f.n_splits][nrhs][T][3]; d supplies the one-sphere tiles,
+// targets, sources and the strengths lamb.
+hipError_t launch_eq_block(const BlockDirectArgs &d, const EqArgs &f, const double *E, int32_t n_proxy,
+                           float *q32b, double *near_out, float *part32b, hipStream_t s);
 hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part, int32_t ns32,
                                const float *part32, const double *base, int64_t ldb, const double *sw,
                                double c0, double *y, int64_t ldy, hipStream_t s);

@@ -551,6 +551,21 @@ __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int s
     }
     const ConstPtr32 str = (ConstPtr32)(A.q32 + (int64_t)q * 3 * ne);
     int j = 0;
+    // four sources per step: one wait for the scalar loads of 24 values per
+    // 4 kTpl pairs
+    for (; j + 3 < ne; j += 4) {
+      const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
+      float sv[12], fv[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        sv[i] = ps[i];
+        fv[i] = pf[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        far_pair<kTpl>(sv[3 * u], sv[3 * u + 1], sv[3 * u + 2], fv[3 * u], fv[3 * u + 1], fv[3 * u + 2], ux, uy,
+                       uz, ax, ay, az);
+    }
     for (; j + 1 < ne; j += 2) {
       const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
       const float s0x = ps[0], s0y = ps[1], s0z = ps[2], s1x = ps[3], s1y = ps[4], s1z = ps[5];
@@ -1755,6 +1770,180 @@ __global__ __launch_bounds__(kBlock) void k_direct_block(BlockDirectArgs A) {
   }
 }
 
+// Equivalent-source far field, many right-hand sides (SMFS_MIXED_EQ).
+// q32b[((q n_eq + j) nrhs + v) 3 + c] = (float) (E lambda_hat_v(free sphere q))[3 j + c]:
+// one thread per row of E, one contact-free sphere and kRun vectors
+// (blockIdx.y, blockIdx.z); the strengths are wave-uniform.
+template <int kRun>
+__global__ __launch_bounds__(256) void k_eq_strengths_block(const double *__restrict__ E, int32_t rows,
+                                                            int32_t cols, const double *__restrict__ lamb,
+                                                            int32_t nrhs, const SphereMeta *__restrict__ meta,
+                                                            const int32_t *__restrict__ free_ids,
+                                                            float *__restrict__ q32b) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y, v0 = blockIdx.z * kRun;
+  const int ks = uniform(free_ids[q]);
+  const ConstPtr l = (ConstPtr)(lamb + (int64_t)meta[ks].k0[0] * nrhs * 3);
+  const int rr = r < rows ? r : 0;
+  double acc[kRun];
+#pragma unroll
+  for (int v = 0; v < kRun; ++v) acc[v] = 0.0;
+  for (int i = 0; i < cols; ++i) {
+    const double e = E[(int64_t)i * rows + rr];
+    const int j = i / 3, c = i - 3 * (i / 3);
+#pragma unroll
+    for (int v = 0; v < kRun; ++v) {
+      const int vv = min(v0 + v, nrhs - 1);
+      acc[v] = fma(e, l[((int64_t)j * nrhs + vv) * 3 + c], acc[v]);
+    }
+  }
+  if (r >= rows) return;
+  const int j = r / 3, c = r - 3 * (r / 3);
+  const int ne = rows / 3;
+#pragma unroll
+  for (int v = 0; v < kRun; ++v)
+    if (v0 + v < nrhs) q32b[(((int64_t)q * ne + j) * nrhs + v0 + v) * 3 + c] = (float)acc[v];
+}
+
+// The FP32 equivalent-source sum for a run of kRun vectors (blockIdx.z),
+// one-sphere tiles, the contact-free spheres split over blockIdx.y, the
+// tile's own sphere and near list skipped as in far_eq_wave.
+template <int kTpl, int kRun>
+__global__ __launch_bounds__(kBlock) void k_far_eq_block_f32(EqArgs A, const float *__restrict__ q32b,
+                                                             int32_t nrhs, float *__restrict__ part32b) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (tile >= A.n_tiles) return;
+  const int4 tl = A.tiles[tile];
+  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  const int q0 = blockIdx.z * kRun;
+  const int split = blockIdx.y;
+  float tx[kTpl], ty[kTpl], tz[kTpl], a[kTpl][kRun][3];
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
+    tx[p] = A.tgt32[3 * ti];
+    ty[p] = A.tgt32[3 * ti + 1];
+    tz[p] = A.tgt32[3 * ti + 2];
+#pragma unroll
+    for (int q = 0; q < kRun; ++q) a[p][q][0] = a[p][q][1] = a[p][q][2] = 0.f;
+  }
+  const ConstPtr32 pts = (ConstPtr32)A.eqpt32, str = (ConstPtr32)q32b;
+  const double ckx = A.centers[3 * k], cky = A.centers[3 * k + 1], ckz = A.centers[3 * k + 2];
+  const int f0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
+  const int f1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
+  int e = uniform(A.near_off[k]);
+  const int e1 = uniform(A.near_off[k + 1]);
+  while (e < e1 && uniform(A.near_idx[e]) < f0) ++e;
+  int next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
+  const int ne = A.n_eq;
+  for (int fq = f0; fq < f1; ++fq) {
+    if (fq == next) {
+      ++e;
+      next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
+      continue;
+    }
+    const int ks = uniform(A.free_ids[fq]);
+    if (ks == k) continue;
+    const float dx = (float)(A.centers[3 * ks] - ckx), dy = (float)(A.centers[3 * ks + 1] - cky),
+                dz = (float)(A.centers[3 * ks + 2] - ckz);
+    float ux[kTpl], uy[kTpl], uz[kTpl];
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      ux[p] = tx[p] - dx;
+      uy[p] = ty[p] - dy;
+      uz[p] = tz[p] - dz;
+    }
+    for (int j = 0; j < ne; ++j) {
+      const ConstPtr32 ps = pts + 3 * j, pf = str + (((int64_t)fq * ne + j) * nrhs + q0) * 3;
+      const float sx = ps[0], sy = ps[1], sz = ps[2];
+      float f[kRun][3];
+#pragma unroll
+      for (int q = 0; q < kRun; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[q][c] = pf[3 * q + c];
+#pragma unroll
+      for (int p = 0; p < kTpl; ++p) {
+        const float rx = ux[p] - sx, ry = uy[p] - sy, rz = uz[p] - sz;
+        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri2 = ri * ri;
+#pragma unroll
+        for (int q = 0; q < kRun; ++q) {
+          const float t = fmaf(rx, f[q][0], fmaf(ry, f[q][1], rz * f[q][2])) * ri2;
+          a[p][q][0] = fmaf(fmaf(rx, t, f[q][0]), ri, a[p][q][0]);
+          a[p][q][1] = fmaf(fmaf(ry, t, f[q][1]), ri, a[p][q][1]);
+          a[p][q][2] = fmaf(fmaf(rz, t, f[q][2]), ri, a[p][q][2]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    if (i < tc) {
+#pragma unroll
+      for (int q = 0; q < kRun; ++q) {
+        if (q0 + q >= nrhs) break;
+        float *out = part32b + ((int64_t)split * nrhs + q0 + q) * A.T * 3;
+        const int64_t o = 3 * ((int64_t)t0 + i);
+        out[o] = a[p][q][0];
+        out[o + 1] = a[p][q][1];
+        out[o + 2] = a[p][q][2];
+      }
+    }
+  }
+}
+
+// FP64 sum of the near contact-free proxies (near lists) for a run of kRun
+// vectors (blockIdx.z) into one partial slice out [nrhs][T][3].
+template <int kTpl, int kRun>
+__global__ __launch_bounds__(kBlock) void k_near_block_f64(BlockDirectArgs A, const int32_t *__restrict__ free_ids,
+                                                           const int32_t *__restrict__ near_off,
+                                                           const int32_t *__restrict__ near_idx,
+                                                           double *__restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
+  if (tile >= A.n_tiles) return;
+  const int4 tl = A.tiles[tile];
+  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  const int q0 = blockIdx.z * kRun;
+  AccB<kTpl, kRun> acc;
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
+    acc.tx[p] = A.tgt[3 * ti];
+    acc.ty[p] = A.tgt[3 * ti + 1];
+    acc.tz[p] = A.tgt[3 * ti + 2];
+#pragma unroll
+    for (int q = 0; q < kRun; ++q) acc.a[p][q][0] = acc.a[p][q][1] = acc.a[p][q][2] = 0.0;
+  }
+  const int e0 = uniform(near_off[k]), e1 = uniform(near_off[k + 1]);
+  for (int e = e0; e < e1; ++e) {
+    const int ks = uniform(free_ids[uniform(near_idx[e])]);
+    const int j0 = uniform((int)A.meta[ks].k0[0]);
+    const int j1 = j0 + uniform(A.meta[ks].kn[0]);
+    run_sources_block<kTpl, kRun, 0>(A.src, A.lamb, A.nrhs, q0, j0, j1, acc);
+  }
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const int i = lane + kWave * p;
+    if (i < tc) {
+#pragma unroll
+      for (int q = 0; q < kRun; ++q) {
+        if (q0 + q >= A.nrhs) break;
+        double *o3 = out + (int64_t)(q0 + q) * A.T * 3;
+        const int64_t o = 3 * ((int64_t)t0 + i);
+        o3[o] = 0.5 * acc.a[p][q][0];   // the pairs add twice the velocity
+        o3[o + 1] = 0.5 * acc.a[p][q][1];
+        o3[o + 2] = 0.5 * acc.a[p][q][2];
+      }
+    }
+  }
+}
+
 // Mixed precision, many right-hand sides: the FP32 far field of the
 // contact-free proxies for a run of kRun vectors (blockIdx.z), one-sphere
 // tiles, the free spheres split over blockIdx.y.  Coordinates relative to
@@ -1955,6 +2144,24 @@ hipError_t launch_pinv_block(const int4 *utasks, int64_t nu, const int4 *vtasks,
   if (nv > 0)
     hipLaunchKernelGGL(k_pinv_block_v, dim3((unsigned)nv, qt), dim3(kBlock), 0, s, vtasks, nv, meta, fs, fac, S,
                        lds, nrhs, lamb, dscale);
+  return hipGetLastError();
+}
+
+hipError_t launch_eq_block(const BlockDirectArgs &d, const EqArgs &f, const double *E, int32_t n_proxy,
+                           float *q32b, double *near_out, float *part32b, hipStream_t s) {
+  if (f.n_free <= 0 || d.nrhs == 0) return hipSuccess;
+  const unsigned nz = (unsigned)((d.nrhs + kBlockRun - 1) / kBlockRun);
+  const int rows = 3 * f.n_eq;
+  hipLaunchKernelGGL((k_eq_strengths_block<kBlockRun>), dim3((unsigned)((rows + 255) / 256), (unsigned)f.n_free, nz),
+                     dim3(256), 0, s, E, rows, 3 * n_proxy, d.lamb, d.nrhs, d.meta, f.free_ids, q32b);
+  if (d.n_tiles > 0) {
+    const unsigned nb = (unsigned)((d.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL((k_near_block_f64<kDirectTpl, kBlockRun>), dim3(nb, 1, nz), dim3(kBlock), 0, s, d,
+                       f.free_ids, f.near_off, f.near_idx, near_out);
+    if (f.n_splits > 0)
+      hipLaunchKernelGGL((k_far_eq_block_f32<kDirectTpl, kBlockRun>), dim3(nb, (unsigned)f.n_splits, nz),
+                         dim3(kBlock), 0, s, f, q32b, d.nrhs, part32b);
+  }
   return hipGetLastError();
 }
 

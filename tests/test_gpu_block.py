@@ -126,7 +126,12 @@ def test_block_solve_matches_oracle_and_single(dev, small12):
         _say(f"  system {q}: block-oracle {d_or:.2e}, block-single {d_single:.2e}, bar {bar:.2e}, "
              f"iterations {out['iterations'][q]} vs {single['iterations']}")
         assert d_or < bar and d_single < bar, q
-        assert abs(int(out["iterations"][q]) - single["iterations"]) <= 3
+        # the same Krylov process as the single solve, whose refinement sweeps
+        # on the FP64 true residual (after its rounding floor) may add more
+        if single["refinements"] == 0:
+            assert abs(int(out["iterations"][q]) - single["iterations"]) <= 3
+        else:
+            assert int(out["iterations"][q]) <= single["iterations"] + 3
     # the true residual floors near 1e-7 here (rounding amplified by the
     # truncated pseudo-inverse of the gap-2e-3 pair), as for single solves
     assert np.all(out["true_rel_residual"] < 1e-6)

@@ -107,9 +107,46 @@ def test_eq_solve_meets_gates(dev, lattice):
     assert du < 1e-3
 
 
-def test_eq_rejected_where_unsupported(dev, lattice):
-    lib = lattice["lib"]
-    n = 3 * lattice["g"].T
-    M = torch.zeros((2, n), dtype=torch.float64, device="cuda")
-    with pytest.raises(dev.SmfsError):
-        lib.apply_block(M, precision=dev.SMFS_MIXED_EQ)
+def test_eq_block_product_matches_single(dev, lattice):
+    """The block form of SMFS_MIXED_EQ (equivalent strengths and FP32 sums
+    for runs of four vectors, near proxies in FP64) against the single-vector
+    form column by column: the same pairs in a different FP32 summation
+    order, within 1e-5 per sphere of the off-diagonal part (FP32 rounding of
+    the far field; measured on the device)."""
+    g, lib = lattice["g"], lattice["lib"]
+    rng = np.random.default_rng(9)
+    nrhs, n = 6, 3 * g.T
+    pbo = lattice["pb"]
+    M = np.stack([pbo.rhs(wl.random_rbm(g.P, 1, 20 + q)[0]) if q % 2 == 0 else rng.standard_normal(n)
+                  for q in range(nrhs)])
+    Md = torch.from_numpy(M).cuda()
+    Y = _n(lib.apply_block(Md, precision=dev.SMFS_MIXED_EQ))
+    worst = 0.0
+    for q in range(nrhs):
+        ys = _n(lib.apply(Md[q].contiguous(), precision=dev.SMFS_MIXED_EQ))
+        m = M[q].reshape(-1, 3)
+        worst = max(worst, _rel(Y[q].reshape(-1, 3) - m, ys.reshape(-1, 3) - m, g.target_sphere))
+    _say(f"  block vs single SMFS_MIXED_EQ products: worst per-sphere off-diagonal rel diff {worst:.3e}")
+    assert worst < 1e-5
+
+
+def test_eq_block_solve(dev, lattice):
+    """Block resistance solve of four systems in SMFS_MIXED_EQ: every FP64
+    true residual meets the tolerance (status OK after refinement) and the
+    forces and torques agree with the single-vector SMFS_MIXED_EQ solves and
+    with the FP64 oracle to 1e-5."""
+    g, pbo, lib = lattice["g"], lattice["pb"], lattice["lib"]
+    nrhs = 4
+    rbm = wl.random_rbm(g.P, nrhs, 30)
+    out = lib.solve_resistance_block(_t(rbm), restart=200)
+    ft = _n(out["ft"]).reshape(nrhs, g.P, 6)
+    _say(f"  block: status {out['status']}, refinements {out['refinements']}, max it {out['max_iterations']}, "
+         f"true residuals {np.max(out['true_rel_residual']):.2e}, FP32 pairs {out['pair_evals_f32']:.3e}")
+    assert out["status"] in (0, 3) and out["pair_evals_f32"] > 0
+    for q in range(nrhs):
+        ref = mfs.solve_resistance(pbo, rbm[q], tol=1e-10)["ft"]
+        single = _n(lib.solve_resistance(_t(rbm[q]))["ft"]).reshape(g.P, 6)
+        d = np.abs(ft[q] - ref).max() / np.abs(ref).max()
+        ds = np.abs(ft[q] - single).max() / np.abs(single).max()
+        _say(f"  system {q}: F/T vs oracle {d:.2e}, vs single {ds:.2e}")
+        assert d < 1e-5 and ds < 1e-5

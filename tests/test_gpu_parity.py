@@ -125,9 +125,14 @@ def test_solve_parity_pair(pair_lib, pair001, pair_ext):
          f"true {out['true_rel_residual']:.2e}, eps_res {out['eps_res_max']:.3e}")
     _say(f"  F: gpu-oracle {dF:.3e}, oracle-oracle(ext) {dF_or:.3e};  u_check: {du:.3e} vs {du_or:.3e}")
     assert _finished(out)
-    # honest status: the estimate reached 1e-10, the true residual did not
+    # honest status: OK exactly when the FP64 true residual met 1e-10
     assert out["converged"] == (out["true_rel_residual"] <= 1e-10)
-    assert abs(out["iterations"] - ref["iterations"]) <= 3
+    # the first Krylov process follows the oracle's; refinement sweeps on the
+    # true residual (after its rounding floor) add iterations
+    if out["refinements"] == 0:
+        assert abs(out["iterations"] - ref["iterations"]) <= 3
+    else:
+        assert out["iterations"] >= ref["iterations"] - 3
     assert dF < max(1e-10, 20 * dF_or)
     assert du < max(1e-10, 20 * du_or)
     Fb = brenner.brenner_force(0.01, 0.5)
