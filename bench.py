@@ -573,6 +573,9 @@ def block_solve(args, torch, smfs, wl):
         dft = max(dft, float(np.abs(f - ft_blk[q]).max() / np.abs(f).max()))
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t2) / k * nrhs
+    log(f"  block solve: {t_block:.1f} s ({args.block_precision}, status {int(blk['status'])}, max it "
+        f"{int(blk['max_iterations'])}, +{int(blk['refinements'])} refinements) against {t_seq:.1f} s for "
+        f"{nrhs} FP64 solves one after another (from {k}); F/T agree to {dft:.1e}")
     return {
         "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S, "nrhs": nrhs, "restart": m,
         "tol": args.block_tol, "setup_s": setup_s, "block_precision": args.block_precision,
@@ -593,6 +596,49 @@ def _gen_request(args):
     from paper_2407_03343_amd import workloads as wl
     i, seed, kw = args
     return wl.serving_stream(n=1, seed=seed * 100003 + i, **kw)[0]
+
+
+def full_solve(args, torch, smfs, wl):
+    """The headline packing solved as a mobility problem (random forces and
+    torques in, rigid motions out), FP64 against SMFS_MIXED_EQ on the same
+    seed, GMRES to --full-tol; the solver prints a progress line every 50
+    iterations."""
+    pk = wl.workload_packing2000(args.full_solve, seed=args.seed)
+    out = {"spheres": pk.P, "tol": args.full_tol, "forms": {}}
+    ft = torch.from_numpy(wl.random_ft(pk.P, 1, 5 + args.seed)[0].reshape(-1)).cuda()
+    rbm = {}
+    for name, prec in (("mixed_eq", smfs.SMFS_MIXED_EQ), ("fp64", smfs.SMFS_FP64)):
+        if name not in args.full_forms:
+            continue
+        pb = smfs.Problem(pk.centers, pk.radius, gmres_restart=args.full_restart, gmres_max_it=args.full_restart,
+                          gmres_tol=args.full_tol, precision=prec, progress=50)
+        pb.bind()
+        t0 = time.perf_counter()
+        pb.setup()
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        log(f"full solve ({name}): {pb.P} spheres, T={pb.T}, S={pb.S}, setup {setup_s:.1f} s")
+        t1 = time.perf_counter()
+        o = pb.solve_mobility(ft, want_check=False)
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t1
+        rbm[name] = o["rbm"].cpu().numpy()
+        out["forms"][name] = dict(setup_s=setup_s, solve_s=solve_s, iterations=o["iterations"],
+                                  refinements=o["refinements"], status=o["status"],
+                                  true_rel_residual=o["true_rel_residual"], pair_evals=o["pair_evals"],
+                                  pair_evals_f32=o["pair_evals_f32"])
+        log(f"  {name}: {o['iterations']} it (+{o['refinements']}), status {o['status']}, true "
+            f"{o['true_rel_residual']:.2e}, {solve_s:.1f} s")
+        del pb
+        torch.cuda.empty_cache()
+    for name, r in rbm.items():
+        out["forms"][name]["rbm_first_sphere"] = [float(v) for v in r[:6]]
+    if "fp64" in rbm and "mixed_eq" in rbm:
+        d = float(np.abs(rbm["mixed_eq"] - rbm["fp64"]).max() / np.abs(rbm["fp64"]).max())
+        out["rbm_rel_diff_eq_vs_fp64"] = d
+        out["speedup_eq_over_fp64"] = out["forms"]["fp64"]["solve_s"] / out["forms"]["mixed_eq"]["solve_s"]
+        log(f"  rigid motions: SMFS_MIXED_EQ vs FP64 {d:.2e}; speed-up {out['speedup_eq_over_fp64']:.2f}x")
+    return out
 
 
 def serving_requests(args):
@@ -765,6 +811,11 @@ def main():
                          "factors, then the counter calibration kernels; nothing else runs")
     ap.add_argument("--apply-precision", choices=["fp64", "mixed_eq"], default="fp64",
                     help="form of the --apply-only products")
+    ap.add_argument("--full-solve", type=int, default=0, metavar="P",
+                    help="mobility solve of the P-sphere packing, FP64 against SMFS_MIXED_EQ")
+    ap.add_argument("--full-tol", type=float, default=1e-5)
+    ap.add_argument("--full-forms", nargs="+", default=["mixed_eq", "fp64"], choices=["mixed_eq", "fp64"])
+    ap.add_argument("--full-restart", type=int, default=1000)
     ap.add_argument("--sections-out", default="", help="JSON file for the optional sections")
     ap.add_argument("--block", type=int, default=0, metavar="NRHS",
                     help="block product of NRHS vectors vs single products (0: skip)")
@@ -847,6 +898,8 @@ def main():
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         extra["serving"] = serving(args, torch, smfs, reqs, arrivals)
+    if args.full_solve > 0:
+        extra["full_solve"] = full_solve(args, torch, smfs, wl)
     if extra:
         log("sections: " + json.dumps(extra))
         if args.sections_out:

@@ -130,6 +130,8 @@ typedef struct smfs_params {
   double eq_check_radius;   /* default 2.5 */
   double eq_separation;     /* default 3.5 */
   double eq_rcond;          /* default 1e-12 */
+  int32_t progress;         /* > 0: one line on stderr every `progress` GMRES iterations
+                               (iteration, residual estimate); 0 (default): silent */
 } smfs_params;
 
 typedef struct smfs_sizes {

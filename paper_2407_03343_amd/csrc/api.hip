@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -772,6 +773,11 @@ int gmres(Problem &pb, int64_t n, const Operator &op, const double *b, double *x
         g[c] = cs[c] * g[c];
         jdone = jp;
         ++st.iterations;
+        if (pb.prm.progress > 0 && st.iterations % pb.prm.progress == 0) {
+          std::fprintf(stderr, "[smfs] GMRES iteration %d, residual estimate %.3e\n", st.iterations,
+                       std::fabs(g[c + 1]) / bnorm);
+          std::fflush(stderr);
+        }
         st.applies = applies_at[jp];
         st.rel_residual = std::fabs(g[c + 1]) / bnorm;
         if (st.rel_residual <= tol) { st.converged = true; stop = true; return SMFS_OK; }
@@ -946,6 +952,7 @@ int smfs_params_default(smfs_params *p) {
   p->eq_check_radius = 2.5;
   p->eq_separation = 3.5;
   p->eq_rcond = 1e-12;
+  p->progress = 0;
   return SMFS_OK;
 }
 
@@ -960,7 +967,7 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
       !(p->mu > 0) || !(p->trunc_rel >= 0) || p->gmres_restart <= 0 || p->gmres_max_it <= 0 ||
       p->n_check_base < 0 || p->cap_alpha[0] < 0 || p->cap_alpha[1] < 0 || p->gmres_check_every < 0 ||
       (p->svd_method != SMFS_SVD_JACOBI && p->svd_method != SMFS_SVD_ROCSOLVER) ||
-      p->eq_points < 0 || p->eq_points > 4096 ||
+      p->eq_points < 0 || p->eq_points > 4096 || p->progress < 0 ||
       (p->eq_points > 0 && !(p->eq_radius > 0 && p->eq_check_radius > p->eq_radius &&
                              p->eq_separation >= p->eq_check_radius + 1.0 && p->eq_rcond > 0 &&
                              p->eq_rcond < 1)) ||

@@ -551,21 +551,6 @@ __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int s
     }
     const ConstPtr32 str = (ConstPtr32)(A.q32 + (int64_t)q * 3 * ne);
     int j = 0;
-    // four sources per step: one wait for the scalar loads of 24 values per
-    // 4 kTpl pairs
-    for (; j + 3 < ne; j += 4) {
-      const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
-      float sv[12], fv[12];
-#pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        sv[i] = ps[i];
-        fv[i] = pf[i];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        far_pair<kTpl>(sv[3 * u], sv[3 * u + 1], sv[3 * u + 2], fv[3 * u], fv[3 * u + 1], fv[3 * u + 2], ux, uy,
-                       uz, ax, ay, az);
-    }
     for (; j + 1 < ne; j += 2) {
       const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
       const float s0x = ps[0], s0y = ps[1], s0z = ps[2], s1x = ps[3], s1y = ps[4], s1z = ps[5];

@@ -53,7 +53,7 @@ class smfs_params(C.Structure):
         ("precision", C.c_int32), ("gmres_tol", C.c_double), ("gmres_max_it", C.c_int32),
         ("gmres_restart", C.c_int32), ("gmres_check_every", C.c_int32), ("svd_method", C.c_int32),
         ("eq_points", C.c_int32), ("eq_radius", C.c_double), ("eq_check_radius", C.c_double),
-        ("eq_separation", C.c_double), ("eq_rcond", C.c_double),
+        ("eq_separation", C.c_double), ("eq_rcond", C.c_double), ("progress", C.c_int32),
     ]
 
 
