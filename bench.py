@@ -633,6 +633,8 @@ def full_solve(args, torch, smfs, wl):
         torch.cuda.empty_cache()
     for name, r in rbm.items():
         out["forms"][name]["rbm_first_sphere"] = [float(v) for v in r[:6]]
+        if args.full_save:
+            np.save(f"{args.full_save}_{name}.npy", r)
     if "fp64" in rbm and "mixed_eq" in rbm:
         d = float(np.abs(rbm["mixed_eq"] - rbm["fp64"]).max() / np.abs(rbm["fp64"]).max())
         out["rbm_rel_diff_eq_vs_fp64"] = d
@@ -816,6 +818,7 @@ def main():
     ap.add_argument("--full-tol", type=float, default=1e-5)
     ap.add_argument("--full-forms", nargs="+", default=["mixed_eq", "fp64"], choices=["mixed_eq", "fp64"])
     ap.add_argument("--full-restart", type=int, default=1000)
+    ap.add_argument("--full-save", default="", help="path prefix for the rigid motions found (.npy)")
     ap.add_argument("--sections-out", default="", help="JSON file for the optional sections")
     ap.add_argument("--block", type=int, default=0, metavar="NRHS",
                     help="block product of NRHS vectors vs single products (0: skip)")
