@@ -132,7 +132,7 @@ size_t workspace_layout(Problem &pb, bool assign) {
                                                                    (int64_t)n_free * pb.prm.n_proxy),
                                                       std::max(1, n_free)) : 0;
   const int32_t ne = eq ? pb.prm.eq_points : 0;
-  const int32_t sp_eq = eq ? std::min<int32_t>(choose_splits((int64_t)stiles.size(), (int64_t)n_free * ne),
+  const int32_t sp_eq = eq ? std::min<int32_t>(choose_splits((int64_t)tiles.size(), (int64_t)n_free * ne),
                                                std::max(1, n_free)) : 0;
   pb.n_eq = ne;
   if (eq) build_near_lists(pb, pb.prm.eq_separation * pb.a);
@@ -522,9 +522,10 @@ int apply_eq(Problem &pb, const double *mu, double *y, hipStream_t s) {
   SMFS_HIP(launch_near_f64(n, s));
   if (pb.prof && (rc = record_event(pb, s, e[4]))) return rc;
   EqArgs f;
-  f.tiles = pb.d_stiles;
-  f.n_tiles = pb.n_stiles;
-  f.tgt32 = pb.d_tgt32;
+  f.tiles = pb.d_tiles;
+  f.n_tiles = pb.n_tiles;
+  f.tsph = pb.d_tsph;
+  f.tgt = pb.d_tgt;
   f.eqpt32 = pb.d_eqpt32;
   f.q32 = pb.d_eqq32;
   f.centers = pb.d_centers;

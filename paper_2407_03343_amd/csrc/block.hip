@@ -158,7 +158,8 @@ int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *m
     EqArgs f;
     f.tiles = pb.d_stiles;
     f.n_tiles = pb.n_stiles;
-    f.tgt32 = pb.d_tgt32;
+    f.tsph = pb.d_tsph;
+    f.tgt = pb.d_tgt;
     f.eqpt32 = pb.d_eqpt32;
     f.q32 = nullptr;
     f.centers = pb.d_centers;

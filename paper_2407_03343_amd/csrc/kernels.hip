@@ -502,66 +502,121 @@ __global__ __launch_bounds__(256) void k_eq_strengths(const double *__restrict__
     if (qb + u < n_free) q32[(int64_t)(qb + u) * rows + r] = (float)acc[u];
 }
 
-// One wave of the FP32 equivalent-source sum: tile `tile`, split `split`
-// of the contact-free spheres (in free-index order, skipping the tile's own
-// sphere and its near list).
+// far_pair for the slots with on[p] set only: a masked slot's new sum is
+// discarded by a select, so it stays unchanged bitwise.
+template <int kTpl>
+__device__ __forceinline__ void far_pair_masked(float sx, float sy, float sz, float fx, float fy, float fz,
+                                                const float (&ux)[kTpl], const float (&uy)[kTpl],
+                                                const float (&uz)[kTpl], float (&ax)[kTpl],
+                                                float (&ay)[kTpl], float (&az)[kTpl], const bool (&on)[kTpl]) {
+#pragma unroll
+  for (int p = 0; p < kTpl; ++p) {
+    const float rx = ux[p] - sx, ry = uy[p] - sy, rz = uz[p] - sz;
+    const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float rf = fmaf(rx, fx, fmaf(ry, fy, rz * fz));
+    const float t = rf * (ri * ri);
+    const float bx = fmaf(fmaf(rx, t, fx), ri, ax[p]);
+    const float by = fmaf(fmaf(ry, t, fy), ri, ay[p]);
+    const float bz = fmaf(fmaf(rz, t, fz), ri, az[p]);
+    ax[p] = on[p] ? bx : ax[p];
+    ay[p] = on[p] ? by : ay[p];
+    az[p] = on[p] ? bz : az[p];
+  }
+}
+
+// The n_eq equivalent sources of one sphere (points pts relative to its
+// centre, strengths str) at the slots' targets ux (relative to the same
+// centre); two sources per step.
+template <int kTpl, bool kMasked>
+__device__ __forceinline__ void eq_sphere(ConstPtr32 pts, ConstPtr32 str, int ne, const float (&ux)[kTpl],
+                                          const float (&uy)[kTpl], const float (&uz)[kTpl], float (&ax)[kTpl],
+                                          float (&ay)[kTpl], float (&az)[kTpl], const bool (&on)[kTpl]) {
+  int j = 0;
+  for (; j + 1 < ne; j += 2) {
+    const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
+    const float s0x = ps[0], s0y = ps[1], s0z = ps[2], s1x = ps[3], s1y = ps[4], s1z = ps[5];
+    const float f0x = pf[0], f0y = pf[1], f0z = pf[2], f1x = pf[3], f1y = pf[4], f1z = pf[5];
+    if (kMasked) {
+      far_pair_masked<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az, on);
+      far_pair_masked<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az, on);
+    } else {
+      far_pair<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az);
+      far_pair<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az);
+    }
+  }
+  if (j < ne) {
+    const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
+    if (kMasked) far_pair_masked<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az, on);
+    else far_pair<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az);
+  }
+}
+
+// One wave of the FP32 equivalent-source sum: tile `tile` and split
+// `split` of the contact-free spheres (free-index order).  A tile holds up
+// to 64 kTpl consecutive targets, which may belong to consecutive spheres,
+// so that every wave has a full tile whatever a sphere's node count.  Each
+// slot skips its own sphere and the near list of its sphere, walking that
+// ascending list beside the sphere loop; a source sphere that only some
+// slots skip is summed in a masked pass.  A slot's coordinates relative to
+// a source sphere's centre are formed in FP64 and rounded once.
 template <int kTpl>
 __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int split) {
   const int lane = threadIdx.x & (kWave - 1);
   if (tile >= A.n_tiles) return;
   const int4 tl = A.tiles[tile];
-  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  const int t0 = uniform(tl.y), tc = uniform(tl.z);
   if (tc <= 0) return;
-  float tx[kTpl], ty[kTpl], tz[kTpl], ax[kTpl], ay[kTpl], az[kTpl];
+  const int q0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
+  const int q1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
+  double tx[kTpl], ty[kTpl], tz[kTpl];  // targets, absolute
+  float ax[kTpl], ay[kTpl], az[kTpl];
+  int own[kTpl], e[kTpl], next[kTpl];
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
     const int i = lane + kWave * p;
     const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
-    tx[p] = A.tgt32[3 * ti];
-    ty[p] = A.tgt32[3 * ti + 1];
-    tz[p] = A.tgt32[3 * ti + 2];
+    tx[p] = A.tgt[3 * ti];
+    ty[p] = A.tgt[3 * ti + 1];
+    tz[p] = A.tgt[3 * ti + 2];
     ax[p] = ay[p] = az[p] = 0.f;
+    const int k = A.tsph[ti];
+    own[p] = k;
+    // the near list of k is ascending: skip its entries below q0
+    e[p] = A.near_off[k];
+    const int e1 = A.near_off[k + 1];
+    while (e[p] < e1 && A.near_idx[e[p]] < q0) ++e[p];
+    next[p] = e[p] < e1 ? A.near_idx[e[p]] : 0x7fffffff;
   }
   const ConstPtr32 pts = (ConstPtr32)A.eqpt32;
-  const double ckx = A.centers[3 * k], cky = A.centers[3 * k + 1], ckz = A.centers[3 * k + 2];
-  const int q0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
-  const int q1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
-  // the near list of k is ascending: skip its entries below q0
-  int e = uniform(A.near_off[k]);
-  const int e1 = uniform(A.near_off[k + 1]);
-  while (e < e1 && uniform(A.near_idx[e]) < q0) ++e;
-  int next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
   const int ne = A.n_eq;
   for (int q = q0; q < q1; ++q) {
-    if (q == next) {
-      ++e;
-      next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
-      continue;
-    }
     const int ks = uniform(A.free_ids[q]);
-    if (ks == k) continue;
-    const float dx = (float)(A.centers[3 * ks] - ckx), dy = (float)(A.centers[3 * ks + 1] - cky),
-                dz = (float)(A.centers[3 * ks + 2] - ckz);
+    bool on[kTpl];
+    bool all_on = true, any_on = false;
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      const bool near = q == next[p];
+      if (near) {
+        ++e[p];
+        next[p] = e[p] < A.near_off[own[p] + 1] ? A.near_idx[e[p]] : 0x7fffffff;
+      }
+      on[p] = !near && ks != own[p];
+      all_on = all_on && on[p];
+      any_on = any_on || on[p];
+    }
+    if (!__any(any_on)) continue;
+    const double sx = A.centers[3 * ks], sy = A.centers[3 * ks + 1], sz = A.centers[3 * ks + 2];
     float ux[kTpl], uy[kTpl], uz[kTpl];
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
-      ux[p] = tx[p] - dx;
-      uy[p] = ty[p] - dy;
-      uz[p] = tz[p] - dz;
+      ux[p] = (float)(tx[p] - sx);
+      uy[p] = (float)(ty[p] - sy);
+      uz[p] = (float)(tz[p] - sz);
     }
     const ConstPtr32 str = (ConstPtr32)(A.q32 + (int64_t)q * 3 * ne);
-    int j = 0;
-    for (; j + 1 < ne; j += 2) {
-      const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
-      const float s0x = ps[0], s0y = ps[1], s0z = ps[2], s1x = ps[3], s1y = ps[4], s1z = ps[5];
-      const float f0x = pf[0], f0y = pf[1], f0z = pf[2], f1x = pf[3], f1y = pf[4], f1z = pf[5];
-      far_pair<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az);
-      far_pair<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az);
-    }
-    if (j < ne) {
-      const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
-      far_pair<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az);
-    }
+    if (__all(all_on)) eq_sphere<kTpl, false>(pts, str, ne, ux, uy, uz, ax, ay, az, on);
+    else eq_sphere<kTpl, true>(pts, str, ne, ux, uy, uz, ax, ay, az, on);
   }
   float *out = A.part32 + (int64_t)split * A.T * 3;
 #pragma unroll
@@ -576,8 +631,10 @@ __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int s
   }
 }
 
+// Eight waves per SIMD: the register budget (64) still holds the four
+// interleaved pair chains of the inner loop.
 template <int kTpl>
-__global__ __launch_bounds__(kBlock) void k_far_eq_f32(EqArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_far_eq_f32(EqArgs A) {
   const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
   far_eq_wave<kTpl>(A, tile, blockIdx.y);
 }
@@ -1792,7 +1849,8 @@ __global__ __launch_bounds__(256) void k_eq_strengths_block(const double *__rest
 
 // The FP32 equivalent-source sum for a run of kRun vectors (blockIdx.z),
 // one-sphere tiles, the contact-free spheres split over blockIdx.y, the
-// tile's own sphere and near list skipped as in far_eq_wave.
+// tile's own sphere and near list skipped and the coordinates formed as in
+// far_eq_wave.
 template <int kTpl, int kRun>
 __global__ __launch_bounds__(kBlock) void k_far_eq_block_f32(EqArgs A, const float *__restrict__ q32b,
                                                              int32_t nrhs, float *__restrict__ part32b) {
@@ -1803,19 +1861,19 @@ __global__ __launch_bounds__(kBlock) void k_far_eq_block_f32(EqArgs A, const flo
   const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
   const int q0 = blockIdx.z * kRun;
   const int split = blockIdx.y;
-  float tx[kTpl], ty[kTpl], tz[kTpl], a[kTpl][kRun][3];
+  double tx[kTpl], ty[kTpl], tz[kTpl];  // targets, absolute
+  float a[kTpl][kRun][3];
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
     const int i = lane + kWave * p;
     const int64_t ti = (int64_t)t0 + (i < tc ? i : 0);
-    tx[p] = A.tgt32[3 * ti];
-    ty[p] = A.tgt32[3 * ti + 1];
-    tz[p] = A.tgt32[3 * ti + 2];
+    tx[p] = A.tgt[3 * ti];
+    ty[p] = A.tgt[3 * ti + 1];
+    tz[p] = A.tgt[3 * ti + 2];
 #pragma unroll
     for (int q = 0; q < kRun; ++q) a[p][q][0] = a[p][q][1] = a[p][q][2] = 0.f;
   }
   const ConstPtr32 pts = (ConstPtr32)A.eqpt32, str = (ConstPtr32)q32b;
-  const double ckx = A.centers[3 * k], cky = A.centers[3 * k + 1], ckz = A.centers[3 * k + 2];
   const int f0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
   const int f1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
   int e = uniform(A.near_off[k]);
@@ -1831,14 +1889,13 @@ __global__ __launch_bounds__(kBlock) void k_far_eq_block_f32(EqArgs A, const flo
     }
     const int ks = uniform(A.free_ids[fq]);
     if (ks == k) continue;
-    const float dx = (float)(A.centers[3 * ks] - ckx), dy = (float)(A.centers[3 * ks + 1] - cky),
-                dz = (float)(A.centers[3 * ks + 2] - ckz);
+    const double sx = A.centers[3 * ks], sy = A.centers[3 * ks + 1], sz = A.centers[3 * ks + 2];
     float ux[kTpl], uy[kTpl], uz[kTpl];
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
-      ux[p] = tx[p] - dx;
-      uy[p] = ty[p] - dy;
-      uz[p] = tz[p] - dz;
+      ux[p] = (float)(tx[p] - sx);
+      uy[p] = (float)(ty[p] - sy);
+      uz[p] = (float)(tz[p] - sz);
     }
     for (int j = 0; j < ne; ++j) {
       const ConstPtr32 ps = pts + 3 * j, pf = str + (((int64_t)fq * ne + j) * nrhs + q0) * 3;

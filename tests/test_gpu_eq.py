@@ -71,6 +71,38 @@ def test_eq_product_matches_oracle(dev, lattice):
         assert d_ex < bar_exact
 
 
+def test_eq_product_small_nodes(dev, oracle_pairsum_built):
+    """18 spheres on a 3 x 3 x 2 lattice of spacing 3.2 plus a contact pair,
+    at 60 proxies and 80 base nodes with 48 equivalent points: a tile of 128
+    consecutive targets then spans two or three spheres whose near lists
+    differ, so the far-field sum runs its masked passes.  Bars as for the
+    default discretisation."""
+    _say("equivalent-source far field: 19-sphere lattice, 60 proxies / 80 base nodes / 48 equivalent points")
+    cs = np.array([[i * 3.2, j * 3.2, k * 3.2] for i in range(3) for j in range(3) for k in range(2)]
+                  + [[0.0, 0.0, -2.01]])
+    small = dict(n_proxy=60, n_colloc_base=80, n_image=4, n_check_base=50)
+    g = geo.build(cs, 1.0, geo.Params(**small))
+    pbo = mfs.Problem(g).setup()
+    lib = dev.Problem(cs, 1.0, precision=dev.SMFS_MIXED_EQ, eq_points=48, **small).bind()
+    _import_oracle_factors(lib, pbo)
+    lib.setup_far_field()
+    ep = ff.EqParams(n_eq=48)
+    E = ff.eq_map(g, ep)
+    counts = np.diff(np.asarray(g.target_offsets))
+    assert counts.min() < 128 and lib.sizes.eq_far_pairs > 0
+    rng = np.random.default_rng(11)
+    ts = g.target_sphere
+    for name, mu, bar in (("physical", pbo.rhs(wl.random_rbm(g.P, 1, 12)[0]), 2e-6),
+                          ("random", rng.standard_normal(3 * g.T), 2e-4)):
+        y = _n(lib.apply(_t(mu), precision=dev.SMFS_MIXED_EQ)).reshape(-1, 3)
+        ref_eq = ff.apply_eq(pbo, mu, ep, E).reshape(-1, 3)
+        m = mu.reshape(-1, 3)
+        d = _rel(y - m, ref_eq - m, ts)
+        _say(f"  {name}: off-diagonal per-sphere rel diff vs oracle EQ {d:.3e} "
+             f"(targets per sphere {counts.min()}..{counts.max()})")
+        assert d < bar
+
+
 def test_eq_zero_and_profile(dev, lattice):
     lib = lattice["lib"]
     z = torch.zeros(3 * lattice["g"].T, dtype=torch.float64, device="cuda")
