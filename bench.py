@@ -674,7 +674,8 @@ def serving(args, torch, smfs, reqs, arrivals):
     solver = dict(gmres_tol=args.serve_tol, gmres_restart=100, gmres_max_it=3000)
     prec = smfs.SMFS_MIXED_FAR if args.serve_precision == "mixed_far" else smfs.SMFS_FP64
     srv = smfs.Server(arena_bytes=args.serve_arena << 30, max_active=args.serve_slots,
-                      setup_workers=args.serve_workers, server_precision=prec, **disc, **solver)
+                      setup_workers=args.serve_workers, server_precision=prec,
+                      iters_per_step=args.serve_iters, **disc, **solver)
     t0 = srv.clock() + 0.02
     ids, i, last_log = [], 0, time.perf_counter()
     while True:
@@ -718,7 +719,8 @@ def serving(args, torch, smfs, reqs, arrivals):
         "not_converged": int(sum(1 for r in res if r["status"] == 1)),
         "max_true_rel_residual": float(max(r["true_rel_residual"] for r in res)),
         "peak_active": st["peak_active"], "steps": st["steps"],
-        "mean_resident_per_step": st["request_iterations"] / max(1, st["steps"]),
+        "iterations_per_step": st["iterations"] / max(1, st["steps"]),
+        "mean_resident_per_iteration": st["request_iterations"] / max(1, st["iterations"]),
         "setup_ms_total": st["setup_ms"], "step_ms_total": st["step_ms"], "tick_ms_total": st["tick_ms"],
         "setup_batches": st["setup_batches"],
         "arena_peak_gib": st["arena_peak"] / 2**30,
@@ -845,6 +847,10 @@ def main():
                     help="products inside the served GMRES iterations")
     ap.add_argument("--serve-sequential", type=int, default=3,
                     help="requests solved one after another for the comparison")
+    ap.add_argument("--serve-iters", type=int, default=8,
+                    help="GMRES iterations per server step (no host round trip between them)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run the serving section alone (no headline line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -862,6 +868,12 @@ def main():
 
     if args.apply_only:
         apply_only(args, torch, smfs, wl)
+        return
+    if args.serve_only:
+        if reqs is None:
+            print("--serve-only needs --serve-requests", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"serving": serving(args, torch, smfs, reqs, arrivals)}), flush=True)
         return
 
     pk, pb, result = headline(args, torch, smfs, wl, budget)

@@ -405,10 +405,10 @@ int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rb
  * their workspace fits into the server's device arena and a slot is free;
  * set-up worker threads build and factorise admitted requests in batches
  * on their own streams while the resident requests keep iterating.  Every call of
- * smfs_server_step performs one GMRES iteration of every resident request:
- * one launch of each kernel of the product with G_hat and of the Arnoldi
- * step covers all of them, and a request that arrives between steps joins
- * at the next one (continuous batching).  A finished request leaves at once
+ * smfs_server_step performs iters_per_step GMRES iterations of every
+ * resident request: one launch of each kernel of the product with G_hat, of
+ * the Arnoldi step and of the Givens step covers all of them, and a request
+ * that arrives between steps joins at the next one (continuous batching).  A finished request leaves at once
  * and its memory and slot go to the next waiting request.  Every request
  * keeps the chunking and summation order of its own problem in every
  * kernel, so a result does not depend on which other requests share the
@@ -445,9 +445,12 @@ typedef struct smfs_server_config {
   size_t worker_scratch_bytes;  /* device scratch per set-up worker: a quarter (at least
                                    64 MiB) for rocSOLVER's work arrays, the rest for the
                                    batched SVD inputs and outputs (0: 4 GiB) */
+  int32_t iters_per_step;       /* GMRES iterations of the resident requests per
+                                   smfs_server_step, 1..1024 (0: 8) */
 } smfs_server_config;
 
-/* Defaults: radius 1, 64 slots, 1 worker, no queue limit, FP64, 4 GiB. */
+/* Defaults: radius 1, 64 slots, 1 worker, no queue limit, FP64, 4 GiB, 8
+ * iterations per step. */
 int smfs_server_config_default(smfs_server_config *c);
 
 /* Bytes of the fixed part of the server's device memory for these
@@ -486,10 +489,17 @@ double smfs_server_clock(void);
 int smfs_server_submit(smfs_server *srv, int32_t P, const double *centers, const double *rbm,
                        double t_arrival, int64_t *id);
 
-/* One iteration of every resident request (see above); then finished
- * requests are completed (true residual, forces and torques) and leave.
- * *n_active: requests resident after the step; *n_waiting: requests
- * queued or being set up.  Returns at once when nothing is resident. */
+/* iters_per_step GMRES iterations of every resident request (see above),
+ * with no host round trip between them: the Givens rotations, the
+ * convergence estimate and the end of a restart cycle are taken on the
+ * device, where each request's cycle state (Arnoldi index, rotated
+ * Hessenberg columns, rotations, rotated right-hand side) lives; a request
+ * that meets its estimate, its iteration limit or the end of its cycle
+ * drops out of the remaining launches of the step.  The host then restarts
+ * such requests from their FP64 true residual or completes them (true
+ * residual, forces and torques), and finished requests leave.  *n_active:
+ * requests resident after the step; *n_waiting: requests queued or being
+ * set up.  Returns at once when nothing is resident. */
 int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting);
 
 typedef struct smfs_request_result {
@@ -518,7 +528,7 @@ int smfs_server_release(smfs_server *srv, int64_t id);
 
 typedef struct smfs_server_stats {
   int64_t steps;               /* calls of smfs_server_step that iterated */
-  int64_t request_iterations;  /* sum over steps of resident requests */
+  int64_t request_iterations;  /* GMRES iterations summed over the requests */
   int64_t completed, failed;
   size_t arena_bytes, arena_peak;
   int32_t peak_active;
@@ -526,6 +536,7 @@ typedef struct smfs_server_stats {
   double tick_ms;              /* of which the batched iteration (launches and readback) */
   double setup_ms;             /* worker time building and factorising requests */
   int64_t setup_batches;       /* admission batches set up */
+  int64_t iterations;          /* batched iterations launched (steps x iters_per_step) */
 } smfs_server_stats;
 int smfs_server_stats_read(smfs_server *srv, smfs_server_stats *st);
 

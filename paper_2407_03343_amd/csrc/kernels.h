@@ -238,6 +238,20 @@ hipError_t launch_combine_block(const double *V, int64_t ld, int32_t nrhs, int32
 // ---- serving: many independent problems per launch ---------------------
 // One entry per resident problem; the product reads x and writes y, the
 // Arnoldi pass then orthogonalises y = V + nv ld against V[0..nv).
+// One resident request's GMRES cycle on the device (serving): the Arnoldi
+// index j within the cycle, the Hessenberg columns in Givens-rotated form,
+// the rotations and the rotated right-hand side g.  Every serving kernel
+// skips a request whose `active` is 0; k_serve_givens clears it when the
+// request needs the host (estimate met, iteration limit, breakdown or the
+// end of the cycle).
+struct ServeGivens {
+  int32_t j, m, active, total, max_it, breakdown;
+  double bnorm, tol, est;
+  double *H;        // (m + 1) x m, column-major
+  double *cs, *sn;  // m each
+  double *g;        // m + 1
+};
+
 struct ServeDesc {
   DirectArgs da;            // direct sum of this problem (str = lam, own part buffer)
   int64_t tile0;            // first tile of this problem in the launch
@@ -251,23 +265,25 @@ struct ServeDesc {
   const double *fac;
   double *sbuf;             // Sigma^-1 U^T x per sphere
   double *lam;              // strengths (dipoles times 2 mu), same array as da.str
-  const double *x;          // input, 3T
-  double *y;                // output G_hat x, 3T
   const double *sw;         // square-root weights, T
   double c0;                // 1 / (8 pi mu)
   int64_t n;                // 3T
-  const double *V;          // Krylov basis, stride ld
+  double *V;                // Krylov basis, stride ld: the product reads V[j], writes V[j + 1]
   int64_t ld;
-  int32_t nv;               // vectors to orthogonalise against
+  ServeGivens *gv;          // the request's cycle state (j, active, ...)
   int32_t nch;              // reduction chunks (mdot_chunks(n))
-  double *red;              // reduction partials, at least nv x nch
-  double *h, *h2;           // out: Gram-Schmidt coefficients; h[nv] = norm
+  double *red;              // reduction partials, at least (j + 1) x nch
+  double *h, *h2;           // Gram-Schmidt coefficients of the two passes; h[j + 1] = norm
 };
 hipError_t launch_serve_product(const ServeDesc *d, int32_t nprob, int64_t tiles, int64_t utasks,
                                 int64_t vtasks, int32_t max_splits, int64_t max_n, int64_t stiles,
                                 int32_t max_splits32, int64_t max_str32, hipStream_t s);
 hipError_t launch_serve_arnoldi(const ServeDesc *d, int32_t nprob, int32_t max_nv, int32_t max_nch,
                                 int64_t max_n, hipStream_t s);
+// The Givens step of every active request (one thread each): rotates the new
+// Hessenberg column h + h2, updates g and j, and clears `active` when the
+// request needs the host.
+hipError_t launch_serve_givens(const ServeDesc *d, int32_t nprob, hipStream_t s);
 
 // The shared factor 0 applied to all n_free contact-free spheres (their
 // sphere ids in free_ids) as two GEMMs on FP64 MFMA; rank and cols are

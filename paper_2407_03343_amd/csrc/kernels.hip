@@ -2300,6 +2300,11 @@ __device__ __forceinline__ int find_problem(int32_t nprob, int64_t t, Key key) {
   return uniform(lo);
 }
 
+// A request takes part in a launch while its cycle state is active; the
+// product reads V[j] and writes V[j + 1] of its basis.
+__device__ __forceinline__ bool serve_on(const ServeDesc &d) { return uniform(d.gv->active) != 0; }
+__device__ __forceinline__ int serve_j(const ServeDesc &d) { return uniform(d.gv->j); }
+
 __global__ __launch_bounds__(kBlock) void k_serve_pinv_u(const ServeDesc *__restrict__ D,
                                                          int32_t nprob, int64_t total) {
   const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
@@ -2307,8 +2312,9 @@ __global__ __launch_bounds__(kBlock) void k_serve_pinv_u(const ServeDesc *__rest
   const int r = find_problem(nprob, t, [D](int i) { return D[i].utask0; });
   const ServeDesc &d = D[r];
   const int64_t tl = t - d.utask0;
-  if (tl >= d.n_utask) return;
-  pinv_u_row(d.utask, tl, d.da.meta, d.fs, d.fac, d.x, d.sbuf);
+  if (tl >= d.n_utask || !serve_on(d)) return;
+  const double *x = d.V + (int64_t)serve_j(d) * d.ld;
+  pinv_u_row(d.utask, tl, d.da.meta, d.fs, d.fac, x, d.sbuf);
 }
 
 __global__ __launch_bounds__(kBlock) void k_serve_pinv_v(const ServeDesc *__restrict__ D,
@@ -2318,7 +2324,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_pinv_v(const ServeDesc *__rest
   const int r = find_problem(nprob, t, [D](int i) { return D[i].vtask0; });
   const ServeDesc &d = D[r];
   const int64_t tl = t - d.vtask0;
-  if (tl >= d.n_vtask) return;
+  if (tl >= d.n_vtask || !serve_on(d)) return;
   pinv_v_row(d.vtask, tl, d.da.meta, d.fs, d.fac, d.sbuf, d.lam, d.da.dscale);
 }
 
@@ -2329,7 +2335,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIR
   if (t >= total) return;
   const int r = find_problem(nprob, t, [D](int i) { return D[i].tile0; });
   const ServeDesc &d = D[r];
-  if ((int)blockIdx.y >= d.da.n_splits) return;
+  if ((int)blockIdx.y >= d.da.n_splits || !serve_on(d)) return;
   direct_wave<kTpl, false>(d.da, t - d.tile0, blockIdx.y);
 }
 
@@ -2337,7 +2343,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SMFS_DIR
 __global__ void k_serve_to32(const ServeDesc *__restrict__ D) {
   const ServeDesc &d = D[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d.fa.n_splits == 0 || i >= d.n_str32) return;
+  if (d.fa.n_splits == 0 || i >= d.n_str32 || !serve_on(d)) return;
   d.str32[i] = (float)d.lam[i];
 }
 
@@ -2351,38 +2357,41 @@ __global__ __launch_bounds__(kBlock) void k_serve_far32(const ServeDesc *__restr
   if (t >= total) return;
   const int r = find_problem(nprob, t, [D](int i) { return D[i].stile0; });
   const ServeDesc &d = D[r];
-  if ((int)blockIdx.y >= d.fa.n_splits) return;
+  if ((int)blockIdx.y >= d.fa.n_splits || !serve_on(d)) return;
   far_wave<kTpl>(d.fa, t - d.stile0, blockIdx.y);
 }
 
-// y = x + W c0 (sum_s part[s] + sum_s part32[s]) (the same arithmetic as
-// k_reduce_epilogue)
+// V[j + 1] = x + W c0 (sum_s part[s] + sum_s part32[s]) with x = V[j] (the
+// same arithmetic as k_reduce_epilogue)
 __global__ void k_serve_reduce(const ServeDesc *__restrict__ D) {
   const ServeDesc &d = D[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
+  if (i >= d.n || !serve_on(d)) return;
+  const int64_t j = serve_j(d);
   const int32_t ns = d.da.n_splits;
   double acc = 0.0;
   for (int s = 0; s < ns; ++s) acc += d.da.part[(int64_t)s * d.n + i];
   for (int s = 0; s < d.fa.n_splits; ++s) acc += (double)d.fa.part32[(int64_t)s * d.n + i];
   double v = d.c0 * acc;
   v *= d.sw[i / 3];
-  v += d.x[i];
-  d.y[i] = v;
+  v += d.V[j * d.ld + i];
+  d.V[(j + 1) * d.ld + i] = v;
 }
 
-// Classical Gram-Schmidt pass against V[0..nv) of every problem (pass 0
-// writes h, pass 1 writes h2), with the chunking and summation order of
-// the single-problem kernels.
+// Classical Gram-Schmidt pass of w = V[j + 1] against V[0..j] of every
+// problem (pass 0 writes h, pass 1 writes h2), with the chunking and
+// summation order of the single-problem kernels.
 __global__ __launch_bounds__(kBlock) void k_serve_mdot(const ServeDesc *__restrict__ D) {
   __shared__ double sh[kDotVecs][kWavesPerBlock];
   const ServeDesc &d = D[blockIdx.z];
+  if (!serve_on(d)) return;   // uniform over the block
   const int c = blockIdx.x;
   const int j0 = blockIdx.y * kDotVecs;
-  if (c >= d.nch || j0 >= d.nv) return;   // uniform over the block
+  const int nv = serve_j(d) + 1;
+  if (c >= d.nch || j0 >= nv) return;   // uniform over the block
   const int64_t chunk = chunk_len(d.n, d.nch);
   const int64_t b = (int64_t)c * chunk, e = min(d.n, b + chunk);
-  const double *w = d.y;
+  const double *w = d.V + (int64_t)nv * d.ld;
   double acc[kDotVecs];
 #pragma unroll
   for (int q = 0; q < kDotVecs; ++q) acc[q] = 0.0;
@@ -2390,17 +2399,17 @@ __global__ __launch_bounds__(kBlock) void k_serve_mdot(const ServeDesc *__restri
     const double wi = w[i];
 #pragma unroll
     for (int q = 0; q < kDotVecs; ++q)
-      if (j0 + q < d.nv) acc[q] = fma(d.V[(int64_t)(j0 + q) * d.ld + i], wi, acc[q]);
+      if (j0 + q < nv) acc[q] = fma(d.V[(int64_t)(j0 + q) * d.ld + i], wi, acc[q]);
   }
   block_sum<kDotVecs>(acc, sh);
-  if (threadIdx.x < kDotVecs && j0 + (int)threadIdx.x < d.nv)
+  if (threadIdx.x < kDotVecs && j0 + (int)threadIdx.x < nv)
     d.red[(int64_t)(j0 + threadIdx.x) * d.nch + c] = acc[threadIdx.x];
 }
 
 __global__ void k_serve_mdot_final(const ServeDesc *__restrict__ D, int pass) {
   const ServeDesc &d = D[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= d.nv) return;
+  if (!serve_on(d) || j >= serve_j(d) + 1) return;
   double s = 0.0;
   for (int c = 0; c < d.nch; ++c) s += d.red[(int64_t)j * d.nch + c];
   (pass ? d.h2 : d.h)[j] = s;
@@ -2409,18 +2418,20 @@ __global__ void k_serve_mdot_final(const ServeDesc *__restrict__ D, int pass) {
 __global__ void k_serve_mupdate(const ServeDesc *__restrict__ D, int pass) {
   const ServeDesc &d = D[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  d.y[i] -= basis_row_dot(d.V, d.ld, d.nv, pass ? d.h2 : d.h, i);
+  if (i >= d.n || !serve_on(d)) return;
+  const int nv = serve_j(d) + 1;
+  d.V[(int64_t)nv * d.ld + i] -= basis_row_dot(d.V, d.ld, nv, pass ? d.h2 : d.h, i);
 }
 
 __global__ __launch_bounds__(kBlock) void k_serve_sumsq(const ServeDesc *__restrict__ D) {
   __shared__ double sh[1][kWavesPerBlock];
   const ServeDesc &d = D[blockIdx.y];
-  if ((int)blockIdx.x >= d.nch) return;
+  if ((int)blockIdx.x >= d.nch || !serve_on(d)) return;
   const int64_t chunk = chunk_len(d.n, d.nch);
   const int64_t b = (int64_t)blockIdx.x * chunk, e = min(d.n, b + chunk);
+  const double *y = d.V + (int64_t)(serve_j(d) + 1) * d.ld;
   double acc[1] = {0.0};
-  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) acc[0] = fma(d.y[i], d.y[i], acc[0]);
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) acc[0] = fma(y[i], y[i], acc[0]);
   block_sum<1>(acc, sh);
   if (threadIdx.x == 0) d.red[blockIdx.x] = acc[0];
 }
@@ -2429,17 +2440,55 @@ __global__ void k_serve_norm(const ServeDesc *__restrict__ D, int32_t nprob) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nprob) return;
   const ServeDesc &d = D[r];
+  if (!d.gv->active) return;
   double s = 0.0;
   for (int c = 0; c < d.nch; ++c) s += d.red[c];
-  d.h[d.nv] = sqrt(s);
+  d.h[d.gv->j + 1] = sqrt(s);
 }
 
 __global__ void k_serve_scale(const ServeDesc *__restrict__ D) {
   const ServeDesc &d = D[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  const double b = d.h[d.nv];
-  d.y[i] = b > 0.0 ? d.y[i] / b : 0.0;
+  if (i >= d.n || !serve_on(d)) return;
+  const int nv = serve_j(d) + 1;
+  const double b = d.h[nv];
+  double *y = d.V + (int64_t)nv * d.ld;
+  y[i] = b > 0.0 ? y[i] / b : 0.0;
+}
+
+// Givens step of one request per thread (the host form of the single-problem
+// solver, on the device): the new column of H is h + h2 (the two
+// Gram-Schmidt passes) with the norm below them; the earlier rotations are
+// applied to it, a new rotation zeroes its last entry and rotates g.  The
+// request stays active until the estimate |g[j+1]| / |b| meets the
+// tolerance, the iteration limit is reached, the new vector vanishes
+// (breakdown) or the cycle is full.
+__global__ void k_serve_givens(const ServeDesc *__restrict__ D, int32_t nprob) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nprob) return;
+  const ServeDesc &d = D[r];
+  ServeGivens &q = *d.gv;
+  if (!q.active) return;
+  const int j = q.j, m = q.m;
+  double *col = q.H + (int64_t)j * (m + 1);
+  for (int k = 0; k <= j + 1; ++k) col[k] = d.h[k] + (k <= j ? d.h2[k] : 0.0);
+  for (int k = 0; k < j; ++k) {
+    const double t = q.cs[k] * col[k] + q.sn[k] * col[k + 1];
+    col[k + 1] = -q.sn[k] * col[k] + q.cs[k] * col[k + 1];
+    col[k] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  q.cs[j] = den > 0 ? col[j] / den : 1.0;
+  q.sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  q.g[j + 1] = -q.sn[j] * q.g[j];
+  q.g[j] = q.cs[j] * q.g[j];
+  q.j = j + 1;
+  q.total += 1;
+  q.est = fabs(q.g[j + 1]) / q.bnorm;
+  q.breakdown = d.h[j + 1] == 0.0 ? 1 : 0;
+  if (q.est <= q.tol || q.total >= q.max_it || q.breakdown || q.j == m) q.active = 0;
 }
 
 }  // namespace
@@ -2480,6 +2529,12 @@ hipError_t launch_serve_arnoldi(const ServeDesc *d, int32_t nprob, int32_t max_n
   hipLaunchKernelGGL(k_serve_sumsq, dim3((unsigned)max_nch, nprob), dim3(kBlock), 0, s, d);
   hipLaunchKernelGGL(k_serve_norm, dim3(blocks_for(nprob)), dim3(kBlock), 0, s, d, nprob);
   hipLaunchKernelGGL(k_serve_scale, dim3(blocks_for(max_n), nprob), dim3(kBlock), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_serve_givens(const ServeDesc *d, int32_t nprob, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_serve_givens, dim3(blocks_for(nprob)), dim3(kBlock), 0, s, d, nprob);
   return hipGetLastError();
 }
 

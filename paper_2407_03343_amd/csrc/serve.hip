@@ -179,8 +179,13 @@ struct smfs_server {
   int64_t next_id = 1;
   bool stop = false;
   ServeDesc *d_desc = nullptr, *h_desc = nullptr;
-  double *d_tick = nullptr, *h_tick = nullptr;
+  double *d_tick = nullptr;      // Gram-Schmidt coefficients of the slots (device only)
   int32_t ldt = 0;               // doubles per request in the tick buffer
+  // GMRES cycle state of the slots on the device, and its host mirror
+  ServeGivens *d_gv = nullptr, *h_gv = nullptr;
+  double *d_gst = nullptr, *h_gst = nullptr;  // H, cs, sn, g of each slot
+  int64_t gstride = 0;           // doubles per slot in d_gst
+  int32_t iters_per_step = 8;    // GMRES iterations per smfs_server_step
   smfs_server_stats st{};
 };
 
@@ -548,6 +553,7 @@ int smfs_server_config_default(smfs_server_config *c) {
   c->max_queued = 0;
   c->precision = SMFS_FP64;
   c->worker_scratch_bytes = kSvdScratch;
+  c->iters_per_step = 8;
   return SMFS_OK;
 }
 
@@ -560,15 +566,15 @@ namespace {
 // factor, descriptors and Hessenberg readback of the slots, every worker's
 // scratch.  Offsets from the start of the caller's memory.
 struct ServerLayout {
-  size_t f0 = 0, desc = 0, tick = 0, workers = 0, arena = 0;
+  size_t f0 = 0, desc = 0, tick = 0, gv = 0, gst = 0, workers = 0, arena = 0;
   size_t worker_bytes = 0, work_bytes = 0;
-  int64_t f0_elems = 0;
+  int64_t f0_elems = 0, gstride = 0;
   int32_t ldt = 0;
 };
 
 int server_layout(const smfs_params *p, const smfs_server_config *c, ServerLayout &L) {
   if (!p || !c || !(c->radius > 0) || c->max_active < 1 || c->max_active > 4096 || c->setup_workers < 1 ||
-      c->setup_workers > 64 || c->max_queued < 0) {
+      c->setup_workers > 64 || c->max_queued < 0 || c->iters_per_step < 0 || c->iters_per_step > 1024) {
     set_error("smfs_server: bad configuration");
     return SMFS_E_INVALID_ARG;
   }
@@ -585,7 +591,9 @@ int server_layout(const smfs_params *p, const smfs_server_config *c, ServerLayou
   const FactorSlot &f = t->factors[0];
   L.f0_elems = (int64_t)f.rows * f.cols + (int64_t)f.cols * f.cols + f.cols;
   smfs_problem_destroy(t);
-  L.ldt = 2 * (std::max(1, p->gmres_restart) + 2);
+  const int64_t m = std::max(1, p->gmres_restart);
+  L.ldt = 2 * ((int32_t)m + 2);
+  L.gstride = ((m + 1) * m + 2 * m + (m + 1) + 31) / 32 * 32;
   L.worker_bytes = al(c->worker_scratch_bytes ? c->worker_scratch_bytes : kSvdScratch);
   // a quarter of each worker's scratch (at least 64 MiB) for rocSOLVER's work arrays
   L.work_bytes = al(std::max<size_t>((size_t)64 << 20, L.worker_bytes / 4));
@@ -600,6 +608,10 @@ int server_layout(const smfs_params *p, const smfs_server_config *c, ServerLayou
   off = al(off + sizeof(ServeDesc) * (size_t)c->max_active);
   L.tick = off;
   off = al(off + sizeof(double) * (size_t)L.ldt * c->max_active);
+  L.gv = off;
+  off = al(off + sizeof(ServeGivens) * (size_t)c->max_active);
+  L.gst = off;
+  off = al(off + sizeof(double) * (size_t)L.gstride * c->max_active);
   L.workers = off;
   off += L.worker_bytes * (size_t)c->setup_workers;
   L.arena = off;
@@ -706,7 +718,13 @@ int smfs_server_create(const smfs_params *p, const smfs_server_config *c, void *
   srv->d_desc = (ServeDesc *)(base + L.desc);
   SMFS_HIP(hipHostMalloc((void **)&srv->h_desc, sizeof(ServeDesc) * c->max_active, hipHostMallocDefault));
   srv->d_tick = (double *)(base + L.tick);
-  SMFS_HIP(hipHostMalloc((void **)&srv->h_tick, sizeof(double) * srv->ldt * c->max_active, hipHostMallocDefault));
+  srv->d_gv = (ServeGivens *)(base + L.gv);
+  srv->d_gst = (double *)(base + L.gst);
+  srv->gstride = L.gstride;
+  srv->iters_per_step = c->iters_per_step > 0 ? c->iters_per_step : 8;
+  SMFS_HIP(hipHostMalloc((void **)&srv->h_gv, sizeof(ServeGivens) * c->max_active, hipHostMallocDefault));
+  SMFS_HIP(hipHostMalloc((void **)&srv->h_gst, sizeof(double) * srv->gstride * c->max_active,
+                         hipHostMallocDefault));
   srv->st.arena_bytes = srv->arena_bytes;
   for (int i = 0; i < c->setup_workers; ++i) srv->workers[i].th = std::thread(worker_main, srv, i);
   guard.s = nullptr;
@@ -732,7 +750,8 @@ void smfs_server_destroy(smfs_server *srv) {
   }
   // the device memory is the caller's; host buffers, streams and handles are ours
   if (srv->h_desc) (void)hipHostFree(srv->h_desc);
-  if (srv->h_tick) (void)hipHostFree(srv->h_tick);
+  if (srv->h_gv) (void)hipHostFree(srv->h_gv);
+  if (srv->h_gst) (void)hipHostFree(srv->h_gst);
   for (Worker &w : srv->workers) {
     if (w.rb) rocblas_destroy_handle(w.rb);
     if (w.s) (void)hipStreamDestroy(w.s);
@@ -815,8 +834,9 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
   const int32_t nprob = (int32_t)run.size();
   if (nprob > 0) {
     int64_t tiles = 0, ut = 0, vt = 0, max_n = 0, stiles = 0, max_str32 = 0;
-    int32_t max_splits = 1, max_nv = 1, max_nch = 1, max_splits32 = 0;
+    int32_t max_splits = 1, max_nch = 1, max_splits32 = 0, max_j = 0;
     const int mh = srv->ldt / 2;
+    const int64_t gs = srv->gstride;
     for (int32_t i = 0; i < nprob; ++i) {
       Req *r = run[i];
       Problem &pb = *r->pb;
@@ -847,55 +867,77 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
       d.n = 3 * pb.T;
       d.ld = pb.kry_ld;
       d.V = pb.d_kry;
-      d.x = pb.d_kry + (int64_t)r->j * d.ld;
-      d.y = pb.d_kry + (int64_t)(r->j + 1) * d.ld;
       d.sw = pb.d_sw;
       d.c0 = 1.0 / (8.0 * kPiS * pb.prm.mu);
-      d.nv = r->j + 1;
+      d.gv = srv->d_gv + i;
       d.nch = mdot_chunks(d.n);
       d.red = pb.d_red;
       d.h = srv->d_tick + (int64_t)i * srv->ldt;
       d.h2 = d.h + mh;
+      // the cycle state of slot i: header and H, cs, sn, g
+      ServeGivens &G = srv->h_gv[i];
+      G.j = r->j;
+      G.m = r->m;
+      G.active = 1;
+      G.total = r->total;
+      G.max_it = srv->prm.gmres_max_it;
+      G.breakdown = 0;
+      G.bnorm = r->bnorm;
+      G.tol = srv->prm.gmres_tol;
+      G.est = r->est;
+      G.H = srv->d_gst + (int64_t)i * gs;
+      G.cs = G.H + (int64_t)(r->m + 1) * r->m;
+      G.sn = G.cs + r->m;
+      G.g = G.sn + r->m;
+      double *hs = srv->h_gst + (int64_t)i * gs;
+      std::copy(r->H.begin(), r->H.end(), hs);
+      std::copy(r->cs.begin(), r->cs.end(), hs + (G.cs - G.H));
+      std::copy(r->sn.begin(), r->sn.end(), hs + (G.sn - G.H));
+      std::copy(r->g.begin(), r->g.end(), hs + (G.g - G.H));
       tiles += pb.n_tiles;
       ut += pb.n_utask;
       vt += pb.n_vtask;
       max_n = std::max(max_n, d.n);
       max_splits = std::max(max_splits, pb.n_splits);
-      max_nv = std::max(max_nv, d.nv);
       max_nch = std::max(max_nch, d.nch);
+      max_j = std::max(max_j, r->j);
     }
     SMFS_HIP(hipMemcpyAsync(srv->d_desc, srv->h_desc, sizeof(ServeDesc) * nprob, hipMemcpyHostToDevice, s));
-    SMFS_HIP(launch_serve_product(srv->d_desc, nprob, tiles, ut, vt, max_splits, max_n, stiles, max_splits32,
-                                  max_str32, s));
-    SMFS_HIP(launch_serve_arnoldi(srv->d_desc, nprob, max_nv, max_nch, max_n, s));
-    SMFS_HIP(hipMemcpyAsync(srv->h_tick, srv->d_tick, sizeof(double) * srv->ldt * nprob,
-                            hipMemcpyDeviceToHost, s));
+    SMFS_HIP(hipMemcpyAsync(srv->d_gv, srv->h_gv, sizeof(ServeGivens) * nprob, hipMemcpyHostToDevice, s));
+    SMFS_HIP(hipMemcpyAsync(srv->d_gst, srv->h_gst, sizeof(double) * gs * nprob, hipMemcpyHostToDevice, s));
+    // iters_per_step iterations of every request with no host round trip:
+    // each launch skips the requests whose cycle state went inactive; the
+    // Arnoldi grids cover the longest possible basis (j grows by one per
+    // iteration and stays below the cycle length)
+    const int m_all = run[0]->m;
+    for (int it = 0; it < srv->iters_per_step; ++it) {
+      const int32_t max_nv = std::min(max_j + it + 1, m_all);
+      SMFS_HIP(launch_serve_product(srv->d_desc, nprob, tiles, ut, vt, max_splits, max_n, stiles, max_splits32,
+                                    max_str32, s));
+      SMFS_HIP(launch_serve_arnoldi(srv->d_desc, nprob, max_nv, max_nch, max_n, s));
+      SMFS_HIP(launch_serve_givens(srv->d_desc, nprob, s));
+    }
+    SMFS_HIP(hipMemcpyAsync(srv->h_gv, srv->d_gv, sizeof(ServeGivens) * nprob, hipMemcpyDeviceToHost, s));
+    SMFS_HIP(hipMemcpyAsync(srv->h_gst, srv->d_gst, sizeof(double) * gs * nprob, hipMemcpyDeviceToHost, s));
     SMFS_HIP(hipStreamSynchronize(s));
     srv->st.tick_ms += (clock_s() - t0) * 1e3;
     ++srv->st.steps;
-    srv->st.request_iterations += nprob;
+    srv->st.iterations += srv->iters_per_step;
     const double tol = srv->prm.gmres_tol;
     for (int32_t i = 0; i < nprob; ++i) {
       Req *r = run[i];
-      const double *a = srv->h_tick + (int64_t)i * srv->ldt, *a2 = a + mh;
-      const int j = r->j, m = r->m;
-      double *col = &r->H[(size_t)j * (m + 1)];
-      for (int k = 0; k <= j + 1; ++k) col[k] = a[k] + (k <= j ? a2[k] : 0.0);
-      for (int k = 0; k < j; ++k) {
-        const double t = r->cs[k] * col[k] + r->sn[k] * col[k + 1];
-        col[k + 1] = -r->sn[k] * col[k] + r->cs[k] * col[k + 1];
-        col[k] = t;
-      }
-      const double den = std::hypot(col[j], col[j + 1]);
-      r->cs[j] = den > 0 ? col[j] / den : 1.0;
-      r->sn[j] = den > 0 ? col[j + 1] / den : 0.0;
-      col[j] = den;
-      col[j + 1] = 0.0;
-      r->g[j + 1] = -r->sn[j] * r->g[j];
-      r->g[j] = r->cs[j] * r->g[j];
-      r->j = j + 1;
-      ++r->total;
-      r->est = std::fabs(r->g[j + 1]) / r->bnorm;
+      const ServeGivens &G = srv->h_gv[i];
+      const double *hs = srv->h_gst + (int64_t)i * gs;
+      const int m = r->m;
+      srv->st.request_iterations += G.total - r->total;
+      r->j = G.j;
+      r->total = G.total;
+      r->est = G.est;
+      std::copy(hs, hs + r->H.size(), r->H.begin());
+      std::copy(hs + (int64_t)(m + 1) * m, hs + (int64_t)(m + 1) * m + m, r->cs.begin());
+      std::copy(hs + (int64_t)(m + 1) * m + m, hs + (int64_t)(m + 1) * m + 2 * m, r->sn.begin());
+      std::copy(hs + (int64_t)(m + 1) * m + 2 * m, hs + (int64_t)(m + 1) * m + 3 * m + 1, r->g.begin());
+      if (G.active) continue;   // still iterating: nothing for the host
       bool done = false, refine = false;
       if (r->est <= tol) {
         r->converged = true;
@@ -904,7 +946,7 @@ int smfs_server_step(smfs_server *srv, int32_t *n_active, int32_t *n_waiting) {
         // refinements); the request goes on when that residual is above tol
         refine = is_mixed(srv->prm.precision) && r->refinements < 2 &&
                  r->total < srv->prm.gmres_max_it;
-      } else if (r->total >= srv->prm.gmres_max_it || a[j + 1] == 0.0) {
+      } else if (r->total >= srv->prm.gmres_max_it || G.breakdown) {
         done = true;
       }
       if (done || r->j == m) {

@@ -137,6 +137,7 @@ def test_server_memory_query():
     cfg = smfs.smfs_server_config()
     assert smfs.lib().smfs_server_config_default(C.byref(cfg)) == 0
     assert cfg.max_active == 64 and cfg.setup_workers == 1 and cfg.worker_scratch_bytes == 4 << 30
+    assert cfg.iters_per_step == 8
     n = C.c_size_t(0)
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == 0
     one = n.value
@@ -148,6 +149,9 @@ def test_server_memory_query():
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -3
     cfg.precision = smfs.SMFS_MIXED_FAR
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == 0
+    cfg.iters_per_step = 2000
+    assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -1
+    cfg.iters_per_step = 8
     cfg.max_active = 0
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -1
 
