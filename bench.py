@@ -670,7 +670,8 @@ def serving(args, torch, smfs, reqs, arrivals):
     single-problem path (a sample of them, timed end to end)."""
     n = len(reqs)
     disc = dict(n_proxy=args.serve_proxy, n_colloc_base=args.serve_colloc, n_image=args.serve_image,
-                n_check_base=0)
+                n_check_base=0,
+                svd_method=smfs.SMFS_SVD_JACOBI if args.serve_svd == "jacobi" else smfs.SMFS_SVD_ROCSOLVER)
     solver = dict(gmres_tol=args.serve_tol, gmres_restart=100, gmres_max_it=3000)
     prec = smfs.SMFS_MIXED_FAR if args.serve_precision == "mixed_far" else smfs.SMFS_FP64
     srv = smfs.Server(arena_bytes=args.serve_arena << 30, max_active=args.serve_slots,
@@ -704,7 +705,7 @@ def serving(args, torch, smfs, reqs, arrivals):
     its = np.array([r["iterations"] for r in res])
     out = {
         "requests": n, "rate_per_s": args.serve_rate, "setup_workers": args.serve_workers,
-        "precision": args.serve_precision,
+        "precision": args.serve_precision, "svd": args.serve_svd,
         "pair_evals_f32": int(sum(r["pair_evals_f32"] for r in res)),
         "refinements_max": int(max(r["refinements"] for r in res)),
         "stagnated": int(sum(1 for r in res if r["status"] == 3)),
@@ -727,6 +728,8 @@ def serving(args, torch, smfs, reqs, arrivals):
     }
     # the same requests one after another through the single-problem path
     k = min(n, args.serve_sequential)
+    if k == 0:
+        return out
     t1 = time.perf_counter()
     for r in reqs[:k]:
         pb = smfs.Problem(r["centers"], 1.0, gmres_check_every=0, **disc, **solver).bind().setup()
@@ -849,6 +852,8 @@ def main():
                     help="products inside the served GMRES iterations")
     ap.add_argument("--serve-sequential", type=int, default=2,
                     help="requests solved one after another for the comparison")
+    ap.add_argument("--serve-svd", choices=["rocsolver", "jacobi"], default="jacobi",
+                    help="SVD of the served requests' self blocks at set-up")
     ap.add_argument("--serve-iters", type=int, default=8,
                     help="GMRES iterations per server step (no host round trip between them)")
     ap.add_argument("--serve-only", action="store_true",

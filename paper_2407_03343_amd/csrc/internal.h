@@ -196,8 +196,9 @@ bool eq_enabled(const Problem &pb);
 // svd.hip: the device Jacobi SVD (QR, one-sided Jacobi on R, U = Q U_R)
 struct JacPlan {
   int w = 8, rows = 4, npad = 0, nbk = 0, npairs = 0;
+  bool wave = false;   // pair tasks of one wave (blocks of at most 768 columns)
   size_t work = 0;
-  size_t a = 0, tau = 0, t = 0, tau2 = 0, x = 0, v = 0, wbuf = 0, off = 0, sig = 0, fro = 0, perm = 0, rank = 0, ptrs = 0, sched = 0;
+  size_t a = 0, tau = 0, t = 0, tau2 = 0, x = 0, v = 0, wbuf = 0, off = 0, sig = 0, fro = 0, perm = 0, rank = 0, ptrs = 0, sched = 0, skip = 0;
   size_t total = 0;
 };
 }  // namespace smfs

@@ -394,6 +394,88 @@ void factor_batch(Worker &wk, std::vector<Req *> &batch) {
   }
 }
 
+// factor_batch with the device Jacobi SVD (svd_method SMFS_SVD_JACOBI): per
+// block shape, chunks of as many blocks as the worker's memory holds (its
+// rocSOLVER part and its scratch, which are contiguous, serve as one region
+// laid out by the Jacobi plan); U, V and sigma are written straight into
+// the requests' factor slots.  A block's sweeps stop when its own rotations
+// do, so its factors do not depend on the other blocks of the call.
+void factor_batch_jacobi(Worker &wk, std::vector<Req *> &batch) {
+  struct Job {
+    Req *r;
+    int fid;
+  };
+  std::map<std::pair<int, int>, std::vector<Job>> groups;
+  for (Req *r : batch) {
+    Problem &pb = *r->pb;
+    for (size_t f = 1; f < pb.factors.size(); ++f)
+      if (pb.factors[f].rep >= 0) groups[{pb.factors[f].rows, pb.factors[f].cols}].push_back(Job{r, (int)f});
+  }
+  hipStream_t s = wk.s;
+  char *region = (char *)wk.work;
+  const size_t region_bytes = wk.work_bytes + wk.scratch_bytes;
+  auto fail = [](Req *r, int rc) {
+    if (r->status == SMFS_OK) {
+      r->status = rc;
+      r->err = smfs_last_error();
+    }
+  };
+  for (auto &grp : groups) {
+    const int m = grp.first.first, n = grp.first.second;
+    std::vector<Job> &jobs = grp.second;
+    int cap = (int)std::min<size_t>(kSvdBatch, jobs.size());
+    while (true) {
+      JacPlan jp;
+      if (jacobi_plan(wk.rb, m, n, cap, jp) == SMFS_OK && jp.total <= region_bytes) break;
+      if (cap == 1) { cap = 0; break; }
+      cap = std::max(1, cap / 2);
+    }
+    if (cap == 0) {
+      set_error("serving: a " + std::to_string(m) + " x " + std::to_string(n) +
+                " block does not fit the set-up worker's memory for the device SVD");
+      for (const Job &jb : jobs) fail(jb.r, SMFS_E_NOMEM);
+      continue;
+    }
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += cap) {
+      const int nb = (int)std::min<size_t>(cap, jobs.size() - j0);
+      JacPlan jp;
+      int rc = jacobi_plan(wk.rb, m, n, nb, jp);
+      double *A = (double *)(region + jp.work);
+      std::vector<double *> U(nb), V(nb), S(nb);
+      for (int q = 0; q < nb && !rc; ++q) {
+        const Job &jb = jobs[j0 + q];
+        Problem &pb = *jb.r->pb;
+        const FactorSlot &fs = pb.factors[jb.fid];
+        const SphereMeta &mk = pb.meta[fs.rep];
+        if (launch_assemble_block(pb.d_tgt, pb.d_sw, pb.d_src, pb.d_meta, fs.rep, mk.M, mk.N, pb.prm.mu,
+                                  A + (size_t)q * m * n, s) != hipSuccess) {
+          set_error("serving: block assembly failed");
+          rc = SMFS_E_DEVICE;
+        }
+        U[q] = pb.d_fac + fs.u_off;
+        V[q] = pb.d_fac + fs.vt_off;
+        S[q] = pb.d_fac + fs.sig_off;
+      }
+      std::vector<int> ranks(nb, 0);
+      int sweeps = 0;
+      if (!rc) rc = jacobi_svd_batch(wk.rb, jp, region, m, n, nb, U.data(), V.data(), S.data(),
+                                     jobs[j0].r->pb->prm.trunc_rel, ranks.data(), &sweeps, s);
+      // the region's rocSOLVER part is the handle's workspace again
+      if (rocblas_set_workspace(wk.rb, wk.work, wk.work_bytes) != rocblas_status_success && !rc) {
+        set_error("rocblas_set_workspace failed");
+        rc = SMFS_E_DEVICE;
+      }
+      for (int q = 0; q < nb; ++q) {
+        const Job &jb = jobs[j0 + q];
+        if (rc) { fail(jb.r, rc); continue; }
+        Problem &pb = *jb.r->pb;
+        pb.factors[jb.fid].rank = ranks[q];
+        pb.svd_sweeps = std::max(pb.svd_sweeps, sweeps);
+      }
+    }
+  }
+}
+
 void worker_main(smfs_server *srv, int wi) {
   (void)hipSetDevice(srv->device);
   Worker &wk = srv->workers[wi];
@@ -431,7 +513,8 @@ void worker_main(smfs_server *srv, int wi) {
         ok.push_back(r);
       }
     }
-    factor_batch(wk, ok);
+    if (srv->prm.svd_method == SMFS_SVD_JACOBI) factor_batch_jacobi(wk, ok);
+    else factor_batch(wk, ok);
     for (Req *r : ok)
       if (r->status == SMFS_OK) {
         const int rc = prepare_request(wk, r);

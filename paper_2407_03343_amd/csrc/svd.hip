@@ -67,6 +67,7 @@ struct JacArgs {
   double *Wout;         // per block and pair task: 2w x 2w rotation product (column-major)
   double *off;          // per block and pair task: largest cosine / tolerance seen before rotation
   const double *fro;    // per block: Frobenius norm of R
+  const int32_t *skip;  // per block: 1 once its sweeps have converged (its tasks leave it as it is)
 };
 
 // Shared memory of a pair task.
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jac_pairs(JacArgs a) {
   const int2 pr = a.pairs[task];
   double *Wo = a.Wout + ((int64_t)b * a.npairs + task) * kW2 * kW2;
   double *offo = a.off + (int64_t)b * a.npairs + task;
-  if (pr.x < 0) {
+  if (pr.x < 0 || a.skip[b]) {
     if (tid == 0) *offo = 0.0;
     return;
   }
@@ -219,15 +220,125 @@ __global__ __launch_bounds__(kJacThreads) void k_jac_pairs(JacArgs a) {
   }
 }
 
+// The pair task of k_jac_pairs in one wave, for blocks of at most 64 kRows
+// rows: lane l holds rows l, l + 64, ... of the 2w columns and row l of W
+// (l < 2w).  The dot products are reduced by an xor butterfly, which leaves
+// the same sums, bitwise, in every lane (each step adds the same two
+// partials), so every lane computes the same rotations and no barrier is
+// needed.
+template <int kRows, int kW2, int q>
+__device__ __forceinline__ void jacw_round(double (&x)[kRows][kW2], double (&wr)[kW2], double &offmax,
+                                           double noise) {
+  constexpr int w = kW2 / 2;
+  double s[3 * w];
+#pragma unroll
+  for (int i = 0; i < w; ++i) {
+    const int ca = rr_a(q, i, kW2), cb = rr_b(q, i, kW2);
+    double aa = 0.0, bb = 0.0, ab = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      aa = fma(x[k][ca], x[k][ca], aa);
+      bb = fma(x[k][cb], x[k][cb], bb);
+      ab = fma(x[k][ca], x[k][cb], ab);
+    }
+    s[3 * i] = aa;
+    s[3 * i + 1] = bb;
+    s[3 * i + 2] = ab;
+  }
+#pragma unroll
+  for (int v = 0; v < 3 * w; ++v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s[v] += __shfl_xor(s[v], o);
+  }
+#pragma unroll
+  for (int i = 0; i < w; ++i) {
+    const int ca = rr_a(q, i, kW2), cb = rr_b(q, i, kW2);
+    const double aa = s[3 * i], bb = s[3 * i + 1], ab = s[3 * i + 2];
+    double c = 1.0, sn = 0.0;
+    if (aa > 0.0 && bb > 0.0) {
+      const double na = sqrt(aa), nb = sqrt(bb);
+      const double cosv = fabs(ab) / (na * nb);
+      offmax = fmax(offmax, cosv / fmax(kSweepTol, noise / fmin(na, nb)));
+      if (cosv > kRotTol) {
+        // x_a' = c x_a - s x_b, x_b' = s x_a + c x_b with x_a'.x_b' = 0
+        const double zeta = (bb - aa) / (2.0 * ab);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = 1.0 / sqrt(1.0 + t * t);
+        sn = c * t;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const double xa = x[k][ca], xb = x[k][cb];
+      x[k][ca] = c * xa - sn * xb;
+      x[k][cb] = sn * xa + c * xb;
+    }
+    const double wa = wr[ca], wb = wr[cb];
+    wr[ca] = c * wa - sn * wb;
+    wr[cb] = sn * wa + c * wb;
+  }
+}
+
+template <int kRows, int kW2, int... Q>
+__device__ __forceinline__ void jacw_rounds(double (&x)[kRows][kW2], double (&wr)[kW2], double &offmax,
+                                            double noise, std::integer_sequence<int, Q...>) {
+  (jacw_round<kRows, kW2, Q>(x, wr, offmax, noise), ...);
+}
+
+template <int kRows, int kW2>
+__global__ __launch_bounds__(64) void k_jac_pairs_wave(JacArgs a) {
+  const int lane = threadIdx.x;
+  const int task = blockIdx.x, b = blockIdx.y;
+  const int2 pr = a.pairs[task];
+  double *Wo = a.Wout + ((int64_t)b * a.npairs + task) * kW2 * kW2;
+  double *offo = a.off + (int64_t)b * a.npairs + task;
+  if (pr.x < 0 || a.skip[b]) {
+    if (lane == 0) *offo = 0.0;
+    return;
+  }
+  constexpr int w = kW2 / 2;
+  double *X = a.X + (int64_t)b * a.x_stride;
+  double x[kRows][kW2];
+#pragma unroll
+  for (int c = 0; c < kW2; ++c) {
+    const int64_t gc = c < w ? (int64_t)pr.x * w + c : (int64_t)pr.y * w + (c - w);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int r = lane + 64 * k;
+      x[k][c] = r < a.n ? X[gc * a.n + r] : 0.0;
+    }
+  }
+  double wr[kW2];
+#pragma unroll
+  for (int c = 0; c < kW2; ++c) wr[c] = c == lane ? 1.0 : 0.0;
+  double offmax = 0.0;
+  jacw_rounds<kRows, kW2>(x, wr, offmax, kNoise * a.fro[b], std::make_integer_sequence<int, kW2 - 1>{});
+#pragma unroll
+  for (int c = 0; c < kW2; ++c) {
+    const int64_t gc = c < w ? (int64_t)pr.x * w + c : (int64_t)pr.y * w + (c - w);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int r = lane + 64 * k;
+      if (r < a.n) X[gc * a.n + r] = x[k][c];
+    }
+  }
+  if (lane < kW2) {
+#pragma unroll
+    for (int c = 0; c < kW2; ++c) Wo[c * kW2 + lane] = wr[c];
+  }
+  if (lane == 0) *offo = offmax;
+}
+
 // V (npad x npad, row-major per block) <- V[:, I u J] W for every pair task
 // of the round: one thread per row.
 template <int kW2>
 __global__ __launch_bounds__(256) void k_jac_vupdate(double *V, int64_t v_stride, int32_t npad,
-                                                     const int2 *pairs, int32_t npairs, const double *Wbuf) {
+                                                     const int2 *pairs, int32_t npairs, const double *Wbuf,
+                                                     const int32_t *skip) {
   __shared__ double W[kW2 * kW2];
   const int task = blockIdx.y, b = blockIdx.z;
   const int2 pr = pairs[task];
-  if (pr.x < 0) return;
+  if (pr.x < 0 || skip[b]) return;
   const double *Wi = Wbuf + ((int64_t)b * npairs + task) * kW2 * kW2;
   for (int e = threadIdx.x; e < kW2 * kW2; e += blockDim.x) W[e] = Wi[e];
   __syncthreads();
@@ -369,8 +480,11 @@ std::vector<int2> block_schedule(int nbk) {
 }  // namespace
 
 // Column-block width and rows per thread for n rows: the 2w columns of a
-// pair task must fit in registers across 512 threads.
-int jacobi_shape(int n, int &w, int &rows) {
+// pair task must fit in registers, across one wave (n <= 768) or across 512
+// threads.
+int jacobi_shape(int n, int &w, int &rows, bool &wave) {
+  wave = n <= 768;   // one wave per pair task, 4 / 8 / 12 rows per lane
+  if (wave) { w = 4; rows = n <= 256 ? 4 : n <= 512 ? 8 : 12; return SMFS_OK; }
   if (n <= 2048) { w = 8; rows = 4; return SMFS_OK; }
   if (n <= 4096) { w = 4; rows = 8; return SMFS_OK; }
   set_error("device SVD: blocks with more than 4096 columns are not supported");
@@ -382,7 +496,7 @@ int jacobi_shape(int n, int &w, int &rows) {
 // QR scalars, X, V, rotation products, cosines, norms, permutations, ranks,
 // slot pointers, schedule.
 int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
-  int rc = jacobi_shape(n, p.w, p.rows);
+  int rc = jacobi_shape(n, p.w, p.rows, p.wave);
   if (rc) return rc;
   p.npad = (n + p.w - 1) / p.w * p.w;
   p.nbk = p.npad / p.w;
@@ -426,7 +540,9 @@ int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
   p.rank = al256(sizeof(int32_t) * (size_t)nb);
   p.ptrs = al256(sizeof(double *) * 3 * (size_t)nb);
   p.sched = al256(sizeof(int2) * (size_t)(p.nbk - 1) * p.npairs);
-  p.total = p.work + p.a + p.tau + p.t + p.tau2 + p.x + p.v + p.wbuf + p.off + p.sig + p.fro + p.perm + p.rank + p.ptrs + p.sched;
+  p.skip = al256(sizeof(int32_t) * (size_t)nb);
+  p.total = p.work + p.a + p.tau + p.t + p.tau2 + p.x + p.v + p.wbuf + p.off + p.sig + p.fro + p.perm + p.rank +
+            p.ptrs + p.sched + p.skip;
   return SMFS_OK;
 }
 
@@ -452,6 +568,7 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   int32_t *drank = (int32_t *)o; o += p.rank;
   double **ptrs = (double **)o; o += p.ptrs;
   int2 *sched = (int2 *)o; o += p.sched;
+  int32_t *skip = (int32_t *)o; o += p.skip;
   if (rocblas_set_workspace(h, work, p.work) != rocblas_status_success) {
     set_error("device SVD: rocblas_set_workspace failed");
     return SMFS_E_DEVICE;
@@ -490,6 +607,11 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   SMFS_HIP(hipMemcpyAsync(sched, sch_host.data(), sizeof(int2) * sch_host.size(), hipMemcpyHostToDevice, s));
   const int rounds = p.nbk - 1;
   std::vector<double> offh((size_t)nb * p.npairs * rounds);
+  // a block whose sweep saw no cosine above its tolerance is left alone by
+  // the later sweeps, so that its factors do not depend on the other blocks
+  // of the batch
+  std::vector<int32_t> skiph(nb, 0);
+  SMFS_HIP(hipMemcpyAsync(skip, skiph.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
     for (int r = 0; r < rounds; ++r) {
@@ -504,26 +626,39 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
       ja.Wout = Wb;
       ja.off = off + (int64_t)r * nb * p.npairs;
       ja.fro = fro;
+      ja.skip = skip;
       const dim3 g((unsigned)p.npairs, (unsigned)nb);
-      if (p.w == 8) hipLaunchKernelGGL((k_jac_pairs<4, 16>), g, dim3(kJacThreads), 0, s, ja);
+      if (p.wave && p.rows == 4) hipLaunchKernelGGL((k_jac_pairs_wave<4, 8>), g, dim3(64), 0, s, ja);
+      else if (p.wave && p.rows == 8) hipLaunchKernelGGL((k_jac_pairs_wave<8, 8>), g, dim3(64), 0, s, ja);
+      else if (p.wave) hipLaunchKernelGGL((k_jac_pairs_wave<12, 8>), g, dim3(64), 0, s, ja);
+      else if (p.w == 8) hipLaunchKernelGGL((k_jac_pairs<4, 16>), g, dim3(kJacThreads), 0, s, ja);
       else hipLaunchKernelGGL((k_jac_pairs<8, 8>), g, dim3(kJacThreads), 0, s, ja);
       SMFS_HIP(hipGetLastError());
       const dim3 gv((unsigned)((p.npad + 255) / 256), (unsigned)p.npairs, (unsigned)nb);
       if (p.w == 8)
-        hipLaunchKernelGGL((k_jac_vupdate<16>), gv, dim3(256), 0, s, V, vs, p.npad, ja.pairs, p.npairs, Wb);
+        hipLaunchKernelGGL((k_jac_vupdate<16>), gv, dim3(256), 0, s, V, vs, p.npad, ja.pairs, p.npairs, Wb, skip);
       else
-        hipLaunchKernelGGL((k_jac_vupdate<8>), gv, dim3(256), 0, s, V, vs, p.npad, ja.pairs, p.npairs, Wb);
+        hipLaunchKernelGGL((k_jac_vupdate<8>), gv, dim3(256), 0, s, V, vs, p.npad, ja.pairs, p.npairs, Wb, skip);
       SMFS_HIP(hipGetLastError());
     }
     SMFS_HIP(hipMemcpyAsync(offh.data(), off, sizeof(double) * offh.size(), hipMemcpyDeviceToHost, s));
     SMFS_HIP(hipStreamSynchronize(s));
-    double mx = 0.0;
-    for (double v : offh) mx = std::max(mx, v);
-    if (!(mx >= 0.0)) {
-      set_error("device SVD: non-finite rotation");
-      return SMFS_E_SVD;
+    // offh: [round][block][task]
+    bool all = true;
+    for (int b = 0; b < nb; ++b) {
+      if (skiph[b]) continue;
+      double mx = 0.0;
+      for (int r = 0; r < rounds; ++r)
+        for (int t = 0; t < p.npairs; ++t) mx = std::max(mx, offh[((size_t)r * nb + b) * p.npairs + t]);
+      if (!(mx >= 0.0)) {
+        set_error("device SVD: non-finite rotation");
+        return SMFS_E_SVD;
+      }
+      if (mx < 1.0) skiph[b] = 1;
+      else all = false;
     }
-    if (mx < 1.0) { ++sweep; break; }
+    if (all) { ++sweep; break; }
+    SMFS_HIP(hipMemcpyAsync(skip, skiph.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
   }
   if (sweeps_out) *sweeps_out = sweep;
   if (sweep >= kMaxSweeps) {

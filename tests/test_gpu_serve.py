@@ -221,3 +221,39 @@ def test_serving_queue_full(dev, stream):
     st = srv.stats()
     srv.close()
     assert st["completed"] == 3 and all(r["status"] in (0, 3) for r in res)
+
+
+def test_serving_jacobi_set_up(dev, oracle_pairsum_built, stream):
+    """Set-up workers on the device Jacobi SVD (svd_method SMFS_SVD_JACOBI):
+    every request completes; a request served alone equals the same request
+    in the mix (a block's Jacobi sweeps stop on its own rotations, so its
+    factors do not depend on the other blocks of a batch); one request
+    against the FP64 oracle at 1e-5."""
+    _say("serving with the device Jacobi SVD: 10 requests through one server")
+    srv = dev.Server(arena_bytes=2 << 30, max_active=8, svd_method=dev.SMFS_SVD_JACOBI, **DISC, **SOLVER)
+    ids = [srv.submit(r["centers"], r["rbm"]) for r in stream]
+    srv.drain(timeout_s=120)
+    res = [srv.poll(i, r["P"]) for i, r in zip(ids, stream)]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(stream) and st["failed"] == 0
+    assert all(r["status"] in (0, 3) and r["true_rel_residual"] < 1e-6 for r in res)
+    for k in (0, 9):
+        r = stream[k]
+        srv = dev.Server(arena_bytes=1 << 30, max_active=1, svd_method=dev.SMFS_SVD_JACOBI, **DISC, **SOLVER)
+        i = srv.submit(r["centers"], r["rbm"])
+        srv.drain(timeout_s=60)
+        alone = srv.poll(i, r["P"])
+        srv.close()
+        _say(f"  request {k} (P={r['P']}) alone: it {alone['iterations']} vs {res[k]['iterations']} in the mix")
+        assert alone["iterations"] == res[k]["iterations"]
+        scale = np.abs(alone["ft"]).max()
+        assert np.abs(alone["ft"] - res[k]["ft"]).max() <= 1e-12 * scale
+    k = 2
+    r = stream[k]
+    g = geo.build(r["centers"], 1.0, geo.Params(**DISC))
+    pbo = mfs.Problem(g).setup()
+    ref = mfs.solve_resistance(pbo, r["rbm"], tol=1e-10)["ft"]
+    d = np.abs(res[k]["ft"] - ref).max() / np.abs(ref).max()
+    _say(f"  request {k} (P={r['P']}): served (Jacobi set-up) vs oracle {d:.2e}")
+    assert d < 1e-5

@@ -114,3 +114,49 @@ def test_jacobi_matches_rocsolver_factors(dev, pair_jacobi, pair001, block0):
     dr = np.linalg.norm(lb - lam_ref) / np.linalg.norm(lam_ref)
     _say(f"  B^+ b: Jacobi vs rocSOLVER {d:.3e}, rocSOLVER vs LAPACK {dr:.3e} (sensitivity {sens:.2e})")
     assert d < 10 * sens
+
+
+@pytest.mark.parametrize("disc", [dict(n_proxy=60, n_colloc_base=80, n_image=4),
+                                  dict(n_proxy=120, n_colloc_base=160, n_image=6),
+                                  dict(n_proxy=200, n_colloc_base=260, n_image=8)],
+                         ids=["cols216", "cols414", "cols672"])
+def test_jacobi_small_blocks(dev, oracle_pairsum_built, disc):
+    """Blocks of at most 768 columns take the one-wave pair tasks (4, 8 and 12
+    rows per lane for 216, 414 and 672 columns): two spheres at gap 0.01 at
+    reduced discretisations, the device Jacobi SVD against the oracle's
+    LAPACK factors: ranks, B^+ b of a physical right-hand side within 10 x
+    its perturbation sensitivity, the same projection residual to 1e-3, and
+    the solve's forces and torques within 1e-5 of the oracle's."""
+    from oracle import geometry as geo
+    pk, rbms = wl.workload_two_sphere_gap001()
+    rbm = rbms[0]
+    g = geo.build(pk.centers, 1.0, geo.Params(**disc))
+    pbo = mfs.Problem(g).setup()
+    ref = mfs.solve_resistance(pbo, rbm, tol=1e-10)
+    lib = dev.Problem(pk.centers, 1.0, svd_method=dev.SMFS_SVD_JACOBI, **disc).bind().setup()
+    B = mfs.self_block(g, 0)
+    assert B.shape[1] <= 768
+    for fid in range(lib.sizes.n_factors):
+        info = lib.factor_info(fid)
+        if info["sphere"] < 0:
+            continue
+        of = pbo.factors[int(pbo.factor_of[info["sphere"]])]
+        assert abs(info["rank"] - of.s.size) <= max(2, of.s.size // 100)
+    b = ref["b"][pbo.tslice(0)]
+    sens = _perturbation_sensitivity(B, b, g.params.trunc_rel)
+    f = pbo.factors[int(pbo.factor_of[0])]
+    lam_ref = f.V @ ((f.U.T @ b) / f.s)
+    lam = _n(lib.transform(_t(ref["b"]))).reshape(-1, 3)[g.local_sources[0]].reshape(-1)
+    d = np.linalg.norm(lam - lam_ref) / np.linalg.norm(lam_ref)
+    r_ref = np.linalg.norm(B @ lam_ref - b) / np.linalg.norm(b)
+    r = np.linalg.norm(B @ lam - b) / np.linalg.norm(b)
+    out = lib.solve_resistance(_t(rbm))
+    ft = _n(out["ft"]).reshape(-1, 6)
+    dF = np.abs(ft - ref["ft"]).max() / np.abs(ref["ft"]).max()
+    _say(f"  {B.shape[0]} x {B.shape[1]}: {lib.sizes.svd_sweeps} sweeps; B^+ b vs LAPACK {d:.2e} "
+         f"(sensitivity {sens:.2e}); residual {r:.6e} (LAPACK {r_ref:.6e}); solve it {out['iterations']}, "
+         f"F/T vs oracle {dF:.2e}")
+    assert 0 < lib.sizes.svd_sweeps < 40
+    assert d < 10 * sens
+    assert abs(r - r_ref) < 1e-3 * r_ref
+    assert _finished(out) and dF < 1e-5
