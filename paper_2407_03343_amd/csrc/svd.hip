@@ -68,6 +68,8 @@ struct JacArgs {
   double *off;          // per block and pair task: largest cosine / tolerance seen before rotation
   const double *fro;    // per block: Frobenius norm of R
   const int32_t *skip;  // per block: 1 once its sweeps have converged (its tasks leave it as it is)
+  double *V;            // k_jac_pairs_wave: V (npad x npad, row-major per block), updated in the task
+  int64_t v_stride;
 };
 
 // Shared memory of a pair task.
@@ -225,7 +227,8 @@ __global__ __launch_bounds__(kJacThreads) void k_jac_pairs(JacArgs a) {
 // (l < 2w).  The dot products are reduced by an xor butterfly, which leaves
 // the same sums, bitwise, in every lane (each step adds the same two
 // partials), so every lane computes the same rotations and no barrier is
-// needed.
+// needed.  The task then applies W to the 2w columns of V itself (the
+// arithmetic of k_jac_vupdate).
 template <int kRows, int kW2, int q>
 __device__ __forceinline__ void jacw_round(double (&x)[kRows][kW2], double (&wr)[kW2], double &offmax,
                                            double noise) {
@@ -290,7 +293,6 @@ __global__ __launch_bounds__(64) void k_jac_pairs_wave(JacArgs a) {
   const int lane = threadIdx.x;
   const int task = blockIdx.x, b = blockIdx.y;
   const int2 pr = a.pairs[task];
-  double *Wo = a.Wout + ((int64_t)b * a.npairs + task) * kW2 * kW2;
   double *offo = a.off + (int64_t)b * a.npairs + task;
   if (pr.x < 0 || a.skip[b]) {
     if (lane == 0) *offo = 0.0;
@@ -322,9 +324,33 @@ __global__ __launch_bounds__(64) void k_jac_pairs_wave(JacArgs a) {
       if (r < a.n) X[gc * a.n + r] = x[k][c];
     }
   }
+  // V[:, I u J] <- V[:, I u J] W, W through LDS into every lane's registers
+  __shared__ double Ws[kW2 * kW2];
   if (lane < kW2) {
 #pragma unroll
-    for (int c = 0; c < kW2; ++c) Wo[c * kW2 + lane] = wr[c];
+    for (int c = 0; c < kW2; ++c) Ws[c * kW2 + lane] = wr[c];
+  }
+  __syncthreads();
+  double W[kW2 * kW2];
+#pragma unroll
+  for (int e = 0; e < kW2 * kW2; ++e) W[e] = Ws[e];
+  double *Vb = a.V + (int64_t)b * a.v_stride;
+  for (int r = lane; r < a.npad; r += 64) {
+    double *row = Vb + (int64_t)r * a.npad;
+    double v[kW2];
+#pragma unroll
+    for (int c = 0; c < w; ++c) {
+      v[c] = row[(int64_t)pr.x * w + c];
+      v[w + c] = row[(int64_t)pr.y * w + c];
+    }
+#pragma unroll
+    for (int c = 0; c < kW2; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < kW2; ++k) t = fma(v[k], W[c * kW2 + k], t);
+      if (c < w) row[(int64_t)pr.x * w + c] = t;
+      else row[(int64_t)pr.y * w + (c - w)] = t;
+    }
   }
   if (lane == 0) *offo = offmax;
 }
@@ -627,6 +653,8 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
       ja.off = off + (int64_t)r * nb * p.npairs;
       ja.fro = fro;
       ja.skip = skip;
+      ja.V = V;
+      ja.v_stride = vs;
       const dim3 g((unsigned)p.npairs, (unsigned)nb);
       if (p.wave && p.rows == 4) hipLaunchKernelGGL((k_jac_pairs_wave<4, 8>), g, dim3(64), 0, s, ja);
       else if (p.wave && p.rows == 8) hipLaunchKernelGGL((k_jac_pairs_wave<8, 8>), g, dim3(64), 0, s, ja);
@@ -634,6 +662,7 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
       else if (p.w == 8) hipLaunchKernelGGL((k_jac_pairs<4, 16>), g, dim3(kJacThreads), 0, s, ja);
       else hipLaunchKernelGGL((k_jac_pairs<8, 8>), g, dim3(kJacThreads), 0, s, ja);
       SMFS_HIP(hipGetLastError());
+      if (p.wave) continue;   // the one-wave tasks update V themselves
       const dim3 gv((unsigned)((p.npad + 255) / 256), (unsigned)p.npairs, (unsigned)nb);
       if (p.w == 8)
         hipLaunchKernelGGL((k_jac_vupdate<16>), gv, dim3(256), 0, s, V, vs, p.npad, ja.pairs, p.npairs, Wb, skip);
