@@ -2,7 +2,9 @@
 // eq. transform; truncation eps_trunc of Section 5), in three stages:
 //   B = Q1 R1 and R1^T = Q2 R2 (rocSOLVER geqrf, batched);
 //   one-sided Jacobi (Hestenes) on X = R2^T in HIP: X J = U_X Sigma;
-//   U = Q1 [U_X; 0] and V = Q2 J (rocSOLVER ormqr), since
+//   U = Q1 [U_X; 0] and V = Q2 J (the reflectors of the two QRs applied by
+//   k_qr_apply to a whole batch, or by rocSOLVER ormqr per block when the
+//   batch is too small to fill the GPU), since
 //   B = Q1 R2^T Q2^T = Q1 U_X Sigma J^T Q2^T.
 // The second QR is a preconditioner: R2^T is much closer to having
 // orthogonal columns than R1 (on a 4500 x 1980 contact block the Jacobi
@@ -15,9 +17,12 @@
 // everything below sqrt(eps) sigma_1, far above the 5e-12 truncation).  The
 // columns are processed in blocks of w: a sweep visits every pair of column
 // blocks once (round-robin schedule, disjoint pairs in parallel); a pair
-// task holds its 2w columns in registers across a 512-thread workgroup and
-// runs one round-robin sweep over the 2w columns, accumulating its
-// rotations in a 2w x 2w matrix that a second kernel applies to V.  Sweeps
+// task holds its 2w columns in registers across a 512-thread workgroup (or
+// one wave, for blocks of at most 768 columns) and runs one round-robin
+// sweep over the 2w columns, accumulating its rotations in a 2w x 2w matrix
+// that is applied to V (by a second kernel, or by the one-wave task itself).
+// A block whose sweep saw no cosine above its tolerance is left alone by
+// the later sweeps.  Sweeps
 // repeat until no pair of columns has a cosine above
 // max(1e-13, 64 eps ||R||_F / min(|x_a|, |x_b|)): rounding in the rotations
 // leaves every column perturbed at the level eps ||R||_F, so a column near
@@ -388,6 +393,52 @@ __global__ __launch_bounds__(256) void k_jac_vupdate(double *V, int64_t v_stride
   }
 }
 
+// C <- Q C for the Householder QR of every block of a batch (the geqrf
+// layout: reflector k is column k of A below the diagonal with an implicit
+// 1 on it; Q = H_0 H_1 ... H_{K-1}, H_k = I - tau_k v_k v_k^T), the
+// reflectors applied last to first.  One wave per block (blockIdx.y) and 8
+// columns of C (blockIdx.x); block b's C has ncols[b] columns of leading
+// dimension ldc, at Cp[b] (or at Cbase + b c_stride when Cp is null).
+__global__ __launch_bounds__(64) void k_qr_apply(const double *A, int64_t a_stride, int32_t m, int32_t K,
+                                                 const double *tau, int64_t tau_stride, double *const *Cp,
+                                                 double *Cbase, int64_t c_stride, int32_t ldc,
+                                                 const int32_t *ncols) {
+  constexpr int kc = 8;
+  const int b = blockIdx.y, lane = threadIdx.x;
+  const int c0 = blockIdx.x * kc;
+  const int nc = ncols[b];
+  if (c0 >= nc) return;
+  const int cn = min(kc, nc - c0);
+  const double *Ab = A + (int64_t)b * a_stride;
+  double *C = (Cp ? Cp[b] : Cbase + (int64_t)b * c_stride) + (int64_t)c0 * ldc;
+  for (int k = K - 1; k >= 0; --k) {
+    const double t = tau[(int64_t)b * tau_stride + k];
+    if (t == 0.0) continue;
+    const double *v = Ab + (int64_t)k * m;
+    double w[kc];
+#pragma unroll
+    for (int j = 0; j < kc; ++j) w[j] = 0.0;
+    for (int i = k + lane; i < m; i += 64) {
+      const double vi = i == k ? 1.0 : v[i];
+#pragma unroll
+      for (int j = 0; j < kc; ++j)
+        if (j < cn) w[j] = fma(vi, C[(int64_t)j * ldc + i], w[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kc; ++j) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) w[j] += __shfl_xor(w[j], o);
+      w[j] *= -t;
+    }
+    for (int i = k + lane; i < m; i += 64) {
+      const double vi = i == k ? 1.0 : v[i];
+#pragma unroll
+      for (int j = 0; j < kc; ++j)
+        if (j < cn) C[(int64_t)j * ldc + i] = fma(w[j], vi, C[(int64_t)j * ldc + i]);
+    }
+  }
+}
+
 // T = R1^T (n x n, column-major, lower triangular) from the upper triangle
 // of the first QR (m x n, column-major, ld m).
 __global__ void k_jac_transpose(const double *A, int64_t a_stride, int32_t m, int32_t n, double *T,
@@ -577,7 +628,7 @@ int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
 // sigma (descending), ranks[q] the kept count (sigma > trunc sigma_1).
 int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, int n, int nb,
                      double *const *U, double *const *Vs, double *const *Ss, double trunc, int *ranks,
-                     int *sweeps_out, hipStream_t s) {
+                     int *sweeps_out, hipStream_t s, bool always_batched_q) {
   char *o = scratch;
   char *work = o; o += p.work;
   double *A = (double *)o; o += p.a;
@@ -743,14 +794,26 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   SMFS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_jac_finalize_j, dim3((unsigned)n, nb), dim3(256), 0, s, f, X);
   SMFS_HIP(hipGetLastError());
-  // U = Q1 [U_X; 0] and V = Q2 J with the reflectors of the two QRs
-  for (int q = 0; q < nb; ++q) {
-    if (rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, m, rh[q], n, A + (size_t)q * m * n, m,
-                         tau + (size_t)q * n, U[q], m) != rocblas_status_success ||
-        rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, n, rh[q], n, T + (size_t)q * ts, n,
-                         tau2 + (size_t)q * n, X + (size_t)q * xs, n) != rocblas_status_success) {
-      set_error("device SVD: ormqr failed");
-      return SMFS_E_SVD;
+  // U = Q1 [U_X; 0] and V = Q2 J with the reflectors of the two QRs: one
+  // launch for the whole batch when it gives at least 1024 waves, else one
+  // rocSOLVER ormqr per block (its blocked form keeps a few large blocks busy)
+  const int rmax = *std::max_element(rh.begin(), rh.end());
+  const dim3 gq((unsigned)((rmax + 7) / 8), (unsigned)nb);
+  if (always_batched_q || (int64_t)gq.x * gq.y >= 1024) {
+    hipLaunchKernelGGL(k_qr_apply, gq, dim3(64), 0, s, A, (int64_t)m * n, m, n, tau, (int64_t)n, ptrs, nullptr,
+                       (int64_t)0, m, drank);
+    SMFS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_qr_apply, gq, dim3(64), 0, s, T, ts, n, n, tau2, (int64_t)n, nullptr, X, xs, n, drank);
+    SMFS_HIP(hipGetLastError());
+  } else {
+    for (int q = 0; q < nb; ++q) {
+      if (rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, m, rh[q], n, A + (size_t)q * m * n, m,
+                           tau + (size_t)q * n, U[q], m) != rocblas_status_success ||
+          rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, n, rh[q], n, T + (size_t)q * ts, n,
+                           tau2 + (size_t)q * n, X + (size_t)q * xs, n) != rocblas_status_success) {
+        set_error("device SVD: ormqr failed");
+        return SMFS_E_SVD;
+      }
     }
   }
   hipLaunchKernelGGL(k_jac_store_v, dim3((unsigned)n, nb), dim3(256), 0, s, f, X);
