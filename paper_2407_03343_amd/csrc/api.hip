@@ -1122,7 +1122,12 @@ std::vector<ShapeGroup> shape_groups(const Problem &pb) {
     out.back().fids.push_back(f);
   }
   for (ShapeGroup &g : out) {
-    g.nb = (int)std::min<size_t>(kSvdBatchMax, g.fids.size());
+    // the Jacobi sweeps launch once per round whatever the batch: batches of
+    // small blocks up to 256 blocks or 2 GiB of blocks
+    int cap = kSvdBatchMax;
+    if (pb.prm.svd_method == SMFS_SVD_JACOBI)
+      cap = (int)std::max<int64_t>(kSvdBatchMax, std::min<int64_t>(256, ((int64_t)2 << 30) / (8 * (int64_t)g.m * g.n)));
+    g.nb = (int)std::min<size_t>((size_t)cap, g.fids.size());
     g.stride = g.fids.size() > 1 ? pb.factors[g.fids[1]].u_off - pb.factors[g.fids[0]].u_off : 0;
   }
   return out;
