@@ -676,7 +676,7 @@ def serving(args, torch, smfs, reqs, arrivals):
     prec = smfs.SMFS_MIXED_FAR if args.serve_precision == "mixed_far" else smfs.SMFS_FP64
     srv = smfs.Server(arena_bytes=args.serve_arena << 30, max_active=args.serve_slots,
                       setup_workers=args.serve_workers, server_precision=prec,
-                      iters_per_step=args.serve_iters, **disc, **solver)
+                      iters_per_step=args.serve_iters, setup_batch=args.serve_setup_batch, **disc, **solver)
     t0 = srv.clock() + 0.02
     ids, i, last_log = [], 0, time.perf_counter()
     while True:
@@ -705,7 +705,7 @@ def serving(args, torch, smfs, reqs, arrivals):
     its = np.array([r["iterations"] for r in res])
     out = {
         "requests": n, "rate_per_s": args.serve_rate, "setup_workers": args.serve_workers,
-        "precision": args.serve_precision, "svd": args.serve_svd,
+        "precision": args.serve_precision, "svd": args.serve_svd, "setup_batch": args.serve_setup_batch,
         "pair_evals_f32": int(sum(r["pair_evals_f32"] for r in res)),
         "refinements_max": int(max(r["refinements"] for r in res)),
         "stagnated": int(sum(1 for r in res if r["status"] == 3)),
@@ -854,6 +854,8 @@ def main():
                     help="requests solved one after another for the comparison")
     ap.add_argument("--serve-svd", choices=["rocsolver", "jacobi"], default="jacobi",
                     help="SVD of the served requests' self blocks at set-up")
+    ap.add_argument("--serve-setup-batch", type=int, default=4,
+                    help="most requests a set-up worker factorises together (smaller: resident sooner)")
     ap.add_argument("--serve-iters", type=int, default=8,
                     help="GMRES iterations per server step (no host round trip between them)")
     ap.add_argument("--serve-only", action="store_true",

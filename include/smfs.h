@@ -447,10 +447,12 @@ typedef struct smfs_server_config {
                                    batched SVD inputs and outputs (0: 4 GiB) */
   int32_t iters_per_step;       /* GMRES iterations of the resident requests per
                                    smfs_server_step, 1..1024 (0: 8) */
+  int32_t setup_batch;          /* most requests a worker sets up together, 1..64 (0: 64):
+                                   smaller batches become resident sooner */
 } smfs_server_config;
 
 /* Defaults: radius 1, 64 slots, 1 worker, no queue limit, FP64, 4 GiB, 8
- * iterations per step. */
+ * iterations per step, set-up batches of up to 64 requests. */
 int smfs_server_config_default(smfs_server_config *c);
 
 /* Bytes of the fixed part of the server's device memory for these
@@ -463,7 +465,7 @@ int smfs_server_memory_bytes(const smfs_params *p, const smfs_server_config *c, 
  * device memory, 256-byte aligned, owned by the caller and used by the
  * server until smfs_server_destroy; the part beyond
  * smfs_server_memory_bytes is the arena.  A worker takes every request that
- * can be admitted at that moment (up to 64) and factorises the self blocks
+ * can be admitted at that moment (up to setup_batch) and factorises the self blocks
  * of all their contact spheres together: batched SVDs per block shape, each
  * call of a fixed batch count for its shape (set by the shape and the
  * worker's scratch alone, so that a request's factors do not depend on its

@@ -638,6 +638,7 @@ int smfs_server_config_default(smfs_server_config *c) {
   c->precision = SMFS_FP64;
   c->worker_scratch_bytes = kSvdScratch;
   c->iters_per_step = 8;
+  c->setup_batch = 64;
   return SMFS_OK;
 }
 
@@ -658,7 +659,8 @@ struct ServerLayout {
 
 int server_layout(const smfs_params *p, const smfs_server_config *c, ServerLayout &L) {
   if (!p || !c || !(c->radius > 0) || c->max_active < 1 || c->max_active > 4096 || c->setup_workers < 1 ||
-      c->setup_workers > 64 || c->max_queued < 0 || c->iters_per_step < 0 || c->iters_per_step > 1024) {
+      c->setup_workers > 64 || c->max_queued < 0 || c->iters_per_step < 0 || c->iters_per_step > 1024 ||
+      c->setup_batch < 0 || c->setup_batch > 64) {
     set_error("smfs_server: bad configuration");
     return SMFS_E_INVALID_ARG;
   }
@@ -806,6 +808,7 @@ int smfs_server_create(const smfs_params *p, const smfs_server_config *c, void *
   srv->d_gst = (double *)(base + L.gst);
   srv->gstride = L.gstride;
   srv->iters_per_step = c->iters_per_step > 0 ? c->iters_per_step : 8;
+  srv->max_batch = c->setup_batch > 0 ? c->setup_batch : 64;
   SMFS_HIP(hipHostMalloc((void **)&srv->h_gv, sizeof(ServeGivens) * c->max_active, hipHostMallocDefault));
   SMFS_HIP(hipHostMalloc((void **)&srv->h_gst, sizeof(double) * srv->gstride * c->max_active,
                          hipHostMallocDefault));

@@ -108,7 +108,7 @@ class smfs_server_config(C.Structure):
     _fields_ = [
         ("radius", C.c_double), ("max_active", C.c_int32), ("setup_workers", C.c_int32),
         ("max_queued", C.c_int32), ("precision", C.c_int32), ("worker_scratch_bytes", C.c_size_t),
-        ("iters_per_step", C.c_int32),
+        ("iters_per_step", C.c_int32), ("setup_batch", C.c_int32),
     ]
 
 
@@ -518,7 +518,8 @@ class Server:
     (keyword overrides of smfs_params) and the sphere radius."""
 
     def __init__(self, radius=1.0, arena_bytes=8 << 30, max_active=64, setup_workers=1, max_queued=0,
-                 server_precision=SMFS_FP64, worker_scratch_bytes=0, iters_per_step=0, **over):
+                 server_precision=SMFS_FP64, worker_scratch_bytes=0, iters_per_step=0, setup_batch=0,
+                 **over):
         """The server's device memory (its fixed part plus an arena of
         arena_bytes) is one torch allocation held by this object."""
         import torch
@@ -534,6 +535,8 @@ class Server:
             cfg.worker_scratch_bytes = worker_scratch_bytes
         if iters_per_step:
             cfg.iters_per_step = iters_per_step
+        if setup_batch:
+            cfg.setup_batch = setup_batch
         self.config = cfg
         fixed = C.c_size_t(0)
         _check(lib().smfs_server_memory_bytes(C.byref(self.params), C.byref(cfg), C.byref(fixed)),

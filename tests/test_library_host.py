@@ -137,7 +137,7 @@ def test_server_memory_query():
     cfg = smfs.smfs_server_config()
     assert smfs.lib().smfs_server_config_default(C.byref(cfg)) == 0
     assert cfg.max_active == 64 and cfg.setup_workers == 1 and cfg.worker_scratch_bytes == 4 << 30
-    assert cfg.iters_per_step == 8
+    assert cfg.iters_per_step == 8 and cfg.setup_batch == 64
     n = C.c_size_t(0)
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == 0
     one = n.value
@@ -152,6 +152,9 @@ def test_server_memory_query():
     cfg.iters_per_step = 2000
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -1
     cfg.iters_per_step = 8
+    cfg.setup_batch = 65
+    assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -1
+    cfg.setup_batch = 0
     cfg.max_active = 0
     assert smfs.lib().smfs_server_memory_bytes(C.byref(p), C.byref(cfg), C.byref(n)) == -1
 
