@@ -439,6 +439,95 @@ __global__ __launch_bounds__(64) void k_qr_apply(const double *A, int64_t a_stri
   }
 }
 
+// k_qr_apply with the wave's columns of C held in registers for the whole
+// sweep over the reflectors (blocks of at most 64 kR rows): lane l holds
+// rows l, l + 64, ... of kC columns.  Only the reflectors are read per step.
+template <int kR, int kC>
+__global__ __launch_bounds__(64) void k_qr_apply_reg(const double *A, int64_t a_stride, int32_t m, int32_t K,
+                                                     const double *tau, int64_t tau_stride, double *const *Cp,
+                                                     double *Cbase, int64_t c_stride, int32_t ldc,
+                                                     const int32_t *ncols) {
+  const int b = blockIdx.y, lane = threadIdx.x;
+  const int c0 = blockIdx.x * kC;
+  const int nc = ncols[b];
+  if (c0 >= nc) return;
+  const int cn = min(kC, nc - c0);
+  const double *Ab = A + (int64_t)b * a_stride;
+  double *C = (Cp ? Cp[b] : Cbase + (int64_t)b * c_stride) + (int64_t)c0 * ldc;
+  double c[kR][kC];
+#pragma unroll
+  for (int t = 0; t < kR; ++t) {
+    const int i = lane + 64 * t;
+#pragma unroll
+    for (int j = 0; j < kC; ++j) c[t][j] = (i < m && j < cn) ? C[(int64_t)j * ldc + i] : 0.0;
+  }
+  for (int k = K - 1; k >= 0; --k) {
+    const double tk = tau[(int64_t)b * tau_stride + k];
+    if (tk == 0.0) continue;
+    const double *v = Ab + (int64_t)k * m;
+    double vv[kR], w[kC];
+#pragma unroll
+    for (int j = 0; j < kC; ++j) w[j] = 0.0;
+#pragma unroll
+    for (int t = 0; t < kR; ++t) {
+      const int i = lane + 64 * t;
+      vv[t] = i == k ? 1.0 : (i > k && i < m ? v[i] : 0.0);
+#pragma unroll
+      for (int j = 0; j < kC; ++j) w[j] = fma(vv[t], c[t][j], w[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kC; ++j) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) w[j] += __shfl_xor(w[j], o);
+      w[j] *= -tk;
+    }
+#pragma unroll
+    for (int t = 0; t < kR; ++t) {
+#pragma unroll
+      for (int j = 0; j < kC; ++j) c[t][j] = fma(w[j], vv[t], c[t][j]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kR; ++t) {
+    const int i = lane + 64 * t;
+    if (i < m) {
+#pragma unroll
+      for (int j = 0; j < kC; ++j)
+        if (j < cn) C[(int64_t)j * ldc + i] = c[t][j];
+    }
+  }
+}
+
+// C <- Q C for every block of a batch (see k_qr_apply), with the register
+// form when a block has at most 4608 rows.
+hipError_t launch_qr_apply(const double *A, int64_t a_stride, int32_t m, int32_t K, const double *tau,
+                           int64_t tau_stride, double *const *Cp, double *Cbase, int64_t c_stride, int32_t ldc,
+                           const int32_t *ncols, int32_t max_cols, int32_t nb, hipStream_t s) {
+  auto grid = [&](int kc) { return dim3((unsigned)((max_cols + kc - 1) / kc), (unsigned)nb); };
+  if (m <= 512)
+    hipLaunchKernelGGL((k_qr_apply_reg<8, 8>), grid(8), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
+                       Cbase, c_stride, ldc, ncols);
+  else if (m <= 1024)
+    hipLaunchKernelGGL((k_qr_apply_reg<16, 4>), grid(4), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
+                       Cbase, c_stride, ldc, ncols);
+  else if (m <= 1536)
+    hipLaunchKernelGGL((k_qr_apply_reg<24, 2>), grid(2), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
+                       Cbase, c_stride, ldc, ncols);
+  else if (m <= 2048)
+    hipLaunchKernelGGL((k_qr_apply_reg<32, 2>), grid(2), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
+                       Cbase, c_stride, ldc, ncols);
+  else if (m <= 3072)
+    hipLaunchKernelGGL((k_qr_apply_reg<48, 1>), grid(1), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
+                       Cbase, c_stride, ldc, ncols);
+  else if (m <= 4608)
+    hipLaunchKernelGGL((k_qr_apply_reg<72, 1>), grid(1), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
+                       Cbase, c_stride, ldc, ncols);
+  else
+    hipLaunchKernelGGL(k_qr_apply, grid(8), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp, Cbase,
+                       c_stride, ldc, ncols);
+  return hipGetLastError();
+}
+
 // T = R1^T (n x n, column-major, lower triangular) from the upper triangle
 // of the first QR (m x n, column-major, ld m).
 __global__ void k_jac_transpose(const double *A, int64_t a_stride, int32_t m, int32_t n, double *T,
@@ -795,26 +884,31 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   hipLaunchKernelGGL(k_jac_finalize_j, dim3((unsigned)n, nb), dim3(256), 0, s, f, X);
   SMFS_HIP(hipGetLastError());
   // U = Q1 [U_X; 0] and V = Q2 J with the reflectors of the two QRs: one
-  // launch for the whole batch when it gives at least 1024 waves, else one
-  // rocSOLVER ormqr per block (its blocked form keeps a few large blocks busy)
+  // launch for the whole batch when the columns fit in registers (at most
+  // 4608 rows), or in serving, or when the batch gives at least 1024 waves;
+  // else one rocSOLVER ormqr per block (its blocked form keeps a few blocks
+  // of many rows busy)
   const int rmax = *std::max_element(rh.begin(), rh.end());
-  const dim3 gq((unsigned)((rmax + 7) / 8), (unsigned)nb);
-  if (always_batched_q || (int64_t)gq.x * gq.y >= 1024) {
-    hipLaunchKernelGGL(k_qr_apply, gq, dim3(64), 0, s, A, (int64_t)m * n, m, n, tau, (int64_t)n, ptrs, nullptr,
-                       (int64_t)0, m, drank);
-    SMFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_qr_apply, gq, dim3(64), 0, s, T, ts, n, n, tau2, (int64_t)n, nullptr, X, xs, n, drank);
-    SMFS_HIP(hipGetLastError());
+  const bool big = always_batched_q || (int64_t)((rmax + 7) / 8) * nb >= 1024;
+  if (m <= 4608 || big) {
+    SMFS_HIP(launch_qr_apply(A, (int64_t)m * n, m, n, tau, (int64_t)n, ptrs, nullptr, 0, m, drank, rmax, nb, s));
   } else {
-    for (int q = 0; q < nb; ++q) {
+    for (int q = 0; q < nb; ++q)
       if (rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, m, rh[q], n, A + (size_t)q * m * n, m,
-                           tau + (size_t)q * n, U[q], m) != rocblas_status_success ||
-          rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, n, rh[q], n, T + (size_t)q * ts, n,
+                           tau + (size_t)q * n, U[q], m) != rocblas_status_success) {
+        set_error("device SVD: ormqr failed");
+        return SMFS_E_SVD;
+      }
+  }
+  if (n <= 4608 || big) {
+    SMFS_HIP(launch_qr_apply(T, ts, n, n, tau2, (int64_t)n, nullptr, X, xs, n, drank, rmax, nb, s));
+  } else {
+    for (int q = 0; q < nb; ++q)
+      if (rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, n, rh[q], n, T + (size_t)q * ts, n,
                            tau2 + (size_t)q * n, X + (size_t)q * xs, n) != rocblas_status_success) {
         set_error("device SVD: ormqr failed");
         return SMFS_E_SVD;
       }
-    }
   }
   hipLaunchKernelGGL(k_jac_store_v, dim3((unsigned)n, nb), dim3(256), 0, s, f, X);
   SMFS_HIP(hipGetLastError());
