@@ -73,7 +73,7 @@ struct JacArgs {
   double *off;          // per block and pair task: largest cosine / tolerance seen before rotation
   const double *fro;    // per block: Frobenius norm of R
   const int32_t *skip;  // per block: 1 once its sweeps have converged (its tasks leave it as it is)
-  double *V;            // k_jac_pairs_wave: V (npad x npad, row-major per block), updated in the task
+  double *V;            // k_jac_pairs_wave: V (npad x npad, column-major per block), updated in the task
   int64_t v_stride;
 };
 
@@ -339,22 +339,22 @@ __global__ __launch_bounds__(64) void k_jac_pairs_wave(JacArgs a) {
   double W[kW2 * kW2];
 #pragma unroll
   for (int e = 0; e < kW2 * kW2; ++e) W[e] = Ws[e];
+  // V is column-major here: the lanes read consecutive rows of a column
   double *Vb = a.V + (int64_t)b * a.v_stride;
+  double *vc[kW2];
+#pragma unroll
+  for (int c = 0; c < kW2; ++c)
+    vc[c] = Vb + (c < w ? (int64_t)pr.x * w + c : (int64_t)pr.y * w + (c - w)) * a.npad;
   for (int r = lane; r < a.npad; r += 64) {
-    double *row = Vb + (int64_t)r * a.npad;
     double v[kW2];
 #pragma unroll
-    for (int c = 0; c < w; ++c) {
-      v[c] = row[(int64_t)pr.x * w + c];
-      v[w + c] = row[(int64_t)pr.y * w + c];
-    }
+    for (int c = 0; c < kW2; ++c) v[c] = vc[c][r];
 #pragma unroll
     for (int c = 0; c < kW2; ++c) {
       double t = 0.0;
 #pragma unroll
       for (int k = 0; k < kW2; ++k) t = fma(v[k], W[c * kW2 + k], t);
-      if (c < w) row[(int64_t)pr.x * w + c] = t;
-      else row[(int64_t)pr.y * w + (c - w)] = t;
+      vc[c][r] = t;
     }
   }
   if (lane == 0) *offo = offmax;
@@ -595,6 +595,7 @@ struct FinalArgs {
   const int32_t *perm;     // per block: n source columns in descending order of norm
   const int32_t *rank;     // per block
   int32_t m, n, npad;
+  int32_t v_colmajor;      // V column-major (the one-wave pair tasks) rather than row-major
   double *const *U;        // per block: slot U (m x n, column-major), V (n x n row-major), sigma
   double *const *Vs;
   double *const *Ss;
@@ -623,7 +624,8 @@ __global__ __launch_bounds__(256) void k_jac_finalize_j(FinalArgs f, double *Jp)
   const int j = f.perm[(int64_t)b * f.n + c];
   const double *vb = f.V + (int64_t)b * f.v_stride;
   double *jc = Jp + (int64_t)b * f.x_stride + (int64_t)c * f.n;
-  for (int r = threadIdx.x; r < f.n; r += blockDim.x) jc[r] = vb[(int64_t)r * f.npad + j];
+  for (int r = threadIdx.x; r < f.n; r += blockDim.x)
+    jc[r] = f.v_colmajor ? vb[(int64_t)j * f.npad + r] : vb[(int64_t)r * f.npad + j];
 }
 
 // Slot V (n x n row-major, rank columns) from Q2 Jp (n x rank, column-major).
@@ -876,6 +878,7 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   f.m = m;
   f.n = n;
   f.npad = p.npad;
+  f.v_colmajor = p.wave ? 1 : 0;
   f.U = ptrs;
   f.Vs = ptrs + nb;
   f.Ss = ptrs + 2 * nb;
