@@ -294,7 +294,7 @@ __device__ __forceinline__ void jacw_rounds(double (&x)[kRows][kW2], double (&wr
 }
 
 template <int kRows, int kW2>
-__global__ __launch_bounds__(64) void k_jac_pairs_wave(JacArgs a) {
+__device__ __forceinline__ void jac_pair_wave(const JacArgs &a) {
   const int lane = threadIdx.x;
   const int task = blockIdx.x, b = blockIdx.y;
   const int2 pr = a.pairs[task];
@@ -358,6 +358,17 @@ __global__ __launch_bounds__(64) void k_jac_pairs_wave(JacArgs a) {
     }
   }
   if (lane == 0) *offo = offmax;
+}
+
+// Blocks of at most 512 rows: two waves per SIMD (the register budget of
+// 256 still holds the task); 768 rows need more registers than that.
+template <int kRows, int kW2>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_jac_pairs_wave(JacArgs a) {
+  jac_pair_wave<kRows, kW2>(a);
+}
+template <int kRows, int kW2>
+__global__ __launch_bounds__(64) void k_jac_pairs_wave_wide(JacArgs a) {
+  jac_pair_wave<kRows, kW2>(a);
 }
 
 // V (npad x npad, row-major per block) <- V[:, I u J] W for every pair task
@@ -800,7 +811,7 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
       const dim3 g((unsigned)p.npairs, (unsigned)nb);
       if (p.wave && p.rows == 4) hipLaunchKernelGGL((k_jac_pairs_wave<4, 8>), g, dim3(64), 0, s, ja);
       else if (p.wave && p.rows == 8) hipLaunchKernelGGL((k_jac_pairs_wave<8, 8>), g, dim3(64), 0, s, ja);
-      else if (p.wave) hipLaunchKernelGGL((k_jac_pairs_wave<12, 8>), g, dim3(64), 0, s, ja);
+      else if (p.wave) hipLaunchKernelGGL((k_jac_pairs_wave_wide<12, 8>), g, dim3(64), 0, s, ja);
       else if (p.w == 8) hipLaunchKernelGGL((k_jac_pairs<4, 16>), g, dim3(kJacThreads), 0, s, ja);
       else hipLaunchKernelGGL((k_jac_pairs<8, 8>), g, dim3(kJacThreads), 0, s, ja);
       SMFS_HIP(hipGetLastError());
