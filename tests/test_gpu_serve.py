@@ -257,3 +257,22 @@ def test_serving_jacobi_set_up(dev, oracle_pairsum_built, stream):
     d = np.abs(res[k]["ft"] - ref).max() / np.abs(ref).max()
     _say(f"  request {k} (P={r['P']}): served (Jacobi set-up) vs oracle {d:.2e}")
     assert d < 1e-5
+
+
+def test_serving_iterations_per_step_do_not_change_results(dev, mixed_run, stream):
+    """The GMRES cycle state lives on the device and the Givens step runs
+    there, so one iteration per server step and eight give the same
+    iterations and forces (to 1e-12; bitwise in practice) in fewer steps."""
+    res8, st8 = mixed_run
+    srv = dev.Server(arena_bytes=2 << 30, max_active=8, iters_per_step=1, **DISC, **SOLVER)
+    ids = [srv.submit(r["centers"], r["rbm"]) for r in stream]
+    srv.drain(timeout_s=120)
+    res1 = [srv.poll(i, r["P"]) for i, r in zip(ids, stream)]
+    st1 = srv.stats()
+    srv.close()
+    _say(f"  steps: {st1['steps']} at one iteration per step, {st8['steps']} at eight")
+    assert st1["iterations"] == st1["steps"] and st8["iterations"] == 8 * st8["steps"]
+    assert st8["steps"] < st1["steps"]
+    for a, b in zip(res1, res8):
+        assert a["iterations"] == b["iterations"] and a["status"] == b["status"]
+        assert np.abs(a["ft"] - b["ft"]).max() <= 1e-12 * np.abs(b["ft"]).max()
