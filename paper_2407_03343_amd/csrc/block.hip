@@ -156,8 +156,8 @@ int apply_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *m
     // contact-free proxies into one more FP64 slice, every other
     // contact-free sphere through its equivalent sources
     EqArgs f;
-    f.tiles = pb.d_stiles;
-    f.n_tiles = pb.n_stiles;
+    f.tiles = pb.d_tiles;
+    f.n_tiles = pb.n_tiles;
     f.tsph = pb.d_tsph;
     f.tgt = pb.d_tgt;
     f.eqpt32 = pb.d_eqpt32;

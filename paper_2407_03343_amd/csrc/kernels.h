@@ -61,9 +61,9 @@ Far32Args far32_args(Problem &pb);
 // equivalent Stokeslets of every contact-free sphere that is neither the
 // tile's own sphere nor in its near list.
 struct EqArgs {
-  const int4 *tiles;        // k_far_eq_f32: tiles of consecutive targets; block form: one-sphere tiles
+  const int4 *tiles;        // tiles of consecutive targets (may span spheres)
   int64_t n_tiles;
-  const int32_t *tsph;      // sphere of each target (k_far_eq_f32)
+  const int32_t *tsph;      // sphere of each target
   const double *tgt;        // targets, T x 3
   const float *eqpt32;      // equivalent points relative to a centre, n_eq x 3
   const float *q32;         // equivalent strengths, free index major: n_free x n_eq x 3

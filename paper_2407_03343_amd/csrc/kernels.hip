@@ -502,53 +502,30 @@ __global__ __launch_bounds__(256) void k_eq_strengths(const double *__restrict__
     if (qb + u < n_free) q32[(int64_t)(qb + u) * rows + r] = (float)acc[u];
 }
 
-// far_pair for the slots with on[p] set only: a masked slot's new sum is
-// discarded by a select, so it stays unchanged bitwise.
-template <int kTpl>
-__device__ __forceinline__ void far_pair_masked(float sx, float sy, float sz, float fx, float fy, float fz,
-                                                const float (&ux)[kTpl], const float (&uy)[kTpl],
-                                                const float (&uz)[kTpl], float (&ax)[kTpl],
-                                                float (&ay)[kTpl], float (&az)[kTpl], const bool (&on)[kTpl]) {
-#pragma unroll
-  for (int p = 0; p < kTpl; ++p) {
-    const float rx = ux[p] - sx, ry = uy[p] - sy, rz = uz[p] - sz;
-    const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-    const float ri = __builtin_amdgcn_rsqf(r2);
-    const float rf = fmaf(rx, fx, fmaf(ry, fy, rz * fz));
-    const float t = rf * (ri * ri);
-    const float bx = fmaf(fmaf(rx, t, fx), ri, ax[p]);
-    const float by = fmaf(fmaf(ry, t, fy), ri, ay[p]);
-    const float bz = fmaf(fmaf(rz, t, fz), ri, az[p]);
-    ax[p] = on[p] ? bx : ax[p];
-    ay[p] = on[p] ? by : ay[p];
-    az[p] = on[p] ? bz : az[p];
-  }
-}
+// A slot that a source sphere must not reach is moved to kOffSlot: its
+// squared distance to every equivalent point overflows to +inf, rsq gives
+// +0 and the pair adds exactly 0 (the projection r.f stays finite for any
+// strength below 1e18), so every slot runs the same loop.
+constexpr float kOffSlot = 1e20f;
 
 // The n_eq equivalent sources of one sphere (points pts relative to its
 // centre, strengths str) at the slots' targets ux (relative to the same
 // centre); two sources per step.
-template <int kTpl, bool kMasked>
+template <int kTpl>
 __device__ __forceinline__ void eq_sphere(ConstPtr32 pts, ConstPtr32 str, int ne, const float (&ux)[kTpl],
                                           const float (&uy)[kTpl], const float (&uz)[kTpl], float (&ax)[kTpl],
-                                          float (&ay)[kTpl], float (&az)[kTpl], const bool (&on)[kTpl]) {
+                                          float (&ay)[kTpl], float (&az)[kTpl]) {
   int j = 0;
   for (; j + 1 < ne; j += 2) {
     const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
     const float s0x = ps[0], s0y = ps[1], s0z = ps[2], s1x = ps[3], s1y = ps[4], s1z = ps[5];
     const float f0x = pf[0], f0y = pf[1], f0z = pf[2], f1x = pf[3], f1y = pf[4], f1z = pf[5];
-    if (kMasked) {
-      far_pair_masked<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az, on);
-      far_pair_masked<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az, on);
-    } else {
-      far_pair<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az);
-      far_pair<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az);
-    }
+    far_pair<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az);
+    far_pair<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az);
   }
   if (j < ne) {
     const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
-    if (kMasked) far_pair_masked<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az, on);
-    else far_pair<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az);
+    far_pair<kTpl>(ps[0], ps[1], ps[2], pf[0], pf[1], pf[2], ux, uy, uz, ax, ay, az);
   }
 }
 
@@ -557,9 +534,10 @@ __device__ __forceinline__ void eq_sphere(ConstPtr32 pts, ConstPtr32 str, int ne
 // to 64 kTpl consecutive targets, which may belong to consecutive spheres,
 // so that every wave has a full tile whatever a sphere's node count.  Each
 // slot skips its own sphere and the near list of its sphere, walking that
-// ascending list beside the sphere loop; a source sphere that only some
-// slots skip is summed in a masked pass.  A slot's coordinates relative to
-// a source sphere's centre are formed in FP64 and rounded once.
+// ascending list beside the sphere loop; a slot that skips a source sphere
+// summed for others is moved out of its reach (kOffSlot).  A slot's
+// coordinates relative to a source sphere's centre are formed in FP64 and
+// rounded once.
 template <int kTpl>
 __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int split) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -593,7 +571,7 @@ __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int s
   for (int q = q0; q < q1; ++q) {
     const int ks = uniform(A.free_ids[q]);
     bool on[kTpl];
-    bool all_on = true, any_on = false;
+    bool any_on = false;
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
       const bool near = q == next[p];
@@ -602,7 +580,6 @@ __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int s
         next[p] = e[p] < A.near_off[own[p] + 1] ? A.near_idx[e[p]] : 0x7fffffff;
       }
       on[p] = !near && ks != own[p];
-      all_on = all_on && on[p];
       any_on = any_on || on[p];
     }
     if (!__any(any_on)) continue;
@@ -610,13 +587,12 @@ __device__ __forceinline__ void far_eq_wave(const EqArgs &A, int64_t tile, int s
     float ux[kTpl], uy[kTpl], uz[kTpl];
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
-      ux[p] = (float)(tx[p] - sx);
-      uy[p] = (float)(ty[p] - sy);
-      uz[p] = (float)(tz[p] - sz);
+      ux[p] = on[p] ? (float)(tx[p] - sx) : kOffSlot;
+      uy[p] = on[p] ? (float)(ty[p] - sy) : kOffSlot;
+      uz[p] = on[p] ? (float)(tz[p] - sz) : kOffSlot;
     }
     const ConstPtr32 str = (ConstPtr32)(A.q32 + (int64_t)q * 3 * ne);
-    if (__all(all_on)) eq_sphere<kTpl, false>(pts, str, ne, ux, uy, uz, ax, ay, az, on);
-    else eq_sphere<kTpl, true>(pts, str, ne, ux, uy, uz, ax, ay, az, on);
+    eq_sphere<kTpl>(pts, str, ne, ux, uy, uz, ax, ay, az);
   }
   float *out = A.part32 + (int64_t)split * A.T * 3;
 #pragma unroll
@@ -1847,10 +1823,43 @@ __global__ __launch_bounds__(256) void k_eq_strengths_block(const double *__rest
     if (v0 + v < nrhs) q32b[(((int64_t)q * ne + j) * nrhs + v0 + v) * 3 + c] = (float)acc[v];
 }
 
-// The FP32 equivalent-source sum for a run of kRun vectors (blockIdx.z),
-// one-sphere tiles, the contact-free spheres split over blockIdx.y, the
-// tile's own sphere and near list skipped and the coordinates formed as in
-// far_eq_wave.
+// The n_eq equivalent sources of one contact-free sphere for a run of kRun
+// vectors at the slots' targets ux (relative to its centre; kOffSlot for a
+// slot it must not reach); str points at the sphere's strengths
+// [j][nrhs][3], q0 the run's first vector.
+template <int kTpl, int kRun>
+__device__ __forceinline__ void eq_sphere_block(ConstPtr32 pts, ConstPtr32 str, int ne, int nrhs, int q0,
+                                                const float (&ux)[kTpl], const float (&uy)[kTpl],
+                                                const float (&uz)[kTpl], float (&a)[kTpl][kRun][3]) {
+  for (int j = 0; j < ne; ++j) {
+    const ConstPtr32 ps = pts + 3 * j, pf = str + ((int64_t)j * nrhs + q0) * 3;
+    const float sx = ps[0], sy = ps[1], sz = ps[2];
+    float f[kRun][3];
+#pragma unroll
+    for (int q = 0; q < kRun; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f[q][c] = pf[3 * q + c];
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      const float rx = ux[p] - sx, ry = uy[p] - sy, rz = uz[p] - sz;
+      const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+      const float ri = __builtin_amdgcn_rsqf(r2);
+      const float ri2 = ri * ri;
+#pragma unroll
+      for (int q = 0; q < kRun; ++q) {
+        const float t = fmaf(rx, f[q][0], fmaf(ry, f[q][1], rz * f[q][2])) * ri2;
+        a[p][q][0] = fmaf(fmaf(rx, t, f[q][0]), ri, a[p][q][0]);
+        a[p][q][1] = fmaf(fmaf(ry, t, f[q][1]), ri, a[p][q][1]);
+        a[p][q][2] = fmaf(fmaf(rz, t, f[q][2]), ri, a[p][q][2]);
+      }
+    }
+  }
+}
+
+// The FP32 equivalent-source sum for a run of kRun vectors (blockIdx.z) on
+// the packed target tiles, the contact-free spheres split over blockIdx.y:
+// each slot skips its own sphere and its sphere's near list, and the
+// coordinates are formed, as in far_eq_wave.
 template <int kTpl, int kRun>
 __global__ __launch_bounds__(kBlock) void k_far_eq_block_f32(EqArgs A, const float *__restrict__ q32b,
                                                              int32_t nrhs, float *__restrict__ part32b) {
@@ -1858,11 +1867,15 @@ __global__ __launch_bounds__(kBlock) void k_far_eq_block_f32(EqArgs A, const flo
   const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + uniform(threadIdx.x / kWave);
   if (tile >= A.n_tiles) return;
   const int4 tl = A.tiles[tile];
-  const int k = uniform(tl.x), t0 = uniform(tl.y), tc = uniform(tl.z);
+  const int t0 = uniform(tl.y), tc = uniform(tl.z);
+  if (tc <= 0) return;
   const int q0 = blockIdx.z * kRun;
   const int split = blockIdx.y;
+  const int f0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
+  const int f1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
   double tx[kTpl], ty[kTpl], tz[kTpl];  // targets, absolute
   float a[kTpl][kRun][3];
+  int own[kTpl], e[kTpl], next[kTpl];
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
     const int i = lane + kWave * p;
@@ -1872,54 +1885,40 @@ __global__ __launch_bounds__(kBlock) void k_far_eq_block_f32(EqArgs A, const flo
     tz[p] = A.tgt[3 * ti + 2];
 #pragma unroll
     for (int q = 0; q < kRun; ++q) a[p][q][0] = a[p][q][1] = a[p][q][2] = 0.f;
+    const int k = A.tsph[ti];
+    own[p] = k;
+    e[p] = A.near_off[k];
+    const int e1 = A.near_off[k + 1];
+    while (e[p] < e1 && A.near_idx[e[p]] < f0) ++e[p];
+    next[p] = e[p] < e1 ? A.near_idx[e[p]] : 0x7fffffff;
   }
-  const ConstPtr32 pts = (ConstPtr32)A.eqpt32, str = (ConstPtr32)q32b;
-  const int f0 = uniform((int)((int64_t)A.n_free * split / A.n_splits));
-  const int f1 = uniform((int)((int64_t)A.n_free * (split + 1) / A.n_splits));
-  int e = uniform(A.near_off[k]);
-  const int e1 = uniform(A.near_off[k + 1]);
-  while (e < e1 && uniform(A.near_idx[e]) < f0) ++e;
-  int next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
+  const ConstPtr32 pts = (ConstPtr32)A.eqpt32;
   const int ne = A.n_eq;
   for (int fq = f0; fq < f1; ++fq) {
-    if (fq == next) {
-      ++e;
-      next = e < e1 ? uniform(A.near_idx[e]) : 0x7fffffff;
-      continue;
-    }
     const int ks = uniform(A.free_ids[fq]);
-    if (ks == k) continue;
+    bool on[kTpl];
+    bool any_on = false;
+#pragma unroll
+    for (int p = 0; p < kTpl; ++p) {
+      const bool near = fq == next[p];
+      if (near) {
+        ++e[p];
+        next[p] = e[p] < A.near_off[own[p] + 1] ? A.near_idx[e[p]] : 0x7fffffff;
+      }
+      on[p] = !near && ks != own[p];
+      any_on = any_on || on[p];
+    }
+    if (!__any(any_on)) continue;
     const double sx = A.centers[3 * ks], sy = A.centers[3 * ks + 1], sz = A.centers[3 * ks + 2];
     float ux[kTpl], uy[kTpl], uz[kTpl];
 #pragma unroll
     for (int p = 0; p < kTpl; ++p) {
-      ux[p] = (float)(tx[p] - sx);
-      uy[p] = (float)(ty[p] - sy);
-      uz[p] = (float)(tz[p] - sz);
+      ux[p] = on[p] ? (float)(tx[p] - sx) : kOffSlot;
+      uy[p] = on[p] ? (float)(ty[p] - sy) : kOffSlot;
+      uz[p] = on[p] ? (float)(tz[p] - sz) : kOffSlot;
     }
-    for (int j = 0; j < ne; ++j) {
-      const ConstPtr32 ps = pts + 3 * j, pf = str + (((int64_t)fq * ne + j) * nrhs + q0) * 3;
-      const float sx = ps[0], sy = ps[1], sz = ps[2];
-      float f[kRun][3];
-#pragma unroll
-      for (int q = 0; q < kRun; ++q)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) f[q][c] = pf[3 * q + c];
-#pragma unroll
-      for (int p = 0; p < kTpl; ++p) {
-        const float rx = ux[p] - sx, ry = uy[p] - sy, rz = uz[p] - sz;
-        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float ri2 = ri * ri;
-#pragma unroll
-        for (int q = 0; q < kRun; ++q) {
-          const float t = fmaf(rx, f[q][0], fmaf(ry, f[q][1], rz * f[q][2])) * ri2;
-          a[p][q][0] = fmaf(fmaf(rx, t, f[q][0]), ri, a[p][q][0]);
-          a[p][q][1] = fmaf(fmaf(ry, t, f[q][1]), ri, a[p][q][1]);
-          a[p][q][2] = fmaf(fmaf(rz, t, f[q][2]), ri, a[p][q][2]);
-        }
-      }
-    }
+    const ConstPtr32 str = (ConstPtr32)(q32b + (int64_t)fq * ne * nrhs * 3);
+    eq_sphere_block<kTpl, kRun>(pts, str, ne, nrhs, q0, ux, uy, uz, a);
   }
 #pragma unroll
   for (int p = 0; p < kTpl; ++p) {
@@ -2200,8 +2199,9 @@ hipError_t launch_eq_block(const BlockDirectArgs &d, const EqArgs &f, const doub
     const unsigned nb = (unsigned)((d.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL((k_near_block_f64<kDirectTpl, kBlockRun>), dim3(nb, 1, nz), dim3(kBlock), 0, s, d,
                        f.free_ids, f.near_off, f.near_idx, near_out);
-    if (f.n_splits > 0)
-      hipLaunchKernelGGL((k_far_eq_block_f32<kDirectTpl, kBlockRun>), dim3(nb, (unsigned)f.n_splits, nz),
+    if (f.n_splits > 0 && f.n_tiles > 0)
+      hipLaunchKernelGGL((k_far_eq_block_f32<kDirectTpl, kBlockRun>),
+                         dim3((unsigned)((f.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)f.n_splits, nz),
                          dim3(kBlock), 0, s, f, q32b, d.nrhs, part32b);
   }
   return hipGetLastError();
