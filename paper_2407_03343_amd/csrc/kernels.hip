@@ -510,18 +510,36 @@ constexpr float kOffSlot = 1e20f;
 
 // The n_eq equivalent sources of one sphere (points pts relative to its
 // centre, strengths str) at the slots' targets ux (relative to the same
-// centre); two sources per step.
+// centre); two sources per step, the next step's points and strengths
+// loaded (wave-uniform, into scalar registers) while this step computes.
 template <int kTpl>
 __device__ __forceinline__ void eq_sphere(ConstPtr32 pts, ConstPtr32 str, int ne, const float (&ux)[kTpl],
                                           const float (&uy)[kTpl], const float (&uz)[kTpl], float (&ax)[kTpl],
                                           float (&ay)[kTpl], float (&az)[kTpl]) {
   int j = 0;
-  for (; j + 1 < ne; j += 2) {
-    const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
-    const float s0x = ps[0], s0y = ps[1], s0z = ps[2], s1x = ps[3], s1y = ps[4], s1z = ps[5];
-    const float f0x = pf[0], f0y = pf[1], f0z = pf[2], f1x = pf[3], f1y = pf[4], f1z = pf[5];
-    far_pair<kTpl>(s0x, s0y, s0z, f0x, f0y, f0z, ux, uy, uz, ax, ay, az);
-    far_pair<kTpl>(s1x, s1y, s1z, f1x, f1y, f1z, ux, uy, uz, ax, ay, az);
+  if (ne >= 2) {
+    float c[12];   // points of sources j, j + 1, then their strengths
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      c[u] = pts[u];
+      c[6 + u] = str[u];
+    }
+    for (; j + 3 < ne; j += 2) {
+      const ConstPtr32 ps = pts + 3 * (j + 2), pf = str + 3 * (j + 2);
+      float nx[12];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        nx[u] = ps[u];
+        nx[6 + u] = pf[u];
+      }
+      far_pair<kTpl>(c[0], c[1], c[2], c[6], c[7], c[8], ux, uy, uz, ax, ay, az);
+      far_pair<kTpl>(c[3], c[4], c[5], c[9], c[10], c[11], ux, uy, uz, ax, ay, az);
+#pragma unroll
+      for (int u = 0; u < 12; ++u) c[u] = nx[u];
+    }
+    far_pair<kTpl>(c[0], c[1], c[2], c[6], c[7], c[8], ux, uy, uz, ax, ay, az);
+    far_pair<kTpl>(c[3], c[4], c[5], c[9], c[10], c[11], ux, uy, uz, ax, ay, az);
+    j += 2;
   }
   if (j < ne) {
     const ConstPtr32 ps = pts + 3 * j, pf = str + 3 * j;
