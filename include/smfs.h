@@ -85,9 +85,11 @@ enum { SMFS_KIND_S = 1, SMFS_KIND_R = 2, SMFS_KIND_D = 4 };
 /* SVD of the self blocks at set-up: SMFS_SVD_JACOBI = Householder QR
  * B = Q1 R1, a second QR R1^T = Q2 R2 (a preconditioner), one-sided Jacobi
  * on R2^T in the library's kernels, then U = Q1 U_X and V = Q2 J; ranks
- * equal LAPACK's on the default blocks, and it is the faster method for
- * small batches (two spheres: 1.1 s against 3.2 s) but not for many large
- * blocks (106 blocks of about 4500 x 2000: 69 s against 41 s).
+ * equal LAPACK's on the default blocks.  It is the faster method for small
+ * batches (two spheres: 1.1 s against 3.2 s) and for blocks of at most 768
+ * columns (a 160-sphere request at 120 proxies: 2.1 s against 6-7 s), but
+ * not for many large blocks (106 blocks of about 4500 x 2000: 69 s against
+ * 41 s).  A block's factors do not depend on the other blocks of its batch.
  * SMFS_SVD_ROCSOLVER = rocSOLVER's bidiagonal gesvd. */
 enum { SMFS_SVD_JACOBI = 0, SMFS_SVD_ROCSOLVER = 1 };
 
