@@ -205,11 +205,9 @@ struct JacPlan {
 typedef struct _rocblas_handle *rocblas_handle;
 namespace smfs {
 int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p);
-// always_batched_q: apply the QR reflectors with the batched kernel whatever
-// the batch size (a block's factors then do not depend on its batch)
 int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, int n, int nb,
                      double *const *U, double *const *Vs, double *const *Ss, double trunc, int *ranks,
-                     int *sweeps_out, hipStream_t s, bool always_batched_q = false);
+                     int *sweeps_out, hipStream_t s);
 // block.hip
 size_t block_apply_bytes(const Problem &pb, int32_t nrhs);
 int block_apply_on(Problem &pb, int32_t nrhs, const double *mu, double *y, int64_t ld, char *base,

@@ -399,8 +399,8 @@ void factor_batch(Worker &wk, std::vector<Req *> &batch) {
 // rocSOLVER part and its scratch, which are contiguous, serve as one region
 // laid out by the Jacobi plan); U, V and sigma are written straight into
 // the requests' factor slots.  A block's sweeps stop when its own rotations
-// do, and the QR reflectors are always applied by the batched kernel, so
-// its factors do not depend on the other blocks of the call.
+// do, and the way its QR reflectors are applied depends on its shape only,
+// so its factors do not depend on the other blocks of the call.
 void factor_batch_jacobi(Worker &wk, std::vector<Req *> &batch) {
   struct Job {
     Req *r;
@@ -460,7 +460,7 @@ void factor_batch_jacobi(Worker &wk, std::vector<Req *> &batch) {
       std::vector<int> ranks(nb, 0);
       int sweeps = 0;
       if (!rc) rc = jacobi_svd_batch(wk.rb, jp, region, m, n, nb, U.data(), V.data(), S.data(),
-                                     jobs[j0].r->pb->prm.trunc_rel, ranks.data(), &sweeps, s, true);
+                                     jobs[j0].r->pb->prm.trunc_rel, ranks.data(), &sweeps, s);
       // the region's rocSOLVER part is the handle's workspace again
       if (rocblas_set_workspace(wk.rb, wk.work, wk.work_bytes) != rocblas_status_success && !rc) {
         set_error("rocblas_set_workspace failed");

@@ -3,8 +3,8 @@
 //   B = Q1 R1 and R1^T = Q2 R2 (rocSOLVER geqrf, batched);
 //   one-sided Jacobi (Hestenes) on X = R2^T in HIP: X J = U_X Sigma;
 //   U = Q1 [U_X; 0] and V = Q2 J (the reflectors of the two QRs applied by
-//   k_qr_apply to a whole batch, or by rocSOLVER ormqr per block when the
-//   batch is too small to fill the GPU), since
+//   k_qr_apply_reg to a whole batch, or by rocSOLVER ormqr per block for
+//   blocks of more than 4608 rows), since
 //   B = Q1 R2^T Q2^T = Q1 U_X Sigma J^T Q2^T.
 // The second QR is a preconditioner: R2^T is much closer to having
 // orthogonal columns than R1 (on a 4500 x 1980 contact block the Jacobi
@@ -407,52 +407,12 @@ __global__ __launch_bounds__(256) void k_jac_vupdate(double *V, int64_t v_stride
 // C <- Q C for the Householder QR of every block of a batch (the geqrf
 // layout: reflector k is column k of A below the diagonal with an implicit
 // 1 on it; Q = H_0 H_1 ... H_{K-1}, H_k = I - tau_k v_k v_k^T), the
-// reflectors applied last to first.  One wave per block (blockIdx.y) and 8
-// columns of C (blockIdx.x); block b's C has ncols[b] columns of leading
-// dimension ldc, at Cp[b] (or at Cbase + b c_stride when Cp is null).
-__global__ __launch_bounds__(64) void k_qr_apply(const double *A, int64_t a_stride, int32_t m, int32_t K,
-                                                 const double *tau, int64_t tau_stride, double *const *Cp,
-                                                 double *Cbase, int64_t c_stride, int32_t ldc,
-                                                 const int32_t *ncols) {
-  constexpr int kc = 8;
-  const int b = blockIdx.y, lane = threadIdx.x;
-  const int c0 = blockIdx.x * kc;
-  const int nc = ncols[b];
-  if (c0 >= nc) return;
-  const int cn = min(kc, nc - c0);
-  const double *Ab = A + (int64_t)b * a_stride;
-  double *C = (Cp ? Cp[b] : Cbase + (int64_t)b * c_stride) + (int64_t)c0 * ldc;
-  for (int k = K - 1; k >= 0; --k) {
-    const double t = tau[(int64_t)b * tau_stride + k];
-    if (t == 0.0) continue;
-    const double *v = Ab + (int64_t)k * m;
-    double w[kc];
-#pragma unroll
-    for (int j = 0; j < kc; ++j) w[j] = 0.0;
-    for (int i = k + lane; i < m; i += 64) {
-      const double vi = i == k ? 1.0 : v[i];
-#pragma unroll
-      for (int j = 0; j < kc; ++j)
-        if (j < cn) w[j] = fma(vi, C[(int64_t)j * ldc + i], w[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < kc; ++j) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) w[j] += __shfl_xor(w[j], o);
-      w[j] *= -t;
-    }
-    for (int i = k + lane; i < m; i += 64) {
-      const double vi = i == k ? 1.0 : v[i];
-#pragma unroll
-      for (int j = 0; j < kc; ++j)
-        if (j < cn) C[(int64_t)j * ldc + i] = fma(w[j], vi, C[(int64_t)j * ldc + i]);
-    }
-  }
-}
-
-// k_qr_apply with the wave's columns of C held in registers for the whole
-// sweep over the reflectors (blocks of at most 64 kR rows): lane l holds
-// rows l, l + 64, ... of kC columns.  Only the reflectors are read per step.
+// reflectors applied last to first.  One wave per block (blockIdx.y) and kC
+// columns of C (blockIdx.x), held in registers for the whole sweep over the
+// reflectors (blocks of at most 64 kR rows): lane l holds rows l, l + 64,
+// ... of the kC columns, and only the reflectors are read per step.  Block
+// b's C has ncols[b] columns of leading dimension ldc, at Cp[b] (or at
+// Cbase + b c_stride when Cp is null).
 template <int kR, int kC>
 __global__ __launch_bounds__(64) void k_qr_apply_reg(const double *A, int64_t a_stride, int32_t m, int32_t K,
                                                      const double *tau, int64_t tau_stride, double *const *Cp,
@@ -509,8 +469,8 @@ __global__ __launch_bounds__(64) void k_qr_apply_reg(const double *A, int64_t a_
   }
 }
 
-// C <- Q C for every block of a batch (see k_qr_apply), with the register
-// form when a block has at most 4608 rows.
+// C <- Q C for every block of a batch (k_qr_apply_reg), for blocks of at
+// most 4608 rows.
 hipError_t launch_qr_apply(const double *A, int64_t a_stride, int32_t m, int32_t K, const double *tau,
                            int64_t tau_stride, double *const *Cp, double *Cbase, int64_t c_stride, int32_t ldc,
                            const int32_t *ncols, int32_t max_cols, int32_t nb, hipStream_t s) {
@@ -530,12 +490,9 @@ hipError_t launch_qr_apply(const double *A, int64_t a_stride, int32_t m, int32_t
   else if (m <= 3072)
     hipLaunchKernelGGL((k_qr_apply_reg<48, 1>), grid(1), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
                        Cbase, c_stride, ldc, ncols);
-  else if (m <= 4608)
+  else
     hipLaunchKernelGGL((k_qr_apply_reg<72, 1>), grid(1), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp,
                        Cbase, c_stride, ldc, ncols);
-  else
-    hipLaunchKernelGGL(k_qr_apply, grid(8), dim3(64), 0, s, A, a_stride, m, K, tau, tau_stride, Cp, Cbase,
-                       c_stride, ldc, ncols);
   return hipGetLastError();
 }
 
@@ -730,7 +687,7 @@ int jacobi_plan(rocblas_handle h, int m, int n, int nb, JacPlan &p) {
 // sigma (descending), ranks[q] the kept count (sigma > trunc sigma_1).
 int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, int n, int nb,
                      double *const *U, double *const *Vs, double *const *Ss, double trunc, int *ranks,
-                     int *sweeps_out, hipStream_t s, bool always_batched_q) {
+                     int *sweeps_out, hipStream_t s) {
   char *o = scratch;
   char *work = o; o += p.work;
   double *A = (double *)o; o += p.a;
@@ -899,12 +856,10 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
   SMFS_HIP(hipGetLastError());
   // U = Q1 [U_X; 0] and V = Q2 J with the reflectors of the two QRs: one
   // launch for the whole batch when the columns fit in registers (at most
-  // 4608 rows), or in serving, or when the batch gives at least 1024 waves;
-  // else one rocSOLVER ormqr per block (its blocked form keeps a few blocks
-  // of many rows busy)
+  // 4608 rows), else one rocSOLVER ormqr per block.  The choice depends on
+  // the block's shape only, so a block's factors do not depend on its batch.
   const int rmax = *std::max_element(rh.begin(), rh.end());
-  const bool big = always_batched_q || (int64_t)((rmax + 7) / 8) * nb >= 1024;
-  if (m <= 4608 || big) {
+  if (m <= 4608) {
     SMFS_HIP(launch_qr_apply(A, (int64_t)m * n, m, n, tau, (int64_t)n, ptrs, nullptr, 0, m, drank, rmax, nb, s));
   } else {
     for (int q = 0; q < nb; ++q)
@@ -914,16 +869,8 @@ int jacobi_svd_batch(rocblas_handle h, const JacPlan &p, char *scratch, int m, i
         return SMFS_E_SVD;
       }
   }
-  if (n <= 4608 || big) {
-    SMFS_HIP(launch_qr_apply(T, ts, n, n, tau2, (int64_t)n, nullptr, X, xs, n, drank, rmax, nb, s));
-  } else {
-    for (int q = 0; q < nb; ++q)
-      if (rocsolver_dormqr(h, rocblas_side_left, rocblas_operation_none, n, rh[q], n, T + (size_t)q * ts, n,
-                           tau2 + (size_t)q * n, X + (size_t)q * xs, n) != rocblas_status_success) {
-        set_error("device SVD: ormqr failed");
-        return SMFS_E_SVD;
-      }
-  }
+  // n <= 4096 (jacobi_shape)
+  SMFS_HIP(launch_qr_apply(T, ts, n, n, tau2, (int64_t)n, nullptr, X, xs, n, drank, rmax, nb, s));
   hipLaunchKernelGGL(k_jac_store_v, dim3((unsigned)n, nb), dim3(256), 0, s, f, X);
   SMFS_HIP(hipGetLastError());
   SMFS_HIP(hipStreamSynchronize(s));
