@@ -115,7 +115,7 @@ struct Problem {
   double *d_chk = nullptr, *d_fac = nullptr, *d_part = nullptr, *d_s = nullptr;
   int32_t *d_tsph = nullptr, *d_csph = nullptr;
   int4 *d_tiles = nullptr, *d_eval_tiles = nullptr;
-  int4 *d_stiles = nullptr;                // one-sphere tiles (FP32 far field, block sum)
+  int4 *d_stiles = nullptr;                // one-sphere tiles (SMFS_MIXED far field, block sums, near sums)
   // mixed precision arrays
   float *d_tgt32 = nullptr, *d_src32 = nullptr, *d_str32 = nullptr, *d_part32 = nullptr;
   float *d_s32 = nullptr, *d_fac32 = nullptr;

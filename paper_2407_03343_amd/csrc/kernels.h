@@ -211,8 +211,9 @@ hipError_t launch_direct_block(const BlockDirectArgs &a, hipStream_t s);
 // SMFS_MIXED_EQ for a block of vectors: equivalent strengths of every
 // contact-free sphere (q32b [free][n_eq][nrhs][3]), the FP64 near proxies
 // into near_out [nrhs][T][3] and the FP32 equivalent-source sum into
-// part32b [f.n_splits][nrhs][T][3]; d supplies the one-sphere tiles,
-// targets, sources and the strengths lamb.
+// part32b [f.n_splits][nrhs][T][3]; d supplies the one-sphere tiles of
+// the near sum, targets, sources and the strengths lamb, f the packed tiles
+// of the far sum.
 hipError_t launch_eq_block(const BlockDirectArgs &d, const EqArgs &f, const double *E, int32_t n_proxy,
                            float *q32b, double *near_out, float *part32b, hipStream_t s);
 hipError_t launch_reduce_block(int64_t n3, int32_t nrhs, int32_t ns, const double *part, int32_t ns32,
