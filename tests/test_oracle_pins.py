@@ -332,6 +332,35 @@ def test_mobility_round_trip(oracle_pairsum_built):
     assert np.abs(m["ft"] - r["ft"]).max() < 1e-8 * np.abs(r["ft"]).max()
 
 
+def test_mobility_two_spheres_far_apart(oracle_pairsum_built):
+    """Two unit spheres 8 radii apart, a force on the first only (mu = 1).
+    Far-field hydrodynamics fixes the answer to high order in a/r: the
+    second sphere moves with the Rotne-Prager-Yamakawa coupling
+    (1/(8 pi r)) [(1 + 2a^2/(3r^2)) I + (1 - 2a^2/r^2) rr] F and turns with
+    half the vorticity of the Stokeslet, (F x r)/(8 pi r^3); the first moves
+    with F/(6 pi a), its component along the line of centres reduced by
+    the first reflection, 1 - (15/4)(a/r)^4 (the method of reflections;
+    transverse corrections are O((a/r)^6)).  A sign or factor slip in the
+    coupling of the augmented system would show at O(1)."""
+    d = 8.0
+    g = geo.build(np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]]), 1.0)
+    pb = mfs.Problem(g).setup()
+    F = np.array([1.0, 0.5, -0.3])
+    ft = np.zeros((2, 6))
+    ft[0, :3] = F
+    V = mfs.solve_mobility(pb, ft, tol=1e-12)["rbm"]
+    r = np.array([d, 0.0, 0.0])
+    rh = r / d
+    M12 = ((1 + 2 / (3 * d * d)) * np.eye(3) + (1 - 2 / (d * d)) * np.outer(rh, rh)) / (8 * math.pi * d)
+    v2, w2 = M12 @ F, np.cross(F, r) / (8 * math.pi * d ** 3)
+    v1 = np.array([F[0] * (1 - 15 / (4 * d ** 4)), F[1], F[2]]) / (6 * math.pi)
+    scale1 = np.abs(F).max() / (6 * math.pi)
+    assert np.abs(V[0, :3] - v1).max() < 1e-4 * scale1          # measured 2.2e-5
+    assert np.abs(V[1, :3] - v2).max() < 2e-4 * np.abs(v2).max()  # measured 4.8e-5
+    assert np.abs(V[1, 3:] - w2).max() < 1e-5 * np.abs(w2).max()  # measured 3.5e-8
+    assert np.abs(V[0, 3:]).max() < 1e-6                        # measured 3.2e-8
+
+
 # -- background flow (eq. bc with u_inf; the paper's fixed clusters in a
 # uniform and in a shear flow) -------------------------------------------------
 
