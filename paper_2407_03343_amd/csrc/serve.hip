@@ -425,11 +425,18 @@ void factor_batch_jacobi(Worker &wk, std::vector<Req *> &batch) {
     const int m = grp.first.first, n = grp.first.second;
     std::vector<Job> &jobs = grp.second;
     int cap = (int)std::min<size_t>(kSvdBatch, jobs.size());
+    int prc = SMFS_OK;
     while (true) {
       JacPlan jp;
-      if (jacobi_plan(wk.rb, m, n, cap, jp) == SMFS_OK && jp.total <= region_bytes) break;
+      prc = jacobi_plan(wk.rb, m, n, cap, jp);
+      if (prc != SMFS_OK) break;   // the shape itself is refused (its error is set)
+      if (jp.total <= region_bytes) break;
       if (cap == 1) { cap = 0; break; }
       cap = std::max(1, cap / 2);
+    }
+    if (prc != SMFS_OK) {
+      for (const Job &jb : jobs) fail(jb.r, prc);
+      continue;
     }
     if (cap == 0) {
       set_error("serving: a " + std::to_string(m) + " x " + std::to_string(n) +
