@@ -521,7 +521,10 @@ class Server:
                  server_precision=SMFS_FP64, worker_scratch_bytes=0, iters_per_step=0, setup_batch=0,
                  **over):
         """The server's device memory (its fixed part plus an arena of
-        arena_bytes) is one torch allocation held by this object."""
+        arena_bytes) is one torch allocation held by this object.
+        iters_per_step: GMRES iterations per step() (0: the library's 8);
+        setup_batch: most requests a set-up worker factorises together (0:
+        64); the other arguments are the fields of smfs_server_config."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("smfs.Server needs a HIP device")
