@@ -188,3 +188,28 @@ def test_far_field_near_lists_and_pair_counts():
     assert smfs.Problem(cs, 1.0, eq_points=0).sizes.eq_far_pairs == 0
     with pytest.raises(smfs.SmfsError):
         smfs.Problem(cs, 1.0, eq_separation=3.0)     # below eq_check_radius + 1
+
+
+def test_out_of_reach_slot_adds_exactly_zero():
+    """The FP32 equivalent-source sum moves a slot that must skip a source
+    sphere to 1e20 instead of masking it.  In IEEE single precision the
+    squared distance then overflows to +inf, 1/sqrt(inf) is +0, the
+    projection r.f stays finite for strengths below 1e18, and the pair
+    (f + r (r.f) / r^2) / r adds exactly zero to the accumulator."""
+    f32 = np.float32
+    rng = np.random.default_rng(3)
+    with np.errstate(over="ignore"):
+        for _ in range(200):
+            s = rng.uniform(-1.0, 1.0, 3).astype(f32)           # equivalent point (radius 1)
+            f = (rng.standard_normal(3) * 10.0 ** rng.uniform(-3, 17)).astype(f32)
+            acc = rng.standard_normal(3).astype(f32)
+            r = (np.full(3, 1e20, f32) - s).astype(f32)
+            r2 = f32(r[0] * r[0] + r[1] * r[1] + r[2] * r[2])
+            assert np.isinf(r2)
+            ri = f32(1.0) / np.sqrt(r2)
+            assert ri == 0.0
+            rf = f32(r[0] * f[0] + r[1] * f[1] + r[2] * f[2])
+            assert np.isfinite(rf)
+            t = f32(rf * f32(ri * ri))
+            new = (acc + (f + r * t) * ri).astype(f32)
+            assert np.array_equal(new, acc)
