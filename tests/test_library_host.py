@@ -213,3 +213,17 @@ def test_out_of_reach_slot_adds_exactly_zero():
             t = f32(rf * f32(ri * ri))
             new = (acc + (f + r * t) * ri).astype(f32)
             assert np.array_equal(new, acc)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """No CPU fallback: with the shared library absent the binding raises on
+    first use (run in a child process so the loaded library of this one is
+    not disturbed)."""
+    import subprocess
+    import sys
+    code = ("from paper_2407_03343_amd import smfs\n"
+            "try:\n    smfs.lib()\nexcept RuntimeError as e:\n    print('raised:', e)\n")
+    env = dict(os.environ, SMFS_LIB=str(tmp_path / "absent" / "libsmfs.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))), env=env)
+    assert r.returncode == 0 and "raised:" in r.stdout and "missing" in r.stdout
