@@ -63,3 +63,11 @@ def test_offdiag_error_ignores_identity_part():
 def test_budget():
     b = bench.Budget(100.0)
     assert b.fits(50.0) and not b.fits(150.0)
+
+
+def test_serve_only_needs_requests():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--serve-only", "--serve-requests", "0"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "--serve-requests" in r.stderr
+    assert r.stdout.strip() == ""
