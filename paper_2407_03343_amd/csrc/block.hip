@@ -345,6 +345,7 @@ int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B
     SMFS_HIP(launch_norm_scale_block(R, ld, nrhs, n, part, nch, beta, ldh, false, s));
     SMFS_HIP(hipMemcpyAsync(hb, beta, sizeof(double) * nrhs * ldh, hipMemcpyDeviceToHost, s));
     SMFS_HIP(hipStreamSynchronize(s));
+    bool all_conv = true, any_miss = false;
     for (int q = 0; q < nrhs; ++q) {
       rn[q] = hb[(size_t)q * ldh];
       if (bnorm[q] == 0.0) continue;
@@ -352,6 +353,16 @@ int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B
       if (refine) st.conv[q] = met ? 1 : 0;       // checked against the FP64 residual
       if (met && !st.conv[q]) st.conv[q] = 1;
       if (met) st.est[q] = rn[q] / bnorm[q];
+      all_conv = all_conv && st.conv[q];
+      any_miss = any_miss || !met;
+    }
+    // The last running systems met the tolerance on this FP64 residual
+    // while others stand converged on their mixed estimates alone: this
+    // restart becomes their refinement, as if the estimates had met first.
+    if (mixed && !refine && all_conv && any_miss && refinements < 2) {
+      ++refinements;
+      for (int q = 0; q < nrhs; ++q)
+        if (bnorm[q] != 0.0) st.conv[q] = rn[q] / bnorm[q] <= tol ? 1 : 0;
     }
     st.refinements = refinements;
   }
