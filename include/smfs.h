@@ -376,12 +376,13 @@ typedef struct smfs_block_out {
   int32_t *iterations;         /* [host, out] nrhs GMRES iteration counts, or NULL */
   double *true_rel_residual;   /* [host, out] nrhs values ||b - G_hat mu|| / ||b||, or NULL */
   int32_t max_iterations;      /* out: block products in the Krylov iterations */
-  int32_t n_converged;         /* out: systems whose GMRES estimate met gmres_tol */
+  int32_t n_converged;         /* out: systems that ended converged: the GMRES estimate,
+                                  or the FP64 residual at a restart, met gmres_tol */
   double t_gmres_ms, t_post_ms;
   int64_t pair_evals;          /* out: pair x right-hand-side evaluations */
   int64_t pair_evals_f32;      /* out: of which in FP32 (mixed precision) */
   int32_t refinements;         /* out: mixed precision: restarts from FP64 true residuals
-                                  after every estimate met the tolerance */
+                                  once every system stood converged (at most 2) */
 } smfs_block_out;
 
 /* Resistance solves for nrhs rigid motions together: rbm [dev]
@@ -390,10 +391,11 @@ typedef struct smfs_block_out {
  * systems advance in lock step through block products, a system that has
  * converged stays frozen while the others go on.  The products follow
  * params.precision: in a mixed form every restart takes the FP64 true
- * residuals, and once every estimate met the tolerance the systems restart
- * from them up to twice (those above the tolerance go on); FP64 block
- * solves take no such refinement (unlike smfs_solve_resistance).  ws as above
- * with restart > 0.  Returns SMFS_OK when every FP64 true residual met
+ * residuals, and once every system stands converged (on its estimate, or
+ * on the FP64 residual of a restart) while some FP64 residual misses the
+ * tolerance, the systems restart from them up to twice (those above the
+ * tolerance go on); FP64 block solves take no such refinement (unlike
+ * smfs_solve_resistance).  ws as above with restart > 0.  Returns SMFS_OK when every FP64 true residual met
  * gmres_tol, SMFS_STAGNATED when every estimate did but some true residual
  * did not, SMFS_NOT_CONVERGED otherwise. */
 int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rbm, int32_t restart,

@@ -215,8 +215,9 @@ struct Pinned {
 int gmres_block(Problem &pb, const BlockLayout &L, int32_t nrhs, const double *B, double *X,
                 double tol, int max_it, BlockStats &st, hipStream_t s, int precision = SMFS_FP64) {
   // mixed products inside the cycles; every restart takes the FP64 true
-  // residual, and a mixed solve whose estimates all met the tolerance
-  // restarts from it up to twice (systems above the tolerance go on)
+  // residual, and a mixed solve whose systems all stand converged while
+  // some FP64 residual misses restarts from it up to twice (systems above
+  // the tolerance go on)
   const bool mixed = is_mixed(precision) && L.nsplit32 > 0;
   int refinements = 0;
   const int64_t n = 3 * pb.T, ld = L.ld;
