@@ -257,6 +257,55 @@ def test_two_spheres_against_brenner(pair001):
     assert eps < 1e-3
 
 
+def _stimson_jeffery(h):
+    """Drag factor F / (6 pi mu a U) of two equal spheres translating with the
+    same velocity along their line of centres, half centre distance h radii
+    (Stimson & Jeffery 1926, bispherical coordinates, cosh(alpha) = h).  The
+    bracket of each term is written as one quotient,
+    [2 - 2 exp(-(2n+1) alpha) + (2n+1) sinh(2 alpha) + (2n+1)^2 sinh^2(alpha)]
+    / [2 sinh((2n+1) alpha) + (2n+1) sinh(2 alpha)], which is 1 minus the
+    published ratio without its cancellation."""
+    al = math.acosh(h)
+    sa, s2 = math.sinh(al), math.sinh(2 * al)
+    tot = 0.0
+    for n in range(1, 100000):
+        k = 2 * n + 1
+        x = k * al
+        if x > 700.0:           # the remaining terms are below exp(-700) relative
+            break
+        num = 2.0 - 2.0 * math.exp(-x) + k * s2 + k * k * sa * sa
+        tot += n * (n + 1) / ((2 * n - 1) * (2 * n + 3)) * num / (2.0 * math.sinh(x) + k * s2)
+    return 4.0 / 3.0 * sa * tot
+
+
+def test_stimson_jeffery_far_field_expansion():
+    """The series above against the method of reflections for spheres far
+    apart: 1 - 3/(2d) + 9/(4d^2) - 19/(8d^3) + O(d^-4), d the centre distance."""
+    for d in (20.0, 40.0, 80.0):
+        r = _stimson_jeffery(d / 2) - (1 - 1.5 / d + 2.25 / d ** 2 - 2.375 / d ** 3)
+        assert abs(r) * d ** 4 < 10.0, (d, r)
+
+
+def test_two_spheres_translating_together(pair001):
+    """Gap 0.01, both spheres moving with unit velocity along the line of
+    centres: each force equals 6 pi mu a U times the Stimson-Jeffery factor
+    (0.6457 here).  With the separating motion pinned against Brenner's
+    series, this fixes both two-body resistance functions along the line
+    of centres, so a sign error in the coupling between the spheres fails
+    one of the two."""
+    pb = pair001["pb"]
+    rbm = np.zeros((2, 6))
+    rbm[:, 0] = 1.0
+    out = mfs.solve_resistance(pb, rbm, tol=1e-10)
+    c = pair001["g"].centers
+    h = 0.5 * np.linalg.norm(c[1] - c[0])
+    Fsj = 6 * math.pi * _stimson_jeffery(h)
+    for F in out["ft"][:, :3]:
+        assert abs(F[0] - Fsj) < 1e-4 * Fsj            # measured 7.8e-6
+        assert np.abs(F[1:]).max() < 1e-5 * Fsj
+    assert np.abs(out["ft"][:, 3:]).max() < 1e-5 * Fsj
+
+
 def test_resistance_matrix_symmetric_positive(pair001):
     """Lorentz reciprocity: the 12 x 12 resistance matrix of the pair is
     symmetric and positive definite (to discretisation accuracy)."""
