@@ -306,6 +306,54 @@ def test_two_spheres_translating_together(pair001):
     assert np.abs(out["ft"][:, 3:]).max() < 1e-5 * Fsj
 
 
+def _jeffery_axial_torque(h, same_sense):
+    """Torque factor T / (8 pi mu a^3 Omega) of two equal spheres spinning
+    about their line of centres, half centre distance h radii (Jeffery 1915,
+    bispherical coordinates, cosh(alpha) = h): sinh^3(alpha) times the sum
+    over n >= 1 of cosech^3(n alpha), with alternating signs (+, -, +, ...)
+    when both spin in the same sense.  Spinning in opposite senses is a
+    sphere spinning at distance h from a no-slip wall."""
+    al = math.acosh(h)
+    tot = 0.0
+    for n in range(1, 100000):
+        if n * al > 230.0:         # cosech^3 below exp(-690)
+            break
+        tot += (-1.0 if same_sense and n % 2 == 0 else 1.0) / math.sinh(n * al) ** 3
+    return math.sinh(al) ** 3 * tot
+
+
+def test_jeffery_series_limits():
+    """At contact the factors tend to zeta(3) (opposite senses) and
+    (3/4) zeta(3) (same sense); far apart to 1 -/+ (a/d)^3, the vorticity
+    of the other sphere's rotlet at distance d."""
+    z3 = 1.2020569031595942
+    assert abs(_jeffery_axial_torque(1 + 1e-8, False) - z3) < 1e-6
+    assert abs(_jeffery_axial_torque(1 + 1e-8, True) - 0.75 * z3) < 1e-6
+    for d in (10.0, 20.0):
+        assert abs(_jeffery_axial_torque(d / 2, True) - (1 - d ** -3)) < 2 * d ** -6
+        assert abs(_jeffery_axial_torque(d / 2, False) - (1 + d ** -3)) < 2 * d ** -6
+
+
+@pytest.mark.parametrize("same_sense", [True, False])
+def test_two_spheres_spinning_about_line_of_centres(pair001, same_sense):
+    """Gap 0.01, unit angular velocities about the line of centres, in the
+    same or opposite senses: each torque equals 8 pi mu a^3 Omega times
+    Jeffery's series (22.684 and 29.932 here; measured agreement 1e-9), the
+    forces and the other torque components vanish.  This pins the rotlet
+    and doublet images and the torque reduction."""
+    pb = pair001["pb"]
+    rbm = np.zeros((2, 6))
+    rbm[0, 3], rbm[1, 3] = 1.0, (1.0 if same_sense else -1.0)
+    out = mfs.solve_resistance(pb, rbm, tol=1e-10)
+    c = pair001["g"].centers
+    Tj = 8 * math.pi * _jeffery_axial_torque(0.5 * np.linalg.norm(c[1] - c[0]), same_sense)
+    ft = out["ft"]
+    assert abs(ft[0, 3] - Tj) < 1e-6 * Tj
+    assert abs(ft[1, 3] - rbm[1, 3] * Tj) < 1e-6 * Tj
+    assert np.abs(ft[:, 4:]).max() < 1e-6 * Tj
+    assert np.abs(ft[:, :3]).max() < 1e-6 * Tj
+
+
 def test_resistance_matrix_symmetric_positive(pair001):
     """Lorentz reciprocity: the 12 x 12 resistance matrix of the pair is
     symmetric and positive definite (to discretisation accuracy)."""
