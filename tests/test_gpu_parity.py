@@ -19,6 +19,8 @@ from oracle import geometry as geo, mfs, brenner
 from oracle.pairsum import pairsum
 from paper_2407_03343_amd import workloads as wl
 
+from closed_forms import jeffery_axial_torque, stimson_jeffery
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -220,6 +222,41 @@ def test_gpu_setup_matches_oracle(dev, pair001):
     assert np.abs(ft - ref).max() < 1e-5 * np.abs(ref).max()
     Fb = brenner.brenner_force(0.01, 0.5)
     assert abs(np.linalg.norm(ft[1, :3]) - Fb) < 1e-3 * Fb
+
+
+def test_pair_device_against_closed_forms(dev):
+    """Device set-up and solves for two spheres at gap 0.01, nothing taken
+    from the oracle: translating together along the line of centres
+    (Stimson-Jeffery), spinning about it in the same and in opposite senses
+    (Jeffery).  Bars 1e-4 for the force and 1e-5 for the torques: the
+    oracle meets them with margins of 13 and 100, and the device factors
+    move the discrete solution by about 1e-6 (rounding amplified by the
+    truncated pseudo-inverses at this gap)."""
+    _say("two spheres, gap 0.01, device set-up: Stimson-Jeffery and Jeffery closed forms")
+    pk = wl.two_sphere(0.01)
+    c = np.asarray(pk.centers)
+    ax = (c[1] - c[0]) / np.linalg.norm(c[1] - c[0])
+    h = 0.5 * np.linalg.norm(c[1] - c[0])
+    lib = dev.Problem(c, 1.0).bind().setup()
+    cases = (("translating together", np.concatenate([ax, 0 * ax]), np.concatenate([ax, 0 * ax]),
+              6 * math.pi * stimson_jeffery(h), 0, 1e-4),
+             ("spinning, same sense", np.concatenate([0 * ax, ax]), np.concatenate([0 * ax, ax]),
+              8 * math.pi * jeffery_axial_torque(h, True), 3, 1e-5),
+             ("spinning, opposite senses", np.concatenate([0 * ax, ax]), np.concatenate([0 * ax, -ax]),
+              8 * math.pi * jeffery_axial_torque(h, False), 3, 1e-5))
+    for name, m0, m1, ref, off, bar in cases:
+        rbm = np.stack([m0, m1])
+        out = lib.solve_resistance(_t(rbm))
+        ft = _n(out["ft"]).reshape(2, 6)
+        along = np.array([ft[q, off:off + 3] @ ax for q in range(2)])
+        want = np.array([ref * (m0[off:off + 3] @ ax), ref * (m1[off:off + 3] @ ax)])
+        d = np.abs(along - want).max() / ref
+        other = np.abs(ft - np.outer(along, np.concatenate([ax, 0 * ax]) if off == 0
+                                     else np.concatenate([0 * ax, ax]))).max() / ref
+        _say(f"  {name}: closed form {ref:.6f}, rel diff {d:.2e}, other components {other:.2e}, "
+             f"it {out['iterations']}, status {out['status']}")
+        assert _finished(out)
+        assert d < bar and other < bar
 
 
 def test_single_sphere_device(dev):

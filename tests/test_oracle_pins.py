@@ -11,6 +11,8 @@ import pytest
 from oracle import geometry as geo, kernels, mfs, brenner
 from oracle.pairsum import pairsum
 
+from closed_forms import jeffery_axial_torque, stimson_jeffery
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
 
@@ -257,32 +259,11 @@ def test_two_spheres_against_brenner(pair001):
     assert eps < 1e-3
 
 
-def _stimson_jeffery(h):
-    """Drag factor F / (6 pi mu a U) of two equal spheres translating with the
-    same velocity along their line of centres, half centre distance h radii
-    (Stimson & Jeffery 1926, bispherical coordinates, cosh(alpha) = h).  The
-    bracket of each term is written as one quotient,
-    [2 - 2 exp(-(2n+1) alpha) + (2n+1) sinh(2 alpha) + (2n+1)^2 sinh^2(alpha)]
-    / [2 sinh((2n+1) alpha) + (2n+1) sinh(2 alpha)], which is 1 minus the
-    published ratio without its cancellation."""
-    al = math.acosh(h)
-    sa, s2 = math.sinh(al), math.sinh(2 * al)
-    tot = 0.0
-    for n in range(1, 100000):
-        k = 2 * n + 1
-        x = k * al
-        if x > 700.0:           # the remaining terms are below exp(-700) relative
-            break
-        num = 2.0 - 2.0 * math.exp(-x) + k * s2 + k * k * sa * sa
-        tot += n * (n + 1) / ((2 * n - 1) * (2 * n + 3)) * num / (2.0 * math.sinh(x) + k * s2)
-    return 4.0 / 3.0 * sa * tot
-
-
 def test_stimson_jeffery_far_field_expansion():
-    """The series above against the method of reflections for spheres far
+    """The Stimson-Jeffery series against the method of reflections for spheres far
     apart: 1 - 3/(2d) + 9/(4d^2) - 19/(8d^3) + O(d^-4), d the centre distance."""
     for d in (20.0, 40.0, 80.0):
-        r = _stimson_jeffery(d / 2) - (1 - 1.5 / d + 2.25 / d ** 2 - 2.375 / d ** 3)
+        r = stimson_jeffery(d / 2) - (1 - 1.5 / d + 2.25 / d ** 2 - 2.375 / d ** 3)
         assert abs(r) * d ** 4 < 10.0, (d, r)
 
 
@@ -299,27 +280,11 @@ def test_two_spheres_translating_together(pair001):
     out = mfs.solve_resistance(pb, rbm, tol=1e-10)
     c = pair001["g"].centers
     h = 0.5 * np.linalg.norm(c[1] - c[0])
-    Fsj = 6 * math.pi * _stimson_jeffery(h)
+    Fsj = 6 * math.pi * stimson_jeffery(h)
     for F in out["ft"][:, :3]:
         assert abs(F[0] - Fsj) < 1e-4 * Fsj            # measured 7.8e-6
         assert np.abs(F[1:]).max() < 1e-5 * Fsj
     assert np.abs(out["ft"][:, 3:]).max() < 1e-5 * Fsj
-
-
-def _jeffery_axial_torque(h, same_sense):
-    """Torque factor T / (8 pi mu a^3 Omega) of two equal spheres spinning
-    about their line of centres, half centre distance h radii (Jeffery 1915,
-    bispherical coordinates, cosh(alpha) = h): sinh^3(alpha) times the sum
-    over n >= 1 of cosech^3(n alpha), with alternating signs (+, -, +, ...)
-    when both spin in the same sense.  Spinning in opposite senses is a
-    sphere spinning at distance h from a no-slip wall."""
-    al = math.acosh(h)
-    tot = 0.0
-    for n in range(1, 100000):
-        if n * al > 230.0:         # cosech^3 below exp(-690)
-            break
-        tot += (-1.0 if same_sense and n % 2 == 0 else 1.0) / math.sinh(n * al) ** 3
-    return math.sinh(al) ** 3 * tot
 
 
 def test_jeffery_series_limits():
@@ -327,11 +292,11 @@ def test_jeffery_series_limits():
     (3/4) zeta(3) (same sense); far apart to 1 -/+ (a/d)^3, the vorticity
     of the other sphere's rotlet at distance d."""
     z3 = 1.2020569031595942
-    assert abs(_jeffery_axial_torque(1 + 1e-8, False) - z3) < 1e-6
-    assert abs(_jeffery_axial_torque(1 + 1e-8, True) - 0.75 * z3) < 1e-6
+    assert abs(jeffery_axial_torque(1 + 1e-8, False) - z3) < 1e-6
+    assert abs(jeffery_axial_torque(1 + 1e-8, True) - 0.75 * z3) < 1e-6
     for d in (10.0, 20.0):
-        assert abs(_jeffery_axial_torque(d / 2, True) - (1 - d ** -3)) < 2 * d ** -6
-        assert abs(_jeffery_axial_torque(d / 2, False) - (1 + d ** -3)) < 2 * d ** -6
+        assert abs(jeffery_axial_torque(d / 2, True) - (1 - d ** -3)) < 2 * d ** -6
+        assert abs(jeffery_axial_torque(d / 2, False) - (1 + d ** -3)) < 2 * d ** -6
 
 
 @pytest.mark.parametrize("same_sense", [True, False])
@@ -346,7 +311,7 @@ def test_two_spheres_spinning_about_line_of_centres(pair001, same_sense):
     rbm[0, 3], rbm[1, 3] = 1.0, (1.0 if same_sense else -1.0)
     out = mfs.solve_resistance(pb, rbm, tol=1e-10)
     c = pair001["g"].centers
-    Tj = 8 * math.pi * _jeffery_axial_torque(0.5 * np.linalg.norm(c[1] - c[0]), same_sense)
+    Tj = 8 * math.pi * jeffery_axial_torque(0.5 * np.linalg.norm(c[1] - c[0]), same_sense)
     ft = out["ft"]
     assert abs(ft[0, 3] - Tj) < 1e-6 * Tj
     assert abs(ft[1, 3] - rbm[1, 3] * Tj) < 1e-6 * Tj
