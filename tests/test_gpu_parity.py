@@ -228,7 +228,8 @@ def test_pair_device_against_closed_forms(dev):
     """Device set-up and solves for two spheres at gap 0.01, nothing taken
     from the oracle: translating together along the line of centres
     (Stimson-Jeffery), spinning about it in the same and in opposite senses
-    (Jeffery).  Bars 1e-4 for the force and 1e-5 for the torques: the
+    (Jeffery); then the mobility problem with the forces and torques of
+    those motions.  Bars 1e-4 for the force and 1e-5 for the torques: the
     oracle meets them with margins of 13 and 100, and the device factors
     move the discrete solution by about 1e-6 (rounding amplified by the
     truncated pseudo-inverses at this gap)."""
@@ -257,6 +258,16 @@ def test_pair_device_against_closed_forms(dev):
              f"it {out['iterations']}, status {out['status']}")
         assert _finished(out)
         assert d < bar and other < bar
+    # the mobility problem: the same motions from the forces and torques
+    for name, m0, m1, ref, off, bar in cases:
+        ft = np.stack([m0, m1])
+        out = lib.solve_mobility(_t(ft))
+        rbm = _n(out["rbm"]).reshape(2, 6)
+        expect = np.stack([m0, m1]) / ref
+        d = np.abs(rbm - expect).max() * ref
+        _say(f"  mobility, {name}: rel diff {d:.2e}, it {out['iterations']}, status {out['status']}")
+        assert _finished(out)
+        assert d < bar
 
 
 def test_single_sphere_device(dev):
