@@ -203,6 +203,37 @@ def test_adaptive_image_count_solve(dev, oracle_pairsum_built):
     assert d < max(1e-10, 20 * d_or)
 
 
+def test_gmres_count_trend_tetrahedron(dev, oracle_pairsum_built):
+    """Section 5.3 (Figure iters): four spheres on a tetrahedron, each pair
+    delta apart, tolerance 1e-6, reduced discretisation (120 proxies, 160
+    base nodes, 6 image nodes), oracle factors imported.  The device's
+    iteration counts follow the oracle's (within 3 when no refinement ran)
+    and grow by a factor in [2, 5] per decade of delta, as the oracle's do
+    (delta^(-1/2) gives 3.16); forces and torques within 1e-5."""
+    _say("GMRES count against the gap: tetrahedron at delta 1e-1, 1e-2, 1e-3")
+    v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)
+    rbm = np.random.default_rng(3).standard_normal((4, 6))
+    prm = dict(n_proxy=120, n_colloc_base=160, n_image=6)
+    its = []
+    for delta in (1e-1, 1e-2, 1e-3):
+        c = v * (2 + delta) / np.linalg.norm(v[0] - v[1])
+        pbo = mfs.Problem(geo.build(c, 1.0, geo.Params(**prm))).setup()
+        lib = dev.Problem(c, 1.0, gmres_tol=1e-6, **prm, **NOGUARD).bind()
+        _import_oracle_factors(lib, pbo)
+        out = lib.solve_resistance(_t(rbm))
+        ref = mfs.solve_resistance(pbo, rbm, tol=1e-6)
+        ft = _n(out["ft"]).reshape(-1, 6)
+        d = np.abs(ft - ref["ft"]).max() / np.abs(ref["ft"]).max()
+        _say(f"  delta {delta:.0e}: it {out['iterations']} (+{out['refinements']} refinements), "
+             f"oracle {ref['iterations']}, status {out['status']}, F/T {d:.2e}")
+        assert _finished(out) and d < 1e-5
+        if out["refinements"] == 0:
+            assert abs(out["iterations"] - ref["iterations"]) <= 3
+        its.append(out["iterations"])
+    for a, b in zip(its, its[1:]):
+        assert 2.0 <= b / a <= 5.0, its
+
+
 def test_gpu_setup_matches_oracle(dev, pair001):
     _say("device setup (rocSOLVER SVD) for two spheres")
     lib = dev.Problem(pair001["pk"].centers, 1.0).bind().setup()
