@@ -193,7 +193,10 @@ int smfs_problem_create(const smfs_params *p, int32_t P, const double *centers,
 void smfs_problem_destroy(smfs_problem *pb);
 int smfs_problem_sizes(const smfs_problem *pb, smfs_sizes *s);
 
-/* Copy node sets out [host]; any pointer may be NULL.  targets T x 3,
+/* Copy node sets out [host] (Section 2.1 proxy and collocation points;
+ * Section 2.3 image lines, eqs. line_points and tj; Section 5.1 cap points
+ * and weights; check points of eq. residual_x); any pointer may be NULL.
+ * targets T x 3,
  * target_sphere T, target_weight T (area weights w_i), sources S x 3,
  * source_kind S (0 S, 1 R, 2 D), source_sphere S, check n_check x 3,
  * check_sphere n_check. */
@@ -201,7 +204,8 @@ int smfs_export_nodes(const smfs_problem *pb, double *targets, int32_t *target_s
                       double *target_weight, double *sources, int32_t *source_kind,
                       int32_t *source_sphere, double *check, int32_t *check_sphere);
 
-/* Factor id of sphere k (0 = the shared contact-free factor). */
+/* Factor id of sphere k (0 = the shared contact-free factor): the SVD of
+ * B_k = W_k G^(kk) behind eq. transform (Section 2.2). */
 int smfs_sphere_factor(const smfs_problem *pb, int32_t k, int32_t *fid);
 /* Shape of self block fid: rows = 3 M, cols = 3 N', rank after truncation
  * (0 before setup/import), representative sphere. */
@@ -241,7 +245,8 @@ int smfs_setup(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_strea
 int smfs_far_field_workspace_bytes(smfs_problem *pb, size_t *bytes);
 int smfs_setup_far_field(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream);
 
-/* Install a factor computed elsewhere.  U [host] rows x rank column-major,
+/* Install a factor of eq. transform (Section 2.2) computed elsewhere.
+ * U [host] rows x rank column-major,
  * sigma [host] rank, V [host] cols x rank row-major.  Synchronises. */
 int smfs_import_factor(smfs_problem *pb, int32_t fid, int32_t rank, const double *U,
                        const double *sigma, const double *V, smfs_stream stream);
@@ -278,11 +283,14 @@ int smfs_rhs(smfs_problem *pb, const double *rbm, double *b, smfs_stream stream)
  * the homogeneous Stokes equations only when divergence-free). */
 int smfs_set_background(smfs_problem *pb, const double *U, const double *L);
 
-/* ft [dev] P x 6 from lambda [dev] S x 3. */
+/* ft [dev] P x 6 from lambda [dev] S x 3: per sphere the summed Stokeslet
+ * strengths and the rotlet strengths plus the Stokeslet moments about the
+ * centre (Remark "Extracting net forces and torques", Section 2.3). */
 int smfs_force_torque(smfs_problem *pb, const double *lambda, double *ft, smfs_stream stream);
 
 /* u [dev] n x 3 = sum over every source of K(x - y) lambda at points x [dev]
- * n x 3 (flow evaluation; no source is skipped). */
+ * n x 3 (flow evaluation, eq. uAll with no source skipped; the velocity
+ * of eq. residual_x at check points). */
 int smfs_eval_velocity(smfs_problem *pb, const double *lambda, int64_t n, const double *x,
                        double *u, smfs_stream stream);
 
@@ -313,15 +321,15 @@ int smfs_solve_resistance(smfs_problem *pb, const double *rbm, smfs_out *out,
  * one of the modes above; gmres_max_it > 0; gmres_tol > 0. */
 int smfs_set_solver(smfs_problem *pb, int32_t precision, double gmres_tol, int32_t gmres_max_it);
 
-/* Mobility solve (forces and torques in, rigid motions out; the paper
- * treats the resistance problem and points to the mobility problem as
- * separate work).  ft [dev] P x 6 = (F, T) exerted on the fluid.  Unknowns
- * (mu, V): the rows G_hat mu - W (v + omega x (x - c)) = -W u_inf at the
- * collocation nodes (u_inf = 0 unless set by smfs_set_background) and, per
- * sphere, the force and torque of
- * lambda = B^+ mu equal to (F, T), scaled by 1/(6 pi mu a) and
- * 1/(8 pi mu a^3).  out->rbm receives V; other outputs as for resistance
- * (the check-point residual is measured against the V found). */
+/* Mobility solve (forces and torques in, rigid motions out; Section 1
+ * names the mobility problem beside the resistance problem of Section 2.2,
+ * eq. resistance, without formulating it; this is the augmented form).
+ * ft [dev] P x 6 = (F, T) exerted on the fluid.  Unknowns (mu, V): the rows
+ * G_hat mu - W (v + omega x (x - c)) = -W u_inf at the collocation nodes
+ * (u_inf = 0 unless set by smfs_set_background) and, per sphere, the force
+ * and torque of lambda = B^+ mu equal to (F, T), scaled by 1/(6 pi mu a)
+ * and 1/(8 pi mu a^3).  out->rbm receives V; other outputs as for
+ * resistance (the check-point residual is measured against the V found). */
 int smfs_solve_mobility(smfs_problem *pb, const double *ft, smfs_out *out, smfs_stream stream);
 
 /* ---- Many right-hand sides ------------------------------------------
@@ -385,38 +393,39 @@ typedef struct smfs_block_out {
                                   once every system stood converged (at most 2) */
 } smfs_block_out;
 
-/* Resistance solves for nrhs rigid motions together: rbm [dev]
- * nrhs x P x 6.  Every system runs its own GMRES(restart) with the
- * problem's gmres_tol and gmres_max_it; the Krylov iterations of all
- * systems advance in lock step through block products, a system that has
- * converged stays frozen while the others go on.  The products follow
- * params.precision: in a mixed form every restart takes the FP64 true
- * residuals, and once every system stands converged (on its estimate, or
- * on the FP64 residual of a restart) while some FP64 residual misses the
- * tolerance, the systems restart from them up to twice (those above the
- * tolerance go on); FP64 block solves take no such refinement (unlike
- * smfs_solve_resistance).  ws as above with restart > 0.  Returns SMFS_OK when every FP64 true residual met
- * gmres_tol, SMFS_STAGNATED when every estimate did but some true residual
- * did not, SMFS_NOT_CONVERGED otherwise. */
+/* Resistance solves (Section 2.2, eq. resistance) for nrhs rigid motions
+ * together: rbm [dev] nrhs x P x 6.  Every system runs its own
+ * GMRES(restart) with the problem's gmres_tol and gmres_max_it; the Krylov
+ * iterations of all systems advance in lock step through block products, a
+ * system that has converged stays frozen while the others go on.  The
+ * products follow params.precision: in a mixed form every restart takes the
+ * FP64 true residuals, and once every system stands converged (on its
+ * estimate, or on the FP64 residual of a restart) while some FP64 residual
+ * misses the tolerance, the systems restart from them up to twice (those
+ * above the tolerance go on); FP64 block solves take no such refinement
+ * (unlike smfs_solve_resistance).  ws as above with restart > 0.  Returns
+ * SMFS_OK when every FP64 true residual met gmres_tol, SMFS_STAGNATED when
+ * every system stood converged but some true residual did not meet it,
+ * SMFS_NOT_CONVERGED otherwise. */
 int smfs_solve_resistance_block(smfs_problem *pb, int32_t nrhs, const double *rbm, int32_t restart,
                                 void *ws, size_t ws_bytes, smfs_block_out *out,
                                 smfs_stream stream);
 
 /* ---- Serving --------------------------------------------------------
- * A server holds many independent resistance problems (different sphere
- * counts and packings, one discretisation) resident on one GPU and
- * advances them together.  Requests are admitted in arrival order when
- * their workspace fits into the server's device arena and a slot is free;
- * set-up worker threads build and factorise admitted requests in batches
- * on their own streams while the resident requests keep iterating.  Every call of
- * smfs_server_step performs iters_per_step GMRES iterations of every
- * resident request: one launch of each kernel of the product with G_hat, of
- * the Arnoldi step and of the Givens step covers all of them, and a request
- * that arrives between steps joins at the next one (continuous batching).  A finished request leaves at once
- * and its memory and slot go to the next waiting request.  Every request
- * keeps the chunking and summation order of its own problem in every
- * kernel, so a result does not depend on which other requests share the
- * launches.
+ * A server holds many independent resistance problems (Section 2.2, eq.
+ * resistance; different sphere counts and packings, one discretisation)
+ * resident on one GPU and advances them together.  Requests are admitted in
+ * arrival order when their workspace fits into the server's device arena
+ * and a slot is free; set-up worker threads build and factorise admitted
+ * requests in batches on their own streams while the resident requests
+ * keep iterating.  Every call of smfs_server_step performs iters_per_step
+ * GMRES iterations of every resident request: one launch of each kernel of
+ * the product with G_hat, of the Arnoldi step and of the Givens step covers
+ * all of them, and a request that arrives between steps joins at the next
+ * one (continuous batching).  A finished request leaves at once and its
+ * memory and slot go to the next waiting request.  Every request keeps the
+ * chunking and summation order of its own problem in every kernel, so a
+ * result does not depend on which other requests share the launches.
  *
  * The shared factor of contact-free spheres (Section 2.2, eq. transform)
  * depends only on the discretisation: the server factorises it once and
