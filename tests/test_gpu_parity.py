@@ -260,7 +260,8 @@ def test_pair_device_against_closed_forms(dev):
     from the oracle: translating together along the line of centres
     (Stimson-Jeffery), spinning about it in the same and in opposite senses
     (Jeffery); then the mobility problem with the forces and torques of
-    those motions.  Bars 1e-4 for the force and 1e-5 for the torques: the
+    those motions, and the pair at rest in a uniform stream along its line
+    of centres and in a rigid rotation about it (background flows).  Bars 1e-4 for the force and 1e-5 for the torques: the
     oracle meets them with margins of 13 and 100, and the device factors
     move the discrete solution by about 1e-6 (rounding amplified by the
     truncated pseudo-inverses at this gap)."""
@@ -297,6 +298,18 @@ def test_pair_device_against_closed_forms(dev):
         expect = np.stack([m0, m1]) / ref
         d = np.abs(rbm - expect).max() * ref
         _say(f"  mobility, {name}: rel diff {d:.2e}, it {out['iterations']}, status {out['status']}")
+        assert _finished(out)
+        assert d < bar
+    # at rest in a uniform stream along the line of centres and in a rigid
+    # rotation about it: the first and second motions above, reversed
+    W = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    for (name, m0, m1, ref, off, bar), flow in zip(cases[:2], (dict(U=ax), dict(L=W))):
+        lib.set_background(**flow)
+        out = lib.solve_resistance(_t(np.zeros((2, 6))))
+        lib.set_background()
+        ft = _n(out["ft"]).reshape(2, 6)
+        d = np.abs(ft + ref * np.stack([m0, m1])).max() / ref
+        _say(f"  at rest in the flow reversing '{name}': rel diff {d:.2e}, status {out['status']}")
         assert _finished(out)
         assert d < bar
 

@@ -347,6 +347,32 @@ def test_mobility_pair_closed_forms(pair001, case):
         assert np.abs(rbm[q] - expect).max() < 10 * bar * want
 
 
+@pytest.mark.parametrize("flow", ["stream", "rotation"])
+def test_pair_at_rest_in_background_flow(pair001, flow):
+    """The pair at gap 0.01 held at rest (eq. bc with v = omega = 0) in a
+    uniform stream along its line of centres, or in a rigid rotation about
+    that line: the disturbance is that of the pair moving with -U, or
+    spinning with -Omega in the same sense, in fluid at rest, so the forces
+    are -6 pi mu a U lambda_SJ and the torques -8 pi mu a^3 Omega tau_J
+    (measured agreement 7.8e-6 and 1e-9)."""
+    c = pair001["g"].centers
+    ax = (c[1] - c[0]) / np.linalg.norm(c[1] - c[0])
+    h = 0.5 * np.linalg.norm(c[1] - c[0])
+    if flow == "stream":
+        u_inf, off, ref, bar = mfs.linear_flow(U=ax), 0, -6 * math.pi * stimson_jeffery(h), 1e-4
+    else:
+        assert np.abs(np.cross(c[0], ax)).max() < 1e-14        # the axis passes through the centres
+        W = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+        u_inf, off, ref, bar = (mfs.linear_flow(L=W), 3, -8 * math.pi * jeffery_axial_torque(h, True),
+                                1e-6)
+    ft = mfs.solve_resistance(pair001["pb"], np.zeros((2, 6)), tol=1e-10, u_inf=u_inf)["ft"]
+    for q in range(2):
+        assert abs(ft[q, off:off + 3] @ ax - ref) < bar * abs(ref)
+        expect = np.zeros(6)
+        expect[off:off + 3] = ref * ax
+        assert np.abs(ft[q] - expect).max() < 10 * bar * abs(ref)
+
+
 def test_resistance_matrix_symmetric_positive(pair001):
     """Lorentz reciprocity: the 12 x 12 resistance matrix of the pair is
     symmetric and positive definite (to discretisation accuracy)."""
