@@ -574,7 +574,8 @@ def block_solve(args, torch, smfs, wl):
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t2) / k * nrhs
     log(f"  block solve: {t_block:.1f} s ({args.block_precision}, status {int(blk['status'])}, max it "
-        f"{int(blk['max_iterations'])}, +{int(blk['refinements'])} refinements) against {t_seq:.1f} s for "
+        f"{int(blk['max_iterations'])}, +{int(blk['refinements'])} refinements, largest true residual "
+        f"{float(np.max(blk['true_rel_residual'])):.2e}) against {t_seq:.1f} s for "
         f"{nrhs} FP64 solves one after another (from {k}); F/T agree to {dft:.1e}")
     return {
         "spheres": pb.P, "collocation_nodes": pb.T, "sources": pb.S, "nrhs": nrhs, "restart": m,
