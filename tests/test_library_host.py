@@ -227,3 +227,47 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
                        cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))), env=env)
     assert r.returncode == 0 and "raised:" in r.stdout and "missing" in r.stdout
+
+
+def _imports(path):
+    """Module names a Python file imports, with the function they sit in
+    (None at module level)."""
+    import ast
+    tree = ast.parse(open(path).read())
+    out = []
+
+    def visit(node, fn):
+        for ch in ast.iter_child_nodes(node):
+            f = ch.name if isinstance(ch, (ast.FunctionDef, ast.AsyncFunctionDef)) else fn
+            if isinstance(ch, ast.Import):
+                out.extend((a.name, fn) for a in ch.names)
+            elif isinstance(ch, ast.ImportFrom):
+                out.append(("." * ch.level + (ch.module or ""), fn))
+            visit(ch, f)
+    visit(tree, None)
+    return out
+
+
+def test_oracle_and_product_share_no_code():
+    """The oracle and the library are independent: no product file imports
+    or includes anything under oracle/, the oracle imports nothing from the
+    package, the input generators hold no import of either side's
+    arithmetic, and the benchmark touches the oracle only inside its CPU
+    baseline."""
+    import glob
+    pkg = os.path.join(ROOT, "paper_2407_03343_amd")
+    for f in glob.glob(os.path.join(pkg, "*.py")):
+        for mod, _ in _imports(f):
+            assert not mod.startswith("oracle"), (f, mod)
+    for f in glob.glob(os.path.join(pkg, "csrc", "*")):
+        for line in open(f, errors="replace"):
+            if line.lstrip().startswith("#include"):
+                assert "oracle" not in line, (f, line)
+    for f in glob.glob(os.path.join(ROOT, "oracle", "*.py")):
+        for mod, _ in _imports(f):
+            assert "paper_2407_03343_amd" not in mod, (f, mod)
+    for mod, _ in _imports(os.path.join(pkg, "workloads.py")):
+        assert mod.split(".")[0] in ("__future__", "math", "dataclasses", "numpy"), mod
+    for mod, fn in _imports(os.path.join(ROOT, "bench.py")):
+        if mod.startswith("oracle"):
+            assert fn == "cpu_baseline", (mod, fn)
