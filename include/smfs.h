@@ -233,7 +233,8 @@ int smfs_setup_workspace_bytes(smfs_problem *pb, size_t *bytes);
 int smfs_setup(smfs_problem *pb, void *scratch, size_t scratch_bytes, smfs_stream stream);
 
 /* Equivalent sources of the contact-free spheres for SMFS_MIXED_EQ (eq_*
- * parameters): assembles the Stokeslet matrices K(check, equivalent) and
+ * parameters; a fast evaluation of the far part of eq. uAll, Section 2.2,
+ * where the paper uses a fast multipole method): assembles the Stokeslet matrices K(check, equivalent) and
  * K(check, proxies) of one sphere on the device, takes the SVD of the first
  * (rocSOLVER) and stores E = K_ce^+ K_cp (3 eq_points x 3 n_proxy, FP64) in
  * the workspace.  E depends on the node sets only, not on the factors, so a

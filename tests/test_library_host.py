@@ -271,3 +271,32 @@ def test_oracle_and_product_share_no_code():
     for mod, fn in _imports(os.path.join(ROOT, "bench.py")):
         if mod.startswith("oracle"):
             assert fn == "cpu_baseline", (mod, fn)
+
+
+def test_header_cites_the_paper_for_every_operation():
+    """Each entry point that computes a step of the method carries a
+    citation of the passage it follows in its own comment; the serving calls
+    under their section's comment; the allocation-free variant names the
+    callers it is for.  Housekeeping calls (defaults, sizes, workspace
+    queries, profiling, errors) need none."""
+    src = open(os.path.join(ROOT, "include", "smfs.h")).read()
+    cite = re.compile(r"Section|eq\.|Remark|Appendix|Table|Figure|Example")
+    own, section = {}, {}
+    last, sec = "", ""
+    for m in re.finditer(r"/\*.*?\*/|^[A-Za-z][^;{}]*?\b(smfs_\w+)\s*\([^;]*?\);", src, re.S | re.M):
+        t = m.group(0)
+        if t.startswith("/*"):
+            last = t
+            if t.startswith("/* ----"):
+                sec = t
+        else:
+            own[m.group(1)], section[m.group(1)] = last, sec
+    operations = ["smfs_problem_create", "smfs_export_nodes", "smfs_sphere_factor", "smfs_setup",
+                  "smfs_setup_far_field", "smfs_import_factor", "smfs_apply", "smfs_transform", "smfs_rhs",
+                  "smfs_set_background", "smfs_force_torque", "smfs_eval_velocity", "smfs_solve_resistance",
+                  "smfs_solve_mobility", "smfs_apply_block", "smfs_solve_resistance_block"]
+    for name in operations:
+        assert cite.search(own[name]), name
+    for name in ("smfs_server_create", "smfs_server_submit", "smfs_server_step", "smfs_server_poll"):
+        assert cite.search(section[name]), name
+    assert "cannot allocate" in own["smfs_apply_block_noalloc"]
