@@ -71,3 +71,20 @@ def test_serve_only_needs_requests():
     assert r.returncode == 2
     assert "--serve-requests" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_profile_summaries_are_short_text_with_their_command():
+    """profiles/ holds short rocprofv3 summaries as text: each names the
+    kernel and workload in its file name, gives the full command, which runs
+    committed files only (the benchmark), and is a few KB."""
+    pdir = os.path.join(ROOT, "profiles")
+    names = sorted(os.listdir(pdir))
+    assert names
+    for n in names:
+        assert n.endswith((".md", ".txt")) and n.startswith("k_"), n
+        text = open(os.path.join(pdir, n)).read()
+        assert len(text.encode()) < 16384, n
+        cmd = [l for l in text.splitlines() if "rocprofv3" in l and "--" in l]
+        assert cmd, n
+        for l in cmd:
+            assert "bench.py" in l and "_work" not in l, (n, l)
