@@ -14,6 +14,8 @@ from paper_2407_03343_amd import workloads as wl
 
 from gpu_common import _say, _t, _n
 
+from closed_forms import jeffery_axial_torque, stimson_jeffery
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -149,6 +151,36 @@ def test_serving_default_discretisation(dev, pair001):
     assert d < 1e-5
     assert abs(np.linalg.norm(r["ft"][1, :3]) - Fb) < 1e-3 * Fb
 
+
+
+def test_serving_close_pair_against_closed_forms(dev):
+    """Three requests of the same pair at gap 0.01 (default discretisation)
+    served together: translating together along the line of centres, and
+    spinning about it in the same and in opposite senses.  Forces against
+    the Stimson-Jeffery series to 1e-4, torques against Jeffery's to 1e-5,
+    as for the single-problem solves."""
+    _say("serving: default discretisation, close pair, three motions against closed forms")
+    import math
+    pk = wl.two_sphere(0.01)
+    c = np.asarray(pk.centers)
+    ax = (c[1] - c[0]) / np.linalg.norm(c[1] - c[0])
+    h = 0.5 * np.linalg.norm(c[1] - c[0])
+    z = 0 * ax
+    cases = ((np.stack([np.r_[ax, z], np.r_[ax, z]]), 0, 6 * math.pi * stimson_jeffery(h), 1e-4),
+             (np.stack([np.r_[z, ax], np.r_[z, ax]]), 3, 8 * math.pi * jeffery_axial_torque(h, True), 1e-5),
+             (np.stack([np.r_[z, ax], np.r_[z, -ax]]), 3, 8 * math.pi * jeffery_axial_torque(h, False), 1e-5))
+    srv = dev.Server(arena_bytes=2 << 30, max_active=4, n_check_base=0, gmres_tol=1e-10,
+                     gmres_restart=200, gmres_max_it=1000)
+    ids = [srv.submit(c, rbm) for rbm, _, _, _ in cases]
+    srv.drain(timeout_s=120)
+    res = [srv.poll(i, 2) for i in ids]
+    srv.close()
+    for (rbm, off, ref, bar), r in zip(cases, res):
+        want = ref * rbm
+        d = np.abs(r["ft"] - want).max() / ref
+        _say(f"  served: status {r['status']}, it {r['iterations']}, closed form {ref:.6f}, rel diff {d:.2e}")
+        assert r["status"] in (0, 3) and r["true_rel_residual"] < 1e-6
+        assert d < bar
 
 
 @pytest.fixture(scope="module")
